@@ -1,0 +1,14 @@
+"""Oracle for the compact finite-difference hot path.
+
+TEST INFRASTRUCTURE ONLY: a plain, slow, independent CPU implementation of
+what the GPU library computes, written from arXiv 2302.14858.  Only the test
+suite, the smoke check and the benchmark's CPU-baseline leg may import it; the
+product library never does, and the two share no code.
+
+* ``oracle.schemes``  - scheme construction (Taylor matching, spectral tuning,
+  matched closures) in exact or high-precision arithmetic.
+* ``oracle.lines``    - FP64 line operator: explicit RHS stencil, closure rows,
+  banded elimination, cyclic (periodic) solve; plain C behind ctypes.
+* ``oracle.dense``    - dense assembled matrices of Eqs. diff_mat_subL/R and
+  the embedded operator of Eq. iter_scheme, solved with numpy (pins only).
+"""
