@@ -1,0 +1,248 @@
+/*
+ * cfd.h - C ABI of the MI355X compact finite-difference library.
+ *
+ * The library applies implicit compact finite-difference derivative
+ * operators  A f~ = h^-d B f  along the grid lines of 3D mesh blocks held on
+ * one GPU (arXiv 2302.14858).  A scheme is the coefficient tuple pair
+ * (alpha^(d), alpha^(0)) of the multi-derivative ansatz, Eq. mdAnsatz with
+ * d_I = (0), together with the explicit closure stencils used on the rows
+ * nearest a block end, Eq. sch_cent_om (Sec. 2.4).  A block has N interior
+ * nodes per direction and N_g ghost layers per side (Eq. gridDisc and the
+ * figure after it); each direction is either closed by the block closure or
+ * periodic (the periodic operator D of Sec. 2.2).
+ *
+ * Conventions used by every call:
+ *  - Return value: cfd_status; CFD_OK on success.  On failure nothing is
+ *    enqueued, output handles are left untouched, and cfd_last_error() returns
+ *    a thread-local message describing the failure.  No call aborts.
+ *  - Pointers named *_dev are device pointers (hipMalloc / torch CUDA tensor
+ *    storage on the plan's device); every other pointer is host memory.
+ *  - Streams are passed as void* holding a hipStream_t (NULL = null stream).
+ *    Work is enqueued asynchronously; errors raised by a kernel surface as
+ *    CFD_EDEVICE from a later call that synchronises.
+ *  - Handles (cfd_scheme*, cfd_plan*) are owned by the library and released
+ *    with the matching *_destroy call.  Destroying NULL is a no-op.
+ *  - Arrays passed in are copied; the caller keeps ownership.
+ */
+#ifndef CFD_MI355X_H
+#define CFD_MI355X_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CFD_ABI_VERSION 1
+
+typedef enum {
+    CFD_OK = 0,
+    CFD_EINVAL = 1,       /* bad argument: null pointer, unknown name, bad layout */
+    CFD_EGHOST = 2,       /* ghost width below what the scheme's closure rows reach */
+    CFD_ESHAPE = 3,       /* block too short for the closure rows / partitions */
+    CFD_ESINGULAR = 4,    /* scheme system singular or not solvable without pivoting */
+    CFD_ENOMEM = 5,       /* host or device allocation failed */
+    CFD_EDEVICE = 6,      /* HIP runtime error (launch, copy, earlier kernel fault) */
+    CFD_EUNSUPPORTED = 7  /* valid request this build does not implement */
+} cfd_status;
+
+typedef enum {
+    CFD_F64 = 0,          /* FP64 storage and arithmetic */
+    CFD_F32 = 1,          /* FP32 storage and arithmetic (tables built in FP64) */
+    CFD_MIXED_BF16 = 2    /* FP32 storage; periodic lines only: dense A^-1 B on
+                             MFMA in split-BF16 with FP32 accumulation, then one
+                             FP64 banded-residual refinement */
+} cfd_dtype;
+
+typedef enum {
+    CFD_BOUNDARY_CLOSURE = 0,   /* block closure of Eq. sch_cent_om; ghosts are input data */
+    CFD_BOUNDARY_PERIODIC = 1   /* the block wraps onto itself; ghosts are not read */
+} cfd_boundary;
+
+typedef struct cfd_scheme cfd_scheme;
+typedef struct cfd_plan cfd_plan;
+
+/* ------------------------------------------------------------------------ */
+/* Library                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* ABI version (CFD_ABI_VERSION of the header the library was built with). */
+int cfd_abi_version(void);
+
+/* Thread-local description of the last failure on this thread ("" if none).
+ * The string stays valid until the next failing call on the same thread. */
+const char *cfd_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Schemes (Sec. 2: Eqs. coeffTupDefn, mdAnsatz, Tcons; Sec. 2.4 closures)   */
+/* ------------------------------------------------------------------------ */
+
+/* Scheme from the built-in registry, constructed on the host in 113-bit
+ * arithmetic from the paper's conditions (Taylor matching, Eq. Tcons;
+ * spectral tuning, Eqs. optfunc and gammacut; matched closures, Sec. 2.4).
+ * Names:
+ *   "(d)P1_M"          d = 1|2, M = 1..3: Pade schemes of Tabs. pade_deg_one/two
+ *                      with the matched closures (d)Pbar_{M+2}.
+ *   "(d)Q1_3[1]", "(d)Q1_3[4pi/5]"
+ *                      tuned tridiagonal schemes of Tabs. num_deg_one/two with
+ *                      the matched closures (d)Qbar_4.
+ *   "(d)QP_O8[1]"      pentadiagonal (implicit half-width 2), RHS half-width 3,
+ *                      formal order 8, tuned with eta_c = 1 by the same
+ *                      procedure; matched closures of half-width 5 on the two
+ *                      rows nearest each block end.
+ *   "(d)EM"            explicit centred schemes of Tab. misc_explicit (M = 1..5),
+ *                      e.g. "(1)E3".
+ * A suffix ":E" replaces a matched closure by the order-only explicit closure
+ * of half-width p (formal order 2p), e.g. "(1)Q1_3[1]:E".
+ * out: receives a library-owned handle.  CFD_EINVAL on an unknown name. */
+cfd_status cfd_scheme_named(const char *name, cfd_scheme **out);
+
+/* Design a centred scheme: derivative degree d (1|2), formal order `order`
+ * (even), implicit half-width nl (0..2), RHS half-width m (1..5).  When the
+ * Taylor conditions leave free coefficients the spectral error of Eq. optfunc
+ * with the cut-off weight of Eq. gammacut at eta_c (0 < eta_c <= pi) is
+ * minimised.  closure_mc > 0 attaches explicit closures of that half-width on
+ * the nl rows nearest each end (matched = 1: lowest error constant matched and
+ * the next power removed, Sec. 2.4; matched = 0: Taylor conditions only, which
+ * needs closure_mc = order/2).  CFD_EINVAL on inconsistent sizes,
+ * CFD_ESINGULAR if the conditions have no solution. */
+cfd_status cfd_scheme_design(int d, int order, int nl, int m, double eta_c,
+                             int closure_mc, int matched, cfd_scheme **out);
+
+/* Scheme from caller coefficients.
+ *   lhs[2nl+1]    alpha^(d)_{-nl..nl}; lhs[nl] must be 1 (normalisation).
+ *   rhs[2m+1]     alpha^(0)_{-m..m}.
+ *   closure[nc*(2mc+1)]  explicit closure rows for the rows k*_- + j,
+ *                 j = 0..nc-1, each alpha^(0)_{-mc..mc}; the right end uses the
+ *                 mirror image (-1)^d c[-n].  nc must equal nl (0 for explicit).
+ * The Taylor conditions up to `order` are checked on every row (residual
+ * <= 1e-12 relative), else CFD_EINVAL.  nl <= 2, m <= 5, mc <= 5. */
+cfd_status cfd_scheme_create(int d, int order, int nl, const double *lhs, int m,
+                             const double *rhs, int nc, int mc, const double *closure,
+                             cfd_scheme **out);
+
+/* Read back a scheme.  Any output pointer may be NULL.  Arrays must hold
+ * 5 (lhs, centred at index 2), 11 (rhs, centred at 5) and 2*11 (closure rows,
+ * each centred at 5) doubles; unused entries are written as 0. */
+cfd_status cfd_scheme_get(const cfd_scheme *s, int *d, int *order, int *nl, int *m,
+                          int *nc, int *mc, double *lhs5, double *rhs11, double *closure22);
+
+/* Ghost layers the scheme needs for boundary kind b: 0 for periodic; for the
+ * closure, the largest reach of any closure or interior row past the block end. */
+cfd_status cfd_scheme_required_ghosts(const cfd_scheme *s, cfd_boundary b, int *ng);
+
+void cfd_scheme_destroy(cfd_scheme *s);
+
+/* ------------------------------------------------------------------------ */
+/* Plans: a batch of blocks x fields x operators, applied in one step        */
+/* ------------------------------------------------------------------------ */
+
+/* One mesh block.  Interior extents n[0..2] = (nx, ny, nz); ng ghost layers on
+ * every side; spacing h[0..2]; boundary[0..2] per direction (cfd_boundary).
+ * Input layout (elements, from the apply call's input base pointer):
+ *   in_offset + f * (nx+2ng)(ny+2ng)(nz+2ng) + ((z+ng)(ny+2ng) + (y+ng))(nx+2ng) + (x+ng)
+ *   for field f, interior node (x,y,z); ghosts at negative / >= n coordinates.
+ * Output layout (interior only): operator op writes F_op fields (nfields, or
+ * 1 when it selects one field), operators packed in order:
+ *   out_offset + (S_op + f) * nx*ny*nz + (z*ny + y)*nx + x,  S_op = sum_{o<op} F_o,
+ *   f = field index (or 0 for a one-field operator).
+ * Offsets of -1 ask the library to pack blocks consecutively in order. */
+typedef struct {
+    int n[3];
+    int ng;
+    double h[3];
+    int boundary[3];
+    long long in_offset;
+    long long out_offset;
+} cfd_block;
+
+/* One derivative operator: a scheme applied along direction dir (0=x,1=y,2=z)
+ * to every field (field = -1) or to one field index. */
+typedef struct {
+    const cfd_scheme *scheme;
+    int dir;
+    int field;
+} cfd_op;
+
+typedef struct {
+    int nblocks;
+    const cfd_block *blocks;   /* nblocks entries */
+    int nfields;               /* fields per block, >= 1 */
+    int nops;                  /* operators, >= 1; output op index = position */
+    const cfd_op *ops;
+    cfd_dtype dtype;
+    int device;                /* HIP device ordinal */
+    int flags;                 /* 0 (reserved) */
+} cfd_plan_desc;
+
+/* Build a plan: validates every block against every operator (CFD_EGHOST,
+ * CFD_ESHAPE), builds and uploads the per-line-class tables (closure and
+ * interior coefficients; partition-local LU factors, spike vectors and
+ * reduced-system rows, all formed in FP64 on the GPU, Eq. sch_cent_om and its
+ * matrix form Eqs. diff_mat_subL/R) and the device work lists.  Nothing is
+ * allocated later by cfd_apply, so applies can be captured in a graph.
+ * Synchronises the device once (table construction). */
+cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out);
+
+/* Total input and output sizes in elements for the packed layout (or the
+ * extent implied by explicit offsets).  Either pointer may be NULL. */
+cfd_status cfd_plan_sizes(const cfd_plan *p, long long *in_elems, long long *out_elems);
+
+/* Resolved per-block offsets (elements).  Arrays of nblocks entries or NULL. */
+cfd_status cfd_plan_offsets(const cfd_plan *p, long long *in_offsets, long long *out_offsets);
+
+/* Number of kernel launches one apply enqueues, and the number of work items. */
+cfd_status cfd_plan_stats(const cfd_plan *p, int *launches, long long *items);
+
+/* Apply every operator to every field of every block.
+ * in_dev: base of the input (element type per dtype), out_dev: base of the
+ * output; both 16-byte aligned.  Enqueued on `stream`; returns immediately. */
+cfd_status cfd_apply(cfd_plan *p, const void *in_dev, void *out_dev, void *stream);
+
+/* Capture one apply with fixed buffers into a HIP graph owned by the plan
+ * (replaces a previous capture).  Enqueues nothing. */
+cfd_status cfd_plan_capture_graph(cfd_plan *p, const void *in_dev, void *out_dev, void *stream);
+
+/* Launch the captured graph on `stream`.  CFD_EINVAL if none was captured. */
+cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream);
+
+/* Time the candidate schedules (partition length per line length, persistent
+ * or one-workgroup-per-item grids) on the given buffers and keep the fastest.
+ * If cache_path is non-NULL the choice is read from / appended to that text
+ * file, keyed by device arch, line length, direction class, dtype and band.
+ * Synchronises the stream.  Invalidates a captured graph. */
+cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, void *stream,
+                             const char *cache_path);
+
+/* Choose the schedule by hand: partition length `L` for line length N (0 =
+ * default), persistent grid on/off.  CFD_EINVAL if L does not divide N or
+ * breaks the partition rules.  Invalidates a captured graph. */
+cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int L, int persistent);
+
+void cfd_plan_destroy(cfd_plan *p);
+
+/* ------------------------------------------------------------------------ */
+/* Ghost exchange for conforming periodic tilings (the communication step    */
+/* of Sec. 2.4, done on the device)                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Blocks of one plan that tile a periodic box as a bx*by*bz lattice (block
+ * index = (kz*by + ky)*bx + kx, all blocks the same shape) exchange face
+ * ghosts: for every field, the ng ghost layers of each face of each block are
+ * copied from the facing interior layers of its neighbour.  Edges and corners
+ * are not filled (no operator reads them).  data_dev is the plan's input
+ * buffer (element type per dtype). */
+cfd_status cfd_halo_exchange(cfd_plan *p, void *data_dev, int bx, int by, int bz, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Element-wise stage kernels for method-of-lines time stepping (classical   */
+/* ERK4, Sec. 3.1): y = a*x + b*y and z = x + c*y over n elements.           */
+/* ------------------------------------------------------------------------ */
+
+cfd_status cfd_axpby(cfd_dtype dtype, long long n, double a, const void *x_dev, double b,
+                     void *y_dev, void *stream);
+cfd_status cfd_xpcy(cfd_dtype dtype, long long n, const void *x_dev, double c, const void *y_dev,
+                    void *z_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFD_MI355X_H */

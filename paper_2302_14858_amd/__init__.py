@@ -1,0 +1,221 @@
+"""Python binding of the MI355X compact finite-difference library.
+
+Thin wrappers over the C ABI (include/cfd.h) with the same names; device
+memory and streams come from torch (ROCm).  Every derivative is computed by
+the HIP kernels in libcfd_mi355x.so; there is no CPU path, and the binding
+raises if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional, Sequence
+
+from . import _lib
+from ._lib import (CFD_BOUNDARY_CLOSURE, CFD_BOUNDARY_PERIODIC, CFD_F32, CFD_F64, CFD_MIXED_BF16, CfdError,
+                   check, lib)
+
+__all__ = ["Scheme", "Plan", "cfd_abi_version", "cfd_axpby", "cfd_xpcy", "CfdError", "CFD_F64", "CFD_F32",
+           "CFD_MIXED_BF16", "CFD_BOUNDARY_CLOSURE", "CFD_BOUNDARY_PERIODIC"]
+
+
+def cfd_abi_version() -> int:
+    return lib().cfd_abi_version()
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t) -> int:
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+class Scheme:
+    """A compact finite-difference scheme (library-owned handle)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @classmethod
+    def cfd_scheme_named(cls, name: str) -> "Scheme":
+        out = ctypes.c_void_p()
+        check(lib().cfd_scheme_named(name.encode(), ctypes.byref(out)))
+        return cls(out.value)
+
+    named = cfd_scheme_named
+
+    @classmethod
+    def cfd_scheme_design(cls, d: int, order: int, nl: int, m: int, eta_c: float = 1.0, closure_mc: int = 0,
+                          matched: bool = True) -> "Scheme":
+        out = ctypes.c_void_p()
+        check(lib().cfd_scheme_design(d, order, nl, m, float(eta_c), closure_mc, int(matched), ctypes.byref(out)))
+        return cls(out.value)
+
+    design = cfd_scheme_design
+
+    @classmethod
+    def cfd_scheme_create(cls, d: int, order: int, lhs: Sequence[float], rhs: Sequence[float],
+                          closure: Sequence[Sequence[float]] = ()) -> "Scheme":
+        nl = (len(lhs) - 1) // 2
+        m = (len(rhs) - 1) // 2
+        nc = len(closure)
+        mc = (len(closure[0]) - 1) // 2 if nc else 0
+        L = (ctypes.c_double * len(lhs))(*lhs)
+        R = (ctypes.c_double * len(rhs))(*rhs)
+        flat = [v for row in closure for v in row] or [0.0]
+        C = (ctypes.c_double * len(flat))(*flat)
+        out = ctypes.c_void_p()
+        check(lib().cfd_scheme_create(d, order, nl, L, m, R, nc, mc, C, ctypes.byref(out)))
+        return cls(out.value)
+
+    create = cfd_scheme_create
+
+    def cfd_scheme_get(self) -> Dict:
+        ints = [ctypes.c_int() for _ in range(6)]
+        lhs = (ctypes.c_double * 5)()
+        rhs = (ctypes.c_double * 11)()
+        cl = (ctypes.c_double * 22)()
+        check(lib().cfd_scheme_get(self._h, *[ctypes.byref(v) for v in ints], lhs, rhs, cl))
+        d, order, nl, m, nc, mc = (v.value for v in ints)
+        return {"d": d, "order": order, "nl": nl, "m": m, "nc": nc, "mc": mc, "lhs": list(lhs), "rhs": list(rhs),
+                "closure": [list(cl[0:11]), list(cl[11:22])]}
+
+    get = cfd_scheme_get
+
+    def cfd_scheme_required_ghosts(self, boundary: int = CFD_BOUNDARY_CLOSURE) -> int:
+        ng = ctypes.c_int()
+        check(lib().cfd_scheme_required_ghosts(self._h, boundary, ctypes.byref(ng)))
+        return ng.value
+
+    required_ghosts = cfd_scheme_required_ghosts
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().cfd_scheme_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+class Plan:
+    """A batch of blocks x fields x operators applied in one step.
+
+    blocks: list of dicts with keys n (3 ints), ng, h (3 floats), boundary (3 ints),
+            optional in_offset / out_offset (elements; default packed).
+    ops:    list of (Scheme, dir) or (Scheme, dir, field).
+    """
+
+    def __init__(self, blocks: List[Dict], nfields: int, ops: Sequence, dtype: int = CFD_F64, device: int = 0):
+        nb = len(blocks)
+        arr = (_lib.cfd_block * nb)()
+        for i, b in enumerate(blocks):
+            arr[i].n = (ctypes.c_int * 3)(*b["n"])
+            arr[i].ng = int(b["ng"])
+            arr[i].h = (ctypes.c_double * 3)(*b["h"])
+            arr[i].boundary = (ctypes.c_int * 3)(*b["boundary"])
+            arr[i].in_offset = int(b.get("in_offset", -1))
+            arr[i].out_offset = int(b.get("out_offset", -1))
+        self._schemes = [op[0] for op in ops]          # keep handles alive
+        oarr = (_lib.cfd_op * len(ops))()
+        for i, op in enumerate(ops):
+            oarr[i].scheme = op[0]._h
+            oarr[i].dir = int(op[1])
+            oarr[i].field = int(op[2]) if len(op) > 2 else -1
+        desc = _lib.cfd_plan_desc(nb, arr, int(nfields), len(ops), oarr, int(dtype), int(device), 0)
+        out = ctypes.c_void_p()
+        check(lib().cfd_plan_create(ctypes.byref(desc), ctypes.byref(out)))
+        self._h = out
+        self.nblocks = nb
+        self.dtype = dtype
+
+    def cfd_plan_sizes(self):
+        a, b = ctypes.c_longlong(), ctypes.c_longlong()
+        check(lib().cfd_plan_sizes(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    sizes = cfd_plan_sizes
+
+    def cfd_plan_offsets(self):
+        a = (ctypes.c_longlong * self.nblocks)()
+        b = (ctypes.c_longlong * self.nblocks)()
+        check(lib().cfd_plan_offsets(self._h, a, b))
+        return list(a), list(b)
+
+    offsets = cfd_plan_offsets
+
+    def cfd_plan_stats(self):
+        a, b = ctypes.c_int(), ctypes.c_longlong()
+        check(lib().cfd_plan_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    stats = cfd_plan_stats
+
+    def cfd_apply(self, inp, out, stream=None) -> None:
+        check(lib().cfd_apply(self._h, _dev_ptr(inp), _dev_ptr(out), _stream_ptr(stream)))
+
+    apply = cfd_apply
+
+    def cfd_plan_capture_graph(self, inp, out, stream=None) -> None:
+        check(lib().cfd_plan_capture_graph(self._h, _dev_ptr(inp), _dev_ptr(out), _stream_ptr(stream)))
+
+    capture_graph = cfd_plan_capture_graph
+
+    def cfd_plan_launch_graph(self, stream=None) -> None:
+        check(lib().cfd_plan_launch_graph(self._h, _stream_ptr(stream)))
+
+    launch_graph = cfd_plan_launch_graph
+
+    def cfd_plan_autotune(self, inp, out, cache_path: Optional[str] = None, stream=None) -> None:
+        check(lib().cfd_plan_autotune(self._h, _dev_ptr(inp), _dev_ptr(out), _stream_ptr(stream),
+                                      cache_path.encode() if cache_path else None))
+
+    autotune = cfd_plan_autotune
+
+    def cfd_plan_set_schedule(self, N: int = 0, L: int = 0, persistent: bool = True) -> None:
+        check(lib().cfd_plan_set_schedule(self._h, N, L, int(persistent)))
+
+    set_schedule = cfd_plan_set_schedule
+
+    def cfd_halo_exchange(self, data, bx: int, by: int, bz: int, stream=None) -> None:
+        check(lib().cfd_halo_exchange(self._h, _dev_ptr(data), bx, by, bz, _stream_ptr(stream)))
+
+    halo_exchange = cfd_halo_exchange
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().cfd_plan_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return CFD_F64
+    if t.dtype == torch.float32:
+        return CFD_F32
+    raise ValueError("float64 or float32 tensors only")
+
+
+def cfd_axpby(a: float, x, b: float, y, stream=None) -> None:
+    """y = a*x + b*y on the GPU."""
+    check(lib().cfd_axpby(_dtype_code(y), y.numel(), float(a), _dev_ptr(x), float(b), _dev_ptr(y),
+                          _stream_ptr(stream)))
+
+
+def cfd_xpcy(x, c: float, y, z, stream=None) -> None:
+    """z = x + c*y on the GPU."""
+    check(lib().cfd_xpcy(_dtype_code(z), z.numel(), _dev_ptr(x), float(c), _dev_ptr(y), _dev_ptr(z),
+                         _stream_ptr(stream)))

@@ -1,0 +1,851 @@
+// Host runtime and C ABI of the MI355X compact finite-difference library.
+//
+// A plan turns (blocks x fields x operators) into:
+//  * passes: one per (block, direction, field selection, fused operator
+//    group); a pass sweeps every line of that direction once and evaluates up
+//    to two operators that share the line data (e.g. the first and second
+//    derivative of the same field);
+//  * tables: per (operator scheme, line length, partition count, boundary)
+//    the coefficient block plus the FP64 solve tables built on the GPU;
+//  * work items of 64 lines, grouped into launch groups by compiled kernel
+//    variant and partition count.  One apply = one kernel launch per group,
+//    each a persistent grid over its items (or one workgroup per item).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "cfd_internal.h"
+
+using namespace cfd;
+
+namespace {
+
+thread_local std::string g_err;
+
+cfd_status fail(cfd_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+cfd_status hip_fail(hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    (void)hipGetLastError();
+    return fail(CFD_EDEVICE, m);
+}
+
+#define HIPCHK(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+}  // namespace
+
+struct cfd_scheme {
+    Scheme s;
+};
+
+namespace {
+
+struct PassHost {
+    int block, dir, field0, nfield;
+    int nops;
+    int op[2];        // plan op indices (output order)
+    int sch[2];       // scheme indices
+    int N, periodic, nl, par, mi, hw;
+    int L = 0, P = 0;
+    const void *fn = nullptr;
+};
+
+struct Group {
+    const void *fn;
+    int P;
+    size_t lds;
+    int64_t item0, nitems;
+    int grid_persist;
+};
+
+struct TabKey {
+    int sch, N, P, periodic;
+    bool operator<(const TabKey &o) const {
+        return std::tie(sch, N, P, periodic) < std::tie(o.sch, o.N, o.P, o.periodic);
+    }
+};
+
+}  // namespace
+
+struct cfd_plan {
+    int device = 0;
+    cfd_dtype dtype = CFD_F64;
+    int nfields = 1;
+    std::vector<cfd_block> blocks;
+    std::vector<Scheme> schemes;          // one per op
+    std::vector<cfd_op> ops;              // scheme pointers not used after creation
+    std::vector<int> op_nf;               // fields each op writes
+    std::vector<int64_t> op_slot;         // S_op
+    std::vector<int64_t> in_off, out_off;
+    int64_t in_elems = 0, out_elems = 0;
+    std::vector<PassHost> passes;
+    std::map<int, int> sched_L;           // N -> L chosen by hand or autotune
+    bool persistent = true;
+    int cus = 256;
+    // device state rebuilt by build()
+    DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff;
+    std::vector<Group> groups;
+    int64_t nitems = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+    }
+    void release() {
+        drop_graph();
+        d_tab64.release();
+        d_tab32.release();
+        d_taboff.release();
+        d_pass.release();
+        d_items.release();
+        d_inoff.release();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        cap_stream = nullptr;
+    }
+};
+
+namespace {
+
+size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }
+
+// Candidate partition lengths for a pass, best first.
+std::vector<int> candidate_Ls(const PassHost &ps, bool f32) {
+    int Ls[16];
+    int n = line_kernel_Ls(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, Ls, 16);
+    std::vector<int> ok;
+    for (int i = 0; i < n; ++i) {
+        int L = Ls[i];
+        if (ps.N % L) continue;
+        int P = ps.N / L;
+        if (P > kMaxP || P < 1) continue;
+        if (ps.nl > 0 && L < 2 * ps.nl) continue;
+        if (!ps.periodic && ps.nl > 0 && P == 1 && L < 2 * ps.nl + 1) continue;
+        if (ps.periodic && ps.hw > ps.N) continue;
+        ok.push_back(L);
+    }
+    // default preference: the largest L <= 24 (register budget), then larger ones
+    std::sort(ok.begin(), ok.end(), [](int a, int b) {
+        bool sa = a <= 24, sb = b <= 24;
+        if (sa != sb) return sa;
+        return sa ? a > b : a < b;
+    });
+    return ok;
+}
+
+cfd_status build(cfd_plan *p) {
+    HIPCHK(hipSetDevice(p->device));
+    p->drop_graph();
+    const bool f32 = p->dtype != CFD_F64;
+    // 1. schedule and kernel variant of every pass
+    for (PassHost &ps : p->passes) {
+        std::vector<int> cands = candidate_Ls(ps, f32);
+        if (cands.empty()) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "no compiled line kernel for N=%d nl=%d nops=%d (stencil half-width %d)",
+                          ps.N, ps.nl, ps.nops, ps.hw);
+            return fail(CFD_EUNSUPPORTED, buf);
+        }
+        int L = cands[0];
+        auto it = p->sched_L.find(ps.N);
+        if (it != p->sched_L.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
+            L = it->second;
+        int mi, hw;
+        ps.fn = find_line_kernel(f32, ps.nl, L, ps.nops, ps.par, ps.mi, ps.hw, &mi, &hw);
+        ps.L = L;
+        ps.P = ps.N / L;
+    }
+    // 2. tables
+    std::map<TabKey, int> tabidx;
+    std::vector<TabKey> keys;
+    std::vector<int64_t> offs;
+    int64_t total = 0;
+    std::vector<std::array<int, 2>> pass_tab(p->passes.size());
+    for (size_t i = 0; i < p->passes.size(); ++i) {
+        const PassHost &ps = p->passes[i];
+        for (int o = 0; o < ps.nops; ++o) {
+            TabKey k{ps.sch[o], ps.N, ps.P, ps.periodic};
+            auto it = tabidx.find(k);
+            int id;
+            if (it == tabidx.end()) {
+                id = (int)keys.size();
+                tabidx[k] = id;
+                keys.push_back(k);
+                offs.push_back(total);
+                int64_t n = table_elems(ps.N, ps.P, p->schemes[ps.sch[o]].nl);
+                total += (n + 7) & ~int64_t(7);
+            } else {
+                id = it->second;
+            }
+            pass_tab[i][o] = id;
+        }
+    }
+    std::vector<double> host_tab(total, 0.0);
+    std::vector<unsigned char> specs(keys.size() * tabspec_size());
+    int64_t scratch_per = 0;
+    for (size_t t = 0; t < keys.size(); ++t) {
+        const TabKey &k = keys[t];
+        const Scheme &s = p->schemes[k.sch];
+        double *cb = host_tab.data() + offs[t];
+        for (int m = 0; m < 11; ++m) cb[kCoefA + m] = s.rhs[m];
+        const double sgn = (s.d % 2) ? -1.0 : 1.0;
+        for (int j = 0; j < kMaxNL; ++j)
+            for (int m = -kMaxHalf; m <= kMaxHalf; ++m) {
+                cb[kCoefCL + j * 11 + 5 + m] = s.cl[j][5 + m];
+                cb[kCoefCR + j * 11 + 5 + m] = sgn * s.cl[j][5 - m];
+            }
+        for (int j = 0; j < 5; ++j) cb[kCoefAlpha + j] = s.lhs[j];
+        const int L = k.N / k.P;
+        fill_tabspec(specs.data() + t * tabspec_size(), k.N, k.P, L, s.nl, k.periodic ? 0 : s.nc, k.periodic,
+                     s.lhs, offs[t]);
+        const int64_t B = 2 * s.nl * k.P;
+        scratch_per = std::max<int64_t>(scratch_per, 2 * B * B + L + 8);
+    }
+    p->d_tab64.release();
+    p->d_tab32.release();
+    p->d_taboff.release();
+    HIPCHK(hipMalloc(&p->d_tab64.p, total * sizeof(double)));
+    HIPCHK(hipMemcpy(p->d_tab64.p, host_tab.data(), total * sizeof(double), hipMemcpyHostToDevice));
+    {
+        void *d_specs = nullptr, *d_scratch = nullptr, *d_status = nullptr;
+        const int ntab = (int)keys.size();
+        hipError_t e = hipMalloc(&d_specs, specs.size());
+        if (e == hipSuccess) e = hipMalloc(&d_scratch, std::max<int64_t>(1, scratch_per * ntab) * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&d_status, ntab * sizeof(int));
+        if (e == hipSuccess) e = hipMemcpy(d_specs, specs.data(), specs.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_build_tables(ntab, d_specs, (double *)p->d_tab64.p, (double *)d_scratch, scratch_per,
+                                    (int *)d_status, nullptr);
+        std::vector<int> status(ntab, 0);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemcpy(status.data(), d_status, ntab * sizeof(int), hipMemcpyDeviceToHost);
+        if (d_specs) (void)hipFree(d_specs);
+        if (d_scratch) (void)hipFree(d_scratch);
+        if (d_status) (void)hipFree(d_status);
+        if (e != hipSuccess) return hip_fail(e, "building solve tables");
+        for (int t = 0; t < ntab; ++t)
+            if (status[t])
+                return fail(CFD_ESINGULAR, "banded system of scheme '" + p->schemes[keys[t].sch].name +
+                                               "' cannot be factored without pivoting");
+    }
+    if (f32) {
+        HIPCHK(hipMalloc(&p->d_tab32.p, total * sizeof(float)));
+        hipError_t e = launch_to_f32(total, (const double *)p->d_tab64.p, (float *)p->d_tab32.p, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "converting tables to FP32");
+    }
+    HIPCHK(hipMalloc(&p->d_taboff.p, std::max<size_t>(1, offs.size()) * sizeof(int64_t)));
+    HIPCHK(hipMemcpy(p->d_taboff.p, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+
+    // 3. pass descriptors
+    std::vector<PassDesc> pd(p->passes.size());
+    for (size_t i = 0; i < p->passes.size(); ++i) {
+        const PassHost &ps = p->passes[i];
+        const cfd_block &b = p->blocks[ps.block];
+        const int64_t ng = b.ng;
+        const int64_t PX = b.n[0] + 2 * ng, PY = b.n[1] + 2 * ng, PZ = b.n[2] + 2 * ng;
+        const int64_t s_in[3] = {1, PX, PX * PY};
+        const int64_t s_out[3] = {1, b.n[0], (int64_t)b.n[0] * b.n[1]};
+        const int d = ps.dir;
+        const int u = (d == 0) ? 1 : 0;
+        const int v = (d == 2) ? 1 : 2;
+        PassDesc &q = pd[i];
+        std::memset(&q, 0, sizeof q);
+        q.in_base = p->in_off[ps.block] + ng * (s_in[0] + s_in[1] + s_in[2]);
+        q.in_fstride = PX * PY * PZ;
+        const int64_t npts = (int64_t)b.n[0] * b.n[1] * b.n[2];
+        for (int o = 0; o < ps.nops; ++o) {
+            q.out_base[o] = p->out_off[ps.block] + p->op_slot[ps.op[o]] * npts;
+            q.tab[o] = pass_tab[i][o];
+            q.hinv[o] = 1.0 / std::pow(b.h[d], p->schemes[ps.sch[o]].d);
+        }
+        q.out_fstride = npts;
+        q.su = (int32_t)s_in[u];
+        q.sv = (int32_t)s_in[v];
+        q.sd = (int32_t)s_in[d];
+        q.osu = (int32_t)s_out[u];
+        q.osv = (int32_t)s_out[v];
+        q.osd = (int32_t)s_out[d];
+        q.nu = b.n[u];
+        q.nlines = b.n[u] * b.n[v];
+        q.N = ps.N;
+        q.ng = b.ng;
+        q.periodic = ps.periodic;
+        q.nfield_pass = ps.nfield;
+        q.field0 = ps.field0;
+    }
+    p->d_pass.release();
+    HIPCHK(hipMalloc(&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
+    HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
+
+    // 4. work items, grouped by (kernel, P); within a group ordered by
+    //    block, field, direction so the passes over one block-field are close
+    //    in time (their shared input stays in cache).
+    std::map<std::pair<const void *, int>, std::vector<WorkItem>> byk;
+    std::vector<std::pair<const void *, int>> order;
+    std::vector<size_t> pidx(p->passes.size());
+    for (size_t i = 0; i < pidx.size(); ++i) pidx[i] = i;
+    std::stable_sort(pidx.begin(), pidx.end(), [&](size_t a, size_t b) {
+        return p->passes[a].block < p->passes[b].block;
+    });
+    for (size_t i : pidx) {
+        const PassHost &ps = p->passes[i];
+        auto key = std::make_pair(ps.fn, ps.P);
+        if (!byk.count(key)) order.push_back(key);
+        auto &vec = byk[key];
+        for (int f = 0; f < ps.nfield; ++f)
+            for (int l0 = 0; l0 < pd[i].nlines; l0 += kWave) vec.push_back(WorkItem{(int32_t)i, f, l0, 0});
+    }
+    std::vector<WorkItem> items;
+    p->groups.clear();
+    for (auto &key : order) {
+        auto &vec = byk[key];
+        Group g;
+        g.fn = key.first;
+        g.P = key.second;
+        g.item0 = (int64_t)items.size();
+        g.nitems = (int64_t)vec.size();
+        // LDS for the boundary exchange: nops x 64 lanes x (B|1) values
+        int nl = 0, nops = 1;
+        for (const PassHost &ps : p->passes)
+            if (ps.fn == g.fn && ps.P == g.P) { nl = ps.nl; nops = ps.nops; break; }
+        const int B = 2 * nl * g.P;
+        g.lds = (nl > 0) ? (size_t)nops * kWave * (B | 1) * elem_size(p->dtype == CFD_F64 ? CFD_F64 : CFD_F32) : 0;
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, g.fn, kWave * g.P, g.lds) != hipSuccess || nb < 1)
+            nb = 1;
+        (void)hipGetLastError();
+        g.grid_persist = (int)std::min<int64_t>(g.nitems, (int64_t)nb * p->cus);
+        items.insert(items.end(), vec.begin(), vec.end());
+        p->groups.push_back(g);
+    }
+    p->nitems = (int64_t)items.size();
+    p->d_items.release();
+    HIPCHK(hipMalloc(&p->d_items.p, std::max<size_t>(1, items.size()) * sizeof(WorkItem)));
+    HIPCHK(hipMemcpy(p->d_items.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    return CFD_OK;
+}
+
+cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
+    const void *tabs = (p->dtype == CFD_F64) ? p->d_tab64.p : p->d_tab32.p;
+    for (const Group &g : p->groups) {
+        if (g.nitems == 0) continue;
+        const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
+        hipError_t e = launch_lines(g.fn, grid, g.P, g.lds, st, (const WorkItem *)p->d_items.p + g.item0,
+                                    (int)g.nitems, (const PassDesc *)p->d_pass.p, tabs,
+                                    (const int64_t *)p->d_taboff.p, in, out);
+        if (e != hipSuccess) return hip_fail(e, "launching line kernel");
+    }
+    return CFD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int cfd_abi_version(void) { return CFD_ABI_VERSION; }
+
+const char *cfd_last_error(void) { return g_err.c_str(); }
+
+cfd_status cfd_scheme_named(const char *name, cfd_scheme **out) {
+    if (!name || !out) return fail(CFD_EINVAL, "cfd_scheme_named: null argument");
+    Scheme s;
+    std::string err;
+    cfd_status st = scheme_from_name(name, s, err);
+    if (st != CFD_OK) return fail(st, err);
+    *out = new cfd_scheme{s};
+    return CFD_OK;
+}
+
+cfd_status cfd_scheme_design(int d, int order, int nl, int m, double eta_c, int closure_mc, int matched,
+                             cfd_scheme **out) {
+    if (!out) return fail(CFD_EINVAL, "cfd_scheme_design: null output");
+    Scheme s;
+    std::string err;
+    cfd_status st = design_centred(d, order, nl, m, eta_c, closure_mc, matched, s, err);
+    if (st != CFD_OK) return fail(st, err);
+    if (nl > 0 && closure_mc == 0) s.nc = 0;
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "design(d=%d,order=%d,nl=%d,m=%d,eta_c=%g,mc=%d,%s)", d, order, nl, m, eta_c,
+                  closure_mc, matched ? "matched" : "order-only");
+    s.name = buf;
+    *out = new cfd_scheme{s};
+    return CFD_OK;
+}
+
+cfd_status cfd_scheme_create(int d, int order, int nl, const double *lhs, int m, const double *rhs, int nc, int mc,
+                             const double *closure, cfd_scheme **out) {
+    if (!out || !lhs || !rhs) return fail(CFD_EINVAL, "cfd_scheme_create: null argument");
+    if (d < 1 || d > 2 || order < 1 || nl < 0 || nl > kMaxNL || m < 0 || m > kMaxHalf || mc < 0 || mc > kMaxHalf)
+        return fail(CFD_EINVAL, "cfd_scheme_create: size out of range");
+    if (nc != nl) return fail(CFD_EINVAL, "cfd_scheme_create: closure rows must equal the implicit half-width");
+    if (nc > 0 && !closure) return fail(CFD_EINVAL, "cfd_scheme_create: closure rows missing");
+    if (std::fabs(lhs[nl] - 1.0) > 1e-15) return fail(CFD_EINVAL, "cfd_scheme_create: alpha^(d)_0 must be 1");
+    Scheme s;
+    s.d = d;
+    s.order = order;
+    s.nl = nl;
+    s.m = m;
+    s.nc = nc;
+    s.mc = mc;
+    for (int j = -nl; j <= nl; ++j) s.lhs[kMaxNL + j] = lhs[nl + j];
+    for (int k = -m; k <= m; ++k) s.rhs[kMaxHalf + k] = rhs[m + k];
+    for (int r = 0; r < nc; ++r)
+        for (int k = -mc; k <= mc; ++k) s.cl[r][kMaxHalf + k] = closure[r * (2 * mc + 1) + mc + k];
+    std::string err;
+    cfd_status st = check_taylor(s, err);
+    if (st != CFD_OK) return fail(st, "cfd_scheme_create: " + err);
+    s.name = "custom";
+    *out = new cfd_scheme{s};
+    return CFD_OK;
+}
+
+cfd_status cfd_scheme_get(const cfd_scheme *sc, int *d, int *order, int *nl, int *m, int *nc, int *mc,
+                          double *lhs5, double *rhs11, double *closure22) {
+    if (!sc) return fail(CFD_EINVAL, "cfd_scheme_get: null scheme");
+    const Scheme &s = sc->s;
+    if (d) *d = s.d;
+    if (order) *order = s.order;
+    if (nl) *nl = s.nl;
+    if (m) *m = s.m;
+    if (nc) *nc = s.nc;
+    if (mc) *mc = s.mc;
+    if (lhs5) std::memcpy(lhs5, s.lhs, sizeof s.lhs);
+    if (rhs11) std::memcpy(rhs11, s.rhs, sizeof s.rhs);
+    if (closure22) std::memcpy(closure22, s.cl, sizeof s.cl);
+    return CFD_OK;
+}
+
+cfd_status cfd_scheme_required_ghosts(const cfd_scheme *sc, cfd_boundary b, int *ng) {
+    if (!sc || !ng) return fail(CFD_EINVAL, "cfd_scheme_required_ghosts: null argument");
+    if (b != CFD_BOUNDARY_CLOSURE && b != CFD_BOUNDARY_PERIODIC)
+        return fail(CFD_EINVAL, "cfd_scheme_required_ghosts: unknown boundary kind");
+    *ng = required_ghosts(sc->s, b == CFD_BOUNDARY_PERIODIC);
+    return CFD_OK;
+}
+
+void cfd_scheme_destroy(cfd_scheme *s) { delete s; }
+
+cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
+    if (!desc || !out) return fail(CFD_EINVAL, "cfd_plan_create: null argument");
+    if (desc->nblocks < 1 || !desc->blocks) return fail(CFD_EINVAL, "cfd_plan_create: no blocks");
+    if (desc->nfields < 1) return fail(CFD_EINVAL, "cfd_plan_create: nfields < 1");
+    if (desc->nops < 1 || !desc->ops) return fail(CFD_EINVAL, "cfd_plan_create: no operators");
+    if (desc->dtype != CFD_F64 && desc->dtype != CFD_F32 && desc->dtype != CFD_MIXED_BF16)
+        return fail(CFD_EINVAL, "cfd_plan_create: unknown dtype");
+    if (desc->dtype == CFD_MIXED_BF16)
+        return fail(CFD_EUNSUPPORTED, "cfd_plan_create: the dense mixed-precision path is created with "
+                                      "cfd_dense_plan_create");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(CFD_EDEVICE, "cfd_plan_create: no HIP device");
+    }
+    if (desc->device < 0 || desc->device >= ndev) return fail(CFD_EINVAL, "cfd_plan_create: bad device ordinal");
+
+    std::unique_ptr<cfd_plan> p(new cfd_plan);
+    p->device = desc->device;
+    p->dtype = desc->dtype;
+    p->nfields = desc->nfields;
+    p->blocks.assign(desc->blocks, desc->blocks + desc->nblocks);
+    p->ops.assign(desc->ops, desc->ops + desc->nops);
+    for (const cfd_op &op : p->ops) {
+        if (!op.scheme) return fail(CFD_EINVAL, "cfd_plan_create: operator without scheme");
+        if (op.dir < 0 || op.dir > 2) return fail(CFD_EINVAL, "cfd_plan_create: operator direction not in 0..2");
+        if (op.field < -1 || op.field >= desc->nfields)
+            return fail(CFD_EINVAL, "cfd_plan_create: operator field out of range");
+        p->schemes.push_back(op.scheme->s);
+    }
+    int64_t slot = 0;
+    for (const cfd_op &op : p->ops) {
+        int nf = op.field < 0 ? desc->nfields : 1;
+        p->op_nf.push_back(nf);
+        p->op_slot.push_back(slot);
+        slot += nf;
+    }
+    // validate blocks, resolve offsets
+    int64_t in_cur = 0, out_cur = 0;
+    for (size_t b = 0; b < p->blocks.size(); ++b) {
+        const cfd_block &bl = p->blocks[b];
+        for (int d = 0; d < 3; ++d) {
+            if (bl.n[d] < 1) return fail(CFD_ESHAPE, "cfd_plan_create: block extent < 1");
+            if (!(bl.h[d] > 0)) return fail(CFD_EINVAL, "cfd_plan_create: grid spacing must be positive");
+            if (bl.boundary[d] != CFD_BOUNDARY_CLOSURE && bl.boundary[d] != CFD_BOUNDARY_PERIODIC)
+                return fail(CFD_EINVAL, "cfd_plan_create: unknown boundary kind");
+        }
+        if (bl.ng < 0) return fail(CFD_EINVAL, "cfd_plan_create: negative ghost width");
+        const int64_t ng = bl.ng;
+        const int64_t in_n = (int64_t)desc->nfields * (bl.n[0] + 2 * ng) * (bl.n[1] + 2 * ng) * (bl.n[2] + 2 * ng);
+        const int64_t out_n = slot * (int64_t)bl.n[0] * bl.n[1] * bl.n[2];
+        if ((bl.in_offset < 0) != (bl.out_offset < 0))
+            return fail(CFD_EINVAL, "cfd_plan_create: give both offsets of a block or neither");
+        int64_t io = bl.in_offset < 0 ? in_cur : bl.in_offset;
+        int64_t oo = bl.out_offset < 0 ? out_cur : bl.out_offset;
+        p->in_off.push_back(io);
+        p->out_off.push_back(oo);
+        in_cur = std::max(in_cur, io + in_n);
+        out_cur = std::max(out_cur, oo + out_n);
+        for (size_t o = 0; o < p->ops.size(); ++o) {
+            const Scheme &s = p->schemes[o];
+            const int d = p->ops[o].dir;
+            const int per = bl.boundary[d] == CFD_BOUNDARY_PERIODIC;
+            const int need = required_ghosts(s, per);
+            if (bl.ng < need) {
+                char buf[200];
+                std::snprintf(buf, sizeof buf,
+                              "block %zu: scheme '%s' needs %d ghost layers along direction %d, block has %d", b,
+                              s.name.c_str(), need, d, bl.ng);
+                return fail(CFD_EGHOST, buf);
+            }
+            const int N = bl.n[d];
+            if (!per && s.nl > 0 && N < 2 * s.nc + 1) {
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "block %zu: %d nodes along direction %d, closure needs >= %d", b, N,
+                              d, 2 * s.nc + 1);
+                return fail(CFD_ESHAPE, buf);
+            }
+            if (per && N < std::max(2 * s.nl + 1, std::max(s.m, s.mc))) {
+                return fail(CFD_ESHAPE, "periodic line shorter than the stencil");
+            }
+        }
+    }
+    p->in_elems = in_cur;
+    p->out_elems = out_cur;
+    if (in_cur > (int64_t(1) << 40) || out_cur > (int64_t(1) << 40))
+        return fail(CFD_EINVAL, "cfd_plan_create: layout too large");
+
+    // passes: per block and direction, group operators by field selection and
+    // fuse an odd-degree with an even-degree operator of equal band
+    for (size_t b = 0; b < p->blocks.size(); ++b) {
+        const cfd_block &bl = p->blocks[b];
+        for (int d = 0; d < 3; ++d) {
+            std::vector<int> ops_d;
+            for (size_t o = 0; o < p->ops.size(); ++o)
+                if (p->ops[o].dir == d) ops_d.push_back((int)o);
+            std::vector<bool> used(p->ops.size(), false);
+            for (int o : ops_d) {
+                if (used[o]) continue;
+                used[o] = true;
+                PassHost ps;
+                ps.block = (int)b;
+                ps.dir = d;
+                ps.field0 = p->ops[o].field < 0 ? 0 : p->ops[o].field;
+                ps.nfield = p->ops[o].field < 0 ? p->nfields : 1;
+                ps.N = bl.n[d];
+                ps.periodic = bl.boundary[d] == CFD_BOUNDARY_PERIODIC;
+                const Scheme &s0 = p->schemes[o];
+                ps.nl = s0.nl;
+                ps.nops = 1;
+                ps.op[0] = o;
+                ps.sch[0] = o;
+                int partner = -1;
+                for (int o2 : ops_d) {
+                    if (used[o2] || p->ops[o2].field != p->ops[o].field) continue;
+                    const Scheme &s1 = p->schemes[o2];
+                    if (s1.nl != s0.nl || s0.nl == 0 || (s0.d % 2) == (s1.d % 2)) continue;
+                    partner = o2;
+                    break;
+                }
+                if (partner >= 0) {
+                    used[partner] = true;
+                    ps.nops = 2;
+                    int odd = (s0.d % 2) ? o : partner, even = (s0.d % 2) ? partner : o;
+                    ps.op[0] = odd;
+                    ps.sch[0] = odd;
+                    ps.op[1] = even;
+                    ps.sch[1] = even;
+                    ps.par = 1;
+                } else {
+                    ps.par = (s0.d % 2) ? 1 : 0;
+                }
+                ps.mi = 0;
+                ps.hw = 0;
+                for (int k = 0; k < ps.nops; ++k) {
+                    const Scheme &s = p->schemes[ps.sch[k]];
+                    ps.mi = std::max(ps.mi, s.m);
+                    ps.hw = std::max(ps.hw, std::max(s.m, ps.periodic ? 0 : s.mc));
+                }
+                p->passes.push_back(ps);
+            }
+        }
+    }
+    HIPCHK(hipSetDevice(p->device));
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) p->cus = prop.multiProcessorCount;
+        (void)hipGetLastError();
+    }
+    cfd_status st = build(p.get());
+    if (st != CFD_OK) {
+        p->release();
+        return st;
+    }
+    *out = p.release();
+    return CFD_OK;
+}
+
+cfd_status cfd_plan_sizes(const cfd_plan *p, long long *in_elems, long long *out_elems) {
+    if (!p) return fail(CFD_EINVAL, "cfd_plan_sizes: null plan");
+    if (in_elems) *in_elems = p->in_elems;
+    if (out_elems) *out_elems = p->out_elems;
+    return CFD_OK;
+}
+
+cfd_status cfd_plan_offsets(const cfd_plan *p, long long *in_offsets, long long *out_offsets) {
+    if (!p) return fail(CFD_EINVAL, "cfd_plan_offsets: null plan");
+    for (size_t b = 0; b < p->blocks.size(); ++b) {
+        if (in_offsets) in_offsets[b] = p->in_off[b];
+        if (out_offsets) out_offsets[b] = p->out_off[b];
+    }
+    return CFD_OK;
+}
+
+cfd_status cfd_plan_stats(const cfd_plan *p, int *launches, long long *items) {
+    if (!p) return fail(CFD_EINVAL, "cfd_plan_stats: null plan");
+    if (launches) *launches = (int)p->groups.size();
+    if (items) *items = p->nitems;
+    return CFD_OK;
+}
+
+cfd_status cfd_apply(cfd_plan *p, const void *in_dev, void *out_dev, void *stream) {
+    if (!p || !in_dev || !out_dev) return fail(CFD_EINVAL, "cfd_apply: null argument");
+    const size_t es = elem_size(p->dtype);
+    if (((uintptr_t)in_dev % es) || ((uintptr_t)out_dev % es))
+        return fail(CFD_EINVAL, "cfd_apply: misaligned buffer");
+    HIPCHK(hipSetDevice(p->device));
+    return enqueue(p, in_dev, out_dev, (hipStream_t)stream);
+}
+
+cfd_status cfd_plan_capture_graph(cfd_plan *p, const void *in_dev, void *out_dev, void *stream) {
+    (void)stream;
+    if (!p || !in_dev || !out_dev) return fail(CFD_EINVAL, "cfd_plan_capture_graph: null argument");
+    HIPCHK(hipSetDevice(p->device));
+    p->drop_graph();
+    if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    cfd_status st = enqueue(p, in_dev, out_dev, p->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st != CFD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    p->graph = g;
+    e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        p->drop_graph();
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return CFD_OK;
+}
+
+cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream) {
+    if (!p) return fail(CFD_EINVAL, "cfd_plan_launch_graph: null plan");
+    if (!p->gexec) return fail(CFD_EINVAL, "cfd_plan_launch_graph: no graph captured");
+    HIPCHK(hipSetDevice(p->device));
+    HIPCHK(hipGraphLaunch(p->gexec, (hipStream_t)stream));
+    return CFD_OK;
+}
+
+cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int L, int persistent) {
+    if (!p) return fail(CFD_EINVAL, "cfd_plan_set_schedule: null plan");
+    if (N > 0) {
+        if (L > 0) {
+            bool ok_any = false;
+            for (const PassHost &ps : p->passes) {
+                if (ps.N != N) continue;
+                std::vector<int> c = candidate_Ls(ps, p->dtype != CFD_F64);
+                if (std::find(c.begin(), c.end(), L) == c.end())
+                    return fail(CFD_EINVAL, "cfd_plan_set_schedule: no compiled kernel for this partition length");
+                ok_any = true;
+            }
+            if (!ok_any) return fail(CFD_EINVAL, "cfd_plan_set_schedule: no line of that length in the plan");
+            p->sched_L[N] = L;
+        } else {
+            p->sched_L.erase(N);
+        }
+    }
+    p->persistent = persistent != 0;
+    return build(p);
+}
+
+cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, void *stream, const char *cache_path) {
+    if (!p || !in_dev || !out_dev) return fail(CFD_EINVAL, "cfd_plan_autotune: null argument");
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t st = (hipStream_t)stream;
+    std::string arch = "gfx";
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+        (void)hipGetLastError();
+    }
+    const char *dt = p->dtype == CFD_F64 ? "f64" : "f32";
+    // keys: one per distinct (N, nl, nops) class
+    std::map<std::tuple<int, int, int>, std::vector<int>> classes;
+    for (const PassHost &ps : p->passes)
+        classes[std::make_tuple(ps.N, ps.nl, ps.nops)] = candidate_Ls(ps, p->dtype != CFD_F64);
+    std::map<std::string, std::pair<int, int>> cache;
+    if (cache_path) {
+        std::ifstream f(cache_path);
+        std::string key;
+        int L, pers;
+        while (f >> key >> L >> pers) cache[key] = {L, pers};
+    }
+    auto keyof = [&](int N, int nl, int nops) {
+        std::ostringstream s;
+        s << arch << ":" << dt << ":N" << N << ":nl" << nl << ":ops" << nops;
+        return s.str();
+    };
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto time_apply = [&](float &ms) -> cfd_status {
+        for (int w = 0; w < 2; ++w) {
+            cfd_status s = enqueue(p, in_dev, out_dev, st);
+            if (s != CFD_OK) return s;
+        }
+        const int reps = 5;
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) {
+            cfd_status s = enqueue(p, in_dev, out_dev, st);
+            if (s != CFD_OK) return s;
+        }
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        ms /= reps;
+        return CFD_OK;
+    };
+    std::vector<std::string> new_lines;
+    cfd_status result = CFD_OK;
+    for (auto &kv : classes) {
+        const int N = std::get<0>(kv.first);
+        const std::string key = keyof(N, std::get<1>(kv.first), std::get<2>(kv.first));
+        auto hit = cache.find(key);
+        if (hit != cache.end() &&
+            std::find(kv.second.begin(), kv.second.end(), hit->second.first) != kv.second.end()) {
+            p->sched_L[N] = hit->second.first;
+            continue;
+        }
+        float best = 1e30f;
+        int bestL = kv.second.empty() ? 0 : kv.second[0];
+        for (int L : kv.second) {
+            p->sched_L[N] = L;
+            result = build(p);
+            if (result != CFD_OK) break;
+            float ms;
+            result = time_apply(ms);
+            if (result != CFD_OK) break;
+            if (ms < best) { best = ms; bestL = L; }
+        }
+        if (result != CFD_OK) break;
+        p->sched_L[N] = bestL;
+        new_lines.push_back(key + " " + std::to_string(bestL) + " 1");
+    }
+    if (result == CFD_OK) {
+        // persistent grid versus one workgroup per item
+        float t_p = 0, t_n = 0;
+        p->persistent = true;
+        result = build(p);
+        if (result == CFD_OK) result = time_apply(t_p);
+        if (result == CFD_OK) {
+            p->persistent = false;
+            result = time_apply(t_n);
+            p->persistent = t_p <= t_n;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != CFD_OK) return result;
+    if (cache_path && !new_lines.empty()) {
+        std::ofstream f(cache_path, std::ios::app);
+        for (const std::string &l : new_lines) f << l << "\n";
+    }
+    return build(p);
+}
+
+cfd_status cfd_halo_exchange(cfd_plan *p, void *data_dev, int bx, int by, int bz, void *stream) {
+    if (!p || !data_dev) return fail(CFD_EINVAL, "cfd_halo_exchange: null argument");
+    if (bx < 1 || by < 1 || bz < 1 || (int64_t)bx * by * bz != (int64_t)p->blocks.size())
+        return fail(CFD_EINVAL, "cfd_halo_exchange: lattice does not match the plan's block count");
+    const cfd_block &b0 = p->blocks[0];
+    for (const cfd_block &b : p->blocks)
+        if (b.n[0] != b0.n[0] || b.n[1] != b0.n[1] || b.n[2] != b0.n[2] || b.ng != b0.ng)
+            return fail(CFD_EINVAL, "cfd_halo_exchange: blocks differ in shape");
+    for (int d = 0; d < 3; ++d)
+        if (b0.ng > b0.n[d]) return fail(CFD_ESHAPE, "cfd_halo_exchange: ghost width exceeds block extent");
+    if (((uintptr_t)data_dev % elem_size(p->dtype))) return fail(CFD_EINVAL, "cfd_halo_exchange: misaligned buffer");
+    HIPCHK(hipSetDevice(p->device));
+    if (!p->d_inoff.p) {
+        HIPCHK(hipMalloc(&p->d_inoff.p, p->in_off.size() * sizeof(int64_t)));
+        HIPCHK(hipMemcpy(p->d_inoff.p, p->in_off.data(), p->in_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
+    hipError_t e = launch_halo(p->dtype != CFD_F64, data_dev, (const int64_t *)p->d_inoff.p, b0.n[0], b0.n[1],
+                               b0.n[2], b0.ng, p->nfields, bx, by, bz, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launching halo exchange");
+    return CFD_OK;
+}
+
+cfd_status cfd_axpby(cfd_dtype dtype, long long n, double a, const void *x_dev, double b, void *y_dev,
+                     void *stream) {
+    if (n < 0 || (n > 0 && (!x_dev || !y_dev))) return fail(CFD_EINVAL, "cfd_axpby: bad argument");
+    if (dtype != CFD_F64 && dtype != CFD_F32) return fail(CFD_EINVAL, "cfd_axpby: dtype must be F64 or F32");
+    hipError_t e = launch_axpby(dtype == CFD_F32, n, a, x_dev, b, y_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launching axpby");
+    return CFD_OK;
+}
+
+cfd_status cfd_xpcy(cfd_dtype dtype, long long n, const void *x_dev, double c, const void *y_dev, void *z_dev,
+                    void *stream) {
+    if (n < 0 || (n > 0 && (!x_dev || !y_dev || !z_dev))) return fail(CFD_EINVAL, "cfd_xpcy: bad argument");
+    if (dtype != CFD_F64 && dtype != CFD_F32) return fail(CFD_EINVAL, "cfd_xpcy: dtype must be F64 or F32");
+    hipError_t e = launch_xpcy(dtype == CFD_F32, n, x_dev, c, y_dev, z_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launching xpcy");
+    return CFD_OK;
+}
+
+void cfd_plan_destroy(cfd_plan *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    p->release();
+    delete p;
+}
+
+}  // extern "C"

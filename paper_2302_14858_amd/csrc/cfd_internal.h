@@ -1,0 +1,122 @@
+// Internal declarations of the MI355X compact finite-difference library.
+// Shared by the host runtime (cfd_host.cpp, scheme_design.cpp) and the
+// device code (cfd_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cfd.h"
+
+namespace cfd {
+
+constexpr int kMaxNL = 2;        // implicit half-width: tri (1) and penta (2)
+constexpr int kMaxHalf = 5;      // RHS / closure stencil half-width
+constexpr int kMaxP = 8;         // partitions per line
+constexpr int kWave = 64;        // CDNA wavefront
+
+// ---------------------------------------------------------------------------
+// Scheme (host only)
+// ---------------------------------------------------------------------------
+struct Scheme {
+    int d = 1;                   // derivative degree
+    int order = 0;               // formal order
+    int nl = 0;                  // implicit half-width
+    int m = 0;                   // interior RHS half-width
+    int nc = 0;                  // closure rows per end (= nl)
+    int mc = 0;                  // closure half-width
+    double lhs[2 * kMaxNL + 1] = {0};         // alpha^(d)_{-2..2}
+    double rhs[2 * kMaxHalf + 1] = {0};       // alpha^(0)_{-5..5}
+    double cl[kMaxNL][2 * kMaxHalf + 1] = {};  // closure rows k*_- + j, centred at 5
+    std::string name;
+};
+
+// Scheme construction (scheme_design.cpp).  Return CFD_OK or an error code
+// with the message in `err`.
+cfd_status design_centred(int d, int order, int nl, int m, double eta_c, int closure_mc,
+                          int matched, Scheme &out, std::string &err);
+cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &err);
+cfd_status check_taylor(const Scheme &s, std::string &err);
+int required_ghosts(const Scheme &s, int periodic);
+
+// ---------------------------------------------------------------------------
+// Device-side plan data (POD, shared with kernels)
+// ---------------------------------------------------------------------------
+
+// Table of one operator on one line class (line length N, partition count
+// P = N / L, boundary kind), elements of the plan's type:
+//   [0, 64)              coefficient block: interior stencil alpha^(0) (11,
+//                        centred), left closure rows (2 x 11), right closure
+//                        rows (2 x 11, mirror images), alpha^(d) (5)
+//   fac  [p][i][5]       partition-local LU of D_L (l1, l2, u1, u2, 1/d)
+//   spk  [p][2nl][L]     spike vectors: local response to the nl left and nl
+//                        right neighbour unknowns
+//   krow [p][2nl][B]     rows of the inverse of the reduced boundary system,
+//                        B = 2 nl P
+constexpr int kCoefA = 0;
+constexpr int kCoefCL = 11;
+constexpr int kCoefCR = 33;
+constexpr int kCoefAlpha = 55;
+constexpr int kCoefHdr = 64;
+
+inline int64_t table_elems(int N, int P, int nl) {
+    const int64_t L = N / P, B = 2 * nl * P;
+    if (nl == 0) return kCoefHdr;
+    return kCoefHdr + (int64_t)N * 5 + (int64_t)P * 2 * nl * L + (int64_t)P * 2 * nl * B;
+}
+
+// One (block, direction, operator-pass) descriptor, read by every workgroup
+// that processes lines of it.  Element offsets/strides.
+struct PassDesc {
+    int64_t in_base;        // input offset of field 0, interior node (0,0,0)
+    int64_t in_fstride;     // input elements per field
+    int64_t out_base[2];    // output offset of each op's first field
+    int64_t out_fstride;    // output elements per field (= nx ny nz)
+    int32_t su, sv, sd;     // input strides along the line's u, v and along the line
+    int32_t osu, osv, osd;  // output strides
+    int32_t nu, nlines;     // lines: u fastest; nlines = nu * nv
+    int32_t N, ng;          // line length, ghost layers
+    int32_t periodic;
+    int32_t nfield_pass;    // fields this pass covers
+    int32_t field0;         // first field index
+    int32_t tab[2];         // table index per op
+    double hinv[2];         // h^-d per op
+};
+
+// One work item: 64 lines of one field of one pass.
+struct WorkItem {
+    int32_t pass;
+    int32_t field;
+    int32_t line0;
+    int32_t pad;
+};
+
+}  // namespace cfd
+
+// ---------------------------------------------------------------------------
+// Device entry points (cfd_kernels.hip)
+// ---------------------------------------------------------------------------
+#include <hip/hip_runtime_api.h>
+
+namespace cfd {
+const void *find_line_kernel(int f32, int nl, int L, int nops, int par, int mi, int hw, int *mi_out,
+                             int *hw_out);
+int line_kernel_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap);
+hipError_t launch_lines(const void *fn, int grid, int P, size_t lds, hipStream_t st, const WorkItem *items,
+                        int nitems, const PassDesc *passes, const void *tabs, const int64_t *taboff,
+                        const void *in, void *out);
+hipError_t launch_build_tables(int ntab, const void *specs, double *data, double *scratch, int64_t scratch_per,
+                               int *status, hipStream_t st);
+hipError_t launch_to_f32(int64_t n, const double *a, float *b, hipStream_t st);
+size_t tabspec_size();
+void fill_tabspec(void *dst, int N, int P, int L, int nl, int nc, int periodic, const double *alpha5,
+                  int64_t off);
+}  // namespace cfd
+
+namespace cfd {
+hipError_t launch_halo(int f32, void *data, const int64_t *off_dev, int nx, int ny, int nz, int ng, int nfields,
+                       int bx, int by, int bz, hipStream_t st);
+hipError_t launch_axpby(int f32, int64_t n, double a, const void *x, double b, void *y, hipStream_t st);
+hipError_t launch_xpcy(int f32, int64_t n, const void *x, double c, const void *y, void *z, hipStream_t st);
+}  // namespace cfd

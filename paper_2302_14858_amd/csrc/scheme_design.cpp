@@ -1,0 +1,467 @@
+// Scheme construction for the compact finite-difference library, on the host
+// in binary128 (__float128) arithmetic.
+//
+// Follows arXiv 2302.14858, Sec. 2 and 2.4:
+//  * centred schemes of Eq. mdAnsatz with d_I = (0): alpha^(d) of half-width nl
+//    (alpha^(d)_0 = 1) and alpha^(0) of half-width m;
+//  * Taylor matching (Eq. Tcons) up to the formal order;
+//  * when coefficients remain free, minimisation of the spectral error of
+//    Eqs. sp_error / optfunc with the cut-off weight of Eq. gammacut;
+//  * explicit closures of Sec. 2.4: Taylor conditions, plus, for the matched
+//    variant, the lowest error constant of the interior scheme
+//    (Eq. errrelmodwavcent) imposed on the closure (the odd power that follows
+//    vanishes by symmetry for a centred stencil).
+//
+// Centred schemes are parametrised by their symmetry from the start: alpha^(d)
+// is symmetric, alpha^(0) is antisymmetric for odd d and symmetric for even d.
+// The spectral error of such a scheme is a real function of eta, and the
+// constrained quadratic minimisation is solved in the null space of the Taylor
+// conditions with Gauss-Legendre quadrature on [0, eta_c].
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cfd_internal.h"
+
+namespace cfd {
+namespace {
+
+typedef __float128 q;
+
+q qabs(q x) { return x < 0 ? -x : x; }
+
+// pi to 36 significant digits
+const q kPi = (q)3.14159265358979323846264338327950288Q;
+
+// sin / cos by reduction to [-pi, pi] and the Taylor series (enough terms for
+// binary128 on that interval).
+void qsincos(q x, q &s, q &c) {
+    q twopi = 2 * kPi;
+    q k = (q)(long long)(x / twopi + (x >= 0 ? (q)0.5 : (q)-0.5));
+    x -= k * twopi;
+    q term = x, sum_s = x;
+    q termc = 1, sum_c = 1;
+    q x2 = x * x;
+    for (int n = 1; n < 60; ++n) {
+        term *= -x2 / ((2 * n) * (2 * n + 1));
+        termc *= -x2 / ((2 * n - 1) * (2 * n));
+        sum_s += term;
+        sum_c += termc;
+    }
+    s = sum_s;
+    c = sum_c;
+}
+
+q qpow_int(q x, int p) {
+    q r = 1;
+    for (int i = 0; i < p; ++i) r *= x;
+    return r;
+}
+
+q qfact(int n) {
+    q r = 1;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+}
+
+// Gauss-Legendre nodes and weights on [a, b] (Newton on P_n).
+void gauss_legendre(int n, q a, q b, std::vector<q> &x, std::vector<q> &w) {
+    x.assign(n, 0);
+    w.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        q z = (q)std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        q pp = 0;
+        for (int it = 0; it < 100; ++it) {
+            q p0 = 1, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                q p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            // p1 = P_n(z), p0 = P_{n-1}(z)
+            pp = n * (z * p1 - p0) / (z * z - 1);
+            q dz = p1 / pp;
+            z -= dz;
+            if (qabs(dz) < (q)1e-33Q) break;
+        }
+        x[i] = (a + b) / 2 + (b - a) / 2 * z;
+        w[i] = (b - a) / ((1 - z * z) * pp * pp);
+    }
+}
+
+// Dense solve with partial pivoting; A is n x n row-major.  false if singular.
+bool qsolve(int n, std::vector<q> A, std::vector<q> &b) {
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (qabs(A[r * n + c]) > qabs(A[p * n + c])) p = r;
+        if (qabs(A[p * n + c]) < (q)1e-60Q) return false;
+        if (p != c) {
+            for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[p * n + k]);
+            std::swap(b[c], b[p]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            q f = A[r * n + c] / A[c * n + c];
+            if (f == 0) continue;
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        q s = b[c];
+        for (int k = c + 1; k < n; ++k) s -= A[c * n + k] * b[k];
+        b[c] = s / A[c * n + c];
+    }
+    return true;
+}
+
+// Unknowns of a centred scheme: alpha_1..alpha_nl, then the RHS parameters
+// b_{m0}..b_m (m0 = 1 for odd d, 0 for even d).  a_{+-k} = (+-1)^d b_k.
+struct Centred {
+    int d, nl, m;
+    int m0() const { return (d % 2) ? 1 : 0; }
+    int nunk() const { return nl + (m - m0() + 1); }
+};
+
+// Taylor row l of Eq. Tcons for a centred scheme, as coefficients of the
+// unknowns plus a constant (the alpha_0 = 1 contribution):
+//   sum_k a_k k^l / l!  -  sum_j alpha_j j^(l-d)/(l-d)!  = 0.
+void taylor_row(const Centred &c, int l, std::vector<q> &row, q &cst) {
+    row.assign(c.nunk(), 0);
+    cst = 0;
+    // alpha part (symmetric): j = 0 gives 1 when l == d; j = +-1.. gives 2 j^(l-d)/(l-d)! for even l-d
+    if (l >= c.d) {
+        int p = l - c.d;
+        if (p == 0) cst -= 1;  // alpha_0 = 1 moved to the constant (with the minus sign)
+        if (p % 2 == 0)
+            for (int j = 1; j <= c.nl; ++j) row[j - 1] -= 2 * qpow_int(j, p) / qfact(p);
+    }
+    // RHS part: sum_k a_k k^l with a antisymmetric (odd d) or symmetric (even d)
+    for (int k = c.m0(); k <= c.m; ++k) {
+        q v;
+        if (k == 0) v = (l == 0) ? 1 : 0;
+        else if ((c.d % 2) == 1) v = (l % 2 == 1) ? 2 * qpow_int(k, l) : 0;
+        else v = (l % 2 == 0) ? 2 * qpow_int(k, l) : 0;
+        row[c.nl + (k - c.m0())] += v / qfact(l);
+    }
+}
+
+bool row_trivial(const std::vector<q> &row, q cst) {
+    if (cst != 0) return false;
+    for (q v : row)
+        if (v != 0) return false;
+    return true;
+}
+
+// Real spectral error e(eta) = g(eta).u + g0(eta) of a centred scheme
+// (Eq. sp_error up to a unit factor i for odd d).
+void spectral_basis(const Centred &c, q eta, std::vector<q> &g, q &g0) {
+    g.assign(c.nunk(), 0);
+    if (c.d == 1) {
+        // e~ = i [ 2 sum b_k sin(k eta) - eta (1 + 2 sum alpha_j cos(j eta)) ]
+        g0 = -eta;
+        for (int j = 1; j <= c.nl; ++j) {
+            q s, co;
+            qsincos(j * eta, s, co);
+            g[j - 1] = -2 * eta * co;
+        }
+        for (int k = 1; k <= c.m; ++k) {
+            q s, co;
+            qsincos(k * eta, s, co);
+            g[c.nl + k - 1] = 2 * s;
+        }
+    } else {
+        // e~ = b_0 + 2 sum b_k cos(k eta) + eta^2 (1 + 2 sum alpha_j cos(j eta))
+        g0 = eta * eta;
+        for (int j = 1; j <= c.nl; ++j) {
+            q s, co;
+            qsincos(j * eta, s, co);
+            g[j - 1] = 2 * eta * eta * co;
+        }
+        for (int k = 0; k <= c.m; ++k) {
+            q s, co;
+            qsincos(k * eta, s, co);
+            g[c.nl + k] = (k == 0) ? (q)1 : 2 * co;
+        }
+    }
+}
+
+// Solve the (possibly underdetermined) constraint set C u = rhs by
+// Gauss-Jordan with full pivoting; returns a particular solution and a basis
+// of the null space.  false if inconsistent.
+bool null_space(int nr, int n, std::vector<q> C, std::vector<q> rhs, std::vector<q> &up,
+                std::vector<std::vector<q>> &Z) {
+    std::vector<int> pivcol;
+    int r = 0;
+    std::vector<bool> used(n, false);
+    for (int c = 0; c < n && r < nr; ++c) {
+        int p = -1;
+        q best = 0;
+        for (int i = r; i < nr; ++i)
+            if (qabs(C[i * n + c]) > best) { best = qabs(C[i * n + c]); p = i; }
+        if (p < 0 || best < (q)1e-40Q) continue;
+        for (int k = 0; k < n; ++k) std::swap(C[r * n + k], C[p * n + k]);
+        std::swap(rhs[r], rhs[p]);
+        q pv = C[r * n + c];
+        for (int k = 0; k < n; ++k) C[r * n + k] /= pv;
+        rhs[r] /= pv;
+        for (int i = 0; i < nr; ++i) {
+            if (i == r) continue;
+            q f = C[i * n + c];
+            if (f == 0) continue;
+            for (int k = 0; k < n; ++k) C[i * n + k] -= f * C[r * n + k];
+            rhs[i] -= f * rhs[r];
+        }
+        pivcol.push_back(c);
+        used[c] = true;
+        ++r;
+    }
+    for (int i = r; i < nr; ++i)
+        if (qabs(rhs[i]) > (q)1e-28Q) return false;
+    up.assign(n, 0);
+    for (int i = 0; i < r; ++i) up[pivcol[i]] = rhs[i];
+    Z.clear();
+    for (int f = 0; f < n; ++f) {
+        if (used[f]) continue;
+        std::vector<q> z(n, 0);
+        z[f] = 1;
+        for (int i = 0; i < r; ++i) z[pivcol[i]] = -C[i * n + f];
+        Z.push_back(z);
+    }
+    return true;
+}
+
+q dot(const std::vector<q> &a, const std::vector<q> &b) {
+    q s = 0;
+    for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+    return s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+cfd_status design_centred(int d, int order, int nl, int m, double eta_c, int closure_mc,
+                          int matched, Scheme &out, std::string &err) {
+    if (d < 1 || d > 2 || order < 2 || order % 2 || nl < 0 || nl > kMaxNL || m < 1 ||
+        m > kMaxHalf || closure_mc < 0 || closure_mc > kMaxHalf) {
+        err = "scheme design: unsupported d/order/nl/m/closure size";
+        return CFD_EINVAL;
+    }
+    Centred c{d, nl, m};
+    const int n = c.nunk();
+    // Taylor rows l = 0 .. order + d - 1 that are not identically zero by symmetry
+    std::vector<q> C, rhs;
+    int nr = 0;
+    for (int l = 0; l < order + d; ++l) {
+        std::vector<q> row;
+        q cst;
+        taylor_row(c, l, row, cst);
+        if (row_trivial(row, cst)) continue;
+        C.insert(C.end(), row.begin(), row.end());
+        rhs.push_back(-cst);
+        ++nr;
+    }
+    std::vector<q> up;
+    std::vector<std::vector<q>> Z;
+    if (!null_space(nr, n, C, rhs, up, Z)) {
+        err = "scheme design: Taylor conditions are inconsistent";
+        return CFD_ESINGULAR;
+    }
+    std::vector<q> u = up;
+    if (!Z.empty()) {
+        if (!(eta_c > 0) || eta_c > M_PI + 1e-12) {
+            err = "scheme design: free coefficients need 0 < eta_c <= pi";
+            return CFD_EINVAL;
+        }
+        // eta_c given as double; recognise 4pi/5 and pi exactly
+        q ec = (q)eta_c;
+        if (std::fabs(eta_c - 4 * M_PI / 5) < 1e-12) ec = 4 * kPi / 5;
+        if (std::fabs(eta_c - M_PI) < 1e-12) ec = kPi;
+        std::vector<q> xs, ws;
+        gauss_legendre(48, 0, ec, xs, ws);
+        const int nf = (int)Z.size();
+        std::vector<q> H(nf * nf, 0), h(nf, 0);
+        for (size_t t = 0; t < xs.size(); ++t) {
+            std::vector<q> g;
+            q g0;
+            spectral_basis(c, xs[t], g, g0);
+            q e0 = dot(g, up) + g0;
+            std::vector<q> ez(nf);
+            for (int i = 0; i < nf; ++i) ez[i] = dot(g, Z[i]);
+            for (int i = 0; i < nf; ++i) {
+                h[i] -= ws[t] * ez[i] * e0;
+                for (int j = 0; j < nf; ++j) H[i * nf + j] += ws[t] * ez[i] * ez[j];
+            }
+        }
+        if (!qsolve(nf, H, h)) {
+            err = "scheme design: spectral objective is degenerate";
+            return CFD_ESINGULAR;
+        }
+        for (int i = 0; i < nf; ++i)
+            for (int k = 0; k < n; ++k) u[k] += h[i] * Z[i][k];
+    }
+    Scheme s;
+    s.d = d;
+    s.order = order;
+    s.nl = nl;
+    s.m = m;
+    s.lhs[kMaxNL] = 1.0;
+    q dn0 = 1;  // alpha . E at eta = 0
+    for (int j = 1; j <= nl; ++j) {
+        s.lhs[kMaxNL + j] = s.lhs[kMaxNL - j] = (double)u[j - 1];
+        dn0 += 2 * u[j - 1];
+    }
+    std::vector<q> a(2 * kMaxHalf + 1, 0);
+    for (int k = c.m0(); k <= m; ++k) {
+        q b = u[nl + k - c.m0()];
+        a[kMaxHalf + k] = b;
+        a[kMaxHalf - k] = (d % 2 && k > 0) ? -b : b;
+    }
+    for (int k = -kMaxHalf; k <= kMaxHalf; ++k) s.rhs[kMaxHalf + k] = (double)a[kMaxHalf + k];
+
+    // Error constant of the interior scheme: T_{q+d} / (alpha . E)(0), with
+    // T_l the Taylor residual of row l (the eta^q coefficient of eps up to i^q).
+    q Tqd = 0;
+    {
+        int l = order + d;
+        for (int k = -m; k <= m; ++k) Tqd += a[kMaxHalf + k] * qpow_int(k, l) / qfact(l);
+        // alpha part
+        for (int j = -nl; j <= nl; ++j) {
+            q al = (j == 0) ? (q)1 : u[std::abs(j) - 1];
+            Tqd -= al * qpow_int(j, order) / qfact(order);
+        }
+    }
+
+    if (nl > 0 && closure_mc > 0) {
+        // closure unknowns: c_1..c_mc (odd d) or c_0..c_mc (even d)
+        Centred cc{d, 0, closure_mc};
+        const int ncu = cc.nunk();
+        std::vector<q> CC, rr;
+        int nrc = 0;
+        for (int l = 0; l < order + d; ++l) {
+            std::vector<q> row;
+            q cst;
+            taylor_row(cc, l, row, cst);
+            if (row_trivial(row, cst)) continue;
+            CC.insert(CC.end(), row.begin(), row.end());
+            rr.push_back(-cst);
+            ++nrc;
+        }
+        if (matched) {
+            std::vector<q> row;
+            q cst;
+            taylor_row(cc, order + d, row, cst);  // explicit: cst == 0 for l > d
+            CC.insert(CC.end(), row.begin(), row.end());
+            rr.push_back(Tqd / dn0);
+            ++nrc;
+        }
+        if (nrc != ncu) {
+            err = "scheme design: closure half-width does not match the number of closure conditions";
+            return CFD_EINVAL;
+        }
+        std::vector<q> sol = rr;
+        if (!qsolve(ncu, CC, sol)) {
+            err = "scheme design: closure conditions are singular";
+            return CFD_ESINGULAR;
+        }
+        double row[2 * kMaxHalf + 1] = {0};
+        for (int k = cc.m0(); k <= closure_mc; ++k) {
+            q b = sol[k - cc.m0()];
+            row[kMaxHalf + k] = (double)b;
+            row[kMaxHalf - k] = (double)((d % 2 && k > 0) ? -b : b);
+        }
+        s.nc = nl;
+        s.mc = closure_mc;
+        for (int j = 0; j < nl; ++j) std::memcpy(s.cl[j], row, sizeof(row));
+    }
+    out = s;
+    return CFD_OK;
+}
+
+cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &err) {
+    std::string base = name, variant;
+    size_t colon = name.find(':');
+    if (colon != std::string::npos) {
+        base = name.substr(0, colon);
+        variant = name.substr(colon + 1);
+    }
+    if (!(variant.empty() || variant == "E")) {
+        err = "unknown closure variant in scheme name '" + name + "'";
+        return CFD_EINVAL;
+    }
+    const bool order_only = (variant == "E");
+    if (base.size() < 5 || base[0] != '(' || base[2] != ')' || (base[1] != '1' && base[1] != '2')) {
+        err = "unknown scheme name '" + name + "'";
+        return CFD_EINVAL;
+    }
+    const int d = base[1] - '0';
+    const std::string kind = base.substr(3);
+    cfd_status st;
+    if (kind.size() == 4 && kind.compare(0, 3, "P1_") == 0 && kind[3] >= '1' && kind[3] <= '3') {
+        int M = kind[3] - '0';
+        int order = 2 * M + 2;
+        st = design_centred(d, order, 1, M, 0.0, order_only ? order / 2 : order / 2 + 1, !order_only, out, err);
+    } else if (kind == "Q1_3[1]" || kind == "Q1_3[4pi/5]") {
+        double ec = (kind == "Q1_3[1]") ? 1.0 : 4 * M_PI / 5;
+        st = design_centred(d, 6, 1, 3, ec, order_only ? 3 : 4, !order_only, out, err);
+    } else if (kind == "QP_O8[1]") {
+        st = design_centred(d, 8, 2, 3, 1.0, order_only ? 4 : 5, !order_only, out, err);
+    } else if (kind.size() == 2 && kind[0] == 'E' && kind[1] >= '1' && kind[1] <= '5' && !order_only) {
+        int M = kind[1] - '0';
+        st = design_centred(d, 2 * M, 0, M, 0.0, 0, 0, out, err);
+    } else {
+        err = "unknown scheme name '" + name + "'";
+        return CFD_EINVAL;
+    }
+    if (st == CFD_OK) out.name = name;
+    return st;
+}
+
+// Taylor check of every row of a scheme (Eq. Tcons): interior rows and the
+// explicit closure rows, up to the formal order.
+cfd_status check_taylor(const Scheme &s, std::string &err) {
+    double scale = 0;
+    for (double v : s.rhs) scale = std::fmax(scale, std::fabs(v));
+    const double tol = 1e-12 * std::fmax(1.0, scale);
+    for (int l = 0; l < s.order + s.d; ++l) {
+        long double res = 0;
+        for (int k = -kMaxHalf; k <= kMaxHalf; ++k)
+            res += (long double)s.rhs[kMaxHalf + k] * std::pow((long double)k, l) / std::tgamma(l + 1.0L);
+        if (l >= s.d)
+            for (int j = -kMaxNL; j <= kMaxNL; ++j)
+                res -= (long double)s.lhs[kMaxNL + j] * std::pow((long double)j, l - s.d) /
+                       std::tgamma(l - s.d + 1.0L);
+        if (std::fabs((double)res) > tol) {
+            char buf[128];
+            std::snprintf(buf, sizeof buf, "interior row violates Taylor condition l=%d (residual %.3g)", l,
+                          (double)res);
+            err = buf;
+            return CFD_EINVAL;
+        }
+        for (int j = 0; j < s.nc; ++j) {
+            long double rc = (l == s.d) ? -1.0L : 0.0L;
+            for (int k = -kMaxHalf; k <= kMaxHalf; ++k)
+                rc += (long double)s.cl[j][kMaxHalf + k] * std::pow((long double)k, l) / std::tgamma(l + 1.0L);
+            if (std::fabs((double)rc) > tol) {
+                char buf[128];
+                std::snprintf(buf, sizeof buf, "closure row %d violates Taylor condition l=%d", j, l);
+                err = buf;
+                return CFD_EINVAL;
+            }
+        }
+    }
+    return CFD_OK;
+}
+
+int required_ghosts(const Scheme &s, int periodic) {
+    if (periodic) return 0;
+    if (s.nl == 0) return s.m;
+    int need = s.m - s.nc;
+    for (int j = 0; j < s.nc; ++j) need = std::max(need, s.mc - j);
+    return need;
+}
+
+}  // namespace cfd
