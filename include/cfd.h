@@ -204,18 +204,30 @@ cfd_status cfd_plan_capture_graph(cfd_plan *p, const void *in_dev, void *out_dev
 /* Launch the captured graph on `stream`.  CFD_EINVAL if none was captured. */
 cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream);
 
-/* Time the candidate schedules (partition length per line length, persistent
- * or one-workgroup-per-item grids) on the given buffers and keep the fastest.
- * If cache_path is non-NULL the choice is read from / appended to that text
- * file, keyed by device arch, line length, direction class, dtype and band.
- * Synchronises the stream.  Invalidates a captured graph. */
+/* Schedule flags. */
+#define CFD_SCHED_PERSISTENT 1   /* grid of (occupancy x CUs) workgroups walking the work list */
+#define CFD_SCHED_SPLIT_X    2   /* lines along x in a launch of their own */
+
+/* Time the candidate schedules on the given buffers and keep the fastest:
+ * the number of partitions per line for every (line length, x or y/z) class,
+ * then the launch shape (persistent grid or one workgroup per item; x lines
+ * fused with y/z or split).  If cache_path is non-NULL the per-class choices
+ * are read from / appended to that text file, keyed by device arch, dtype,
+ * line length, direction class, band and fused operators.  Synchronises the
+ * stream.  Invalidates a captured graph. */
 cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, void *stream,
                              const char *cache_path);
 
-/* Choose the schedule by hand: partition length `L` for line length N (0 =
- * default), persistent grid on/off.  CFD_EINVAL if L does not divide N or
- * breaks the partition rules.  Invalidates a captured graph. */
-cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int L, int persistent);
+/* Choose the schedule by hand: lines of length N along x (xlines = 1) or along
+ * y/z (xlines = 0) are cut into `partitions` partitions (1, 2 or 4; 0 restores
+ * the default); flags is a set of CFD_SCHED_*.  N = 0 only sets the flags.
+ * CFD_EINVAL if no compiled kernel fits.  Invalidates a captured graph. */
+cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions, int flags);
+
+/* Read back the schedule: flags and, for up to cap line classes, their
+ * (N, xlines, partitions).  n_classes receives the number of classes. */
+cfd_status cfd_plan_get_schedule(const cfd_plan *p, int *persistent, int *split_x, int *n_classes, int *N,
+                                 int *xlines, int *partitions, int cap);
 
 void cfd_plan_destroy(cfd_plan *p);
 

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "cfd_internal.h"
+#include "cfd_kernels_reg.h"
 
 using namespace cfd;
 
@@ -75,22 +76,21 @@ struct PassHost {
     int op[2];        // plan op indices (output order)
     int sch[2];       // scheme indices
     int N, periodic, nl, par, mi, hw;
-    int L = 0, P = 0;
-    const void *fn = nullptr;
+    int P = 0, L = 0, lcode = 0;
+    const LineClass *cls = nullptr;
 };
 
 struct Group {
     const void *fn;
-    int P;
     size_t lds;
     int64_t item0, nitems;
     int grid_persist;
 };
 
 struct TabKey {
-    int sch, N, P, periodic;
+    int sch, N, P, L, periodic;
     bool operator<(const TabKey &o) const {
-        return std::tie(sch, N, P, periodic) < std::tie(o.sch, o.N, o.P, o.periodic);
+        return std::tie(sch, N, P, L, periodic) < std::tie(o.sch, o.N, o.P, o.L, o.periodic);
     }
 };
 
@@ -108,9 +108,11 @@ struct cfd_plan {
     std::vector<int64_t> in_off, out_off;
     int64_t in_elems = 0, out_elems = 0;
     std::vector<PassHost> passes;
-    std::map<int, int> sched_L;           // N -> L chosen by hand or autotune
+    std::map<std::pair<int, int>, int> sched_P;   // (N, x-direction) -> partitions per line
     bool persistent = true;
+    bool split_x = false;                 // x-lines in a launch of their own
     int cus = 256;
+    size_t max_lds = 65536;
     // device state rebuilt by build()
     DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff;
     std::vector<Group> groups;
@@ -142,26 +144,55 @@ namespace {
 
 size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }
 
-// Candidate partition lengths for a pass, best first.
-std::vector<int> candidate_Ls(const PassHost &ps, bool f32) {
+// Tile bytes an x item with P partitions of L rows needs in LDS.
+size_t x_tile_bytes(int P, int L, int hw, size_t es) {
+    return 256 * sizeof(int) + (size_t)(kWave * 4 / P) * (size_t)((P * L + 2 * hw) | 1) * es;
+}
+
+// Partition length for P partitions of an N-node line: the smallest compiled
+// L with P L >= N (P L == N for periodic lines) whose last partition holds
+// every right-closure row.  0 if none.
+int partition_length(const PassHost &ps, bool f32, int P) {
     int Ls[16];
-    int n = line_kernel_Ls(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, Ls, 16);
-    std::vector<int> ok;
+    const int n = line_class_Ls(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, Ls, 16);
+    int best = 0;
     for (int i = 0; i < n; ++i) {
-        int L = Ls[i];
-        if (ps.N % L) continue;
-        int P = ps.N / L;
-        if (P > kMaxP || P < 1) continue;
+        const int L = Ls[i];
+        if ((int64_t)P * L < ps.N) continue;
+        if (ps.periodic && P * L != ps.N) continue;
         if (ps.nl > 0 && L < 2 * ps.nl) continue;
-        if (!ps.periodic && ps.nl > 0 && P == 1 && L < 2 * ps.nl + 1) continue;
-        if (ps.periodic && ps.hw > ps.N) continue;
-        ok.push_back(L);
+        if ((P - 1) * L > ps.N - ps.nl) continue;   // every right-closure row in the last partition
+        if (P > 1 && (P - 1) * L >= ps.N) continue;                            // no empty partition
+        if (!best || L < best) best = L;
     }
-    // default preference: the largest L <= 24 (register budget), then larger ones
-    std::sort(ok.begin(), ok.end(), [](int a, int b) {
-        bool sa = a <= 24, sb = b <= 24;
+    return best;
+}
+
+// Candidate partition counts for a pass, best first.  A candidate needs a
+// compiled class with a fitting L, and (x lines) an LDS tile that fits next
+// to the exchange area.
+std::vector<int> candidate_Ps(const PassHost &ps, bool f32, size_t max_lds) {
+    std::vector<int> ok;
+    const size_t es = f32 ? 4 : 8;
+    for (int P = 1; P <= 4; P *= 2) {
+        const int L = partition_length(ps, f32, P);
+        if (!L) continue;
+        const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L);
+        if (!k) continue;
+        if (ps.periodic && k->hw > ps.N) continue;
+        size_t lds = (size_t)k->exch * es;
+        if (ps.dir == 0) lds += x_tile_bytes(P, L, k->hw, es);
+        if (lds > max_lds) continue;
+        ok.push_back(P);
+    }
+    // default preference: y/z lines: fewest partitions with L <= 24 (register
+    // budget); x lines: L <= 16 (LDS tile); then the rest in order
+    const int Lcap = ps.dir == 0 ? 16 : 24;
+    auto Lof = [&](int P) { return partition_length(ps, f32, P); };
+    std::stable_sort(ok.begin(), ok.end(), [&](int a, int b) {
+        const bool sa = Lof(a) <= Lcap, sb = Lof(b) <= Lcap;
         if (sa != sb) return sa;
-        return sa ? a > b : a < b;
+        return sa ? a < b : a > b;
     });
     return ok;
 }
@@ -170,23 +201,26 @@ cfd_status build(cfd_plan *p) {
     HIPCHK(hipSetDevice(p->device));
     p->drop_graph();
     const bool f32 = p->dtype != CFD_F64;
-    // 1. schedule and kernel variant of every pass
+    // 1. schedule and kernel class of every pass
     for (PassHost &ps : p->passes) {
-        std::vector<int> cands = candidate_Ls(ps, f32);
+        std::vector<int> cands = candidate_Ps(ps, f32, p->max_lds);
         if (cands.empty()) {
-            char buf[160];
-            std::snprintf(buf, sizeof buf, "no compiled line kernel for N=%d nl=%d nops=%d (stencil half-width %d)",
-                          ps.N, ps.nl, ps.nops, ps.hw);
+            char buf[200];
+            std::snprintf(buf, sizeof buf,
+                          "no compiled line kernel for N=%d nl=%d nops=%d (stencil half-width %d, direction %d)",
+                          ps.N, ps.nl, ps.nops, ps.hw, ps.dir);
             return fail(CFD_EUNSUPPORTED, buf);
         }
-        int L = cands[0];
-        auto it = p->sched_L.find(ps.N);
-        if (it != p->sched_L.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
-            L = it->second;
-        int mi, hw;
-        ps.fn = find_line_kernel(f32, ps.nl, L, ps.nops, ps.par, ps.mi, ps.hw, &mi, &hw);
-        ps.L = L;
-        ps.P = ps.N / L;
+        int P = cands[0];
+        auto it = p->sched_P.find(std::make_pair(ps.N, ps.dir == 0 ? 1 : 0));
+        if (it != p->sched_P.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
+            P = it->second;
+        ps.P = P;
+        ps.L = partition_length(ps, f32, P);
+        ps.cls = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, ps.L);
+        ps.lcode = 0;
+        for (int j = 0; j < ps.cls->nL; ++j)
+            if (ps.cls->Ls[j] == ps.L) ps.lcode = j;
     }
     // 2. tables
     std::map<TabKey, int> tabidx;
@@ -197,7 +231,7 @@ cfd_status build(cfd_plan *p) {
     for (size_t i = 0; i < p->passes.size(); ++i) {
         const PassHost &ps = p->passes[i];
         for (int o = 0; o < ps.nops; ++o) {
-            TabKey k{ps.sch[o], ps.N, ps.P, ps.periodic};
+            TabKey k{ps.sch[o], ps.N, ps.P, ps.L, ps.periodic};
             auto it = tabidx.find(k);
             int id;
             if (it == tabidx.end()) {
@@ -205,7 +239,7 @@ cfd_status build(cfd_plan *p) {
                 tabidx[k] = id;
                 keys.push_back(k);
                 offs.push_back(total);
-                int64_t n = table_elems(ps.N, ps.P, p->schemes[ps.sch[o]].nl);
+                int64_t n = table_elems(ps.P * ps.L, ps.P, p->schemes[ps.sch[o]].nl);
                 total += (n + 7) & ~int64_t(7);
             } else {
                 id = it->second;
@@ -228,11 +262,11 @@ cfd_status build(cfd_plan *p) {
                 cb[kCoefCR + j * 11 + 5 + m] = sgn * s.cl[j][5 - m];
             }
         for (int j = 0; j < 5; ++j) cb[kCoefAlpha + j] = s.lhs[j];
-        const int L = k.N / k.P;
+        const int L = k.L;
         fill_tabspec(specs.data() + t * tabspec_size(), k.N, k.P, L, s.nl, k.periodic ? 0 : s.nc, k.periodic,
                      s.lhs, offs[t]);
         const int64_t B = 2 * s.nl * k.P;
-        scratch_per = std::max<int64_t>(scratch_per, 2 * B * B + L + 8);
+        scratch_per = std::max<int64_t>(scratch_per, 2 * B * B + L + (int64_t)k.P * L * 5 + 8);
     }
     p->d_tab64.release();
     p->d_tab32.release();
@@ -311,47 +345,59 @@ cfd_status build(cfd_plan *p) {
     HIPCHK(hipMalloc(&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
 
-    // 4. work items, grouped by (kernel, P); within a group ordered by
-    //    block, field, direction so the passes over one block-field are close
-    //    in time (their shared input stays in cache).
-    std::map<std::pair<const void *, int>, std::vector<WorkItem>> byk;
-    std::vector<std::pair<const void *, int>> order;
-    std::vector<size_t> pidx(p->passes.size());
-    for (size_t i = 0; i < pidx.size(); ++i) pidx[i] = i;
-    std::stable_sort(pidx.begin(), pidx.end(), [&](size_t a, size_t b) {
-        return p->passes[a].block < p->passes[b].block;
-    });
-    for (size_t i : pidx) {
-        const PassHost &ps = p->passes[i];
-        auto key = std::make_pair(ps.fn, ps.P);
-        if (!byk.count(key)) order.push_back(key);
-        auto &vec = byk[key];
-        for (int f = 0; f < ps.nfield; ++f)
-            for (int l0 = 0; l0 < pd[i].nlines; l0 += kWave) vec.push_back(WorkItem{(int32_t)i, f, l0, 0});
+    // 4. work items.  One launch group per kernel class (x lines optionally in
+    //    a group of their own); within a group the items of one block-field
+    //    are adjacent (x, y, z passes together) so its input is re-read from
+    //    cache rather than HBM.
+    const size_t es = f32 ? 4 : 8;
+    std::map<std::pair<const void *, int>, int> gidx;
+    std::vector<std::vector<WorkItem>> gitems;
+    std::vector<Group> groups;
+    std::vector<std::vector<int>> by_block(p->blocks.size());
+    for (size_t i = 0; i < p->passes.size(); ++i) by_block[p->passes[i].block].push_back((int)i);
+    for (size_t b = 0; b < p->blocks.size(); ++b) {
+        for (int f = 0; f < p->nfields; ++f) {
+            for (int i : by_block[b]) {
+                const PassHost &ps = p->passes[i];
+                if (f < ps.field0 || f >= ps.field0 + ps.nfield) continue;
+                const int sub = (p->split_x && ps.dir == 0) ? 1 : 0;
+                auto key = std::make_pair(ps.cls->fn, sub);
+                auto it = gidx.find(key);
+                int gi;
+                if (it == gidx.end()) {
+                    gi = (int)groups.size();
+                    gidx[key] = gi;
+                    Group g;
+                    g.fn = ps.cls->fn;
+                    g.lds = (size_t)ps.cls->exch * es;
+                    groups.push_back(g);
+                    gitems.emplace_back();
+                } else {
+                    gi = it->second;
+                }
+                if (ps.dir == 0)
+                    groups[gi].lds = std::max(groups[gi].lds, (size_t)ps.cls->exch * es +
+                                                                  x_tile_bytes(ps.P, ps.L, ps.cls->hw, es));
+                const int per_item = kWave * (4 / ps.P);
+                const int meta = ps.P | (ps.lcode << 4);
+                for (int l0 = 0; l0 < pd[i].nlines; l0 += per_item)
+                    gitems[gi].push_back(WorkItem{(int32_t)i, f - ps.field0, l0, meta});
+            }
+        }
     }
     std::vector<WorkItem> items;
-    p->groups.clear();
-    for (auto &key : order) {
-        auto &vec = byk[key];
-        Group g;
-        g.fn = key.first;
-        g.P = key.second;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        Group &g = groups[gi];
         g.item0 = (int64_t)items.size();
-        g.nitems = (int64_t)vec.size();
-        // LDS for the boundary exchange: nops x 64 lanes x (B|1) values
-        int nl = 0, nops = 1;
-        for (const PassHost &ps : p->passes)
-            if (ps.fn == g.fn && ps.P == g.P) { nl = ps.nl; nops = ps.nops; break; }
-        const int B = 2 * nl * g.P;
-        g.lds = (nl > 0) ? (size_t)nops * kWave * (B | 1) * elem_size(p->dtype == CFD_F64 ? CFD_F64 : CFD_F32) : 0;
+        g.nitems = (int64_t)gitems[gi].size();
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, g.fn, kWave * g.P, g.lds) != hipSuccess || nb < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, g.fn, kWave * 4, g.lds) != hipSuccess || nb < 1)
             nb = 1;
         (void)hipGetLastError();
         g.grid_persist = (int)std::min<int64_t>(g.nitems, (int64_t)nb * p->cus);
-        items.insert(items.end(), vec.begin(), vec.end());
-        p->groups.push_back(g);
+        items.insert(items.end(), gitems[gi].begin(), gitems[gi].end());
     }
+    p->groups = groups;
     p->nitems = (int64_t)items.size();
     p->d_items.release();
     HIPCHK(hipMalloc(&p->d_items.p, std::max<size_t>(1, items.size()) * sizeof(WorkItem)));
@@ -364,7 +410,7 @@ cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
     for (const Group &g : p->groups) {
         if (g.nitems == 0) continue;
         const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
-        hipError_t e = launch_lines(g.fn, grid, g.P, g.lds, st, (const WorkItem *)p->d_items.p + g.item0,
+        hipError_t e = launch_lines(g.fn, grid, g.lds, st, (const WorkItem *)p->d_items.p + g.item0,
                                     (int)g.nitems, (const PassDesc *)p->d_pass.p, tabs,
                                     (const int64_t *)p->d_taboff.p, in, out);
         if (e != hipSuccess) return hip_fail(e, "launching line kernel");
@@ -608,7 +654,10 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
     HIPCHK(hipSetDevice(p->device));
     {
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) p->cus = prop.multiProcessorCount;
+        if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+            p->cus = prop.multiProcessorCount;
+            p->max_lds = prop.sharedMemPerBlock;
+        }
         (void)hipGetLastError();
     }
     cfd_status st = build(p.get());
@@ -684,25 +733,29 @@ cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream) {
     return CFD_OK;
 }
 
-cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int L, int persistent) {
+cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions, int flags) {
     if (!p) return fail(CFD_EINVAL, "cfd_plan_set_schedule: null plan");
+    if (flags & ~(CFD_SCHED_PERSISTENT | CFD_SCHED_SPLIT_X))
+        return fail(CFD_EINVAL, "cfd_plan_set_schedule: unknown flag");
     if (N > 0) {
-        if (L > 0) {
-            bool ok_any = false;
+        const auto key = std::make_pair(N, xlines ? 1 : 0);
+        if (partitions > 0) {
+            bool any = false;
             for (const PassHost &ps : p->passes) {
-                if (ps.N != N) continue;
-                std::vector<int> c = candidate_Ls(ps, p->dtype != CFD_F64);
-                if (std::find(c.begin(), c.end(), L) == c.end())
-                    return fail(CFD_EINVAL, "cfd_plan_set_schedule: no compiled kernel for this partition length");
-                ok_any = true;
+                if (ps.N != N || (ps.dir == 0) != (xlines != 0)) continue;
+                std::vector<int> c = candidate_Ps(ps, p->dtype != CFD_F64, p->max_lds);
+                if (std::find(c.begin(), c.end(), partitions) == c.end())
+                    return fail(CFD_EINVAL, "cfd_plan_set_schedule: no compiled kernel for that partition count");
+                any = true;
             }
-            if (!ok_any) return fail(CFD_EINVAL, "cfd_plan_set_schedule: no line of that length in the plan");
-            p->sched_L[N] = L;
+            if (!any) return fail(CFD_EINVAL, "cfd_plan_set_schedule: no such lines in the plan");
+            p->sched_P[key] = partitions;
         } else {
-            p->sched_L.erase(N);
+            p->sched_P.erase(key);
         }
     }
-    p->persistent = persistent != 0;
+    p->persistent = (flags & CFD_SCHED_PERSISTENT) != 0;
+    p->split_x = (flags & CFD_SCHED_SPLIT_X) != 0;
     return build(p);
 }
 
@@ -716,21 +769,23 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
         (void)hipGetLastError();
     }
-    const char *dt = p->dtype == CFD_F64 ? "f64" : "f32";
-    // keys: one per distinct (N, nl, nops) class
-    std::map<std::tuple<int, int, int>, std::vector<int>> classes;
+    const bool f32 = p->dtype != CFD_F64;
+    const char *dt = f32 ? "f32" : "f64";
+    // one class per (line length, x or y/z, band, fused operators)
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> classes;
     for (const PassHost &ps : p->passes)
-        classes[std::make_tuple(ps.N, ps.nl, ps.nops)] = candidate_Ls(ps, p->dtype != CFD_F64);
-    std::map<std::string, std::pair<int, int>> cache;
+        classes[std::make_tuple(ps.N, ps.dir == 0 ? 1 : 0, ps.nl, ps.nops)] = candidate_Ps(ps, f32, p->max_lds);
+    std::map<std::string, int> cache;
     if (cache_path) {
         std::ifstream f(cache_path);
         std::string key;
-        int L, pers;
-        while (f >> key >> L >> pers) cache[key] = {L, pers};
+        int v;
+        while (f >> key >> v) cache[key] = v;
     }
-    auto keyof = [&](int N, int nl, int nops) {
+    auto keyof = [&](const std::tuple<int, int, int, int> &k) {
         std::ostringstream s;
-        s << arch << ":" << dt << ":N" << N << ":nl" << nl << ":ops" << nops;
+        s << arch << ":" << dt << ":N" << std::get<0>(k) << ":x" << std::get<1>(k) << ":nl" << std::get<2>(k)
+          << ":ops" << std::get<3>(k);
         return s.str();
     };
     hipEvent_t e0, e1;
@@ -756,40 +811,44 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     std::vector<std::string> new_lines;
     cfd_status result = CFD_OK;
     for (auto &kv : classes) {
-        const int N = std::get<0>(kv.first);
-        const std::string key = keyof(N, std::get<1>(kv.first), std::get<2>(kv.first));
+        const auto skey = std::make_pair(std::get<0>(kv.first), std::get<1>(kv.first));
+        const std::string key = keyof(kv.first);
         auto hit = cache.find(key);
-        if (hit != cache.end() &&
-            std::find(kv.second.begin(), kv.second.end(), hit->second.first) != kv.second.end()) {
-            p->sched_L[N] = hit->second.first;
+        if (hit != cache.end() && std::find(kv.second.begin(), kv.second.end(), hit->second) != kv.second.end()) {
+            p->sched_P[skey] = hit->second;
             continue;
         }
+        if (kv.second.size() < 2) continue;
         float best = 1e30f;
-        int bestL = kv.second.empty() ? 0 : kv.second[0];
-        for (int L : kv.second) {
-            p->sched_L[N] = L;
+        int bestP = kv.second[0];
+        for (int P : kv.second) {
+            p->sched_P[skey] = P;
             result = build(p);
             if (result != CFD_OK) break;
             float ms;
             result = time_apply(ms);
             if (result != CFD_OK) break;
-            if (ms < best) { best = ms; bestL = L; }
+            if (ms < best) { best = ms; bestP = P; }
         }
         if (result != CFD_OK) break;
-        p->sched_L[N] = bestL;
-        new_lines.push_back(key + " " + std::to_string(bestL) + " 1");
+        p->sched_P[skey] = bestP;
+        new_lines.push_back(key + " " + std::to_string(bestP));
     }
     if (result == CFD_OK) {
-        // persistent grid versus one workgroup per item
-        float t_p = 0, t_n = 0;
-        p->persistent = true;
-        result = build(p);
-        if (result == CFD_OK) result = time_apply(t_p);
-        if (result == CFD_OK) {
-            p->persistent = false;
-            result = time_apply(t_n);
-            p->persistent = t_p <= t_n;
-        }
+        // launch shape: persistent grid or one workgroup per item; x lines fused or split
+        float best = 1e30f;
+        bool bp = true, bs = false;
+        for (int pers = 1; pers >= 0 && result == CFD_OK; --pers)
+            for (int split = 0; split <= 1 && result == CFD_OK; ++split) {
+                p->persistent = pers;
+                p->split_x = split;
+                result = build(p);
+                float ms = 0;
+                if (result == CFD_OK) result = time_apply(ms);
+                if (result == CFD_OK && ms < best) { best = ms; bp = pers; bs = split; }
+            }
+        p->persistent = bp;
+        p->split_x = bs;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -799,6 +858,25 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         for (const std::string &l : new_lines) f << l << "\n";
     }
     return build(p);
+}
+
+cfd_status cfd_plan_get_schedule(const cfd_plan *p, int *persistent, int *split_x, int *n_classes, int *N,
+                                 int *xlines, int *partitions, int cap) {
+    if (!p) return fail(CFD_EINVAL, "cfd_plan_get_schedule: null plan");
+    if (persistent) *persistent = p->persistent;
+    if (split_x) *split_x = p->split_x;
+    std::map<std::pair<int, int>, int> used;
+    for (const PassHost &ps : p->passes) used[std::make_pair(ps.N, ps.dir == 0 ? 1 : 0)] = ps.P;
+    if (n_classes) *n_classes = (int)used.size();
+    int i = 0;
+    for (auto &kv : used) {
+        if (i >= cap) break;
+        if (N) N[i] = kv.first.first;
+        if (xlines) xlines[i] = kv.first.second;
+        if (partitions) partitions[i] = kv.second;
+        ++i;
+    }
+    return CFD_OK;
 }
 
 cfd_status cfd_halo_exchange(cfd_plan *p, void *data_dev, int bx, int by, int bz, void *stream) {

@@ -49,7 +49,8 @@ int required_ghosts(const Scheme &s, int periodic);
 //   [0, 64)              coefficient block: interior stencil alpha^(0) (11,
 //                        centred), left closure rows (2 x 11), right closure
 //                        rows (2 x 11, mirror images), alpha^(d) (5)
-//   fac  [p][i][5]       partition-local LU of D_L (l1, l2, u1, u2, 1/d)
+//   fwd  [p L + i][2]    partition-local LU of D_L, forward factors (l1, l2)
+//   bwd  [p L + i][3]    backward factors (u1, u2, 1/d)
 //   spk  [p][2nl][L]     spike vectors: local response to the nl left and nl
 //                        right neighbour unknowns
 //   krow [p][2nl][B]     rows of the inverse of the reduced boundary system,
@@ -84,12 +85,14 @@ struct PassDesc {
     double hinv[2];         // h^-d per op
 };
 
-// One work item: 64 lines of one field of one pass.
+// One work item: 64 * (4 / P) lines of one field of one pass.
+// meta: P (partitions per line) in bits 0..3, index of L in the kernel's
+// compiled set in bits 4..7.
 struct WorkItem {
     int32_t pass;
     int32_t field;
     int32_t line0;
-    int32_t pad;
+    int32_t meta;
 };
 
 }  // namespace cfd
@@ -100,12 +103,11 @@ struct WorkItem {
 #include <hip/hip_runtime_api.h>
 
 namespace cfd {
-const void *find_line_kernel(int f32, int nl, int L, int nops, int par, int mi, int hw, int *mi_out,
-                             int *hw_out);
-int line_kernel_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap);
-hipError_t launch_lines(const void *fn, int grid, int P, size_t lds, hipStream_t st, const WorkItem *items,
-                        int nitems, const PassDesc *passes, const void *tabs, const int64_t *taboff,
-                        const void *in, void *out);
+struct LineClass;
+const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L);
+int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap);
+hipError_t launch_lines(const void *fn, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
+                        const PassDesc *passes, const void *tabs, const int64_t *taboff, const void *in, void *out);
 hipError_t launch_build_tables(int ntab, const void *specs, double *data, double *scratch, int64_t scratch_per,
                                int *status, hipStream_t st);
 hipError_t launch_to_f32(int64_t n, const double *a, float *b, hipStream_t st);

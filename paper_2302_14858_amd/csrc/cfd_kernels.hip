@@ -1,225 +1,27 @@
-// Device kernels of the MI355X compact finite-difference library (gfx950).
-//
-// Line operator (arXiv 2302.14858, Eq. sch_cent_om and its matrix form
-// Eqs. diff_mat_subL / diff_mat_subR): on every grid line of N nodes the
-// derivative f~ solves  D_L f~ = h^-d D_R f,  where D_L has identity rows on
-// the block-closure rows and the banded alpha^(d) rows elsewhere, and D_R has
-// the explicit closure stencil or the interior stencil alpha^(0).  Periodic
-// lines use the circulant operator instead.
-//
-// GPU decomposition (not from the paper, whose TDMA runs one line at a time):
-//  * a line is cut into P partitions of L = N/P consecutive rows;
-//  * one wavefront owns one partition of 64 lines: lane = line, so loads and
-//    stores along y and z are coalesced across the wavefront and every table
-//    entry a wavefront reads is uniform (scalar loads);
-//  * each lane streams its partition once: the RHS stencil is evaluated from a
-//    register ring and fused with forward elimination, then back substitution
-//    gives the partition-local solution y;
-//  * the partitions are coupled through 2*nl boundary unknowns each.  Their
-//    values follow from the boundary entries of every partition's y by one
-//    fixed linear map (rows of the inverse reduced system); the lanes of a
-//    line exchange those entries through LDS and correct
-//    x = y - sum(boundary value * spike vector).  For periodic lines the same
-//    algebra closes the wrap-around, which is the Woodbury form of the cyclic
-//    solve.
-// All line-independent quantities (local LU factors, spikes, reduced-system
-// rows) are built once per plan in FP64 by k_build_tables.
+// Device kernels of the MI355X compact finite-difference library (gfx950):
+// FP64 table construction, the registry of compiled line-kernel classes and
+// the FP64 instantiations of the line kernel (cfd_lines.h).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "cfd_internal.h"
+#include "cfd_kernels_reg.h"
+#include "cfd_lines.h"
 
 namespace cfd {
-
-// ---------------------------------------------------------------------------
-// Line kernel
-// ---------------------------------------------------------------------------
-//   T     storage and arithmetic type
-//   NL    implicit half-width (0 explicit, 1 tri, 2 penta)
-//   L     rows per partition
-//   NOPS  operators sharing one pass over the input (same field, direction)
-//   PAR   bit o set: operator o has an antisymmetric interior stencil (odd d)
-//   MI    interior stencil half-width
-//   HW    ring half-width = max(MI, closure half-width)
-template <typename T, int NL, int L, int NOPS, int PAR, int MI, int HW>
-__global__ void __launch_bounds__(512)
-k_lines(const WorkItem *__restrict__ items, int nitems, const PassDesc *__restrict__ passes,
-        const T *__restrict__ tabs, const int64_t *__restrict__ taboff, const T *__restrict__ in,
-        T *__restrict__ out)
-{
-    static_assert(NL == 0 || L >= 2 * NL, "partition too short");
-    constexpr int R = 2 * HW + 1;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *lds = reinterpret_cast<T *>(smem_raw);
-
-    const int P = blockDim.x >> 6;
-    const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = threadIdx.x & 63;
-    const int B = 2 * NL * P;
-    const int Bp = B | 1;
-
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const WorkItem wi = items[it];
-        const PassDesc &pd = passes[wi.pass];
-        const int N = pd.N;
-        const int ng = pd.ng;
-        const bool periodic = pd.periodic != 0;
-
-        int line = wi.line0 + g;
-        const bool active = line < pd.nlines;
-        if (!active) line = pd.nlines - 1;
-        const int lu = line % pd.nu;
-        const int lv = line / pd.nu;
-        const T *src = in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride +
-                       (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
-        const int64_t sd = pd.sd;
-        const int k0 = p * L;
-
-        const T *tb[NOPS];
-#pragma unroll
-        for (int o = 0; o < NOPS; ++o) tb[o] = tabs + taboff[pd.tab[o]];
-
-        // node j of this line; out-of-block nodes read as 0 (their weights are 0)
-        auto load = [&](int j) -> T {
-            if (periodic) {
-                if (j < 0) j += N;
-                if (j >= N) j -= N;
-                return src[(int64_t)j * sd];
-            }
-            if (j < -ng || j >= N + ng) return T(0);
-            return src[(int64_t)j * sd];
-        };
-
-        T f[R];
-#pragma unroll
-        for (int t = 0; t < R - 1; ++t) f[t] = load(k0 - HW + t);
-
-        T y[NOPS][L];
-        const bool first = (p == 0) && !periodic;
-        const bool last = (p == P - 1) && !periodic;
-
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            f[R - 1] = load(k0 + i + HW);
-#pragma unroll
-            for (int o = 0; o < NOPS; ++o) {
-                const T *cf = tb[o];
-                T r;
-                if ((PAR >> o) & 1) {  // constant after unrolling
-                    r = T(0);
-#pragma unroll
-                    for (int m = 1; m <= MI; ++m) r += cf[kCoefA + 5 + m] * (f[HW + m] - f[HW - m]);
-                } else {
-                    r = cf[kCoefA + 5] * f[HW];
-#pragma unroll
-                    for (int m = 1; m <= MI; ++m) r += cf[kCoefA + 5 + m] * (f[HW + m] + f[HW - m]);
-                }
-                if constexpr (NL > 0) {
-                    // explicit closure rows (identity rows of D_L)
-                    if (i < NL && first) {
-                        const T *c = cf + kCoefCL + i * 11;
-                        T s = T(0);
-#pragma unroll
-                        for (int m = -HW; m <= HW; ++m) s += c[5 + m] * f[HW + m];
-                        r = s;
-                    }
-                    if (i >= L - NL && last) {
-                        const T *c = cf + kCoefCR + (L - 1 - i) * 11;
-                        T s = T(0);
-#pragma unroll
-                        for (int m = -HW; m <= HW; ++m) s += c[5 + m] * f[HW + m];
-                        r = s;
-                    }
-                    // forward elimination with the partition-local factors
-                    const T *fac = cf + kCoefHdr + (int64_t)(k0 + i) * 5;
-                    if (i >= 1) r -= fac[0] * y[o][i - 1];
-                    if (NL >= 2 && i >= 2) r -= fac[1] * y[o][i - 2];
-                }
-                y[o][i] = r;
-            }
-#pragma unroll
-            for (int t = 0; t < R - 1; ++t) f[t] = f[t + 1];
-        }
-
-        if constexpr (NL > 0) {
-            // back substitution
-#pragma unroll
-            for (int o = 0; o < NOPS; ++o) {
-                const T *cf = tb[o];
-#pragma unroll
-                for (int i = L - 1; i >= 0; --i) {
-                    const T *fac = cf + kCoefHdr + (int64_t)(k0 + i) * 5;
-                    T v = y[o][i];
-                    if (i + 1 < L) v -= fac[2] * y[o][i + 1];
-                    if (NL >= 2 && i + 2 < L) v -= fac[3] * y[o][i + 2];
-                    y[o][i] = v * fac[4];
-                }
-            }
-            // coupling of the partitions (and the periodic wrap)
-            if (periodic || P > 1) {
-                // boundary slots: rows 0..NL-1 and L-NL..L-1 of every partition
-#pragma unroll
-                for (int o = 0; o < NOPS; ++o) {
-                    T *row = lds + ((int64_t)o * 64 + g) * Bp + p * 2 * NL;
-#pragma unroll
-                    for (int t = 0; t < NL; ++t) {
-                        row[t] = y[o][t];
-                        row[NL + t] = y[o][L - NL + t];
-                    }
-                }
-                __syncthreads();
-#pragma unroll
-                for (int o = 0; o < NOPS; ++o) {
-                    const T *cf = tb[o];
-                    const int Lrows = N;  // fac occupies N*5 entries
-                    const T *spk = cf + kCoefHdr + (int64_t)Lrows * 5 + (int64_t)p * 2 * NL * L;
-                    const T *krow = cf + kCoefHdr + (int64_t)Lrows * 5 + (int64_t)P * 2 * NL * L +
-                                    (int64_t)p * 2 * NL * B;
-                    const T *row = lds + ((int64_t)o * 64 + g) * Bp;
-                    T xq[2 * NL];
-#pragma unroll
-                    for (int q = 0; q < 2 * NL; ++q) xq[q] = T(0);
-                    for (int b = 0; b < B; ++b) {
-                        const T yb = row[b];
-#pragma unroll
-                        for (int q = 0; q < 2 * NL; ++q) xq[q] += krow[q * B + b] * yb;
-                    }
-#pragma unroll
-                    for (int i = 0; i < L; ++i) {
-                        T v = y[o][i];
-#pragma unroll
-                        for (int q = 0; q < 2 * NL; ++q) v -= xq[q] * spk[q * L + i];
-                        y[o][i] = v;
-                    }
-                }
-                __syncthreads();  // LDS is reused by the next item
-            }
-        }
-
-        if (active) {
-#pragma unroll
-            for (int o = 0; o < NOPS; ++o) {
-                T *dst = out + pd.out_base[o] + (int64_t)wi.field * pd.out_fstride + (int64_t)lv * pd.osv +
-                         (int64_t)lu * pd.osu;
-                const T hinv = (T)pd.hinv[o];
-#pragma unroll
-                for (int i = 0; i < L; ++i) dst[(int64_t)(k0 + i) * pd.osd] = y[o][i] * hinv;
-            }
-        }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Table construction, FP64, one thread per table
 // ---------------------------------------------------------------------------
 struct TabSpec {
-    int N, P, L, nl, nc, periodic;
+    int N, P, L, nl, nc, periodic;   // line length, partitions, rows per partition (P L >= N)
     double alpha[2 * kMaxNL + 1];
     int64_t off;   // element offset of the table (coefficient block first)
 };
 
-// Entry of D_L in global row k at unwrapped offset o (column k + o).
+// Entry of D_L in global row k at unwrapped offset o (column k + o).  Rows
+// past the line end (padding of the last partition) are identity rows.
 __device__ inline double dl_entry(const TabSpec &s, int k, int o) {
     const bool ident = !s.periodic && (k < s.nc || k >= s.N - s.nc);
     if (ident) return o == 0 ? 1.0 : 0.0;
@@ -252,20 +54,23 @@ __global__ void k_build_tables(int ntab, const TabSpec *__restrict__ specs, doub
     if (t >= ntab) return;
     const TabSpec s = specs[t];
     double *tab = data + s.off;
-    double *fac = tab + kCoefHdr;
     const int N = s.N, P = s.P, L = s.L, nl = s.nl;
     if (nl == 0) { status[t] = 0; return; }
     const int B = 2 * nl * P;
-    double *spk = fac + (int64_t)N * 5;
+    const int Npad = P * L;
+    double *fwd = tab + kCoefHdr;                        // Npad x 2
+    double *bwd = fwd + (int64_t)Npad * 2;               // Npad x 3
+    double *spk = fwd + (int64_t)Npad * 5;
     double *krow = spk + (int64_t)P * 2 * nl * L;
     double *K = scratch + (int64_t)t * scratch_per;      // B x B
     double *Kinv = K + (int64_t)B * B;                   // B x B
     double *v = Kinv + (int64_t)B * B;                   // L
+    double *facs = v + L;                                // Npad x 5 (l1, l2, u1, u2, 1/d)
     int bad = 0;
 
     // 1. partition-local banded LU without pivoting (Doolittle, nl <= 2)
     for (int p = 0; p < P; ++p) {
-        double *F = fac + (int64_t)p * L * 5;
+        double *F = facs + (int64_t)p * L * 5;
         for (int i = 0; i < L; ++i) {
             const int k = p * L + i;
             auto a = [&](int o) -> double {   // local entry (row i, col i+o), in partition only
@@ -293,6 +98,13 @@ __global__ void k_build_tables(int ntab, const TabSpec *__restrict__ specs, doub
             F[i * 5 + 4] = 1.0 / dd;
         }
     }
+    for (int k = 0; k < Npad; ++k) {
+        fwd[k * 2 + 0] = facs[k * 5 + 0];
+        fwd[k * 2 + 1] = facs[k * 5 + 1];
+        bwd[k * 3 + 0] = facs[k * 5 + 2];
+        bwd[k * 3 + 1] = facs[k * 5 + 3];
+        bwd[k * 3 + 2] = facs[k * 5 + 4];
+    }
     // 2. spike vectors: response of partition p to its nl left and nl right
     //    neighbour unknowns (columns pL - j and (p+1)L + j - 1, j = 1..nl)
     for (int p = 0; p < P; ++p) {
@@ -306,12 +118,11 @@ __global__ void k_build_tables(int ntab, const TabSpec *__restrict__ specs, doub
                 const int o = col - k;
                 double e = 0.0;
                 if (o >= -nl && o <= nl) {
-                    if (s.periodic || (col >= 0 && col < N)) e = dl_entry(s, k, o);
-                    if (!s.periodic && (col < 0 || col >= N)) e = 0.0;
+                    if (s.periodic || (col >= 0 && col < Npad)) e = dl_entry(s, k, o);
                 }
                 v[i] = e;
             }
-            local_solve(fac + (int64_t)p * L * 5, L, nl, v);
+            local_solve(facs + (int64_t)p * L * 5, L, nl, v);
             for (int i = 0; i < L; ++i) spk[((int64_t)p * 2 * nl + q) * L + i] = v[i];
         }
     }
@@ -376,70 +187,50 @@ __global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restr
 }
 
 // ---------------------------------------------------------------------------
-// Registry of compiled line-kernel variants
+// Registry of compiled line-kernel classes
 // ---------------------------------------------------------------------------
-struct LineLaunch {
-    int f32, nl, L, nops, par, mi, hw;
-    const void *fn;
-};
+const LineClass kLineClassesF64[] = { CFD_LINE_CLASSES(double, 0) };
+extern const LineClass kLineClassesF32[];
+extern const int kNumLineClassesF32;
 
-#define CFD_LK(T, F32, NL, L, NOPS, PAR, MI, HW) \
-    {F32, NL, L, NOPS, PAR, MI, HW, reinterpret_cast<const void *>(&k_lines<T, NL, L, NOPS, PAR, MI, HW>)}
-
-#define CFD_LK_BOTH(NL, L, NOPS, PAR, MI, HW) \
-    CFD_LK(double, 0, NL, L, NOPS, PAR, MI, HW), CFD_LK(float, 1, NL, L, NOPS, PAR, MI, HW)
-
-static const LineLaunch kLineKernels[] = {
-    // pentadiagonal, first + second derivative fused (M = 3, closures of half-width 5)
-    CFD_LK_BOTH(2, 8, 2, 1, 3, 5), CFD_LK_BOTH(2, 12, 2, 1, 3, 5), CFD_LK_BOTH(2, 16, 2, 1, 3, 5),
-    CFD_LK_BOTH(2, 24, 2, 1, 3, 5),
-    // tridiagonal, first + second derivative fused (M = 3, closures of half-width 4)
-    CFD_LK_BOTH(1, 8, 2, 1, 3, 4), CFD_LK_BOTH(1, 16, 2, 1, 3, 4), CFD_LK_BOTH(1, 24, 2, 1, 3, 4),
-    CFD_LK_BOTH(1, 32, 2, 1, 3, 4),
-    // tridiagonal, one first derivative (M = 3 / M = 2)
-    CFD_LK_BOTH(1, 8, 1, 1, 3, 4), CFD_LK_BOTH(1, 16, 1, 1, 3, 4), CFD_LK_BOTH(1, 24, 1, 1, 3, 4),
-    CFD_LK_BOTH(1, 32, 1, 1, 3, 4),
-    CFD_LK_BOTH(1, 8, 1, 1, 2, 4), CFD_LK_BOTH(1, 16, 1, 1, 2, 4), CFD_LK_BOTH(1, 32, 1, 1, 2, 4),
-    // generic single-operator variants (any stencil up to half-width 5)
-    CFD_LK_BOTH(1, 8, 1, 1, 5, 5), CFD_LK_BOTH(1, 16, 1, 1, 5, 5), CFD_LK_BOTH(1, 8, 1, 0, 5, 5),
-    CFD_LK_BOTH(1, 16, 1, 0, 5, 5), CFD_LK_BOTH(2, 8, 1, 1, 5, 5), CFD_LK_BOTH(2, 16, 1, 1, 5, 5),
-    CFD_LK_BOTH(2, 8, 1, 0, 5, 5), CFD_LK_BOTH(2, 16, 1, 0, 5, 5),
-    // explicit schemes
-    CFD_LK_BOTH(0, 8, 1, 1, 5, 5), CFD_LK_BOTH(0, 8, 1, 0, 5, 5),
-};
-
-const void *find_line_kernel(int f32, int nl, int L, int nops, int par, int mi, int hw, int *mi_out, int *hw_out) {
-    // exact stencil match first, then the smallest generic variant that covers it
-    const LineLaunch *best = nullptr;
-    for (const LineLaunch &k : kLineKernels) {
-        if (k.f32 != f32 || k.nl != nl || k.L != L || k.nops != nops || k.par != par) continue;
-        if (k.mi < mi || k.hw < hw) continue;
-        if (!best || (k.mi + k.hw) < (best->mi + best->hw)) best = &k;
+const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L) {
+    const LineClass *tab = f32 ? kLineClassesF32 : kLineClassesF64;
+    const int n = f32 ? kNumLineClassesF32 : (int)(sizeof(kLineClassesF64) / sizeof(kLineClassesF64[0]));
+    const LineClass *best = nullptr;
+    for (int i = 0; i < n; ++i) {
+        const LineClass &k = tab[i];
+        if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw) continue;
+        bool hasL = false;
+        for (int j = 0; j < k.nL; ++j) hasL |= (k.Ls[j] == L);
+        if (!hasL) continue;
+        if (!best || (k.mi + k.hw) < (best->mi + best->hw) ||
+            ((k.mi + k.hw) == (best->mi + best->hw) && k.nL < best->nL))
+            best = &k;
     }
-    if (!best) return nullptr;
-    *mi_out = best->mi;
-    *hw_out = best->hw;
-    return best->fn;
+    return best;
 }
 
-// L values that have at least one compiled variant for (f32, nl, nops, par)
-int line_kernel_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap) {
-    int n = 0;
-    for (const LineLaunch &k : kLineKernels) {
-        if (k.f32 != f32 || k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw) continue;
-        bool seen = false;
-        for (int i = 0; i < n; ++i) seen |= (Ls[i] == k.L);
-        if (!seen && n < cap) Ls[n++] = k.L;
+int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap) {
+    const LineClass *tab = f32 ? kLineClassesF32 : kLineClassesF64;
+    const int n = f32 ? kNumLineClassesF32 : (int)(sizeof(kLineClassesF64) / sizeof(kLineClassesF64[0]));
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) {
+        const LineClass &k = tab[i];
+        if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw) continue;
+        for (int j = 0; j < k.nL; ++j) {
+            bool seen = false;
+            for (int q = 0; q < cnt; ++q) seen |= (Ls[q] == k.Ls[j]);
+            if (!seen && cnt < cap) Ls[cnt++] = k.Ls[j];
+        }
     }
-    return n;
+    return cnt;
 }
 
-hipError_t launch_lines(const void *fn, int grid, int P, size_t lds, hipStream_t st, const WorkItem *items,
-                        int nitems, const PassDesc *passes, const void *tabs, const int64_t *taboff,
-                        const void *in, void *out) {
+hipError_t launch_lines(const void *fn, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
+                        const PassDesc *passes, const void *tabs, const int64_t *taboff, const void *in, void *out) {
     void *args[] = {(void *)&items, (void *)&nitems, (void *)&passes, (void *)&tabs,
                     (void *)&taboff, (void *)&in, (void *)&out};
-    return hipLaunchKernel(fn, dim3(grid), dim3(64 * P), args, lds, st);
+    return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWGW), args, lds, st);
 }
 
 hipError_t launch_build_tables(int ntab, const void *specs, double *data, double *scratch, int64_t scratch_per,

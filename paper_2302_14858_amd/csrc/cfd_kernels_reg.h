@@ -1,0 +1,46 @@
+// Registry of compiled line-kernel classes (shared by the FP64 and FP32
+// instantiation units).  A class fixes the band (nl), the operators fused in
+// one pass (nops), their parities (par), the interior stencil half-width (mi)
+// and the ring half-width (hw); each compiled kernel carries a set of
+// partition lengths L chosen per work item.
+#pragma once
+
+#include "cfd_internal.h"
+
+namespace cfd {
+
+struct LineClass {
+    int nl, nops, par, mi, hw;
+    int nL;
+    int Ls[8];
+    int exch;          // exchange-area elements
+    const void *fn;
+};
+
+#define CFD_LC(T, NL, NOPS, PAR, MI, HW, ...)                                                        \
+    LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__}, exch_elems<NL, NOPS>(),      \
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, __VA_ARGS__>)}
+
+// The classes compiled for each precision.
+#define CFD_LINE_CLASSES(T, F32)                                                  \
+    /* pentadiagonal, first + second derivative, RHS half-width 3, closures 5 */  \
+    CFD_LC(T, 2, 2, 1, 3, 5, 8, 12, 16, 24),                                      \
+    /* tridiagonal, first + second derivative, RHS half-width 3, closures 4 */    \
+    CFD_LC(T, 1, 2, 1, 3, 4, 8, 12, 16, 24, 32),                                  \
+    /* tridiagonal first derivative, RHS half-width 3 (short and long lines) */   \
+    CFD_LC(T, 1, 1, 1, 3, 4, 8, 12, 16, 24, 32),                                  \
+    CFD_LC(T, 1, 1, 1, 3, 4, 48, 64),                                             \
+    /* tridiagonal first derivative, RHS half-width 2 */                          \
+    CFD_LC(T, 1, 1, 1, 2, 4, 8, 16, 32, 64),                                      \
+    /* any single operator with stencils up to half-width 5 */                    \
+    CFD_LC(T, 1, 1, 1, 5, 5, 8, 12, 16, 24, 32),                                  \
+    CFD_LC(T, 1, 1, 0, 5, 5, 8, 12, 16, 24, 32),                                  \
+    CFD_LC(T, 2, 1, 1, 5, 5, 8, 12, 16, 24, 32),                                  \
+    CFD_LC(T, 2, 1, 0, 5, 5, 8, 12, 16, 24, 32),                                  \
+    /* explicit schemes */                                                        \
+    CFD_LC(T, 0, 1, 1, 5, 5, 8, 16, 32),                                          \
+    CFD_LC(T, 0, 1, 0, 5, 5, 8, 16, 32)
+
+const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L);
+
+}  // namespace cfd

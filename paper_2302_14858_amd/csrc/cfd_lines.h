@@ -1,0 +1,429 @@
+// Line kernel of the MI355X compact finite-difference library (gfx950).
+//
+// Line operator (arXiv 2302.14858, Eq. sch_cent_om and its matrix form
+// Eqs. diff_mat_subL / diff_mat_subR): on every grid line of N nodes the
+// derivative f~ solves  D_L f~ = h^-d D_R f,  where D_L has identity rows on
+// the block-closure rows and the banded alpha^(d) rows elsewhere, and D_R has
+// the explicit closure stencil or the interior stencil alpha^(0).  Periodic
+// lines use the circulant operator instead.
+//
+// GPU decomposition (not from the paper, whose TDMA runs one line at a time):
+//  * a line is cut into P partitions of L = N/P consecutive rows; a workgroup
+//    of 4 wavefronts holds 4/P groups of 64 lines, and each wavefront owns one
+//    partition of one group: lane = line, so the line-independent tables a
+//    wavefront reads are uniform (scalar loads);
+//  * lines along y and z are read straight from HBM: consecutive lanes are
+//    consecutive x, so every load and store is coalesced;
+//  * lines along x are contiguous in memory: the workgroup first stages its
+//    lines (with ghosts) in LDS with coalesced loads, the lanes read their line
+//    from LDS, and the results go back through LDS to coalesced stores;
+//  * each lane streams its partition once: the RHS stencil is evaluated from a
+//    register ring and fused with forward elimination, then back substitution
+//    gives the partition-local solution y;
+//  * partitions are coupled through 2*nl boundary unknowns each.  Their values
+//    follow from the boundary entries of every partition's y by one fixed
+//    linear map (rows of the inverse reduced system): the lanes of a line
+//    exchange those entries through LDS and correct
+//    x = y - sum(boundary value * spike vector).  For periodic lines the same
+//    algebra closes the wrap-around (the Woodbury form of the cyclic solve).
+// All line-independent quantities are built once per plan in FP64 on the GPU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cfd_internal.h"
+
+namespace cfd {
+
+constexpr int kWGW = 4;   // wavefronts per workgroup
+
+
+
+
+// Exchange area of the partition coupling, elements of T, for NL and NOPS:
+// (4/P) groups x NOPS x 64 lanes x ((2 NL P) | 1), maximised over P.
+template <int NL, int NOPS>
+__host__ __device__ constexpr int exch_elems() {
+    int best = 0;
+    for (int P = 1; P <= kWGW; P *= 2) {
+        int v = (kWGW / P) * NOPS * 64 * ((2 * NL * P) | 1);
+        best = v > best ? v : best;
+    }
+    return NL > 0 ? best : 0;
+}
+
+// Per-item context shared by the template bodies.
+template <typename T>
+struct LineCtx {
+    const PassDesc *pd;
+    const T *tb[2];         // tables of the operators
+    const T *src;           // global: node 0 of this lane's line (non-x)
+    T *tile;                // LDS tile of staged x-lines (x only)
+    T *exch;                // LDS exchange area
+    int P, p, sub, g;       // partitions, this wave's partition, line group, lane
+    int tpitch;             // tile row pitch (elements)
+    int trow;               // this lane's tile row
+    bool periodic;
+};
+
+// One lane: the p-th partition (L rows) of its line, all NOPS operators.
+// Leaves the solution (times h^-d) in y.
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool X, bool PAD>
+__device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS][L]) {
+    const PassDesc &pd = *c.pd;
+    const int N = pd.N;
+    const int ng = pd.ng;
+    const int k0 = c.p * L;
+    const int64_t sd = pd.sd;
+
+    const int Npad = c.P * L;
+    // node j of this line (global path): only the halo of the first and last
+    // partition can leave the line; out-of-block nodes read as 0 (zero weights)
+    auto edge_load = [&](int j) -> T {
+        if (c.periodic) {
+            if (j < 0) j += N;
+            if (j >= N) j -= N;
+            return c.src[(int64_t)j * sd];
+        }
+        if (j < -ng || j >= N + ng) return T(0);
+        return c.src[(int64_t)j * sd];
+    };
+
+    // every input node of the partition (its rows and a halo of HW on each
+    // side) is requested before any arithmetic, so all of the partition's loads
+    // are in flight together
+    T fin[L + 2 * HW];
+    if constexpr (X) {
+#pragma unroll
+        for (int t = 0; t < L + 2 * HW; ++t) fin[t] = c.tile[c.trow * c.tpitch + k0 + t];
+    } else {
+        const bool lo_edge = c.p == 0;
+        const bool hi_edge = c.p == c.P - 1;
+        // walk a pointer along the line: one stride add per node keeps the
+        // addresses in vector registers instead of one scalar offset per node
+        const T *q = c.src + (int64_t)(k0 - HW) * sd;
+#pragma unroll
+        for (int t = 0; t < L + 2 * HW; ++t) {
+            const int j = k0 - HW + t;
+            const bool edge = (t < HW && lo_edge) || ((t >= L + HW || (PAD && t >= HW + L - (Npad - N))) && hi_edge);
+            fin[t] = edge ? edge_load(j) : *q;
+            q += sd;
+        }
+    }
+    const bool first = (c.p == 0) && !c.periodic;
+    // the last partition of a closure line: its last NL rows are the right
+    // closure rows, unless the line is padded (PAD): then rows >= N are
+    // decoupled identity rows with zero right-hand side and the closure rows
+    // sit at runtime positions
+    const bool last = (c.p == c.P - 1) && !c.periodic;
+
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const T *f = fin + i;   // f[HW + m] is node k0 + i + m
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o) {
+            const T *cf = c.tb[o];
+            T r;
+            if ((PAR >> o) & 1) {   // antisymmetric interior stencil
+                r = T(0);
+#pragma unroll
+                for (int m = 1; m <= MI; ++m) r += cf[kCoefA + 5 + m] * (f[HW + m] - f[HW - m]);
+            } else {
+                r = cf[kCoefA + 5] * f[HW];
+#pragma unroll
+                for (int m = 1; m <= MI; ++m) r += cf[kCoefA + 5 + m] * (f[HW + m] + f[HW - m]);
+            }
+            if constexpr (NL > 0) {
+                // explicit closure rows (identity rows of D_L)
+                if (i < NL && first) {
+                    const T *cl = cf + kCoefCL + i * 11;
+                    T s = T(0);
+#pragma unroll
+                    for (int m = -HW; m <= HW; ++m) s += cl[5 + m] * f[HW + m];
+                    r = s;
+                }
+                if constexpr (PAD) {
+                    if (last) {
+                        const int k = k0 + i;
+                        if (k >= N - NL) {
+                            if (k < N) {
+                                const T *cr = cf + kCoefCR + (N - 1 - k) * 11;
+                                T s = T(0);
+#pragma unroll
+                                for (int m = -HW; m <= HW; ++m) s += cr[5 + m] * f[HW + m];
+                                r = s;
+                            } else {
+                                r = T(0);
+                            }
+                        }
+                    }
+                } else {
+                    if (i >= L - NL && last) {
+                        const T *cr = cf + kCoefCR + (L - 1 - i) * 11;
+                        T s = T(0);
+#pragma unroll
+                        for (int m = -HW; m <= HW; ++m) s += cr[5 + m] * f[HW + m];
+                        r = s;
+                    }
+                }
+                // forward elimination with the partition-local factors
+                const T *fw = cf + kCoefHdr + (int64_t)(k0 + i) * 2;
+                if (i >= 1) r -= fw[0] * y[o][i - 1];
+                if (NL >= 2 && i >= 2) r -= fw[1] * y[o][i - 2];
+            }
+            y[o][i] = r;
+        }
+    }
+
+    if constexpr (NL > 0) {
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o) {
+            const T *cf = c.tb[o];
+#pragma unroll
+            for (int i = L - 1; i >= 0; --i) {
+                const T *bw = cf + kCoefHdr + (int64_t)Npad * 2 + (int64_t)(k0 + i) * 3;
+                T v = y[o][i];
+                if (i + 1 < L) v -= bw[0] * y[o][i + 1];
+                if (NL >= 2 && i + 2 < L) v -= bw[1] * y[o][i + 2];
+                y[o][i] = v * bw[2];
+            }
+        }
+        if (c.periodic || c.P > 1) {
+            const int B = 2 * NL * c.P;
+            const int Bp = B | 1;
+#pragma unroll
+            for (int o = 0; o < NOPS; ++o) {
+                T *row = c.exch + ((int64_t)(c.sub * NOPS + o) * 64 + c.g) * Bp + c.p * 2 * NL;
+#pragma unroll
+                for (int t = 0; t < NL; ++t) {
+                    row[t] = y[o][t];
+                    row[NL + t] = y[o][L - NL + t];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int o = 0; o < NOPS; ++o) {
+                const T *cf = c.tb[o];
+                const T *spk = cf + kCoefHdr + (int64_t)Npad * 5 + (int64_t)c.p * 2 * NL * L;
+                const T *krow = cf + kCoefHdr + (int64_t)Npad * 5 + (int64_t)c.P * 2 * NL * L + (int64_t)c.p * 2 * NL * B;
+                const T *row = c.exch + ((int64_t)(c.sub * NOPS + o) * 64 + c.g) * Bp;
+                T xq[2 * NL];
+#pragma unroll
+                for (int q = 0; q < 2 * NL; ++q) xq[q] = T(0);
+                for (int b = 0; b < B; ++b) {
+                    const T yb = row[b];
+#pragma unroll
+                    for (int q = 0; q < 2 * NL; ++q) xq[q] += krow[q * B + b] * yb;
+                }
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    T v = y[o][i];
+#pragma unroll
+                    for (int q = 0; q < 2 * NL; ++q) v -= xq[q] * spk[q * L + i];
+                    y[o][i] = v;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < NOPS; ++o) {
+        const T hinv = (T)pd.hinv[o];
+#pragma unroll
+        for (int i = 0; i < L; ++i) y[o][i] *= hinv;
+    }
+}
+
+// Stage the x-lines of this item in LDS: row r holds nodes -HW .. Npad+HW-1
+// of line line0 + r (zero outside the ghosts, wrapped for periodic lines,
+// whose Npad equals N).  The per-row source offsets are computed once
+// (rowoff, in LDS); the copy is flat over rows x columns with the column and
+// row advanced incrementally, 8 loads in flight per thread before their LDS
+// writes.
+template <typename T, int HW>
+__device__ __forceinline__ void stage_x(const PassDesc &pd, const T *base, int line0, int nrows, int Npad, T *tile,
+                                        int tpitch, int *rowoff, bool periodic) {
+    const int N = pd.N, ng = pd.ng;
+    const int W = Npad + 2 * HW;
+    const int tid = threadIdx.x;
+    constexpr int NT = 64 * kWGW;
+    for (int r = tid; r < nrows; r += NT) {
+        int line = line0 + r;
+        if (line >= pd.nlines) line = pd.nlines - 1;
+        const int lu = line % pd.nu, lv = line / pd.nu;
+        rowoff[r] = lv * pd.sv + lu * pd.su;
+    }
+    __syncthreads();
+    const int total = nrows * W;
+    const int dr = NT / W, dc = NT - dr * W;
+    int r = tid / W, col = tid - (tid / W) * W;
+    constexpr int BATCH = 8;
+    for (int e0 = 0; e0 < total; e0 += NT * BATCH) {
+        T v[BATCH];
+        int dst[BATCH];
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b) {
+            const int e = e0 + b * NT + tid;
+            dst[b] = -1;
+            v[b] = T(0);
+            if (e < total) {
+                int j = col - HW;
+                bool ok = true;
+                if (periodic) {
+                    if (j < 0) j += N;
+                    if (j >= N) j -= N;
+                } else {
+                    ok = (j >= -ng && j < N + ng);
+                }
+                if (ok) v[b] = base[rowoff[r] + j];
+                dst[b] = r * tpitch + col;
+            }
+            col += dc;
+            r += dr;
+            if (col >= W) { col -= W; ++r; }
+        }
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b)
+            if (dst[b] >= 0) tile[dst[b]] = v[b];
+    }
+}
+
+// Write the x results staged in the tile (row r = line line0 + r, pitch
+// opitch) to the interior output: consecutive x-lines of one field are
+// consecutive rows of the output, so the item's results are one contiguous
+// run of nrows * N elements.
+template <typename T>
+__device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N, int opitch) {
+    constexpr int NT = 64 * kWGW;
+    const int tid = threadIdx.x;
+    const int total = nrows * N;
+    const int dr = NT / N, dc = NT - dr * N;
+    int r = tid / N, col = tid - (tid / N) * N;
+    for (int e = tid; e < total; e += NT) {
+        dst[e] = tile[r * opitch + col];
+        col += dc;
+        r += dr;
+        if (col >= N) { col -= N; ++r; }
+    }
+}
+
+// Item body for one compiled partition length L.
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool PAD>
+__device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *out, bool xdir, bool active,
+                                         int lu, int lv) {
+    const PassDesc &pd = *c.pd;
+    T y[NOPS][L];
+    if (xdir) {
+        solve_partition<T, NL, NOPS, PAR, MI, HW, L, true, PAD>(c, y);
+        // results back through the tile, then contiguous coalesced stores:
+        // x-lines line0.. of one field are consecutive rows of the interior output
+        const int nsub = kWGW / c.P;
+        const int nrows_all = nsub * 64;
+        const int N = pd.N;
+        const int opitch = N | 1;
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o) {
+            __syncthreads();   // every lane is done with the input / previous op in the tile
+#pragma unroll
+            for (int i = 0; i < L; ++i)
+                if (c.p * L + i < N) c.tile[c.trow * opitch + c.p * L + i] = y[o][i];
+            __syncthreads();
+            T *dst = out + pd.out_base[o] + (int64_t)wi.field * pd.out_fstride + (int64_t)wi.line0 * N;
+            int nrows = pd.nlines - wi.line0;
+            if (nrows > nrows_all) nrows = nrows_all;
+            store_x(dst, c.tile, nrows, N, opitch);
+        }
+    } else {
+        solve_partition<T, NL, NOPS, PAR, MI, HW, L, false, PAD>(c, y);
+        if (active) {
+#pragma unroll
+            for (int o = 0; o < NOPS; ++o) {
+                T *dst = out + pd.out_base[o] + (int64_t)wi.field * pd.out_fstride + (int64_t)lv * pd.osv +
+                         (int64_t)lu * pd.osu + (int64_t)c.p * L * pd.osd;
+                const int64_t osd = pd.osd;
+                const int nreal = pd.N - c.p * L;   // rows of this partition inside the line
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    if (!PAD || i < nreal) *dst = y[o][i];
+                    dst += osd;
+                }
+            }
+        }
+    }
+    __syncthreads();   // LDS (tile and exchange) is reused by the next item
+}
+
+template <int... Ls>
+struct LSet {
+    static constexpr int n = sizeof...(Ls);
+};
+
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L0, int... Ls>
+__device__ __forceinline__ void dispatch_L(int lcode, bool pad, LineCtx<T> &c, const WorkItem &wi, T *out,
+                                           bool xdir, bool active, int lu, int lv) {
+    if (lcode == 0) {
+        if (pad)
+            run_item<T, NL, NOPS, PAR, MI, HW, L0, true>(c, wi, out, xdir, active, lu, lv);
+        else
+            run_item<T, NL, NOPS, PAR, MI, HW, L0, false>(c, wi, out, xdir, active, lu, lv);
+        return;
+    }
+    if constexpr (sizeof...(Ls) > 0) dispatch_L<T, NL, NOPS, PAR, MI, HW, Ls...>(lcode - 1, pad, c, wi, out,
+                                                                                 xdir, active, lu, lv);
+}
+
+// Persistent line kernel: every workgroup walks the work list with a grid
+// stride.  Work item meta: P in bits 0..3, index of L in the compiled set in
+// bits 4..7.  Dynamic LDS: exchange area, then the x tile.
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int... Ls>
+__global__ void __launch_bounds__(64 * kWGW)
+k_lines(const WorkItem *__restrict__ items, int nitems, const PassDesc *__restrict__ passes,
+        const T *__restrict__ tabs, const int64_t *__restrict__ taboff, const T *__restrict__ in,
+        T *__restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *exch = reinterpret_cast<T *>(smem_raw);
+    int *rowoff = reinterpret_cast<int *>(exch + exch_elems<NL, NOPS>());   // 256 row offsets
+    T *tile = exch + exch_elems<NL, NOPS>() + 256 * sizeof(int) / sizeof(T);
+    constexpr int kLs[] = {Ls...};
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = threadIdx.x & 63;
+
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const WorkItem wi = items[it];
+        const PassDesc &pd = passes[wi.pass];
+        LineCtx<T> c;
+        c.pd = &pd;
+        c.P = wi.meta & 15;
+        const int lcode = (wi.meta >> 4) & 15;
+        c.sub = w / c.P;
+        c.p = w - c.sub * c.P;
+        c.g = g;
+        c.periodic = pd.periodic != 0;
+        c.exch = exch;
+        c.tile = tile;
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o) c.tb[o] = tabs + taboff[pd.tab[o]];
+        const bool xdir = pd.sd == 1;
+        int line = wi.line0 + c.sub * 64 + g;
+        const bool active = line < pd.nlines;
+        if (!active) line = pd.nlines - 1;
+        const int lu = line % pd.nu;
+        const int lv = line / pd.nu;
+        const T *fbase = in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride;
+        if (xdir) {
+            const int nsub = kWGW / c.P;
+            const int Npad = c.P * kLs[lcode];
+            c.tpitch = (Npad + 2 * HW) | 1;
+            c.trow = c.sub * 64 + g;
+            stage_x<T, HW>(pd, fbase, wi.line0, nsub * 64, Npad, tile, c.tpitch, rowoff, c.periodic);
+            __syncthreads();
+        } else {
+            c.src = fbase + (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
+        }
+        const bool pad = c.P * kLs[lcode] != pd.N;
+        dispatch_L<T, NL, NOPS, PAR, MI, HW, Ls...>(lcode, pad, c, wi, out, xdir, active, lu, lv);
+    }
+}
+
+}  // namespace cfd

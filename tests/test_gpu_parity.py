@@ -60,3 +60,62 @@ def test_periodic_dxyz(cuda, n):
     g = H.gpu_run(plan, wl, ops)
     o = H.oracle_run(wl, ops)
     assert H.max_rel_err(g, o) <= H.ERR_F64
+
+
+def _schedules(plan_Ns):
+    for N in plan_Ns:
+        for x in (0, 1):
+            for P in (1, 2, 4):
+                yield N, x, P
+
+
+def test_every_schedule_same_result(cuda):
+    """Partition counts, persistent / per-item grids and fused / split x launches all agree with the oracle."""
+    import paper_2302_14858_amd as P
+    wl = synth.batch64(nblocks=4, nfields=2, sizes=(16, 24, 32, 48), seed=5)
+    plan = H.make_plan(wl, D12_PENTA)
+    o = H.oracle_run(wl, D12_PENTA)
+    tried = 0
+    for N in sorted({b.n[d] for b in wl.blocks for d in range(3)}):
+        for x in (0, 1):
+            for parts in (1, 2, 4):
+                try:
+                    plan.set_schedule(N, x, parts, persistent=bool(parts % 2), split_x=(parts == 2))
+                except P.CfdError:
+                    continue
+                g = H.gpu_run(plan, wl, D12_PENTA)
+                assert H.max_rel_err(g, o) <= H.ERR_F64, (N, x, parts)
+                tried += 1
+    assert tried >= 8
+
+
+def test_periodic_partitions_long_lines(cuda):
+    """Cyclic solve split over 1, 2 and 4 partitions (the reduced system closes the wrap)."""
+    wl = synth.periodic256(n=128, nfields=1, nmodes=8, kmax=40)
+    ops = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2)]
+    plan = H.make_plan(wl, ops)
+    o = H.oracle_run(wl, ops)
+    for x in (0, 1):
+        for parts in (2, 4):
+            plan.set_schedule(128, x, parts)
+            g = H.gpu_run(plan, wl, ops)
+            assert H.max_rel_err(g, o) <= H.ERR_F64, (x, parts)
+
+
+def test_graph_replay_matches_eager(cuda):
+    import torch
+    wl = synth.batch64(nblocks=3, nfields=2)
+    plan = H.make_plan(wl, D12_PENTA)
+    nin, nout = plan.sizes()
+    x = torch.from_numpy(wl.data).cuda()
+    y_eager = torch.empty(nout, dtype=torch.float64, device="cuda")
+    y_graph = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.apply(x, y_eager)
+    plan.capture_graph(x, y_graph)
+    for rep in range(4):
+        y_graph.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.launch_graph()
+        torch.cuda.synchronize()
+        assert torch.equal(y_graph, y_eager), rep
+        x.mul_(1.0)   # unrelated eager work between replays
