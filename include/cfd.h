@@ -207,6 +207,8 @@ cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream);
 /* Schedule flags. */
 #define CFD_SCHED_PERSISTENT 1   /* grid of (occupancy x CUs) workgroups walking the work list */
 #define CFD_SCHED_SPLIT_X    2   /* lines along x in a launch of their own */
+#define CFD_SCHED_XCD        4   /* persistent grid with one work queue per XCD: the
+                                    x/y/z passes of a block-field stay on one L2 */
 
 /* Time the candidate schedules on the given buffers and keep the fastest:
  * the number of partitions per line for every (line length, x or y/z) class,
@@ -224,8 +226,10 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
  * CFD_EINVAL if no compiled kernel fits.  Invalidates a captured graph. */
 cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions, int flags);
 
-/* Read back the schedule: flags and, for up to cap line classes, their
- * (N, xlines, partitions).  n_classes receives the number of classes. */
+/* Read back the schedule: persistent receives 0 (one workgroup per item),
+ * 1 (persistent grid) or 2 (persistent, XCD-aware queues); split_x the x split
+ * flag; for up to cap line classes their (N, xlines, partitions).  n_classes
+ * receives the number of classes. */
 cfd_status cfd_plan_get_schedule(const cfd_plan *p, int *persistent, int *split_x, int *n_classes, int *N,
                                  int *xlines, int *partitions, int cap);
 

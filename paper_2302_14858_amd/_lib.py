@@ -12,7 +12,7 @@ STATUS_NAMES = ["CFD_OK", "CFD_EINVAL", "CFD_EGHOST", "CFD_ESHAPE", "CFD_ESINGUL
                 "CFD_EUNSUPPORTED"]
 CFD_F64, CFD_F32, CFD_MIXED_BF16 = 0, 1, 2
 CFD_BOUNDARY_CLOSURE, CFD_BOUNDARY_PERIODIC = 0, 1
-CFD_SCHED_PERSISTENT, CFD_SCHED_SPLIT_X = 1, 2
+CFD_SCHED_PERSISTENT, CFD_SCHED_SPLIT_X, CFD_SCHED_XCD = 1, 2, 4
 
 
 class cfd_block(ctypes.Structure):

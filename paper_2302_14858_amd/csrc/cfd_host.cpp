@@ -85,6 +85,7 @@ struct Group {
     size_t lds;
     int64_t item0, nitems;
     int grid_persist;
+    int qoff_index = -1;   // offset of this group's 9 queue bounds in d_qoff (XCD-aware mode)
 };
 
 struct TabKey {
@@ -111,10 +112,11 @@ struct cfd_plan {
     std::map<std::pair<int, int>, int> sched_P;   // (N, x-direction) -> partitions per line
     bool persistent = true;
     bool split_x = false;                 // x-lines in a launch of their own
+    bool xcd = false;                     // XCD-aware queues (persistent grid only)
     int cus = 256;
     size_t max_lds = 65536;
     // device state rebuilt by build()
-    DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff;
+    DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff, d_qoff;
     std::vector<Group> groups;
     int64_t nitems = 0;
     hipStream_t cap_stream = nullptr;
@@ -135,6 +137,7 @@ struct cfd_plan {
         d_pass.release();
         d_items.release();
         d_inoff.release();
+        d_qoff.release();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
     }
@@ -143,6 +146,8 @@ struct cfd_plan {
 namespace {
 
 size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }
+
+constexpr int kXCDq = 8;   // queues of the XCD-aware schedule (one per XCD)
 
 // Tile bytes an x item with P partitions of L rows needs in LDS.
 size_t x_tile_bytes(int P, int L, int hw, size_t es) {
@@ -352,6 +357,8 @@ cfd_status build(cfd_plan *p) {
     const size_t es = f32 ? 4 : 8;
     std::map<std::pair<const void *, int>, int> gidx;
     std::vector<std::vector<WorkItem>> gitems;
+    std::vector<std::vector<int>> gbf;        // block-field of each item
+    std::vector<std::vector<int64_t>> gcost;  // rows x lines of each item
     std::vector<Group> groups;
     std::vector<std::vector<int>> by_block(p->blocks.size());
     for (size_t i = 0; i < p->passes.size(); ++i) by_block[p->passes[i].block].push_back((int)i);
@@ -372,6 +379,8 @@ cfd_status build(cfd_plan *p) {
                     g.lds = (size_t)ps.cls->exch * es;
                     groups.push_back(g);
                     gitems.emplace_back();
+                    gbf.emplace_back();
+                    gcost.emplace_back();
                 } else {
                     gi = it->second;
                 }
@@ -380,12 +389,16 @@ cfd_status build(cfd_plan *p) {
                                                                   x_tile_bytes(ps.P, ps.L, ps.cls->hw, es));
                 const int per_item = kWave * (4 / ps.P);
                 const int meta = ps.P | (ps.lcode << 4);
-                for (int l0 = 0; l0 < pd[i].nlines; l0 += per_item)
+                for (int l0 = 0; l0 < pd[i].nlines; l0 += per_item) {
                     gitems[gi].push_back(WorkItem{(int32_t)i, f - ps.field0, l0, meta});
+                    gbf[gi].push_back((int)(b * p->nfields + f));
+                    gcost[gi].push_back((int64_t)per_item * ps.P * ps.L);
+                }
             }
         }
     }
     std::vector<WorkItem> items;
+    std::vector<int> qoffs;
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         Group &g = groups[gi];
         g.item0 = (int64_t)items.size();
@@ -395,9 +408,41 @@ cfd_status build(cfd_plan *p) {
             nb = 1;
         (void)hipGetLastError();
         g.grid_persist = (int)std::min<int64_t>(g.nitems, (int64_t)nb * p->cus);
-        items.insert(items.end(), gitems[gi].begin(), gitems[gi].end());
+        if (p->xcd && p->persistent && g.nitems >= 8 * kXCDq) {
+            // deal whole block-fields to kXCDq queues, least-loaded first, keeping
+            // each block-field's items (its x/y/z passes) together and in order
+            std::vector<std::vector<WorkItem>> q(kXCDq);
+            std::vector<int64_t> load(kXCDq, 0);
+            const auto &its = gitems[gi];
+            size_t a = 0;
+            while (a < its.size()) {
+                size_t e = a;
+                int64_t cost = 0;
+                while (e < its.size() && gbf[gi][e] == gbf[gi][a]) cost += gcost[gi][e++];
+                const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                q[k].insert(q[k].end(), its.begin() + a, its.begin() + e);
+                load[k] += cost;
+                a = e;
+            }
+            g.qoff_index = (int)qoffs.size();
+            int off = 0;
+            for (int k = 0; k < kXCDq; ++k) {
+                qoffs.push_back(off);
+                off += (int)q[k].size();
+                items.insert(items.end(), q[k].begin(), q[k].end());
+            }
+            qoffs.push_back(off);
+            g.grid_persist = std::max(kXCDq, (g.grid_persist / kXCDq) * kXCDq);
+        } else {
+            items.insert(items.end(), gitems[gi].begin(), gitems[gi].end());
+        }
     }
     p->groups = groups;
+    p->d_qoff.release();
+    if (!qoffs.empty()) {
+        HIPCHK(hipMalloc(&p->d_qoff.p, qoffs.size() * sizeof(int)));
+        HIPCHK(hipMemcpy(p->d_qoff.p, qoffs.data(), qoffs.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     p->nitems = (int64_t)items.size();
     p->d_items.release();
     HIPCHK(hipMalloc(&p->d_items.p, std::max<size_t>(1, items.size()) * sizeof(WorkItem)));
@@ -410,8 +455,9 @@ cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
     for (const Group &g : p->groups) {
         if (g.nitems == 0) continue;
         const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
+        const int *qoff = (g.qoff_index >= 0) ? (const int *)p->d_qoff.p + g.qoff_index : nullptr;
         hipError_t e = launch_lines(g.fn, grid, g.lds, st, (const WorkItem *)p->d_items.p + g.item0,
-                                    (int)g.nitems, (const PassDesc *)p->d_pass.p, tabs,
+                                    (int)g.nitems, qoff, (const PassDesc *)p->d_pass.p, tabs,
                                     (const int64_t *)p->d_taboff.p, in, out);
         if (e != hipSuccess) return hip_fail(e, "launching line kernel");
     }
@@ -735,7 +781,7 @@ cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream) {
 
 cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions, int flags) {
     if (!p) return fail(CFD_EINVAL, "cfd_plan_set_schedule: null plan");
-    if (flags & ~(CFD_SCHED_PERSISTENT | CFD_SCHED_SPLIT_X))
+    if (flags & ~(CFD_SCHED_PERSISTENT | CFD_SCHED_SPLIT_X | CFD_SCHED_XCD))
         return fail(CFD_EINVAL, "cfd_plan_set_schedule: unknown flag");
     if (N > 0) {
         const auto key = std::make_pair(N, xlines ? 1 : 0);
@@ -756,6 +802,7 @@ cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions,
     }
     p->persistent = (flags & CFD_SCHED_PERSISTENT) != 0;
     p->split_x = (flags & CFD_SCHED_SPLIT_X) != 0;
+    p->xcd = (flags & CFD_SCHED_XCD) != 0;
     return build(p);
 }
 
@@ -835,19 +882,23 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         new_lines.push_back(key + " " + std::to_string(bestP));
     }
     if (result == CFD_OK) {
-        // launch shape: persistent grid or one workgroup per item; x lines fused or split
+        // launch shape: persistent grid (plain or XCD-aware queues) or one
+        // workgroup per item; x lines fused with y/z or split
         float best = 1e30f;
-        bool bp = true, bs = false;
-        for (int pers = 1; pers >= 0 && result == CFD_OK; --pers)
+        int bmode = 1;
+        bool bs = false;
+        for (int mode = 0; mode < 3 && result == CFD_OK; ++mode)
             for (int split = 0; split <= 1 && result == CFD_OK; ++split) {
-                p->persistent = pers;
+                p->persistent = mode != 0;
+                p->xcd = mode == 2;
                 p->split_x = split;
                 result = build(p);
                 float ms = 0;
                 if (result == CFD_OK) result = time_apply(ms);
-                if (result == CFD_OK && ms < best) { best = ms; bp = pers; bs = split; }
+                if (result == CFD_OK && ms < best) { best = ms; bmode = mode; bs = split; }
             }
-        p->persistent = bp;
+        p->persistent = bmode != 0;
+        p->xcd = bmode == 2;
         p->split_x = bs;
     }
     (void)hipEventDestroy(e0);
@@ -863,7 +914,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
 cfd_status cfd_plan_get_schedule(const cfd_plan *p, int *persistent, int *split_x, int *n_classes, int *N,
                                  int *xlines, int *partitions, int cap) {
     if (!p) return fail(CFD_EINVAL, "cfd_plan_get_schedule: null plan");
-    if (persistent) *persistent = p->persistent;
+    if (persistent) *persistent = p->persistent ? (p->xcd ? 2 : 1) : 0;
     if (split_x) *split_x = p->split_x;
     std::map<std::pair<int, int>, int> used;
     for (const PassHost &ps : p->passes) used[std::make_pair(ps.N, ps.dir == 0 ? 1 : 0)] = ps.P;

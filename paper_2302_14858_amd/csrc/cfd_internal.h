@@ -107,7 +107,8 @@ struct LineClass;
 const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L);
 int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap);
 hipError_t launch_lines(const void *fn, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
-                        const PassDesc *passes, const void *tabs, const int64_t *taboff, const void *in, void *out);
+                        const int *qoff, const PassDesc *passes, const void *tabs, const int64_t *taboff,
+                        const void *in, void *out);
 hipError_t launch_build_tables(int ntab, const void *specs, double *data, double *scratch, int64_t scratch_per,
                                int *status, hipStream_t st);
 hipError_t launch_to_f32(int64_t n, const double *a, float *b, hipStream_t st);

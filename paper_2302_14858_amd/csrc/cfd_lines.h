@@ -38,6 +38,7 @@
 namespace cfd {
 
 constexpr int kWGW = 4;   // wavefronts per workgroup
+constexpr int kXCD = 8;   // accelerator complex dies (each with its own L2)
 
 
 
@@ -52,6 +53,21 @@ __host__ __device__ constexpr int exch_elems() {
         best = v > best ? v : best;
     }
     return NL > 0 ? best : 0;
+}
+
+// Derivatives are written once and not read again by this launch: streaming
+// (non-temporal) stores keep them from evicting the input lines that the other
+// directions' passes over the same block-field re-read from L2.
+#ifndef CFD_NT_STORES
+#define CFD_NT_STORES 1
+#endif
+template <typename T>
+__device__ __forceinline__ void store_out(T *p, T v) {
+#if CFD_NT_STORES
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
 }
 
 // Per-item context shared by the template bodies.
@@ -301,7 +317,7 @@ __device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N,
     const int dr = NT / N, dc = NT - dr * N;
     int r = tid / N, col = tid - (tid / N) * N;
     for (int e = tid; e < total; e += NT) {
-        dst[e] = tile[r * opitch + col];
+        store_out(dst + e, tile[r * opitch + col]);
         col += dc;
         r += dr;
         if (col >= N) { col -= N; ++r; }
@@ -345,7 +361,7 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
                 const int nreal = pd.N - c.p * L;   // rows of this partition inside the line
 #pragma unroll
                 for (int i = 0; i < L; ++i) {
-                    if (!PAD || i < nreal) *dst = y[o][i];
+                    if (!PAD || i < nreal) store_out(dst, y[o][i]);
                     dst += osd;
                 }
             }
@@ -378,9 +394,9 @@ __device__ __forceinline__ void dispatch_L(int lcode, bool pad, LineCtx<T> &c, c
 // bits 4..7.  Dynamic LDS: exchange area, then the x tile.
 template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int... Ls>
 __global__ void __launch_bounds__(64 * kWGW)
-k_lines(const WorkItem *__restrict__ items, int nitems, const PassDesc *__restrict__ passes,
-        const T *__restrict__ tabs, const int64_t *__restrict__ taboff, const T *__restrict__ in,
-        T *__restrict__ out) {
+k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ qoff,
+        const PassDesc *__restrict__ passes, const T *__restrict__ tabs, const int64_t *__restrict__ taboff,
+        const T *__restrict__ in, T *__restrict__ out) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *exch = reinterpret_cast<T *>(smem_raw);
     int *rowoff = reinterpret_cast<int *>(exch + exch_elems<NL, NOPS>());   // 256 row offsets
@@ -389,7 +405,19 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const PassDesc *__restri
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = threadIdx.x & 63;
 
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    // Work distribution.  Plain: grid-stride over the list.  XCD-aware (qoff
+    // given, grid a multiple of kXCD): workgroup ids are dealt round-robin to
+    // the XCDs, so workgroup b runs on XCD b % kXCD and takes the items of
+    // queue b % kXCD; each queue holds whole block-fields, whose x/y/z passes
+    // then share one XCD's L2.
+    int it = blockIdx.x, it_end = nitems, stride = gridDim.x;
+    if (qoff) {
+        const int q = blockIdx.x % kXCD;
+        it = qoff[q] + blockIdx.x / kXCD;
+        it_end = qoff[q + 1];
+        stride = gridDim.x / kXCD;
+    }
+    for (; it < it_end; it += stride) {
         const WorkItem wi = items[it];
         const PassDesc &pd = passes[wi.pass];
         LineCtx<T> c;

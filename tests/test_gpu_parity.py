@@ -80,13 +80,19 @@ def test_every_schedule_same_result(cuda):
         for x in (0, 1):
             for parts in (1, 2, 4):
                 try:
-                    plan.set_schedule(N, x, parts, persistent=bool(parts % 2), split_x=(parts == 2))
+                    plan.set_schedule(N, x, parts, persistent=(parts != 2), split_x=(parts == 2),
+                                      xcd=(parts == 4))
                 except P.CfdError:
                     continue
                 g = H.gpu_run(plan, wl, D12_PENTA)
                 assert H.max_rel_err(g, o) <= H.ERR_F64, (N, x, parts)
                 tried += 1
     assert tried >= 8
+    for mode in ({"persistent": True, "xcd": True}, {"persistent": True, "xcd": True, "split_x": True},
+                 {"persistent": False}):
+        plan.set_schedule(0, **mode)
+        g = H.gpu_run(plan, wl, D12_PENTA)
+        assert H.max_rel_err(g, o) <= H.ERR_F64, mode
 
 
 def test_periodic_partitions_long_lines(cuda):
