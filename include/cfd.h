@@ -258,6 +258,24 @@ cfd_status cfd_axpby(cfd_dtype dtype, long long n, double a, const void *x_dev, 
 cfd_status cfd_xpcy(cfd_dtype dtype, long long n, const void *x_dev, double c, const void *y_dev,
                     void *z_dev, void *stream);
 
+/* One explicit Runge-Kutta stage of the first-order wave system
+ *   d_t phi = Pi,  d_t Pi = sum_i d_i psi_i,  d_t psi_i = d_i Pi
+ * (the first-order reduction of the wave equation behind the shifted-wave
+ * tests of Sec. 3) for a plan with nfields = 5 (phi, Pi, psi_x, psi_y, psi_z)
+ * and exactly the six operators [D_x Pi, D_y Pi, D_z Pi, D_x psi_x, D_y psi_y,
+ * D_z psi_z] (op = {scheme of degree 1, dir, field}).  src_dev is the stage
+ * state and derivs_dev the plan's output computed from it; the right-hand side
+ * k is assembled on interior nodes and
+ *   stage = u0 + a k   (skipped if stage_dev is NULL; stage may equal src;
+ *                       ghosts untouched),
+ *   acc  += b k.
+ * u0, src, stage and acc are in the plan's input layout (element type per
+ * dtype).  Classical RK4: acc = u; stage sources u, s, s, s with
+ * a = dt/2, dt/2, dt, - and b = dt/6, dt/3, dt/3, dt/6 (s written in place);
+ * then u = acc and refresh ghosts with cfd_halo_exchange. */
+cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev,
+                             void *acc_dev, const void *derivs_dev, double a, double b, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -200,6 +200,13 @@ class Plan:
 
     get_schedule = cfd_plan_get_schedule
 
+    def cfd_wave_rk_stage(self, u0, src, stage, acc, derivs, a: float, b: float, stream=None) -> None:
+        check(lib().cfd_wave_rk_stage(self._h, _dev_ptr(u0), _dev_ptr(src),
+                                      _dev_ptr(stage) if stage is not None else None, _dev_ptr(acc),
+                                      _dev_ptr(derivs), float(a), float(b), _stream_ptr(stream)))
+
+    wave_rk_stage = cfd_wave_rk_stage
+
     def cfd_halo_exchange(self, data, bx: int, by: int, bz: int, stream=None) -> None:
         check(lib().cfd_halo_exchange(self._h, _dev_ptr(data), bx, by, bz, _stream_ptr(stream)))
 

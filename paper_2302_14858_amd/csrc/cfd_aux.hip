@@ -95,6 +95,49 @@ __global__ void k_xpcy(int64_t n, const T *__restrict__ x, T c, const T *__restr
         z[i] = x[i] + c * y[i];
 }
 
+// Method-of-lines stage for the first-order wave system
+//   d_t phi = Pi,  d_t Pi = sum_i d_i psi_i,  d_t psi_i = d_i Pi
+// on one block: k is assembled from the stage state src (its Pi) and the
+// derivative outputs d = [D_x Pi, D_y Pi, D_z Pi, D_x psi_x, D_y psi_y,
+// D_z psi_z] computed from src (interior, [op][z][y][x]); on interior nodes
+// stage = u0 + a k (if stage is given; stage may alias src, each node is read
+// before it is written by the same thread) and acc += b k.  State arrays hold
+// the five fields with ghosts, [f][z][y][x].
+template <typename T>
+__global__ void k_wave_stage(const T *u0, const T *src, T *stage, T *__restrict__ acc,
+                             const T *__restrict__ d, const int64_t *__restrict__ in_off,
+                             const int64_t *__restrict__ out_off, const int *__restrict__ shapes, int nblocks,
+                             int64_t total, T a, T b) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        // locate the block: shapes[4b..4b+3] = nx, ny, nz, ng; blocks are
+        // enumerated by a running count of interior points (prefix in shapes[4*nblocks + b])
+        int lo = 0, hi = nblocks - 1;
+        const int *pre = shapes + 4 * nblocks;   // int64 prefix stored as 2 ints per block
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            const int64_t pm = ((int64_t)pre[2 * mid + 1] << 32) | (uint32_t)pre[2 * mid];
+            if (pm <= e) lo = mid; else hi = mid - 1;
+        }
+        const int bi = lo;
+        const int64_t pb = ((int64_t)pre[2 * bi + 1] << 32) | (uint32_t)pre[2 * bi];
+        const int nx = shapes[4 * bi], ny = shapes[4 * bi + 1], nz = shapes[4 * bi + 2], ng = shapes[4 * bi + 3];
+        const int64_t r = e - pb;
+        const int64_t n3 = (int64_t)nx * ny * nz;
+        const int x = (int)(r % nx), y = (int)((r / nx) % ny), z = (int)(r / ((int64_t)nx * ny));
+        const int64_t PX = nx + 2 * ng, PY = ny + 2 * ng, PZ = nz + 2 * ng;
+        const int64_t fs = PX * PY * PZ;
+        const int64_t ip = in_off[bi] + ((int64_t)(z + ng) * PY + (y + ng)) * PX + (x + ng);
+        const T *db = d + out_off[bi] + r;
+        const T k[5] = {src[ip + fs], db[3 * n3] + db[4 * n3] + db[5 * n3], db[0], db[n3], db[2 * n3]};
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            if (stage) stage[ip + f * fs] = u0[ip + f * fs] + a * k[f];
+            acc[ip + f * fs] += b * k[f];
+        }
+    }
+}
+
 static int grid_for(int64_t n) {
     int64_t g = (n + 255) / 256;
     if (g > 8192) g = 8192;
@@ -137,4 +180,24 @@ hipError_t launch_xpcy(int f32, int64_t n, const void *x, double c, const void *
     return hipGetLastError();
 }
 
+}  // namespace cfd
+
+namespace cfd {
+hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *stage, void *acc, const void *d,
+                             const int64_t *in_off, const int64_t *out_off, const int *shapes, int nblocks,
+                             int64_t total, double a, double b, hipStream_t st) {
+    if (total == 0) return hipSuccess;
+    int64_t g = (total + 255) / 256;
+    if (g > 16384) g = 16384;
+    if (f32)
+        hipLaunchKernelGGL(k_wave_stage<float>, dim3((int)g), dim3(256), 0, st, (const float *)u0, (const float *)src,
+                           (float *)stage,
+                           (float *)acc, (const float *)d, in_off, out_off, shapes, nblocks, total, (float)a,
+                           (float)b);
+    else
+        hipLaunchKernelGGL(k_wave_stage<double>, dim3((int)g), dim3(256), 0, st, (const double *)u0,
+                           (const double *)src, (double *)stage, (double *)acc, (const double *)d, in_off, out_off, shapes, nblocks,
+                           total, a, b);
+    return hipGetLastError();
+}
 }  // namespace cfd

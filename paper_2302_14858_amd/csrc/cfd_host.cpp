@@ -116,7 +116,7 @@ struct cfd_plan {
     int cus = 256;
     size_t max_lds = 65536;
     // device state rebuilt by build()
-    DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff, d_qoff;
+    DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff, d_qoff, d_outoff, d_shapes;
     std::vector<Group> groups;
     int64_t nitems = 0;
     hipStream_t cap_stream = nullptr;
@@ -138,6 +138,8 @@ struct cfd_plan {
         d_items.release();
         d_inoff.release();
         d_qoff.release();
+        d_outoff.release();
+        d_shapes.release();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
     }
@@ -967,6 +969,52 @@ cfd_status cfd_xpcy(cfd_dtype dtype, long long n, const void *x_dev, double c, c
     if (dtype != CFD_F64 && dtype != CFD_F32) return fail(CFD_EINVAL, "cfd_xpcy: dtype must be F64 or F32");
     hipError_t e = launch_xpcy(dtype == CFD_F32, n, x_dev, c, y_dev, z_dev, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launching xpcy");
+    return CFD_OK;
+}
+
+cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev, void *acc_dev,
+                             const void *derivs_dev, double a, double b, void *stream) {
+    if (!p || !u0_dev || !src_dev || !acc_dev || !derivs_dev)
+        return fail(CFD_EINVAL, "cfd_wave_rk_stage: null argument");
+    // the plan must hold the five wave fields and the six first-derivative operators
+    static const int want[6][2] = {{0, 1}, {1, 1}, {2, 1}, {0, 2}, {1, 3}, {2, 4}};
+    if (p->nfields != 5 || p->ops.size() != 6)
+        return fail(CFD_EINVAL, "cfd_wave_rk_stage: plan needs 5 fields and 6 operators");
+    for (int o = 0; o < 6; ++o)
+        if (p->ops[o].dir != want[o][0] || p->ops[o].field != want[o][1] || p->schemes[o].d != 1)
+            return fail(CFD_EINVAL, "cfd_wave_rk_stage: operators must be D_x Pi, D_y Pi, D_z Pi, D_x psi_x, "
+                                    "D_y psi_y, D_z psi_z (first derivatives)");
+    if (p->dtype != CFD_F64 && p->dtype != CFD_F32) return fail(CFD_EINVAL, "cfd_wave_rk_stage: dtype");
+    HIPCHK(hipSetDevice(p->device));
+    const int nb = (int)p->blocks.size();
+    if (!p->d_shapes.p) {
+        std::vector<int> sh(4 * nb + 2 * nb);
+        int64_t pre = 0;
+        for (int b = 0; b < nb; ++b) {
+            const cfd_block &bl = p->blocks[b];
+            sh[4 * b] = bl.n[0];
+            sh[4 * b + 1] = bl.n[1];
+            sh[4 * b + 2] = bl.n[2];
+            sh[4 * b + 3] = bl.ng;
+            sh[4 * nb + 2 * b] = (int)(uint32_t)(pre & 0xffffffff);
+            sh[4 * nb + 2 * b + 1] = (int)(pre >> 32);
+            pre += (int64_t)bl.n[0] * bl.n[1] * bl.n[2];
+        }
+        HIPCHK(hipMalloc(&p->d_shapes.p, sh.size() * sizeof(int)));
+        HIPCHK(hipMemcpy(p->d_shapes.p, sh.data(), sh.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMalloc(&p->d_outoff.p, nb * sizeof(int64_t)));
+        HIPCHK(hipMemcpy(p->d_outoff.p, p->out_off.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
+    if (!p->d_inoff.p) {
+        HIPCHK(hipMalloc(&p->d_inoff.p, p->in_off.size() * sizeof(int64_t)));
+        HIPCHK(hipMemcpy(p->d_inoff.p, p->in_off.data(), p->in_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
+    int64_t total = 0;
+    for (const cfd_block &bl : p->blocks) total += (int64_t)bl.n[0] * bl.n[1] * bl.n[2];
+    hipError_t e = launch_wave_stage(p->dtype == CFD_F32, u0_dev, src_dev, stage_dev, acc_dev, derivs_dev,
+                                     (const int64_t *)p->d_inoff.p, (const int64_t *)p->d_outoff.p,
+                                     (const int *)p->d_shapes.p, nb, total, a, b, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launching wave stage");
     return CFD_OK;
 }
 
