@@ -566,13 +566,6 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
     if (desc->dtype == CFD_MIXED_BF16)
         return fail(CFD_EUNSUPPORTED, "cfd_plan_create: the dense mixed-precision path is created with "
                                       "cfd_dense_plan_create");
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
-        (void)hipGetLastError();
-        return fail(CFD_EDEVICE, "cfd_plan_create: no HIP device");
-    }
-    if (desc->device < 0 || desc->device >= ndev) return fail(CFD_EINVAL, "cfd_plan_create: bad device ordinal");
-
     std::unique_ptr<cfd_plan> p(new cfd_plan);
     p->device = desc->device;
     p->dtype = desc->dtype;
@@ -699,6 +692,13 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
             }
         }
     }
+    // the descriptor is valid; from here on the device is needed
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(CFD_EDEVICE, "cfd_plan_create: no HIP device");
+    }
+    if (desc->device < 0 || desc->device >= ndev) return fail(CFD_EINVAL, "cfd_plan_create: bad device ordinal");
     HIPCHK(hipSetDevice(p->device));
     {
         hipDeviceProp_t prop;

@@ -1,0 +1,138 @@
+"""The C ABI without a GPU: exported symbols, scheme construction on the host,
+validation and error paths.  No kernel is launched here."""
+import ctypes
+import re
+import os
+
+import numpy as np
+import pytest
+
+import paper_2302_14858_amd as P
+from paper_2302_14858_amd import _lib
+from oracle import schemes as OS
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "cfd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cfd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+def test_abi_version():
+    assert P.cfd_abi_version() == 1
+
+
+NAMES = ["(1)P1_1", "(2)P1_1", "(1)P1_2", "(2)P1_2", "(1)P1_3", "(2)P1_3", "(1)Q1_3[1]", "(2)Q1_3[1]",
+         "(1)Q1_3[4pi/5]", "(2)Q1_3[4pi/5]", "(1)QP_O8[1]", "(2)QP_O8[1]", "(1)Q1_3[1]:E", "(2)QP_O8[1]:E",
+         "(1)E3", "(2)E4"]
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_registry_matches_oracle_construction(name):
+    """The library's binary128 construction and the oracle's exact/mpmath one agree to round-off."""
+    g = P.Scheme.named(name).get()
+    o = OS.named(name)
+    lhs = np.zeros(5)
+    lhs[2 - o.nl:3 + o.nl] = o.lhs_floats()
+    rhs = np.zeros(11)
+    rhs[5 - o.M:6 + o.M] = o.rhs_floats()
+    assert np.max(np.abs(lhs - g["lhs"])) <= 2e-16
+    assert np.max(np.abs(rhs - g["rhs"])) <= 4e-16 * max(1, np.max(np.abs(rhs)))
+    mc, rows = o.closure_floats()
+    for j, r in enumerate(rows):
+        c = np.zeros(11)
+        c[5 - mc:6 + mc] = r
+        assert np.max(np.abs(c - np.array(g["closure"][j]))) <= 4e-16 * max(1, np.max(np.abs(c)))
+    assert P.Scheme.named(name).required_ghosts() == OS.required_ghosts(o, False)
+    assert P.Scheme.named(name).required_ghosts(P.CFD_BOUNDARY_PERIODIC) == 0
+
+
+def test_design_general_scheme():
+    """cfd_scheme_design reproduces the registry entry it generalises."""
+    a = P.Scheme.design(1, 6, 1, 3, 1.0, 4, True).get()
+    b = P.Scheme.named("(1)Q1_3[1]").get()
+    assert np.allclose(a["lhs"], b["lhs"], atol=1e-16) and np.allclose(a["rhs"], b["rhs"], atol=1e-16)
+
+
+def test_create_from_paper_table():
+    """(1)P1_2 with its closure typed from Tab. pade_deg_one is accepted."""
+    s = P.Scheme.create(1, 6, [1 / 3, 1, 1 / 3], [-1 / 36, -28 / 36, 0, 28 / 36, 1 / 36],
+                        [[v / 300 for v in (1, -11, 59, -239, 0, 239, -59, 11, -1)]])
+    g = s.get()
+    assert g["nl"] == 1 and g["mc"] == 4
+    assert s.required_ghosts() == 4
+
+
+def test_create_rejects_inconsistent_coefficients():
+    with pytest.raises(P.CfdError) as e:
+        P.Scheme.create(1, 6, [1 / 3, 1, 1 / 3], [-1 / 36, -28 / 36, 0, 28 / 36, 1.01 / 36],
+                        [[v / 300 for v in (1, -11, 59, -239, 0, 239, -59, 11, -1)]])
+    assert e.value.status == _lib.CFD_EINVAL
+    with pytest.raises(P.CfdError):
+        P.Scheme.create(1, 6, [1 / 3, 0.9, 1 / 3], [-1 / 36, -28 / 36, 0, 28 / 36, 1 / 36], [[0.0] * 9])
+
+
+def test_unknown_name():
+    with pytest.raises(P.CfdError) as e:
+        P.Scheme.named("(1)Z9")
+    assert e.value.status == _lib.CFD_EINVAL
+    assert "unknown" in str(e.value)
+
+
+def _blk(n=(16, 16, 16), ng=4, boundary=(0, 0, 0)):
+    return dict(n=n, ng=ng, h=(0.1, 0.1, 0.1), boundary=boundary)
+
+
+def test_plan_ghost_width_checked():
+    s = P.Scheme.named("(1)QP_O8[1]")      # needs 5 ghost layers
+    with pytest.raises(P.CfdError) as e:
+        P.Plan([_blk(ng=4)], 1, [(s, 0)])
+    assert e.value.status == _lib.CFD_EGHOST
+
+
+def test_plan_short_line_rejected():
+    s = P.Scheme.named("(1)QP_O8[1]")
+    with pytest.raises(P.CfdError) as e:
+        P.Plan([_blk(n=(4, 16, 16), ng=5)], 1, [(s, 0)])
+    assert e.value.status == _lib.CFD_ESHAPE
+
+
+def test_plan_bad_arguments():
+    s = P.Scheme.named("(1)Q1_3[1]")
+    with pytest.raises(P.CfdError) as e:
+        P.Plan([_blk()], 1, [(s, 3)])
+    assert e.value.status == _lib.CFD_EINVAL
+    with pytest.raises(P.CfdError) as e:
+        P.Plan([_blk()], 2, [(s, 0, 5)])
+    assert e.value.status == _lib.CFD_EINVAL
+    with pytest.raises(P.CfdError) as e:
+        P.Plan([dict(n=(16, 16, 16), ng=4, h=(0.0, 0.1, 0.1), boundary=(0, 0, 0))], 1, [(s, 0)])
+    assert e.value.status == _lib.CFD_EINVAL
+
+
+def test_valid_plan_needs_a_device_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    s = P.Scheme.named("(1)Q1_3[1]")
+    with pytest.raises(P.CfdError) as e:
+        P.Plan([_blk()], 1, [(s, 0)])
+    assert e.value.status == _lib.CFD_EDEVICE
+
+
+def test_stage_kernels_validate_arguments():
+    L = _lib.lib()
+    assert L.cfd_axpby(0, -1, 1.0, None, 1.0, None, None) == _lib.CFD_EINVAL
+    assert L.cfd_xpcy(7, 0, None, 1.0, None, None, None) == _lib.CFD_EINVAL
+    assert L.cfd_axpby(0, 0, 1.0, None, 1.0, None, None) == _lib.CFD_OK   # empty is a no-op
