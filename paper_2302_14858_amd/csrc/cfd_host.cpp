@@ -117,6 +117,7 @@ struct cfd_plan {
     size_t max_lds = 65536;
     // device state rebuilt by build()
     DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff, d_qoff, d_outoff, d_shapes;
+    DevBuf d_dense, d_dense_specs;        // dense mixed-precision tables
     std::vector<Group> groups;
     int64_t nitems = 0;
     hipStream_t cap_stream = nullptr;
@@ -140,6 +141,8 @@ struct cfd_plan {
         d_qoff.release();
         d_outoff.release();
         d_shapes.release();
+        d_dense.release();
+        d_dense_specs.release();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
     }
@@ -147,7 +150,7 @@ struct cfd_plan {
 
 namespace {
 
-size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }
+size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }   // F32 and MIXED_BF16 store FP32
 
 constexpr int kXCDq = 8;   // queues of the XCD-aware schedule (one per XCD)
 
@@ -204,9 +207,54 @@ std::vector<int> candidate_Ps(const PassHost &ps, bool f32, size_t max_lds) {
     return ok;
 }
 
+// Pass descriptors (strides, offsets, h^-d) of every pass; table indices from pass_tab.
+std::vector<PassDesc> pass_descs(const cfd_plan *p, const std::vector<std::array<int, 2>> &pass_tab) {
+    std::vector<PassDesc> pd(p->passes.size());
+    for (size_t i = 0; i < p->passes.size(); ++i) {
+        const PassHost &ps = p->passes[i];
+        const cfd_block &b = p->blocks[ps.block];
+        const int64_t ng = b.ng;
+        const int64_t PX = b.n[0] + 2 * ng, PY = b.n[1] + 2 * ng, PZ = b.n[2] + 2 * ng;
+        const int64_t s_in[3] = {1, PX, PX * PY};
+        const int64_t s_out[3] = {1, b.n[0], (int64_t)b.n[0] * b.n[1]};
+        const int d = ps.dir;
+        const int u = (d == 0) ? 1 : 0;
+        const int v = (d == 2) ? 1 : 2;
+        PassDesc &q = pd[i];
+        std::memset(&q, 0, sizeof q);
+        q.in_base = p->in_off[ps.block] + ng * (s_in[0] + s_in[1] + s_in[2]);
+        q.in_fstride = PX * PY * PZ;
+        const int64_t npts = (int64_t)b.n[0] * b.n[1] * b.n[2];
+        for (int o = 0; o < ps.nops; ++o) {
+            q.out_base[o] = p->out_off[ps.block] + p->op_slot[ps.op[o]] * npts;
+            q.tab[o] = pass_tab[i][o];
+            q.hinv[o] = 1.0 / std::pow(b.h[d], p->schemes[ps.sch[o]].d);
+        }
+        q.out_fstride = npts;
+        q.su = (int32_t)s_in[u];
+        q.sv = (int32_t)s_in[v];
+        q.sd = (int32_t)s_in[d];
+        q.osu = (int32_t)s_out[u];
+        q.osv = (int32_t)s_out[v];
+        q.osd = (int32_t)s_out[d];
+        q.nu = b.n[u];
+        q.nlines = b.n[u] * b.n[v];
+        q.N = ps.N;
+        q.ng = b.ng;
+        q.periodic = ps.periodic;
+        q.nfield_pass = ps.nfield;
+        q.field0 = ps.field0;
+    }
+
+    return pd;
+}
+
+cfd_status build_dense(cfd_plan *p);
+
 cfd_status build(cfd_plan *p) {
     HIPCHK(hipSetDevice(p->device));
     p->drop_graph();
+    if (p->dtype == CFD_MIXED_BF16) return build_dense(p);
     const bool f32 = p->dtype != CFD_F64;
     // 1. schedule and kernel class of every pass
     for (PassHost &ps : p->passes) {
@@ -311,43 +359,7 @@ cfd_status build(cfd_plan *p) {
     HIPCHK(hipMalloc(&p->d_taboff.p, std::max<size_t>(1, offs.size()) * sizeof(int64_t)));
     HIPCHK(hipMemcpy(p->d_taboff.p, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice));
 
-    // 3. pass descriptors
-    std::vector<PassDesc> pd(p->passes.size());
-    for (size_t i = 0; i < p->passes.size(); ++i) {
-        const PassHost &ps = p->passes[i];
-        const cfd_block &b = p->blocks[ps.block];
-        const int64_t ng = b.ng;
-        const int64_t PX = b.n[0] + 2 * ng, PY = b.n[1] + 2 * ng, PZ = b.n[2] + 2 * ng;
-        const int64_t s_in[3] = {1, PX, PX * PY};
-        const int64_t s_out[3] = {1, b.n[0], (int64_t)b.n[0] * b.n[1]};
-        const int d = ps.dir;
-        const int u = (d == 0) ? 1 : 0;
-        const int v = (d == 2) ? 1 : 2;
-        PassDesc &q = pd[i];
-        std::memset(&q, 0, sizeof q);
-        q.in_base = p->in_off[ps.block] + ng * (s_in[0] + s_in[1] + s_in[2]);
-        q.in_fstride = PX * PY * PZ;
-        const int64_t npts = (int64_t)b.n[0] * b.n[1] * b.n[2];
-        for (int o = 0; o < ps.nops; ++o) {
-            q.out_base[o] = p->out_off[ps.block] + p->op_slot[ps.op[o]] * npts;
-            q.tab[o] = pass_tab[i][o];
-            q.hinv[o] = 1.0 / std::pow(b.h[d], p->schemes[ps.sch[o]].d);
-        }
-        q.out_fstride = npts;
-        q.su = (int32_t)s_in[u];
-        q.sv = (int32_t)s_in[v];
-        q.sd = (int32_t)s_in[d];
-        q.osu = (int32_t)s_out[u];
-        q.osv = (int32_t)s_out[v];
-        q.osd = (int32_t)s_out[d];
-        q.nu = b.n[u];
-        q.nlines = b.n[u] * b.n[v];
-        q.N = ps.N;
-        q.ng = b.ng;
-        q.periodic = ps.periodic;
-        q.nfield_pass = ps.nfield;
-        q.field0 = ps.field0;
-    }
+    std::vector<PassDesc> pd = pass_descs(p, pass_tab);
     p->d_pass.release();
     HIPCHK(hipMalloc(&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
@@ -452,7 +464,121 @@ cfd_status build(cfd_plan *p) {
     return CFD_OK;
 }
 
+
+// Dense mixed-precision plans: periodic lines only, one operator per pass,
+// tables formed in FP64 on the GPU (A^-1 B and A^-1 by Gauss-Jordan).
+cfd_status build_dense(cfd_plan *p) {
+    std::map<std::pair<int, int>, int> tabidx;   // (scheme, N) -> table
+    std::vector<std::pair<int, int>> keys;
+    std::vector<int64_t> offs;
+    int64_t total = 0;
+    std::vector<std::array<int, 2>> pass_tab(p->passes.size());
+    for (size_t i = 0; i < p->passes.size(); ++i) {
+        const PassHost &ps = p->passes[i];
+        auto k = std::make_pair(ps.sch[0], ps.N);
+        auto it = tabidx.find(k);
+        int id;
+        if (it == tabidx.end()) {
+            id = (int)keys.size();
+            tabidx[k] = id;
+            keys.push_back(k);
+            offs.push_back(total);
+            total += (int64_t)((dense_tab_bytes(ps.N) + 255) & ~size_t(255));
+        } else {
+            id = it->second;
+        }
+        pass_tab[i] = {id, id};
+    }
+    const int ntab = (int)keys.size();
+    std::vector<unsigned char> specs(ntab * dense_tab_struct_size());
+    std::vector<double> coefs(ntab * 16, 0.0);
+    int64_t scratch_per = 0;
+    for (int t = 0; t < ntab; ++t) {
+        const Scheme &s = p->schemes[keys[t].first];
+        const int N = keys[t].second;
+        fill_dense_tab(specs.data() + t * dense_tab_struct_size(), N, s.nl, s.m, offs[t]);
+        for (int m = 0; m < 11; ++m) coefs[t * 16 + m] = s.rhs[m];
+        for (int j = 0; j < 5; ++j) coefs[t * 16 + 11 + j] = s.lhs[j];
+        scratch_per = std::max<int64_t>(scratch_per, (int64_t)N * 3 * N);
+    }
+    p->d_dense.release();
+    p->d_dense_specs.release();
+    HIPCHK(hipMalloc(&p->d_dense.p, std::max<int64_t>(total, 256)));
+    HIPCHK(hipMalloc(&p->d_dense_specs.p, specs.size()));
+    HIPCHK(hipMemcpy(p->d_dense_specs.p, specs.data(), specs.size(), hipMemcpyHostToDevice));
+    {
+        void *d_coefs = nullptr, *d_scratch = nullptr, *d_status = nullptr;
+        hipError_t e = hipMalloc(&d_coefs, coefs.size() * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&d_scratch, scratch_per * ntab * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&d_status, ntab * sizeof(int));
+        if (e == hipSuccess) e = hipMemcpy(d_coefs, coefs.data(), coefs.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_dense_form(ntab, p->d_dense_specs.p, (const double *)d_coefs, (unsigned char *)p->d_dense.p,
+                                  (double *)d_scratch, scratch_per, (int *)d_status, nullptr);
+        std::vector<int> status(ntab, 0);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemcpy(status.data(), d_status, ntab * sizeof(int), hipMemcpyDeviceToHost);
+        if (d_coefs) (void)hipFree(d_coefs);
+        if (d_scratch) (void)hipFree(d_scratch);
+        if (d_status) (void)hipFree(d_status);
+        if (e != hipSuccess) return hip_fail(e, "forming the dense periodic operator");
+        for (int t = 0; t < ntab; ++t)
+            if (status[t]) return fail(CFD_ESINGULAR, "periodic operator matrix is singular");
+    }
+    std::vector<PassDesc> pd = pass_descs(p, pass_tab);
+    p->d_pass.release();
+    HIPCHK(hipMalloc(&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
+    HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
+    // work items: 32 lines of one pass and field; one group (kernel) per (N, x or not)
+    std::map<std::pair<int, int>, std::vector<unsigned char>> by_class;
+    const size_t isz = dense_item_size();
+    for (size_t b = 0; b < p->blocks.size(); ++b)
+        for (int f = 0; f < p->nfields; ++f)
+            for (size_t i = 0; i < p->passes.size(); ++i) {
+                const PassHost &ps = p->passes[i];
+                if (ps.block != (int)b || f < ps.field0 || f >= ps.field0 + ps.nfield) continue;
+                const int xd = (pd[i].sd == 1 && pd[i].osd == 1) ? 1 : 0;
+                std::vector<unsigned char> &items = by_class[std::make_pair(ps.N, xd)];
+                for (int l0 = 0; l0 < pd[i].nlines; l0 += 32) {
+                    items.resize(items.size() + isz);
+                    fill_dense_item(items.data() + items.size() - isz, (int)i, f - ps.field0, l0, pass_tab[i][0]);
+                }
+            }
+    std::vector<unsigned char> items;
+    p->groups.clear();
+    for (auto &kv : by_class) {
+        Group g;
+        g.fn = dense_apply_fn(kv.first.first, kv.first.second != 0);
+        if (!g.fn) return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: unsupported line length");
+        g.lds = 0;
+        g.item0 = (int64_t)(items.size() / isz);
+        g.nitems = (int64_t)(kv.second.size() / isz);
+        int per_cu = 1;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, g.fn, 256, 0));
+        g.grid_persist = (int)std::min<int64_t>(g.nitems, (int64_t)p->cus * std::max(1, per_cu));
+        items.insert(items.end(), kv.second.begin(), kv.second.end());
+        p->groups.push_back(g);
+    }
+    p->nitems = (int64_t)(items.size() / isz);
+    p->d_items.release();
+    HIPCHK(hipMalloc(&p->d_items.p, std::max<size_t>(1, items.size())));
+    HIPCHK(hipMemcpy(p->d_items.p, items.data(), items.size(), hipMemcpyHostToDevice));
+    return CFD_OK;
+}
+
 cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
+    if (p->dtype == CFD_MIXED_BF16) {
+        const size_t isz = dense_item_size();
+        for (const Group &g : p->groups) {
+            if (g.nitems == 0) continue;
+            const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
+            hipError_t e = launch_dense_apply(g.fn, grid, st, (const unsigned char *)p->d_items.p + g.item0 * isz,
+                                              (int)g.nitems, (const PassDesc *)p->d_pass.p, p->d_dense_specs.p,
+                                              (const unsigned char *)p->d_dense.p, (const float *)in, (float *)out);
+            if (e != hipSuccess) return hip_fail(e, "launching dense apply");
+        }
+        return CFD_OK;
+    }
     const void *tabs = (p->dtype == CFD_F64) ? p->d_tab64.p : p->d_tab32.p;
     for (const Group &g : p->groups) {
         if (g.nitems == 0) continue;
@@ -563,9 +689,6 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
     if (desc->nops < 1 || !desc->ops) return fail(CFD_EINVAL, "cfd_plan_create: no operators");
     if (desc->dtype != CFD_F64 && desc->dtype != CFD_F32 && desc->dtype != CFD_MIXED_BF16)
         return fail(CFD_EINVAL, "cfd_plan_create: unknown dtype");
-    if (desc->dtype == CFD_MIXED_BF16)
-        return fail(CFD_EUNSUPPORTED, "cfd_plan_create: the dense mixed-precision path is created with "
-                                      "cfd_dense_plan_create");
     std::unique_ptr<cfd_plan> p(new cfd_plan);
     p->device = desc->device;
     p->dtype = desc->dtype;
@@ -630,6 +753,13 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
             if (per && N < std::max(2 * s.nl + 1, std::max(s.m, s.mc))) {
                 return fail(CFD_ESHAPE, "periodic line shorter than the stencil");
             }
+            if (desc->dtype == CFD_MIXED_BF16) {
+                if (!per)
+                    return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: periodic lines only");
+                if (N % 32 || N < 32 || N > 256)
+                    return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: line length must be 32..256, "
+                                                  "a multiple of 32");
+            }
         }
     }
     p->in_elems = in_cur;
@@ -663,6 +793,7 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
                 ps.sch[0] = o;
                 int partner = -1;
                 for (int o2 : ops_d) {
+                    if (desc->dtype == CFD_MIXED_BF16) break;   // the dense path runs one operator per pass
                     if (used[o2] || p->ops[o2].field != p->ops[o].field) continue;
                     const Scheme &s1 = p->schemes[o2];
                     if (s1.nl != s0.nl || s0.nl == 0 || (s0.d % 2) == (s1.d % 2)) continue;
@@ -785,6 +916,8 @@ cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions,
     if (!p) return fail(CFD_EINVAL, "cfd_plan_set_schedule: null plan");
     if (flags & ~(CFD_SCHED_PERSISTENT | CFD_SCHED_SPLIT_X | CFD_SCHED_XCD))
         return fail(CFD_EINVAL, "cfd_plan_set_schedule: unknown flag");
+    if (p->dtype == CFD_MIXED_BF16 && N > 0)
+        return fail(CFD_EINVAL, "cfd_plan_set_schedule: the dense path has no partition schedule");
     if (N > 0) {
         const auto key = std::make_pair(N, xlines ? 1 : 0);
         if (partitions > 0) {
@@ -820,6 +953,31 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     }
     const bool f32 = p->dtype != CFD_F64;
     const char *dt = f32 ? "f32" : "f64";
+    if (p->dtype == CFD_MIXED_BF16) {
+        // only the grid kind: persistent or one workgroup per item
+        hipEvent_t a0, a1;
+        HIPCHK(hipEventCreate(&a0));
+        HIPCHK(hipEventCreate(&a1));
+        float best = 1e30f;
+        bool bp = true;
+        cfd_status r = CFD_OK;
+        for (int pers = 1; pers >= 0 && r == CFD_OK; --pers) {
+            p->persistent = pers;
+            for (int w = 0; w < 2 && r == CFD_OK; ++w) r = enqueue(p, in_dev, out_dev, st);
+            if (r != CFD_OK) break;
+            (void)hipEventRecord(a0, st);
+            for (int w = 0; w < 5 && r == CFD_OK; ++w) r = enqueue(p, in_dev, out_dev, st);
+            (void)hipEventRecord(a1, st);
+            (void)hipEventSynchronize(a1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, a0, a1);
+            if (ms < best) { best = ms; bp = pers; }
+        }
+        (void)hipEventDestroy(a0);
+        (void)hipEventDestroy(a1);
+        p->persistent = bp;
+        return r;
+    }
     // one class per (line length, x or y/z, band, fused operators)
     std::map<std::tuple<int, int, int, int>, std::vector<int>> classes;
     for (const PassHost &ps : p->passes)

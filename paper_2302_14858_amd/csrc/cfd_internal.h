@@ -126,3 +126,17 @@ hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *sta
                              const int64_t *in_off, const int64_t *out_off, const int *shapes, int nblocks,
                              int64_t total, double a, double b, hipStream_t st);
 }  // namespace cfd
+
+namespace cfd {
+hipError_t launch_dense_form(int ntab, const void *tabs, const double *coefs, unsigned char *out, double *scratch,
+                             int64_t scratch_per, int *status, hipStream_t st);
+const void *dense_apply_fn(int N, bool xdir);   // nullptr: unsupported line length
+hipError_t launch_dense_apply(const void *fn, int grid, hipStream_t st, const void *items, int nitems,
+                              const PassDesc *passes, const void *tabs, const unsigned char *tabdata, const float *in,
+                              float *out);
+size_t dense_tab_bytes(int N);
+size_t dense_tab_struct_size();
+size_t dense_item_size();
+void fill_dense_tab(void *dst, int N, int nl, int m, int64_t off);
+void fill_dense_item(void *dst, int pass, int field, int line0, int tab);
+}  // namespace cfd

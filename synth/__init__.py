@@ -14,6 +14,7 @@ small-amplitude noise; uneven mesh blocks with ghost layers, Sec. 2.4):
 * ``batch64``     : 64 blocks with extents drawn from {16,24,32,48}^3, h = 1/64,
                     origins uniform in [0,1)^3, 22 fields of 8 modes, k in [1,6]^3.
 * ``periodic256`` : periodic 256^3, h = 2 pi/256, 8 fields of 32 modes, k in [1,120]^3.
+* ``periodic_box``: small anisotropic periodic boxes (ragged line counts) for edge cases.
 * ``wave192``     : periodic 192^3 plane wave k = (3,5,7) for the first-order wave
                     system (phi, Pi, psi_x, psi_y, psi_z), as one periodic block
                     or as a 4x4x4 lattice of 48^3 blocks.
@@ -179,6 +180,18 @@ def periodic256(seed: int = 4, n: int = 256, nfields: int = 8, nmodes: int = 32,
     modes = [_random_modes(rng, nmodes, 1, kmax, 1.0) for _ in range(nfields)]
     data, offs = _fill([blk], nfields, lambda b, f, x, y, z: eval_modes(modes[f], x, y, z))
     return Workload("periodic256", [blk], nfields, data, offs, [[m] for m in modes])
+
+
+def periodic_box(seed: int = 6, n=(64, 5, 7), nfields: int = 2, nmodes: int = 16, kmax: int = 20) -> Workload:
+    """Anisotropic periodic box [0, 2 pi)^3 with n[d] nodes along axis d (no ghosts)."""
+    rng = np.random.default_rng(seed)
+    h = tuple(2 * np.pi / v for v in n)
+    blk = Block(tuple(int(v) for v in n), 0, h, (PERIODIC,) * 3, (0.0, 0.0, 0.0))
+    modes = [_random_modes(rng, nmodes, 0, kmax, 1.0, exclude_zero=True) for _ in range(nfields)]
+    for m in modes:      # keep every mode resolved on the coarsest axis
+        m.k = np.minimum(m.k, np.array([max(0, v // 2 - 1) for v in n]))
+    data, offs = _fill([blk], nfields, lambda b, f, x, y, z: eval_modes(modes[f], x, y, z))
+    return Workload("periodic_box", [blk], nfields, data, offs, [[m] for m in modes])
 
 
 WAVE_K = (3, 5, 7)

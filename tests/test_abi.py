@@ -136,3 +136,12 @@ def test_stage_kernels_validate_arguments():
     assert L.cfd_axpby(0, -1, 1.0, None, 1.0, None, None) == _lib.CFD_EINVAL
     assert L.cfd_xpcy(7, 0, None, 1.0, None, None, None) == _lib.CFD_EINVAL
     assert L.cfd_axpby(0, 0, 1.0, None, 1.0, None, None) == _lib.CFD_OK   # empty is a no-op
+
+
+def test_mixed_dense_plan_limits():
+    """The dense mixed-precision path takes periodic lines of 32..256 nodes, multiples of 32."""
+    s = P.Scheme.named("(1)Q1_3[1]")
+    for n, bnd in [((64, 64, 64), (0, 0, 0)), ((40, 64, 64), (1, 1, 1)), ((288, 32, 32), (1, 1, 1))]:
+        with pytest.raises(P.CfdError) as e:
+            P.Plan([dict(n=n, ng=4, h=(0.1, 0.1, 0.1), boundary=bnd)], 1, [(s, 0)], dtype=P.CFD_MIXED_BF16)
+        assert e.value.status == _lib.CFD_EUNSUPPORTED

@@ -1,0 +1,81 @@
+"""GPU parity of the dense mixed-precision periodic path (BF16 MFMA products,
+FP32 accumulation, one FP64-residual refinement) against the FP64 oracle.
+
+Bar: relative max-norm error <= 1e-5 per (block, operator, field).
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+MIXED = 2
+
+
+@pytest.mark.parametrize("n,scheme", [(64, "(1)Q1_3[1]"), (96, "(2)Q1_3[1]"), (32, "(1)QP_O8[1]"),
+                                      (128, "(1)P1_2")])
+def test_dense_periodic_dxyz(cuda, n, scheme):
+    wl = synth.periodic256(n=n, nfields=2, nmodes=16, kmax=n // 3)
+    ops = [(scheme, 0), (scheme, 1), (scheme, 2)]
+    plan = H.make_plan(wl, ops, dtype=MIXED)
+    g = H.gpu_run(plan, wl, ops, dtype=MIXED)
+    o = H.oracle_run(wl, ops)
+    assert H.max_rel_err(g, o) <= H.ERR_F32
+
+
+def test_dense_longest_line_penta_d2(cuda):
+    wl = synth.periodic_box(n=(256, 3, 2), nfields=1, kmax=60)
+    ops = [("(2)QP_O8[1]", 0)]
+    plan = H.make_plan(wl, ops, dtype=MIXED)
+    g = H.gpu_run(plan, wl, ops, dtype=MIXED)
+    o = H.oracle_run(wl, ops)
+    assert H.max_rel_err(g, o) <= H.ERR_F32
+
+
+@pytest.mark.parametrize("n", [(64, 5, 7), (32, 1, 1), (5, 96, 3), (3, 2, 160)])
+def test_dense_ragged_line_counts(cuda, n):
+    """Line counts that leave a partial 32-line tile; one periodic direction each."""
+    d = int(np.argmax(n))
+    wl = synth.periodic_box(n=n, nfields=3, kmax=10)
+    ops = [("(1)Q1_3[1]", d)]
+    plan = H.make_plan(wl, ops, dtype=MIXED)
+    g = H.gpu_run(plan, wl, ops, dtype=MIXED)
+    o = H.oracle_run(wl, ops)
+    assert H.max_rel_err(g, o) <= H.ERR_F32
+
+
+def test_dense_graph_replay_and_grids(cuda):
+    import torch
+    wl = synth.periodic256(n=64, nfields=2, nmodes=16, kmax=20)
+    ops = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2)]
+    plan = H.make_plan(wl, ops, dtype=MIXED)
+    o = H.oracle_run(wl, ops)
+    for pers in (True, False):
+        plan.set_schedule(persistent=pers)
+        assert H.max_rel_err(H.gpu_run(plan, wl, ops, dtype=MIXED), o) <= H.ERR_F32
+    nin, nout = plan.sizes()
+    x = torch.from_numpy(wl.data).to(device="cuda", dtype=torch.float32)
+    y = torch.full((nout,), float("nan"), dtype=torch.float32, device="cuda")
+    plan.capture_graph(x, y)
+    ref = None
+    for rep in range(3):
+        y.fill_(float("nan"))
+        plan.launch_graph()
+        torch.cuda.synchronize()
+        got = y.cpu().numpy()
+        if ref is None:
+            ref = got
+            assert H.max_rel_err(H.unpack(wl, ops, got.astype(np.float64), plan.offsets()[1]), o) <= H.ERR_F32
+        else:
+            assert np.array_equal(got, ref)
+
+
+def test_dense_agrees_with_fp32_banded(cuda):
+    """Mixed and FP32 banded results agree with each other to the FP32 bar."""
+    wl = synth.periodic256(n=64, nfields=1, nmodes=16, kmax=20)
+    ops = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2)]
+    gm = H.gpu_run(H.make_plan(wl, ops, dtype=MIXED), wl, ops, dtype=MIXED)
+    gf = H.gpu_run(H.make_plan(wl, ops, dtype=1), wl, ops, dtype=1)
+    for o in range(3):
+        assert H.rel_err(gm[0][o][0], gf[0][o][0]) <= 2 * H.ERR_F32
