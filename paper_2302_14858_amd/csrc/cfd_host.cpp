@@ -156,7 +156,7 @@ constexpr int kXCDq = 8;   // queues of the XCD-aware schedule (one per XCD)
 
 // Tile bytes an x item with P partitions of L rows needs in LDS.
 size_t x_tile_bytes(int P, int L, int hw, size_t es) {
-    return 256 * sizeof(int) + (size_t)(kWave * 4 / P) * (size_t)((P * L + 2 * hw) | 1) * es;
+    return (size_t)(kWave * 4 / P) * (size_t)((P * L + 2 * hw) | 1) * es;
 }
 
 // Partition length for P partitions of an N-node line: the smallest compiled

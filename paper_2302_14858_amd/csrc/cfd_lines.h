@@ -253,74 +253,85 @@ __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS
 
 // Stage the x-lines of this item in LDS: row r holds nodes -HW .. Npad+HW-1
 // of line line0 + r (zero outside the ghosts, wrapped for periodic lines,
-// whose Npad equals N).  The per-row source offsets are computed once
-// (rowoff, in LDS); the copy is flat over rows x columns with the column and
-// row advanced incrementally, 8 loads in flight per thread before their LDS
-// writes.
+// whose Npad equals N; rows past the last line read as zero).  Thread tid owns
+// the node pair tid % CW (CW = W / 2 pairs per row) of the rows
+// tid / CW + k * RPP, RPP = 256 / CW rows per pass: its line advances by RPP
+// per pass without a division, and the loads of BATCH passes are in flight
+// together before their LDS writes.  W is even (Npad and 2 HW are).
 template <typename T, int HW>
 __device__ __forceinline__ void stage_x(const PassDesc &pd, const T *base, int line0, int nrows, int Npad, T *tile,
-                                        int tpitch, int *rowoff, bool periodic) {
-    const int N = pd.N, ng = pd.ng;
-    const int W = Npad + 2 * HW;
-    const int tid = threadIdx.x;
+                                        int tpitch, bool periodic) {
     constexpr int NT = 64 * kWGW;
-    for (int r = tid; r < nrows; r += NT) {
-        int line = line0 + r;
-        if (line >= pd.nlines) line = pd.nlines - 1;
-        const int lu = line % pd.nu, lv = line / pd.nu;
-        rowoff[r] = lv * pd.sv + lu * pd.su;
-    }
-    __syncthreads();
-    const int total = nrows * W;
-    const int dr = NT / W, dc = NT - dr * W;
-    int r = tid / W, col = tid - (tid / W) * W;
     constexpr int BATCH = 8;
-    for (int e0 = 0; e0 < total; e0 += NT * BATCH) {
-        T v[BATCH];
+    const int N = pd.N, ng = pd.ng;
+    const int CW = (Npad + 2 * HW) >> 1;
+    const int RPP = NT / CW;
+    const int tid = threadIdx.x;
+    const int r0 = tid / CW;
+    const int c2 = tid - r0 * CW;
+    if (r0 >= RPP) return;   // no barrier inside: idle threads may leave early
+    // source offsets of the pair's two nodes within a line (-1: outside, reads 0)
+    int j[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        int jj = 2 * c2 + h - HW;
+        if (periodic) {
+            if (jj < 0) jj += N;
+            if (jj >= N) jj -= N;
+        } else if (jj < -ng || jj >= N + ng) {
+            jj = INT32_MIN;
+        }
+        j[h] = jj;
+    }
+    const int nr = min(nrows, pd.nlines - line0);   // rows that are real lines
+    int line = line0 + r0;
+    int lu = line % pd.nu, lv = line / pd.nu;
+    for (int rb = r0; rb < nrows; rb += BATCH * RPP) {
+        T v[BATCH][2];
         int dst[BATCH];
 #pragma unroll
         for (int b = 0; b < BATCH; ++b) {
-            const int e = e0 + b * NT + tid;
-            dst[b] = -1;
-            v[b] = T(0);
-            if (e < total) {
-                int j = col - HW;
-                bool ok = true;
-                if (periodic) {
-                    if (j < 0) j += N;
-                    if (j >= N) j -= N;
-                } else {
-                    ok = (j >= -ng && j < N + ng);
-                }
-                if (ok) v[b] = base[rowoff[r] + j];
-                dst[b] = r * tpitch + col;
+            const int r = rb + b * RPP;
+            dst[b] = r < nrows ? r * tpitch + 2 * c2 : -1;
+            const T *row = base + (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) v[b][h] = (r < nr && j[h] != INT32_MIN) ? row[j[h]] : T(0);
+            lu += RPP;
+            while (lu >= pd.nu) {
+                lu -= pd.nu;
+                ++lv;
             }
-            col += dc;
-            r += dr;
-            if (col >= W) { col -= W; ++r; }
         }
 #pragma unroll
         for (int b = 0; b < BATCH; ++b)
-            if (dst[b] >= 0) tile[dst[b]] = v[b];
+            if (dst[b] >= 0) {
+                tile[dst[b]] = v[b][0];
+                tile[dst[b] + 1] = v[b][1];
+            }
     }
 }
 
 // Write the x results staged in the tile (row r = line line0 + r, pitch
 // opitch) to the interior output: consecutive x-lines of one field are
 // consecutive rows of the output, so the item's results are one contiguous
-// run of nrows * N elements.
+// run of nrows * N elements.  Thread tid owns node pair tid % CO of rows
+// tid / CO + k * RPP.
 template <typename T>
 __device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N, int opitch) {
     constexpr int NT = 64 * kWGW;
+    const int CO = (N + 1) >> 1;
+    const int RPP = NT / CO;
     const int tid = threadIdx.x;
-    const int total = nrows * N;
-    const int dr = NT / N, dc = NT - dr * N;
-    int r = tid / N, col = tid - (tid / N) * N;
-    for (int e = tid; e < total; e += NT) {
-        store_out(dst + e, tile[r * opitch + col]);
-        col += dc;
-        r += dr;
-        if (col >= N) { col -= N; ++r; }
+    const int r0 = tid / CO;
+    const int c = 2 * (tid - r0 * CO);
+    if (r0 >= RPP) return;
+    const bool second = c + 1 < N;
+#pragma unroll 4
+    for (int r = r0; r < nrows; r += RPP) {
+        const T a = tile[r * opitch + c];
+        const T b = tile[r * opitch + c + 1];
+        store_out(dst + (int64_t)r * N + c, a);
+        if (second) store_out(dst + (int64_t)r * N + c + 1, b);
     }
 }
 
@@ -399,8 +410,7 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
         const T *__restrict__ in, T *__restrict__ out) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *exch = reinterpret_cast<T *>(smem_raw);
-    int *rowoff = reinterpret_cast<int *>(exch + exch_elems<NL, NOPS>());   // 256 row offsets
-    T *tile = exch + exch_elems<NL, NOPS>() + 256 * sizeof(int) / sizeof(T);
+    T *tile = exch + exch_elems<NL, NOPS>();
     constexpr int kLs[] = {Ls...};
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = threadIdx.x & 63;
@@ -444,7 +454,7 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
             const int Npad = c.P * kLs[lcode];
             c.tpitch = (Npad + 2 * HW) | 1;
             c.trow = c.sub * 64 + g;
-            stage_x<T, HW>(pd, fbase, wi.line0, nsub * 64, Npad, tile, c.tpitch, rowoff, c.periodic);
+            stage_x<T, HW>(pd, fbase, wi.line0, nsub * 64, Npad, tile, c.tpitch, c.periodic);
             __syncthreads();
         } else {
             c.src = fbase + (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
