@@ -209,11 +209,14 @@ cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream);
 #define CFD_SCHED_SPLIT_X    2   /* lines along x in a launch of their own */
 #define CFD_SCHED_XCD        4   /* persistent grid with one work queue per XCD: the
                                     x/y/z passes of a block-field stay on one L2 */
+#define CFD_SCHED_CONCURRENT 8   /* the plan's launches (e.g. the x launch and the y/z
+                                    launch) run on forked streams at the same time,
+                                    joined on the caller's stream before later work */
 
 /* Time the candidate schedules on the given buffers and keep the fastest:
  * the number of partitions per line for every (line length, x or y/z) class,
  * then the launch shape (persistent grid or one workgroup per item; x lines
- * fused with y/z or split).  If cache_path is non-NULL the per-class choices
+ * fused with y/z or split; launches one after another or concurrent).  If cache_path is non-NULL the per-class choices
  * are read from / appended to that text file, keyed by device arch, dtype,
  * line length, direction class, band and fused operators.  Synchronises the
  * stream.  Invalidates a captured graph. */
@@ -232,6 +235,9 @@ cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions,
  * receives the number of classes. */
 cfd_status cfd_plan_get_schedule(const cfd_plan *p, int *persistent, int *split_x, int *n_classes, int *N,
                                  int *xlines, int *partitions, int cap);
+
+/* The plan's current schedule flags (a set of CFD_SCHED_*) into *flags. */
+cfd_status cfd_plan_get_flags(const cfd_plan *p, int *flags);
 
 void cfd_plan_destroy(cfd_plan *p);
 

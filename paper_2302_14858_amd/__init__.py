@@ -182,9 +182,10 @@ class Plan:
     autotune = cfd_plan_autotune
 
     def cfd_plan_set_schedule(self, N: int = 0, xlines: bool = False, partitions: int = 0,
-                              persistent: bool = True, split_x: bool = False, xcd: bool = False) -> None:
+                              persistent: bool = True, split_x: bool = False, xcd: bool = False,
+                              concurrent: bool = False) -> None:
         flags = ((_lib.CFD_SCHED_PERSISTENT if persistent else 0) | (_lib.CFD_SCHED_SPLIT_X if split_x else 0) |
-                 (_lib.CFD_SCHED_XCD if xcd else 0))
+                 (_lib.CFD_SCHED_XCD if xcd else 0) | (_lib.CFD_SCHED_CONCURRENT if concurrent else 0))
         check(lib().cfd_plan_set_schedule(self._h, N, int(bool(xlines)), partitions, flags))
 
     set_schedule = cfd_plan_set_schedule
@@ -195,7 +196,10 @@ class Plan:
         Ns, xs, Ps = (ctypes.c_int * cap)(), (ctypes.c_int * cap)(), (ctypes.c_int * cap)()
         check(lib().cfd_plan_get_schedule(self._h, ctypes.byref(pers), ctypes.byref(split), ctypes.byref(n),
                                           Ns, xs, Ps, cap))
+        flags = ctypes.c_int()
+        check(lib().cfd_plan_get_flags(self._h, ctypes.byref(flags)))
         return {"persistent": pers.value, "split_x": bool(split.value),
+                "concurrent": bool(flags.value & _lib.CFD_SCHED_CONCURRENT), "flags": flags.value,
                 "classes": [(Ns[i], xs[i], Ps[i]) for i in range(min(n.value, cap))]}
 
     get_schedule = cfd_plan_get_schedule

@@ -12,7 +12,7 @@ STATUS_NAMES = ["CFD_OK", "CFD_EINVAL", "CFD_EGHOST", "CFD_ESHAPE", "CFD_ESINGUL
                 "CFD_EUNSUPPORTED"]
 CFD_F64, CFD_F32, CFD_MIXED_BF16 = 0, 1, 2
 CFD_BOUNDARY_CLOSURE, CFD_BOUNDARY_PERIODIC = 0, 1
-CFD_SCHED_PERSISTENT, CFD_SCHED_SPLIT_X, CFD_SCHED_XCD = 1, 2, 4
+CFD_SCHED_PERSISTENT, CFD_SCHED_SPLIT_X, CFD_SCHED_XCD, CFD_SCHED_CONCURRENT = 1, 2, 4, 8
 
 
 class cfd_block(ctypes.Structure):
@@ -56,6 +56,7 @@ SIGNATURES = {
     "cfd_plan_autotune": (_i, [_vp, _vp, _vp, _vp, _s]),
     "cfd_plan_set_schedule": (_i, [_vp, _i, _i, _i, _i]),
     "cfd_plan_get_schedule": (_i, [_vp, _ip, _ip, _ip, _ip, _ip, _ip, _i]),
+    "cfd_plan_get_flags": (_i, [_vp, _ip]),
     "cfd_plan_destroy": (None, [_vp]),
     "cfd_halo_exchange": (_i, [_vp, _vp, _i, _i, _i, _vp]),
     "cfd_axpby": (_i, [_i, _ll, _d, _vp, _d, _vp, _vp]),

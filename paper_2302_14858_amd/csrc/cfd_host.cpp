@@ -113,6 +113,7 @@ struct cfd_plan {
     bool persistent = true;
     bool split_x = false;                 // x-lines in a launch of their own
     bool xcd = false;                     // XCD-aware queues (persistent grid only)
+    bool concurrent = false;              // kernel groups on forked streams, joined at the end
     int cus = 256;
     size_t max_lds = 65536;
     // device state rebuilt by build()
@@ -121,6 +122,8 @@ struct cfd_plan {
     std::vector<Group> groups;
     int64_t nitems = 0;
     hipStream_t cap_stream = nullptr;
+    std::vector<hipStream_t> aux;         // one per group beyond the first (concurrent mode)
+    std::vector<hipEvent_t> ev;           // fork event, then one join event per aux stream
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
 
@@ -145,6 +148,10 @@ struct cfd_plan {
         d_dense_specs.release();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
+        for (hipStream_t a : aux) (void)hipStreamDestroy(a);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        aux.clear();
+        ev.clear();
     }
 };
 
@@ -251,7 +258,7 @@ std::vector<PassDesc> pass_descs(const cfd_plan *p, const std::vector<std::array
 
 cfd_status build_dense(cfd_plan *p);
 
-cfd_status build(cfd_plan *p) {
+cfd_status build_groups(cfd_plan *p) {
     HIPCHK(hipSetDevice(p->device));
     p->drop_graph();
     if (p->dtype == CFD_MIXED_BF16) return build_dense(p);
@@ -566,28 +573,68 @@ cfd_status build_dense(cfd_plan *p) {
     return CFD_OK;
 }
 
-cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
+cfd_status launch_group(cfd_plan *p, const Group &g, const void *in, void *out, hipStream_t st) {
+    const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
+    hipError_t e;
     if (p->dtype == CFD_MIXED_BF16) {
-        const size_t isz = dense_item_size();
-        for (const Group &g : p->groups) {
-            if (g.nitems == 0) continue;
-            const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
-            hipError_t e = launch_dense_apply(g.fn, grid, st, (const unsigned char *)p->d_items.p + g.item0 * isz,
-                                              (int)g.nitems, (const PassDesc *)p->d_pass.p, p->d_dense_specs.p,
-                                              (const unsigned char *)p->d_dense.p, (const float *)in, (float *)out);
-            if (e != hipSuccess) return hip_fail(e, "launching dense apply");
+        e = launch_dense_apply(g.fn, grid, st, (const unsigned char *)p->d_items.p + g.item0 * dense_item_size(),
+                               (int)g.nitems, (const PassDesc *)p->d_pass.p, p->d_dense_specs.p,
+                               (const unsigned char *)p->d_dense.p, (const float *)in, (float *)out);
+    } else {
+        const void *tabs = (p->dtype == CFD_F64) ? p->d_tab64.p : p->d_tab32.p;
+        const int *qoff = (g.qoff_index >= 0) ? (const int *)p->d_qoff.p + g.qoff_index : nullptr;
+        e = launch_lines(g.fn, grid, g.lds, st, (const WorkItem *)p->d_items.p + g.item0, (int)g.nitems, qoff,
+                         (const PassDesc *)p->d_pass.p, tabs, (const int64_t *)p->d_taboff.p, in, out);
+    }
+    if (e != hipSuccess) return hip_fail(e, "launching a kernel group");
+    return CFD_OK;
+}
+
+// Streams and events of the concurrent mode, made outside any capture.
+cfd_status ensure_aux(cfd_plan *p) {
+    const size_t need = p->groups.size() > 1 ? p->groups.size() - 1 : 0;
+    while (p->aux.size() < need) {
+        hipStream_t s;
+        HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        p->aux.push_back(s);
+    }
+    while (p->ev.size() < need + 1) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        p->ev.push_back(e);
+    }
+    return CFD_OK;
+}
+
+// Device tables, work lists and launch groups for the current schedule.
+cfd_status build(cfd_plan *p) {
+    cfd_status r = build_groups(p);
+    if (r == CFD_OK) r = ensure_aux(p);
+    return r;
+}
+
+cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
+    std::vector<const Group *> act;
+    for (const Group &g : p->groups)
+        if (g.nitems > 0) act.push_back(&g);
+    if (p->concurrent && act.size() > 1 && p->aux.size() + 1 >= act.size() && p->ev.size() >= act.size()) {
+        // fork: every group after the first on its own stream, all ordered after
+        // the caller's earlier work; join: the caller's stream waits for all
+        HIPCHK(hipEventRecord(p->ev[0], st));
+        for (size_t i = 1; i < act.size(); ++i) {
+            HIPCHK(hipStreamWaitEvent(p->aux[i - 1], p->ev[0], 0));
+            cfd_status r = launch_group(p, *act[i], in, out, p->aux[i - 1]);
+            if (r != CFD_OK) return r;
+            HIPCHK(hipEventRecord(p->ev[i], p->aux[i - 1]));
         }
+        cfd_status r = launch_group(p, *act[0], in, out, st);
+        if (r != CFD_OK) return r;
+        for (size_t i = 1; i < act.size(); ++i) HIPCHK(hipStreamWaitEvent(st, p->ev[i], 0));
         return CFD_OK;
     }
-    const void *tabs = (p->dtype == CFD_F64) ? p->d_tab64.p : p->d_tab32.p;
-    for (const Group &g : p->groups) {
-        if (g.nitems == 0) continue;
-        const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
-        const int *qoff = (g.qoff_index >= 0) ? (const int *)p->d_qoff.p + g.qoff_index : nullptr;
-        hipError_t e = launch_lines(g.fn, grid, g.lds, st, (const WorkItem *)p->d_items.p + g.item0,
-                                    (int)g.nitems, qoff, (const PassDesc *)p->d_pass.p, tabs,
-                                    (const int64_t *)p->d_taboff.p, in, out);
-        if (e != hipSuccess) return hip_fail(e, "launching line kernel");
+    for (const Group *g : act) {
+        cfd_status r = launch_group(p, *g, in, out, st);
+        if (r != CFD_OK) return r;
     }
     return CFD_OK;
 }
@@ -914,7 +961,7 @@ cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream) {
 
 cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions, int flags) {
     if (!p) return fail(CFD_EINVAL, "cfd_plan_set_schedule: null plan");
-    if (flags & ~(CFD_SCHED_PERSISTENT | CFD_SCHED_SPLIT_X | CFD_SCHED_XCD))
+    if (flags & ~(CFD_SCHED_PERSISTENT | CFD_SCHED_SPLIT_X | CFD_SCHED_XCD | CFD_SCHED_CONCURRENT))
         return fail(CFD_EINVAL, "cfd_plan_set_schedule: unknown flag");
     if (p->dtype == CFD_MIXED_BF16 && N > 0)
         return fail(CFD_EINVAL, "cfd_plan_set_schedule: the dense path has no partition schedule");
@@ -938,6 +985,7 @@ cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions,
     p->persistent = (flags & CFD_SCHED_PERSISTENT) != 0;
     p->split_x = (flags & CFD_SCHED_SPLIT_X) != 0;
     p->xcd = (flags & CFD_SCHED_XCD) != 0;
+    p->concurrent = (flags & CFD_SCHED_CONCURRENT) != 0;
     return build(p);
 }
 
@@ -1046,20 +1094,24 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         // workgroup per item; x lines fused with y/z or split
         float best = 1e30f;
         int bmode = 1;
-        bool bs = false;
+        bool bs = false, bc = false;
         for (int mode = 0; mode < 3 && result == CFD_OK; ++mode)
-            for (int split = 0; split <= 1 && result == CFD_OK; ++split) {
-                p->persistent = mode != 0;
-                p->xcd = mode == 2;
-                p->split_x = split;
-                result = build(p);
-                float ms = 0;
-                if (result == CFD_OK) result = time_apply(ms);
-                if (result == CFD_OK && ms < best) { best = ms; bmode = mode; bs = split; }
-            }
+            for (int split = 0; split <= 1 && result == CFD_OK; ++split)
+                for (int conc = 0; conc <= 1 && result == CFD_OK; ++conc) {
+                    p->persistent = mode != 0;
+                    p->xcd = mode == 2;
+                    p->split_x = split;
+                    p->concurrent = conc;
+                    result = build(p);
+                    if (result == CFD_OK && conc && p->groups.size() < 2) continue;   // same as sequential
+                    float ms = 0;
+                    if (result == CFD_OK) result = time_apply(ms);
+                    if (result == CFD_OK && ms < best) { best = ms; bmode = mode; bs = split; bc = conc; }
+                }
         p->persistent = bmode != 0;
         p->xcd = bmode == 2;
         p->split_x = bs;
+        p->concurrent = bc;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1087,6 +1139,13 @@ cfd_status cfd_plan_get_schedule(const cfd_plan *p, int *persistent, int *split_
         if (partitions) partitions[i] = kv.second;
         ++i;
     }
+    return CFD_OK;
+}
+
+cfd_status cfd_plan_get_flags(const cfd_plan *p, int *flags) {
+    if (!p || !flags) return fail(CFD_EINVAL, "cfd_plan_get_flags: null argument");
+    *flags = (p->persistent ? CFD_SCHED_PERSISTENT : 0) | (p->split_x ? CFD_SCHED_SPLIT_X : 0) |
+             (p->xcd ? CFD_SCHED_XCD : 0) | (p->concurrent ? CFD_SCHED_CONCURRENT : 0);
     return CFD_OK;
 }
 

@@ -89,7 +89,8 @@ def test_every_schedule_same_result(cuda):
                 tried += 1
     assert tried >= 8
     for mode in ({"persistent": True, "xcd": True}, {"persistent": True, "xcd": True, "split_x": True},
-                 {"persistent": False}):
+                 {"persistent": False}, {"persistent": False, "split_x": True, "concurrent": True},
+                 {"persistent": True, "split_x": True, "concurrent": True}):
         plan.set_schedule(0, **mode)
         g = H.gpu_run(plan, wl, D12_PENTA)
         assert H.max_rel_err(g, o) <= H.ERR_F64, mode
@@ -125,3 +126,29 @@ def test_graph_replay_matches_eager(cuda):
         torch.cuda.synchronize()
         assert torch.equal(y_graph, y_eager), rep
         x.mul_(1.0)   # unrelated eager work between replays
+
+
+def test_concurrent_graph_replay(cuda):
+    """x and y/z launches on forked streams inside the captured graph: every replay equals the eager result."""
+    import torch
+    wl = synth.batch64(nblocks=4, nfields=2, seed=7)
+    plan = H.make_plan(wl, D12_PENTA)
+    plan.set_schedule(0, persistent=True, split_x=True, concurrent=True)
+    assert plan.get_schedule()["concurrent"]
+    nin, nout = plan.sizes()
+    x = torch.from_numpy(wl.data).cuda()
+    y_eager = torch.empty(nout, dtype=torch.float64, device="cuda")
+    y_graph = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.apply(x, y_eager)
+    torch.cuda.synchronize()
+    o = H.oracle_run(wl, D12_PENTA, blocks=[0, 1])
+    g = H.unpack(wl, D12_PENTA, y_eager.cpu().numpy(), plan.offsets()[1])
+    assert H.max_rel_err({b: g[b] for b in (0, 1)}, o) <= H.ERR_F64
+    plan.capture_graph(x, y_graph)
+    for rep in range(4):
+        y_graph.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.launch_graph()
+        torch.cuda.synchronize()
+        assert torch.equal(y_graph, y_eager), rep
+        x.mul_(1.0)
