@@ -8,7 +8,11 @@ graph launch.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line: derivative evaluations per second (interior points x
 fields x (direction, order) pairs), the roofline of the line kernels against
-HBM bandwidth, and the oracle's CPU throughput on a bounded sample.
+HBM bandwidth, and the oracle's CPU throughput on a bounded sample.  Under
+"extra": the same step in FP32, one 128^3 block with closures (tridiagonal
+D1+D2), the periodic 256^3 precision study (banded FP64 / banded FP32 / dense
+mixed BF16 with FP64 residual refinement, each with its error against the
+oracle) and the RK4 wave evolution on a periodic 192^3 grid.
 """
 from __future__ import annotations
 
@@ -26,6 +30,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 OPS_PENTA = [("(1)QP_O8[1]", 0), ("(1)QP_O8[1]", 1), ("(1)QP_O8[1]", 2),
              ("(2)QP_O8[1]", 0), ("(2)QP_O8[1]", 1), ("(2)QP_O8[1]", 2)]
+OPS_TRI = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2),
+           ("(2)Q1_3[1]", 0), ("(2)Q1_3[1]", 1), ("(2)Q1_3[1]", 2)]
+OPS_D1_TRI = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2)]
 
 
 def algorithmic_bytes(wl, ops, esize):
@@ -112,6 +119,112 @@ def cpu_baseline(wl, ops, budget_s=12.0):
                       f"fields x {len(ops)} ops: {evals} evals in {dt:.1f} s"}
 
 
+def _field_err(y, plan, wl, ops, fields):
+    """Relative max-norm error of the listed fields (all ops, block 0) against the oracle."""
+    from tests import helpers as H
+    from oracle import lines as OL
+    from oracle import schemes as OS
+    import synth
+    _, ooffs = plan.offsets()
+    blk = wl.blocks[0]
+    npts = int(np.prod(blk.n))
+    nf = wl.nfields
+    worst = 0.0
+    for o, (name, d) in enumerate(ops):
+        s = OS.named(name)
+        for f in fields:
+            off = ooffs[0] + (o * nf + f) * npts
+            got = y[off:off + npts].double().cpu().numpy().reshape(blk.n[2], blk.n[1], blk.n[0])
+            ref = OL.apply_block(s, wl.field_view(0, f), blk.ng, blk.h[d], d,
+                                 periodic=blk.boundary[d] == synth.PERIODIC)
+            worst = max(worst, H.rel_err(got, ref))
+    return worst
+
+
+def extra_block128(steps, warmup, autotune):
+    """One 128^3 block, ng = 4, tridiagonal tuned D1 + D2 along x, y, z with matched closures, FP64."""
+    import torch
+    import synth
+    import paper_2302_14858_amd as P
+    wl = synth.block128()
+    plan, x, y, ms, _, _, _ = run_gpu(wl, OPS_TRI, P.CFD_F64, steps, warmup, autotune=autotune)
+    evals = wl.interior_points * wl.nfields * len(OPS_TRI)
+    alg, _, _ = algorithmic_bytes(wl, OPS_TRI, 8)
+    out = {"workload": "block128: one 128^3 block on [-1,1]^3, ng=4, Gaussian + N(0,1e-3) noise modes, "
+                       "(d)Q1_3[1] D1+D2 along x,y,z with matched closures, FP64",
+           "ms_per_step": ms, "value": evals / (ms * 1e-3), "unit": "evals/s",
+           "achieved_GBs": alg / (ms * 1e-3) / 1e9, "err_vs_oracle": _field_err(y, plan, wl, OPS_TRI, [0])}
+    del plan, x, y
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_periodic256(steps, warmup, autotune):
+    """Periodic 256^3 x 8 fields, tridiagonal D1 along x, y, z: banded FP64, banded FP32, dense mixed."""
+    import torch
+    import synth
+    import paper_2302_14858_amd as P
+    wl = synth.periodic256()
+    evals = wl.interior_points * wl.nfields * len(OPS_D1_TRI)
+    out = {"workload": "periodic256: 256^3, 8 fields of 32 modes with k up to 120, (1)Q1_3[1] D1 along x,y,z"}
+    for label, dt, es in (("f64_banded", P.CFD_F64, 8), ("f32_banded", P.CFD_F32, 4),
+                          ("mixed_dense_bf16", P.CFD_MIXED_BF16, 4)):
+        plan, x, y, ms, _, _, _ = run_gpu(wl, OPS_D1_TRI, dt, steps, warmup, autotune=autotune)
+        alg, _, _ = algorithmic_bytes(wl, OPS_D1_TRI, es)
+        out[label] = {"ms_per_step": ms, "value": evals / (ms * 1e-3), "unit": "evals/s",
+                      "achieved_GBs": alg / (ms * 1e-3) / 1e9,
+                      "err_vs_oracle": _field_err(y, plan, wl, OPS_D1_TRI, [0, wl.nfields - 1]),
+                      "err_sample": "fields 0 and 7, all three directions, every node"}
+        del plan, x, y
+        torch.cuda.empty_cache()
+    out["speedup_mixed_vs_f64"] = out["f64_banded"]["ms_per_step"] / out["mixed_dense_bf16"]["ms_per_step"]
+    out["speedup_f32_vs_f64"] = out["f64_banded"]["ms_per_step"] / out["f32_banded"]["ms_per_step"]
+    return out
+
+
+def extra_wave192(nsteps=200):
+    """RK4 of the first-order wave system on a periodic 192^3 grid, k = (3,5,7), dt = h/4."""
+    import torch
+    import synth
+    import paper_2302_14858_amd as P
+    from paper_2302_14858_amd.wave import WaveRK4
+    n = 192
+    wl = synth.wave192(n=n)
+    h = wl.blocks[0].h[0]
+    dt = 0.25 * h
+    k = np.array(synth.WAVE_K, dtype=np.float64)
+    w = float(np.sqrt(np.sum(k * k)))
+    T = nsteps * dt
+    xs = np.arange(n) * h
+    ex = [np.exp(-1j * k[a] * xs) for a in range(3)]
+    exact = synth.wave_state(xs, xs, xs, T)[0]
+    out = {"workload": f"wave192: periodic 192^3, plane wave k=(3,5,7), dt=h/4, {nsteps} RK4 steps, (1)Q1_3[1]"}
+    for label, dt_code in (("f64", P.CFD_F64), ("f32", P.CFD_F32)):
+        blocks = [dict(n=b.n, ng=b.ng, h=b.h, boundary=b.boundary) for b in wl.blocks]
+        rk = WaveRK4(blocks, P.Scheme.named("(1)Q1_3[1]"), dt, dtype=dt_code)
+        rk.load(wl.data)
+        rk.capture()
+        rk.load(wl.data)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rk.run(nsteps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / nsteps
+        phi = rk.u[: n ** 3].double().cpu().numpy().reshape(n, n, n)
+        F = np.einsum("zyx,x,y,z->", phi, ex[0], ex[1], ex[2]) / n ** 3
+        F_exact = np.exp(-1j * w * T) / 2j
+        dphase = float(np.angle(F / F_exact))
+        l2 = float(np.sqrt(np.mean((phi - exact) ** 2)) / np.sqrt(np.mean(exact ** 2)))
+        out[label] = {"ms_per_step": ms, "evals_per_s": 6 * 4 * n ** 3 / (ms * 1e-3), "l2_rel_err_vs_exact": l2,
+                      "phase_err_rad": abs(dphase), "T": T}
+        del rk
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +287,12 @@ def main():
                                    "achieved_GBs": alg32 / (ms32 * 1e-3) / 1e9}}
         del x, y, plan
         torch.cuda.empty_cache()
+        print("bench: block128", file=sys.stderr, flush=True)
+        result["extra"]["block128"] = extra_block128(args.steps, args.warmup, not args.no_autotune)
+        print("bench: periodic256 precision study", file=sys.stderr, flush=True)
+        result["extra"]["periodic256"] = extra_periodic256(min(args.steps, 20), args.warmup, not args.no_autotune)
+        print("bench: wave192 RK4", file=sys.stderr, flush=True)
+        result["extra"]["wave192"] = extra_wave192()
     if not args.no_cpu:
         print("bench: CPU oracle sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(wl, ops)

@@ -257,6 +257,7 @@ cfd_status cfd_halo_exchange(cfd_plan *p, void *data_dev, int bx, int by, int bz
 /* ------------------------------------------------------------------------ */
 /* Element-wise stage kernels for method-of-lines time stepping (classical   */
 /* ERK4, Sec. 3.1): y = a*x + b*y and z = x + c*y over n elements.           */
+/* With b = 0, y is overwritten without being read (any prior contents).     */
 /* ------------------------------------------------------------------------ */
 
 cfd_status cfd_axpby(cfd_dtype dtype, long long n, double a, const void *x_dev, double b,

@@ -86,7 +86,7 @@ __global__ void k_halo(T *__restrict__ data, const int64_t *__restrict__ off, in
 template <typename T>
 __global__ void k_axpby(int64_t n, T a, const T *__restrict__ x, T b, T *__restrict__ y) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        y[i] = a * x[i] + b * y[i];
+        y[i] = b == T(0) ? a * x[i] : a * x[i] + b * y[i];   // b = 0: y is not read
 }
 
 template <typename T>

@@ -10,7 +10,7 @@ from __future__ import annotations
 
 from typing import Dict, List, Optional
 
-from . import CFD_F32, CFD_F64, Plan, Scheme
+from . import CFD_F32, CFD_F64, Plan, Scheme, cfd_axpby
 
 
 def wave_ops(scheme: Scheme):
@@ -46,7 +46,7 @@ class WaveRK4:
     def step(self):
         """u <- RK4 step of size dt."""
         dt = self.dt
-        self.acc.copy_(self.u)
+        cfd_axpby(1.0, self.u, 0.0, self.acc)          # acc = u
         src = self.u
         for a, b in ((dt / 2, dt / 6), (dt / 2, dt / 3), (dt, dt / 3), (None, dt / 6)):
             self.plan.apply(src, self.d)
@@ -55,7 +55,7 @@ class WaveRK4:
             if a is not None:
                 self._halo(self.stage)
                 src = self.stage
-        self.u.copy_(self.acc)
+        cfd_axpby(1.0, self.acc, 0.0, self.u)          # u = acc
         self._halo(self.u)
 
     def capture(self):
