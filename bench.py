@@ -28,6 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per batch64 FP64 step (x launch + y/z launch), from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# passes scaled by what the same counters read for a 1 GiB device copy (x2.0 and x1.0).  Valid for
+# the line kernels as they are now; set to None when they change until the counters are taken again.
+MEASURED_TRAFFIC_BYTES = 3.17e9
 OPS_PENTA = [("(1)QP_O8[1]", 0), ("(1)QP_O8[1]", 1), ("(1)QP_O8[1]", 2),
              ("(2)QP_O8[1]", 0), ("(2)QP_O8[1]", 1), ("(2)QP_O8[1]", 2)]
 OPS_TRI = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2),
@@ -272,7 +276,7 @@ def main():
                    "evals_per_step": evals, "kernel_launches_per_step": launches, "work_items": items},
         "err_vs_oracle": err64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC_BYTES,
                      "algorithmic_bytes": alg, "read_bytes": rd, "write_bytes": wr},
     }
     del x, y, plan

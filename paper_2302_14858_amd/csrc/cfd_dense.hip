@@ -226,8 +226,11 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
         for (int k = 0; k < KT; ++k) {
             int i, c;
             dense_elem<N, XDIR>(tid, k, i, c);
+            // unconditional load (lines past the last one read line 0, then 0 is
+            // selected): no branch around it, so all KT loads stay in flight
             const int64_t o = cin[c];
-            pre[k] = o >= 0 ? fbase[o + (XDIR ? (int64_t)i : (int64_t)i * sd)] : 0.f;
+            const float v = fbase[(o >= 0 ? o : 0) + (XDIR ? (int64_t)i : (int64_t)i * sd)];
+            pre[k] = o >= 0 ? v : 0.f;
         }
         const unsigned short *ge =
             reinterpret_cast<const unsigned short *>(tabdata + tabs[wi.tab].off + 16 * sizeof(double));

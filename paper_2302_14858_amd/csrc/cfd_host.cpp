@@ -537,7 +537,9 @@ cfd_status build_dense(cfd_plan *p) {
     HIPCHK(hipMalloc(&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
     // work items: 32 lines of one pass and field; one group (kernel) per (N, x or not)
-    std::map<std::pair<int, int>, std::vector<unsigned char>> by_class;
+    // items of one table are kept together: a workgroup keeps the table's
+    // circulant blocks in registers while consecutive items use it
+    std::map<std::pair<int, int>, std::vector<std::array<int, 4>>> by_class_t;   // (tab, pass, field, line0)
     const size_t isz = dense_item_size();
     for (size_t b = 0; b < p->blocks.size(); ++b)
         for (int f = 0; f < p->nfields; ++f)
@@ -545,12 +547,21 @@ cfd_status build_dense(cfd_plan *p) {
                 const PassHost &ps = p->passes[i];
                 if (ps.block != (int)b || f < ps.field0 || f >= ps.field0 + ps.nfield) continue;
                 const int xd = (pd[i].sd == 1 && pd[i].osd == 1) ? 1 : 0;
-                std::vector<unsigned char> &items = by_class[std::make_pair(ps.N, xd)];
-                for (int l0 = 0; l0 < pd[i].nlines; l0 += 32) {
-                    items.resize(items.size() + isz);
-                    fill_dense_item(items.data() + items.size() - isz, (int)i, f - ps.field0, l0, pass_tab[i][0]);
-                }
+                auto &v = by_class_t[std::make_pair(ps.N, xd)];
+                for (int l0 = 0; l0 < pd[i].nlines; l0 += 32)
+                    v.push_back({pass_tab[i][0], (int)i, f - ps.field0, l0});
             }
+    std::map<std::pair<int, int>, std::vector<unsigned char>> by_class;
+    for (auto &kv : by_class_t) {
+        std::stable_sort(kv.second.begin(), kv.second.end(),
+                         [](const std::array<int, 4> &x, const std::array<int, 4> &y) { return x[0] < y[0]; });
+        std::vector<unsigned char> &items = by_class[kv.first];
+        items.resize(kv.second.size() * isz);
+        for (size_t e = 0; e < kv.second.size(); ++e) {
+            const auto &t = kv.second[e];
+            fill_dense_item(items.data() + e * isz, t[1], t[2], t[3], t[0]);
+        }
+    }
     std::vector<unsigned char> items;
     p->groups.clear();
     for (auto &kv : by_class) {

@@ -145,3 +145,11 @@ def test_mixed_dense_plan_limits():
         with pytest.raises(P.CfdError) as e:
             P.Plan([dict(n=n, ng=4, h=(0.1, 0.1, 0.1), boundary=bnd)], 1, [(s, 0)], dtype=P.CFD_MIXED_BF16)
         assert e.value.status == _lib.CFD_EUNSUPPORTED
+
+
+def test_schedule_calls_validate_arguments():
+    L = _lib.lib()
+    flags = ctypes.c_int(-1)
+    assert L.cfd_plan_get_flags(None, ctypes.byref(flags)) == _lib.CFD_EINVAL
+    assert L.cfd_plan_set_schedule(None, 0, 0, 0, _lib.CFD_SCHED_CONCURRENT) == _lib.CFD_EINVAL
+    assert L.cfd_plan_get_schedule(None, None, None, None, None, None, None, 0) == _lib.CFD_EINVAL
