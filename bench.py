@@ -65,8 +65,7 @@ def run_gpu(wl, ops, dtype, steps, warmup, autotune=True):
     x = torch.from_numpy(wl.data).to(device="cuda", dtype=tdt)
     y = torch.empty(nout, dtype=tdt, device="cuda")
     if autotune:
-        plan.autotune(x, y, cache_path=os.path.join(ROOT, "_work", "autotune_cache.txt")
-                      if os.path.isdir(os.path.join(ROOT, "_work")) else None)
+        plan.autotune(x, y)   # no cache: every run tunes on the box it runs on
     plan.capture_graph(x, y)
     for _ in range(warmup):
         plan.launch_graph()

@@ -207,18 +207,22 @@ cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream);
 /* Schedule flags. */
 #define CFD_SCHED_PERSISTENT 1   /* grid of (occupancy x CUs) workgroups walking the work list */
 #define CFD_SCHED_SPLIT_X    2   /* lines along x in a launch of their own */
-#define CFD_SCHED_XCD        4   /* persistent grid with one work queue per XCD: the
-                                    x/y/z passes of a block-field stay on one L2 */
+#define CFD_SCHED_XCD        4   /* block-fields dealt to the 8 XCDs, the same way in
+                                    every launch, so the x/y/z passes of a block-field
+                                    stay on one L2: a persistent grid walks one queue
+                                    per XCD; a per-item grid gets the items in an order
+                                    where workgroup b (on XCD b mod 8) takes its XCD's */
 #define CFD_SCHED_CONCURRENT 8   /* the plan's launches (e.g. the x launch and the y/z
                                     launch) run on forked streams at the same time,
                                     joined on the caller's stream before later work */
 
 /* Time the candidate schedules on the given buffers and keep the fastest:
- * the number of partitions per line for every (line length, x or y/z) class,
- * then the launch shape (persistent grid or one workgroup per item; x lines
- * fused with y/z or split; launches one after another or concurrent).  If cache_path is non-NULL the per-class choices
+ * the launch shape (persistent grid, XCD-aware or not, or one workgroup per
+ * item; x lines fused with y/z or split; launches one after another or
+ * concurrent), then under that shape the number of partitions per line for
+ * every (line length, x or y/z) class, then the launch shape again.  If cache_path is non-NULL the per-class choices
  * are read from / appended to that text file, keyed by device arch, dtype,
- * line length, direction class, band and fused operators.  Synchronises the
+ * line length, direction class, band, fused operators and launch shape.  Synchronises the
  * stream.  Invalidates a captured graph. */
 cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, void *stream,
                              const char *cache_path);
@@ -230,7 +234,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
 cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions, int flags);
 
 /* Read back the schedule: persistent receives 0 (one workgroup per item),
- * 1 (persistent grid) or 2 (persistent, XCD-aware queues); split_x the x split
+ * 1 (persistent grid) or 2 (XCD-aware); split_x the x split
  * flag; for up to cap line classes their (N, xlines, partitions).  n_classes
  * receives the number of classes. */
 cfd_status cfd_plan_get_schedule(const cfd_plan *p, int *persistent, int *split_x, int *n_classes, int *N,

@@ -418,6 +418,24 @@ cfd_status build_groups(cfd_plan *p) {
             }
         }
     }
+    // XCD-aware modes: block-fields are dealt to kXCDq queues (least-loaded
+    // first, by the cost of all their passes in every group), the same way for
+    // every group, so a block-field's x, y and z lines, also in separate
+    // launches, share one XCD's L2.  Workgroup b runs on XCD b mod kXCDq.
+    const int nbf = (int)(p->blocks.size() * p->nfields);
+    std::vector<int> bf_queue(nbf, 0);
+    if (p->xcd) {
+        std::vector<int64_t> bf_cost(nbf, 0);
+        for (size_t gi = 0; gi < groups.size(); ++gi)
+            for (size_t e = 0; e < gitems[gi].size(); ++e) bf_cost[gbf[gi][e]] += gcost[gi][e];
+        std::vector<int64_t> load(kXCDq, 0);
+        for (int bf = 0; bf < nbf; ++bf) {
+            if (!bf_cost[bf]) continue;
+            const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            bf_queue[bf] = k;
+            load[k] += bf_cost[bf];
+        }
+    }
     std::vector<WorkItem> items;
     std::vector<int> qoffs;
     for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -429,31 +447,34 @@ cfd_status build_groups(cfd_plan *p) {
             nb = 1;
         (void)hipGetLastError();
         g.grid_persist = (int)std::min<int64_t>(g.nitems, (int64_t)nb * p->cus);
-        if (p->xcd && p->persistent && g.nitems >= 8 * kXCDq) {
-            // deal whole block-fields to kXCDq queues, least-loaded first, keeping
-            // each block-field's items (its x/y/z passes) together and in order
+        g.qoff_index = -1;
+        if (p->xcd && g.nitems >= 8 * kXCDq) {
             std::vector<std::vector<WorkItem>> q(kXCDq);
-            std::vector<int64_t> load(kXCDq, 0);
-            const auto &its = gitems[gi];
-            size_t a = 0;
-            while (a < its.size()) {
-                size_t e = a;
-                int64_t cost = 0;
-                while (e < its.size() && gbf[gi][e] == gbf[gi][a]) cost += gcost[gi][e++];
-                const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                q[k].insert(q[k].end(), its.begin() + a, its.begin() + e);
-                load[k] += cost;
-                a = e;
-            }
-            g.qoff_index = (int)qoffs.size();
-            int off = 0;
-            for (int k = 0; k < kXCDq; ++k) {
+            for (size_t e = 0; e < gitems[gi].size(); ++e) q[bf_queue[gbf[gi][e]]].push_back(gitems[gi][e]);
+            if (p->persistent) {
+                // persistent grid: workgroup b walks queue b mod kXCDq
+                g.qoff_index = (int)qoffs.size();
+                int off = 0;
+                for (int k = 0; k < kXCDq; ++k) {
+                    qoffs.push_back(off);
+                    off += (int)q[k].size();
+                    items.insert(items.end(), q[k].begin(), q[k].end());
+                }
                 qoffs.push_back(off);
-                off += (int)q[k].size();
-                items.insert(items.end(), q[k].begin(), q[k].end());
+                g.grid_persist = std::max(kXCDq, (g.grid_persist / kXCDq) * kXCDq);
+            } else {
+                // one workgroup per item: queue k's items at positions k, k + kXCDq, ...;
+                // shorter queues are padded with empty items (pass -1)
+                size_t len = 0;
+                for (auto &v : q) len = std::max(len, v.size());
+                for (size_t r = 0; r < len; ++r)
+                    for (int k = 0; k < kXCDq; ++k)
+                        items.push_back(r < q[k].size() ? q[k][r] : WorkItem{-1, 0, 0, 0});
+                g.nitems = (int64_t)(items.size() - g.item0);
+                g.grid_persist = (int)std::min<int64_t>(g.nitems, (int64_t)nb * p->cus);
+                g.qoff_index = (int)qoffs.size();   // marker: workgroups pick their XCD's item
+                qoffs.push_back(-1);
             }
-            qoffs.push_back(off);
-            g.grid_persist = std::max(kXCDq, (g.grid_persist / kXCDq) * kXCDq);
         } else {
             items.insert(items.end(), gitems[gi].begin(), gitems[gi].end());
         }
@@ -1050,7 +1071,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     }
     auto keyof = [&](const std::tuple<int, int, int, int> &k) {
         std::ostringstream s;
-        s << arch << ":" << dt << ":N" << std::get<0>(k) << ":x" << std::get<1>(k) << ":nl" << std::get<2>(k)
+        s << "v2:" << arch << ":" << dt << ":N" << std::get<0>(k) << ":x" << std::get<1>(k) << ":nl" << std::get<2>(k)
           << ":ops" << std::get<3>(k);
         return s.str();
     };
@@ -1062,7 +1083,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
             cfd_status s = enqueue(p, in_dev, out_dev, st);
             if (s != CFD_OK) return s;
         }
-        const int reps = 5;
+        const int reps = 10;
         HIPCHK(hipEventRecord(e0, st));
         for (int r = 0; r < reps; ++r) {
             cfd_status s = enqueue(p, in_dev, out_dev, st);
@@ -1074,11 +1095,44 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         ms /= reps;
         return CFD_OK;
     };
+    // launch shape: persistent grid, XCD-aware queues or per-item grid (plain
+    // or in XCD-interleaved order); x lines fused with y/z or split; launches
+    // sequential or concurrent
+    auto tune_shape = [&]() -> cfd_status {
+        float best = 1e30f;
+        int bmode = 1;
+        bool bs = false, bc = false;
+        cfd_status r = CFD_OK;
+        // mode: 0 per-item grid, 1 persistent, 2 persistent with XCD queues,
+        // 3 per-item grid in XCD-interleaved order
+        for (int mode = 0; mode < 4 && r == CFD_OK; ++mode)
+            for (int split = 0; split <= 1 && r == CFD_OK; ++split)
+                for (int conc = 0; conc <= 1 && r == CFD_OK; ++conc) {
+                    p->persistent = mode == 1 || mode == 2;
+                    p->xcd = mode >= 2;
+                    p->split_x = split;
+                    p->concurrent = conc;
+                    r = build(p);
+                    if (r == CFD_OK && conc && p->groups.size() < 2) continue;   // same as sequential
+                    float ms = 0;
+                    if (r == CFD_OK) r = time_apply(ms);
+                    if (r == CFD_OK && ms < best) { best = ms; bmode = mode; bs = split; bc = conc; }
+                }
+        p->persistent = bmode == 1 || bmode == 2;
+        p->xcd = bmode >= 2;
+        p->split_x = bs;
+        p->concurrent = bc;
+        return r;
+    };
     std::vector<std::string> new_lines;
-    cfd_status result = CFD_OK;
+    // 1. the launch shape with the default partitions; 2. partitions per class
+    // under that shape; 3. the launch shape again with those partitions
+    cfd_status result = tune_shape();
+    const int shape = (p->persistent ? 1 : 0) | (p->split_x ? 2 : 0) | (p->xcd ? 4 : 0) | (p->concurrent ? 8 : 0);
     for (auto &kv : classes) {
+        if (result != CFD_OK) break;
         const auto skey = std::make_pair(std::get<0>(kv.first), std::get<1>(kv.first));
-        const std::string key = keyof(kv.first);
+        const std::string key = keyof(kv.first) + ":shape" + std::to_string(shape);
         auto hit = cache.find(key);
         if (hit != cache.end() && std::find(kv.second.begin(), kv.second.end(), hit->second) != kv.second.end()) {
             p->sched_P[skey] = hit->second;
@@ -1100,30 +1154,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         p->sched_P[skey] = bestP;
         new_lines.push_back(key + " " + std::to_string(bestP));
     }
-    if (result == CFD_OK) {
-        // launch shape: persistent grid (plain or XCD-aware queues) or one
-        // workgroup per item; x lines fused with y/z or split
-        float best = 1e30f;
-        int bmode = 1;
-        bool bs = false, bc = false;
-        for (int mode = 0; mode < 3 && result == CFD_OK; ++mode)
-            for (int split = 0; split <= 1 && result == CFD_OK; ++split)
-                for (int conc = 0; conc <= 1 && result == CFD_OK; ++conc) {
-                    p->persistent = mode != 0;
-                    p->xcd = mode == 2;
-                    p->split_x = split;
-                    p->concurrent = conc;
-                    result = build(p);
-                    if (result == CFD_OK && conc && p->groups.size() < 2) continue;   // same as sequential
-                    float ms = 0;
-                    if (result == CFD_OK) result = time_apply(ms);
-                    if (result == CFD_OK && ms < best) { best = ms; bmode = mode; bs = split; bc = conc; }
-                }
-        p->persistent = bmode != 0;
-        p->xcd = bmode == 2;
-        p->split_x = bs;
-        p->concurrent = bc;
-    }
+    if (result == CFD_OK) result = tune_shape();
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (result != CFD_OK) return result;

@@ -415,13 +415,26 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = threadIdx.x & 63;
 
-    // Work distribution.  Plain: grid-stride over the list.  XCD-aware (qoff
-    // given, grid a multiple of kXCD): workgroup ids are dealt round-robin to
-    // the XCDs, so workgroup b runs on XCD b % kXCD and takes the items of
-    // queue b % kXCD; each queue holds whole block-fields, whose x/y/z passes
-    // then share one XCD's L2.
+    // Work distribution.  Plain: grid-stride over the list (with one workgroup
+    // per item, the host may have ordered the list so that item b belongs to
+    // XCD b % kXCD; padding items have pass -1).  XCD-aware persistent grid
+    // (qoff given, grid a multiple of kXCD): workgroup ids are dealt
+    // round-robin to the XCDs, so workgroup b runs on XCD b % kXCD and takes
+    // the items of queue b % kXCD; each queue holds whole block-fields, whose
+    // x/y/z passes then share one XCD's L2.
     int it = blockIdx.x, it_end = nitems, stride = gridDim.x;
-    if (qoff) {
+    if (qoff && qoff[0] < 0) {
+        // one workgroup per item, list in XCD-interleaved order (position 8 r + k
+        // holds queue k's r-th item; length a multiple of 8).  A launch's
+        // workgroups are dealt round-robin to the XCDs from a launch-dependent
+        // start, so workgroup b takes the item of its group of 8 that belongs to
+        // the XCD it runs on (read from the hardware): a permutation within the
+        // group, and the same XCD for a block-field in every launch.
+        const int xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kXCD - 1);   // HW_REG_XCC_ID
+        it = (int)(blockIdx.x & ~(unsigned)(kXCD - 1)) + xcc;
+        it_end = it + 1;
+        stride = 1;
+    } else if (qoff) {
         const int q = blockIdx.x % kXCD;
         it = qoff[q] + blockIdx.x / kXCD;
         it_end = qoff[q + 1];
@@ -429,6 +442,7 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
     }
     for (; it < it_end; it += stride) {
         const WorkItem wi = items[it];
+        if (wi.pass < 0) continue;   // padding of the XCD-interleaved order
         const PassDesc &pd = passes[wi.pass];
         LineCtx<T> c;
         c.pd = &pd;

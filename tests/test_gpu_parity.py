@@ -90,6 +90,8 @@ def test_every_schedule_same_result(cuda):
     assert tried >= 8
     for mode in ({"persistent": True, "xcd": True}, {"persistent": True, "xcd": True, "split_x": True},
                  {"persistent": False}, {"persistent": False, "split_x": True, "concurrent": True},
+                 {"persistent": False, "xcd": True}, {"persistent": False, "xcd": True, "split_x": True,
+                                                      "concurrent": True},
                  {"persistent": True, "split_x": True, "concurrent": True}):
         plan.set_schedule(0, **mode)
         g = H.gpu_run(plan, wl, D12_PENTA)
