@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per batch64 FP64 step (x launch + y/z launch), from rocprofv3 FETCH_SIZE and WRITE_SIZE
 # passes scaled by what the same counters read for a 1 GiB device copy (x2.0 and x1.0).  Valid for
 # the line kernels as they are now; set to None when they change until the counters are taken again.
-MEASURED_TRAFFIC_BYTES = 3.17e9
+MEASURED_TRAFFIC_BYTES = 3.01e9
 OPS_PENTA = [("(1)QP_O8[1]", 0), ("(1)QP_O8[1]", 1), ("(1)QP_O8[1]", 2),
              ("(2)QP_O8[1]", 0), ("(2)QP_O8[1]", 1), ("(2)QP_O8[1]", 2)]
 OPS_TRI = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2),
@@ -55,16 +55,25 @@ def algorithmic_bytes(wl, ops, esize):
     return (rd + wr) * esize, rd * esize, wr * esize
 
 
-def run_gpu(wl, ops, dtype, steps, warmup, autotune=True):
+def run_gpu(wl, ops, dtype, steps, warmup, autotune=True, schedule=None):
+    """schedule: None (autotune or defaults) or (flags, [(N, xlines, partitions), ...]) set by hand."""
     import torch
     import paper_2302_14858_amd as P
+    from paper_2302_14858_amd import _lib
     from tests import helpers as H
     tdt = torch.float64 if dtype == P.CFD_F64 else torch.float32
     plan = H.make_plan(wl, ops, dtype=dtype)
     nin, nout = plan.sizes()
     x = torch.from_numpy(wl.data).to(device="cuda", dtype=tdt)
     y = torch.empty(nout, dtype=tdt, device="cuda")
-    if autotune:
+    if schedule is not None:
+        flags, parts = schedule
+        kw = dict(persistent=bool(flags & _lib.CFD_SCHED_PERSISTENT), split_x=bool(flags & _lib.CFD_SCHED_SPLIT_X),
+                  xcd=bool(flags & _lib.CFD_SCHED_XCD), concurrent=bool(flags & _lib.CFD_SCHED_CONCURRENT))
+        plan.set_schedule(0, **kw)
+        for N, xl, Pp in parts:
+            plan.set_schedule(N, xl, Pp, **kw)
+    elif autotune:
         plan.autotune(x, y)   # no cache: every run tunes on the box it runs on
     plan.capture_graph(x, y)
     for _ in range(warmup):
@@ -236,6 +245,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--flags", type=int, default=None,
+                    help="set the batch64 launch shape by hand (a set of CFD_SCHED_* bits) instead of autotuning")
+    ap.add_argument("--parts", default="",
+                    help="with --flags: partitions per class as N:xlines:P,... (as printed in config.schedule)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -251,8 +264,13 @@ def main():
     evals = wl.interior_points * wl.nfields * len(ops)
 
     print("bench: FP64 batched step", file=sys.stderr, flush=True)
+    schedule = None
+    if args.flags is not None:
+        parts = [tuple(int(v) for v in t.split(":")) for t in args.parts.split(",") if t]
+        schedule = (args.flags, parts)
     plan, x, y, ev_ms, wall, launches, items = run_gpu(wl, ops, P.CFD_F64, args.steps, args.warmup,
-                                                       autotune=not args.no_autotune)
+                                                       autotune=not args.no_autotune, schedule=schedule)
+    sched = plan.get_schedule()
     alg, rd, wr = algorithmic_bytes(wl, ops, 8)
     achieved = alg / (ev_ms * 1e-3) / 1e9
     err64 = check_sample(plan, y, wl, ops, blocks=[0, 1, 2])
@@ -272,7 +290,9 @@ def main():
         "config": {"workload": "batch64: 64 blocks, extents from {16,24,32,48}^3 (seed 3), ng=5, 22 fields, "
                                "D1+D2 along x,y,z, (d)QP_O8[1] + matched closures, one graph launch",
                    "interior_points": wl.interior_points, "fields": wl.nfields, "ops": len(ops),
-                   "evals_per_step": evals, "kernel_launches_per_step": launches, "work_items": items},
+                   "evals_per_step": evals, "kernel_launches_per_step": launches, "work_items": items,
+                   "schedule": {"flags": sched["flags"],
+                                "parts": ",".join(f"{n}:{xl}:{pp}" for n, xl, pp in sched["classes"])}},
         "err_vs_oracle": err64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC_BYTES,
