@@ -277,15 +277,18 @@ cfd_status cfd_xpcy(cfd_dtype dtype, long long n, const void *x_dev, double c, c
  * D_z psi_z] (op = {scheme of degree 1, dir, field}).  src_dev is the stage
  * state and derivs_dev the plan's output computed from it; the right-hand side
  * k is assembled on interior nodes and
- *   stage = u0 + a k   (skipped if stage_dev is NULL; stage may equal src;
- *                       ghosts untouched),
- *   acc  += b k.
- * u0, src, stage and acc are in the plan's input layout (element type per
- * dtype).  Classical RK4: acc = u; stage sources u, s, s, s with
- * a = dt/2, dt/2, dt, - and b = dt/6, dt/3, dt/3, dt/6 (s written in place);
- * then u = acc and refresh ghosts with cfd_halo_exchange. */
+ *   stage = u0 + a k      (skipped if stage_dev is NULL; stage may equal src;
+ *                          ghosts untouched),
+ *   acc   = acc_in + b k  (acc_in NULL means acc itself; acc_in may equal u0,
+ *                          which is then read once).
+ * u0, src, stage, acc_in and acc are in the plan's input layout (element type
+ * per dtype).  Classical RK4 with stage sources u, s, s, s, a = dt/2, dt/2,
+ * dt, - and b = dt/6, dt/3, dt/3, dt/6 (s written in place): the first stage
+ * takes acc_in = u, the last writes acc = u, so no state copies are needed;
+ * then refresh ghosts with cfd_halo_exchange. */
 cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev,
-                             void *acc_dev, const void *derivs_dev, double a, double b, void *stream);
+                             const void *acc_in_dev, void *acc_dev, const void *derivs_dev, double a, double b,
+                             void *stream);
 
 #ifdef __cplusplus
 }

@@ -204,9 +204,11 @@ class Plan:
 
     get_schedule = cfd_plan_get_schedule
 
-    def cfd_wave_rk_stage(self, u0, src, stage, acc, derivs, a: float, b: float, stream=None) -> None:
+    def cfd_wave_rk_stage(self, u0, src, stage, acc, derivs, a: float, b: float, stream=None, acc_in=None) -> None:
+        """stage = u0 + a k (unless stage is None); acc = acc_in + b k (acc_in None: acc itself)."""
         check(lib().cfd_wave_rk_stage(self._h, _dev_ptr(u0), _dev_ptr(src),
-                                      _dev_ptr(stage) if stage is not None else None, _dev_ptr(acc),
+                                      _dev_ptr(stage) if stage is not None else None,
+                                      _dev_ptr(acc_in) if acc_in is not None else None, _dev_ptr(acc),
                                       _dev_ptr(derivs), float(a), float(b), _stream_ptr(stream)))
 
     wave_rk_stage = cfd_wave_rk_stage

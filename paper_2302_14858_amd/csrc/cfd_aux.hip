@@ -104,7 +104,7 @@ __global__ void k_xpcy(int64_t n, const T *__restrict__ x, T c, const T *__restr
 // before it is written by the same thread) and acc += b k.  State arrays hold
 // the five fields with ghosts, [f][z][y][x].
 template <typename T>
-__global__ void k_wave_stage(const T *u0, const T *src, T *stage, T *__restrict__ acc,
+__global__ void k_wave_stage(const T *u0, const T *src, T *stage, const T *acc_in, T *acc,
                              const T *__restrict__ d, const int64_t *__restrict__ in_off,
                              const int64_t *__restrict__ out_off, const int *__restrict__ shapes, int nblocks,
                              int64_t total, T a, T b) {
@@ -132,8 +132,11 @@ __global__ void k_wave_stage(const T *u0, const T *src, T *stage, T *__restrict_
         const T k[5] = {src[ip + fs], db[3 * n3] + db[4 * n3] + db[5 * n3], db[0], db[n3], db[2 * n3]};
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-            if (stage) stage[ip + f * fs] = u0[ip + f * fs] + a * k[f];
-            acc[ip + f * fs] += b * k[f];
+            T u = T(0);
+            if (stage || acc_in == u0) u = u0[ip + f * fs];
+            const T ai = (acc_in == u0) ? u : acc_in[ip + f * fs];
+            if (stage) stage[ip + f * fs] = u + a * k[f];
+            acc[ip + f * fs] = ai + b * k[f];
         }
     }
 }
@@ -183,7 +186,8 @@ hipError_t launch_xpcy(int f32, int64_t n, const void *x, double c, const void *
 }  // namespace cfd
 
 namespace cfd {
-hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *stage, void *acc, const void *d,
+hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *stage, const void *acc_in, void *acc,
+                             const void *d,
                              const int64_t *in_off, const int64_t *out_off, const int *shapes, int nblocks,
                              int64_t total, double a, double b, hipStream_t st) {
     if (total == 0) return hipSuccess;
@@ -191,12 +195,12 @@ hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *sta
     if (g > 16384) g = 16384;
     if (f32)
         hipLaunchKernelGGL(k_wave_stage<float>, dim3((int)g), dim3(256), 0, st, (const float *)u0, (const float *)src,
-                           (float *)stage,
+                           (float *)stage, (const float *)acc_in,
                            (float *)acc, (const float *)d, in_off, out_off, shapes, nblocks, total, (float)a,
                            (float)b);
     else
         hipLaunchKernelGGL(k_wave_stage<double>, dim3((int)g), dim3(256), 0, st, (const double *)u0,
-                           (const double *)src, (double *)stage, (double *)acc, (const double *)d, in_off, out_off, shapes, nblocks,
+                           (const double *)src, (double *)stage, (const double *)acc_in, (double *)acc, (const double *)d, in_off, out_off, shapes, nblocks,
                            total, a, b);
     return hipGetLastError();
 }

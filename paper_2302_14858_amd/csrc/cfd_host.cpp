@@ -1231,8 +1231,9 @@ cfd_status cfd_xpcy(cfd_dtype dtype, long long n, const void *x_dev, double c, c
     return CFD_OK;
 }
 
-cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev, void *acc_dev,
-                             const void *derivs_dev, double a, double b, void *stream) {
+cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev,
+                             const void *acc_in_dev, void *acc_dev, const void *derivs_dev, double a, double b,
+                             void *stream) {
     if (!p || !u0_dev || !src_dev || !acc_dev || !derivs_dev)
         return fail(CFD_EINVAL, "cfd_wave_rk_stage: null argument");
     // the plan must hold the five wave fields and the six first-derivative operators
@@ -1270,7 +1271,8 @@ cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_de
     }
     int64_t total = 0;
     for (const cfd_block &bl : p->blocks) total += (int64_t)bl.n[0] * bl.n[1] * bl.n[2];
-    hipError_t e = launch_wave_stage(p->dtype == CFD_F32, u0_dev, src_dev, stage_dev, acc_dev, derivs_dev,
+    if (!acc_in_dev) acc_in_dev = acc_dev;
+    hipError_t e = launch_wave_stage(p->dtype == CFD_F32, u0_dev, src_dev, stage_dev, acc_in_dev, acc_dev, derivs_dev,
                                      (const int64_t *)p->d_inoff.p, (const int64_t *)p->d_outoff.p,
                                      (const int *)p->d_shapes.p, nb, total, a, b, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launching wave stage");

@@ -10,7 +10,7 @@ from __future__ import annotations
 
 from typing import Dict, List, Optional
 
-from . import CFD_F32, CFD_F64, Plan, Scheme, cfd_axpby
+from . import CFD_F32, CFD_F64, Plan, Scheme
 
 
 def wave_ops(scheme: Scheme):
@@ -44,18 +44,18 @@ class WaveRK4:
             self.plan.halo_exchange(buf, *self.lattice)
 
     def step(self):
-        """u <- RK4 step of size dt."""
+        """u <- RK4 step of size dt (the first stage reads acc from u, the last writes u)."""
         dt = self.dt
-        cfd_axpby(1.0, self.u, 0.0, self.acc)          # acc = u
         src = self.u
-        for a, b in ((dt / 2, dt / 6), (dt / 2, dt / 3), (dt, dt / 3), (None, dt / 6)):
+        stages = ((dt / 2, dt / 6), (dt / 2, dt / 3), (dt, dt / 3), (None, dt / 6))
+        for i, (a, b) in enumerate(stages):
             self.plan.apply(src, self.d)
-            self.plan.wave_rk_stage(self.u, src, self.stage if a is not None else None, self.acc, self.d,
-                                    a if a is not None else 0.0, b)
-            if a is not None:
+            last = i == len(stages) - 1
+            self.plan.wave_rk_stage(self.u, src, None if last else self.stage, self.u if last else self.acc,
+                                    self.d, 0.0 if a is None else a, b, acc_in=self.u if i == 0 else self.acc)
+            if not last:
                 self._halo(self.stage)
                 src = self.stage
-        cfd_axpby(1.0, self.acc, 0.0, self.u)          # u = acc
         self._halo(self.u)
 
     def capture(self):
