@@ -249,10 +249,23 @@ def main():
                     help="set the batch64 launch shape by hand (a set of CFD_SCHED_* bits) instead of autotuning")
     ap.add_argument("--parts", default="",
                     help="with --flags: partitions per class as N:xlines:P,... (as printed in config.schedule)")
+    ap.add_argument("--only", choices=["block128", "periodic256", "wave192"], default=None,
+                    help="run just one of the other workloads and print its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.only:
+        import torch
+        torch.cuda.init()
+        if args.only == "block128":
+            r = extra_block128(args.steps, args.warmup, not args.no_autotune)
+        elif args.only == "periodic256":
+            r = extra_periodic256(min(args.steps, 20), args.warmup, not args.no_autotune)
+        else:
+            r = extra_wave192()
+        print(json.dumps({args.only: r}), flush=True)
+        return
 
     import torch
     import synth
