@@ -77,6 +77,7 @@ struct PassHost {
     int sch[2];       // scheme indices
     int N, periodic, nl, par, mi, hw;
     int P = 0, L = 0, lcode = 0;
+    int C = 1;        // x lines: column chunks the LDS tile is staged in (divides P)
     const LineClass *cls = nullptr;
 };
 
@@ -161,9 +162,28 @@ size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }   // F32 and MIXE
 
 constexpr int kXCDq = 8;   // queues of the XCD-aware schedule (one per XCD)
 
-// Tile bytes an x item with P partitions of L rows needs in LDS.
-size_t x_tile_bytes(int P, int L, int hw, size_t es) {
-    return (size_t)(kWave * 4 / P) * (size_t)((P * L + 2 * hw) | 1) * es;
+// Tile bytes an x item with P partitions of L rows needs in LDS: 64 (4/P)
+// lines by the columns of one chunk (P/C partitions plus the halo).
+size_t x_tile_bytes(int P, int L, int hw, size_t es, int C = 1) {
+    return (size_t)(kWave * 4 / P) * (size_t)((P / C * L + 2 * hw) | 1) * es;
+}
+
+// Column chunks for x lines: the fewest (dividing P) that keep tile and
+// exchange area within 80 KiB, so two workgroups share a CU (the line
+// classes' registers allow no more than that for long partitions); long lines
+// are then staged chunk by chunk.
+// Only kernel classes compiled with the chunk loop (partitions of 48 rows or
+// more) stage in chunks.
+bool chunked(const LineClass *k) {
+    int m = 0;
+    for (int j = 0; j < k->nL; ++j) m = std::max(m, k->Ls[j]);
+    return m >= 48;
+}
+
+int x_chunks(int P, int L, int hw, size_t es, size_t exch) {
+    for (int C = 1; C <= P; C *= 2)
+        if (x_tile_bytes(P, L, hw, es, C) + exch <= 81920) return C;
+    return P;
 }
 
 // Partition length for P partitions of an N-node line: the smallest compiled
@@ -198,7 +218,7 @@ std::vector<int> candidate_Ps(const PassHost &ps, bool f32, size_t max_lds) {
         if (!k) continue;
         if (ps.periodic && k->hw > ps.N) continue;
         size_t lds = (size_t)k->exch * es;
-        if (ps.dir == 0) lds += x_tile_bytes(P, L, k->hw, es);
+        if (ps.dir == 0) lds += x_tile_bytes(P, L, k->hw, es, chunked(k) ? x_chunks(P, L, k->hw, es, lds) : 1);
         if (lds > max_lds) continue;
         ok.push_back(P);
     }
@@ -283,6 +303,8 @@ cfd_status build_groups(cfd_plan *p) {
         ps.lcode = 0;
         for (int j = 0; j < ps.cls->nL; ++j)
             if (ps.cls->Ls[j] == ps.L) ps.lcode = j;
+        const size_t es1 = f32 ? 4 : 8;
+        ps.C = (ps.dir == 0 && chunked(ps.cls)) ? x_chunks(ps.P, ps.L, ps.cls->hw, es1, (size_t)ps.cls->exch * es1) : 1;
     }
     // 2. tables
     std::map<TabKey, int> tabidx;
@@ -407,9 +429,9 @@ cfd_status build_groups(cfd_plan *p) {
                 }
                 if (ps.dir == 0)
                     groups[gi].lds = std::max(groups[gi].lds, (size_t)ps.cls->exch * es +
-                                                                  x_tile_bytes(ps.P, ps.L, ps.cls->hw, es));
+                                                                  x_tile_bytes(ps.P, ps.L, ps.cls->hw, es, ps.C));
                 const int per_item = kWave * (4 / ps.P);
-                const int meta = ps.P | (ps.lcode << 4);
+                const int meta = ps.P | (ps.lcode << 4) | ((ps.C - 1) << 8);
                 for (int l0 = 0; l0 < pd[i].nlines; l0 += per_item) {
                     gitems[gi].push_back(WorkItem{(int32_t)i, f - ps.field0, l0, meta});
                     gbf[gi].push_back((int)(b * p->nfields + f));

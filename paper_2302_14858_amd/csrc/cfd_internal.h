@@ -87,7 +87,7 @@ struct PassDesc {
 
 // One work item: 64 * (4 / P) lines of one field of one pass.
 // meta: P (partitions per line) in bits 0..3, index of L in the kernel's
-// compiled set in bits 4..7.
+// compiled set in bits 4..7, x lines: column chunks C - 1 in bits 8..9.
 struct WorkItem {
     int32_t pass;
     int32_t field;

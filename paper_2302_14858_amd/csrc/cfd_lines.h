@@ -81,13 +81,16 @@ struct LineCtx {
     int P, p, sub, g;       // partitions, this wave's partition, line group, lane
     int tpitch;             // tile row pitch (elements)
     int trow;               // this lane's tile row
+    int C, chunk;           // x lines: column chunks of the tile, this wave's chunk
+    const T *fbase;         // x lines: node (0, 0, 0) of the item's field
+    int line0;              // x lines: first line of the item
     bool periodic;
 };
 
 // One lane: the p-th partition (L rows) of its line, all NOPS operators.
 // Leaves the solution (times h^-d) in y.
 template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool X, bool PAD>
-__device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS][L]) {
+__device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS][L], T (&fin)[L + 2 * HW]) {
     const PassDesc &pd = *c.pd;
     const int N = pd.N;
     const int ng = pd.ng;
@@ -109,12 +112,8 @@ __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS
 
     // every input node of the partition (its rows and a halo of HW on each
     // side) is requested before any arithmetic, so all of the partition's loads
-    // are in flight together
-    T fin[L + 2 * HW];
-    if constexpr (X) {
-#pragma unroll
-        for (int t = 0; t < L + 2 * HW; ++t) fin[t] = c.tile[c.trow * c.tpitch + k0 + t];
-    } else {
+    // are in flight together.  x lines: the caller has read fin from the tile.
+    if constexpr (!X) {
         const bool lo_edge = c.p == 0;
         const bool hi_edge = c.p == c.P - 1;
         // walk a pointer along the line: one stride add per node keeps the
@@ -251,20 +250,20 @@ __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS
     }
 }
 
-// Stage the x-lines of this item in LDS: row r holds nodes -HW .. Npad+HW-1
-// of line line0 + r (zero outside the ghosts, wrapped for periodic lines,
-// whose Npad equals N; rows past the last line read as zero).  Thread tid owns
-// the node pair tid % CW (CW = W / 2 pairs per row) of the rows
-// tid / CW + k * RPP, RPP = 256 / CW rows per pass: its line advances by RPP
-// per pass without a division, and the loads of BATCH passes are in flight
-// together before their LDS writes.  W is even (Npad and 2 HW are).
+// Stage the x-lines of this item in LDS: column t of row r holds node n0 + t
+// of line line0 + r, t < W (zero outside the ghosts, wrapped for periodic
+// lines; rows past the last line read as zero).  Thread tid owns the node
+// pair tid % CW (CW = W / 2 pairs per row) of the rows tid / CW + k * RPP,
+// RPP = 256 / CW rows per pass: its line advances by RPP per pass without a
+// division, and the loads of BATCH passes are in flight together before their
+// LDS writes.  W is even (partition lengths and 2 HW are).
 template <typename T, int HW>
-__device__ __forceinline__ void stage_x(const PassDesc &pd, const T *base, int line0, int nrows, int Npad, T *tile,
-                                        int tpitch, bool periodic) {
+__device__ __forceinline__ void stage_x(const PassDesc &pd, const T *base, int line0, int nrows, int n0, int W,
+                                        T *tile, int tpitch, bool periodic) {
     constexpr int NT = 64 * kWGW;
     constexpr int BATCH = 8;
     const int N = pd.N, ng = pd.ng;
-    const int CW = (Npad + 2 * HW) >> 1;
+    const int CW = W >> 1;
     const int RPP = NT / CW;
     const int tid = threadIdx.x;
     const int r0 = tid / CW;
@@ -274,7 +273,7 @@ __device__ __forceinline__ void stage_x(const PassDesc &pd, const T *base, int l
     int j[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        int jj = 2 * c2 + h - HW;
+        int jj = n0 + 2 * c2 + h;
         if (periodic) {
             if (jj < 0) jj += N;
             if (jj >= N) jj -= N;
@@ -312,20 +311,19 @@ __device__ __forceinline__ void stage_x(const PassDesc &pd, const T *base, int l
 }
 
 // Write the x results staged in the tile (row r = line line0 + r, pitch
-// opitch) to the interior output: consecutive x-lines of one field are
-// consecutive rows of the output, so the item's results are one contiguous
-// run of nrows * N elements.  Thread tid owns node pair tid % CO of rows
-// tid / CO + k * RPP.
+// opitch, ncols columns) to the interior output rows of length N:
+// consecutive x-lines of one field are consecutive rows of the output.
+// Thread tid owns node pair tid % CO of rows tid / CO + k * RPP.
 template <typename T>
-__device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N, int opitch) {
+__device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N, int ncols, int opitch) {
     constexpr int NT = 64 * kWGW;
-    const int CO = (N + 1) >> 1;
+    const int CO = (ncols + 1) >> 1;
     const int RPP = NT / CO;
     const int tid = threadIdx.x;
     const int r0 = tid / CO;
     const int c = 2 * (tid - r0 * CO);
     if (r0 >= RPP) return;
-    const bool second = c + 1 < N;
+    const bool second = c + 1 < ncols;
 #pragma unroll 4
     for (int r = r0; r < nrows; r += RPP) {
         const T a = tile[r * opitch + c];
@@ -336,33 +334,79 @@ __device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N,
 }
 
 // Item body for one compiled partition length L.
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool PAD>
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool PAD, bool CHK>
 __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *out, bool xdir, bool active,
                                          int lu, int lv) {
     const PassDesc &pd = *c.pd;
     T y[NOPS][L];
     if (xdir) {
-        solve_partition<T, NL, NOPS, PAR, MI, HW, L, true, PAD>(c, y);
-        // results back through the tile, then contiguous coalesced stores:
-        // x-lines line0.. of one field are consecutive rows of the interior output
+        // the tile holds one column chunk (P/C partitions and the halo) at a
+        // time: stage it, the waves of that chunk read their inputs, next chunk
         const int nsub = kWGW / c.P;
         const int nrows_all = nsub * 64;
         const int N = pd.N;
-        const int opitch = N | 1;
+        const int C = CHK ? c.C : 1;
+        const int PC = c.P / C;
+        T fin[L + 2 * HW];
+        if constexpr (CHK) {   // classes with long partitions: any number of chunks
+            for (int ch = 0; ch < C; ++ch) {
+                if (ch > 0) __syncthreads();   // the previous chunk's readers are done
+                stage_x<T, HW>(pd, c.fbase, c.line0, nrows_all, ch * PC * L - HW, PC * L + 2 * HW, c.tile,
+                               c.tpitch, c.periodic);
+                __syncthreads();
+                if (c.chunk == ch) {
+                    const int k0 = (c.p - ch * PC) * L;
 #pragma unroll
-        for (int o = 0; o < NOPS; ++o) {
-            __syncthreads();   // every lane is done with the input / previous op in the tile
+                    for (int t = 0; t < L + 2 * HW; ++t) fin[t] = c.tile[c.trow * c.tpitch + k0 + t];
+                }
+            }
+        } else {   // one chunk: the whole line, staged by the kernel before dispatch
 #pragma unroll
-            for (int i = 0; i < L; ++i)
-                if (c.p * L + i < N) c.tile[c.trow * opitch + c.p * L + i] = y[o][i];
-            __syncthreads();
-            T *dst = out + pd.out_base[o] + (int64_t)wi.field * pd.out_fstride + (int64_t)wi.line0 * N;
+            for (int t = 0; t < L + 2 * HW; ++t) fin[t] = c.tile[c.trow * c.tpitch + c.p * L + t];
+        }
+        solve_partition<T, NL, NOPS, PAR, MI, HW, L, true, PAD>(c, y, fin);
+        // results back through the tile, chunk by chunk, then contiguous
+        // coalesced stores: x-lines line0.. of one field are consecutive rows
+        // of the interior output
+        if constexpr (CHK) {
+            const int opitch = (PC * L) | 1;
             int nrows = pd.nlines - wi.line0;
             if (nrows > nrows_all) nrows = nrows_all;
-            store_x(dst, c.tile, nrows, N, opitch);
+#pragma unroll
+            for (int o = 0; o < NOPS; ++o) {
+                T *dst = out + pd.out_base[o] + (int64_t)wi.field * pd.out_fstride + (int64_t)wi.line0 * N;
+                for (int ch = 0; ch < C; ++ch) {
+                    __syncthreads();   // every lane is done with the input / previous chunk in the tile
+                    if (c.chunk == ch) {
+                        const int k0 = (c.p - ch * PC) * L;
+#pragma unroll
+                        for (int i = 0; i < L; ++i)
+                            if (c.p * L + i < N) c.tile[c.trow * opitch + k0 + i] = y[o][i];
+                    }
+                    __syncthreads();
+                    const int col0 = ch * PC * L;
+                    const int ncols = min(N - col0, PC * L);
+                    if (ncols > 0) store_x(dst + col0, c.tile, nrows, N, ncols, opitch);
+                }
+            }
+        } else {
+            const int opitch = N | 1;
+#pragma unroll
+            for (int o = 0; o < NOPS; ++o) {
+                __syncthreads();   // every lane is done with the input / previous op in the tile
+#pragma unroll
+                for (int i = 0; i < L; ++i)
+                    if (c.p * L + i < N) c.tile[c.trow * opitch + c.p * L + i] = y[o][i];
+                __syncthreads();
+                T *dst = out + pd.out_base[o] + (int64_t)wi.field * pd.out_fstride + (int64_t)wi.line0 * N;
+                int nrows = pd.nlines - wi.line0;
+                if (nrows > nrows_all) nrows = nrows_all;
+                store_x(dst, c.tile, nrows, N, N, opitch);
+            }
         }
     } else {
-        solve_partition<T, NL, NOPS, PAR, MI, HW, L, false, PAD>(c, y);
+        T fin[L + 2 * HW];
+        solve_partition<T, NL, NOPS, PAR, MI, HW, L, false, PAD>(c, y, fin);
         if (active) {
 #pragma unroll
             for (int o = 0; o < NOPS; ++o) {
@@ -386,23 +430,35 @@ struct LSet {
     static constexpr int n = sizeof...(Ls);
 };
 
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L0, int... Ls>
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool CHK, int L0, int... Ls>
 __device__ __forceinline__ void dispatch_L(int lcode, bool pad, LineCtx<T> &c, const WorkItem &wi, T *out,
                                            bool xdir, bool active, int lu, int lv) {
     if (lcode == 0) {
         if (pad)
-            run_item<T, NL, NOPS, PAR, MI, HW, L0, true>(c, wi, out, xdir, active, lu, lv);
+            run_item<T, NL, NOPS, PAR, MI, HW, L0, true, CHK>(c, wi, out, xdir, active, lu, lv);
         else
-            run_item<T, NL, NOPS, PAR, MI, HW, L0, false>(c, wi, out, xdir, active, lu, lv);
+            run_item<T, NL, NOPS, PAR, MI, HW, L0, false, CHK>(c, wi, out, xdir, active, lu, lv);
         return;
     }
-    if constexpr (sizeof...(Ls) > 0) dispatch_L<T, NL, NOPS, PAR, MI, HW, Ls...>(lcode - 1, pad, c, wi, out,
-                                                                                 xdir, active, lu, lv);
+    if constexpr (sizeof...(Ls) > 0) dispatch_L<T, NL, NOPS, PAR, MI, HW, CHK, Ls...>(lcode - 1, pad, c, wi, out,
+                                                                                      xdir, active, lu, lv);
+}
+
+// Classes whose partitions reach this many rows stage long x lines in column
+// chunks (the host sets C > 1 only for them).
+constexpr int kChunkMinL = 48;
+
+template <int... Ls>
+constexpr int max_L() {
+    int m = 0;
+    for (int v : {Ls...}) m = v > m ? v : m;
+    return m;
 }
 
 // Persistent line kernel: every workgroup walks the work list with a grid
 // stride.  Work item meta: P in bits 0..3, index of L in the compiled set in
-// bits 4..7.  Dynamic LDS: exchange area, then the x tile.
+// bits 4..7, x lines: column chunks - 1 in bits 8..9.  Dynamic LDS: exchange
+// area, then the x tile (one column chunk).
 template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int... Ls>
 __global__ void __launch_bounds__(64 * kWGW)
 k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ qoff,
@@ -412,6 +468,7 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
     T *exch = reinterpret_cast<T *>(smem_raw);
     T *tile = exch + exch_elems<NL, NOPS>();
     constexpr int kLs[] = {Ls...};
+    constexpr bool kChunked = max_L<Ls...>() >= kChunkMinL;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = threadIdx.x & 63;
 
@@ -464,17 +521,28 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
         const int lv = line / pd.nu;
         const T *fbase = in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride;
         if (xdir) {
-            const int nsub = kWGW / c.P;
-            const int Npad = c.P * kLs[lcode];
-            c.tpitch = (Npad + 2 * HW) | 1;
             c.trow = c.sub * 64 + g;
-            stage_x<T, HW>(pd, fbase, wi.line0, nsub * 64, Npad, tile, c.tpitch, c.periodic);
-            __syncthreads();
+            if constexpr (kChunked) {   // staged chunk by chunk in the item body
+                c.C = ((wi.meta >> 8) & 3) + 1;
+                const int PC = c.P / c.C;
+                c.chunk = c.p / PC;
+                c.tpitch = (PC * kLs[lcode] + 2 * HW) | 1;
+                c.fbase = fbase;
+                c.line0 = wi.line0;
+            } else {
+                const int Npad = c.P * kLs[lcode];
+                c.C = 1;
+                c.chunk = 0;
+                c.tpitch = (Npad + 2 * HW) | 1;
+                stage_x<T, HW>(pd, fbase, wi.line0, (kWGW / c.P) * 64, -HW, Npad + 2 * HW, tile, c.tpitch,
+                               c.periodic);
+                __syncthreads();
+            }
         } else {
             c.src = fbase + (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
         }
         const bool pad = c.P * kLs[lcode] != pd.N;
-        dispatch_L<T, NL, NOPS, PAR, MI, HW, Ls...>(lcode, pad, c, wi, out, xdir, active, lu, lv);
+        dispatch_L<T, NL, NOPS, PAR, MI, HW, kChunked, Ls...>(lcode, pad, c, wi, out, xdir, active, lu, lv);
     }
 }
 
