@@ -23,9 +23,6 @@ namespace cfd {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
-constexpr int kDenseLines = 32;        // lines per tile (two 16-wide MFMA column blocks)
-constexpr int kDensePitch = 34;        // LDS row pitch of the tile (floats): the 4 row groups of a
-                                       // B fragment read fall in distinct banks
 constexpr int kDenseMaxN = 256;
 constexpr int kDenseExt = 16;          // wrap-around margin of the extended circulant rows
 
@@ -134,6 +131,21 @@ k_dense_form(const DenseTab *__restrict__ tabs, const double *__restrict__ coefs
 
 // ---------------------------------------------------------------------------
 // Apply
+//
+// A workgroup takes an item of 64 lines; each of its four waves owns 16 of
+// them (one MFMA column block) and works on its own, with no workgroup
+// barrier except when the item's table differs from the one staged.
+// Per wave and item:
+//   1. its lines' inputs (prefetched into registers in the B-operand layout:
+//      lane (q, c) holds nodes 32 kb + 8 q + t of line c) go to its LDS tile F
+//      and are split into BF16 hi / lo fragments;
+//   2. yhat = D f: the 16 x 32 block of D at strip s, column block kb depends
+//      only on w = (2 kb - s) mod N/16, so the loop runs over w with the two
+//      A fragments of w (hi, lo) live and every kb it meets;
+//   3. yhat (times h^-d) into its LDS tile Y; FP64 residual per lane over a
+//      quarter of one line, r kept as BF16 in registers, then written over F;
+//   4. y = yhat + R r with R's fragments and the same loop;
+//   5. stores straight from the accumulators.
 // ---------------------------------------------------------------------------
 struct DenseItem {
     int32_t pass;
@@ -142,286 +154,285 @@ struct DenseItem {
     int32_t tab;
 };
 
-// 8 consecutive circulant entries ext[start .. start + 7] of an extended row: the
-// A fragment of lane (q, r) of a 16 x 32 block of D.  start is only 2-byte aligned
-// (it moves with r), so five aligned dwords are read and shifted by one element
-// where start is odd.
-__device__ __forceinline__ bf16x8 circ_frag(const unsigned short *ext, int start) {
-    const uint32_t *d = reinterpret_cast<const uint32_t *>(ext) + (start >> 1);
-    uint32_t w[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) w[k] = d[k];
-    const uint32_t sh = (uint32_t)(start & 1) * 2u;   // bytes
-    uint32_t o[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) o[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
-    bf16x8 v;
-    __builtin_memcpy(&v, o, sizeof v);
-    return v;
-}
+constexpr int kDenseWaves = 4;
+constexpr int kDenseLinesW = 16;                            // lines per wave
+constexpr int kDenseItemLines = kDenseWaves * kDenseLinesW;   // lines per item
 
-// Element offsets of a tile's lines in the input and the output (-1 past the last line).
-__device__ __forceinline__ void dense_cols(const DenseItem &wi, const PassDesc *__restrict__ passes, int c,
-                                           int64_t *col_in, int64_t *col_out) {
-    const PassDesc &pd = passes[wi.pass];
-    int64_t a = -1, o = -1;
-    if (c < min(kDenseLines, pd.nlines - wi.line0)) {
-        const int line = wi.line0 + c;
-        const int lu = line % pd.nu, lv = line / pd.nu;
-        a = (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
-        o = (int64_t)lv * pd.osv + (int64_t)lu * pd.osu;
-    }
-    col_in[c] = a;
-    col_out[c] = o;
-}
+// LDS geometry of one line length.
+//  * per-wave tiles F and Y: 16 lines x FP floats, FP = N + 4 (FP / 4 odd:
+//    the 16 lanes of a quarter-wave reading 16 B at one node of 16 lines hit
+//    distinct banks);
+//  * circulant tables: per term (D_hi, D_lo, R_hi) eight skewed copies
+//    E_j[x] = row[(x - j - 16) mod N], x < 2 SPD, SPD dwords apart; lane
+//    (q, c) reads its 8 entries of fragment w at E_{c % 8}[16 + 8 q - 8 (c / 8) + 16 w],
+//    a 16-byte-aligned position.  SPD is an odd multiple of 8, which spreads
+//    the 16 lanes of a quarter-wave over all banks.
+template <int N>
+struct DenseGeom {
+    static constexpr int NW = N / 16;   // strips = distinct circulant blocks per term
+    static constexpr int NK = N / 32;   // 32-wide column blocks
+    static constexpr int FP = N + 4;
+    static constexpr int SPD0 = ((N + 32) / 2 + 7) / 8 * 8;
+    static constexpr int SPD = (SPD0 / 8) % 2 ? SPD0 : SPD0 + 8;
+    static constexpr int TILE = 2 * kDenseLinesW * FP;                  // floats per wave (F, Y)
+    static constexpr int LDS = kDenseWaves * TILE + 3 * 8 * SPD;        // dwords
+};
 
-// Thread <-> tile element maps, element k = 0 .. N/8 - 1 of thread tid:
-//  * y/z lines: node g + 8k of line c (c = tid % 32, g = tid / 32): 32 threads
-//    read one node of 32 lines that are neighbours in memory;
-//  * x lines (nodes consecutive in memory): chunk g + 8k of 32 nodes, node
-//    (chunk % (N/32)) * 32 + tid % 32 of line chunk / (N/32).
-template <int N, bool XDIR>
-__device__ __forceinline__ void dense_elem(int tid, int k, int &i, int &c) {
-    const int g = tid >> 5, lane = tid & 31;
-    if constexpr (XDIR) {
-        constexpr int CPL = N / 32;
-        const int chunk = g + 8 * k;
-        c = chunk / CPL;
-        i = (chunk - c * CPL) * 32 + lane;
-    } else {
-        c = lane;
-        i = g + 8 * k;
+__device__ __forceinline__ bf16x8 split_hi(const float (&v)[8], bf16x8 &lo) {
+    bf16x8 hi;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const __bf16 h = (__bf16)v[t];
+        hi[t] = h;
+        lo[t] = (__bf16)(v[t] - (float)h);
     }
+    return hi;
 }
 
 template <int N, bool XDIR>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(64 * kDenseWaves)
 k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *__restrict__ passes,
               const DenseTab *__restrict__ tabs, const unsigned char *__restrict__ tabdata,
               const float *__restrict__ in, float *__restrict__ out) {
-    constexpr int KT = N / 8;                       // tile elements per thread = rows per residual group
-    constexpr int NE = 3 * (N + 48);                // circulant rows (bf16)
-    constexpr int EK = (NE + 255) / 256;
-    constexpr int NSTRIP = N / 16;                  // 16-row strips of the product
-    constexpr int SPW = (NSTRIP + 3) / 4;           // strips per wave
-    __shared__ float F[N * kDensePitch];            // input tile, then the result
-    __shared__ float Y[N * kDensePitch];            // first approximation yhat, then the residual
-    __shared__ __attribute__((aligned(16))) unsigned short Eraw[NE + 8];
-    __shared__ int64_t col_in[2][kDenseLines], col_out[2][kDenseLines];   // this tile's and the next one's
+    using G = DenseGeom<N>;
+    constexpr int NW = G::NW, NK = G::NK, FP = G::FP, SPD = G::SPD;
+    constexpr int QR = N / 4;   // residual rows per lane
+    __shared__ __attribute__((aligned(16))) float smem[G::LDS];
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l = tid & 63;
-    const int q = l >> 4, r16 = l & 15;
-    const int cown = tid & (kDenseLines - 1);
-    const int g = tid >> 5;
+    const int q = l >> 4, c = l & 15;
+    float *Fw = smem + w * G::TILE;
+    float *Yw = Fw + kDenseLinesW * FP;
+    unsigned short *Fb = reinterpret_cast<unsigned short *>(Fw);   // r as BF16 over F, pitch 2 FP
+    unsigned short *T = reinterpret_cast<unsigned short *>(smem + kDenseWaves * G::TILE);
+    const int fbase_lane = (c & 7) * 2 * SPD + 16 + 8 * q - 8 * (c >> 3);   // BF16 index, fragment 0
 
-    // One tile's loads (input and circulant rows) into registers, all in flight at once.
-    float pre[KT];
-    unsigned short pre_e[EK];
-    auto issue_loads = [&](const DenseItem &wi, const int64_t *cin) {
+    // input / output offset of this lane's line (lines past the last one: line0's, not stored)
+    auto line_offsets = [&](const DenseItem &wi, const PassDesc &pd, int64_t &oi, int64_t &oo, bool &live) {
+        int line = wi.line0 + w * kDenseLinesW + c;
+        live = line < pd.nlines;
+        if (!live) line = wi.line0;
+        const int lu = line % pd.nu, lv = line / pd.nu;
+        oi = (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
+        oo = (int64_t)lv * pd.osv + (int64_t)lu * pd.osu;
+    };
+    float pre[NK][8];
+    auto load_tile = [&](const DenseItem &wi) {
         const PassDesc &pd = passes[wi.pass];
-        const float *fbase = in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride;
-        const int64_t sd = pd.sd;
+        const float *fb = in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride;
+        int64_t oi, oo;
+        bool live;
+        line_offsets(wi, pd, oi, oo, live);
+        const float *src = fb + oi;
+        if constexpr (XDIR) {
+            const bool al = ((reinterpret_cast<uintptr_t>(fb) & 15) == 0) && ((pd.su & 3) == 0) && ((pd.sv & 3) == 0);
+            if (al) {
 #pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            int i, c;
-            dense_elem<N, XDIR>(tid, k, i, c);
-            // unconditional load (lines past the last one read line 0, then 0 is
-            // selected): no branch around it, so all KT loads stay in flight
-            const int64_t o = cin[c];
-            const float v = fbase[(o >= 0 ? o : 0) + (XDIR ? (int64_t)i : (int64_t)i * sd)];
-            pre[k] = o >= 0 ? v : 0.f;
-        }
-        const unsigned short *ge =
-            reinterpret_cast<const unsigned short *>(tabdata + tabs[wi.tab].off + 16 * sizeof(double));
+                for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
-        for (int k = 0; k < EK; ++k) {
-            const int j = tid + 256 * k;
-            pre_e[k] = (j < NE) ? ge[j] : (unsigned short)0;
+                    for (int h = 0; h < 2; ++h) {
+                        const float4 v = *reinterpret_cast<const float4 *>(src + 32 * kb + 8 * q + 4 * h);
+                        pre[kb][4 * h] = v.x;
+                        pre[kb][4 * h + 1] = v.y;
+                        pre[kb][4 * h + 2] = v.z;
+                        pre[kb][4 * h + 3] = v.w;
+                    }
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < NK; ++kb)
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) pre[kb][t] = src[32 * kb + 8 * q + t];
+            }
+        } else {
+            const int64_t sd = pd.sd;
+#pragma unroll
+            for (int kb = 0; kb < NK; ++kb)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) pre[kb][t] = src[(int64_t)(32 * kb + 8 * q + t) * sd];
         }
     };
 
-    if (blockIdx.x < nitems) {
-        const DenseItem w0 = items[blockIdx.x];
-        if (tid < kDenseLines) dense_cols(w0, passes, tid, col_in[0], col_out[0]);
-        __syncthreads();
-        issue_loads(w0, col_in[0]);
-    }
-    int buf = 0;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x, buf ^= 1) {
+    int cur_tab = -1;
+    if (blockIdx.x < nitems) load_tile(items[blockIdx.x]);
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const DenseItem wi = items[it];
         const PassDesc &pd = passes[wi.pass];
+        const DenseTab tb = tabs[wi.tab];
+        // circulant tables of this item's scheme (all waves hold the same item)
+        if (wi.tab != cur_tab) {
+            __syncthreads();   // every wave is done with the previous table
+            const unsigned short *rows = reinterpret_cast<const unsigned short *>(tabdata + tb.off + 16 * sizeof(double));
+            for (int e = tid; e < 3 * 8 * 2 * SPD; e += 64 * kDenseWaves) {
+                const int term = e / (16 * SPD);
+                const int rem = e - term * 16 * SPD;
+                const int j = rem / (2 * SPD);
+                const int x = rem - j * 2 * SPD;
+                int k = (x - j - 16) % N;
+                if (k < 0) k += N;
+                T[e] = rows[term * (N + 48) + kDenseExt + k];
+            }
+            __syncthreads();
+            cur_tab = wi.tab;
+        }
         const double hinv = pd.hinv[0];
-        const double *cf = reinterpret_cast<const double *>(tabdata + tabs[wi.tab].off);
+        const double *cf = reinterpret_cast<const double *>(tabdata + tb.off);
+        int64_t oi, oo;
+        bool live;
+        line_offsets(wi, pd, oi, oo, live);
 
-        // 1. the prefetched tile into LDS, F[i][c] = f(node i of line line0 + c);
-        // the next tile's loads go out as soon as its line offsets are known
+        // 1. inputs to F (B layout, 16 B per write) and BF16 hi / lo fragments
 #pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            int i, c;
-            dense_elem<N, XDIR>(tid, k, i, c);
-            F[i * kDensePitch + c] = pre[k];
-        }
+        for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
-        for (int k = 0; k < EK; ++k) {
-            const int j = tid + 256 * k;
-            if (j < NE) Eraw[j] = pre_e[k];
-        }
-        const int nxt = it + gridDim.x;
-        DenseItem wn{};
-        if (nxt < nitems) {
-            wn = items[nxt];
-            if (tid < kDenseLines) dense_cols(wn, passes, tid, col_in[buf ^ 1], col_out[buf ^ 1]);
-        }
-        __syncthreads();
-        if (nxt < nitems) issue_loads(wn, col_in[buf ^ 1]);
+            for (int h = 0; h < 2; ++h)
+                *reinterpret_cast<float4 *>(Fw + c * FP + 32 * kb + 8 * q + 4 * h) =
+                    make_float4(pre[kb][4 * h], pre[kb][4 * h + 1], pre[kb][4 * h + 2], pre[kb][4 * h + 3]);
+        bf16x8 bh[NK], bl[NK];
+#pragma unroll
+        for (int kb = 0; kb < NK; ++kb) bh[kb] = split_hi(pre[kb], bl[kb]);
+        // the next item's inputs are in flight from here to its step 1
+        if (it + gridDim.x < nitems) load_tile(items[it + gridDim.x]);
 
-        // 2. yhat = D f on MFMA (v_mfma_f32_16x16x32_bf16): wave w owns strips w, w + 4, ...
-        // D = D_hi + D_lo and f = f_hi + f_lo in BF16; the lo * lo term is dropped
-        f32x4 acc[SPW][2];
+        // 2. yhat = D_hi f_hi + D_hi f_lo + D_lo f_hi
+        f32x4 acc[NW];
 #pragma unroll
-        for (int j = 0; j < SPW; ++j) {
-            acc[j][0] = f32x4{0.f, 0.f, 0.f, 0.f};
-            acc[j][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-        const unsigned short *mhi = Eraw, *mlo = Eraw + (N + 48), *rhi = Eraw + 2 * (N + 48);
-#pragma unroll 1
-        for (int k0 = 0; k0 < N; k0 += 32) {
-            bf16x8 bh[2], bl[2];
+        for (int s = 0; s < NW; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int sub = 0; sub < 2; ++sub)
+        for (int wb = 0; wb < NW; ++wb) {
+            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(T + fbase_lane + 16 * wb);
+            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(T + 16 * SPD + fbase_lane + 16 * wb);
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const float v = F[(k0 + 8 * q + t) * kDensePitch + 16 * sub + r16];
-                    const __bf16 h = (__bf16)v;
-                    bh[sub][t] = h;
-                    bl[sub][t] = (__bf16)(v - (float)h);
-                }
+            for (int kb = 0; kb < NK; ++kb) {
+                const int s = (2 * kb - wb + NW) % NW;
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[kb], acc[s], 0, 0, 0);
+            }
 #pragma unroll
-            for (int j = 0; j < SPW; ++j) {
-                const int s = w + 4 * j;
-                if (s < NSTRIP) {
-                    // A fragment: D[16 s + r16][k0 + 8 q + t] = m[(k0 + 8 q + t - 16 s - r16) mod N]
-                    const int start = kDenseExt + wrapN(k0 - 16 * s, N) + 8 * q - r16;
-                    const bf16x8 ah = circ_frag(mhi, start);
-                    const bf16x8 al = circ_frag(mlo, start);
+            for (int kb = 0; kb < NK; ++kb) {
+                const int s = (2 * kb - wb + NW) % NW;
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[kb], acc[s], 0, 0, 0);
+            }
 #pragma unroll
-                    for (int sub = 0; sub < 2; ++sub) {
-                        acc[j][sub] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[sub], acc[j][sub], 0, 0, 0);
-                        acc[j][sub] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[sub], acc[j][sub], 0, 0, 0);
-                        acc[j][sub] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[sub], acc[j][sub], 0, 0, 0);
-                    }
-                }
+            for (int kb = 0; kb < NK; ++kb) {
+                const int s = (2 * kb - wb + NW) % NW;
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[kb], acc[s], 0, 0, 0);
             }
         }
-        // the BF16 rows hold A^-1 B; D = h^-d A^-1 B.  yhat into its own tile
-        // (C layout: row 16 s + 4 q + t, column 16 sub + r16)
+        // 3. yhat = h^-d A^-1 B f into Y (C layout: lane (q, c) holds rows 16 s + 4 q + t of line c)
         const float scale = (float)hinv;
 #pragma unroll
-        for (int j = 0; j < SPW; ++j) {
-            const int s = w + 4 * j;
-            if (s < NSTRIP)
+        for (int s = 0; s < NW; ++s) {
 #pragma unroll
-                for (int sub = 0; sub < 2; ++sub)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        acc[j][sub][t] *= scale;
-                        Y[(16 * s + 4 * q + t) * kDensePitch + 16 * sub + r16] = acc[j][sub][t];
-                    }
+            for (int t = 0; t < 4; ++t) acc[s][t] *= scale;
+            *reinterpret_cast<f32x4 *>(Yw + c * FP + 16 * s + 4 * q) = acc[s];
         }
-        __syncthreads();
-
-        // 3. FP64 residual r = h^-d B f - A yhat on rows g*KT .. g*KT + KT - 1 of column
-        // cown, with sliding windows over f (11 nodes) and yhat (5 nodes).  r overwrites
-        // yhat in Y: a row is read by another thread only within 2 rows of a group's
-        // ends, so those 4 rows wait in registers until every thread is past its reads.
+        __builtin_amdgcn_wave_barrier();
+        // FP64 residual r = h^-d B f - A yhat on rows q N/4 .. q N/4 + N/4 - 1 of line c,
+        // four rows at a time: f rows i-8 .. i+11 and yhat rows i-4 .. i+7 in registers
+        uint32_t rpk[QR / 2];
         {
             double cb[11], ca[5];
 #pragma unroll
             for (int t = 0; t < 11; ++t) cb[t] = cf[t] * hinv;
 #pragma unroll
             for (int t = 0; t < 5; ++t) ca[t] = cf[11 + t];
-            const int i0 = g * KT;
-            double fw[11], yw[5];
-            float edge[4];
+            const float *Fl = Fw + c * FP;
+            const float *Yl = Yw + c * FP;
+            const int i0 = q * QR;
+            auto ld4 = [&](const float *base, int row) {
+                row = (row + N) % N;
+                return *reinterpret_cast<const float4 *>(base + row);
+            };
+            double fwin[20], ywin[12];
+            {
 #pragma unroll
-            for (int t = 0; t < 11; ++t) fw[t] = (double)F[wrapN(i0 - 5 + t, N) * kDensePitch + cown];
-#pragma unroll
-            for (int t = 0; t < 5; ++t) yw[t] = (double)Y[wrapN(i0 - 2 + t, N) * kDensePitch + cown];
-#pragma unroll
-            for (int j = 0; j < KT; ++j) {
-                double bf = 0.0, ay = 0.0;
-#pragma unroll
-                for (int t = 0; t < 11; ++t) bf = fma(cb[t], fw[t], bf);
-#pragma unroll
-                for (int t = 0; t < 5; ++t) ay = fma(ca[t], yw[t], ay);
-                const float r = (float)(bf - ay);
-                if (j + 1 < KT) {
-#pragma unroll
-                    for (int t = 0; t < 10; ++t) fw[t] = fw[t + 1];
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) yw[t] = yw[t + 1];
-                    fw[10] = (double)F[wrapN(i0 + j + 6, N) * kDensePitch + cown];
-                    yw[4] = (double)Y[wrapN(i0 + j + 3, N) * kDensePitch + cown];
+                for (int k = 0; k < 4; ++k) {
+                    const float4 v = ld4(Fl, i0 - 8 + 4 * k);
+                    fwin[4 * k] = v.x; fwin[4 * k + 1] = v.y; fwin[4 * k + 2] = v.z; fwin[4 * k + 3] = v.w;
                 }
-                if (j < 2) edge[j] = r;
-                else if (j >= KT - 2) edge[j - KT + 4] = r;
-                else Y[(i0 + j) * kDensePitch + cown] = r;   // own rows, already in the window
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const float4 v = ld4(Yl, i0 - 4 + 4 * k);
+                    ywin[4 * k] = v.x; ywin[4 * k + 1] = v.y; ywin[4 * k + 2] = v.z; ywin[4 * k + 3] = v.w;
+                }
             }
-            __syncthreads();
-            Y[i0 * kDensePitch + cown] = edge[0];
-            Y[(i0 + 1) * kDensePitch + cown] = edge[1];
-            Y[(i0 + KT - 2) * kDensePitch + cown] = edge[2];
-            Y[(i0 + KT - 1) * kDensePitch + cown] = edge[3];
+#pragma unroll
+            for (int g4 = 0; g4 < QR / 4; ++g4) {
+                const int i = i0 + 4 * g4;
+                {
+                    const float4 v = ld4(Fl, i + 8);
+                    fwin[16] = v.x; fwin[17] = v.y; fwin[18] = v.z; fwin[19] = v.w;
+                    const float4 u = ld4(Yl, i + 4);
+                    ywin[8] = u.x; ywin[9] = u.y; ywin[10] = u.z; ywin[11] = u.w;
+                }
+                float rr[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    // row i + t: f at window index 8 + t + m, yhat at 4 + t + m
+                    double bf = 0.0, ay = 0.0;
+#pragma unroll
+                    for (int m = 0; m < 11; ++m) bf = fma(cb[m], fwin[3 + t + m], bf);
+#pragma unroll
+                    for (int m = 0; m < 5; ++m) ay = fma(ca[m], ywin[2 + t + m], ay);
+                    rr[t] = (float)(bf - ay);
+                }
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const __bf16 lo = (__bf16)rr[2 * t], hi = (__bf16)rr[2 * t + 1];
+                    rpk[2 * g4 + t] = (uint32_t)__builtin_bit_cast(unsigned short, lo) |
+                                      ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+                }
+#pragma unroll
+                for (int k = 0; k < 16; ++k) fwin[k] = fwin[k + 4];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) ywin[k] = ywin[k + 4];
+            }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+        // r (BF16) over F: rows q N/4 .. of line c, then read back in the B layout
+#pragma unroll
+        for (int k = 0; k < QR / 8; ++k)
+            *reinterpret_cast<uint4 *>(Fb + c * 2 * FP + q * QR + 8 * k) =
+                make_uint4(rpk[4 * k], rpk[4 * k + 1], rpk[4 * k + 2], rpk[4 * k + 3]);
+        __builtin_amdgcn_wave_barrier();
+        bf16x8 rb[NK];
+#pragma unroll
+        for (int kb = 0; kb < NK; ++kb) rb[kb] = *reinterpret_cast<const bf16x8 *>(Fb + c * 2 * FP + 32 * kb + 8 * q);
 
-        // 4. y = yhat + R r (R = A^-1 in one BF16 term), accumulated onto yhat
-#pragma unroll 1
-        for (int k0 = 0; k0 < N; k0 += 32) {
-            bf16x8 rb[2];
+        // 4. y = yhat + R r (R = A^-1 in one BF16 term)
 #pragma unroll
-            for (int sub = 0; sub < 2; ++sub)
+        for (int wb = 0; wb < NW; ++wb) {
+            const bf16x8 ar = *reinterpret_cast<const bf16x8 *>(T + 32 * SPD + fbase_lane + 16 * wb);
 #pragma unroll
-                for (int t = 0; t < 8; ++t) rb[sub][t] = (__bf16)Y[(k0 + 8 * q + t) * kDensePitch + 16 * sub + r16];
+            for (int kb = 0; kb < NK; ++kb) {
+                const int s = (2 * kb - wb + NW) % NW;
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, rb[kb], acc[s], 0, 0, 0);
+            }
+        }
+        // 5. stores: rows 16 s + 4 q .. + 3 of line c
+        if (live) {
+            float *dst = out + pd.out_base[0] + (int64_t)wi.field * pd.out_fstride + oo;
+            if constexpr (XDIR) {
+                if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
 #pragma unroll
-            for (int j = 0; j < SPW; ++j) {
-                const int s = w + 4 * j;
-                if (s < NSTRIP) {
-                    const int start = kDenseExt + wrapN(k0 - 16 * s, N) + 8 * q - r16;
-                    const bf16x8 a = circ_frag(rhi, start);
+                    for (int s = 0; s < NW; ++s)
+                        __builtin_nontemporal_store(acc[s], reinterpret_cast<f32x4 *>(dst + 16 * s + 4 * q));
+                } else {
 #pragma unroll
-                    for (int sub = 0; sub < 2; ++sub)
-                        acc[j][sub] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, rb[sub], acc[j][sub], 0, 0, 0);
+                    for (int s = 0; s < NW; ++s)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) __builtin_nontemporal_store(acc[s][t], dst + 16 * s + 4 * q + t);
                 }
+            } else {
+                const int64_t osd = pd.osd;
+#pragma unroll
+                for (int s = 0; s < NW; ++s)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        __builtin_nontemporal_store(acc[s][t], dst + (int64_t)(16 * s + 4 * q + t) * osd);
             }
         }
-        // 5. results through the tile to coalesced stores
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < SPW; ++j) {
-            const int s = w + 4 * j;
-            if (s < NSTRIP)
-#pragma unroll
-                for (int sub = 0; sub < 2; ++sub)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) F[(16 * s + 4 * q + t) * kDensePitch + 16 * sub + r16] = acc[j][sub][t];
-        }
-        __syncthreads();
-        {
-            float *obase = out + pd.out_base[0] + (int64_t)wi.field * pd.out_fstride;
-            const int64_t osd = pd.osd;
-#pragma unroll
-            for (int k = 0; k < KT; ++k) {
-                int i, c;
-                dense_elem<N, XDIR>(tid, k, i, c);
-                const int64_t o = col_out[buf][c];
-                if (o >= 0)
-                    __builtin_nontemporal_store(F[i * kDensePitch + c],
-                                                obase + o + (XDIR ? (int64_t)i : (int64_t)i * osd));
-            }
-        }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -463,6 +474,7 @@ hipError_t launch_dense_apply(const void *fn, int grid, hipStream_t st, const vo
 size_t dense_tab_bytes(int N) { return 16 * sizeof(double) + 3 * (size_t)(N + 48) * 2; }
 size_t dense_tab_struct_size() { return sizeof(DenseTab); }
 size_t dense_item_size() { return sizeof(DenseItem); }
+int dense_item_lines() { return kDenseItemLines; }
 void fill_dense_tab(void *dst, int N, int nl, int m, int64_t off) {
     DenseTab t;
     t.N = N; t.nl = nl; t.m = m; t.pad = 0; t.off = off;

@@ -579,9 +579,9 @@ cfd_status build_dense(cfd_plan *p) {
     p->d_pass.release();
     HIPCHK(hipMalloc(&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
-    // work items: 32 lines of one pass and field; one group (kernel) per (N, x or not)
-    // items of one table are kept together: a workgroup keeps the table's
-    // circulant blocks in registers while consecutive items use it
+    // work items: dense_item_lines() lines of one pass and field; one group
+    // (kernel) per (N, x or not).  Items of one table are kept together: a
+    // workgroup stages the table's circulant blocks in LDS once for them
     std::map<std::pair<int, int>, std::vector<std::array<int, 4>>> by_class_t;   // (tab, pass, field, line0)
     const size_t isz = dense_item_size();
     for (size_t b = 0; b < p->blocks.size(); ++b)
@@ -591,7 +591,7 @@ cfd_status build_dense(cfd_plan *p) {
                 if (ps.block != (int)b || f < ps.field0 || f >= ps.field0 + ps.nfield) continue;
                 const int xd = (pd[i].sd == 1 && pd[i].osd == 1) ? 1 : 0;
                 auto &v = by_class_t[std::make_pair(ps.N, xd)];
-                for (int l0 = 0; l0 < pd[i].nlines; l0 += 32)
+                for (int l0 = 0; l0 < pd[i].nlines; l0 += dense_item_lines())
                     v.push_back({pass_tab[i][0], (int)i, f - ps.field0, l0});
             }
     std::map<std::pair<int, int>, std::vector<unsigned char>> by_class;

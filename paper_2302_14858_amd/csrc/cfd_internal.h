@@ -138,6 +138,7 @@ hipError_t launch_dense_apply(const void *fn, int grid, hipStream_t st, const vo
 size_t dense_tab_bytes(int N);
 size_t dense_tab_struct_size();
 size_t dense_item_size();
+int dense_item_lines();   // lines per dense work item
 void fill_dense_tab(void *dst, int N, int nl, int m, int64_t off);
 void fill_dense_item(void *dst, int pass, int field, int line0, int tab);
 }  // namespace cfd
