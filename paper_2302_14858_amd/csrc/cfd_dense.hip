@@ -134,16 +134,19 @@ k_dense_form(const DenseTab *__restrict__ tabs, const double *__restrict__ coefs
 //
 // A workgroup takes an item of 64 lines; each of its four waves owns 16 of
 // them (one MFMA column block) and works on its own, with no workgroup
-// barrier except when the item's table differs from the one staged.
-// Per wave and item:
-//   1. its lines' inputs (prefetched into registers in the B-operand layout:
-//      lane (q, c) holds nodes 32 kb + 8 q + t of line c) go to its LDS tile F
-//      and are split into BF16 hi / lo fragments;
+// barrier except when the item's table differs from the one staged.  Two
+// workgroups share a CU, so one wave's matrix-core work overlaps another's
+// FP64 residual.  Per wave and item:
+//   1. its lines' inputs, read in the B-operand layout (lane (q, c) holds
+//      nodes 32 kb + 8 q + t of line c), go to its LDS tile F and are split
+//      into BF16 hi / lo fragments;
 //   2. yhat = D f: the 16 x 32 block of D at strip s, column block kb depends
 //      only on w = (2 kb - s) mod N/16, so the loop runs over w with the two
-//      A fragments of w (hi, lo) live and every kb it meets;
-//   3. yhat (times h^-d) into its LDS tile Y; FP64 residual per lane over a
-//      quarter of one line, r kept as BF16 in registers, then written over F;
+//      A fragments of w (hi, lo) live and meets every kb once;
+//   3. FP64 residual r = h^-d B f - A yhat in the accumulator layout (lane
+//      (q, c) holds rows 16 s + 4 q .. + 3 of line c): yhat's neighbour rows
+//      come from the lanes 16 above and below, f from F; r goes to LDS as
+//      BF16 over the part of F no later strip reads;
 //   4. y = yhat + R r with R's fragments and the same loop;
 //   5. stores straight from the accumulators.
 // ---------------------------------------------------------------------------
@@ -155,12 +158,12 @@ struct DenseItem {
 };
 
 constexpr int kDenseWaves = 4;
-constexpr int kDenseLinesW = 16;                            // lines per wave
+constexpr int kDenseLinesW = 16;                              // lines per wave
 constexpr int kDenseItemLines = kDenseWaves * kDenseLinesW;   // lines per item
 
 // LDS geometry of one line length.
-//  * per-wave tiles F and Y: 16 lines x FP floats, FP = N + 4 (FP / 4 odd:
-//    the 16 lanes of a quarter-wave reading 16 B at one node of 16 lines hit
+//  * per-wave tile F: 16 lines x FP floats, FP = N + 4 (FP / 4 odd: the 16
+//    lanes of a quarter-wave reading 16 B at one node of 16 lines hit
 //    distinct banks);
 //  * circulant tables: per term (D_hi, D_lo, R_hi) eight skewed copies
 //    E_j[x] = row[(x - j - 16) mod N], x < 2 SPD, SPD dwords apart; lane
@@ -174,8 +177,8 @@ struct DenseGeom {
     static constexpr int FP = N + 4;
     static constexpr int SPD0 = ((N + 32) / 2 + 7) / 8 * 8;
     static constexpr int SPD = (SPD0 / 8) % 2 ? SPD0 : SPD0 + 8;
-    static constexpr int TILE = 2 * kDenseLinesW * FP;                  // floats per wave (F, Y)
-    static constexpr int LDS = kDenseWaves * TILE + 3 * 8 * SPD;        // dwords
+    static constexpr int TILE = kDenseLinesW * FP;                // floats per wave
+    static constexpr int LDS = kDenseWaves * TILE + 3 * 8 * SPD;  // dwords
 };
 
 __device__ __forceinline__ bf16x8 split_hi(const float (&v)[8], bf16x8 &lo) {
@@ -189,72 +192,32 @@ __device__ __forceinline__ bf16x8 split_hi(const float (&v)[8], bf16x8 &lo) {
     return hi;
 }
 
+// Two FP32 values to packed BF16 (round to nearest even), a in the low half.
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    const __bf16 x = (__bf16)a, y = (__bf16)b;
+    return (uint32_t)__builtin_bit_cast(unsigned short, x) | ((uint32_t)__builtin_bit_cast(unsigned short, y) << 16);
+}
+
 template <int N, bool XDIR>
-__global__ void __launch_bounds__(64 * kDenseWaves)
+__global__ void __launch_bounds__(64 * kDenseWaves) __attribute__((amdgpu_waves_per_eu(2)))
 k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *__restrict__ passes,
               const DenseTab *__restrict__ tabs, const unsigned char *__restrict__ tabdata,
               const float *__restrict__ in, float *__restrict__ out) {
     using G = DenseGeom<N>;
     constexpr int NW = G::NW, NK = G::NK, FP = G::FP, SPD = G::SPD;
-    constexpr int QR = N / 4;   // residual rows per lane
     __shared__ __attribute__((aligned(16))) float smem[G::LDS];
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l = tid & 63;
     const int q = l >> 4, c = l & 15;
     float *Fw = smem + w * G::TILE;
-    float *Yw = Fw + kDenseLinesW * FP;
     unsigned short *Fb = reinterpret_cast<unsigned short *>(Fw);   // r as BF16 over F, pitch 2 FP
     unsigned short *T = reinterpret_cast<unsigned short *>(smem + kDenseWaves * G::TILE);
     const int fbase_lane = (c & 7) * 2 * SPD + 16 + 8 * q - 8 * (c >> 3);   // BF16 index, fragment 0
-
-    // input / output offset of this lane's line (lines past the last one: line0's, not stored)
-    auto line_offsets = [&](const DenseItem &wi, const PassDesc &pd, int64_t &oi, int64_t &oo, bool &live) {
-        int line = wi.line0 + w * kDenseLinesW + c;
-        live = line < pd.nlines;
-        if (!live) line = wi.line0;
-        const int lu = line % pd.nu, lv = line / pd.nu;
-        oi = (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
-        oo = (int64_t)lv * pd.osv + (int64_t)lu * pd.osu;
-    };
-    float pre[NK][8];
-    auto load_tile = [&](const DenseItem &wi) {
-        const PassDesc &pd = passes[wi.pass];
-        const float *fb = in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride;
-        int64_t oi, oo;
-        bool live;
-        line_offsets(wi, pd, oi, oo, live);
-        const float *src = fb + oi;
-        if constexpr (XDIR) {
-            const bool al = ((reinterpret_cast<uintptr_t>(fb) & 15) == 0) && ((pd.su & 3) == 0) && ((pd.sv & 3) == 0);
-            if (al) {
-#pragma unroll
-                for (int kb = 0; kb < NK; ++kb)
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const float4 v = *reinterpret_cast<const float4 *>(src + 32 * kb + 8 * q + 4 * h);
-                        pre[kb][4 * h] = v.x;
-                        pre[kb][4 * h + 1] = v.y;
-                        pre[kb][4 * h + 2] = v.z;
-                        pre[kb][4 * h + 3] = v.w;
-                    }
-            } else {
-#pragma unroll
-                for (int kb = 0; kb < NK; ++kb)
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) pre[kb][t] = src[32 * kb + 8 * q + t];
-            }
-        } else {
-            const int64_t sd = pd.sd;
-#pragma unroll
-            for (int kb = 0; kb < NK; ++kb)
-#pragma unroll
-                for (int t = 0; t < 8; ++t) pre[kb][t] = src[(int64_t)(32 * kb + 8 * q + t) * sd];
-        }
-    };
+    const int addr_dn = ((l - 16) & 63) << 2;   // ds_bpermute address of lane l - 16
+    const int addr_up = ((l + 16) & 63) << 2;   // of lane l + 16
 
     int cur_tab = -1;
-    if (blockIdx.x < nitems) load_tile(items[blockIdx.x]);
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const DenseItem wi = items[it];
         const PassDesc &pd = passes[wi.pass];
@@ -275,13 +238,49 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
             __syncthreads();
             cur_tab = wi.tab;
         }
-        const double hinv = pd.hinv[0];
-        const double *cf = reinterpret_cast<const double *>(tabdata + tb.off);
-        int64_t oi, oo;
-        bool live;
-        line_offsets(wi, pd, oi, oo, live);
+        // this lane's line (lines past the last one compute on line0 and store nothing);
+        // byte offsets within the field stay below 2^32 (checked at plan creation)
+        int line = wi.line0 + w * kDenseLinesW + c;
+        const bool live = line < pd.nlines;
+        if (!live) line = wi.line0;
+        const int lu = line % pd.nu, lv = line / pd.nu;
+        const uint32_t oi = 4u * (uint32_t)(lv * pd.sv + lu * pd.su);
+        const uint32_t oo = 4u * (uint32_t)(lv * pd.osv + lu * pd.osu);
+        const char *fb = reinterpret_cast<const char *>(in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride);
 
-        // 1. inputs to F (B layout, 16 B per write) and BF16 hi / lo fragments
+        // 1. inputs: node 32 kb + 8 q + t of line c
+        float pre[NK][8];
+        if constexpr (XDIR) {
+            const bool al = ((reinterpret_cast<uintptr_t>(fb) & 15) == 0) && ((pd.su & 3) == 0) && ((pd.sv & 3) == 0);
+            const uint32_t o0 = oi + 32u * q;
+            if (al) {
+#pragma unroll
+                for (int kb = 0; kb < NK; ++kb)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const float4 v = *reinterpret_cast<const float4 *>(fb + o0 + 128u * kb + 16u * h);
+                        pre[kb][4 * h] = v.x;
+                        pre[kb][4 * h + 1] = v.y;
+                        pre[kb][4 * h + 2] = v.z;
+                        pre[kb][4 * h + 3] = v.w;
+                    }
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < NK; ++kb)
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+                        pre[kb][t] = *reinterpret_cast<const float *>(fb + o0 + 128u * kb + 4u * t);
+            }
+        } else {
+            const uint32_t sdb = 4u * (uint32_t)pd.sd;
+            const uint32_t o0 = oi + 8u * q * sdb;
+#pragma unroll
+            for (int kb = 0; kb < NK; ++kb)
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    pre[kb][t] = *reinterpret_cast<const float *>(fb + o0 + (uint32_t)(32 * kb + t) * sdb);
+        }
+        // to F (B layout, 16 B per write) and BF16 hi / lo fragments
 #pragma unroll
         for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
@@ -291,8 +290,6 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
         bf16x8 bh[NK], bl[NK];
 #pragma unroll
         for (int kb = 0; kb < NK; ++kb) bh[kb] = split_hi(pre[kb], bl[kb]);
-        // the next item's inputs are in flight from here to its step 1
-        if (it + gridDim.x < nitems) load_tile(items[it + gridDim.x]);
 
         // 2. yhat = D_hi f_hi + D_hi f_lo + D_lo f_hi
         f32x4 acc[NW];
@@ -318,82 +315,72 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
                 acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[kb], acc[s], 0, 0, 0);
             }
         }
-        // 3. yhat = h^-d A^-1 B f into Y (C layout: lane (q, c) holds rows 16 s + 4 q + t of line c)
+        // 3. yhat = h^-d A^-1 B f; FP64 residual on rows 16 s + 4 q + t of line c
+        const double hinv = pd.hinv[0];
         const float scale = (float)hinv;
 #pragma unroll
-        for (int s = 0; s < NW; ++s) {
+        for (int s = 0; s < NW; ++s)
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[s][t] *= scale;
-            *reinterpret_cast<f32x4 *>(Yw + c * FP + 16 * s + 4 * q) = acc[s];
-        }
-        __builtin_amdgcn_wave_barrier();
-        // FP64 residual r = h^-d B f - A yhat on rows q N/4 .. q N/4 + N/4 - 1 of line c,
-        // four rows at a time: f rows i-8 .. i+11 and yhat rows i-4 .. i+7 in registers
-        uint32_t rpk[QR / 2];
         {
+            const double *cf = reinterpret_cast<const double *>(tabdata + tb.off);
             double cb[11], ca[5];
 #pragma unroll
             for (int t = 0; t < 11; ++t) cb[t] = cf[t] * hinv;
 #pragma unroll
             for (int t = 0; t < 5; ++t) ca[t] = cf[11 + t];
             const float *Fl = Fw + c * FP;
-            const float *Yl = Yw + c * FP;
-            const int i0 = q * QR;
-            auto ld4 = [&](const float *base, int row) {
-                row = (row + N) % N;
-                return *reinterpret_cast<const float4 *>(base + row);
-            };
-            double fwin[20], ywin[12];
-            {
+            uint32_t r01[2][2];   // strips 0 and 1: F rows they would overwrite are read by the last strip
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float4 v = ld4(Fl, i0 - 8 + 4 * k);
-                    fwin[4 * k] = v.x; fwin[4 * k + 1] = v.y; fwin[4 * k + 2] = v.z; fwin[4 * k + 3] = v.w;
-                }
+            for (int s = 0; s < NW; ++s) {
+                const int sm = (s + NW - 1) % NW, sp = (s + 1) % NW;
+                // yhat rows 16 s + 4 q - 2 .. + 5: two from lane l - 16 (q = 0: strip s - 1
+                // of lane q = 3), four own, two from lane l + 16 (q = 3: strip s + 1 of q = 0)
+                const float dn2 = q == 3 ? acc[sm][2] : acc[s][2];
+                const float dn3 = q == 3 ? acc[sm][3] : acc[s][3];
+                const float up0 = q == 0 ? acc[sp][0] : acc[s][0];
+                const float up1 = q == 0 ? acc[sp][1] : acc[s][1];
+                double yw[8];
+                yw[0] = (double)__builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr_dn, __builtin_bit_cast(int, dn2)));
+                yw[1] = (double)__builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr_dn, __builtin_bit_cast(int, dn3)));
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const float4 v = ld4(Yl, i0 - 4 + 4 * k);
-                    ywin[4 * k] = v.x; ywin[4 * k + 1] = v.y; ywin[4 * k + 2] = v.z; ywin[4 * k + 3] = v.w;
-                }
-            }
+                for (int t = 0; t < 4; ++t) yw[2 + t] = (double)acc[s][t];
+                yw[6] = (double)__builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr_up, __builtin_bit_cast(int, up0)));
+                yw[7] = (double)__builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr_up, __builtin_bit_cast(int, up1)));
+                // f rows 16 s + 4 q - 8 .. + 11
+                float fw[20];
 #pragma unroll
-            for (int g4 = 0; g4 < QR / 4; ++g4) {
-                const int i = i0 + 4 * g4;
-                {
-                    const float4 v = ld4(Fl, i + 8);
-                    fwin[16] = v.x; fwin[17] = v.y; fwin[18] = v.z; fwin[19] = v.w;
-                    const float4 u = ld4(Yl, i + 4);
-                    ywin[8] = u.x; ywin[9] = u.y; ywin[10] = u.z; ywin[11] = u.w;
+                for (int k = 0; k < 5; ++k) {
+                    const int row = (16 * s + 4 * q - 8 + 4 * k + N) % N;
+                    const float4 v = *reinterpret_cast<const float4 *>(Fl + row);
+                    fw[4 * k] = v.x; fw[4 * k + 1] = v.y; fw[4 * k + 2] = v.z; fw[4 * k + 3] = v.w;
                 }
                 float rr[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    // row i + t: f at window index 8 + t + m, yhat at 4 + t + m
                     double bf = 0.0, ay = 0.0;
 #pragma unroll
-                    for (int m = 0; m < 11; ++m) bf = fma(cb[m], fwin[3 + t + m], bf);
+                    for (int m = 0; m < 11; ++m) bf = fma(cb[m], (double)fw[3 + t + m], bf);
 #pragma unroll
-                    for (int m = 0; m < 5; ++m) ay = fma(ca[m], ywin[2 + t + m], ay);
-                    rr[t] = (float)(bf - ay);
+                    for (int m = 0; m < 5; ++m) ay = fma(ca[m], yw[t + m], ay);
+                    float rf = (float)(bf - ay);
+                    __asm__ volatile("" : "+v"(rf));   // keeps the f64 -> f32 -> bf16 rounding in two plain steps
+                    rr[t] = rf;
                 }
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const __bf16 lo = (__bf16)rr[2 * t], hi = (__bf16)rr[2 * t + 1];
-                    rpk[2 * g4 + t] = (uint32_t)__builtin_bit_cast(unsigned short, lo) |
-                                      ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+                const uint32_t p0 = pack_bf16(rr[0], rr[1]), p1 = pack_bf16(rr[2], rr[3]);
+                if (s < 2) {
+                    r01[s][0] = p0;
+                    r01[s][1] = p1;
+                } else {
+                    // BF16 rows 16 s + 4 q .. + 3 of line c sit over F rows 8 s + 2 q .. + 1,
+                    // which no later strip reads
+                    *reinterpret_cast<uint2 *>(Fb + c * 2 * FP + 16 * s + 4 * q) = make_uint2(p0, p1);
                 }
-#pragma unroll
-                for (int k = 0; k < 16; ++k) fwin[k] = fwin[k + 4];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) ywin[k] = ywin[k + 4];
             }
-        }
-        __builtin_amdgcn_wave_barrier();
-        // r (BF16) over F: rows q N/4 .. of line c, then read back in the B layout
 #pragma unroll
-        for (int k = 0; k < QR / 8; ++k)
-            *reinterpret_cast<uint4 *>(Fb + c * 2 * FP + q * QR + 8 * k) =
-                make_uint4(rpk[4 * k], rpk[4 * k + 1], rpk[4 * k + 2], rpk[4 * k + 3]);
+            for (int s = 0; s < 2 && s < NW; ++s)
+                *reinterpret_cast<uint2 *>(Fb + c * 2 * FP + 16 * s + 4 * q) = make_uint2(r01[s][0], r01[s][1]);
+        }
         __builtin_amdgcn_wave_barrier();
         bf16x8 rb[NK];
 #pragma unroll
@@ -411,25 +398,29 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
         }
         // 5. stores: rows 16 s + 4 q .. + 3 of line c
         if (live) {
-            float *dst = out + pd.out_base[0] + (int64_t)wi.field * pd.out_fstride + oo;
+            char *ob = reinterpret_cast<char *>(out + pd.out_base[0] + (int64_t)wi.field * pd.out_fstride);
             if constexpr (XDIR) {
+                char *dst = ob + oo + 16u * q;
                 if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
 #pragma unroll
                     for (int s = 0; s < NW; ++s)
-                        __builtin_nontemporal_store(acc[s], reinterpret_cast<f32x4 *>(dst + 16 * s + 4 * q));
+                        __builtin_nontemporal_store(acc[s], reinterpret_cast<f32x4 *>(dst + 64 * s));
                 } else {
 #pragma unroll
                     for (int s = 0; s < NW; ++s)
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) __builtin_nontemporal_store(acc[s][t], dst + 16 * s + 4 * q + t);
+                        for (int t = 0; t < 4; ++t)
+                            __builtin_nontemporal_store(acc[s][t], reinterpret_cast<float *>(dst + 64 * s + 4 * t));
                 }
             } else {
-                const int64_t osd = pd.osd;
+                const uint32_t osdb = 4u * (uint32_t)pd.osd;
+                const uint32_t o0 = oo + 4u * q * osdb;
 #pragma unroll
                 for (int s = 0; s < NW; ++s)
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
-                        __builtin_nontemporal_store(acc[s][t], dst + (int64_t)(16 * s + 4 * q + t) * osd);
+                        __builtin_nontemporal_store(acc[s][t],
+                                                    reinterpret_cast<float *>(ob + o0 + (uint32_t)(16 * s + t) * osdb));
             }
         }
         __builtin_amdgcn_wave_barrier();

@@ -576,6 +576,9 @@ cfd_status build_dense(cfd_plan *p) {
             if (status[t]) return fail(CFD_ESINGULAR, "periodic operator matrix is singular");
     }
     std::vector<PassDesc> pd = pass_descs(p, pass_tab);
+    for (const PassDesc &q : pd)   // the kernel addresses a field with 32-bit byte offsets
+        if (q.in_fstride * 4 >= (int64_t(1) << 32) || q.out_fstride * 4 >= (int64_t(1) << 32))
+            return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: a field exceeds 4 GiB");
     p->d_pass.release();
     HIPCHK(hipMalloc(&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
