@@ -30,6 +30,7 @@ constexpr int kDenseExt = 16;          // wrap-around margin of the extended cir
 //   double coefs[16]:  b_{-5..5} (interior stencil), alpha_{-2..2}
 //   bf16 mhi[N+48], mlo[N+48], rhi[N+48]: extended circulant rows,
 //       ext[kDenseExt + k] = row[k mod N] for k in [-16, N+32)
+//   uint32 mask[3]: significant 16 x 32 circulant blocks of each term (bit w)
 struct DenseTab {
     int N;
     int nl, m;     // band and RHS half-width
@@ -126,7 +127,32 @@ k_dense_form(const DenseTab *__restrict__ tabs, const double *__restrict__ coefs
         mlo[j] = (__bf16)(float)(d - (double)(float)h);
         rhi[j] = (__bf16)(float)r;
     }
-    if (threadIdx.x == 0) status[blockIdx.x] = bad;
+    // significant circulant blocks: the 16 x 32 block w of a term holds the row
+    // entries at offsets 16 w - 15 .. 16 w + 31; it is kept if one of them
+    // reaches 2^-24 of the row's largest entry (A^-1 B and A^-1 decay
+    // geometrically away from the diagonal; the FP64 residual refinement
+    // absorbs what the dropped blocks leave in yhat)
+    if (threadIdx.x == 0) {
+        double dmax = 0.0, rmax = 0.0;
+        for (int k = 0; k < N; ++k) {
+            dmax = fmax(dmax, fabs(M[k + N]));
+            rmax = fmax(rmax, fabs(M[k + 2 * N]));
+        }
+        const double thr = dmax * 0x1p-24, thr_r = rmax * 0x1p-24;
+        uint32_t mk[3] = {0u, 0u, 0u};
+        for (int w = 0; w < N / 16; ++w)
+            for (int o = -15; o <= 31; ++o) {
+                const int k = wrapN(16 * w + o, N);
+                const double d = M[k + N], r = M[k + 2 * N];
+                const double lo = d - (double)(float)(__bf16)(float)d;
+                if (fabs(d) >= thr) mk[0] |= 1u << w;
+                if (fabs(lo) >= thr) mk[1] |= 1u << w;
+                if (fabs(r) >= thr_r) mk[2] |= 1u << w;
+            }
+        uint32_t *mo = reinterpret_cast<uint32_t *>(base + 16 * sizeof(double) + 3 * (size_t)(N + 48) * 2);
+        for (int k = 0; k < 3; ++k) mo[k] = mk[k];
+        status[blockIdx.x] = bad;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -142,7 +168,8 @@ k_dense_form(const DenseTab *__restrict__ tabs, const double *__restrict__ coefs
 //      into BF16 hi / lo fragments;
 //   2. yhat = D f: the 16 x 32 block of D at strip s, column block kb depends
 //      only on w = (2 kb - s) mod N/16, so the loop runs over w with the two
-//      A fragments of w (hi, lo) live and meets every kb once;
+//      A fragments of w (hi, lo) live and meets every kb once; blocks the
+//      table marks as negligible are skipped;
 //   3. FP64 residual r = h^-d B f - A yhat in the accumulator layout (lane
 //      (q, c) holds rows 16 s + 4 q .. + 3 of line c): yhat's neighbour rows
 //      come from the lanes 16 above and below, f from F; r goes to LDS as
@@ -217,39 +244,25 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
     const int addr_dn = ((l - 16) & 63) << 2;   // ds_bpermute address of lane l - 16
     const int addr_up = ((l + 16) & 63) << 2;   // of lane l + 16
 
-    int cur_tab = -1;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const DenseItem wi = items[it];
-        const PassDesc &pd = passes[wi.pass];
-        const DenseTab tb = tabs[wi.tab];
-        // circulant tables of this item's scheme (all waves hold the same item)
-        if (wi.tab != cur_tab) {
-            __syncthreads();   // every wave is done with the previous table
-            const unsigned short *rows = reinterpret_cast<const unsigned short *>(tabdata + tb.off + 16 * sizeof(double));
-            for (int e = tid; e < 3 * 8 * 2 * SPD; e += 64 * kDenseWaves) {
-                const int term = e / (16 * SPD);
-                const int rem = e - term * 16 * SPD;
-                const int j = rem / (2 * SPD);
-                const int x = rem - j * 2 * SPD;
-                int k = (x - j - 16) % N;
-                if (k < 0) k += N;
-                T[e] = rows[term * (N + 48) + kDenseExt + k];
-            }
-            __syncthreads();
-            cur_tab = wi.tab;
-        }
-        // this lane's line (lines past the last one compute on line0 and store nothing);
-        // byte offsets within the field stay below 2^32 (checked at plan creation)
+    // this lane's line of an item (lines past the last one compute on line0 and
+    // store nothing); byte offsets within the field stay below 2^32 (checked at
+    // plan creation)
+    auto line_of = [&](const DenseItem &wi, const PassDesc &pd, uint32_t &oi, uint32_t &oo) {
         int line = wi.line0 + w * kDenseLinesW + c;
         const bool live = line < pd.nlines;
         if (!live) line = wi.line0;
         const int lu = line % pd.nu, lv = line / pd.nu;
-        const uint32_t oi = 4u * (uint32_t)(lv * pd.sv + lu * pd.su);
-        const uint32_t oo = 4u * (uint32_t)(lv * pd.osv + lu * pd.osu);
+        oi = 4u * (uint32_t)(lv * pd.sv + lu * pd.su);
+        oo = 4u * (uint32_t)(lv * pd.osv + lu * pd.osu);
+        return live;
+    };
+    // an item's inputs: node 32 kb + 8 q + t of line c
+    float pre[NK][8];
+    auto load_item = [&](const DenseItem &wi) {
+        const PassDesc &pd = passes[wi.pass];
+        uint32_t oi, oo;
+        (void)line_of(wi, pd, oi, oo);
         const char *fb = reinterpret_cast<const char *>(in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride);
-
-        // 1. inputs: node 32 kb + 8 q + t of line c
-        float pre[NK][8];
         if constexpr (XDIR) {
             const bool al = ((reinterpret_cast<uintptr_t>(fb) & 15) == 0) && ((pd.su & 3) == 0) && ((pd.sv & 3) == 0);
             const uint32_t o0 = oi + 32u * q;
@@ -280,6 +293,34 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
                 for (int t = 0; t < 8; ++t)
                     pre[kb][t] = *reinterpret_cast<const float *>(fb + o0 + (uint32_t)(32 * kb + t) * sdb);
         }
+    };
+
+    int cur_tab = -1;
+    if (blockIdx.x < nitems) load_item(items[blockIdx.x]);
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const DenseItem wi = items[it];
+        const PassDesc &pd = passes[wi.pass];
+        const DenseTab tb = tabs[wi.tab];
+        // circulant tables of this item's scheme (all waves hold the same item)
+        if (wi.tab != cur_tab) {
+            __syncthreads();   // every wave is done with the previous table
+            const unsigned short *rows = reinterpret_cast<const unsigned short *>(tabdata + tb.off + 16 * sizeof(double));
+            for (int e = tid; e < 3 * 8 * 2 * SPD; e += 64 * kDenseWaves) {
+                const int term = e / (16 * SPD);
+                const int rem = e - term * 16 * SPD;
+                const int j = rem / (2 * SPD);
+                const int x = rem - j * 2 * SPD;
+                int k = (x - j - 16) % N;
+                if (k < 0) k += N;
+                T[e] = rows[term * (N + 48) + kDenseExt + k];
+            }
+            __syncthreads();
+            cur_tab = wi.tab;
+        }
+        uint32_t oi, oo;
+        const bool live = line_of(wi, pd, oi, oo);
+
+        // 1. the prefetched inputs
         // to F (B layout, 16 B per write) and BF16 hi / lo fragments
 #pragma unroll
         for (int kb = 0; kb < NK; ++kb)
@@ -290,29 +331,38 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
         bf16x8 bh[NK], bl[NK];
 #pragma unroll
         for (int kb = 0; kb < NK; ++kb) bh[kb] = split_hi(pre[kb], bl[kb]);
+        // the next item's inputs are in flight from here to its step 1
+        if (it + gridDim.x < nitems) load_item(items[it + gridDim.x]);
 
-        // 2. yhat = D_hi f_hi + D_hi f_lo + D_lo f_hi
+        // 2. yhat = D_hi f_hi + D_hi f_lo + D_lo f_hi over the significant blocks
+        const uint32_t *mask = reinterpret_cast<const uint32_t *>(tabdata + tb.off + 16 * sizeof(double) +
+                                                                  3 * (size_t)(N + 48) * 2);
+        const uint32_t m_hi = mask[0], m_lo = mask[1], m_r = mask[2];
         f32x4 acc[NW];
 #pragma unroll
         for (int s = 0; s < NW; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int wb = 0; wb < NW; ++wb) {
-            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(T + fbase_lane + 16 * wb);
-            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(T + 16 * SPD + fbase_lane + 16 * wb);
+            if (m_hi & (1u << wb)) {
+                const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(T + fbase_lane + 16 * wb);
 #pragma unroll
-            for (int kb = 0; kb < NK; ++kb) {
-                const int s = (2 * kb - wb + NW) % NW;
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[kb], acc[s], 0, 0, 0);
+                for (int kb = 0; kb < NK; ++kb) {
+                    const int s = (2 * kb - wb + NW) % NW;
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[kb], acc[s], 0, 0, 0);
+                }
+#pragma unroll
+                for (int kb = 0; kb < NK; ++kb) {
+                    const int s = (2 * kb - wb + NW) % NW;
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[kb], acc[s], 0, 0, 0);
+                }
             }
+            if (m_lo & (1u << wb)) {
+                const bf16x8 al = *reinterpret_cast<const bf16x8 *>(T + 16 * SPD + fbase_lane + 16 * wb);
 #pragma unroll
-            for (int kb = 0; kb < NK; ++kb) {
-                const int s = (2 * kb - wb + NW) % NW;
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[kb], acc[s], 0, 0, 0);
-            }
-#pragma unroll
-            for (int kb = 0; kb < NK; ++kb) {
-                const int s = (2 * kb - wb + NW) % NW;
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[kb], acc[s], 0, 0, 0);
+                for (int kb = 0; kb < NK; ++kb) {
+                    const int s = (2 * kb - wb + NW) % NW;
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[kb], acc[s], 0, 0, 0);
+                }
             }
         }
         // 3. yhat = h^-d A^-1 B f; FP64 residual on rows 16 s + 4 q + t of line c
@@ -329,7 +379,7 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
             for (int t = 0; t < 11; ++t) cb[t] = cf[t] * hinv;
 #pragma unroll
             for (int t = 0; t < 5; ++t) ca[t] = cf[11 + t];
-            const float *Fl = Fw + c * FP;
+            const f32x4 *Fl4 = reinterpret_cast<const f32x4 *>(Fw + c * FP);   // 16-byte reads (FP % 4 == 0)
             uint32_t r01[2][2];   // strips 0 and 1: F rows they would overwrite are read by the last strip
 #pragma unroll
             for (int s = 0; s < NW; ++s) {
@@ -351,9 +401,10 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
                 float fw[20];
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    const int row = (16 * s + 4 * q - 8 + 4 * k + N) % N;
-                    const float4 v = *reinterpret_cast<const float4 *>(Fl + row);
-                    fw[4 * k] = v.x; fw[4 * k + 1] = v.y; fw[4 * k + 2] = v.z; fw[4 * k + 3] = v.w;
+                    f32x4 v = Fl4[((16 * s + 4 * q - 8 + 4 * k + N) % N) >> 2];
+                    if (k == 0 || k == 4) __asm__ volatile("" : "+v"(v));   // one 16-byte read, not a narrowed one
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) fw[4 * k + e] = v[e];
                 }
                 float rr[4];
 #pragma unroll
@@ -389,11 +440,13 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
         // 4. y = yhat + R r (R = A^-1 in one BF16 term)
 #pragma unroll
         for (int wb = 0; wb < NW; ++wb) {
-            const bf16x8 ar = *reinterpret_cast<const bf16x8 *>(T + 32 * SPD + fbase_lane + 16 * wb);
+            if (m_r & (1u << wb)) {
+                const bf16x8 ar = *reinterpret_cast<const bf16x8 *>(T + 32 * SPD + fbase_lane + 16 * wb);
 #pragma unroll
-            for (int kb = 0; kb < NK; ++kb) {
-                const int s = (2 * kb - wb + NW) % NW;
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, rb[kb], acc[s], 0, 0, 0);
+                for (int kb = 0; kb < NK; ++kb) {
+                    const int s = (2 * kb - wb + NW) % NW;
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, rb[kb], acc[s], 0, 0, 0);
+                }
             }
         }
         // 5. stores: rows 16 s + 4 q .. + 3 of line c
@@ -462,7 +515,7 @@ hipError_t launch_dense_apply(const void *fn, int grid, hipStream_t st, const vo
     return hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, st);
 }
 
-size_t dense_tab_bytes(int N) { return 16 * sizeof(double) + 3 * (size_t)(N + 48) * 2; }
+size_t dense_tab_bytes(int N) { return 16 * sizeof(double) + 3 * (size_t)(N + 48) * 2 + 4 * sizeof(uint32_t); }
 size_t dense_tab_struct_size() { return sizeof(DenseTab); }
 size_t dense_item_size() { return sizeof(DenseItem); }
 int dense_item_lines() { return kDenseItemLines; }
