@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "cfd_internal.h"
 
@@ -296,7 +297,6 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
     };
 
     int cur_tab = -1;
-    if (blockIdx.x < nitems) load_item(items[blockIdx.x]);
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const DenseItem wi = items[it];
         const PassDesc &pd = passes[wi.pass];
@@ -320,7 +320,8 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
         uint32_t oi, oo;
         const bool live = line_of(wi, pd, oi, oo);
 
-        // 1. the prefetched inputs
+        // 1. inputs (the other workgroup on the CU covers their latency)
+        load_item(wi);
         // to F (B layout, 16 B per write) and BF16 hi / lo fragments
 #pragma unroll
         for (int kb = 0; kb < NK; ++kb)
@@ -331,8 +332,6 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
         bf16x8 bh[NK], bl[NK];
 #pragma unroll
         for (int kb = 0; kb < NK; ++kb) bh[kb] = split_hi(pre[kb], bl[kb]);
-        // the next item's inputs are in flight from here to its step 1
-        if (it + gridDim.x < nitems) load_item(items[it + gridDim.x]);
 
         // 2. yhat = D_hi f_hi + D_hi f_lo + D_lo f_hi over the significant blocks
         const uint32_t *mask = reinterpret_cast<const uint32_t *>(tabdata + tb.off + 16 * sizeof(double) +
@@ -372,11 +371,16 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
         for (int s = 0; s < NW; ++s)
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[s][t] *= scale;
-        {
+        // one strip loop per RHS half-width bound (3 covers the interior schemes
+        // of Sec. 2: fewer FMAs and LDS reads; 5 any stencil the tables hold)
+        auto residual = [&](auto mr_c) {
+            constexpr int MR = decltype(mr_c)::value;
+            constexpr int NCH = MR <= 3 ? 3 : 5;   // 4-row chunks of f per strip
+            constexpr int C0 = 4 * (NCH / 2);      // rows of f before the strip's first row
             const double *cf = reinterpret_cast<const double *>(tabdata + tb.off);
-            double cb[11], ca[5];
+            double cb[2 * MR + 1], ca[5];
 #pragma unroll
-            for (int t = 0; t < 11; ++t) cb[t] = cf[t] * hinv;
+            for (int t = 0; t < 2 * MR + 1; ++t) cb[t] = cf[5 - MR + t] * hinv;
 #pragma unroll
             for (int t = 0; t < 5; ++t) ca[t] = cf[11 + t];
             const f32x4 *Fl4 = reinterpret_cast<const f32x4 *>(Fw + c * FP);   // 16-byte reads (FP % 4 == 0)
@@ -397,12 +401,12 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
                 for (int t = 0; t < 4; ++t) yw[2 + t] = (double)acc[s][t];
                 yw[6] = (double)__builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr_up, __builtin_bit_cast(int, up0)));
                 yw[7] = (double)__builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr_up, __builtin_bit_cast(int, up1)));
-                // f rows 16 s + 4 q - 8 .. + 11
-                float fw[20];
+                // f rows 16 s + 4 q - C0 .. 16 s + 4 q - C0 + 4 NCH - 1
+                float fw[4 * NCH];
 #pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    f32x4 v = Fl4[((16 * s + 4 * q - 8 + 4 * k + N) % N) >> 2];
-                    if (k == 0 || k == 4) __asm__ volatile("" : "+v"(v));   // one 16-byte read, not a narrowed one
+                for (int k = 0; k < NCH; ++k) {
+                    f32x4 v = Fl4[((16 * s + 4 * q - C0 + 4 * k + N) % N) >> 2];
+                    if (k == 0 || k == NCH - 1) __asm__ volatile("" : "+v"(v));   // one 16-byte read, not a narrowed one
 #pragma unroll
                     for (int e = 0; e < 4; ++e) fw[4 * k + e] = v[e];
                 }
@@ -411,7 +415,7 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
                 for (int t = 0; t < 4; ++t) {
                     double bf = 0.0, ay = 0.0;
 #pragma unroll
-                    for (int m = 0; m < 11; ++m) bf = fma(cb[m], (double)fw[3 + t + m], bf);
+                    for (int m = 0; m < 2 * MR + 1; ++m) bf = fma(cb[m], (double)fw[C0 - MR + t + m], bf);
 #pragma unroll
                     for (int m = 0; m < 5; ++m) ay = fma(ca[m], yw[t + m], ay);
                     float rf = (float)(bf - ay);
@@ -431,7 +435,11 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
 #pragma unroll
             for (int s = 0; s < 2 && s < NW; ++s)
                 *reinterpret_cast<uint2 *>(Fb + c * 2 * FP + 16 * s + 4 * q) = make_uint2(r01[s][0], r01[s][1]);
-        }
+        };
+        if (tb.m <= 3)
+            residual(std::integral_constant<int, 3>{});
+        else
+            residual(std::integral_constant<int, 5>{});
         __builtin_amdgcn_wave_barrier();
         bf16x8 rb[NK];
 #pragma unroll
