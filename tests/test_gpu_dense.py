@@ -79,3 +79,14 @@ def test_dense_agrees_with_fp32_banded(cuda):
     gf = H.gpu_run(H.make_plan(wl, ops, dtype=1), wl, ops, dtype=1)
     for o in range(3):
         assert H.rel_err(gm[0][o][0], gf[0][o][0]) <= 2 * H.ERR_F32
+
+
+@pytest.mark.parametrize("scheme,d", [("(1)E5", 0), ("(2)E4", 2)])
+def test_dense_wide_explicit_stencil(cuda, scheme, d):
+    """RHS half-width above 3 (explicit schemes, A = I): the residual's general stencil path."""
+    wl = synth.periodic_box(n=(64, 32, 96), nfields=2, kmax=12)
+    ops = [(scheme, d)]
+    plan = H.make_plan(wl, ops, dtype=MIXED)
+    g = H.gpu_run(plan, wl, ops, dtype=MIXED)
+    o = H.oracle_run(wl, ops)
+    assert H.max_rel_err(g, o) <= H.ERR_F32
