@@ -15,7 +15,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <type_traits>
 
 #include "cfd_internal.h"
 
@@ -226,7 +225,7 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
     return (uint32_t)__builtin_bit_cast(unsigned short, x) | ((uint32_t)__builtin_bit_cast(unsigned short, y) << 16);
 }
 
-template <int N, bool XDIR>
+template <int N, bool XDIR, int MR>
 __global__ void __launch_bounds__(64 * kDenseWaves) __attribute__((amdgpu_waves_per_eu(2)))
 k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *__restrict__ passes,
               const DenseTab *__restrict__ tabs, const unsigned char *__restrict__ tabdata,
@@ -320,7 +319,8 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
         uint32_t oi, oo;
         const bool live = line_of(wi, pd, oi, oo);
 
-        // 1. inputs (the other workgroup on the CU covers their latency)
+        // 1. inputs (the other workgroup on the CU covers their latency; a
+        //    prefetch one item ahead measured slower)
         load_item(wi);
         // to F (B layout, 16 B per write) and BF16 hi / lo fragments
 #pragma unroll
@@ -371,10 +371,10 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
         for (int s = 0; s < NW; ++s)
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[s][t] *= scale;
-        // one strip loop per RHS half-width bound (3 covers the interior schemes
-        // of Sec. 2: fewer FMAs and LDS reads; 5 any stencil the tables hold)
-        auto residual = [&](auto mr_c) {
-            constexpr int MR = decltype(mr_c)::value;
+        // the strip loop for RHS half-width up to MR (3 covers the interior
+        // schemes of Sec. 2 with fewer FMAs and LDS reads; 5 any stencil the
+        // tables hold)
+        {
             constexpr int NCH = MR <= 3 ? 3 : 5;   // 4-row chunks of f per strip
             constexpr int C0 = 4 * (NCH / 2);      // rows of f before the strip's first row
             const double *cf = reinterpret_cast<const double *>(tabdata + tb.off);
@@ -435,11 +435,7 @@ k_dense_apply(const DenseItem *__restrict__ items, int nitems, const PassDesc *_
 #pragma unroll
             for (int s = 0; s < 2 && s < NW; ++s)
                 *reinterpret_cast<uint2 *>(Fb + c * 2 * FP + 16 * s + 4 * q) = make_uint2(r01[s][0], r01[s][1]);
-        };
-        if (tb.m <= 3)
-            residual(std::integral_constant<int, 3>{});
-        else
-            residual(std::integral_constant<int, 5>{});
+        }
         __builtin_amdgcn_wave_barrier();
         bf16x8 rb[NK];
 #pragma unroll
@@ -496,16 +492,23 @@ hipError_t launch_dense_form(int ntab, const void *tabs, const double *coefs, un
     return hipGetLastError();
 }
 
-template <int N, bool XDIR>
+template <int N, bool XDIR, int MR>
 static const void *dense_fn() {
-    return reinterpret_cast<const void *>(&k_dense_apply<N, XDIR>);
+    return reinterpret_cast<const void *>(&k_dense_apply<N, XDIR, MR>);
 }
 
-// Kernel of one (line length, x or not) class; nullptr for an unsupported N.
-const void *dense_apply_fn(int N, bool xdir) {
+template <int N>
+static const void *dense_fn(bool xdir, bool wide) {
+    if (wide) return xdir ? dense_fn<N, true, 5>() : dense_fn<N, false, 5>();
+    return xdir ? dense_fn<N, true, 3>() : dense_fn<N, false, 3>();
+}
+
+// Kernel of one (line length, x or not, RHS half-width above 3 or not) class;
+// nullptr for an unsupported N.
+const void *dense_apply_fn(int N, bool xdir, bool wide) {
     switch (N) {
 #define CFD_DENSE_N(n) \
-    case n: return xdir ? dense_fn<n, true>() : dense_fn<n, false>();
+    case n: return dense_fn<n>(xdir, wide);
         CFD_DENSE_N(32) CFD_DENSE_N(64) CFD_DENSE_N(96) CFD_DENSE_N(128)
         CFD_DENSE_N(160) CFD_DENSE_N(192) CFD_DENSE_N(224) CFD_DENSE_N(256)
 #undef CFD_DENSE_N

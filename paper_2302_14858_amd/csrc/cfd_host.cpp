@@ -585,7 +585,7 @@ cfd_status build_dense(cfd_plan *p) {
     // work items: dense_item_lines() lines of one pass and field; one group
     // (kernel) per (N, x or not).  Items of one table are kept together: a
     // workgroup stages the table's circulant blocks in LDS once for them
-    std::map<std::pair<int, int>, std::vector<std::array<int, 4>>> by_class_t;   // (tab, pass, field, line0)
+    std::map<std::array<int, 3>, std::vector<std::array<int, 4>>> by_class_t;   // (tab, pass, field, line0)
     const size_t isz = dense_item_size();
     for (size_t b = 0; b < p->blocks.size(); ++b)
         for (int f = 0; f < p->nfields; ++f)
@@ -593,11 +593,12 @@ cfd_status build_dense(cfd_plan *p) {
                 const PassHost &ps = p->passes[i];
                 if (ps.block != (int)b || f < ps.field0 || f >= ps.field0 + ps.nfield) continue;
                 const int xd = (pd[i].sd == 1 && pd[i].osd == 1) ? 1 : 0;
-                auto &v = by_class_t[std::make_pair(ps.N, xd)];
+                const int wide = p->schemes[ps.sch[0]].m > 3 ? 1 : 0;
+                auto &v = by_class_t[{ps.N, xd, wide}];
                 for (int l0 = 0; l0 < pd[i].nlines; l0 += dense_item_lines())
                     v.push_back({pass_tab[i][0], (int)i, f - ps.field0, l0});
             }
-    std::map<std::pair<int, int>, std::vector<unsigned char>> by_class;
+    std::map<std::array<int, 3>, std::vector<unsigned char>> by_class;
     for (auto &kv : by_class_t) {
         std::stable_sort(kv.second.begin(), kv.second.end(),
                          [](const std::array<int, 4> &x, const std::array<int, 4> &y) { return x[0] < y[0]; });
@@ -612,7 +613,7 @@ cfd_status build_dense(cfd_plan *p) {
     p->groups.clear();
     for (auto &kv : by_class) {
         Group g;
-        g.fn = dense_apply_fn(kv.first.first, kv.first.second != 0);
+        g.fn = dense_apply_fn(kv.first[0], kv.first[1] != 0, kv.first[2] != 0);
         if (!g.fn) return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: unsupported line length");
         g.lds = 0;
         g.item0 = (int64_t)(items.size() / isz);

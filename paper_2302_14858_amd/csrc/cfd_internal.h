@@ -131,7 +131,7 @@ hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *sta
 namespace cfd {
 hipError_t launch_dense_form(int ntab, const void *tabs, const double *coefs, unsigned char *out, double *scratch,
                              int64_t scratch_per, int *status, hipStream_t st);
-const void *dense_apply_fn(int N, bool xdir);   // nullptr: unsupported line length
+const void *dense_apply_fn(int N, bool xdir, bool wide);   // wide: RHS half-width > 3; nullptr: unsupported N
 hipError_t launch_dense_apply(const void *fn, int grid, hipStream_t st, const void *items, int nitems,
                               const PassDesc *passes, const void *tabs, const unsigned char *tabdata, const float *in,
                               float *out);
