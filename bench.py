@@ -195,45 +195,58 @@ def extra_periodic256(steps, warmup, autotune):
 
 
 def extra_wave192(nsteps=200):
-    """RK4 of the first-order wave system on a periodic 192^3 grid, k = (3,5,7), dt = h/4."""
+    """RK4 of the first-order wave system on a periodic 192^3 grid, k = (3,5,7), dt = h/4.
+
+    Two discretisations of the same domain: one periodic 192^3 block (cyclic lines), and a 4 x 4 x 4
+    lattice of 48^3 blocks with N_g = 4, matched closures and a device ghost exchange every stage."""
     import torch
     import synth
     import paper_2302_14858_amd as P
     from paper_2302_14858_amd.wave import WaveRK4
     n = 192
-    wl = synth.wave192(n=n)
-    h = wl.blocks[0].h[0]
-    dt = 0.25 * h
     k = np.array(synth.WAVE_K, dtype=np.float64)
     w = float(np.sqrt(np.sum(k * k)))
-    T = nsteps * dt
-    xs = np.arange(n) * h
-    ex = [np.exp(-1j * k[a] * xs) for a in range(3)]
-    exact = synth.wave_state(xs, xs, xs, T)[0]
-    out = {"workload": f"wave192: periodic 192^3, plane wave k=(3,5,7), dt=h/4, {nsteps} RK4 steps, (1)Q1_3[1]"}
-    for label, dt_code in (("f64", P.CFD_F64), ("f32", P.CFD_F32)):
-        blocks = [dict(n=b.n, ng=b.ng, h=b.h, boundary=b.boundary) for b in wl.blocks]
-        rk = WaveRK4(blocks, P.Scheme.named("(1)Q1_3[1]"), dt, dtype=dt_code)
-        rk.load(wl.data)
-        rk.capture()
-        rk.load(wl.data)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        rk.run(nsteps)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / nsteps
-        phi = rk.u[: n ** 3].double().cpu().numpy().reshape(n, n, n)
-        F = np.einsum("zyx,x,y,z->", phi, ex[0], ex[1], ex[2]) / n ** 3
-        F_exact = np.exp(-1j * w * T) / 2j
-        dphase = float(np.angle(F / F_exact))
-        l2 = float(np.sqrt(np.mean((phi - exact) ** 2)) / np.sqrt(np.mean(exact ** 2)))
-        out[label] = {"ms_per_step": ms, "evals_per_s": 6 * 4 * n ** 3 / (ms * 1e-3), "l2_rel_err_vs_exact": l2,
-                      "phase_err_rad": abs(dphase), "T": T}
-        del rk
-        torch.cuda.empty_cache()
+    out = {"workload": f"wave192: periodic 192^3, plane wave k=(3,5,7), dt=h/4, {nsteps} RK4 steps, (1)Q1_3[1]; "
+                       "'f64'/'f32': one periodic block; 'blocks_*': 64 blocks of 48^3, ng=4, closures + halo exchange"}
+    for variant, bpd in (("", 1), ("blocks_", 4)):
+        wl = synth.wave192(n=n, blocks_per_dim=bpd, ng=4)
+        h = wl.blocks[0].h[0]
+        dt = 0.25 * h
+        T = nsteps * dt
+        xs = np.arange(n) * h
+        ex = [np.exp(-1j * k[a] * xs) for a in range(3)]
+        exact = synth.wave_state(xs, xs, xs, T)[0]
+        for label, dt_code in (("f64", P.CFD_F64), ("f32", P.CFD_F32)):
+            blocks = [dict(n=b.n, ng=b.ng, h=b.h, boundary=b.boundary) for b in wl.blocks]
+            rk = WaveRK4(blocks, P.Scheme.named("(1)Q1_3[1]"), dt, dtype=dt_code,
+                         lattice=(bpd,) * 3 if bpd > 1 else None)
+            rk.load(wl.data)
+            rk.capture()
+            rk.load(wl.data)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rk.run(nsteps)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / nsteps
+            if bpd == 1:
+                phi = rk.u[: n ** 3].double().cpu().numpy().reshape(n, n, n)
+            else:
+                nb, ng = n // bpd, 4
+                m = nb + 2 * ng
+                u = rk.u.double().cpu().numpy().reshape(bpd, bpd, bpd, 5, m, m, m)[:, :, :, 0, ng:ng + nb, ng:ng + nb,
+                                                                                  ng:ng + nb]
+                phi = u.transpose(0, 3, 1, 4, 2, 5).reshape(n, n, n)   # (kz, z, ky, y, kx, x)
+            F = np.einsum("zyx,x,y,z->", phi, ex[0], ex[1], ex[2]) / n ** 3
+            F_exact = np.exp(-1j * w * T) / 2j
+            dphase = float(np.angle(F / F_exact))
+            l2 = float(np.sqrt(np.mean((phi - exact) ** 2)) / np.sqrt(np.mean(exact ** 2)))
+            out[variant + label] = {"ms_per_step": ms, "evals_per_s": 6 * 4 * n ** 3 / (ms * 1e-3),
+                                    "l2_rel_err_vs_exact": l2, "phase_err_rad": abs(dphase), "T": T}
+            del rk
+            torch.cuda.empty_cache()
     return out
 
 
