@@ -90,3 +90,15 @@ def test_dense_wide_explicit_stencil(cuda, scheme, d):
     g = H.gpu_run(plan, wl, ops, dtype=MIXED)
     o = H.oracle_run(wl, ops)
     assert H.max_rel_err(g, o) <= H.ERR_F32
+
+
+def test_dense_several_tables_in_one_launch(cuda):
+    """y and z lines of three schemes share one kernel class: workgroups re-stage the circulant
+    tables whenever the item's table changes (persistent and one-workgroup-per-item grids)."""
+    wl = synth.periodic_box(n=(24, 64, 64), nfields=2, kmax=12)
+    ops = [("(1)Q1_3[1]", 1), ("(2)Q1_3[1]", 2), ("(1)QP_O8[1]", 2), ("(2)QP_O8[1]", 1)]
+    plan = H.make_plan(wl, ops, dtype=MIXED)
+    o = H.oracle_run(wl, ops)
+    for pers in (True, False):
+        plan.set_schedule(persistent=pers)
+        assert H.max_rel_err(H.gpu_run(plan, wl, ops, dtype=MIXED), o) <= H.ERR_F32
