@@ -162,6 +162,14 @@ size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }   // F32 and MIXE
 
 constexpr int kXCDq = 8;   // queues of the XCD-aware schedule (one per XCD)
 
+// Exchange-area bytes an item needs: partition coupling (P > 1) or the
+// periodic wrap; none for a single-partition closure line.  Same layout as
+// the kernel's (4/P line groups x operators x 64 lanes x (2 nl P | 1)).
+size_t exch_bytes(int nl, int nops, int P, bool periodic, size_t es) {
+    if (nl <= 0 || (P <= 1 && !periodic)) return 0;
+    return (size_t)(4 / P) * nops * kWave * (size_t)((2 * nl * P) | 1) * es;
+}
+
 // Tile bytes an x item with P partitions of L rows needs in LDS: 64 (4/P)
 // lines by the columns of one chunk (P/C partitions plus the halo).
 size_t x_tile_bytes(int P, int L, int hw, size_t es, int C = 1) {
@@ -217,7 +225,7 @@ std::vector<int> candidate_Ps(const PassHost &ps, bool f32, size_t max_lds) {
         const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L);
         if (!k) continue;
         if (ps.periodic && k->hw > ps.N) continue;
-        size_t lds = (size_t)k->exch * es;
+        size_t lds = exch_bytes(ps.nl, ps.nops, P, ps.periodic, es);
         if (ps.dir == 0) lds += x_tile_bytes(P, L, k->hw, es, chunked(k) ? x_chunks(P, L, k->hw, es, lds) : 1);
         if (lds > max_lds) continue;
         ok.push_back(P);
@@ -304,7 +312,9 @@ cfd_status build_groups(cfd_plan *p) {
         for (int j = 0; j < ps.cls->nL; ++j)
             if (ps.cls->Ls[j] == ps.L) ps.lcode = j;
         const size_t es1 = f32 ? 4 : 8;
-        ps.C = (ps.dir == 0 && chunked(ps.cls)) ? x_chunks(ps.P, ps.L, ps.cls->hw, es1, (size_t)ps.cls->exch * es1) : 1;
+        ps.C = (ps.dir == 0 && chunked(ps.cls))
+                   ? x_chunks(ps.P, ps.L, ps.cls->hw, es1, exch_bytes(ps.nl, ps.nops, ps.P, ps.periodic, es1))
+                   : 1;
     }
     // 2. tables
     std::map<TabKey, int> tabidx;
@@ -394,9 +404,12 @@ cfd_status build_groups(cfd_plan *p) {
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
 
     // 4. work items.  One launch group per kernel class (x lines optionally in
-    //    a group of their own); within a group the items of one block-field
-    //    are adjacent (x, y, z passes together) so its input is re-read from
-    //    cache rather than HBM.
+    //    a group of their own; with concurrent launches, y/z items that need
+    //    no LDS also in a group of their own, whose workgroups then fit on CUs
+    //    whose LDS the x launch fills); within a group the items of one
+    //    block-field are adjacent (x, y, z passes together) so its input is
+    //    re-read from cache rather than HBM.  A group's LDS is the most any of
+    //    its items needs.
     const size_t es = f32 ? 4 : 8;
     std::map<std::pair<const void *, int>, int> gidx;
     std::vector<std::vector<WorkItem>> gitems;
@@ -410,7 +423,11 @@ cfd_status build_groups(cfd_plan *p) {
             for (int i : by_block[b]) {
                 const PassHost &ps = p->passes[i];
                 if (f < ps.field0 || f >= ps.field0 + ps.nfield) continue;
-                const int sub = (p->split_x && ps.dir == 0) ? 1 : 0;
+                size_t lds = exch_bytes(ps.nl, ps.nops, ps.P, ps.periodic, es);
+                if (ps.dir == 0) lds += x_tile_bytes(ps.P, ps.L, ps.cls->hw, es, ps.C);
+                int sub = 0;
+                if (p->split_x && ps.dir == 0) sub = 1;
+                else if (p->split_x && p->concurrent && lds == 0) sub = 2;
                 auto key = std::make_pair(ps.cls->fn, sub);
                 auto it = gidx.find(key);
                 int gi;
@@ -419,7 +436,7 @@ cfd_status build_groups(cfd_plan *p) {
                     gidx[key] = gi;
                     Group g;
                     g.fn = ps.cls->fn;
-                    g.lds = (size_t)ps.cls->exch * es;
+                    g.lds = 0;
                     groups.push_back(g);
                     gitems.emplace_back();
                     gbf.emplace_back();
@@ -427,9 +444,7 @@ cfd_status build_groups(cfd_plan *p) {
                 } else {
                     gi = it->second;
                 }
-                if (ps.dir == 0)
-                    groups[gi].lds = std::max(groups[gi].lds, (size_t)ps.cls->exch * es +
-                                                                  x_tile_bytes(ps.P, ps.L, ps.cls->hw, es, ps.C));
+                groups[gi].lds = std::max(groups[gi].lds, lds);
                 const int per_item = kWave * (4 / ps.P);
                 const int meta = ps.P | (ps.lcode << 4) | ((ps.C - 1) << 8);
                 for (int l0 = 0; l0 < pd[i].nlines; l0 += per_item) {
@@ -1104,21 +1119,28 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // a candidate's time: the best of three runs of 10 applies after 3 warm-up
+    // applies (single runs vary by several percent between candidates that
+    // differ by less)
     auto time_apply = [&](float &ms) -> cfd_status {
-        for (int w = 0; w < 2; ++w) {
+        for (int w = 0; w < 3; ++w) {
             cfd_status s = enqueue(p, in_dev, out_dev, st);
             if (s != CFD_OK) return s;
         }
         const int reps = 10;
-        HIPCHK(hipEventRecord(e0, st));
-        for (int r = 0; r < reps; ++r) {
-            cfd_status s = enqueue(p, in_dev, out_dev, st);
-            if (s != CFD_OK) return s;
+        ms = 1e30f;
+        for (int trial = 0; trial < 3; ++trial) {
+            HIPCHK(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) {
+                cfd_status s = enqueue(p, in_dev, out_dev, st);
+                if (s != CFD_OK) return s;
+            }
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t / reps);
         }
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        ms /= reps;
         return CFD_OK;
     };
     // launch shape: persistent grid, XCD-aware queues or per-item grid (plain

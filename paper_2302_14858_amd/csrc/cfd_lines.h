@@ -55,6 +55,14 @@ __host__ __device__ constexpr int exch_elems() {
     return NL > 0 ? best : 0;
 }
 
+// Exchange elements an item with P partitions uses: partition coupling or the
+// periodic wrap (a single-partition closure line uses none).  The x tile
+// starts right after them.
+template <int NL, int NOPS>
+__device__ __forceinline__ int exch_elems_for(int P, bool periodic) {
+    return (NL > 0 && (P > 1 || periodic)) ? (kWGW / P) * NOPS * 64 * ((2 * NL * P) | 1) : 0;
+}
+
 // Derivatives are written once and not read again by this launch: streaming
 // (non-temporal) stores keep them from evicting the input lines that the other
 // directions' passes over the same block-field re-read from L2.
@@ -458,7 +466,7 @@ constexpr int max_L() {
 // Persistent line kernel: every workgroup walks the work list with a grid
 // stride.  Work item meta: P in bits 0..3, index of L in the compiled set in
 // bits 4..7, x lines: column chunks - 1 in bits 8..9.  Dynamic LDS: exchange
-// area, then the x tile (one column chunk).
+// area (as much as the item uses), then the x tile (one column chunk).
 template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int... Ls>
 __global__ void __launch_bounds__(64 * kWGW)
 k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ qoff,
@@ -466,7 +474,6 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
         const T *__restrict__ in, T *__restrict__ out) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *exch = reinterpret_cast<T *>(smem_raw);
-    T *tile = exch + exch_elems<NL, NOPS>();
     constexpr int kLs[] = {Ls...};
     constexpr bool kChunked = max_L<Ls...>() >= kChunkMinL;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -510,7 +517,6 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
         c.g = g;
         c.periodic = pd.periodic != 0;
         c.exch = exch;
-        c.tile = tile;
 #pragma unroll
         for (int o = 0; o < NOPS; ++o) c.tb[o] = tabs + taboff[pd.tab[o]];
         const bool xdir = pd.sd == 1;
@@ -521,6 +527,8 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
         const int lv = line / pd.nu;
         const T *fbase = in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride;
         if (xdir) {
+            T *tile = exch + exch_elems_for<NL, NOPS>(c.P, c.periodic);
+            c.tile = tile;
             c.trow = c.sub * 64 + g;
             if constexpr (kChunked) {   // staged chunk by chunk in the item body
                 c.C = ((wi.meta >> 8) & 3) + 1;
