@@ -101,41 +101,46 @@ __global__ void k_xpcy(int64_t n, const T *__restrict__ x, T c, const T *__restr
 // derivative outputs d = [D_x Pi, D_y Pi, D_z Pi, D_x psi_x, D_y psi_y,
 // D_z psi_z] computed from src (interior, [op][z][y][x]); on interior nodes
 // stage = u0 + a k (if stage is given; stage may alias src, each node is read
-// before it is written by the same thread) and acc += b k.  State arrays hold
-// the five fields with ghosts, [f][z][y][x].
+// before it is written by the same thread) and acc = acc_in + b k.  State
+// arrays hold the five fields with ghosts, [f][z][y][x].
+// One wave per 64-node piece of an interior x-row (all blocks' pieces
+// numbered consecutively, unitpre[b] = first piece of block b): the piece's
+// block, row and x offset are found once, wave-uniform, and each lane takes
+// one node.
 template <typename T>
-__global__ void k_wave_stage(const T *u0, const T *src, T *stage, const T *acc_in, T *acc,
-                             const T *__restrict__ d, const int64_t *__restrict__ in_off,
-                             const int64_t *__restrict__ out_off, const int *__restrict__ shapes, int nblocks,
-                             int64_t total, T a, T b) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        // locate the block: shapes[4b..4b+3] = nx, ny, nz, ng; blocks are
-        // enumerated by a running count of interior points (prefix in shapes[4*nblocks + b])
+__global__ void __launch_bounds__(256)
+k_wave_stage(const T *u0, const T *src, T *stage, const T *acc_in, T *acc, const T *__restrict__ d,
+             const int64_t *__restrict__ in_off, const int64_t *__restrict__ out_off,
+             const int *__restrict__ shapes, const int *__restrict__ unitpre, int nblocks, int nunits, T a, T b) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool acc_is_u0 = acc_in == u0;
+    for (int u = blockIdx.x * 4 + wv; u < nunits; u += gridDim.x * 4) {
         int lo = 0, hi = nblocks - 1;
-        const int *pre = shapes + 4 * nblocks;   // int64 prefix stored as 2 ints per block
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            const int64_t pm = ((int64_t)pre[2 * mid + 1] << 32) | (uint32_t)pre[2 * mid];
-            if (pm <= e) lo = mid; else hi = mid - 1;
+            if (unitpre[mid] <= u) lo = mid; else hi = mid - 1;
         }
         const int bi = lo;
-        const int64_t pb = ((int64_t)pre[2 * bi + 1] << 32) | (uint32_t)pre[2 * bi];
         const int nx = shapes[4 * bi], ny = shapes[4 * bi + 1], nz = shapes[4 * bi + 2], ng = shapes[4 * bi + 3];
-        const int64_t r = e - pb;
-        const int64_t n3 = (int64_t)nx * ny * nz;
-        const int x = (int)(r % nx), y = (int)((r / nx) % ny), z = (int)(r / ((int64_t)nx * ny));
+        const int cpr = (nx + 63) >> 6;   // pieces per row
+        const int uu = u - unitpre[bi];
+        const int rr = uu / cpr;
+        const int x = ((uu - rr * cpr) << 6) + lane;
+        if (x >= nx) continue;
+        const int z = rr / ny, y = rr - z * ny;
         const int64_t PX = nx + 2 * ng, PY = ny + 2 * ng, PZ = nz + 2 * ng;
         const int64_t fs = PX * PY * PZ;
-        const int64_t ip = in_off[bi] + ((int64_t)(z + ng) * PY + (y + ng)) * PX + (x + ng);
-        const T *db = d + out_off[bi] + r;
+        const int64_t n3 = (int64_t)nx * ny * nz;
+        const int64_t ip = in_off[bi] + ((int64_t)(z + ng) * PY + (y + ng)) * PX + ng + x;
+        const T *db = d + out_off[bi] + (int64_t)rr * nx + x;
         const T k[5] = {src[ip + fs], db[3 * n3] + db[4 * n3] + db[5 * n3], db[0], db[n3], db[2 * n3]};
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-            T u = T(0);
-            if (stage || acc_in == u0) u = u0[ip + f * fs];
-            const T ai = (acc_in == u0) ? u : acc_in[ip + f * fs];
-            if (stage) stage[ip + f * fs] = u + a * k[f];
+            T v = T(0);
+            if (stage || acc_is_u0) v = u0[ip + f * fs];
+            const T ai = acc_is_u0 ? v : acc_in[ip + f * fs];
+            if (stage) stage[ip + f * fs] = v + a * k[f];
             acc[ip + f * fs] = ai + b * k[f];
         }
     }
@@ -187,21 +192,19 @@ hipError_t launch_xpcy(int f32, int64_t n, const void *x, double c, const void *
 
 namespace cfd {
 hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *stage, const void *acc_in, void *acc,
-                             const void *d,
-                             const int64_t *in_off, const int64_t *out_off, const int *shapes, int nblocks,
-                             int64_t total, double a, double b, hipStream_t st) {
-    if (total == 0) return hipSuccess;
-    int64_t g = (total + 255) / 256;
-    if (g > 16384) g = 16384;
+                             const void *d, const int64_t *in_off, const int64_t *out_off, const int *shapes,
+                             const int *unitpre, int nblocks, int nunits, double a, double b, hipStream_t st) {
+    if (nunits == 0) return hipSuccess;
+    int g = (nunits + 3) / 4;
+    if (g > 65535) g = 65535;
     if (f32)
-        hipLaunchKernelGGL(k_wave_stage<float>, dim3((int)g), dim3(256), 0, st, (const float *)u0, (const float *)src,
-                           (float *)stage, (const float *)acc_in,
-                           (float *)acc, (const float *)d, in_off, out_off, shapes, nblocks, total, (float)a,
-                           (float)b);
+        hipLaunchKernelGGL(k_wave_stage<float>, dim3(g), dim3(256), 0, st, (const float *)u0, (const float *)src,
+                           (float *)stage, (const float *)acc_in, (float *)acc, (const float *)d, in_off, out_off,
+                           shapes, unitpre, nblocks, nunits, (float)a, (float)b);
     else
-        hipLaunchKernelGGL(k_wave_stage<double>, dim3((int)g), dim3(256), 0, st, (const double *)u0,
-                           (const double *)src, (double *)stage, (const double *)acc_in, (double *)acc, (const double *)d, in_off, out_off, shapes, nblocks,
-                           total, a, b);
+        hipLaunchKernelGGL(k_wave_stage<double>, dim3(g), dim3(256), 0, st, (const double *)u0, (const double *)src,
+                           (double *)stage, (const double *)acc_in, (double *)acc, (const double *)d, in_off, out_off,
+                           shapes, unitpre, nblocks, nunits, a, b);
     return hipGetLastError();
 }
 }  // namespace cfd

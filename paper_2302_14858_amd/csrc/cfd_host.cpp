@@ -1295,19 +1295,23 @@ cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_de
     if (p->dtype != CFD_F64 && p->dtype != CFD_F32) return fail(CFD_EINVAL, "cfd_wave_rk_stage: dtype");
     HIPCHK(hipSetDevice(p->device));
     const int nb = (int)p->blocks.size();
+    // shapes: nx, ny, nz, ng per block, then the first 64-node row piece of each block (and the total)
+    int64_t nunits64 = 0;
+    for (const cfd_block &bl : p->blocks) nunits64 += (int64_t)bl.n[1] * bl.n[2] * ((bl.n[0] + 63) / 64);
+    if (nunits64 >= (int64_t(1) << 31)) return fail(CFD_EUNSUPPORTED, "cfd_wave_rk_stage: grid too large");
     if (!p->d_shapes.p) {
-        std::vector<int> sh(4 * nb + 2 * nb);
-        int64_t pre = 0;
+        std::vector<int> sh(4 * nb + nb + 1);
+        int units = 0;
         for (int b = 0; b < nb; ++b) {
             const cfd_block &bl = p->blocks[b];
             sh[4 * b] = bl.n[0];
             sh[4 * b + 1] = bl.n[1];
             sh[4 * b + 2] = bl.n[2];
             sh[4 * b + 3] = bl.ng;
-            sh[4 * nb + 2 * b] = (int)(uint32_t)(pre & 0xffffffff);
-            sh[4 * nb + 2 * b + 1] = (int)(pre >> 32);
-            pre += (int64_t)bl.n[0] * bl.n[1] * bl.n[2];
+            sh[4 * nb + b] = units;
+            units += bl.n[1] * bl.n[2] * ((bl.n[0] + 63) / 64);
         }
+        sh[4 * nb + nb] = units;
         HIPCHK(hipMalloc(&p->d_shapes.p, sh.size() * sizeof(int)));
         HIPCHK(hipMemcpy(p->d_shapes.p, sh.data(), sh.size() * sizeof(int), hipMemcpyHostToDevice));
         HIPCHK(hipMalloc(&p->d_outoff.p, nb * sizeof(int64_t)));
@@ -1317,12 +1321,11 @@ cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_de
         HIPCHK(hipMalloc(&p->d_inoff.p, p->in_off.size() * sizeof(int64_t)));
         HIPCHK(hipMemcpy(p->d_inoff.p, p->in_off.data(), p->in_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     }
-    int64_t total = 0;
-    for (const cfd_block &bl : p->blocks) total += (int64_t)bl.n[0] * bl.n[1] * bl.n[2];
     if (!acc_in_dev) acc_in_dev = acc_dev;
+    const int *shapes = (const int *)p->d_shapes.p;
     hipError_t e = launch_wave_stage(p->dtype == CFD_F32, u0_dev, src_dev, stage_dev, acc_in_dev, acc_dev, derivs_dev,
-                                     (const int64_t *)p->d_inoff.p, (const int64_t *)p->d_outoff.p,
-                                     (const int *)p->d_shapes.p, nb, total, a, b, (hipStream_t)stream);
+                                     (const int64_t *)p->d_inoff.p, (const int64_t *)p->d_outoff.p, shapes,
+                                     shapes + 4 * nb, nb, (int)nunits64, a, b, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launching wave stage");
     return CFD_OK;
 }

@@ -123,9 +123,8 @@ hipError_t launch_halo(int f32, void *data, const int64_t *off_dev, int nx, int 
 hipError_t launch_axpby(int f32, int64_t n, double a, const void *x, double b, void *y, hipStream_t st);
 hipError_t launch_xpcy(int f32, int64_t n, const void *x, double c, const void *y, void *z, hipStream_t st);
 hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *stage, const void *acc_in, void *acc,
-                             const void *d,
-                             const int64_t *in_off, const int64_t *out_off, const int *shapes, int nblocks,
-                             int64_t total, double a, double b, hipStream_t st);
+                             const void *d, const int64_t *in_off, const int64_t *out_off, const int *shapes,
+                             const int *unitpre, int nblocks, int nunits, double a, double b, hipStream_t st);
 }  // namespace cfd
 
 namespace cfd {
