@@ -255,7 +255,10 @@ void cfd_plan_destroy(cfd_plan *p);
  * ghosts: for every field, the ng ghost layers of each face of each block are
  * copied from the facing interior layers of its neighbour.  Edges and corners
  * are not filled (no operator reads them).  data_dev is the plan's input
- * buffer (element type per dtype). */
+ * buffer (element type per dtype).  CFD_EINVAL if the lattice does not match
+ * the plan's blocks or they differ in shape, CFD_ESHAPE if ng exceeds an
+ * extent, CFD_EUNSUPPORTED if one block-field holds 2^31 or more elements or
+ * nfields*bx*by*bz exceeds 65535. */
 cfd_status cfd_halo_exchange(cfd_plan *p, void *data_dev, int bx, int by, int bz, void *stream);
 
 /* ------------------------------------------------------------------------ */

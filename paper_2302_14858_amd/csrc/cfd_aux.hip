@@ -10,77 +10,63 @@
 
 namespace cfd {
 
-// Ghost element e of the 6 faces of every block-field, for a lattice of
-// identical blocks (n interior, ng ghosts) at in_off[b] with nfields fields.
-// Face order: x-, x+, y-, y+, z-, z+; a face holds ng layers of the interior
-// extent of the other two directions.
+// Face ghosts of every block-field, for a lattice of identical blocks (n
+// interior, ng ghosts) at off[b] with nfields fields.  blockIdx.y is the
+// block-field (b nfields + f, wave-uniform); thread r of it takes ghost r of
+// its 6 faces in the order x-, x+, y-, y+, z-, z+, each face holding ng
+// layers of the interior extent of the other two directions.  Index
+// arithmetic within a field is 32-bit.
 template <typename T>
 __global__ void k_halo(T *__restrict__ data, const int64_t *__restrict__ off, int nx, int ny, int nz, int ng,
-                       int nfields, int bx, int by, int bz, int64_t total) {
-    const int64_t PX = nx + 2 * ng, PY = ny + 2 * ng, PZ = nz + 2 * ng;
-    const int64_t fstride = PX * PY * PZ;
-    const int64_t fx = (int64_t)ng * ny * nz, fy = (int64_t)ng * nx * nz, fz = (int64_t)ng * nx * ny;
-    const int64_t per_field = 2 * (fx + fy + fz);
-    const int64_t per_block = per_field * nfields;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = e / per_block;
-        int64_t r = e - b * per_block;
-        const int64_t f = r / per_field;
-        r -= f * per_field;
-        const int kx = (int)(b % bx), ky = (int)((b / bx) % by), kz = (int)(b / ((int64_t)bx * by));
-        int x, y, z, nb;
-        if (r < 2 * fx) {
-            const int side = r >= fx;
-            int64_t q = side ? r - fx : r;
-            const int layer = (int)(q % ng);
-            q /= ng;
-            y = (int)(q % ny);
-            z = (int)(q / ny);
-            // ghost x and the source x in the neighbour
-            x = side ? nx + layer : -ng + layer;
-            const int nkx = (kx + (side ? 1 : bx - 1)) % bx;
-            nb = (kz * by + ky) * bx + nkx;
-            const int sx = side ? layer : nx - ng + layer;
-            const int64_t dst = off[b] + f * fstride + ((int64_t)(z + ng) * PY + (y + ng)) * PX + (x + ng);
-            const int64_t src = off[nb] + f * fstride + ((int64_t)(z + ng) * PY + (y + ng)) * PX + (sx + ng);
-            data[dst] = data[src];
-            continue;
-        }
-        r -= 2 * fx;
-        if (r < 2 * fy) {
-            const int side = r >= fy;
-            int64_t q = side ? r - fy : r;
-            x = (int)(q % nx);
-            q /= nx;
-            const int layer = (int)(q % ng);
-            z = (int)(q / ng);
-            y = side ? ny + layer : -ng + layer;
-            const int nky = (ky + (side ? 1 : by - 1)) % by;
-            nb = (kz * by + nky) * bx + kx;
-            const int sy = side ? layer : ny - ng + layer;
-            const int64_t dst = off[b] + f * fstride + ((int64_t)(z + ng) * PY + (y + ng)) * PX + (x + ng);
-            const int64_t src = off[nb] + f * fstride + ((int64_t)(z + ng) * PY + (sy + ng)) * PX + (x + ng);
-            data[dst] = data[src];
-            continue;
-        }
+                       int nfields, int bx, int by, int bz, int per_field) {
+    const int r0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r0 >= per_field) return;
+    const int bf = blockIdx.y;
+    const int b = bf / nfields, f = bf - b * nfields;
+    const int kx = b % bx, ky = (b / bx) % by, kz = b / (bx * by);
+    const int PX = nx + 2 * ng, PY = ny + 2 * ng, PZ = nz + 2 * ng;
+    const int64_t fbase = (int64_t)f * PX * PY * PZ;
+    const int fx = ng * ny * nz, fy = ng * nx * nz;
+    int r = r0;
+    int nb, dst, src;
+    if (r < 2 * fx) {
+        const int side = r >= fx;
+        int q = side ? r - fx : r;
+        const int layer = q % ng;
+        q /= ng;
+        const int y = q % ny, z = q / ny;
+        const int x = side ? nx + layer : -ng + layer;          // ghost x
+        const int sx = side ? layer : nx - ng + layer;          // source x in the neighbour
+        nb = (kz * by + ky) * bx + (kx + (side ? 1 : bx - 1)) % bx;
+        const int row = ((z + ng) * PY + (y + ng)) * PX;
+        dst = row + x + ng;
+        src = row + sx + ng;
+    } else if ((r -= 2 * fx) < 2 * fy) {
+        const int side = r >= fy;
+        int q = side ? r - fy : r;
+        const int x = q % nx;
+        q /= nx;
+        const int layer = q % ng, z = q / ng;
+        const int y = side ? ny + layer : -ng + layer;
+        const int sy = side ? layer : ny - ng + layer;
+        nb = (kz * by + (ky + (side ? 1 : by - 1)) % by) * bx + kx;
+        dst = ((z + ng) * PY + (y + ng)) * PX + x + ng;
+        src = ((z + ng) * PY + (sy + ng)) * PX + x + ng;
+    } else {
         r -= 2 * fy;
-        {
-            const int side = r >= fz;
-            int64_t q = side ? r - fz : r;
-            x = (int)(q % nx);
-            q /= nx;
-            y = (int)(q % ny);
-            const int layer = (int)(q / ny);
-            z = side ? nz + layer : -ng + layer;
-            const int nkz = (kz + (side ? 1 : bz - 1)) % bz;
-            nb = (nkz * by + ky) * bx + kx;
-            const int sz = side ? layer : nz - ng + layer;
-            const int64_t dst = off[b] + f * fstride + ((int64_t)(z + ng) * PY + (y + ng)) * PX + (x + ng);
-            const int64_t src = off[nb] + f * fstride + ((int64_t)(sz + ng) * PY + (y + ng)) * PX + (x + ng);
-            data[dst] = data[src];
-        }
+        const int fz = ng * nx * ny;
+        const int side = r >= fz;
+        int q = side ? r - fz : r;
+        const int x = q % nx;
+        q /= nx;
+        const int y = q % ny, layer = q / ny;
+        const int z = side ? nz + layer : -ng + layer;
+        const int sz = side ? layer : nz - ng + layer;
+        nb = (((kz + (side ? 1 : bz - 1)) % bz) * by + ky) * bx + kx;
+        dst = ((z + ng) * PY + (y + ng)) * PX + x + ng;
+        src = ((sz + ng) * PY + (y + ng)) * PX + x + ng;
     }
+    data[off[b] + fbase + dst] = data[off[nb] + fbase + src];
 }
 
 template <typename T>
@@ -155,14 +141,15 @@ static int grid_for(int64_t n) {
 hipError_t launch_halo(int f32, void *data, const int64_t *off_dev, int nx, int ny, int nz, int ng, int nfields,
                        int bx, int by, int bz, hipStream_t st) {
     const int64_t per_field = 2 * ((int64_t)ng * ny * nz + (int64_t)ng * nx * nz + (int64_t)ng * nx * ny);
-    const int64_t total = per_field * nfields * (int64_t)bx * by * bz;
-    if (total == 0) return hipSuccess;
+    const int64_t nbf = (int64_t)nfields * bx * by * bz;
+    if (per_field == 0 || nbf == 0) return hipSuccess;
+    const dim3 grid((unsigned)((per_field + 255) / 256), (unsigned)nbf);
     if (f32)
-        hipLaunchKernelGGL(k_halo<float>, dim3(grid_for(total)), dim3(256), 0, st, (float *)data, off_dev, nx, ny, nz,
-                           ng, nfields, bx, by, bz, total);
+        hipLaunchKernelGGL(k_halo<float>, grid, dim3(256), 0, st, (float *)data, off_dev, nx, ny, nz, ng, nfields, bx,
+                           by, bz, (int)per_field);
     else
-        hipLaunchKernelGGL(k_halo<double>, dim3(grid_for(total)), dim3(256), 0, st, (double *)data, off_dev, nx, ny,
-                           nz, ng, nfields, bx, by, bz, total);
+        hipLaunchKernelGGL(k_halo<double>, grid, dim3(256), 0, st, (double *)data, off_dev, nx, ny, nz, ng, nfields, bx,
+                           by, bz, (int)per_field);
     return hipGetLastError();
 }
 

@@ -1250,6 +1250,12 @@ cfd_status cfd_halo_exchange(cfd_plan *p, void *data_dev, int bx, int by, int bz
     for (int d = 0; d < 3; ++d)
         if (b0.ng > b0.n[d]) return fail(CFD_ESHAPE, "cfd_halo_exchange: ghost width exceeds block extent");
     if (((uintptr_t)data_dev % elem_size(p->dtype))) return fail(CFD_EINVAL, "cfd_halo_exchange: misaligned buffer");
+    {   // the kernel indexes within a field in 32 bits and puts the block-fields on the grid's y axis
+        const int64_t g = b0.ng;
+        const int64_t fe = (b0.n[0] + 2 * g) * (b0.n[1] + 2 * g) * (b0.n[2] + 2 * g);
+        if (fe >= (int64_t(1) << 31) || (int64_t)p->nfields * bx * by * bz > 65535)
+            return fail(CFD_EUNSUPPORTED, "cfd_halo_exchange: block or lattice too large");
+    }
     HIPCHK(hipSetDevice(p->device));
     if (!p->d_inoff.p) {
         HIPCHK(hipMalloc(&p->d_inoff.p, p->in_off.size() * sizeof(int64_t)));
