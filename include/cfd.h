@@ -293,6 +293,18 @@ cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_de
                              const void *acc_in_dev, void *acc_dev, const void *derivs_dev, double a, double b,
                              void *stream);
 
+/* The same stage for blocks that tile a periodic box as a bx*by*bz lattice
+ * (the layout of cfd_halo_exchange), with the ghost exchange fused in: the
+ * state the next derivative reads (stage, or acc when stage_dev is NULL) also
+ * gets its face ghosts, each interior node within ng of a face writing its new
+ * value into the facing ghost layer of the neighbour across that face.  The
+ * result equals cfd_wave_rk_stage followed by cfd_halo_exchange on that state,
+ * without a second pass over the ghost data.  Errors as cfd_wave_rk_stage, and
+ * as cfd_halo_exchange for the lattice. */
+cfd_status cfd_wave_rk_stage_halo(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev,
+                                  const void *acc_in_dev, void *acc_dev, const void *derivs_dev, double a, double b,
+                                  int bx, int by, int bz, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

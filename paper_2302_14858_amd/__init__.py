@@ -213,6 +213,18 @@ class Plan:
 
     wave_rk_stage = cfd_wave_rk_stage
 
+    def cfd_wave_rk_stage_halo(self, u0, src, stage, acc, derivs, a: float, b: float, bx: int, by: int, bz: int,
+                               stream=None, acc_in=None) -> None:
+        """wave_rk_stage on a bx x by x bz periodic block lattice, also refreshing the face ghosts of the
+        state the next derivative reads (stage, or acc when stage is None)."""
+        check(lib().cfd_wave_rk_stage_halo(self._h, _dev_ptr(u0), _dev_ptr(src),
+                                           _dev_ptr(stage) if stage is not None else None,
+                                           _dev_ptr(acc_in) if acc_in is not None else None, _dev_ptr(acc),
+                                           _dev_ptr(derivs), float(a), float(b), int(bx), int(by), int(bz),
+                                           _stream_ptr(stream)))
+
+    wave_rk_stage_halo = cfd_wave_rk_stage_halo
+
     def cfd_halo_exchange(self, data, bx: int, by: int, bz: int, stream=None) -> None:
         check(lib().cfd_halo_exchange(self._h, _dev_ptr(data), bx, by, bz, _stream_ptr(stream)))
 

@@ -62,6 +62,7 @@ SIGNATURES = {
     "cfd_axpby": (_i, [_i, _ll, _d, _vp, _d, _vp, _vp]),
     "cfd_xpcy": (_i, [_i, _ll, _vp, _d, _vp, _vp, _vp]),
     "cfd_wave_rk_stage": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp]),
+    "cfd_wave_rk_stage_halo": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _i, _i, _i, _vp]),
 }
 
 _lib = None

@@ -93,14 +93,22 @@ __global__ void k_xpcy(int64_t n, const T *__restrict__ x, T c, const T *__restr
 // numbered consecutively, unitpre[b] = first piece of block b): the piece's
 // block, row and x offset are found once, wave-uniform, and each lane takes
 // one node.
+// With a lattice (bx > 0: the blocks tile a periodic box as in
+// cfd_halo_exchange) the state the next derivative reads (stage if given,
+// else acc) also has its face ghosts refreshed: a node within ng of a face
+// writes its new value into the facing ghost layer of the neighbour across
+// that face.  Interior nodes are only read and ghost nodes only written here,
+// so stage may still alias src.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_wave_stage(const T *u0, const T *src, T *stage, const T *acc_in, T *acc, const T *__restrict__ d,
              const int64_t *__restrict__ in_off, const int64_t *__restrict__ out_off,
-             const int *__restrict__ shapes, const int *__restrict__ unitpre, int nblocks, int nunits, T a, T b) {
+             const int *__restrict__ shapes, const int *__restrict__ unitpre, int nblocks, int nunits, T a, T b,
+             int bx, int by, int bz) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool acc_is_u0 = acc_in == u0;
+    T *next = stage ? stage : acc;
     for (int u = blockIdx.x * 4 + wv; u < nunits; u += gridDim.x * 4) {
         int lo = 0, hi = nblocks - 1;
         while (lo < hi) {
@@ -121,13 +129,32 @@ k_wave_stage(const T *u0, const T *src, T *stage, const T *acc_in, T *acc, const
         const int64_t ip = in_off[bi] + ((int64_t)(z + ng) * PY + (y + ng)) * PX + ng + x;
         const T *db = d + out_off[bi] + (int64_t)rr * nx + x;
         const T k[5] = {src[ip + fs], db[3 * n3] + db[4 * n3] + db[5 * n3], db[0], db[n3], db[2 * n3]};
+        T nv[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
             T v = T(0);
             if (stage || acc_is_u0) v = u0[ip + f * fs];
             const T ai = acc_is_u0 ? v : acc_in[ip + f * fs];
-            if (stage) stage[ip + f * fs] = v + a * k[f];
-            acc[ip + f * fs] = ai + b * k[f];
+            const T sv = v + a * k[f], av = ai + b * k[f];
+            if (stage) stage[ip + f * fs] = sv;
+            acc[ip + f * fs] = av;
+            nv[f] = stage ? sv : av;
+        }
+        if (bx > 0) {
+            // ghost copies of this node in the neighbours across the faces it is near
+            const int kx = bi % bx, ky = (bi / bx) % by, kz = bi / (bx * by);
+            const int64_t here = ((int64_t)(z + ng) * PY + (y + ng)) * PX + ng + x;   // offset within a field
+            auto put = [&](int nb, int64_t shift) {
+                T *dst = next + in_off[nb] + here + shift;
+#pragma unroll
+                for (int f = 0; f < 5; ++f) dst[f * fs] = nv[f];
+            };
+            if (x < ng) put((kz * by + ky) * bx + (kx + bx - 1) % bx, nx);
+            if (x >= nx - ng) put((kz * by + ky) * bx + (kx + 1) % bx, -(int64_t)nx);
+            if (y < ng) put((kz * by + (ky + by - 1) % by) * bx + kx, (int64_t)ny * PX);
+            if (y >= ny - ng) put((kz * by + (ky + 1) % by) * bx + kx, -(int64_t)ny * PX);
+            if (z < ng) put((((kz + bz - 1) % bz) * by + ky) * bx + kx, (int64_t)nz * PX * PY);
+            if (z >= nz - ng) put((((kz + 1) % bz) * by + ky) * bx + kx, -(int64_t)nz * PX * PY);
         }
     }
 }
@@ -180,18 +207,19 @@ hipError_t launch_xpcy(int f32, int64_t n, const void *x, double c, const void *
 namespace cfd {
 hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *stage, const void *acc_in, void *acc,
                              const void *d, const int64_t *in_off, const int64_t *out_off, const int *shapes,
-                             const int *unitpre, int nblocks, int nunits, double a, double b, hipStream_t st) {
+                             const int *unitpre, int nblocks, int nunits, double a, double b, int bx, int by, int bz,
+                             hipStream_t st) {
     if (nunits == 0) return hipSuccess;
     int g = (nunits + 3) / 4;
     if (g > 65535) g = 65535;
     if (f32)
         hipLaunchKernelGGL(k_wave_stage<float>, dim3(g), dim3(256), 0, st, (const float *)u0, (const float *)src,
                            (float *)stage, (const float *)acc_in, (float *)acc, (const float *)d, in_off, out_off,
-                           shapes, unitpre, nblocks, nunits, (float)a, (float)b);
+                           shapes, unitpre, nblocks, nunits, (float)a, (float)b, bx, by, bz);
     else
         hipLaunchKernelGGL(k_wave_stage<double>, dim3(g), dim3(256), 0, st, (const double *)u0, (const double *)src,
                            (double *)stage, (const double *)acc_in, (double *)acc, (const double *)d, in_off, out_off,
-                           shapes, unitpre, nblocks, nunits, a, b);
+                           shapes, unitpre, nblocks, nunits, a, b, bx, by, bz);
     return hipGetLastError();
 }
 }  // namespace cfd

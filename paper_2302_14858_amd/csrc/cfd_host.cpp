@@ -1285,9 +1285,9 @@ cfd_status cfd_xpcy(cfd_dtype dtype, long long n, const void *x_dev, double c, c
     return CFD_OK;
 }
 
-cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev,
-                             const void *acc_in_dev, void *acc_dev, const void *derivs_dev, double a, double b,
-                             void *stream) {
+namespace {
+cfd_status wave_stage(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev, const void *acc_in_dev,
+                      void *acc_dev, const void *derivs_dev, double a, double b, int bx, int by, int bz, void *stream) {
     if (!p || !u0_dev || !src_dev || !acc_dev || !derivs_dev)
         return fail(CFD_EINVAL, "cfd_wave_rk_stage: null argument");
     // the plan must hold the five wave fields and the six first-derivative operators
@@ -1331,9 +1331,31 @@ cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_de
     const int *shapes = (const int *)p->d_shapes.p;
     hipError_t e = launch_wave_stage(p->dtype == CFD_F32, u0_dev, src_dev, stage_dev, acc_in_dev, acc_dev, derivs_dev,
                                      (const int64_t *)p->d_inoff.p, (const int64_t *)p->d_outoff.p, shapes,
-                                     shapes + 4 * nb, nb, (int)nunits64, a, b, (hipStream_t)stream);
+                                     shapes + 4 * nb, nb, (int)nunits64, a, b, bx, by, bz, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launching wave stage");
     return CFD_OK;
+}
+}  // namespace
+
+cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev,
+                             const void *acc_in_dev, void *acc_dev, const void *derivs_dev, double a, double b,
+                             void *stream) {
+    return wave_stage(p, u0_dev, src_dev, stage_dev, acc_in_dev, acc_dev, derivs_dev, a, b, 0, 0, 0, stream);
+}
+
+cfd_status cfd_wave_rk_stage_halo(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev,
+                                  const void *acc_in_dev, void *acc_dev, const void *derivs_dev, double a, double b,
+                                  int bx, int by, int bz, void *stream) {
+    if (!p) return fail(CFD_EINVAL, "cfd_wave_rk_stage_halo: null plan");
+    if (bx < 1 || by < 1 || bz < 1 || (int64_t)bx * by * bz != (int64_t)p->blocks.size())
+        return fail(CFD_EINVAL, "cfd_wave_rk_stage_halo: lattice does not match the plan's block count");
+    const cfd_block &b0 = p->blocks[0];
+    for (const cfd_block &bl : p->blocks)
+        if (bl.n[0] != b0.n[0] || bl.n[1] != b0.n[1] || bl.n[2] != b0.n[2] || bl.ng != b0.ng)
+            return fail(CFD_EINVAL, "cfd_wave_rk_stage_halo: blocks differ in shape");
+    for (int d = 0; d < 3; ++d)
+        if (b0.ng > b0.n[d]) return fail(CFD_ESHAPE, "cfd_wave_rk_stage_halo: ghost width exceeds block extent");
+    return wave_stage(p, u0_dev, src_dev, stage_dev, acc_in_dev, acc_dev, derivs_dev, a, b, bx, by, bz, stream);
 }
 
 void cfd_plan_destroy(cfd_plan *p) {

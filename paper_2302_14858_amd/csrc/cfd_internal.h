@@ -124,7 +124,8 @@ hipError_t launch_axpby(int f32, int64_t n, double a, const void *x, double b, v
 hipError_t launch_xpcy(int f32, int64_t n, const void *x, double c, const void *y, void *z, hipStream_t st);
 hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *stage, const void *acc_in, void *acc,
                              const void *d, const int64_t *in_off, const int64_t *out_off, const int *shapes,
-                             const int *unitpre, int nblocks, int nunits, double a, double b, hipStream_t st);
+                             const int *unitpre, int nblocks, int nunits, double a, double b, int bx, int by, int bz,
+                             hipStream_t st);   // bx = 0: no ghost refresh
 }  // namespace cfd
 
 namespace cfd {

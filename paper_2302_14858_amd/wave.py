@@ -2,9 +2,9 @@
 
 State: five fields (phi, Pi, psi_x, psi_y, psi_z) on mesh blocks.  Each stage
 is one batched derivative apply of the plan (D_x, D_y, D_z of Pi and
-D_i psi_i), one fused stage kernel (cfd_wave_rk_stage) and, for block
-tilings, a device ghost exchange (cfd_halo_exchange).  A whole step can be
-captured in one HIP graph.
+D_i psi_i) and one fused stage kernel (cfd_wave_rk_stage; on block lattices
+cfd_wave_rk_stage_halo, which also refreshes the face ghosts).  A whole step
+can be captured in one HIP graph.
 """
 from __future__ import annotations
 
@@ -44,19 +44,22 @@ class WaveRK4:
             self.plan.halo_exchange(buf, *self.lattice)
 
     def step(self):
-        """u <- RK4 step of size dt (the first stage reads acc from u, the last writes u)."""
+        """u <- RK4 step of size dt (the first stage reads acc from u, the last writes u).  On a block
+        lattice the stage kernel also refreshes the ghosts of the state the next stage reads."""
         dt = self.dt
         src = self.u
         stages = ((dt / 2, dt / 6), (dt / 2, dt / 3), (dt, dt / 3), (None, dt / 6))
         for i, (a, b) in enumerate(stages):
             self.plan.apply(src, self.d)
             last = i == len(stages) - 1
-            self.plan.wave_rk_stage(self.u, src, None if last else self.stage, self.u if last else self.acc,
-                                    self.d, 0.0 if a is None else a, b, acc_in=self.u if i == 0 else self.acc)
-            if not last:
-                self._halo(self.stage)
-                src = self.stage
-        self._halo(self.u)
+            args = (self.u, src, None if last else self.stage, self.u if last else self.acc, self.d,
+                    0.0 if a is None else a, b)
+            acc_in = self.u if i == 0 else self.acc
+            if self.lattice is not None:
+                self.plan.wave_rk_stage_halo(*args, *self.lattice, acc_in=acc_in)
+            else:
+                self.plan.wave_rk_stage(*args, acc_in=acc_in)
+            src = self.stage
 
     def capture(self):
         """Capture one step in a HIP graph (torch.cuda.CUDAGraph); run() then replays it."""

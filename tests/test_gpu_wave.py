@@ -91,3 +91,36 @@ def test_rk4_graph_replay_matches_eager(cuda):
         b.run(1)
         torch.cuda.synchronize()
         assert torch.equal(a.u, b.u), rep
+
+
+@pytest.mark.parametrize("lattice,nb", [((2, 2, 2), 12), ((3, 1, 2), 8)])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_fused_stage_halo_equals_stage_then_exchange(cuda, lattice, nb, dtype):
+    """cfd_wave_rk_stage_halo = cfd_wave_rk_stage followed by cfd_halo_exchange of the state the next
+    stage reads (stage, or acc when no stage is written), bit for bit, also with a lattice of extent 1."""
+    import torch
+    import paper_2302_14858_amd as P
+    from paper_2302_14858_amd.wave import wave_ops
+    bx, by, bz = lattice
+    blocks = [dict(n=(nb, nb, nb), ng=4, h=(0.1, 0.1, 0.1), boundary=(synth.CLOSURE,) * 3)
+              for _ in range(bx * by * bz)]
+    plan = P.Plan(blocks, 5, wave_ops(P.Scheme.named("(1)Q1_3[1]")), dtype=dtype)
+    nin, nout = plan.sizes()
+    tdt = torch.float64 if dtype == 0 else torch.float32
+    rng = np.random.default_rng(11)
+    u, src, stage0, acc0 = (torch.from_numpy(rng.standard_normal(nin)).to(device="cuda", dtype=tdt)
+                            for _ in range(4))
+    d = torch.from_numpy(rng.standard_normal(nout)).to(device="cuda", dtype=tdt)
+    for with_stage in (True, False):
+        res = []
+        for fused in (False, True):
+            stage, acc = stage0.clone(), acc0.clone()
+            st = stage if with_stage else None
+            if fused:
+                plan.wave_rk_stage_halo(u, src, st, acc, d, 0.25, 0.125, *lattice)
+            else:
+                plan.wave_rk_stage(u, src, st, acc, d, 0.25, 0.125)
+                plan.halo_exchange(stage if with_stage else acc, *lattice)
+            torch.cuda.synchronize()
+            res.append((stage.cpu().numpy(), acc.cpu().numpy()))
+        assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1]), with_stage
