@@ -23,7 +23,6 @@ namespace cfd {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
-constexpr int kDenseMaxN = 256;
 constexpr int kDenseExt = 16;          // wrap-around margin of the extended circulant rows
 
 // Layout of one dense table (per scheme and line length), in bytes:

@@ -13,12 +13,11 @@ struct LineClass {
     int nl, nops, par, mi, hw;
     int nL;
     int Ls[8];
-    int exch;          // exchange-area elements
     const void *fn;
 };
 
 #define CFD_LC(T, NL, NOPS, PAR, MI, HW, ...)                                                        \
-    LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__}, exch_elems<NL, NOPS>(),      \
+    LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
               reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, __VA_ARGS__>)}
 
 // The classes compiled for each precision.

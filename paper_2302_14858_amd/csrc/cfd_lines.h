@@ -41,22 +41,9 @@ constexpr int kWGW = 4;   // wavefronts per workgroup
 constexpr int kXCD = 8;   // accelerator complex dies (each with its own L2)
 
 
-
-
-// Exchange area of the partition coupling, elements of T, for NL and NOPS:
-// (4/P) groups x NOPS x 64 lanes x ((2 NL P) | 1), maximised over P.
-template <int NL, int NOPS>
-__host__ __device__ constexpr int exch_elems() {
-    int best = 0;
-    for (int P = 1; P <= kWGW; P *= 2) {
-        int v = (kWGW / P) * NOPS * 64 * ((2 * NL * P) | 1);
-        best = v > best ? v : best;
-    }
-    return NL > 0 ? best : 0;
-}
-
-// Exchange elements an item with P partitions uses: partition coupling or the
-// periodic wrap (a single-partition closure line uses none).  The x tile
+// Exchange elements (of T) an item with P partitions uses for partition
+// coupling or the periodic wrap: (4/P) line groups x NOPS x 64 lanes x
+// ((2 NL P) | 1); a single-partition closure line uses none.  The x tile
 // starts right after them.
 template <int NL, int NOPS>
 __device__ __forceinline__ int exch_elems_for(int P, bool periodic) {
