@@ -6,11 +6,12 @@
 //   * forms A^-1 B and A^-1 in FP64 on the GPU (dense Gauss-Jordan on
 //     [A | B | I], k_dense_form) and keeps row 0 of each (a circulant matrix
 //     is its first row): D[i][j] = m[(j - i) mod N], R[i][j] = rho[(j - i) mod N];
-//   * splits m into BF16 hi + lo terms and rho into a BF16 hi term;
-//   * per tile of 32 lines: yhat = D_hi f_hi + D_hi f_lo + D_lo f_hi on MFMA
-//     (v_mfma_f32_16x16x32_bf16, FP32 accumulation), then one refinement with
-//     the FP64 banded residual r = h^-d B f - A yhat and y = yhat + R_hi r_hi
-//     accumulated into the same registers.
+//   * splits m into BF16 hi + lo terms and rho into a BF16 hi term, and marks
+//     the 16 x 32 circulant blocks whose entries are not negligible;
+//   * per wave and 16 lines: yhat = D_hi f_hi + D_hi f_lo + D_lo f_hi over
+//     those blocks on MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation), then
+//     one refinement with the FP64 banded residual r = h^-d B f - A yhat and
+//     y = yhat + R_hi r accumulated into the same registers.
 // Inputs and outputs are FP32.
 #include <hip/hip_runtime.h>
 
