@@ -105,31 +105,50 @@ def check_sample(plan, y, wl, ops, blocks):
     return H.max_rel_err(g, o)
 
 
-def cpu_baseline(wl, ops, budget_s=12.0):
-    """Oracle (plain C, OpenMP over lines) on a bounded sample of the same workload."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, ops, budget_s=12.0, one_core_s=3.0):
+    """Oracle (plain C, OpenMP over lines) on a bounded sample of the same workload: all host
+    threads for budget_s, and one thread for one_core_s (run first; the all-thread run then sets
+    the thread count back)."""
     from oracle import lines as OL
     from oracle import schemes as OS
     schemes = {op[0]: OS.named(op[0]) for op in ops}
     threads = OL.max_threads()
-    evals = 0
-    t0 = time.perf_counter()
-    nb = 0
-    passes = 0
-    while time.perf_counter() - t0 < budget_s:
-        for b, blk in enumerate(wl.blocks):
-            for f in range(wl.nfields):
-                fv = wl.field_view(b, f)
-                for name, d in ops:
-                    OL.apply_block(schemes[name], fv, blk.ng, blk.h[d], d)
-                evals += len(ops) * int(np.prod(blk.n))
-            nb += 1
-            if time.perf_counter() - t0 > budget_s:
-                break
-        passes += 1
-    dt = time.perf_counter() - t0
+
+    def sample(nthreads, budget):
+        evals = nb = passes = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            for b, blk in enumerate(wl.blocks):
+                for f in range(wl.nfields):
+                    fv = wl.field_view(b, f)
+                    for name, d in ops:
+                        OL.apply_block(schemes[name], fv, blk.ng, blk.h[d], d, nthreads=nthreads)
+                    evals += len(ops) * int(np.prod(blk.n))
+                nb += 1
+                if time.perf_counter() - t0 > budget:
+                    break
+            passes += 1
+        return evals, nb, passes, time.perf_counter() - t0
+
+    e1, nb1, _, dt1 = sample(1, one_core_s)
+    evals, nb, passes, dt = sample(threads, budget_s)
     return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{nb} block passes over the {len(wl.blocks)} blocks ({passes} sweeps) x {wl.nfields} "
-                      f"fields x {len(ops)} ops: {evals} evals in {dt:.1f} s"}
+                      f"fields x {len(ops)} ops: {evals} evals in {dt:.1f} s",
+            "one_core": {"value": e1 / dt1, "unit": "evals/s",
+                         "sample": f"{nb1} block passes x {wl.nfields} fields x {len(ops)} ops in {dt1:.1f} s"},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
 
 def _field_err(y, plan, wl, ops, fields):
