@@ -404,12 +404,12 @@ cfd_status build_groups(cfd_plan *p) {
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
 
     // 4. work items.  One launch group per kernel class (x lines optionally in
-    //    a group of their own; with concurrent launches, y/z items that need
-    //    no LDS also in a group of their own, whose workgroups then fit on CUs
-    //    whose LDS the x launch fills); within a group the items of one
-    //    block-field are adjacent (x, y, z passes together) so its input is
-    //    re-read from cache rather than HBM.  A group's LDS is the most any of
-    //    its items needs.
+    //    a group of their own; with concurrent launches, the y/z items of
+    //    blocks none of whose y/z lines need LDS also in a group of their own,
+    //    whose workgroups then fit on CUs whose LDS the x launch fills);
+    //    within a group the items of one block-field are adjacent (x, y, z
+    //    passes together) so its input is re-read from cache rather than HBM.
+    //    A group's LDS is the most any of its items needs.
     const size_t es = f32 ? 4 : 8;
     std::map<std::pair<const void *, int>, int> gidx;
     std::vector<std::vector<WorkItem>> gitems;
@@ -419,6 +419,13 @@ cfd_status build_groups(cfd_plan *p) {
     std::vector<std::vector<int>> by_block(p->blocks.size());
     for (size_t i = 0; i < p->passes.size(); ++i) by_block[p->passes[i].block].push_back((int)i);
     for (size_t b = 0; b < p->blocks.size(); ++b) {
+        // the LDS-free y/z launch takes a block only if none of its y/z passes
+        // needs LDS, so a block-field's y and z lines stay in one launch
+        bool yz_lds_free = true;
+        for (int i : by_block[b]) {
+            const PassHost &ps = p->passes[i];
+            if (ps.dir != 0 && exch_bytes(ps.nl, ps.nops, ps.P, ps.periodic, es) > 0) yz_lds_free = false;
+        }
         for (int f = 0; f < p->nfields; ++f) {
             for (int i : by_block[b]) {
                 const PassHost &ps = p->passes[i];
@@ -427,7 +434,7 @@ cfd_status build_groups(cfd_plan *p) {
                 if (ps.dir == 0) lds += x_tile_bytes(ps.P, ps.L, ps.cls->hw, es, ps.C);
                 int sub = 0;
                 if (p->split_x && ps.dir == 0) sub = 1;
-                else if (p->split_x && p->concurrent && lds == 0) sub = 2;
+                else if (p->split_x && p->concurrent && yz_lds_free) sub = 2;
                 auto key = std::make_pair(ps.cls->fn, sub);
                 auto it = gidx.find(key);
                 int gi;
