@@ -75,7 +75,7 @@ def run_gpu(wl, ops, dtype, steps, warmup, autotune=True, schedule=None):
         for N, xl, Pp in parts:
             plan.set_schedule(N, xl, Pp, **kw)
     elif autotune:
-        plan.autotune(x, y)   # no cache: every run tunes on the box it runs on
+        plan.autotune(x, y)   # no cache: every run tunes on the device it runs on
     plan.capture_graph(x, y)
     for _ in range(warmup):
         plan.launch_graph()
