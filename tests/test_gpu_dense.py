@@ -102,3 +102,14 @@ def test_dense_several_tables_in_one_launch(cuda):
     for pers in (True, False):
         plan.set_schedule(persistent=pers)
         assert H.max_rel_err(H.gpu_run(plan, wl, ops, dtype=MIXED), o) <= H.ERR_F32
+
+
+def test_dense_rejects_fields_over_4GiB(cuda):
+    """The dense kernels address a field with 32-bit byte offsets: larger fields are refused at plan creation."""
+    import paper_2302_14858_amd as P
+    from paper_2302_14858_amd import _lib
+    sch = P.Scheme.named("(1)Q1_3[1]")
+    blocks = [dict(n=(256, 4096, 1100), ng=0, h=(0.1, 0.1, 0.1), boundary=(synth.PERIODIC,) * 3)]
+    with pytest.raises(P.CfdError) as e:
+        P.Plan(blocks, 1, [(sch, 0, -1)], dtype=MIXED)
+    assert e.value.status == _lib.CFD_EUNSUPPORTED

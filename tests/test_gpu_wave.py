@@ -124,3 +124,33 @@ def test_fused_stage_halo_equals_stage_then_exchange(cuda, lattice, nb, dtype):
             torch.cuda.synchronize()
             res.append((stage.cpu().numpy(), acc.cpu().numpy()))
         assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1]), with_stage
+
+
+def test_fused_stage_halo_rejects_bad_lattices(cuda):
+    """Lattice checks of cfd_wave_rk_stage_halo, made on the host before any launch."""
+    import torch
+    import paper_2302_14858_amd as P
+    from paper_2302_14858_amd import _lib
+    from paper_2302_14858_amd.wave import wave_ops
+    sch = P.Scheme.named("(1)Q1_3[1]")
+
+    def plan_of(shapes, ng=4):
+        return P.Plan([dict(n=n, ng=ng, h=(0.1, 0.1, 0.1), boundary=(synth.CLOSURE,) * 3) for n in shapes], 5,
+                      wave_ops(sch))
+
+    def call(plan, lattice):
+        nin, nout = plan.sizes()
+        u = torch.zeros(nin, dtype=torch.float64, device="cuda")
+        d = torch.zeros(nout, dtype=torch.float64, device="cuda")
+        plan.wave_rk_stage_halo(u, u, u.clone(), u.clone(), d, 0.5, 0.5, *lattice)
+
+    good = plan_of([(8, 8, 8)] * 2)
+    for lattice, status in (((2, 2, 1), _lib.CFD_EINVAL), ((1, 1, 1), _lib.CFD_EINVAL), ((0, 2, 1), _lib.CFD_EINVAL)):
+        with pytest.raises(P.CfdError) as e:
+            call(good, lattice)
+        assert e.value.status == status, lattice
+    with pytest.raises(P.CfdError) as e:   # blocks of different shapes
+        call(plan_of([(8, 8, 8), (8, 8, 12)]), (2, 1, 1))
+    assert e.value.status == _lib.CFD_EINVAL
+    call(good, (2, 1, 1))                  # the valid lattice runs
+    torch.cuda.synchronize()
