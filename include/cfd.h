@@ -214,16 +214,20 @@ cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream);
                                     where workgroup b (on XCD b mod 8) takes its XCD's */
 #define CFD_SCHED_CONCURRENT 8   /* the plan's launches (e.g. the x launch and the y/z
                                     launch) run on forked streams at the same time,
-                                    joined on the caller's stream before later work */
+                                    joined on the caller's stream before later work;
+                                    with CFD_SCHED_SPLIT_X the y/z lines of blocks that
+                                    need no LDS for them get a launch of their own */
 
 /* Time the candidate schedules on the given buffers and keep the fastest:
  * the launch shape (persistent grid, XCD-aware or not, or one workgroup per
  * item; x lines fused with y/z or split; launches one after another or
  * concurrent), then under that shape the number of partitions per line for
- * every (line length, x or y/z) class, then the launch shape again.  If cache_path is non-NULL the per-class choices
- * are read from / appended to that text file, keyed by device arch, dtype,
- * line length, direction class, band, fused operators and launch shape.  Synchronises the
- * stream.  Invalidates a captured graph. */
+ * every (line length, x or y/z) class, then the launch shape again.  Each
+ * candidate's time is the best of three runs of 10 applies.  If cache_path
+ * is non-NULL the per-class choices are read from / appended to that text
+ * file, keyed by device arch, dtype, line length, direction class, band,
+ * fused operators and launch shape.  Synchronises the stream.  Invalidates a
+ * captured graph. */
 cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, void *stream,
                              const char *cache_path);
 
