@@ -1119,7 +1119,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     }
     auto keyof = [&](const std::tuple<int, int, int, int> &k) {
         std::ostringstream s;
-        s << "v2:" << arch << ":" << dt << ":N" << std::get<0>(k) << ":x" << std::get<1>(k) << ":nl" << std::get<2>(k)
+        s << "v3:" << arch << ":" << dt << ":N" << std::get<0>(k) << ":x" << std::get<1>(k) << ":nl" << std::get<2>(k)
           << ":ops" << std::get<3>(k);
         return s.str();
     };
