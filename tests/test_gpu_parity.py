@@ -154,3 +154,21 @@ def test_concurrent_graph_replay(cuda):
         torch.cuda.synchronize()
         assert torch.equal(y_graph, y_eager), rep
         x.mul_(1.0)
+
+
+def test_autotune_cache_round_trip(cuda, tmp_path):
+    """Autotuning writes its per-class choices to the cache file; a second plan tuned from that file
+    takes them and still matches the oracle."""
+    import torch
+    wl = synth.batch64(nblocks=4, nfields=2, sizes=(16, 24, 32, 48), seed=9)
+    o = H.oracle_run(wl, D12_PENTA)
+    cache = str(tmp_path / "tune.txt")
+    for _ in range(2):
+        plan = H.make_plan(wl, D12_PENTA)
+        nin, nout = plan.sizes()
+        x = torch.from_numpy(wl.data).cuda()
+        y = torch.empty(nout, dtype=torch.float64, device="cuda")
+        plan.autotune(x, y, cache_path=cache)
+        assert H.max_rel_err(H.gpu_run(plan, wl, D12_PENTA), o) <= H.ERR_F64
+    lines = open(cache).read().split()
+    assert lines and lines[0].startswith("v3:")
