@@ -113,3 +113,21 @@ def test_dense_rejects_fields_over_4GiB(cuda):
     with pytest.raises(P.CfdError) as e:
         P.Plan(blocks, 1, [(sch, 0, -1)], dtype=MIXED)
     assert e.value.status == _lib.CFD_EUNSUPPORTED
+
+
+def test_dense_x_lines_unaligned_input(cuda):
+    """An odd ghost width puts x-line inputs off 16-byte alignment: the per-element load path."""
+    rng = np.random.default_rng(12)
+    n = (64, 6, 5)
+    h = tuple(2 * np.pi / v for v in n)
+    blk = synth.Block(n, 1, h, (synth.PERIODIC,) * 3, (0.0, 0.0, 0.0))
+    modes = [synth._random_modes(rng, 8, 0, 10, 1.0, exclude_zero=True) for _ in range(2)]
+    for m in modes:
+        m.k = np.minimum(m.k, np.array([max(0, v // 2 - 1) for v in n]))
+    data, offs = synth._fill([blk], 2, lambda b, f, x, y, z: synth.eval_modes(modes[f], x, y, z))
+    wl = synth.Workload("unaligned", [blk], 2, data, offs, [[m] for m in modes])
+    ops = [("(1)Q1_3[1]", 0)]
+    plan = H.make_plan(wl, ops, dtype=MIXED)
+    g = H.gpu_run(plan, wl, ops, dtype=MIXED)
+    o = H.oracle_run(wl, ops)
+    assert H.max_rel_err(g, o) <= H.ERR_F32
