@@ -95,14 +95,19 @@ def run_gpu(wl, ops, dtype, steps, warmup, autotune=True, schedule=None):
     return plan, x, y, ev_ms, wall, launches, items
 
 
-def check_sample(plan, y, wl, ops, blocks):
-    """Sampled parity against the oracle on a few blocks (all fields, all ops)."""
+def oracle_reference(plan, wl, ops):
+    """The oracle's result for every block, field and operator, in the plan's output layout."""
     from tests import helpers as H
     _, ooffs = plan.offsets()
-    flat = y.double().cpu().numpy()
-    g = H.unpack(wl, ops, flat, ooffs)
-    o = H.oracle_run(wl, ops, blocks=blocks)
-    return H.max_rel_err(g, o)
+    _, nout = plan.sizes()
+    return H.oracle_flat(wl, ops, ooffs, nout)
+
+
+def err_vs_oracle(plan, y, wl, ops, ref):
+    """Worst relative max-norm error over every output node (each block, field and operator)."""
+    from tests import helpers as H
+    _, ooffs = plan.offsets()
+    return H.compare_flat(y.double().cpu().numpy(), ref, wl, ops, ooffs)
 
 
 def _cpu_model() -> str:
@@ -151,41 +156,23 @@ def cpu_baseline(wl, ops, budget_s=12.0, one_core_s=3.0):
             "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
 
-def _field_err(y, plan, wl, ops, fields):
-    """Relative max-norm error of the listed fields (all ops, block 0) against the oracle."""
-    from tests import helpers as H
-    from oracle import lines as OL
-    from oracle import schemes as OS
-    import synth
-    _, ooffs = plan.offsets()
-    blk = wl.blocks[0]
-    npts = int(np.prod(blk.n))
-    nf = wl.nfields
-    worst = 0.0
-    for o, (name, d) in enumerate(ops):
-        s = OS.named(name)
-        for f in fields:
-            off = ooffs[0] + (o * nf + f) * npts
-            got = y[off:off + npts].double().cpu().numpy().reshape(blk.n[2], blk.n[1], blk.n[0])
-            ref = OL.apply_block(s, wl.field_view(0, f), blk.ng, blk.h[d], d,
-                                 periodic=blk.boundary[d] == synth.PERIODIC)
-            worst = max(worst, H.rel_err(got, ref))
-    return worst
-
-
-def extra_block128(steps, warmup, autotune):
-    """One 128^3 block, ng = 4, tridiagonal tuned D1 + D2 along x, y, z with matched closures, FP64."""
+def extra_block128(steps, warmup, autotune, ng=4):
+    """One 128^3 block, tridiagonal tuned D1 + D2 along x, y, z, FP64: at ng = 4 with the matched
+    closures, at ng = 3 with the order-only closures (:E)."""
     import torch
     import synth
     import paper_2302_14858_amd as P
-    wl = synth.block128()
-    plan, x, y, ms, _, _, _ = run_gpu(wl, OPS_TRI, P.CFD_F64, steps, warmup, autotune=autotune)
-    evals = wl.interior_points * wl.nfields * len(OPS_TRI)
-    alg, _, _ = algorithmic_bytes(wl, OPS_TRI, 8)
-    out = {"workload": "block128: one 128^3 block on [-1,1]^3, ng=4, Gaussian + N(0,1e-3) noise modes, "
-                       "(d)Q1_3[1] D1+D2 along x,y,z with matched closures, FP64",
+    ops = OPS_TRI if ng >= 4 else [(n + ":E", d) for n, d in OPS_TRI]
+    wl = synth.block128(ng=ng)
+    plan, x, y, ms, _, _, _ = run_gpu(wl, ops, P.CFD_F64, steps, warmup, autotune=autotune)
+    evals = wl.interior_points * wl.nfields * len(ops)
+    alg, _, _ = algorithmic_bytes(wl, ops, 8)
+    closure = "matched closures" if ng >= 4 else "order-only closures (:E)"
+    out = {"workload": f"block128: one 128^3 block on [-1,1]^3, ng={ng}, Gaussian + N(0,1e-3) noise modes, "
+                       f"(d)Q1_3[1] D1+D2 along x,y,z with {closure}, FP64",
            "ms_per_step": ms, "value": evals / (ms * 1e-3), "unit": "evals/s",
-           "achieved_GBs": alg / (ms * 1e-3) / 1e9, "err_vs_oracle": _field_err(y, plan, wl, OPS_TRI, [0])}
+           "achieved_GBs": alg / (ms * 1e-3) / 1e9,
+           "err_vs_oracle": err_vs_oracle(plan, y, wl, ops, oracle_reference(plan, wl, ops))}
     del plan, x, y
     torch.cuda.empty_cache()
     return out
@@ -199,14 +186,17 @@ def extra_periodic256(steps, warmup, autotune):
     wl = synth.periodic256()
     evals = wl.interior_points * wl.nfields * len(OPS_D1_TRI)
     out = {"workload": "periodic256: 256^3, 8 fields of 32 modes with k up to 120, (1)Q1_3[1] D1 along x,y,z"}
+    ref = None
     for label, dt, es in (("f64_banded", P.CFD_F64, 8), ("f32_banded", P.CFD_F32, 4),
                           ("mixed_dense_bf16", P.CFD_MIXED_BF16, 4)):
         plan, x, y, ms, _, _, _ = run_gpu(wl, OPS_D1_TRI, dt, steps, warmup, autotune=autotune)
         alg, _, _ = algorithmic_bytes(wl, OPS_D1_TRI, es)
+        if ref is None:
+            ref = oracle_reference(plan, wl, OPS_D1_TRI)
         out[label] = {"ms_per_step": ms, "value": evals / (ms * 1e-3), "unit": "evals/s",
                       "achieved_GBs": alg / (ms * 1e-3) / 1e9,
-                      "err_vs_oracle": _field_err(y, plan, wl, OPS_D1_TRI, [0, wl.nfields - 1]),
-                      "err_sample": "fields 0 and 7, all three directions, every node"}
+                      "err_vs_oracle": err_vs_oracle(plan, y, wl, OPS_D1_TRI, ref),
+                      "err_sample": "all 8 fields, all three directions, every node"}
         del plan, x, y
         torch.cuda.empty_cache()
     out["speedup_mixed_vs_f64"] = out["f64_banded"]["ms_per_step"] / out["mixed_dense_bf16"]["ms_per_step"]
@@ -319,7 +309,9 @@ def main():
     sched = plan.get_schedule()
     alg, rd, wr = algorithmic_bytes(wl, ops, 8)
     achieved = alg / (ev_ms * 1e-3) / 1e9
-    err64 = check_sample(plan, y, wl, ops, blocks=[0, 1, 2])
+    print("bench: oracle over every block, field and operator", file=sys.stderr, flush=True)
+    ref = oracle_reference(plan, wl, ops)
+    err64 = err_vs_oracle(plan, y, wl, ops, ref)
     result = {
         "metric": "derivative evals/s (points x fields x (dir, order) pairs), FP64, batched penta O(8) D1+D2",
         "value": evals / (ev_ms * 1e-3),
@@ -340,6 +332,7 @@ def main():
                    "schedule": {"flags": sched["flags"],
                                 "parts": ",".join(f"{n}:{xl}:{pp}" for n, xl, pp in sched["classes"])}},
         "err_vs_oracle": err64,
+        "err_scope": "every output node of every block, field and operator",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC_BYTES,
                      "algorithmic_bytes": alg, "read_bytes": rd, "write_bytes": wr},
@@ -351,13 +344,16 @@ def main():
         plan, x, y, ms32, _, _, _ = run_gpu(wl, ops, P.CFD_F32, args.steps, args.warmup,
                                             autotune=not args.no_autotune)
         alg32, _, _ = algorithmic_bytes(wl, ops, 4)
-        err32 = check_sample(plan, y, wl, ops, blocks=[0, 1, 2])
+        err32 = err_vs_oracle(plan, y, wl, ops, ref)
         result["extra"] = {"f32": {"value": evals / (ms32 * 1e-3), "ms_per_step": ms32, "err_vs_oracle": err32,
                                    "achieved_GBs": alg32 / (ms32 * 1e-3) / 1e9}}
         del x, y, plan
         torch.cuda.empty_cache()
+        del ref
         print("bench: block128", file=sys.stderr, flush=True)
         result["extra"]["block128"] = extra_block128(args.steps, args.warmup, not args.no_autotune)
+        print("bench: block128 at ng=3", file=sys.stderr, flush=True)
+        result["extra"]["block128_ng3"] = extra_block128(args.steps, args.warmup, not args.no_autotune, ng=3)
         print("bench: periodic256 precision study", file=sys.stderr, flush=True)
         result["extra"]["periodic256"] = extra_periodic256(min(args.steps, 20), args.warmup, not args.no_autotune)
         print("bench: wave192 RK4", file=sys.stderr, flush=True)

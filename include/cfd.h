@@ -114,7 +114,13 @@ cfd_status cfd_scheme_design(int d, int order, int nl, int m, double eta_c,
  *                 j = 0..nc-1, each alpha^(0)_{-mc..mc}; the right end uses the
  *                 mirror image (-1)^d c[-n].  nc must equal nl (0 for explicit).
  * The Taylor conditions up to `order` are checked on every row (residual
- * <= 1e-12 relative), else CFD_EINVAL.  nl <= 2, m <= 5, mc <= 5. */
+ * <= 1e-12 relative), else CFD_EINVAL.  The interior rows must be centred as in
+ * Eq. sch_cent_om: alpha^(d) symmetric and alpha^(0) antisymmetric for odd d,
+ * symmetric for even d (to 1e-14 relative), else CFD_EUNSUPPORTED (biased
+ * stencils are not implemented).  The symbol of the interior implicit rows,
+ * 1 + 2 a1 cos t + 2 a2 cos 2t, must stay positive on [0, pi] (the periodic
+ * system of Sec. 2.2 is singular otherwise), else CFD_ESINGULAR.
+ * nl <= 2, m <= 5, mc <= 5. */
 cfd_status cfd_scheme_create(int d, int order, int nl, const double *lhs, int m,
                              const double *rhs, int nc, int mc, const double *closure,
                              cfd_scheme **out);
@@ -177,8 +183,11 @@ typedef struct {
  * CFD_ESHAPE), builds and uploads the per-line-class tables (closure and
  * interior coefficients; partition-local LU factors, spike vectors and
  * reduced-system rows, all formed in FP64 on the GPU, Eq. sch_cent_om and its
- * matrix form Eqs. diff_mat_subL/R) and the device work lists.  Nothing is
- * allocated later by cfd_apply, so applies can be captured in a graph.
+ * matrix form Eqs. diff_mat_subL/R), the device work lists and the block
+ * layout used by the ghost exchange and the stage kernels.  Nothing is
+ * allocated later by cfd_apply, cfd_halo_exchange or the stage calls, so
+ * they can be captured in a graph.  The first plan on a device also checks
+ * how that device deals workgroups to its XCDs (see CFD_SCHED_XCD).
  * Synchronises the device once (table construction). */
 cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out);
 
@@ -192,16 +201,21 @@ cfd_status cfd_plan_offsets(const cfd_plan *p, long long *in_offsets, long long 
 /* Number of kernel launches one apply enqueues, and the number of work items. */
 cfd_status cfd_plan_stats(const cfd_plan *p, int *launches, long long *items);
 
-/* Apply every operator to every field of every block.
+/* Apply every operator to every field of every block: on every grid line the
+ * derivative solves the banded system of Eq. sch_cent_om (block closure) or
+ * the circulant system of the periodic D of Sec. 2.2, times h^-d.
  * in_dev: base of the input (element type per dtype), out_dev: base of the
- * output; both 16-byte aligned.  Enqueued on `stream`; returns immediately. */
+ * output; both 16-byte aligned, else CFD_EINVAL.  Input and output must not
+ * overlap.  Enqueued on `stream`; returns immediately.  Allocates nothing. */
 cfd_status cfd_apply(cfd_plan *p, const void *in_dev, void *out_dev, void *stream);
 
-/* Capture one apply with fixed buffers into a HIP graph owned by the plan
- * (replaces a previous capture).  Enqueues nothing. */
+/* Capture one apply (the operator of cfd_apply: Eq. sch_cent_om per line)
+ * with fixed buffers into a HIP graph owned by the plan (replaces a previous
+ * capture).  Buffers as for cfd_apply (16-byte aligned).  Enqueues nothing. */
 cfd_status cfd_plan_capture_graph(cfd_plan *p, const void *in_dev, void *out_dev, void *stream);
 
-/* Launch the captured graph on `stream`.  CFD_EINVAL if none was captured. */
+/* Launch the captured graph (one cfd_apply, Eq. sch_cent_om per line) on
+ * `stream`.  CFD_EINVAL if none was captured. */
 cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream);
 
 /* Schedule flags. */
@@ -211,23 +225,33 @@ cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream);
                                     every launch, so the x/y/z passes of a block-field
                                     stay on one L2: a persistent grid walks one queue
                                     per XCD; a per-item grid gets the items in an order
-                                    where workgroup b (on XCD b mod 8) takes its XCD's */
+                                    where each workgroup takes the item of its aligned
+                                    group of 8 that belongs to the XCD it runs on.  The
+                                    per-item form needs the device to deal workgroups
+                                    round-robin over 8 XCDs; plan creation checks that
+                                    on probe launches and, if it does not hold,
+                                    cfd_plan_set_schedule refuses the per-item form
+                                    (CFD_EUNSUPPORTED) and the autotuner skips it */
 #define CFD_SCHED_CONCURRENT 8   /* the plan's launches (e.g. the x launch and the y/z
                                     launch) run on forked streams at the same time,
                                     joined on the caller's stream before later work;
                                     with CFD_SCHED_SPLIT_X the y/z lines of blocks that
                                     need no LDS for them get a launch of their own */
 
-/* Time the candidate schedules on the given buffers and keep the fastest:
+/* Time the candidate schedules of the operator of cfd_apply (Eq.
+ * sch_cent_om per line) on the given buffers and keep the fastest:
  * the launch shape (persistent grid, XCD-aware or not, or one workgroup per
  * item; x lines fused with y/z or split; launches one after another or
  * concurrent), then under that shape the number of partitions per line for
  * every (line length, x or y/z) class, then the launch shape again.  Each
- * candidate's time is the best of three runs of 10 applies.  If cache_path
+ * candidate's time is the best of three runs of 10 applies.  The winner's
+ * output is then compared bit for bit with the plain persistent grid's (same
+ * partitions); if they differ the plain shape is kept.  If cache_path
  * is non-NULL the per-class choices are read from / appended to that text
  * file, keyed by device arch, dtype, line length, direction class, band,
- * fused operators and launch shape.  Synchronises the stream.  Invalidates a
- * captured graph. */
+ * fused operators and launch shape.  Overwrites out_dev.  Allocates a
+ * temporary output-sized buffer for the check.  Synchronises the stream.
+ * Invalidates a captured graph. */
 cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, void *stream,
                              const char *cache_path);
 
@@ -308,6 +332,17 @@ cfd_status cfd_wave_rk_stage(cfd_plan *p, const void *u0_dev, const void *src_de
 cfd_status cfd_wave_rk_stage_halo(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev,
                                   const void *acc_in_dev, void *acc_dev, const void *derivs_dev, double a, double b,
                                   int bx, int by, int bz, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Test hook                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Make the library's n-th following device allocation (n = 0: the next one)
+ * fail as if the device were out of memory; n < 0 turns the hook off.  For
+ * tests of the CFD_ENOMEM paths: every call that allocates returns CFD_ENOMEM
+ * and frees what it had allocated.  Process-wide, not thread-safe against
+ * concurrent plan creation. */
+void cfd_debug_fail_alloc(long long n);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,10 @@ product library never does, and the two share no code.
   matched closures) in exact or high-precision arithmetic.
 * ``oracle.lines``    - FP64 line operator: explicit RHS stencil, closure rows,
   banded elimination, cyclic (periodic) solve; plain C behind ctypes.
-* ``oracle.dense``    - dense assembled matrices of Eqs. diff_mat_subL/R and
-  the embedded operator of Eq. iter_scheme, solved with numpy (pins only).
+* ``oracle.wave``     - the first-order wave system under classical RK4: the
+  closed-form evolution of one Fourier mode and a plain stepped integrator.
+
+The dense assembled matrices of Eqs. diff_mat_subL/R and the embedded
+operator of Eq. iter_scheme that pin ``oracle.lines`` are written out in the
+tests themselves (``tests/test_oracle_lines.py``), with numpy.
 """

@@ -254,6 +254,11 @@ def cfd_axpby(a: float, x, b: float, y, stream=None) -> None:
                           _stream_ptr(stream)))
 
 
+def cfd_debug_fail_alloc(n: int) -> None:
+    """Test hook: the library's n-th following device allocation fails (n < 0: off)."""
+    lib().cfd_debug_fail_alloc(int(n))
+
+
 def cfd_xpcy(x, c: float, y, z, stream=None) -> None:
     """z = x + c*y on the GPU."""
     check(lib().cfd_xpcy(_dtype_code(z), z.numel(), _dev_ptr(x), float(c), _dev_ptr(y), _dev_ptr(z),

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -21,6 +22,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <tuple>
@@ -43,7 +45,27 @@ cfd_status fail(cfd_status st, const std::string &msg) {
 cfd_status hip_fail(hipError_t e, const char *what) {
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
     (void)hipGetLastError();
-    return fail(CFD_EDEVICE, m);
+    return fail(e == hipErrorOutOfMemory ? CFD_ENOMEM : CFD_EDEVICE, m);
+}
+
+// Every device allocation of the library goes through dmalloc.  A test hook
+// (cfd_debug_fail_alloc) can make the n-th following allocation fail as if the
+// device were out of memory, to check that every failure path returns
+// CFD_ENOMEM and frees what it had allocated.
+std::atomic<long long> g_alloc_fail_after{-1};
+
+hipError_t dmalloc(void **ptr, size_t bytes) {
+    long long n = g_alloc_fail_after.load();
+    while (n >= 0) {
+        if (g_alloc_fail_after.compare_exchange_weak(n, n - 1)) {
+            if (n == 0) {
+                *ptr = nullptr;
+                return hipErrorOutOfMemory;
+            }
+            break;
+        }
+    }
+    return hipMalloc(ptr, bytes);
 }
 
 #define HIPCHK(expr)                                   \
@@ -117,6 +139,8 @@ struct cfd_plan {
     bool concurrent = false;              // kernel groups on forked streams, joined at the end
     int cus = 256;
     size_t max_lds = 65536;
+    bool xcd_interleave_ok = false;       // dispatch check passed: the XCD-interleaved per-item order covers every item
+    int64_t nunits = 0;                   // 64-node row pieces of all blocks (stage kernels)
     // device state rebuilt by build()
     DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff, d_qoff, d_outoff, d_shapes;
     DevBuf d_dense, d_dense_specs;        // dense mixed-precision tables
@@ -286,6 +310,47 @@ std::vector<PassDesc> pass_descs(const cfd_plan *p, const std::vector<std::array
 
 cfd_status build_dense(cfd_plan *p);
 
+// Does this device deal a launch's workgroups round-robin over its kXCDq
+// XCDs, so that every aligned group of kXCDq consecutive workgroups runs on
+// kXCDq distinct XCDs?  The XCD-interleaved per-item order (each workgroup
+// takes the item of its group that belongs to the XCD it runs on) covers every
+// item only then.  Checked once per device on probe launches of several grid
+// sizes (the first XCD of a launch varies), the result cached.
+bool xcd_dispatch_ok(int device) {
+    static std::mutex mu;
+    static std::map<int, bool> known;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = known.find(device);
+    if (it != known.end()) return it->second;
+    bool ok = true;
+    const int grids[] = {8 * 512, 8 * 64 + 3, 8 * 300 + 5, 8 * 1024, 8 * 33 + 1, 8 * 700};
+    int *d = nullptr;
+    std::vector<int> h(8 * 1024);
+    if (dmalloc((void **)&d, h.size() * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;   // not cached: a later plan may retry
+    }
+    for (int rep = 0; rep < 3 && ok; ++rep)
+        for (int g : grids) {
+            hipError_t e = launch_xcc_probe(g, d, nullptr);
+            if (e == hipSuccess) e = hipMemcpy(h.data(), d, g * sizeof(int), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                ok = false;
+                break;
+            }
+            for (int b0 = 0; b0 + kXCDq <= g && ok; b0 += kXCDq) {
+                unsigned seen = 0;
+                for (int k = 0; k < kXCDq; ++k) seen |= 1u << (h[b0 + k] & (kXCDq - 1));
+                ok = seen == (1u << kXCDq) - 1;
+            }
+            if (!ok) break;
+        }
+    (void)hipFree(d);
+    (void)hipGetLastError();
+    known[device] = ok;
+    return ok;
+}
+
 cfd_status build_groups(cfd_plan *p) {
     HIPCHK(hipSetDevice(p->device));
     p->drop_graph();
@@ -365,14 +430,14 @@ cfd_status build_groups(cfd_plan *p) {
     p->d_tab64.release();
     p->d_tab32.release();
     p->d_taboff.release();
-    HIPCHK(hipMalloc(&p->d_tab64.p, total * sizeof(double)));
+    HIPCHK(dmalloc((void **)&p->d_tab64.p, total * sizeof(double)));
     HIPCHK(hipMemcpy(p->d_tab64.p, host_tab.data(), total * sizeof(double), hipMemcpyHostToDevice));
     {
         void *d_specs = nullptr, *d_scratch = nullptr, *d_status = nullptr;
         const int ntab = (int)keys.size();
-        hipError_t e = hipMalloc(&d_specs, specs.size());
-        if (e == hipSuccess) e = hipMalloc(&d_scratch, std::max<int64_t>(1, scratch_per * ntab) * sizeof(double));
-        if (e == hipSuccess) e = hipMalloc(&d_status, ntab * sizeof(int));
+        hipError_t e = dmalloc((void **)&d_specs, specs.size());
+        if (e == hipSuccess) e = dmalloc((void **)&d_scratch, std::max<int64_t>(1, scratch_per * ntab) * sizeof(double));
+        if (e == hipSuccess) e = dmalloc((void **)&d_status, ntab * sizeof(int));
         if (e == hipSuccess) e = hipMemcpy(d_specs, specs.data(), specs.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = launch_build_tables(ntab, d_specs, (double *)p->d_tab64.p, (double *)d_scratch, scratch_per,
@@ -390,17 +455,17 @@ cfd_status build_groups(cfd_plan *p) {
                                                "' cannot be factored without pivoting");
     }
     if (f32) {
-        HIPCHK(hipMalloc(&p->d_tab32.p, total * sizeof(float)));
+        HIPCHK(dmalloc((void **)&p->d_tab32.p, total * sizeof(float)));
         hipError_t e = launch_to_f32(total, (const double *)p->d_tab64.p, (float *)p->d_tab32.p, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "converting tables to FP32");
     }
-    HIPCHK(hipMalloc(&p->d_taboff.p, std::max<size_t>(1, offs.size()) * sizeof(int64_t)));
+    HIPCHK(dmalloc((void **)&p->d_taboff.p, std::max<size_t>(1, offs.size()) * sizeof(int64_t)));
     HIPCHK(hipMemcpy(p->d_taboff.p, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice));
 
     std::vector<PassDesc> pd = pass_descs(p, pass_tab);
     p->d_pass.release();
-    HIPCHK(hipMalloc(&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
+    HIPCHK(dmalloc((void **)&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
 
     // 4. work items.  One launch group per kernel class (x lines optionally in
@@ -492,7 +557,7 @@ cfd_status build_groups(cfd_plan *p) {
         (void)hipGetLastError();
         g.grid_persist = (int)std::min<int64_t>(g.nitems, (int64_t)nb * p->cus);
         g.qoff_index = -1;
-        if (p->xcd && g.nitems >= 8 * kXCDq) {
+        if (p->xcd && g.nitems >= 8 * kXCDq && (p->persistent || p->xcd_interleave_ok)) {
             std::vector<std::vector<WorkItem>> q(kXCDq);
             for (size_t e = 0; e < gitems[gi].size(); ++e) q[bf_queue[gbf[gi][e]]].push_back(gitems[gi][e]);
             if (p->persistent) {
@@ -526,12 +591,12 @@ cfd_status build_groups(cfd_plan *p) {
     p->groups = groups;
     p->d_qoff.release();
     if (!qoffs.empty()) {
-        HIPCHK(hipMalloc(&p->d_qoff.p, qoffs.size() * sizeof(int)));
+        HIPCHK(dmalloc((void **)&p->d_qoff.p, qoffs.size() * sizeof(int)));
         HIPCHK(hipMemcpy(p->d_qoff.p, qoffs.data(), qoffs.size() * sizeof(int), hipMemcpyHostToDevice));
     }
     p->nitems = (int64_t)items.size();
     p->d_items.release();
-    HIPCHK(hipMalloc(&p->d_items.p, std::max<size_t>(1, items.size()) * sizeof(WorkItem)));
+    HIPCHK(dmalloc((void **)&p->d_items.p, std::max<size_t>(1, items.size()) * sizeof(WorkItem)));
     HIPCHK(hipMemcpy(p->d_items.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
     return CFD_OK;
 }
@@ -575,14 +640,14 @@ cfd_status build_dense(cfd_plan *p) {
     }
     p->d_dense.release();
     p->d_dense_specs.release();
-    HIPCHK(hipMalloc(&p->d_dense.p, std::max<int64_t>(total, 256)));
-    HIPCHK(hipMalloc(&p->d_dense_specs.p, specs.size()));
+    HIPCHK(dmalloc((void **)&p->d_dense.p, std::max<int64_t>(total, 256)));
+    HIPCHK(dmalloc((void **)&p->d_dense_specs.p, specs.size()));
     HIPCHK(hipMemcpy(p->d_dense_specs.p, specs.data(), specs.size(), hipMemcpyHostToDevice));
     {
         void *d_coefs = nullptr, *d_scratch = nullptr, *d_status = nullptr;
-        hipError_t e = hipMalloc(&d_coefs, coefs.size() * sizeof(double));
-        if (e == hipSuccess) e = hipMalloc(&d_scratch, scratch_per * ntab * sizeof(double));
-        if (e == hipSuccess) e = hipMalloc(&d_status, ntab * sizeof(int));
+        hipError_t e = dmalloc((void **)&d_coefs, coefs.size() * sizeof(double));
+        if (e == hipSuccess) e = dmalloc((void **)&d_scratch, scratch_per * ntab * sizeof(double));
+        if (e == hipSuccess) e = dmalloc((void **)&d_status, ntab * sizeof(int));
         if (e == hipSuccess) e = hipMemcpy(d_coefs, coefs.data(), coefs.size() * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = launch_dense_form(ntab, p->d_dense_specs.p, (const double *)d_coefs, (unsigned char *)p->d_dense.p,
@@ -602,7 +667,7 @@ cfd_status build_dense(cfd_plan *p) {
         if (q.in_fstride * 4 >= (int64_t(1) << 32) || q.out_fstride * 4 >= (int64_t(1) << 32))
             return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: a field exceeds 4 GiB");
     p->d_pass.release();
-    HIPCHK(hipMalloc(&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
+    HIPCHK(dmalloc((void **)&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
     // work items: dense_item_lines() lines of one pass and field; one group
     // (kernel) per (N, x or not).  Items of one table are kept together: a
@@ -648,7 +713,7 @@ cfd_status build_dense(cfd_plan *p) {
     }
     p->nitems = (int64_t)(items.size() / isz);
     p->d_items.release();
-    HIPCHK(hipMalloc(&p->d_items.p, std::max<size_t>(1, items.size())));
+    HIPCHK(dmalloc((void **)&p->d_items.p, std::max<size_t>(1, items.size())));
     HIPCHK(hipMemcpy(p->d_items.p, items.data(), items.size(), hipMemcpyHostToDevice));
     return CFD_OK;
 }
@@ -686,6 +751,34 @@ cfd_status ensure_aux(cfd_plan *p) {
     return CFD_OK;
 }
 
+// Block layout on the device, read by the ghost exchange and the stage
+// kernels: input and output offsets per block, and per block (nx, ny, nz, ng)
+// followed by the first 64-node row piece of each block and their total.
+// Uploaded once at plan creation, so those calls allocate nothing.
+cfd_status upload_layout(cfd_plan *p) {
+    const int nb = (int)p->blocks.size();
+    std::vector<int> sh(4 * nb + nb + 1);
+    int64_t units = 0;
+    for (int b = 0; b < nb; ++b) {
+        const cfd_block &bl = p->blocks[b];
+        sh[4 * b] = bl.n[0];
+        sh[4 * b + 1] = bl.n[1];
+        sh[4 * b + 2] = bl.n[2];
+        sh[4 * b + 3] = bl.ng;
+        sh[4 * nb + b] = (int)std::min<int64_t>(units, INT32_MAX);
+        units += (int64_t)bl.n[1] * bl.n[2] * ((bl.n[0] + 63) / 64);
+    }
+    sh[4 * nb + nb] = (int)std::min<int64_t>(units, INT32_MAX);
+    p->nunits = units;
+    HIPCHK(dmalloc((void **)&p->d_shapes.p, sh.size() * sizeof(int)));
+    HIPCHK(hipMemcpy(p->d_shapes.p, sh.data(), sh.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(dmalloc((void **)&p->d_outoff.p, nb * sizeof(int64_t)));
+    HIPCHK(hipMemcpy(p->d_outoff.p, p->out_off.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(dmalloc((void **)&p->d_inoff.p, nb * sizeof(int64_t)));
+    HIPCHK(hipMemcpy(p->d_inoff.p, p->in_off.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+    return CFD_OK;
+}
+
 // Device tables, work lists and launch groups for the current schedule.
 cfd_status build(cfd_plan *p) {
     cfd_status r = build_groups(p);
@@ -717,6 +810,56 @@ cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
         if (r != CFD_OK) return r;
     }
     return CFD_OK;
+}
+
+// Apply the plan with its current schedule into out_dev, and with the plain
+// persistent grid (same partitions, no XCD order, no split, sequential) into
+// a temporary buffer; same = every 32-bit word of the two outputs agrees.
+// Both buffers are first filled with the same pattern, so output words no
+// item writes (gaps between explicitly placed blocks) compare equal.
+cfd_status same_as_plain(cfd_plan *p, const void *in_dev, void *out_dev, hipStream_t st, bool &same) {
+    const size_t bytes = (size_t)p->out_elems * elem_size(p->dtype);
+    same = true;
+    if (bytes == 0) return CFD_OK;
+    void *tmp = nullptr;
+    unsigned long long *cnt = nullptr;
+    hipError_t e = dmalloc(&tmp, bytes);
+    if (e == hipSuccess) e = dmalloc((void **)&cnt, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        if (tmp) (void)hipFree(tmp);
+        return hip_fail(e, "autotune check buffer");
+    }
+    const bool pe = p->persistent, xc = p->xcd, sx = p->split_x, cc = p->concurrent;
+    cfd_status r = CFD_OK;
+    e = hipMemsetAsync(out_dev, 0x7f, bytes, st);
+    if (e == hipSuccess) e = hipMemsetAsync(tmp, 0x7f, bytes, st);
+    if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st);
+    if (e != hipSuccess) r = hip_fail(e, "autotune check fill");
+    if (r == CFD_OK) r = enqueue(p, in_dev, out_dev, st);
+    if (r == CFD_OK) {
+        p->persistent = true;
+        p->xcd = p->split_x = p->concurrent = false;
+        r = build(p);
+        if (r == CFD_OK) r = enqueue(p, in_dev, tmp, st);
+        p->persistent = pe;
+        p->xcd = xc;
+        p->split_x = sx;
+        p->concurrent = cc;
+        cfd_status r2 = build(p);
+        if (r == CFD_OK) r = r2;
+    }
+    unsigned long long diff = 0;
+    if (r == CFD_OK) {
+        e = launch_count_diff((int64_t)(bytes / 4), out_dev, tmp, cnt, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&diff, cnt, sizeof diff, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) r = hip_fail(e, "autotune check");
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(tmp);
+    (void)hipFree(cnt);
+    same = diff == 0;
+    return r;
 }
 
 }  // namespace
@@ -777,6 +920,8 @@ cfd_status cfd_scheme_create(int d, int order, int nl, const double *lhs, int m,
         for (int k = -mc; k <= mc; ++k) s.cl[r][kMaxHalf + k] = closure[r * (2 * mc + 1) + mc + k];
     std::string err;
     cfd_status st = check_taylor(s, err);
+    if (st == CFD_OK) st = check_centred(s, err);
+    if (st == CFD_OK) st = check_symbol(s, err);
     if (st != CFD_OK) return fail(st, "cfd_scheme_create: " + err);
     s.name = "custom";
     *out = new cfd_scheme{s};
@@ -924,6 +1069,12 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
                     if (used[o2] || p->ops[o2].field != p->ops[o].field) continue;
                     const Scheme &s1 = p->schemes[o2];
                     if (s1.nl != s0.nl || s0.nl == 0 || (s0.d % 2) == (s1.d % 2)) continue;
+                    // fuse only where a two-operator kernel class is compiled
+                    const bool per = bl.boundary[d] == CFD_BOUNDARY_PERIODIC;
+                    const int mi2 = std::max(s0.m, s1.m);
+                    const int hw2 = std::max(std::max(s0.m, per ? 0 : s0.mc), std::max(s1.m, per ? 0 : s1.mc));
+                    int Ls[16];
+                    if (line_class_Ls(desc->dtype != CFD_F64, s0.nl, 2, 1, mi2, hw2, Ls, 16) == 0) continue;
                     partner = o2;
                     break;
                 }
@@ -966,7 +1117,9 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
         }
         (void)hipGetLastError();
     }
-    cfd_status st = build(p.get());
+    p->xcd_interleave_ok = xcd_dispatch_ok(p->device);
+    cfd_status st = upload_layout(p.get());
+    if (st == CFD_OK) st = build(p.get());
     if (st != CFD_OK) {
         p->release();
         return st;
@@ -1000,9 +1153,8 @@ cfd_status cfd_plan_stats(const cfd_plan *p, int *launches, long long *items) {
 
 cfd_status cfd_apply(cfd_plan *p, const void *in_dev, void *out_dev, void *stream) {
     if (!p || !in_dev || !out_dev) return fail(CFD_EINVAL, "cfd_apply: null argument");
-    const size_t es = elem_size(p->dtype);
-    if (((uintptr_t)in_dev % es) || ((uintptr_t)out_dev % es))
-        return fail(CFD_EINVAL, "cfd_apply: misaligned buffer");
+    if (((uintptr_t)in_dev % 16) || ((uintptr_t)out_dev % 16))
+        return fail(CFD_EINVAL, "cfd_apply: buffers must be 16-byte aligned");
     HIPCHK(hipSetDevice(p->device));
     return enqueue(p, in_dev, out_dev, (hipStream_t)stream);
 }
@@ -1010,6 +1162,8 @@ cfd_status cfd_apply(cfd_plan *p, const void *in_dev, void *out_dev, void *strea
 cfd_status cfd_plan_capture_graph(cfd_plan *p, const void *in_dev, void *out_dev, void *stream) {
     (void)stream;
     if (!p || !in_dev || !out_dev) return fail(CFD_EINVAL, "cfd_plan_capture_graph: null argument");
+    if (((uintptr_t)in_dev % 16) || ((uintptr_t)out_dev % 16))
+        return fail(CFD_EINVAL, "cfd_plan_capture_graph: buffers must be 16-byte aligned");
     HIPCHK(hipSetDevice(p->device));
     p->drop_graph();
     if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
@@ -1062,6 +1216,9 @@ cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions,
             p->sched_P.erase(key);
         }
     }
+    if ((flags & CFD_SCHED_XCD) && !(flags & CFD_SCHED_PERSISTENT) && !p->xcd_interleave_ok && p->dtype != CFD_MIXED_BF16)
+        return fail(CFD_EUNSUPPORTED, "cfd_plan_set_schedule: the XCD-interleaved per-item order needs workgroups "
+                                      "dealt round-robin over 8 XCDs, which this device did not show");
     p->persistent = (flags & CFD_SCHED_PERSISTENT) != 0;
     p->split_x = (flags & CFD_SCHED_SPLIT_X) != 0;
     p->xcd = (flags & CFD_SCHED_XCD) != 0;
@@ -1161,7 +1318,8 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         // mode: 0 per-item grid, 1 persistent, 2 persistent with XCD queues,
         // 3 per-item grid in XCD-interleaved order
         for (int mode = 0; mode < 4 && r == CFD_OK; ++mode)
-            for (int split = 0; split <= 1 && r == CFD_OK; ++split)
+            for (int split = 0; split <= 1 && r == CFD_OK; ++split) {
+                if (mode == 3 && !p->xcd_interleave_ok) break;
                 for (int conc = 0; conc <= 1 && r == CFD_OK; ++conc) {
                     p->persistent = mode == 1 || mode == 2;
                     p->xcd = mode >= 2;
@@ -1173,6 +1331,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
                     if (r == CFD_OK) r = time_apply(ms);
                     if (r == CFD_OK && ms < best) { best = ms; bmode = mode; bs = split; bc = conc; }
                 }
+            }
         p->persistent = bmode == 1 || bmode == 2;
         p->xcd = bmode >= 2;
         p->split_x = bs;
@@ -1217,7 +1376,22 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         std::ofstream f(cache_path, std::ios::app);
         for (const std::string &l : new_lines) f << l << "\n";
     }
-    return build(p);
+    result = build(p);
+    // The winner must give bit for bit what the plain persistent grid gives
+    // with the same partitions (the launch shape only decides which
+    // workgroup runs which item); otherwise fall back to the plain shape.
+    if (result == CFD_OK) {
+        bool same = false;
+        result = same_as_plain(p, in_dev, out_dev, st, same);
+        if (result == CFD_OK && !same) {
+            p->persistent = true;
+            p->xcd = false;
+            p->split_x = false;
+            p->concurrent = false;
+            result = build(p);
+        }
+    }
+    return result;
 }
 
 cfd_status cfd_plan_get_schedule(const cfd_plan *p, int *persistent, int *split_x, int *n_classes, int *N,
@@ -1264,10 +1438,6 @@ cfd_status cfd_halo_exchange(cfd_plan *p, void *data_dev, int bx, int by, int bz
             return fail(CFD_EUNSUPPORTED, "cfd_halo_exchange: block or lattice too large");
     }
     HIPCHK(hipSetDevice(p->device));
-    if (!p->d_inoff.p) {
-        HIPCHK(hipMalloc(&p->d_inoff.p, p->in_off.size() * sizeof(int64_t)));
-        HIPCHK(hipMemcpy(p->d_inoff.p, p->in_off.data(), p->in_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-    }
     hipError_t e = launch_halo(p->dtype != CFD_F64, data_dev, (const int64_t *)p->d_inoff.p, b0.n[0], b0.n[1],
                                b0.n[2], b0.ng, p->nfields, bx, by, bz, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launching halo exchange");
@@ -1308,32 +1478,8 @@ cfd_status wave_stage(cfd_plan *p, const void *u0_dev, const void *src_dev, void
     if (p->dtype != CFD_F64 && p->dtype != CFD_F32) return fail(CFD_EINVAL, "cfd_wave_rk_stage: dtype");
     HIPCHK(hipSetDevice(p->device));
     const int nb = (int)p->blocks.size();
-    // shapes: nx, ny, nz, ng per block, then the first 64-node row piece of each block (and the total)
-    int64_t nunits64 = 0;
-    for (const cfd_block &bl : p->blocks) nunits64 += (int64_t)bl.n[1] * bl.n[2] * ((bl.n[0] + 63) / 64);
-    if (nunits64 >= (int64_t(1) << 31)) return fail(CFD_EUNSUPPORTED, "cfd_wave_rk_stage: grid too large");
-    if (!p->d_shapes.p) {
-        std::vector<int> sh(4 * nb + nb + 1);
-        int units = 0;
-        for (int b = 0; b < nb; ++b) {
-            const cfd_block &bl = p->blocks[b];
-            sh[4 * b] = bl.n[0];
-            sh[4 * b + 1] = bl.n[1];
-            sh[4 * b + 2] = bl.n[2];
-            sh[4 * b + 3] = bl.ng;
-            sh[4 * nb + b] = units;
-            units += bl.n[1] * bl.n[2] * ((bl.n[0] + 63) / 64);
-        }
-        sh[4 * nb + nb] = units;
-        HIPCHK(hipMalloc(&p->d_shapes.p, sh.size() * sizeof(int)));
-        HIPCHK(hipMemcpy(p->d_shapes.p, sh.data(), sh.size() * sizeof(int), hipMemcpyHostToDevice));
-        HIPCHK(hipMalloc(&p->d_outoff.p, nb * sizeof(int64_t)));
-        HIPCHK(hipMemcpy(p->d_outoff.p, p->out_off.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
-    }
-    if (!p->d_inoff.p) {
-        HIPCHK(hipMalloc(&p->d_inoff.p, p->in_off.size() * sizeof(int64_t)));
-        HIPCHK(hipMemcpy(p->d_inoff.p, p->in_off.data(), p->in_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-    }
+    if (p->nunits >= (int64_t(1) << 31)) return fail(CFD_EUNSUPPORTED, "cfd_wave_rk_stage: grid too large");
+    const int64_t nunits64 = p->nunits;
     if (!acc_in_dev) acc_in_dev = acc_dev;
     const int *shapes = (const int *)p->d_shapes.p;
     hipError_t e = launch_wave_stage(p->dtype == CFD_F32, u0_dev, src_dev, stage_dev, acc_in_dev, acc_dev, derivs_dev,
@@ -1364,6 +1510,8 @@ cfd_status cfd_wave_rk_stage_halo(cfd_plan *p, const void *u0_dev, const void *s
         if (b0.ng > b0.n[d]) return fail(CFD_ESHAPE, "cfd_wave_rk_stage_halo: ghost width exceeds block extent");
     return wave_stage(p, u0_dev, src_dev, stage_dev, acc_in_dev, acc_dev, derivs_dev, a, b, bx, by, bz, stream);
 }
+
+void cfd_debug_fail_alloc(long long n) { g_alloc_fail_after.store(n < 0 ? -1 : n); }
 
 void cfd_plan_destroy(cfd_plan *p) {
     if (!p) return;

@@ -38,6 +38,8 @@ cfd_status design_centred(int d, int order, int nl, int m, double eta_c, int clo
                           int matched, Scheme &out, std::string &err);
 cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &err);
 cfd_status check_taylor(const Scheme &s, std::string &err);
+cfd_status check_centred(const Scheme &s, std::string &err);
+cfd_status check_symbol(const Scheme &s, std::string &err);
 int required_ghosts(const Scheme &s, int periodic);
 
 // ---------------------------------------------------------------------------
@@ -112,6 +114,8 @@ hipError_t launch_lines(const void *fn, int grid, size_t lds, hipStream_t st, co
 hipError_t launch_build_tables(int ntab, const void *specs, double *data, double *scratch, int64_t scratch_per,
                                int *status, hipStream_t st);
 hipError_t launch_to_f32(int64_t n, const double *a, float *b, hipStream_t st);
+hipError_t launch_xcc_probe(int grid, int *out, hipStream_t st);
+hipError_t launch_count_diff(int64_t nwords, const void *a, const void *b, unsigned long long *cnt, hipStream_t st);
 size_t tabspec_size();
 void fill_tabspec(void *dst, int N, int P, int L, int nl, int nc, int periodic, const double *alpha5,
                   int64_t off);

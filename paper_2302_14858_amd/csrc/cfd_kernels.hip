@@ -3,6 +3,7 @@
 // the FP64 instantiations of the line kernel (cfd_lines.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "cfd_internal.h"
@@ -181,6 +182,24 @@ __global__ void k_build_tables(int ntab, const TabSpec *__restrict__ specs, doub
     status[t] = bad;
 }
 
+// XCD (accelerator complex die) that runs each workgroup, one record per
+// workgroup: the plan checks on it that every aligned group of kXCD
+// consecutive workgroups is spread over all kXCD dies before it offers the
+// XCD-interleaved per-item order.
+__global__ void k_xcc_probe(int *__restrict__ out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);   // HW_REG_XCC_ID
+}
+
+// Number of 32-bit words that differ between a and b (bitwise).
+__global__ void k_count_diff(int64_t n, const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+                             unsigned long long *__restrict__ cnt) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += a[i] != b[i];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
+}
+
 __global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = (float)a[i];
@@ -247,6 +266,18 @@ hipError_t launch_to_f32(int64_t n, const double *a, float *b, hipStream_t st) {
     if (grid > 4096) grid = 4096;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_to_f32, dim3(grid), dim3(256), 0, st, n, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_xcc_probe(int grid, int *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_xcc_probe, dim3(grid), dim3(64), 0, st, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_diff(int64_t nwords, const void *a, const void *b, unsigned long long *cnt, hipStream_t st) {
+    int grid = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (nwords + 255) / 256));
+    hipLaunchKernelGGL(k_count_diff, dim3(grid), dim3(256), 0, st, nwords, (const uint32_t *)a, (const uint32_t *)b,
+                       cnt);
     return hipGetLastError();
 }
 

@@ -109,8 +109,15 @@ __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS
     // side) is requested before any arithmetic, so all of the partition's loads
     // are in flight together.  x lines: the caller has read fin from the tile.
     if constexpr (!X) {
-        const bool lo_edge = c.p == 0;
-        const bool hi_edge = c.p == c.P - 1;
+        // a partition's halo can also leave the stored line (nodes -ng ..
+        // N+ng-1) when the compiled ring half-width HW exceeds what the
+        // scheme needs (e.g. an explicit 6th-order stencil at ng = 3 in a
+        // class compiled for half-width 5): such loads go through edge_load,
+        // which reads zeros there (the stencil weights beyond the scheme's
+        // reach are zero).  Periodic lines wrap, and an inner partition's halo
+        // stays inside the line because L >= HW.
+        const bool lo_edge = c.p == 0 || (!c.periodic && k0 - HW < -ng);
+        const bool hi_edge = c.p == c.P - 1 || (!c.periodic && k0 + L + HW > N + ng);
         // walk a pointer along the line: one stride add per node keeps the
         // addresses in vector registers instead of one scalar offset per node
         const T *q = c.src + (int64_t)(k0 - HW) * sd;

@@ -377,6 +377,11 @@ cfd_status design_centred(int d, int order, int nl, int m, double eta_c, int clo
         s.mc = closure_mc;
         for (int j = 0; j < nl; ++j) std::memcpy(s.cl[j], row, sizeof(row));
     }
+    cfd_status sst = check_symbol(s, err);
+    if (sst != CFD_OK) {
+        err = "scheme design: " + err;
+        return sst;
+    }
     out = s;
     return CFD_OK;
 }
@@ -452,6 +457,58 @@ cfd_status check_taylor(const Scheme &s, std::string &err) {
                 return CFD_EINVAL;
             }
         }
+    }
+    return CFD_OK;
+}
+
+// Centred form the line kernels rely on: they evaluate the interior RHS from
+// the m > 0 half of alpha^(0) in symmetric form, so alpha^(0) must be
+// antisymmetric for odd d and symmetric for even d, and alpha^(d) symmetric
+// (Eq. sch_cent_om uses centred interior rows).  Biased stencils are rejected.
+cfd_status check_centred(const Scheme &s, std::string &err) {
+    double scale = 0;
+    for (double v : s.rhs) scale = std::fmax(scale, std::fabs(v));
+    for (double v : s.lhs) scale = std::fmax(scale, std::fabs(v));
+    const double tol = 1e-14 * std::fmax(1.0, scale);
+    const double sgn = (s.d % 2) ? -1.0 : 1.0;
+    for (int k = 1; k <= kMaxHalf; ++k)
+        if (std::fabs(s.rhs[kMaxHalf - k] - sgn * s.rhs[kMaxHalf + k]) > tol) {
+            err = (s.d % 2) ? "interior stencil alpha^(0) is not antisymmetric (biased stencils are not supported)"
+                            : "interior stencil alpha^(0) is not symmetric (biased stencils are not supported)";
+            return CFD_EUNSUPPORTED;
+        }
+    if (s.d % 2 && std::fabs(s.rhs[kMaxHalf]) > tol) {
+        err = "interior stencil alpha^(0) of an odd derivative has a nonzero centre weight";
+        return CFD_EUNSUPPORTED;
+    }
+    for (int j = 1; j <= kMaxNL; ++j)
+        if (std::fabs(s.lhs[kMaxNL - j] - s.lhs[kMaxNL + j]) > tol) {
+            err = "implicit stencil alpha^(d) is not symmetric (biased stencils are not supported)";
+            return CFD_EUNSUPPORTED;
+        }
+    return CFD_OK;
+}
+
+// The symbol of the interior rows of D_L, 1 + 2 a1 cos t + 2 a2 cos 2t
+// (periodic D of Sec. 2.2; a centred alpha^(d)), must stay positive on
+// [0, pi]: a zero makes the periodic matrix singular for some N and the
+// closure systems lose the diagonal strength no-pivot elimination relies on.
+// With c = cos t it is the quadratic (1 - 2 a2) + 2 a1 c + 4 a2 c^2 on
+// [-1, 1]; its minimum is taken at an end or at the vertex.
+cfd_status check_symbol(const Scheme &s, std::string &err) {
+    const double a1 = s.lhs[kMaxNL + 1], a2 = s.lhs[kMaxNL + 2];
+    auto sym = [&](double c) { return (1.0 - 2.0 * a2) + 2.0 * a1 * c + 4.0 * a2 * c * c; };
+    double mn = std::fmin(sym(-1.0), sym(1.0));
+    if (a2 != 0.0) {
+        const double cv = -a1 / (4.0 * a2);
+        if (cv > -1.0 && cv < 1.0) mn = std::fmin(mn, sym(cv));
+    }
+    if (!(mn > 1e-12)) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "implicit stencil symbol 1 + 2a1 cos t + 2a2 cos 2t reaches %.3g <= 0 "
+                                       "(singular periodic system)", mn);
+        err = buf;
+        return CFD_ESINGULAR;
     }
     return CFD_OK;
 }

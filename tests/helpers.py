@@ -100,3 +100,69 @@ def max_rel_err(gpu, ora):
             for f, ref in enumerate(fl):
                 worst = max(worst, rel_err(gpu[b][o][f], ref))
     return worst
+
+
+def oracle_flat(wl, ops, ooffs, nout, blocks=None):
+    """The oracle's result in the plan's packed output layout (float64, NaN where nothing is written)."""
+    ref = np.full(nout, np.nan)
+    nf = op_fields(wl, ops)
+    schemes = {op[0]: OS.named(op[0]) for op in ops}
+    blocks = range(len(wl.blocks)) if blocks is None else blocks
+    for b in blocks:
+        blk = wl.blocks[b]
+        nx, ny, nz = blk.n
+        npts = nx * ny * nz
+        slot = 0
+        for o, op in enumerate(ops):
+            d = op[1]
+            fsel = list(range(wl.nfields)) if (len(op) < 3 or op[2] < 0) else [op[2]]
+            for j, f in enumerate(fsel):
+                off = ooffs[b] + (slot + j) * npts
+                view = ref[off:off + npts].reshape(nz, ny, nx)
+                OL.apply_block(schemes[op[0]], wl.field_view(b, f), blk.ng, blk.h[d], d,
+                               periodic=blk.boundary[d] == synth.PERIODIC, out=view)
+            slot += nf[o]
+    return ref
+
+
+def compare_flat(got, ref, wl, ops, ooffs, blocks=None):
+    """Worst relative max-norm error over every (block, operator, field) and every node.
+
+    ``got`` is the whole output buffer as float64.  Raises if any output node is NaN or
+    if a node the oracle defines was not written (the buffer is NaN-prefilled)."""
+    assert got.shape == ref.shape
+    written = ~np.isnan(ref)
+    bad = np.isnan(got) & written
+    assert not bad.any(), f"{int(bad.sum())} output nodes left unwritten (NaN), first at {int(np.argmax(bad))}"
+    assert np.isfinite(got[written]).all(), "non-finite output"
+    nf = op_fields(wl, ops)
+    blocks = range(len(wl.blocks)) if blocks is None else blocks
+    worst = 0.0
+    for b in blocks:
+        blk = wl.blocks[b]
+        npts = int(np.prod(blk.n))
+        for s in range(sum(nf)):
+            off = ooffs[b] + s * npts
+            worst = max(worst, rel_err(got[off:off + npts], ref[off:off + npts]))
+    return worst
+
+
+def full_parity(plan, wl, ops, dtype=0, ref=None):
+    """Apply the plan once (eager, NaN-prefilled output) and return the worst relative error over
+    every output node against the oracle (see compare_flat)."""
+    import torch
+    tdt = torch.float64 if dtype == 0 else torch.float32
+    _, nout = plan.sizes()
+    _, ooffs = plan.offsets()
+    x = torch.from_numpy(wl.data).to(device="cuda", dtype=tdt)
+    y = torch.full((nout,), float("nan"), dtype=tdt, device="cuda")
+    plan.apply(x, y)
+    torch.cuda.synchronize()
+    got = y.double().cpu().numpy()
+    if ref is None:
+        ref = oracle_flat(wl, ops, ooffs, nout)
+    return compare_flat(got, ref, wl, ops, ooffs)
+
+
+def tol_for(dtype):
+    return ERR_F64 if dtype == 0 else ERR_F32

@@ -153,3 +153,31 @@ def test_schedule_calls_validate_arguments():
     assert L.cfd_plan_get_flags(None, ctypes.byref(flags)) == _lib.CFD_EINVAL
     assert L.cfd_plan_set_schedule(None, 0, 0, 0, _lib.CFD_SCHED_CONCURRENT) == _lib.CFD_EINVAL
     assert L.cfd_plan_get_schedule(None, None, None, None, None, None, None, 0) == _lib.CFD_EINVAL
+
+
+def test_create_rejects_biased_stencils():
+    """The line kernels evaluate the interior RHS in centred form (Eq. sch_cent_om): a biased stencil
+    that satisfies the Taylor conditions, e.g. the backward difference (-1, 1, 0) for d = 1, is refused
+    rather than silently differentiated with its mirrored half."""
+    with pytest.raises(P.CfdError) as e:
+        P.Scheme.create(1, 1, [1.0], [-1.0, 1.0, 0.0])
+    assert e.value.status == _lib.CFD_EUNSUPPORTED
+    with pytest.raises(P.CfdError) as e:   # asymmetric implicit stencil
+        P.Scheme.create(1, 2, [0.2, 1, 0.3], [-0.75, 0.0, 0.75], [[-0.5, 0.0, 0.5]])
+    assert e.value.status in (_lib.CFD_EUNSUPPORTED, _lib.CFD_EINVAL)
+
+
+def test_create_rejects_nonpositive_symbol():
+    """alpha_1 = 0.6: the symbol 1 + 1.2 cos t vanishes inside [0, pi] (singular periodic system)."""
+    a = 0.6
+    with pytest.raises(P.CfdError) as e:
+        P.Scheme.create(1, 2, [a, 1, a], [-(1 + 2 * a) / 2, 0.0, (1 + 2 * a) / 2], [[-0.5, 0.0, 0.5]])
+    assert e.value.status == _lib.CFD_ESINGULAR
+    # alpha_1 = 0.49 stays positive and is accepted
+    a = 0.49
+    P.Scheme.create(1, 2, [a, 1, a], [-(1 + 2 * a) / 2, 0.0, (1 + 2 * a) / 2], [[-0.5, 0.0, 0.5]])
+
+
+def test_debug_alloc_hook_is_harmless_without_device():
+    P.cfd_debug_fail_alloc(0)
+    P.cfd_debug_fail_alloc(-1)

@@ -40,49 +40,100 @@ def _graph_run(wl, ops, dtype, autotune=True):
     return plan, y
 
 
-def _sampled_err(plan, y, wl, ops, blocks, fields):
-    """Worst relative error over the sampled (block, field) pairs, every operator, every node."""
+def _full_err(plan, y, wl, ops, ref=None):
+    """Worst relative error over every block, operator, field and node; also checks that no
+    output node is left NaN (the output buffer is NaN-prefilled)."""
     _, ooffs = plan.offsets()
-    schemes = {name: OS.named(name) for name, _ in ops}
-    worst = 0.0
-    for b in blocks:
-        blk = wl.blocks[b]
-        npts = int(np.prod(blk.n))
-        for o, (name, d) in enumerate(ops):
-            for f in fields:
-                off = ooffs[b] + (o * wl.nfields + f) * npts
-                got = y[off:off + npts].double().cpu().numpy().reshape(blk.n[2], blk.n[1], blk.n[0])
-                ref = OL.apply_block(schemes[name], wl.field_view(b, f), blk.ng, blk.h[d], d,
-                                     periodic=blk.boundary[d] == synth.PERIODIC)
-                worst = max(worst, H.rel_err(got, ref))
-    return worst
+    got = y.double().cpu().numpy()
+    if ref is None:
+        ref = H.oracle_flat(wl, ops, ooffs, got.size)
+    return H.compare_flat(got, ref, wl, ops, ooffs)
+
+
+_BATCH64 = {}
+
+
+def _batch64_ref():
+    """The batch64 workload and the oracle's full result (computed once for FP64 and FP32)."""
+    if not _BATCH64:
+        wl = synth.batch64()
+        import paper_2302_14858_amd as P
+        plan = H.make_plan(wl, OPS_PENTA)
+        _, ooffs = plan.offsets()
+        _, nout = plan.sizes()
+        _BATCH64["wl"] = wl
+        _BATCH64["ref"] = H.oracle_flat(wl, OPS_PENTA, ooffs, nout)
+    return _BATCH64["wl"], _BATCH64["ref"]
 
 
 @pytest.mark.parametrize("dtype,tol", [(0, H.ERR_F64), (1, H.ERR_F32)])
 def test_batch64_full_autotuned_graph(cuda, dtype, tol):
-    """The benchmark step: 64 blocks x 22 fields x penta D1+D2 along x, y, z, one graph."""
-    wl = synth.batch64()
+    """The benchmark step: 64 blocks x 22 fields x penta D1+D2 along x, y, z, one graph; every output
+    node of every block, field and operator against the oracle."""
+    wl, ref = _batch64_ref()
     plan, y = _graph_run(wl, OPS_PENTA, dtype)
-    # blocks of every extent class, first/middle/last fields
-    sizes = {}
-    for b, blk in enumerate(wl.blocks):
-        sizes.setdefault(blk.n, b)
-    blocks = sorted(set(list(sizes.values())[:6] + [0, len(wl.blocks) - 1]))
-    assert _sampled_err(plan, y, wl, OPS_PENTA, blocks, [0, 11, 21]) <= tol
+    print(f"batch64 dtype={dtype} schedule={plan.get_schedule()}", flush=True)
+    assert _full_err(plan, y, wl, OPS_PENTA, ref) <= tol
+
+
+@pytest.mark.parametrize("flags", [{"persistent": False, "xcd": True, "split_x": True, "concurrent": True},
+                                   {"persistent": True, "xcd": True}, {"persistent": False}])
+def test_batch64_full_each_launch_shape(cuda, flags):
+    """Every output node of batch64 (FP64) under the XCD-interleaved per-item order, the XCD-queue
+    persistent grid and the plain per-item grid, default partitions."""
+    import paper_2302_14858_amd as P
+    wl, ref = _batch64_ref()
+    plan = H.make_plan(wl, OPS_PENTA)
+    try:
+        plan.set_schedule(0, **flags)
+    except P.CfdError as e:
+        assert e.status == P._lib.CFD_EUNSUPPORTED and not flags["persistent"]
+        pytest.skip("XCD-interleaved per-item order not offered on this device")
+    import torch
+    nin, nout = plan.sizes()
+    x = torch.from_numpy(wl.data).cuda()
+    y = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.capture_graph(x, y)
+    plan.launch_graph()
+    torch.cuda.synchronize()
+    assert _full_err(plan, y, wl, OPS_PENTA, ref) <= H.ERR_F64
 
 
 def test_block128_full(cuda):
     wl = synth.block128()
     plan, y = _graph_run(wl, OPS_TRI, 0)
-    assert _sampled_err(plan, y, wl, OPS_TRI, [0], [0]) <= H.ERR_F64
+    assert _full_err(plan, y, wl, OPS_TRI) <= H.ERR_F64
+
+
+def test_block128_ng3_order_only_closures(cuda):
+    """The 128^3 block at the literal 3 ghost layers: the order-only closures (1)/(2)Q1_3[1]:E."""
+    ops = [("(1)Q1_3[1]:E", d) for d in range(3)] + [("(2)Q1_3[1]:E", d) for d in range(3)]
+    wl = synth.block128(ng=3)
+    plan, y = _graph_run(wl, ops, 0)
+    assert _full_err(plan, y, wl, ops) <= H.ERR_F64
+
+
+_P256 = {}
+
+
+def _periodic256_ref():
+    if not _P256:
+        wl = synth.periodic256()
+        plan = H.make_plan(wl, OPS_D1)
+        _, ooffs = plan.offsets()
+        _, nout = plan.sizes()
+        _P256["wl"] = wl
+        _P256["ref"] = H.oracle_flat(wl, OPS_D1, ooffs, nout)
+    return _P256["wl"], _P256["ref"]
 
 
 @pytest.mark.parametrize("dtype,tol", [(0, H.ERR_F64), (1, H.ERR_F32), (2, H.ERR_F32)])
 def test_periodic256_full(cuda, dtype, tol):
-    """Periodic 256^3 x 8 fields, tri D1 along x, y, z: banded FP64, banded FP32, dense mixed."""
-    wl = synth.periodic256()
+    """Periodic 256^3 x 8 fields, tri D1 along x, y, z: banded FP64, banded FP32, dense mixed; all
+    8 fields, every node."""
+    wl, ref = _periodic256_ref()
     plan, y = _graph_run(wl, OPS_D1, dtype)
-    assert _sampled_err(plan, y, wl, OPS_D1, [0], [0, 7]) <= tol
+    assert _full_err(plan, y, wl, OPS_D1, ref) <= tol
 
 
 @pytest.mark.parametrize("dtype,tol", [(0, 1e-12), (1, 1e-5)])

@@ -120,6 +120,102 @@ def test_tuned_scheme_is_constrained_minimum(name):
             assert eps_of(d) > e0
 
 
+def _rational_null_space(rows):
+    """Basis of the null space of a rational matrix (list of rows of Fractions), by exact RREF."""
+    A = [list(r) for r in rows]
+    n = len(A[0])
+    piv_cols, r = [], 0
+    for c in range(n):
+        p = next((i for i in range(r, len(A)) if A[i][c] != 0), None)
+        if p is None:
+            continue
+        A[r], A[p] = A[p], A[r]
+        pv = A[r][c]
+        A[r] = [v / pv for v in A[r]]
+        for i in range(len(A)):
+            if i != r and A[i][c] != 0:
+                f = A[i][c]
+                A[i] = [a - f * b for a, b in zip(A[i], A[r])]
+        piv_cols.append(c)
+        r += 1
+        if r == len(A):
+            break
+    free = [c for c in range(n) if c not in piv_cols]
+    basis = []
+    for fcol in free:
+        z = [F(0)] * n
+        z[fcol] = F(1)
+        for i, pc in enumerate(piv_cols):
+            z[pc] = -A[i][fcol]
+        basis.append(z)
+    return basis
+
+
+@pytest.mark.parametrize("name", ["(1)Q1_3[1]", "(2)Q1_3[1]", "(1)QP_O8[1]", "(2)QP_O8[1]",
+                                  "(1)Q1_3[4pi/5]"])
+def test_tuned_scheme_is_minimum_along_every_null_direction(name):
+    """Eq. optfunc at the tuned scheme against every direction that keeps the constraints (the
+    normalisation and the Taylor rows of Eq. Tcons, no symmetry imposed): the exact rational null
+    space of the constraint rows, each basis vector and two mixed directions.  Along each the
+    objective has zero slope and positive curvature, so every perturbation raises it."""
+    s = S.named(name)
+    eta_c = mp.mpf(1) if name.endswith("[1]") else 4 * mp.pi / 5
+    nl, M = s.nl, s.M
+    layout = S._unknown_layout((s.dr, nl, nl), [(0, M, M)])
+    rows = [S._normalisation_row(layout, s.dr)] + [S.taylor_row(layout, l) for l in range(s.order + s.dr)]
+    Z = _rational_null_space(rows)
+    # the constraint rows are independent: the free directions are what they leave over
+    assert len(Z) == len(layout) - len(rows) >= 1
+    # each constraint holds exactly along each direction
+    for z in Z:
+        for r in rows:
+            assert sum(a * b for a, b in zip(r, z)) == 0
+    dirs = list(Z)
+    if len(Z) >= 2:
+        dirs.append([a + b for a, b in zip(Z[0], Z[1])])
+        dirs.append([a - 2 * b for a, b in zip(Z[0], Z[1])])
+    with mp.workdps(30):
+        c0 = [S._mpf(v) for v in s.lhs.coef] + [S._mpf(v) for v in s.rhs[0].coef]
+
+        def J(c):
+            lhs, rhs = S._unpack(layout, c, (s.dr, nl, nl), [(0, M, M)])
+            t = S.Scheme("t", s.dr, s.order, lhs, rhs)
+            return mp.quad(lambda e: abs(S.spectral_error(t, e)) ** 2, [0, eta_c])
+
+        j0 = J(c0)
+        for z in dirs:
+            zn = [S._mpf(v) for v in z]
+            scale = mp.sqrt(mp.fsum(v * v for v in zn))
+            zn = [v / scale for v in zn]
+            for delta in (mp.mpf("1e-3"), mp.mpf("1e-2")):
+                jp = J([a + delta * b for a, b in zip(c0, zn)])
+                jm = J([a - delta * b for a, b in zip(c0, zn)])
+                curv = jp + jm - 2 * j0
+                assert jp > j0 and jm > j0
+                assert curv > 0
+                assert abs(jp - jm) < 1e-12 * curv, (name, float(jp - jm), float(curv))
+
+
+@pytest.mark.parametrize("name,need", [("(1)P1_1", 3), ("(2)P1_2", 4), ("(1)P1_3", 5), ("(1)Q1_3[1]", 4),
+                                       ("(2)Q1_3[4pi/5]", 4), ("(1)QP_O8[1]", 5), ("(2)QP_O8[1]", 5),
+                                       ("(1)Q1_3[1]:E", 3), ("(2)QP_O8[1]:E", 4), ("(1)E3", 3), ("(2)E4", 4)])
+def test_required_ghosts_follow_the_closure_rule(name, need):
+    """Ghost layers from the reach of the closure rows (Sec. 2.4, Eq. sch_cent_om): a matched closure
+    of a scheme of formal order 2p has half-width p + 1, so N_g >= p + 1; the order-only closure has
+    half-width p (N_g >= p); an explicit E_M reaches M.  Periodic lines need none."""
+    s = S.named(name)
+    p = s.order // 2
+    if s.nl == 0:
+        rule = s.M
+    elif name.endswith(":E"):
+        rule = p
+    else:
+        rule = p + 1
+    assert rule == need
+    assert S.required_ghosts(s, False) == need
+    assert S.required_ghosts(s, True) == 0
+
+
 def test_phi_estimate_table():
     """Tab. phi_estimate from Eq. adv_ppw_estimate with the oracle's error constants."""
     g = GOLD["phi_estimate"]
