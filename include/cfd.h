@@ -334,6 +334,41 @@ cfd_status cfd_wave_rk_stage_halo(cfd_plan *p, const void *u0_dev, const void *s
                                   int bx, int by, int bz, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Allocation-free apply                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): one
+ * operator (scheme s along direction dir) on every line of one block, without
+ * a plan and without allocating.  The result equals, bit for bit, that of a
+ * plan holding this one operator (cfd_plan_create + cfd_apply with the
+ * default schedule).  The solve tables, pass record, work list and the
+ * scratch of the FP64 table build that a plan would allocate are kept in one
+ * file-scope device array of 8 MiB per GPU, held until the process ends;
+ * every step is a kernel launch on `stream`, and nothing is copied from host
+ * memory.
+ *   blk      the block (in_offset / out_offset are ignored: the input starts
+ *            at in_dev, the output at out_dev).
+ *   nfields  fields in the input, laid out as for a plan (ghosts included).
+ *   field    -1: every field, output [field][z][y][x] (interior only);
+ *            k: field k only, output [z][y][x].
+ *   dtype    CFD_F64 or CFD_F32 (CFD_MIXED_BF16: CFD_EUNSUPPORTED).
+ * Errors as cfd_plan_create for the block and scheme (CFD_EGHOST,
+ * CFD_ESHAPE, CFD_EINVAL, 16-byte alignment), and CFD_EUNSUPPORTED when the
+ * tables and work list would exceed the 8 MiB array (about half a million
+ * work items of 64-256 lines each) or no compiled kernel fits the line
+ * length.  A factorisation breakdown (CFD_ESINGULAR at plan creation) is not
+ * detected here; schemes are checked for a positive symbol when created.
+ * Calls on one GPU share the array, and each call's kernels overwrite it:
+ * calls that overlap on one GPU (on different streams, or from different
+ * threads without ordering) race and give undefined results.  The first
+ * call on a device looks up the array's address (hipGetSymbolAddress); make
+ * that call outside graph capture. */
+cfd_status cfd_apply_block_noalloc(const cfd_scheme *s, const cfd_block *blk, int dir, int nfields,
+                                   int field, cfd_dtype dtype, const void *in_dev, void *out_dev,
+                                   void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Test hook                                                                 */
 /* ------------------------------------------------------------------------ */
 

@@ -254,6 +254,20 @@ def cfd_axpby(a: float, x, b: float, y, stream=None) -> None:
                           _stream_ptr(stream)))
 
 
+def cfd_apply_block_noalloc(scheme: "Scheme", block: Dict, direction: int, nfields: int, inp, out, field: int = -1,
+                            dtype: int = CFD_F64, stream=None) -> None:
+    """One operator on every line of one block without a plan and without device allocation."""
+    b = _lib.cfd_block()
+    b.n = (ctypes.c_int * 3)(*block["n"])
+    b.ng = int(block["ng"])
+    b.h = (ctypes.c_double * 3)(*block["h"])
+    b.boundary = (ctypes.c_int * 3)(*block["boundary"])
+    b.in_offset = -1
+    b.out_offset = -1
+    check(lib().cfd_apply_block_noalloc(scheme._h, ctypes.byref(b), int(direction), int(nfields), int(field),
+                                        int(dtype), _dev_ptr(inp), _dev_ptr(out), _stream_ptr(stream)))
+
+
 def cfd_debug_fail_alloc(n: int) -> None:
     """Test hook: the library's n-th following device allocation fails (n < 0: off)."""
     lib().cfd_debug_fail_alloc(int(n))

@@ -86,22 +86,7 @@ struct DevBuf {
 
 }  // namespace
 
-struct cfd_scheme {
-    Scheme s;
-};
-
 namespace {
-
-struct PassHost {
-    int block, dir, field0, nfield;
-    int nops;
-    int op[2];        // plan op indices (output order)
-    int sch[2];       // scheme indices
-    int N, periodic, nl, par, mi, hw;
-    int P = 0, L = 0, lcode = 0;
-    int C = 1;        // x lines: column chunks the LDS tile is staged in (divides P)
-    const LineClass *cls = nullptr;
-};
 
 struct Group {
     const void *fn;
@@ -180,11 +165,7 @@ struct cfd_plan {
     }
 };
 
-namespace {
-
-size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }   // F32 and MIXED_BF16 store FP32
-
-constexpr int kXCDq = 8;   // queues of the XCD-aware schedule (one per XCD)
+namespace cfd {
 
 // Exchange-area bytes an item needs: partition coupling (P > 1) or the
 // periodic wrap; none for a single-partition closure line.  Same layout as
@@ -196,7 +177,7 @@ size_t exch_bytes(int nl, int nops, int P, bool periodic, size_t es) {
 
 // Tile bytes an x item with P partitions of L rows needs in LDS: 64 (4/P)
 // lines by the columns of one chunk (P/C partitions plus the halo).
-size_t x_tile_bytes(int P, int L, int hw, size_t es, int C = 1) {
+size_t x_tile_bytes(int P, int L, int hw, size_t es, int C) {
     return (size_t)(kWave * 4 / P) * (size_t)((P / C * L + 2 * hw) | 1) * es;
 }
 
@@ -237,11 +218,12 @@ int partition_length(const PassHost &ps, bool f32, int P) {
     return best;
 }
 
-// Candidate partition counts for a pass, best first.  A candidate needs a
-// compiled class with a fitting L, and (x lines) an LDS tile that fits next
-// to the exchange area.
-std::vector<int> candidate_Ps(const PassHost &ps, bool f32, size_t max_lds) {
-    std::vector<int> ok;
+// Candidate partition counts for a pass, best first, into out[0..3); returns
+// how many.  A candidate needs a compiled class with a fitting L, and (x
+// lines) an LDS tile that fits next to the exchange area.  No heap use (the
+// allocation-free apply calls this too).
+int candidate_Ps(const PassHost &ps, bool f32, size_t max_lds, int out[3]) {
+    int ok[3], Lok[3], n = 0;
     const size_t es = f32 ? 4 : 8;
     for (int P = 1; P <= 4; P *= 2) {
         const int L = partition_length(ps, f32, P);
@@ -252,19 +234,108 @@ std::vector<int> candidate_Ps(const PassHost &ps, bool f32, size_t max_lds) {
         size_t lds = exch_bytes(ps.nl, ps.nops, P, ps.periodic, es);
         if (ps.dir == 0) lds += x_tile_bytes(P, L, k->hw, es, chunked(k) ? x_chunks(P, L, k->hw, es, lds) : 1);
         if (lds > max_lds) continue;
-        ok.push_back(P);
+        ok[n] = P;
+        Lok[n] = L;
+        ++n;
     }
     // default preference: y/z lines: fewest partitions with L <= 24 (register
-    // budget); x lines: L <= 16 (LDS tile); then the rest in order
+    // budget); x lines: L <= 16 (LDS tile); then the rest, most partitions first
     const int Lcap = ps.dir == 0 ? 16 : 24;
-    auto Lof = [&](int P) { return partition_length(ps, f32, P); };
-    std::stable_sort(ok.begin(), ok.end(), [&](int a, int b) {
-        const bool sa = Lof(a) <= Lcap, sb = Lof(b) <= Lcap;
-        if (sa != sb) return sa;
-        return sa ? a < b : a > b;
-    });
-    return ok;
+    int m = 0;
+    for (int i = 0; i < n; ++i)
+        if (Lok[i] <= Lcap) out[m++] = ok[i];
+    for (int i = n - 1; i >= 0; --i)
+        if (Lok[i] > Lcap) out[m++] = ok[i];
+    return m;
 }
+
+std::vector<int> candidate_Ps(const PassHost &ps, bool f32, size_t max_lds) {
+    int c[3];
+    const int n = candidate_Ps(ps, f32, max_lds, c);
+    return std::vector<int>(c, c + n);
+}
+
+// Strides, offsets and line counts of one pass over block b along ps.dir.
+// in_off: the block's input offset; out_base[o]: where operator o's first
+// field starts in the output; tab[o]: table index; hinv[o] = h^-d.
+void fill_pass_desc(PassDesc &q, const cfd_block &b, int64_t in_off, const PassHost &ps, const int64_t out_base[2],
+                    const int tab[2], const double hinv[2]) {
+    const int64_t ng = b.ng;
+    const int64_t PX = b.n[0] + 2 * ng, PY = b.n[1] + 2 * ng, PZ = b.n[2] + 2 * ng;
+    const int64_t s_in[3] = {1, PX, PX * PY};
+    const int64_t s_out[3] = {1, b.n[0], (int64_t)b.n[0] * b.n[1]};
+    const int d = ps.dir;
+    const int u = (d == 0) ? 1 : 0;
+    const int v = (d == 2) ? 1 : 2;
+    std::memset(&q, 0, sizeof q);
+    q.in_base = in_off + ng * (s_in[0] + s_in[1] + s_in[2]);
+    q.in_fstride = PX * PY * PZ;
+    for (int o = 0; o < ps.nops; ++o) {
+        q.out_base[o] = out_base[o];
+        q.tab[o] = tab[o];
+        q.hinv[o] = hinv[o];
+    }
+    q.out_fstride = (int64_t)b.n[0] * b.n[1] * b.n[2];
+    q.su = (int32_t)s_in[u];
+    q.sv = (int32_t)s_in[v];
+    q.sd = (int32_t)s_in[d];
+    q.osu = (int32_t)s_out[u];
+    q.osv = (int32_t)s_out[v];
+    q.osd = (int32_t)s_out[d];
+    q.nu = b.n[u];
+    q.nlines = b.n[u] * b.n[v];
+    q.N = ps.N;
+    q.ng = b.ng;
+    q.periodic = ps.periodic;
+    q.nfield_pass = ps.nfield;
+    q.field0 = ps.field0;
+}
+
+cfd_status set_error(cfd_status st, const std::string &msg) { return fail(st, msg); }
+
+// Coefficient block of a table (the first kCoefHdr elements): interior
+// stencil, left closure rows, right closure rows (mirror images,
+// (-1)^d c[-m]) and alpha^(d).
+void fill_coef_block(double *cb, const Scheme &s) {
+    for (int i = 0; i < kCoefHdr; ++i) cb[i] = 0.0;
+    for (int m = 0; m < 11; ++m) cb[kCoefA + m] = s.rhs[m];
+    const double sgn = (s.d % 2) ? -1.0 : 1.0;
+    for (int j = 0; j < kMaxNL; ++j)
+        for (int m = -kMaxHalf; m <= kMaxHalf; ++m) {
+            cb[kCoefCL + j * 11 + 5 + m] = s.cl[j][5 + m];
+            cb[kCoefCR + j * 11 + 5 + m] = sgn * s.cl[j][5 - m];
+        }
+    for (int j = 0; j < 5; ++j) cb[kCoefAlpha + j] = s.lhs[j];
+}
+
+// Kernel class, partition length and LDS bytes of a pass with P partitions.
+void place_pass(PassHost &ps, bool f32, int P) {
+    ps.P = P;
+    ps.L = partition_length(ps, f32, P);
+    ps.cls = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, ps.L);
+    ps.lcode = 0;
+    for (int j = 0; j < ps.cls->nL; ++j)
+        if (ps.cls->Ls[j] == ps.L) ps.lcode = j;
+    const size_t es = f32 ? 4 : 8;
+    ps.C = (ps.dir == 0 && chunked(ps.cls))
+               ? x_chunks(ps.P, ps.L, ps.cls->hw, es, exch_bytes(ps.nl, ps.nops, ps.P, ps.periodic, es))
+               : 1;
+}
+
+size_t pass_lds(const PassHost &ps, bool f32) {
+    const size_t es = f32 ? 4 : 8;
+    size_t lds = exch_bytes(ps.nl, ps.nops, ps.P, ps.periodic, es);
+    if (ps.dir == 0) lds += x_tile_bytes(ps.P, ps.L, ps.cls->hw, es, ps.C);
+    return lds;
+}
+
+}  // namespace cfd
+
+namespace {
+
+size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }   // F32 and MIXED_BF16 store FP32
+
+constexpr int kXCDq = 8;   // queues of the XCD-aware schedule (one per XCD)
 
 // Pass descriptors (strides, offsets, h^-d) of every pass; table indices from pass_tab.
 std::vector<PassDesc> pass_descs(const cfd_plan *p, const std::vector<std::array<int, 2>> &pass_tab) {
@@ -272,39 +343,17 @@ std::vector<PassDesc> pass_descs(const cfd_plan *p, const std::vector<std::array
     for (size_t i = 0; i < p->passes.size(); ++i) {
         const PassHost &ps = p->passes[i];
         const cfd_block &b = p->blocks[ps.block];
-        const int64_t ng = b.ng;
-        const int64_t PX = b.n[0] + 2 * ng, PY = b.n[1] + 2 * ng, PZ = b.n[2] + 2 * ng;
-        const int64_t s_in[3] = {1, PX, PX * PY};
-        const int64_t s_out[3] = {1, b.n[0], (int64_t)b.n[0] * b.n[1]};
-        const int d = ps.dir;
-        const int u = (d == 0) ? 1 : 0;
-        const int v = (d == 2) ? 1 : 2;
-        PassDesc &q = pd[i];
-        std::memset(&q, 0, sizeof q);
-        q.in_base = p->in_off[ps.block] + ng * (s_in[0] + s_in[1] + s_in[2]);
-        q.in_fstride = PX * PY * PZ;
         const int64_t npts = (int64_t)b.n[0] * b.n[1] * b.n[2];
+        int64_t ob[2] = {0, 0};
+        int tab[2] = {0, 0};
+        double hinv[2] = {0, 0};
         for (int o = 0; o < ps.nops; ++o) {
-            q.out_base[o] = p->out_off[ps.block] + p->op_slot[ps.op[o]] * npts;
-            q.tab[o] = pass_tab[i][o];
-            q.hinv[o] = 1.0 / std::pow(b.h[d], p->schemes[ps.sch[o]].d);
+            ob[o] = p->out_off[ps.block] + p->op_slot[ps.op[o]] * npts;
+            tab[o] = pass_tab[i][o];
+            hinv[o] = 1.0 / std::pow(b.h[ps.dir], p->schemes[ps.sch[o]].d);
         }
-        q.out_fstride = npts;
-        q.su = (int32_t)s_in[u];
-        q.sv = (int32_t)s_in[v];
-        q.sd = (int32_t)s_in[d];
-        q.osu = (int32_t)s_out[u];
-        q.osv = (int32_t)s_out[v];
-        q.osd = (int32_t)s_out[d];
-        q.nu = b.n[u];
-        q.nlines = b.n[u] * b.n[v];
-        q.N = ps.N;
-        q.ng = b.ng;
-        q.periodic = ps.periodic;
-        q.nfield_pass = ps.nfield;
-        q.field0 = ps.field0;
+        fill_pass_desc(pd[i], b, p->in_off[ps.block], ps, ob, tab, hinv);
     }
-
     return pd;
 }
 
@@ -370,16 +419,7 @@ cfd_status build_groups(cfd_plan *p) {
         auto it = p->sched_P.find(std::make_pair(ps.N, ps.dir == 0 ? 1 : 0));
         if (it != p->sched_P.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
             P = it->second;
-        ps.P = P;
-        ps.L = partition_length(ps, f32, P);
-        ps.cls = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, ps.L);
-        ps.lcode = 0;
-        for (int j = 0; j < ps.cls->nL; ++j)
-            if (ps.cls->Ls[j] == ps.L) ps.lcode = j;
-        const size_t es1 = f32 ? 4 : 8;
-        ps.C = (ps.dir == 0 && chunked(ps.cls))
-                   ? x_chunks(ps.P, ps.L, ps.cls->hw, es1, exch_bytes(ps.nl, ps.nops, ps.P, ps.periodic, es1))
-                   : 1;
+        place_pass(ps, f32, P);
     }
     // 2. tables
     std::map<TabKey, int> tabidx;
@@ -412,15 +452,7 @@ cfd_status build_groups(cfd_plan *p) {
     for (size_t t = 0; t < keys.size(); ++t) {
         const TabKey &k = keys[t];
         const Scheme &s = p->schemes[k.sch];
-        double *cb = host_tab.data() + offs[t];
-        for (int m = 0; m < 11; ++m) cb[kCoefA + m] = s.rhs[m];
-        const double sgn = (s.d % 2) ? -1.0 : 1.0;
-        for (int j = 0; j < kMaxNL; ++j)
-            for (int m = -kMaxHalf; m <= kMaxHalf; ++m) {
-                cb[kCoefCL + j * 11 + 5 + m] = s.cl[j][5 + m];
-                cb[kCoefCR + j * 11 + 5 + m] = sgn * s.cl[j][5 - m];
-            }
-        for (int j = 0; j < 5; ++j) cb[kCoefAlpha + j] = s.lhs[j];
+        fill_coef_block(host_tab.data() + offs[t], s);
         const int L = k.L;
         fill_tabspec(specs.data() + t * tabspec_size(), k.N, k.P, L, s.nl, k.periodic ? 0 : s.nc, k.periodic,
                      s.lhs, offs[t]);
@@ -495,8 +527,7 @@ cfd_status build_groups(cfd_plan *p) {
             for (int i : by_block[b]) {
                 const PassHost &ps = p->passes[i];
                 if (f < ps.field0 || f >= ps.field0 + ps.nfield) continue;
-                size_t lds = exch_bytes(ps.nl, ps.nops, ps.P, ps.periodic, es);
-                if (ps.dir == 0) lds += x_tile_bytes(ps.P, ps.L, ps.cls->hw, es, ps.C);
+                const size_t lds = pass_lds(ps, f32);
                 int sub = 0;
                 if (p->split_x && ps.dir == 0) sub = 1;
                 else if (p->split_x && p->concurrent && yz_lds_free) sub = 2;

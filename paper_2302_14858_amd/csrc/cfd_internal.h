@@ -104,8 +104,40 @@ struct WorkItem {
 // ---------------------------------------------------------------------------
 #include <hip/hip_runtime_api.h>
 
+struct cfd_scheme {
+    cfd::Scheme s;
+};
+
 namespace cfd {
 struct LineClass;
+
+// One pass of a plan: the lines of one block along one direction, for up to
+// two operators that share the line data.
+struct PassHost {
+    int block = 0, dir = 0, field0 = 0, nfield = 1;
+    int nops = 1;
+    int op[2] = {0, 0};   // plan op indices (output order)
+    int sch[2] = {0, 0};  // scheme indices
+    int N = 0, periodic = 0, nl = 0, par = 0, mi = 0, hw = 0;
+    int P = 0, L = 0, lcode = 0;
+    int C = 1;            // x lines: column chunks the LDS tile is staged in (divides P)
+    const LineClass *cls = nullptr;
+};
+
+// Schedule helpers shared by plans and the allocation-free apply (cfd_host.cpp).
+size_t exch_bytes(int nl, int nops, int P, bool periodic, size_t es);
+size_t x_tile_bytes(int P, int L, int hw, size_t es, int C = 1);
+bool chunked(const LineClass *k);
+int x_chunks(int P, int L, int hw, size_t es, size_t exch);
+int partition_length(const PassHost &ps, bool f32, int P);
+int candidate_Ps(const PassHost &ps, bool f32, size_t max_lds, int out[3]);
+void fill_pass_desc(PassDesc &q, const cfd_block &b, int64_t in_off, const PassHost &ps, const int64_t out_base[2],
+                    const int tab[2], const double hinv[2]);
+void place_pass(PassHost &ps, bool f32, int P);
+void fill_coef_block(double *cb, const Scheme &s);
+cfd_status set_error(cfd_status st, const std::string &msg);   // message for cfd_last_error
+size_t pass_lds(const PassHost &ps, bool f32);
+
 const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L);
 int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap);
 hipError_t launch_lines(const void *fn, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
