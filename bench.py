@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE passes scaled by what the same counters read for a 1 GiB device copy
 # (x2.0 and x1.0).  Valid for the line kernels as they are now; set to None when they change until
 # the counters are taken again.
-MEASURED_TRAFFIC_BYTES = 3.00e9
+MEASURED_TRAFFIC_BYTES = None
 OPS_PENTA = [("(1)QP_O8[1]", 0), ("(1)QP_O8[1]", 1), ("(1)QP_O8[1]", 2),
              ("(2)QP_O8[1]", 0), ("(2)QP_O8[1]", 1), ("(2)QP_O8[1]", 2)]
 OPS_TRI = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2),

@@ -195,13 +195,16 @@ bool chunked(const LineClass *k) {
 
 int x_chunks(int P, int L, int hw, size_t es, size_t exch) {
     for (int C = 1; C <= P; C *= 2)
-        if (x_tile_bytes(P, L, hw, es, C) + exch <= 81920) return C;
+        if (std::max(x_tile_bytes(P, L, hw, es, C), exch) <= 81920) return C;
     return P;
 }
 
 // Partition length for P partitions of an N-node line: the smallest compiled
 // L with P L >= N (P L == N for periodic lines) whose last partition holds
-// every right-closure row.  0 if none.
+// every right-closure row.  0 if none.  For a closure line the ring of an
+// inner partition, HW nodes past its last row with HW the half-width the
+// kernel class is compiled for, must stay inside the stored line (N + ng
+// nodes): the kernel loads it without bounds checks.
 int partition_length(const PassHost &ps, bool f32, int P) {
     int Ls[16];
     const int n = line_class_Ls(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, Ls, 16);
@@ -213,6 +216,10 @@ int partition_length(const PassHost &ps, bool f32, int P) {
         if (ps.nl > 0 && L < 2 * ps.nl) continue;
         if ((P - 1) * L > ps.N - ps.nl) continue;   // every right-closure row in the last partition
         if (P > 1 && (P - 1) * L >= ps.N) continue;                            // no empty partition
+        if (!ps.periodic && P > 1 && ps.dir != 0) {
+            const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L);
+            if (!k || (P - 1) * L + k->hw > ps.N + ps.ng) continue;
+        }
         if (!best || L < best) best = L;
     }
     return best;
@@ -232,7 +239,8 @@ int candidate_Ps(const PassHost &ps, bool f32, size_t max_lds, int out[3]) {
         if (!k) continue;
         if (ps.periodic && k->hw > ps.N) continue;
         size_t lds = exch_bytes(ps.nl, ps.nops, P, ps.periodic, es);
-        if (ps.dir == 0) lds += x_tile_bytes(P, L, k->hw, es, chunked(k) ? x_chunks(P, L, k->hw, es, lds) : 1);
+        if (ps.dir == 0)   // the x tile and the exchange area share the LDS
+            lds = std::max(lds, x_tile_bytes(P, L, k->hw, es, chunked(k) ? x_chunks(P, L, k->hw, es, lds) : 1));
         if (lds > max_lds) continue;
         ok[n] = P;
         Lok[n] = L;
@@ -325,7 +333,7 @@ void place_pass(PassHost &ps, bool f32, int P) {
 size_t pass_lds(const PassHost &ps, bool f32) {
     const size_t es = f32 ? 4 : 8;
     size_t lds = exch_bytes(ps.nl, ps.nops, ps.P, ps.periodic, es);
-    if (ps.dir == 0) lds += x_tile_bytes(ps.P, ps.L, ps.cls->hw, es, ps.C);
+    if (ps.dir == 0) lds = std::max(lds, x_tile_bytes(ps.P, ps.L, ps.cls->hw, es, ps.C));   // shared area
     return lds;
 }
 
@@ -1088,6 +1096,7 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
                 ps.field0 = p->ops[o].field < 0 ? 0 : p->ops[o].field;
                 ps.nfield = p->ops[o].field < 0 ? p->nfields : 1;
                 ps.N = bl.n[d];
+                ps.ng = bl.ng;
                 ps.periodic = bl.boundary[d] == CFD_BOUNDARY_PERIODIC;
                 const Scheme &s0 = p->schemes[o];
                 ps.nl = s0.nl;
@@ -1307,7 +1316,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     }
     auto keyof = [&](const std::tuple<int, int, int, int> &k) {
         std::ostringstream s;
-        s << "v3:" << arch << ":" << dt << ":N" << std::get<0>(k) << ":x" << std::get<1>(k) << ":nl" << std::get<2>(k)
+        s << "v4:" << arch << ":" << dt << ":N" << std::get<0>(k) << ":x" << std::get<1>(k) << ":nl" << std::get<2>(k)
           << ":ops" << std::get<3>(k);
         return s.str();
     };
@@ -1341,8 +1350,8 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     // launch shape: persistent grid, XCD-aware queues or per-item grid (plain
     // or in XCD-interleaved order); x lines fused with y/z or split; launches
     // sequential or concurrent
-    auto tune_shape = [&]() -> cfd_status {
-        float best = 1e30f;
+    auto tune_shape = [&](float &best) -> cfd_status {
+        best = 1e30f;
         int bmode = 1;
         bool bs = false, bc = false;
         cfd_status r = CFD_OK;
@@ -1369,10 +1378,52 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         p->concurrent = bc;
         return r;
     };
+    // Partition presets: the default preference, and a compact one (the
+    // fewest partitions with at most 16 rows for y/z lines and 12 for x
+    // lines), under which every pass can use the kernel classes compiled
+    // without long partitions (fewer registers, more waves per SIMD).  Tuning
+    // one class at a time does not find the compact set: moving a single
+    // class to another kernel adds a launch.
+    auto apply_preset = [&](int which) {
+        p->sched_P.clear();
+        if (which == 0) return;
+        for (const PassHost &ps : p->passes) {
+            int c[3];
+            const int n = candidate_Ps(ps, f32, p->max_lds, c);
+            const int cap = ps.dir == 0 ? 12 : 16;
+            int pick = 0;
+            for (int i = 0; i < n; ++i)
+                if (partition_length(ps, f32, c[i]) <= cap && (!pick || c[i] < pick)) pick = c[i];
+            if (pick) p->sched_P[std::make_pair(ps.N, ps.dir == 0 ? 1 : 0)] = pick;
+        }
+    };
     std::vector<std::string> new_lines;
-    // 1. the launch shape with the default partitions; 2. partitions per class
-    // under that shape; 3. the launch shape again with those partitions
-    cfd_status result = tune_shape();
+    // 1. the launch shape under each preset; 2. partitions per class under the
+    // best preset and shape; 3. the launch shape again with those partitions
+    cfd_status result = CFD_OK;
+    {
+        float best = 1e30f;
+        int bpre = 0;
+        bool bpe = true, bx = false, bs = false, bc = false;
+        for (int pre = 0; pre < 2 && result == CFD_OK; ++pre) {
+            apply_preset(pre);
+            float ms = 0;
+            result = tune_shape(ms);
+            if (result == CFD_OK && ms < best) {
+                best = ms;
+                bpre = pre;
+                bpe = p->persistent;
+                bx = p->xcd;
+                bs = p->split_x;
+                bc = p->concurrent;
+            }
+        }
+        apply_preset(bpre);
+        p->persistent = bpe;
+        p->xcd = bx;
+        p->split_x = bs;
+        p->concurrent = bc;
+    }
     const int shape = (p->persistent ? 1 : 0) | (p->split_x ? 2 : 0) | (p->xcd ? 4 : 0) | (p->concurrent ? 8 : 0);
     for (auto &kv : classes) {
         if (result != CFD_OK) break;
@@ -1399,7 +1450,10 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         p->sched_P[skey] = bestP;
         new_lines.push_back(key + " " + std::to_string(bestP));
     }
-    if (result == CFD_OK) result = tune_shape();
+    if (result == CFD_OK) {
+        float ms = 0;
+        result = tune_shape(ms);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (result != CFD_OK) return result;

@@ -118,7 +118,7 @@ struct PassHost {
     int nops = 1;
     int op[2] = {0, 0};   // plan op indices (output order)
     int sch[2] = {0, 0};  // scheme indices
-    int N = 0, periodic = 0, nl = 0, par = 0, mi = 0, hw = 0;
+    int N = 0, ng = 0, periodic = 0, nl = 0, par = 0, mi = 0, hw = 0;
     int P = 0, L = 0, lcode = 0;
     int C = 1;            // x lines: column chunks the LDS tile is staged in (divides P)
     const LineClass *cls = nullptr;

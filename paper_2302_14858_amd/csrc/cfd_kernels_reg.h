@@ -22,9 +22,13 @@ struct LineClass {
 
 // The classes compiled for each precision.
 #define CFD_LINE_CLASSES(T, F32)                                                  \
-    /* pentadiagonal, first + second derivative, RHS half-width 3, closures 5 */  \
+    /* pentadiagonal, first + second derivative, RHS half-width 3, closures 5; */ \
+    /* the class without 24-row partitions needs fewer registers (4 waves per */  \
+    /* SIMD instead of 3) and is preferred for the lengths it has */              \
+    CFD_LC(T, 2, 2, 1, 3, 5, 8, 12, 16),                                          \
     CFD_LC(T, 2, 2, 1, 3, 5, 8, 12, 16, 24),                                      \
     /* tridiagonal, first + second derivative, RHS half-width 3, closures 4 */    \
+    CFD_LC(T, 1, 2, 1, 3, 4, 8, 12, 16),                                          \
     CFD_LC(T, 1, 2, 1, 3, 4, 8, 12, 16, 24, 32),                                  \
     /* tridiagonal first derivative, RHS half-width 3 (short and long lines) */   \
     CFD_LC(T, 1, 1, 1, 3, 4, 8, 12, 16, 24, 32),                                  \
@@ -37,8 +41,8 @@ struct LineClass {
     CFD_LC(T, 2, 1, 1, 5, 5, 8, 12, 16, 24, 32),                                  \
     CFD_LC(T, 2, 1, 0, 5, 5, 8, 12, 16, 24, 32),                                  \
     /* explicit schemes */                                                        \
-    CFD_LC(T, 0, 1, 1, 5, 5, 8, 16, 32),                                          \
-    CFD_LC(T, 0, 1, 0, 5, 5, 8, 16, 32)
+    CFD_LC(T, 0, 1, 1, 5, 5, 8, 12, 16, 24, 32),                                  \
+    CFD_LC(T, 0, 1, 0, 5, 5, 8, 12, 16, 24, 32)
 
 const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L);
 

@@ -43,8 +43,9 @@ constexpr int kXCD = 8;   // accelerator complex dies (each with its own L2)
 
 // Exchange elements (of T) an item with P partitions uses for partition
 // coupling or the periodic wrap: (4/P) line groups x NOPS x 64 lanes x
-// ((2 NL P) | 1); a single-partition closure line uses none.  The x tile
-// starts right after them.
+// ((2 NL P) | 1); a single-partition closure line uses none.  x items share
+// the area with their tile: the exchange runs after every lane has read its
+// inputs from the tile and before the results are staged back into it.
 template <int NL, int NOPS>
 __device__ __forceinline__ int exch_elems_for(int P, bool periodic) {
     return (NL > 0 && (P > 1 || periodic)) ? (kWGW / P) * NOPS * 64 * ((2 * NL * P) | 1) : 0;
@@ -93,8 +94,11 @@ __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS
     const int64_t sd = pd.sd;
 
     const int Npad = c.P * L;
-    // node j of this line (global path): only the halo of the first and last
-    // partition can leave the line; out-of-block nodes read as 0 (zero weights)
+    // node j of this line (global path) for the first and last partition,
+    // whose halo can leave the line: out-of-block nodes read as 0 (their
+    // weights are zero; a class compiled for a wider ring than the scheme
+    // reaches, e.g. an explicit 6th-order stencil at ng = 3 in a class for
+    // half-width 5, also meets nodes past the stored ghosts here)
     auto edge_load = [&](int j) -> T {
         if (c.periodic) {
             if (j < 0) j += N;
@@ -109,15 +113,12 @@ __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS
     // side) is requested before any arithmetic, so all of the partition's loads
     // are in flight together.  x lines: the caller has read fin from the tile.
     if constexpr (!X) {
-        // a partition's halo can also leave the stored line (nodes -ng ..
-        // N+ng-1) when the compiled ring half-width HW exceeds what the
-        // scheme needs (e.g. an explicit 6th-order stencil at ng = 3 in a
-        // class compiled for half-width 5): such loads go through edge_load,
-        // which reads zeros there (the stencil weights beyond the scheme's
-        // reach are zero).  Periodic lines wrap, and an inner partition's halo
-        // stays inside the line because L >= HW.
-        const bool lo_edge = c.p == 0 || (!c.periodic && k0 - HW < -ng);
-        const bool hi_edge = c.p == c.P - 1 || (!c.periodic && k0 + L + HW > N + ng);
+        // only the first and last partition's halo can leave the stored line
+        // (nodes -ng .. N+ng-1): an inner partition starts at k0 >= L >= HW,
+        // and the host admits P partitions of a closure line only if
+        // (P-1) L + HW <= N + ng (periodic lines wrap, and L >= HW)
+        const bool lo_edge = c.p == 0;
+        const bool hi_edge = c.p == c.P - 1;
         // walk a pointer along the line: one stride add per node keeps the
         // addresses in vector registers instead of one scalar offset per node
         const T *q = c.src + (int64_t)(k0 - HW) * sd;
@@ -210,6 +211,9 @@ __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS
         if (c.periodic || c.P > 1) {
             const int B = 2 * NL * c.P;
             const int Bp = B | 1;
+            // x lines: the exchange area overlays the tile, which other waves
+            // may still be reading their inputs from
+            if constexpr (X) __syncthreads();
 #pragma unroll
             for (int o = 0; o < NOPS; ++o) {
                 T *row = c.exch + ((int64_t)(c.sub * NOPS + o) * 64 + c.g) * Bp + c.p * 2 * NL;
@@ -521,7 +525,7 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
         const int lv = line / pd.nu;
         const T *fbase = in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride;
         if (xdir) {
-            T *tile = exch + exch_elems_for<NL, NOPS>(c.P, c.periodic);
+            T *tile = exch;   // shared with the exchange area (see exch_elems_for)
             c.tile = tile;
             c.trow = c.sub * 64 + g;
             if constexpr (kChunked) {   // staged chunk by chunk in the item body

@@ -155,6 +155,7 @@ extern "C" cfd_status cfd_apply_block_noalloc(const cfd_scheme *sc, const cfd_bl
     ps.nfield = field < 0 ? nfields : 1;
     ps.nops = 1;
     ps.N = N;
+    ps.ng = b.ng;
     ps.periodic = per;
     ps.nl = s.nl;
     ps.par = (s.d % 2) ? 1 : 0;
