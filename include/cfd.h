@@ -273,6 +273,25 @@ cfd_status cfd_plan_get_flags(const cfd_plan *p, int *flags);
 
 void cfd_plan_destroy(cfd_plan *p);
 
+/* Hybrid iteration of the block closures (Sec. ssec:domdec_iter, Eq.
+ * iter_center_P; matrix form Eq. iter_scheme).  The plan's blocks tile a
+ * periodic box as a bx*by*bz lattice (block index (kz*by + ky)*bx + kx, all
+ * blocks the same shape, block closures in every direction, ghosts filled from
+ * the neighbours, e.g. by cfd_halo_exchange).  With iterations = n >= 1 every
+ * apply returns iterate [n]: iterate 0 is the block closure; iterate i solves
+ * the interior tridiagonal rows of each block line on k*_- - 1 .. k*_+ + 1 with
+ * the derivative at k*_- - 2 and k*_+ + 2 fixed to the neighbouring blocks'
+ * iterate i - 1 at those nodes.  Only tridiagonal schemes (CFD_EUNSUPPORTED
+ * otherwise); ng must cover the closure and the interior stencil on the row
+ * past the block end, max(closure requirement, M + 1) (CFD_EGHOST).
+ * iterations = 0 returns to the plain block closure.  Allocates the end-value
+ * arrays (two values per line, operator and field, five arrays) and builds the
+ * end-node weights in FP64 on the device; invalidates a captured graph.  An
+ * apply then enqueues n + 1 small kernels over the end values before the line
+ * kernels, and reads the input twice.  CFD_EINVAL if the lattice does not
+ * match the plan. */
+cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, int bz);
+
 /* ------------------------------------------------------------------------ */
 /* Ghost exchange for conforming periodic tilings (the communication step    */
 /* of Sec. 2.4, done on the device)                                          */

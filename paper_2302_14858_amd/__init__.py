@@ -225,6 +225,12 @@ class Plan:
 
     wave_rk_stage_halo = cfd_wave_rk_stage_halo
 
+    def cfd_plan_set_iteration(self, iterations: int, bx: int = 1, by: int = 1, bz: int = 1) -> None:
+        """Hybrid closure iteration on a periodic bx x by x bz block lattice (0: plain block closure)."""
+        check(lib().cfd_plan_set_iteration(self._h, int(iterations), int(bx), int(by), int(bz)))
+
+    set_iteration = cfd_plan_set_iteration
+
     def cfd_halo_exchange(self, data, bx: int, by: int, bz: int, stream=None) -> None:
         check(lib().cfd_halo_exchange(self._h, _dev_ptr(data), bx, by, bz, _stream_ptr(stream)))
 

@@ -64,6 +64,7 @@ SIGNATURES = {
     "cfd_wave_rk_stage": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp]),
     "cfd_wave_rk_stage_halo": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _i, _i, _i, _vp]),
     "cfd_debug_fail_alloc": (None, [_ll]),
+    "cfd_plan_set_iteration": (_i, [_vp, _i, _i, _i, _i]),
     "cfd_apply_block_noalloc": (_i, [_vp, ctypes.POINTER(cfd_block), _i, _i, _i, _i, _vp, _vp, _vp]),
 }
 

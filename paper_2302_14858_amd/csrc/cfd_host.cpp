@@ -125,6 +125,11 @@ struct cfd_plan {
     int cus = 256;
     size_t max_lds = 65536;
     bool xcd_interleave_ok = false;       // dispatch check passed: the XCD-interleaved per-item order covers every item
+    // hybrid closure iteration: iterations (0: off), end-node offset c, lattice
+    int iter_n = 0, iter_c = 2, lat[3] = {0, 0, 0};
+    std::vector<Scheme> base_schemes;     // the block-closure schemes while schemes holds the iterated ones
+    DevBuf d_iops, d_weights, d_ends0, d_endsf, d_ebufA, d_ebufB, d_ev;
+    int n_iops = 0, iter_max_units = 0;
     int64_t nunits = 0;                   // 64-node row pieces of all blocks (stage kernels)
     // device state rebuilt by build()
     DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff, d_qoff, d_outoff, d_shapes;
@@ -143,6 +148,17 @@ struct cfd_plan {
         gexec = nullptr;
         graph = nullptr;
     }
+    void release_iteration() {
+        d_iops.release();
+        d_weights.release();
+        d_ends0.release();
+        d_endsf.release();
+        d_ebufA.release();
+        d_ebufB.release();
+        d_ev.release();
+        n_iops = 0;
+        iter_max_units = 0;
+    }
     void release() {
         drop_graph();
         d_tab64.release();
@@ -156,6 +172,7 @@ struct cfd_plan {
         d_shapes.release();
         d_dense.release();
         d_dense_specs.release();
+        release_iteration();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
         for (hipStream_t a : aux) (void)hipStreamDestroy(a);
@@ -207,7 +224,7 @@ int x_chunks(int P, int L, int hw, size_t es, size_t exch) {
 // nodes): the kernel loads it without bounds checks.
 int partition_length(const PassHost &ps, bool f32, int P) {
     int Ls[16];
-    const int n = line_class_Ls(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, Ls, 16);
+    const int n = line_class_Ls(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, Ls, 16, ps.ext);
     int best = 0;
     for (int i = 0; i < n; ++i) {
         const int L = Ls[i];
@@ -217,7 +234,7 @@ int partition_length(const PassHost &ps, bool f32, int P) {
         if ((P - 1) * L > ps.N - ps.nl) continue;   // every right-closure row in the last partition
         if (P > 1 && (P - 1) * L >= ps.N) continue;                            // no empty partition
         if (!ps.periodic && P > 1 && ps.dir != 0) {
-            const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L);
+            const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L, ps.ext);
             if (!k || (P - 1) * L + k->hw > ps.N + ps.ng) continue;
         }
         if (!best || L < best) best = L;
@@ -235,7 +252,7 @@ int candidate_Ps(const PassHost &ps, bool f32, size_t max_lds, int out[3]) {
     for (int P = 1; P <= 4; P *= 2) {
         const int L = partition_length(ps, f32, P);
         if (!L) continue;
-        const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L);
+        const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L, ps.ext);
         if (!k) continue;
         if (ps.periodic && k->hw > ps.N) continue;
         size_t lds = exch_bytes(ps.nl, ps.nops, P, ps.periodic, es);
@@ -320,7 +337,7 @@ void fill_coef_block(double *cb, const Scheme &s) {
 void place_pass(PassHost &ps, bool f32, int P) {
     ps.P = P;
     ps.L = partition_length(ps, f32, P);
-    ps.cls = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, ps.L);
+    ps.cls = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, ps.L, ps.ext);
     ps.lcode = 0;
     for (int j = 0; j < ps.cls->nL; ++j)
         if (ps.cls->Ls[j] == ps.L) ps.lcode = j;
@@ -408,6 +425,93 @@ bool xcd_dispatch_ok(int device) {
     return ok;
 }
 
+// Device records of the hybrid closure iteration: one IterOp per (pass,
+// operator) with its neighbours on the lattice, the end-node weights (FP64,
+// built on the device), the end-value arrays, and each pass's ev_base.
+cfd_status build_iteration(cfd_plan *p, std::vector<PassDesc> &pd, const std::vector<std::array<int, 2>> &pass_tab,
+                           const std::vector<int64_t> &toffs) {
+    const int nb = (int)p->blocks.size();
+    const int bx = p->lat[0], by = p->lat[1];
+    auto block_of = [&](int kx, int ky, int kz) { return (kz * by + ky) * bx + kx; };
+    // (pass, op) units and their neighbours
+    std::map<std::pair<int, int>, int> opidx;
+    std::vector<std::pair<int, int>> pops;
+    for (size_t i = 0; i < p->passes.size(); ++i)
+        for (int o = 0; o < p->passes[i].nops; ++o) {
+            opidx[std::make_pair((int)i, o)] = (int)pops.size();
+            pops.push_back(std::make_pair((int)i, o));
+        }
+    auto find_pass = [&](int block, int dir, int op) -> int {
+        for (size_t i = 0; i < p->passes.size(); ++i) {
+            const PassHost &q = p->passes[i];
+            if (q.block != block || q.dir != dir) continue;
+            for (int o = 0; o < q.nops; ++o)
+                if (q.op[o] == op) return opidx[std::make_pair((int)i, o)];
+        }
+        return -1;
+    };
+    // end-node weights per (op scheme, N)
+    std::map<std::pair<int, int>, int64_t> wofs;
+    std::vector<unsigned char> wspecs;
+    int64_t wtotal = 0;
+    int maxN = 0;
+    std::vector<unsigned char> recs(pops.size() * iter_op_size());
+    int64_t ubase = 0;
+    int max_units = 0;
+    for (size_t u = 0; u < pops.size(); ++u) {
+        const int i = pops[u].first, o = pops[u].second;
+        const PassHost &ps = p->passes[i];
+        const int op = ps.op[o];
+        const int b = ps.block;
+        const int kx = b % bx, ky = (b / bx) % by, kz = b / (bx * by);
+        int km[3] = {kx, ky, kz}, kp[3] = {kx, ky, kz};
+        km[ps.dir] = (km[ps.dir] + p->lat[ps.dir] - 1) % p->lat[ps.dir];
+        kp[ps.dir] = (kp[ps.dir] + 1) % p->lat[ps.dir];
+        const int nm = find_pass(block_of(km[0], km[1], km[2]), ps.dir, op);
+        const int np = find_pass(block_of(kp[0], kp[1], kp[2]), ps.dir, op);
+        if (nm < 0 || np < 0 || b >= nb) return fail(CFD_EINVAL, "hybrid iteration: neighbour pass not found");
+        auto wk = std::make_pair(ps.sch[o], ps.N);
+        if (!wofs.count(wk)) {
+            wofs[wk] = wtotal;
+            const size_t at = wspecs.size();
+            wspecs.resize(at + end_weight_spec_size());
+            fill_end_weight_spec(wspecs.data() + at, ps.N, p->iter_c, p->base_schemes[ps.sch[o]],
+                                 p->schemes[ps.sch[o]], wtotal);
+            wtotal += 4 * (int64_t)(ps.N + 2 * kMaxHalf);
+            maxN = std::max(maxN, ps.N);
+        }
+        const int nunits = pd[i].nlines * ps.nfield;
+        const int64_t gofs = toffs[pass_tab[i][o]] + table_gvec_offset(ps.P * ps.L, ps.P, ps.nl);
+        fill_iter_op(recs.data() + u * iter_op_size(), i, o, nm, np, ubase, nunits, ps.N, p->iter_c, ps.P * ps.L,
+                     wofs[wk], gofs, pd[i].hinv[o]);
+        pd[i].ev_base[o] = 2 * ubase;
+        ubase += nunits;
+        max_units = std::max(max_units, nunits);
+    }
+    const int nw = (int)(wspecs.size() / end_weight_spec_size());
+    const size_t es = p->dtype == CFD_F64 ? 8 : 4;
+    HIPCHK(dmalloc((void **)&p->d_iops.p, recs.size()));
+    HIPCHK(hipMemcpy(p->d_iops.p, recs.data(), recs.size(), hipMemcpyHostToDevice));
+    HIPCHK(dmalloc((void **)&p->d_weights.p, std::max<int64_t>(1, wtotal) * sizeof(double)));
+    for (DevBuf *bp : {&p->d_ends0, &p->d_endsf, &p->d_ebufA, &p->d_ebufB, &p->d_ev})
+        HIPCHK(dmalloc((void **)&bp->p, std::max<int64_t>(1, 2 * ubase) * es));
+    {
+        void *d_specs = nullptr, *d_scr = nullptr;
+        hipError_t e = dmalloc(&d_specs, std::max<size_t>(1, wspecs.size()));
+        if (e == hipSuccess) e = dmalloc(&d_scr, (size_t)4 * nw * 2 * maxN * sizeof(double) + 8);
+        if (e == hipSuccess) e = hipMemcpy(d_specs, wspecs.data(), wspecs.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_end_weights(nw, d_specs, (double *)p->d_weights.p, (double *)d_scr, maxN, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (d_specs) (void)hipFree(d_specs);
+        if (d_scr) (void)hipFree(d_scr);
+        if (e != hipSuccess) return hip_fail(e, "building end-node weights");
+    }
+    p->n_iops = (int)pops.size();
+    p->iter_max_units = max_units;
+    return CFD_OK;
+}
+
 cfd_status build_groups(cfd_plan *p) {
     HIPCHK(hipSetDevice(p->device));
     p->drop_graph();
@@ -463,9 +567,8 @@ cfd_status build_groups(cfd_plan *p) {
         fill_coef_block(host_tab.data() + offs[t], s);
         const int L = k.L;
         fill_tabspec(specs.data() + t * tabspec_size(), k.N, k.P, L, s.nl, k.periodic ? 0 : s.nc, k.periodic,
-                     s.lhs, offs[t]);
-        const int64_t B = 2 * s.nl * k.P;
-        scratch_per = std::max<int64_t>(scratch_per, 2 * B * B + L + (int64_t)k.P * L * 5 + 8);
+                     s.lhs, offs[t], s.ext, s.cl_d0, s.cl_up, s.gamma);
+        scratch_per = std::max<int64_t>(scratch_per, tab_scratch(k.P, L, s.nl));
     }
     p->d_tab64.release();
     p->d_tab32.release();
@@ -504,6 +607,11 @@ cfd_status build_groups(cfd_plan *p) {
     HIPCHK(hipMemcpy(p->d_taboff.p, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice));
 
     std::vector<PassDesc> pd = pass_descs(p, pass_tab);
+    p->release_iteration();
+    if (p->iter_n > 0) {
+        cfd_status r = build_iteration(p, pd, pass_tab, offs);
+        if (r != CFD_OK) return r;
+    }
     p->d_pass.release();
     HIPCHK(dmalloc((void **)&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
@@ -768,7 +876,8 @@ cfd_status launch_group(cfd_plan *p, const Group &g, const void *in, void *out, 
         const void *tabs = (p->dtype == CFD_F64) ? p->d_tab64.p : p->d_tab32.p;
         const int *qoff = (g.qoff_index >= 0) ? (const int *)p->d_qoff.p + g.qoff_index : nullptr;
         e = launch_lines(g.fn, grid, g.lds, st, (const WorkItem *)p->d_items.p + g.item0, (int)g.nitems, qoff,
-                         (const PassDesc *)p->d_pass.p, tabs, (const int64_t *)p->d_taboff.p, in, out);
+                         (const PassDesc *)p->d_pass.p, tabs, (const int64_t *)p->d_taboff.p, in, out,
+                         p->iter_n > 0 ? p->d_ev.p : nullptr);
     }
     if (e != hipSuccess) return hip_fail(e, "launching a kernel group");
     return CFD_OK;
@@ -825,7 +934,32 @@ cfd_status build(cfd_plan *p) {
     return r;
 }
 
+// Hybrid closure iteration, before the line kernels: end-node values of
+// iterate 0 and of the zero-end-value solutions, iter_n - 1 exchange steps,
+// then every line's end values for the last iterate (into d_ev).
+cfd_status enqueue_iteration(cfd_plan *p, const void *in, hipStream_t st) {
+    const int f32 = p->dtype != CFD_F64;
+    hipError_t e = launch_end_values(f32, p->n_iops, p->iter_max_units, p->d_iops.p, (const PassDesc *)p->d_pass.p,
+                                     (const double *)p->d_weights.p, in, p->d_ends0.p, p->d_endsf.p, st);
+    const void *prev = p->d_ends0.p;
+    for (int i = 1; i < p->iter_n && e == hipSuccess; ++i) {
+        void *next = (i % 2) ? p->d_ebufA.p : p->d_ebufB.p;
+        e = launch_iter_ends(f32, p->n_iops, p->iter_max_units, p->d_iops.p, (const double *)p->d_tab64.p,
+                             p->d_endsf.p, prev, next, 0, st);
+        prev = next;
+    }
+    if (e == hipSuccess)
+        e = launch_iter_ends(f32, p->n_iops, p->iter_max_units, p->d_iops.p, (const double *)p->d_tab64.p,
+                             p->d_endsf.p, prev, p->d_ev.p, 1, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the closure iteration");
+    return CFD_OK;
+}
+
 cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
+    if (p->iter_n > 0 && p->n_iops > 0) {
+        cfd_status r = enqueue_iteration(p, in, st);
+        if (r != CFD_OK) return r;
+    }
     std::vector<const Group *> act;
     for (const Group &g : p->groups)
         if (g.nitems > 0) act.push_back(&g);
@@ -1594,6 +1728,80 @@ cfd_status cfd_wave_rk_stage_halo(cfd_plan *p, const void *u0_dev, const void *s
     for (int d = 0; d < 3; ++d)
         if (b0.ng > b0.n[d]) return fail(CFD_ESHAPE, "cfd_wave_rk_stage_halo: ghost width exceeds block extent");
     return wave_stage(p, u0_dev, src_dev, stage_dev, acc_in_dev, acc_dev, derivs_dev, a, b, bx, by, bz, stream);
+}
+
+cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, int bz) {
+    if (!p) return fail(CFD_EINVAL, "cfd_plan_set_iteration: null plan");
+    if (iterations < 0) return fail(CFD_EINVAL, "cfd_plan_set_iteration: negative iteration count");
+    if (p->dtype == CFD_MIXED_BF16)
+        return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: not available on the dense mixed-precision path");
+    const int c = 2;
+    auto restore = [&]() {
+        if (!p->base_schemes.empty()) p->schemes = p->base_schemes;
+        p->base_schemes.clear();
+        for (PassHost &ps : p->passes) ps.ext = 0;
+        p->iter_n = 0;
+    };
+    if (iterations == 0) {
+        restore();
+        for (PassHost &ps : p->passes) {
+            ps.mi = ps.hw = 0;
+            for (int k = 0; k < ps.nops; ++k) {
+                const Scheme &s = p->schemes[ps.sch[k]];
+                ps.mi = std::max(ps.mi, s.m);
+                ps.hw = std::max(ps.hw, std::max(s.m, ps.periodic ? 0 : s.mc));
+            }
+        }
+        HIPCHK(hipSetDevice(p->device));
+        return build(p);
+    }
+    if (bx < 1 || by < 1 || bz < 1 || (int64_t)bx * by * bz != (int64_t)p->blocks.size())
+        return fail(CFD_EINVAL, "cfd_plan_set_iteration: lattice does not match the plan's block count");
+    const cfd_block &b0 = p->blocks[0];
+    for (const cfd_block &b : p->blocks) {
+        if (b.n[0] != b0.n[0] || b.n[1] != b0.n[1] || b.n[2] != b0.n[2] || b.ng != b0.ng)
+            return fail(CFD_EINVAL, "cfd_plan_set_iteration: blocks differ in shape");
+        for (int d = 0; d < 3; ++d)
+            if (b.boundary[d] != CFD_BOUNDARY_CLOSURE)
+                return fail(CFD_EINVAL, "cfd_plan_set_iteration: blocks must use the block closure in every "
+                                        "direction (the lattice wraps)");
+    }
+    std::vector<Scheme> base = p->base_schemes.empty() ? p->schemes : p->base_schemes;
+    std::vector<Scheme> it(base.size());
+    for (size_t o = 0; o < base.size(); ++o) {
+        std::string err;
+        cfd_status st = make_iterated(base[o], c, it[o], err);
+        if (st != CFD_OK) return fail(st, "cfd_plan_set_iteration: scheme '" + base[o].name + "': " + err);
+        const int need = std::max(required_ghosts(base[o], 0), required_ghosts(it[o], 0));
+        if (b0.ng < need) {
+            char buf[200];
+            std::snprintf(buf, sizeof buf, "cfd_plan_set_iteration: scheme '%s' iterated needs %d ghost layers, "
+                          "blocks have %d", base[o].name.c_str(), need, b0.ng);
+            return fail(CFD_EGHOST, buf);
+        }
+        if (b0.n[p->ops[o].dir] < 2 * c + 1)
+            return fail(CFD_ESHAPE, "cfd_plan_set_iteration: block too short for the iteration's end nodes");
+    }
+    p->base_schemes = base;
+    p->schemes = it;
+    for (PassHost &ps : p->passes) {
+        ps.ext = 1;
+        ps.mi = ps.hw = 0;
+        for (int k = 0; k < ps.nops; ++k) {
+            const Scheme &s = p->schemes[ps.sch[k]];
+            ps.mi = std::max(ps.mi, s.m);
+            ps.hw = std::max(ps.hw, std::max(s.m, s.mc));
+        }
+    }
+    p->iter_n = iterations;
+    p->iter_c = c;
+    p->lat[0] = bx;
+    p->lat[1] = by;
+    p->lat[2] = bz;
+    HIPCHK(hipSetDevice(p->device));
+    cfd_status st = build(p);
+    if (st != CFD_OK) restore();
+    return st;
 }
 
 void cfd_debug_fail_alloc(long long n) { g_alloc_fail_after.store(n < 0 ? -1 : n); }

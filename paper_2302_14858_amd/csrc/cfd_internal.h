@@ -29,6 +29,12 @@ struct Scheme {
     double lhs[2 * kMaxNL + 1] = {0};         // alpha^(d)_{-2..2}
     double rhs[2 * kMaxHalf + 1] = {0};       // alpha^(0)_{-5..5}
     double cl[kMaxNL][2 * kMaxHalf + 1] = {};  // closure rows k*_- + j, centred at 5
+    // Iterated closure (Sec. ssec:domdec_iter): the closure row k*_- is an
+    // implicit row of D_L, (cl_d0, cl_up) on columns (k*_-, k*_- + 1), mirrored
+    // at k*_+, and its right side also carries gamma times an end value taken
+    // from the neighbouring block's previous iterate.
+    int ext = 0;
+    double cl_d0 = 1.0, cl_up = 0.0, gamma = 0.0;
     std::string name;
 };
 
@@ -37,6 +43,7 @@ struct Scheme {
 cfd_status design_centred(int d, int order, int nl, int m, double eta_c, int closure_mc,
                           int matched, Scheme &out, std::string &err);
 cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &err);
+cfd_status make_iterated(const Scheme &base, int c, Scheme &out, std::string &err);
 cfd_status check_taylor(const Scheme &s, std::string &err);
 cfd_status check_centred(const Scheme &s, std::string &err);
 cfd_status check_symbol(const Scheme &s, std::string &err);
@@ -57,6 +64,8 @@ int required_ghosts(const Scheme &s, int periodic);
 //                        right neighbour unknowns
 //   krow [p][2nl][B]     rows of the inverse of the reduced boundary system,
 //                        B = 2 nl P
+//   gvec [2][Npad]       iterated closures: response to the left / right end
+//                        value (zero otherwise)
 constexpr int kCoefA = 0;
 constexpr int kCoefCL = 11;
 constexpr int kCoefCR = 33;
@@ -66,6 +75,10 @@ constexpr int kCoefHdr = 64;
 inline int64_t table_elems(int N, int P, int nl) {
     const int64_t L = N / P, B = 2 * nl * P;
     if (nl == 0) return kCoefHdr;
+    return kCoefHdr + (int64_t)N * 5 + (int64_t)P * 2 * nl * L + (int64_t)P * 2 * nl * B + 2 * (int64_t)N;
+}
+inline int64_t table_gvec_offset(int N, int P, int nl) {   // N here is P L
+    const int64_t L = N / P, B = 2 * nl * P;
     return kCoefHdr + (int64_t)N * 5 + (int64_t)P * 2 * nl * L + (int64_t)P * 2 * nl * B;
 }
 
@@ -85,6 +98,8 @@ struct PassDesc {
     int32_t field0;         // first field index
     int32_t tab[2];         // table index per op
     double hinv[2];         // h^-d per op
+    int64_t ev_base[2];     // iterated closures: element offset of each op's end values
+                            // (two per line: left, right; field-major), else unused
 };
 
 // One work item: 64 * (4 / P) lines of one field of one pass.
@@ -119,6 +134,7 @@ struct PassHost {
     int op[2] = {0, 0};   // plan op indices (output order)
     int sch[2] = {0, 0};  // scheme indices
     int N = 0, ng = 0, periodic = 0, nl = 0, par = 0, mi = 0, hw = 0;
+    int ext = 0;          // iterated closures: the kernel adds the end-value terms
     int P = 0, L = 0, lcode = 0;
     int C = 1;            // x lines: column chunks the LDS tile is staged in (divides P)
     const LineClass *cls = nullptr;
@@ -138,11 +154,11 @@ void fill_coef_block(double *cb, const Scheme &s);
 cfd_status set_error(cfd_status st, const std::string &msg);   // message for cfd_last_error
 size_t pass_lds(const PassHost &ps, bool f32);
 
-const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L);
-int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap);
+const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext = 0);
+int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap, int ext = 0);
 hipError_t launch_lines(const void *fn, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
                         const int *qoff, const PassDesc *passes, const void *tabs, const int64_t *taboff,
-                        const void *in, void *out);
+                        const void *in, void *out, const void *ev = nullptr);
 hipError_t launch_build_tables(int ntab, const void *specs, double *data, double *scratch, int64_t scratch_per,
                                int *status, hipStream_t st);
 hipError_t launch_to_f32(int64_t n, const double *a, float *b, hipStream_t st);
@@ -150,7 +166,12 @@ hipError_t launch_xcc_probe(int grid, int *out, hipStream_t st);
 hipError_t launch_count_diff(int64_t nwords, const void *a, const void *b, unsigned long long *cnt, hipStream_t st);
 size_t tabspec_size();
 void fill_tabspec(void *dst, int N, int P, int L, int nl, int nc, int periodic, const double *alpha5,
-                  int64_t off);
+                  int64_t off, int ext = 0, double cl_d0 = 1.0, double cl_up = 0.0, double gamma = 0.0);
+// scratch (doubles) the table builder needs per table
+inline int64_t tab_scratch(int P, int L, int nl) {
+    const int64_t B = 2 * nl * P, Npad = (int64_t)P * L;
+    return 2 * B * B + L + Npad * 5 + B + Npad + 8;
+}
 }  // namespace cfd
 
 namespace cfd {
@@ -162,6 +183,20 @@ hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *sta
                              const void *d, const int64_t *in_off, const int64_t *out_off, const int *shapes,
                              const int *unitpre, int nblocks, int nunits, double a, double b, int bx, int by, int bz,
                              hipStream_t st);   // bx = 0: no ghost refresh
+}  // namespace cfd
+
+namespace cfd {
+// hybrid closure iteration (cfd_iterate.hip)
+size_t end_weight_spec_size();
+size_t iter_op_size();
+void fill_end_weight_spec(void *dst, int N, int c, const Scheme &blk, const Scheme &it, int64_t off);
+void fill_iter_op(void *dst, int pass, int o, int nbr_m, int nbr_p, int64_t ubase, int nunits, int N, int c, int Npad,
+                  int64_t wofs, int64_t gofs, double hinv);
+hipError_t launch_end_weights(int ntab, const void *specs, double *data, double *scratch, int stride, hipStream_t st);
+hipError_t launch_end_values(int f32, int nops, int max_units, const void *ops, const PassDesc *passes,
+                             const double *weights, const void *in, void *ends0, void *endsf, hipStream_t st);
+hipError_t launch_iter_ends(int f32, int nops, int max_units, const void *ops, const double *tabs64, const void *endsf,
+                            const void *prev, void *next, int gather, hipStream_t st);
 }  // namespace cfd
 
 namespace cfd {

@@ -19,13 +19,22 @@ struct TabSpec {
     int N, P, L, nl, nc, periodic;   // line length, partitions, rows per partition (P L >= N)
     double alpha[2 * kMaxNL + 1];
     int64_t off;   // element offset of the table (coefficient block first)
+    int ext;                         // implicit closure rows (iterated closure, nc = 1)
+    double cl_d0, cl_up, gamma;      // their D_L entries and end-value weight
 };
 
 // Entry of D_L in global row k at unwrapped offset o (column k + o).  Rows
-// past the line end (padding of the last partition) are identity rows.
+// past the line end (padding of the last partition) are identity rows, and
+// so are the closure rows unless they are the implicit rows of an iterated
+// closure: (cl_d0, cl_up) on row 0, mirrored on row N - 1.
 __device__ inline double dl_entry(const TabSpec &s, int k, int o) {
-    const bool ident = !s.periodic && (k < s.nc || k >= s.N - s.nc);
-    if (ident) return o == 0 ? 1.0 : 0.0;
+    if (!s.periodic && k >= s.N) return o == 0 ? 1.0 : 0.0;
+    const bool clo = !s.periodic && (k < s.nc || k >= s.N - s.nc);
+    if (clo && s.ext) {
+        if (o == 0) return s.cl_d0;
+        return (k < s.nc ? o == 1 : o == -1) ? s.cl_up : 0.0;
+    }
+    if (clo) return o == 0 ? 1.0 : 0.0;
     if (o < -s.nl || o > s.nl) return 0.0;
     if (!s.periodic && (k + o < 0 || k + o >= s.N)) return 0.0;
     return s.alpha[kMaxNL + o];
@@ -179,6 +188,30 @@ __global__ void k_build_tables(int ntab, const TabSpec *__restrict__ specs, doub
                 krow[((int64_t)p * 2 * nl + q) * B + b] = (src >= 0) ? Kinv[src * B + b] : 0.0;
         }
     }
+    // 5. end-value influence vectors of an iterated closure: the solution for
+    //    a right side gamma at row 0 (left end value) and at row N - 1 (right),
+    //    by the same partition algebra the line kernel runs; zero otherwise
+    double *gv = krow + (int64_t)P * 2 * nl * B;         // [2][Npad]
+    double *yb = facs + (int64_t)Npad * 5;               // B boundary entries
+    double *gtmp = yb + B;                               // Npad
+    for (int side = 0; side < 2; ++side) {
+        double *g = gv + (int64_t)side * Npad;
+        for (int k = 0; k < Npad; ++k) g[k] = 0.0;
+        if (!s.ext || s.periodic) continue;
+        g[side ? s.N - 1 : 0] = s.gamma;
+        for (int p = 0; p < P; ++p) local_solve(facs + (int64_t)p * L * 5, L, nl, g + (int64_t)p * L);
+        for (int p = 0; p < P; ++p)
+            for (int tq = 0; tq < 2 * nl; ++tq) yb[p * 2 * nl + tq] = g[p * L + (tq < nl ? tq : L - 2 * nl + tq)];
+        for (int k = 0; k < Npad; ++k) gtmp[k] = g[k];
+        for (int p = 0; p < P; ++p) {
+            for (int q = 0; q < 2 * nl; ++q) {
+                double xq = 0.0;
+                for (int b = 0; b < B; ++b) xq += krow[((int64_t)p * 2 * nl + q) * B + b] * yb[b];
+                for (int i = 0; i < L; ++i) gtmp[p * L + i] -= xq * spk[((int64_t)p * 2 * nl + q) * L + i];
+            }
+        }
+        for (int k = 0; k < Npad; ++k) g[k] = gtmp[k];
+    }
     status[t] = bad;
 }
 
@@ -212,13 +245,13 @@ const LineClass kLineClassesF64[] = { CFD_LINE_CLASSES(double, 0) };
 extern const LineClass kLineClassesF32[];
 extern const int kNumLineClassesF32;
 
-const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L) {
+const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext) {
     const LineClass *tab = f32 ? kLineClassesF32 : kLineClassesF64;
     const int n = f32 ? kNumLineClassesF32 : (int)(sizeof(kLineClassesF64) / sizeof(kLineClassesF64[0]));
     const LineClass *best = nullptr;
     for (int i = 0; i < n; ++i) {
         const LineClass &k = tab[i];
-        if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw) continue;
+        if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw || k.ext != ext) continue;
         bool hasL = false;
         for (int j = 0; j < k.nL; ++j) hasL |= (k.Ls[j] == L);
         if (!hasL) continue;
@@ -229,13 +262,13 @@ const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int
     return best;
 }
 
-int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap) {
+int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap, int ext) {
     const LineClass *tab = f32 ? kLineClassesF32 : kLineClassesF64;
     const int n = f32 ? kNumLineClassesF32 : (int)(sizeof(kLineClassesF64) / sizeof(kLineClassesF64[0]));
     int cnt = 0;
     for (int i = 0; i < n; ++i) {
         const LineClass &k = tab[i];
-        if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw) continue;
+        if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw || k.ext != ext) continue;
         for (int j = 0; j < k.nL; ++j) {
             bool seen = false;
             for (int q = 0; q < cnt; ++q) seen |= (Ls[q] == k.Ls[j]);
@@ -247,9 +280,9 @@ int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, i
 
 hipError_t launch_lines(const void *fn, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
                         const int *qoff, const PassDesc *passes, const void *tabs, const int64_t *taboff,
-                        const void *in, void *out) {
+                        const void *in, void *out, const void *ev) {
     void *args[] = {(void *)&items, (void *)&nitems, (void *)&qoff, (void *)&passes, (void *)&tabs,
-                    (void *)&taboff, (void *)&in, (void *)&out};
+                    (void *)&taboff, (void *)&in, (void *)&out, (void *)&ev};
     return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWGW), args, lds, st);
 }
 
@@ -283,11 +316,13 @@ hipError_t launch_count_diff(int64_t nwords, const void *a, const void *b, unsig
 
 size_t tabspec_size() { return sizeof(TabSpec); }
 
-void fill_tabspec(void *dst, int N, int P, int L, int nl, int nc, int periodic, const double *alpha5, int64_t off) {
+void fill_tabspec(void *dst, int N, int P, int L, int nl, int nc, int periodic, const double *alpha5, int64_t off,
+                  int ext, double cl_d0, double cl_up, double gamma) {
     TabSpec s;
     s.N = N; s.P = P; s.L = L; s.nl = nl; s.nc = nc; s.periodic = periodic;
     for (int i = 0; i < 2 * kMaxNL + 1; ++i) s.alpha[i] = alpha5[i];
     s.off = off;
+    s.ext = ext; s.cl_d0 = cl_d0; s.cl_up = cl_up; s.gamma = gamma;
     *reinterpret_cast<TabSpec *>(dst) = s;
 }
 

@@ -14,11 +14,15 @@ struct LineClass {
     int nL;
     int Ls[8];
     const void *fn;
+    int ext;      // adds the end-value terms of an iterated closure
 };
 
 #define CFD_LC(T, NL, NOPS, PAR, MI, HW, ...)                                                        \
     LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
-              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, __VA_ARGS__>)}
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, false, __VA_ARGS__>), 0}
+#define CFD_LC_EXT(T, NL, NOPS, PAR, MI, HW, ...)                                                    \
+    LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, true, __VA_ARGS__>), 1}
 
 // The classes compiled for each precision.
 #define CFD_LINE_CLASSES(T, F32)                                                  \
@@ -42,8 +46,12 @@ struct LineClass {
     CFD_LC(T, 2, 1, 0, 5, 5, 8, 12, 16, 24, 32),                                  \
     /* explicit schemes */                                                        \
     CFD_LC(T, 0, 1, 1, 5, 5, 8, 12, 16, 24, 32),                                  \
-    CFD_LC(T, 0, 1, 0, 5, 5, 8, 12, 16, 24, 32)
+    CFD_LC(T, 0, 1, 0, 5, 5, 8, 12, 16, 24, 32),                                  \
+    /* iterated closures of tridiagonal schemes (hybrid closure iteration) */    \
+    CFD_LC_EXT(T, 1, 2, 1, 3, 4, 8, 12, 16),                                      \
+    CFD_LC_EXT(T, 1, 1, 1, 3, 4, 8, 12, 16, 24, 32),                              \
+    CFD_LC_EXT(T, 1, 1, 0, 5, 5, 8, 12, 16, 24, 32)
 
-const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L);
+const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext);
 
 }  // namespace cfd

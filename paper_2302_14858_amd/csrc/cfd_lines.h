@@ -81,11 +81,12 @@ struct LineCtx {
     const T *fbase;         // x lines: node (0, 0, 0) of the item's field
     int line0;              // x lines: first line of the item
     bool periodic;
+    T em[2], ep[2];         // iterated closures: this lane's end values per op
 };
 
 // One lane: the p-th partition (L rows) of its line, all NOPS operators.
 // Leaves the solution (times h^-d) in y.
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool X, bool PAD>
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool X, bool PAD, bool EXT>
 __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS][L], T (&fin)[L + 2 * HW]) {
     const PassDesc &pd = *c.pd;
     const int N = pd.N;
@@ -254,6 +255,18 @@ __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS
 #pragma unroll
         for (int i = 0; i < L; ++i) y[o][i] *= hinv;
     }
+    if constexpr (EXT) {
+        // iterated closure (Eq. iter_center_P): the block system carries the
+        // two end values on its closure rows; add their responses (the
+        // influence vectors of the table, zero on padding rows)
+        const int64_t B = 2 * NL * c.P;
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o) {
+            const T *gv = c.tb[o] + kCoefHdr + (int64_t)Npad * 5 + (int64_t)c.P * 2 * NL * L + (int64_t)c.P * 2 * NL * B;
+#pragma unroll
+            for (int i = 0; i < L; ++i) y[o][i] += c.em[o] * gv[k0 + i] + c.ep[o] * gv[Npad + k0 + i];
+        }
+    }
 }
 
 // Stage the x-lines of this item in LDS: column t of row r holds node n0 + t
@@ -340,7 +353,7 @@ __device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N,
 }
 
 // Item body for one compiled partition length L.
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool PAD, bool CHK>
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool PAD, bool CHK, bool EXT>
 __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *out, bool xdir, bool active,
                                          int lu, int lv) {
     const PassDesc &pd = *c.pd;
@@ -370,7 +383,7 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
 #pragma unroll
             for (int t = 0; t < L + 2 * HW; ++t) fin[t] = c.tile[c.trow * c.tpitch + c.p * L + t];
         }
-        solve_partition<T, NL, NOPS, PAR, MI, HW, L, true, PAD>(c, y, fin);
+        solve_partition<T, NL, NOPS, PAR, MI, HW, L, true, PAD, EXT>(c, y, fin);
         // results back through the tile, chunk by chunk, then contiguous
         // coalesced stores: x-lines line0.. of one field are consecutive rows
         // of the interior output
@@ -412,7 +425,7 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
         }
     } else {
         T fin[L + 2 * HW];
-        solve_partition<T, NL, NOPS, PAR, MI, HW, L, false, PAD>(c, y, fin);
+        solve_partition<T, NL, NOPS, PAR, MI, HW, L, false, PAD, EXT>(c, y, fin);
         if (active) {
 #pragma unroll
             for (int o = 0; o < NOPS; ++o) {
@@ -436,18 +449,18 @@ struct LSet {
     static constexpr int n = sizeof...(Ls);
 };
 
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool CHK, int L0, int... Ls>
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool CHK, bool EXT, int L0, int... Ls>
 __device__ __forceinline__ void dispatch_L(int lcode, bool pad, LineCtx<T> &c, const WorkItem &wi, T *out,
                                            bool xdir, bool active, int lu, int lv) {
     if (lcode == 0) {
         if (pad)
-            run_item<T, NL, NOPS, PAR, MI, HW, L0, true, CHK>(c, wi, out, xdir, active, lu, lv);
+            run_item<T, NL, NOPS, PAR, MI, HW, L0, true, CHK, EXT>(c, wi, out, xdir, active, lu, lv);
         else
-            run_item<T, NL, NOPS, PAR, MI, HW, L0, false, CHK>(c, wi, out, xdir, active, lu, lv);
+            run_item<T, NL, NOPS, PAR, MI, HW, L0, false, CHK, EXT>(c, wi, out, xdir, active, lu, lv);
         return;
     }
-    if constexpr (sizeof...(Ls) > 0) dispatch_L<T, NL, NOPS, PAR, MI, HW, CHK, Ls...>(lcode - 1, pad, c, wi, out,
-                                                                                      xdir, active, lu, lv);
+    if constexpr (sizeof...(Ls) > 0)
+        dispatch_L<T, NL, NOPS, PAR, MI, HW, CHK, EXT, Ls...>(lcode - 1, pad, c, wi, out, xdir, active, lu, lv);
 }
 
 // Classes whose partitions reach this many rows stage long x lines in column
@@ -464,12 +477,13 @@ constexpr int max_L() {
 // Persistent line kernel: every workgroup walks the work list with a grid
 // stride.  Work item meta: P in bits 0..3, index of L in the compiled set in
 // bits 4..7, x lines: column chunks - 1 in bits 8..9.  Dynamic LDS: exchange
-// area (as much as the item uses), then the x tile (one column chunk).
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int... Ls>
+// area and x tile (one column chunk), overlaid.  EXT: iterated closures, with
+// each line's two end values per op read from ev.
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool EXT, int... Ls>
 __global__ void __launch_bounds__(64 * kWGW)
 k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ qoff,
         const PassDesc *__restrict__ passes, const T *__restrict__ tabs, const int64_t *__restrict__ taboff,
-        const T *__restrict__ in, T *__restrict__ out) {
+        const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ ev) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *exch = reinterpret_cast<T *>(smem_raw);
     constexpr int kLs[] = {Ls...};
@@ -521,6 +535,14 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
         int line = wi.line0 + c.sub * 64 + g;
         const bool active = line < pd.nlines;
         if (!active) line = pd.nlines - 1;
+        if constexpr (EXT) {
+#pragma unroll
+            for (int o = 0; o < NOPS; ++o) {
+                const T *e = ev + pd.ev_base[o] + ((int64_t)wi.field * pd.nlines + line) * 2;
+                c.em[o] = e[0];
+                c.ep[o] = e[1];
+            }
+        }
         const int lu = line % pd.nu;
         const int lv = line / pd.nu;
         const T *fbase = in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride;
@@ -548,7 +570,7 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
             c.src = fbase + (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
         }
         const bool pad = c.P * kLs[lcode] != pd.N;
-        dispatch_L<T, NL, NOPS, PAR, MI, HW, kChunked, Ls...>(lcode, pad, c, wi, out, xdir, active, lu, lv);
+        dispatch_L<T, NL, NOPS, PAR, MI, HW, kChunked, EXT, Ls...>(lcode, pad, c, wi, out, xdir, active, lu, lv);
     }
 }
 

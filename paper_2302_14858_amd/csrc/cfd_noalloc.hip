@@ -170,8 +170,7 @@ extern "C" cfd_status cfd_apply_block_noalloc(const cfd_scheme *sc, const cfd_bl
     // scratch layout: FP64 table, FP32 table, factorisation scratch, records, work list
     const int Npad = ps.P * ps.L;
     const int64_t tel = (table_elems(Npad, ps.P, s.nl) + 7) & ~int64_t(7);
-    const int64_t B = 2 * s.nl * ps.P;
-    const int64_t bscr = 2 * B * B + ps.L + (int64_t)ps.P * ps.L * 5 + 8;
+    const int64_t bscr = tab_scratch(ps.P, ps.L, s.nl);
     const int per_item = kWave * (4 / ps.P);
     const int64_t nlines = (int64_t)b.n[dir == 0 ? 1 : 0] * b.n[dir == 2 ? 1 : 2];
     const int64_t items_per_field = (nlines + per_item - 1) / per_item;
@@ -213,7 +212,8 @@ extern "C" cfd_status cfd_apply_block_noalloc(const cfd_scheme *sc, const cfd_bl
     SetupArgs a;
     std::memset(&a, 0, sizeof a);
     fill_coef_block(a.coef, s);
-    fill_tabspec(a.spec, N, ps.P, ps.L, s.nl, per ? 0 : s.nc, per, s.lhs, 0);   // real length; rows >= N are padding
+    fill_tabspec(a.spec, N, ps.P, ps.L, s.nl, per ? 0 : s.nc, per, s.lhs, 0, s.ext, s.cl_d0, s.cl_up,
+                 s.gamma);   // real length; rows >= N are padding
     {
         const int64_t ob[2] = {0, 0};
         const int tab[2] = {0, 0};

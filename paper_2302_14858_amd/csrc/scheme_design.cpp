@@ -425,6 +425,58 @@ cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &e
     return st;
 }
 
+// The system one iterate of the hybrid closure iteration solves on a block
+// line (Eq. iter_center_P): the interior rows of a centred tridiagonal scheme
+// on k*_- - c + 1 .. k*_+ + c - 1, with the derivative at k*_- - c and
+// k*_+ + c fixed to end values e-, e+.  For c = 2 the extra row k*_- - 1,
+//   alpha e- + x_{-1} + alpha x_0 = r_{-1},
+// is eliminated into row k*_-:
+//   (1 - alpha^2) x_0 + alpha x_1 = r_0 - alpha r_{-1} + alpha^2 e-,
+// with r_k the interior stencil at row k, so the system on the block's own
+// nodes has an implicit closure row (1 - alpha^2, alpha) whose stencil is
+// a_m - alpha a_{m+1} (half-width M + 1) and whose end-value weight is
+// gamma = alpha^2; the right end is its mirror image.  For c = 1 the closure
+// row is the interior row itself with gamma = -alpha.
+cfd_status make_iterated(const Scheme &base, int c, Scheme &out, std::string &err) {
+    if (base.nl != 1) {
+        err = "the hybrid closure iteration is defined for tridiagonal schemes";
+        return CFD_EUNSUPPORTED;
+    }
+    if (c != 1 && c != 2) {
+        err = "iteration end nodes must lie 1 or 2 nodes past the block end";
+        return CFD_EINVAL;
+    }
+    const double al = base.lhs[kMaxNL + 1];
+    Scheme s = base;
+    s.nc = 1;
+    s.ext = 1;
+    s.cl_up = al;
+    for (int j = 0; j < kMaxNL; ++j)
+        for (int m = 0; m <= 2 * kMaxHalf; ++m) s.cl[j][m] = 0.0;
+    if (c == 1) {
+        s.cl_d0 = 1.0;
+        s.gamma = -al;
+        s.mc = base.m;
+        for (int m = -base.m; m <= base.m; ++m) s.cl[0][kMaxHalf + m] = base.rhs[kMaxHalf + m];
+    } else {
+        if (base.m + 1 > kMaxHalf) {
+            err = "iterated closure stencil wider than the supported half-width";
+            return CFD_EUNSUPPORTED;
+        }
+        s.cl_d0 = 1.0 - al * al;
+        s.gamma = al * al;
+        s.mc = base.m + 1;
+        for (int o = -base.m - 1; o <= base.m; ++o) {
+            const double a0 = (o >= -base.m) ? base.rhs[kMaxHalf + o] : 0.0;
+            const double a1 = (o + 1 <= base.m) ? base.rhs[kMaxHalf + o + 1] : 0.0;
+            s.cl[0][kMaxHalf + o] = a0 - al * a1;
+        }
+    }
+    s.name = base.name + ":iter";
+    out = s;
+    return CFD_OK;
+}
+
 // Taylor check of every row of a scheme (Eq. Tcons): interior rows and the
 // explicit closure rows, up to the formal order.
 cfd_status check_taylor(const Scheme &s, std::string &err) {

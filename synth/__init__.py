@@ -15,6 +15,8 @@ small-amplitude noise; uneven mesh blocks with ghost layers, Sec. 2.4):
                     origins uniform in [0,1)^3, 22 fields of 8 modes, k in [1,6]^3.
 * ``periodic256`` : periodic 256^3, h = 2 pi/256, 8 fields of 32 modes, k in [1,120]^3.
 * ``periodic_box``: small anisotropic periodic boxes (ragged line counts) for edge cases.
+* ``lattice``     : a periodic box tiled by equal blocks with closures (ghosts sampled
+                    from the same periodic field), for the hybrid closure iteration.
 * ``wave192``     : periodic 192^3 plane wave k = (3,5,7) for the first-order wave
                     system (phi, Pi, psi_x, psi_y, psi_z), as one periodic block
                     or as a 4x4x4 lattice of 48^3 blocks.
@@ -192,6 +194,26 @@ def periodic_box(seed: int = 6, n=(64, 5, 7), nfields: int = 2, nmodes: int = 16
         m.k = np.minimum(m.k, np.array([max(0, v // 2 - 1) for v in n]))
     data, offs = _fill([blk], nfields, lambda b, f, x, y, z: eval_modes(modes[f], x, y, z))
     return Workload("periodic_box", [blk], nfields, data, offs, [[m] for m in modes])
+
+
+def lattice(n=(16, 16, 16), lat=(3, 2, 2), ng: int = 4, nfields: int = 2, nmodes: int = 12, kmax: int = 6,
+            seed: int = 8) -> Workload:
+    """A periodic box [0, 2 pi)^3 tiled by lat[0] x lat[1] x lat[2] equal blocks of n interior nodes
+    (block index (kz*lat[1] + ky)*lat[0] + kx), cell-centred, with closures on every face; each field is
+    one sum of plane waves sampled on every block including its ghosts, so the ghosts equal the
+    neighbouring blocks' interior values."""
+    rng = np.random.default_rng(seed)
+    NG = [n[d] * lat[d] for d in range(3)]
+    h = tuple(2 * np.pi / v for v in NG)
+    modes = [_random_modes(rng, nmodes, 0, kmax, 1.0, exclude_zero=True) for _ in range(nfields)]
+    blocks = []
+    for kz in range(lat[2]):
+        for ky in range(lat[1]):
+            for kx in range(lat[0]):
+                org = tuple((k * n[d] + 0.5) * h[d] for d, k in enumerate((kx, ky, kz)))
+                blocks.append(Block(tuple(n), ng, h, (CLOSURE,) * 3, org))
+    data, offs = _fill(blocks, nfields, lambda b, f, x, y, z: eval_modes(modes[f], x, y, z))
+    return Workload("lattice", blocks, nfields, data, offs, [[m] for m in modes])
 
 
 WAVE_K = (3, 5, 7)

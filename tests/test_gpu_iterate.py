@@ -1,0 +1,143 @@
+"""GPU parity of the hybrid closure iteration (Sec. ssec:domdec_iter, Eq. iter_center_P) against
+the oracle (oracle/iterate.py), every output node, on periodic lattices of blocks.
+
+Bar: relative max-norm error per (block, operator, field) <= 1e-12 in FP64 and <= 1e-5 in FP32.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import iterate as IT
+from oracle import lines as OL
+from oracle import schemes as OS
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _ops(names, dirs=(0, 1, 2)):
+    return [(n, d) for n in names for d in dirs]
+
+
+def _iter_ref(wl, ops, lat, iters, ooffs, nout):
+    """The oracle's iterate [iters] in the plan's output layout."""
+    ref = np.full(nout, np.nan)
+    nb = len(wl.blocks)
+    n = wl.blocks[0].n
+    npts = int(np.prod(n))
+    keys = [(b % lat[0], (b // lat[0]) % lat[1], b // (lat[0] * lat[1])) for b in range(nb)]
+    for o, (name, d) in enumerate(ops):
+        s = OS.named(name)
+        for f in range(wl.nfields):
+            fields = {keys[b]: wl.field_view(b, f) for b in range(nb)}
+            res = IT.iterate_lattice(s, fields, lat, wl.blocks[0].ng, wl.blocks[0].h[d], d, iters)
+            for b in range(nb):
+                off = ooffs[b] + (o * wl.nfields + f) * npts
+                ref[off:off + npts] = res[keys[b]].ravel()
+    return ref
+
+
+def _run(plan, wl, dtype, graph=False):
+    import torch
+    tdt = torch.float64 if dtype == 0 else torch.float32
+    _, nout = plan.sizes()
+    x = torch.from_numpy(wl.data).to(device="cuda", dtype=tdt)
+    y = torch.full((nout,), float("nan"), dtype=tdt, device="cuda")
+    if graph:
+        plan.capture_graph(x, y)
+        plan.launch_graph()
+    else:
+        plan.apply(x, y)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("names", [("(1)Q1_3[1]", "(2)Q1_3[1]"), ("(1)P1_2",), ("(2)Q1_3[1]",)])
+def test_iterates_match_oracle(cuda, names, dtype):
+    lat = (3, 2, 2)
+    wl = synth.lattice(n=(16, 12, 20), lat=lat, ng=4, nfields=2, seed=8)
+    ops = _ops(names)
+    plan = H.make_plan(wl, ops, dtype=dtype)
+    _, ooffs = plan.offsets()
+    _, nout = plan.sizes()
+    for iters in (1, 2, 5):
+        plan.set_iteration(iters, *lat)
+        got = _run(plan, wl, dtype)
+        ref = _iter_ref(wl, ops, lat, iters, ooffs, nout)
+        err = H.compare_flat(got, ref, wl, ops, ooffs)
+        print(f"iterate {iters} {names} dtype {dtype}: {err:.3e}", flush=True)
+        assert err <= H.tol_for(dtype), (iters, err)
+    # back to the plain block closure
+    plan.set_iteration(0)
+    got = _run(plan, wl, dtype)
+    assert H.compare_flat(got, H.oracle_flat(wl, ops, ooffs, nout), wl, ops, ooffs) <= H.tol_for(dtype)
+
+
+def test_iterates_converge_to_global_periodic_operator(cuda):
+    """Many iterations give the global periodic operator on the box the lattice tiles."""
+    lat = (2, 2, 3)
+    n = (16, 16, 12)
+    wl = synth.lattice(n=n, lat=lat, ng=4, nfields=1, seed=9)
+    ops = _ops(["(1)Q1_3[1]"])
+    plan = H.make_plan(wl, ops)
+    plan.set_iteration(40, *lat)
+    got = _run(plan, wl, 0, graph=True)
+    _, ooffs = plan.offsets()
+    NG = [n[d] * lat[d] for d in range(3)]
+    s = OS.named("(1)Q1_3[1]")
+    hh = wl.blocks[0].h
+    glob = synth.Block(tuple(NG), 0, hh, (synth.PERIODIC,) * 3, tuple(0.5 * v for v in hh))
+    data, offs = synth._fill([glob], 1, lambda b, f, x, y, z: synth.eval_modes(wl.modes[0][0], x, y, z))
+    gw = synth.Workload("global", [glob], 1, data, offs)
+    worst = 0.0
+    npts = int(np.prod(n))
+    for d in range(3):
+        gref = OL.apply_block(s, gw.field_view(0, 0), 0, wl.blocks[0].h[d], d, periodic=True)
+        for b, blk in enumerate(wl.blocks):
+            kx, ky, kz = b % lat[0], (b // lat[0]) % lat[1], b // (lat[0] * lat[1])
+            sub = gref[kz * n[2]:(kz + 1) * n[2], ky * n[1]:(ky + 1) * n[1], kx * n[0]:(kx + 1) * n[0]]
+            off = ooffs[b] + d * npts
+            worst = max(worst, H.rel_err(got[off:off + npts].reshape(n[2], n[1], n[0]), sub))
+    assert worst <= 1e-12, worst
+
+
+def test_iteration_graph_replays_equal_eager(cuda):
+    import torch
+    lat = (2, 2, 2)
+    wl = synth.lattice(n=(16, 16, 16), lat=lat, ng=4, nfields=2, seed=10)
+    ops = _ops(["(1)Q1_3[1]", "(2)Q1_3[1]"])
+    plan = H.make_plan(wl, ops)
+    plan.set_iteration(3, *lat)
+    _, nout = plan.sizes()
+    x = torch.from_numpy(wl.data).cuda()
+    y0 = torch.empty(nout, dtype=torch.float64, device="cuda")
+    plan.apply(x, y0)
+    y = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.capture_graph(x, y)
+    for rep in range(3):
+        y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.launch_graph()
+        torch.cuda.synchronize()
+        assert torch.equal(y, y0), rep
+        x.mul_(1.0)
+
+
+def test_iteration_rejects_what_it_cannot_do(cuda):
+    import paper_2302_14858_amd as P
+    lat = (2, 2, 2)
+    wl = synth.lattice(n=(16, 16, 16), lat=lat, ng=5, nfields=1, seed=11)
+    plan = H.make_plan(wl, _ops(["(1)QP_O8[1]"]))
+    with pytest.raises(P.CfdError) as e:
+        plan.set_iteration(2, *lat)
+    assert e.value.status == P._lib.CFD_EUNSUPPORTED
+    plan = H.make_plan(wl, _ops(["(1)Q1_3[1]"]))
+    with pytest.raises(P.CfdError) as e:
+        plan.set_iteration(2, 2, 2, 1)
+    assert e.value.status == P._lib.CFD_EINVAL
+    wl3 = synth.lattice(n=(16, 16, 16), lat=lat, ng=3, nfields=1, seed=11)
+    plan = H.make_plan(wl3, _ops(["(1)Q1_3[1]:E"]))
+    with pytest.raises(P.CfdError) as e:
+        plan.set_iteration(2, *lat)
+    assert e.value.status == P._lib.CFD_EGHOST
