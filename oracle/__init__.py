@@ -11,6 +11,10 @@ product library never does, and the two share no code.
   banded elimination, cyclic (periodic) solve; plain C behind ctypes.
 * ``oracle.wave``     - the first-order wave system under classical RK4: the
   closed-form evolution of one Fourier mode and a plain stepped integrator.
+* ``oracle.iterate``  - hybrid iteration of the block closures.
+* ``oracle.biased``   - biased (upwind) schemes U, V, X with their xi-closures,
+  their line operator (dense solve) and the upwind selection by a velocity
+  field.
 
 The dense assembled matrices of Eqs. diff_mat_subL/R and the embedded
 operator of Eq. iter_scheme that pin ``oracle.lines`` are written out in the
