@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define CFD_ABI_VERSION 1
+#define CFD_ABI_VERSION 2
 
 typedef enum {
     CFD_OK = 0,
@@ -92,8 +92,57 @@ const char *cfd_last_error(void);
  *                      e.g. "(1)E3".
  * A suffix ":E" replaces a matched closure by the order-only explicit closure
  * of half-width p (formal order 2p), e.g. "(1)Q1_3[1]:E".
+ * Biased first-degree schemes (Sec. ssec:domdec_drp), see
+ * cfd_scheme_design_biased:
+ *   "(1)VM-", "(1)VM+" M = 1..4: V_M of Tab. ucd_fast, left / right biased,
+ *                      with the xi-closure of Tab. ucd_fast_closure.
+ *   "(1)XM-", "(1)XM+" M = 1..3: X_M of Tab. ccux_deg_one_col with its closure.
+ *   "(1)VM", "(1)XM"   both biases as an upwind pair: an operator with this
+ *                      scheme reads a velocity field c (cfd_op.vel_field) and
+ *                      returns c d f, left-biased where c > 0 and right-biased
+ *                      where c < 0 (Eq. biasderapproxadv).
  * out: receives a library-owned handle.  CFD_EINVAL on an unknown name. */
 cfd_status cfd_scheme_named(const char *name, cfd_scheme **out);
+
+/* Design a biased first-degree scheme of Sec. ssec:domdec_drp on the host in
+ * binary128.  family 'V': V_M (M = 1..4), Eq. defChenSchemes with
+ * alpha^(2)_0 = 0, formal order 2M+1, fixed by Taylor matching (Eq. Tcons).
+ * family 'X': X_M (M = 1..3), the combination lambda U_M + (1 - lambda)
+ * V_{M+1} of Eq. LCslowfast with the f'' sample of U_M replaced by the
+ * explicit (2)E_{M+2}, formal order 2M+2; lambda <= 0 takes the value printed
+ * with the scheme (Tab. ccux_deg_one_col).  The closure at the block end the
+ * bias points away from is the mirror-image scheme plus xi dx^q alpha^(1) .
+ * f^(q) over its two implicit nodes, f^(q) from the centred binomial
+ * difference (q)E_{q/2} (Tab. diss_scheme), q the first even order above the
+ * formal order, xi matching the lowest imaginary term of the interior
+ * scheme's wavenumber error (Eqs. ucd_slow_closure_chi, ucd_fast_closure_chi).
+ * bias: -1 left-biased (closure row at k*_-, Eq. closure_left_X), +1 right-
+ * biased (its mirror image), 0 upwind pair (see cfd_scheme_named).
+ * Ghost layers needed: the reach of both biases' rows (M + 2 for X_M, M + 1
+ * for V_M).  CFD_EUNSUPPORTED outside the ranges above (stencil half-widths
+ * above 5), CFD_EINVAL on a bad family or bias. */
+cfd_status cfd_scheme_design_biased(char family, int M, double lambda, int bias, cfd_scheme **out);
+
+/* Read back a biased scheme: bias (-1, +1, 0), its formal order, alpha =
+ * alpha^(1)_{-1} of the left-biased interior row alpha x_{k-1} + x_k =
+ * sum_m a_m f_{k+m}, a[11] = a_{-5..5}, and the left closure row
+ * x_0 + alpha x_1 = sum_m c_m f_m, c[12] = c_{-5..6}.  Any pointer may be
+ * NULL.  CFD_EINVAL for a centred scheme. */
+cfd_status cfd_scheme_get_biased(const cfd_scheme *s, int *bias, int *order, double *alpha, double *a11,
+                                 double *c12);
+
+/* Fully determined scheme of the multi-derivative ansatz (Eq. mdAnsatz):
+ * derivative of degree dr on offsets -L..R (alpha^(dr)_0 = 1) against
+ * nclass sample classes, class c of derivative degree dI[c] on offsets
+ * -Lk[c]..Rk[c] (e.g. dI = (0, 2) for the Hermite-type schemes, or a biased
+ * extent L != R).  As many Taylor conditions (Eq. Tcons) as unknowns are
+ * imposed, solved in binary128.  coef receives the L+R+1 left coefficients,
+ * then each class's Lk+Rk+1 coefficients, in offset order; cap is its length
+ * in doubles (CFD_EINVAL if too small).  order receives the formal order
+ * (first violated Taylor condition minus dr).  nclass 1..4, every extent
+ * <= 16 nodes.  CFD_ESINGULAR if the conditions are singular. */
+cfd_status cfd_taylor_scheme(int dr, int L, int R, int nclass, const int *dI, const int *Lk, const int *Rk,
+                             double *coef, int cap, int *order);
 
 /* Design a centred scheme: derivative degree d (1|2), formal order `order`
  * (even), implicit half-width nl (0..2), RHS half-width m (1..5).  When the
@@ -161,11 +210,15 @@ typedef struct {
 } cfd_block;
 
 /* One derivative operator: a scheme applied along direction dir (0=x,1=y,2=z)
- * to every field (field = -1) or to one field index. */
+ * to every field (field = -1) or to one field index.  vel_field: for an
+ * upwind pair of biased schemes (e.g. "(1)X2"), the field holding the
+ * velocity c; the operator returns c d f with the bias chosen per node by the
+ * sign of c (Eq. biasderapproxadv); -1 for every other scheme. */
 typedef struct {
     const cfd_scheme *scheme;
     int dir;
     int field;
+    int vel_field;
 } cfd_op;
 
 typedef struct {

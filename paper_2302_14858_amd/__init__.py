@@ -14,12 +14,32 @@ from . import _lib
 from ._lib import (CFD_BOUNDARY_CLOSURE, CFD_BOUNDARY_PERIODIC, CFD_F32, CFD_F64, CFD_MIXED_BF16, CfdError,
                    check, lib)
 
-__all__ = ["Scheme", "Plan", "cfd_abi_version", "cfd_axpby", "cfd_xpcy", "CfdError", "CFD_F64", "CFD_F32",
+__all__ = ["Scheme", "Plan", "cfd_abi_version", "cfd_taylor_scheme", "cfd_axpby", "cfd_xpcy", "CfdError", "CFD_F64", "CFD_F32",
            "CFD_MIXED_BF16", "CFD_BOUNDARY_CLOSURE", "CFD_BOUNDARY_PERIODIC"]
 
 
 def cfd_abi_version() -> int:
     return lib().cfd_abi_version()
+
+
+def cfd_taylor_scheme(dr: int, L: int, R: int, classes: Sequence) -> Dict:
+    """Fully determined multi-derivative scheme: classes is a list of (d_I, L_k, R_k)."""
+    n = len(classes)
+    dI = (ctypes.c_int * n)(*[c[0] for c in classes])
+    Lk = (ctypes.c_int * n)(*[c[1] for c in classes])
+    Rk = (ctypes.c_int * n)(*[c[2] for c in classes])
+    cap = (L + R + 1) + sum(c[1] + c[2] + 1 for c in classes)
+    coef = (ctypes.c_double * cap)()
+    order = ctypes.c_int()
+    check(lib().cfd_taylor_scheme(dr, L, R, n, dI, Lk, Rk, coef, cap, ctypes.byref(order)))
+    vals = list(coef)
+    out = {"order": order.value, "lhs": vals[:L + R + 1], "rhs": []}
+    pos = L + R + 1
+    for c in classes:
+        w = c[1] + c[2] + 1
+        out["rhs"].append(vals[pos:pos + w])
+        pos += w
+    return out
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -91,6 +111,24 @@ class Scheme:
 
     get = cfd_scheme_get
 
+    @classmethod
+    def cfd_scheme_design_biased(cls, family: str, M: int, lam: float = 0.0, bias: int = -1) -> "Scheme":
+        out = ctypes.c_void_p()
+        check(lib().cfd_scheme_design_biased(family.encode(), M, float(lam), int(bias), ctypes.byref(out)))
+        return cls(out.value)
+
+    design_biased = cfd_scheme_design_biased
+
+    def cfd_scheme_get_biased(self) -> Dict:
+        bias, order, alpha = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        a = (ctypes.c_double * 11)()
+        c = (ctypes.c_double * 12)()
+        check(lib().cfd_scheme_get_biased(self._h, ctypes.byref(bias), ctypes.byref(order), ctypes.byref(alpha),
+                                          a, c))
+        return {"bias": bias.value, "order": order.value, "alpha": alpha.value, "a": list(a), "c": list(c)}
+
+    get_biased = cfd_scheme_get_biased
+
     def cfd_scheme_required_ghosts(self, boundary: int = CFD_BOUNDARY_CLOSURE) -> int:
         ng = ctypes.c_int()
         check(lib().cfd_scheme_required_ghosts(self._h, boundary, ctypes.byref(ng)))
@@ -112,7 +150,8 @@ class Plan:
 
     blocks: list of dicts with keys n (3 ints), ng, h (3 floats), boundary (3 ints),
             optional in_offset / out_offset (elements; default packed).
-    ops:    list of (Scheme, dir) or (Scheme, dir, field).
+    ops:    list of (Scheme, dir), (Scheme, dir, field) or (Scheme, dir, field, vel_field);
+            vel_field (the velocity of an upwind pair) defaults to -1.
     """
 
     def __init__(self, blocks: List[Dict], nfields: int, ops: Sequence, dtype: int = CFD_F64, device: int = 0):
@@ -131,6 +170,7 @@ class Plan:
             oarr[i].scheme = op[0]._h
             oarr[i].dir = int(op[1])
             oarr[i].field = int(op[2]) if len(op) > 2 else -1
+            oarr[i].vel_field = int(op[3]) if len(op) > 3 else -1
         desc = _lib.cfd_plan_desc(nb, arr, int(nfields), len(ops), oarr, int(dtype), int(device), 0)
         out = ctypes.c_void_p()
         check(lib().cfd_plan_create(ctypes.byref(desc), ctypes.byref(out)))

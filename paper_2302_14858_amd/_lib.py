@@ -21,7 +21,8 @@ class cfd_block(ctypes.Structure):
 
 
 class cfd_op(ctypes.Structure):
-    _fields_ = [("scheme", ctypes.c_void_p), ("dir", ctypes.c_int), ("field", ctypes.c_int)]
+    _fields_ = [("scheme", ctypes.c_void_p), ("dir", ctypes.c_int), ("field", ctypes.c_int),
+                ("vel_field", ctypes.c_int)]
 
 
 class cfd_plan_desc(ctypes.Structure):
@@ -44,6 +45,9 @@ SIGNATURES = {
     "cfd_scheme_design": (_i, [_i, _i, _i, _i, _d, _i, _i, _pp]),
     "cfd_scheme_create": (_i, [_i, _i, _i, _dp, _i, _dp, _i, _i, _dp, _pp]),
     "cfd_scheme_get": (_i, [_vp, _ip, _ip, _ip, _ip, _ip, _ip, _dp, _dp, _dp]),
+    "cfd_scheme_design_biased": (_i, [ctypes.c_char, _i, _d, _i, _pp]),
+    "cfd_scheme_get_biased": (_i, [_vp, _ip, _ip, _dp, _dp, _dp]),
+    "cfd_taylor_scheme": (_i, [_i, _i, _i, _i, _ip, _ip, _ip, _dp, _i, _ip]),
     "cfd_scheme_required_ghosts": (_i, [_vp, _i, _ip]),
     "cfd_scheme_destroy": (None, [_vp]),
     "cfd_plan_create": (_i, [ctypes.POINTER(cfd_plan_desc), _pp]),

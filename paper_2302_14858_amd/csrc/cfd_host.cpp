@@ -134,6 +134,15 @@ struct cfd_plan {
     // device state rebuilt by build()
     DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff, d_qoff, d_outoff, d_shapes;
     DevBuf d_dense, d_dense_specs;        // dense mixed-precision tables
+    // biased (upwind) operators: one pass per (block, op), work items grouped
+    // by stencil half-width class, coefficient records per op
+    struct BGroup {
+        int hb = 0;
+        int64_t item0 = 0, nitems = 0;
+    };
+    std::vector<BGroup> bgroups;
+    int64_t nbitems = 0;
+    DevBuf d_bpass, d_bitems, d_bcoef;
     std::vector<Group> groups;
     int64_t nitems = 0;
     hipStream_t cap_stream = nullptr;
@@ -172,6 +181,9 @@ struct cfd_plan {
         d_shapes.release();
         d_dense.release();
         d_dense_specs.release();
+        d_bpass.release();
+        d_bitems.release();
+        d_bcoef.release();
         release_iteration();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
@@ -515,6 +527,11 @@ cfd_status build_iteration(cfd_plan *p, std::vector<PassDesc> &pd, const std::ve
 cfd_status build_groups(cfd_plan *p) {
     HIPCHK(hipSetDevice(p->device));
     p->drop_graph();
+    if (p->passes.empty()) {   // only biased operators
+        p->groups.clear();
+        p->nitems = 0;
+        return CFD_OK;
+    }
     if (p->dtype == CFD_MIXED_BF16) return build_dense(p);
     const bool f32 = p->dtype != CFD_F64;
     // 1. schedule and kernel class of every pass
@@ -865,6 +882,115 @@ cfd_status build_dense(cfd_plan *p) {
     return CFD_OK;
 }
 
+// Biased (upwind) operators: one BiasPass per (block, operator) over the
+// fields the operator selects, work items of 64 lines per (pass, field),
+// grouped by stencil half-width class; coefficient records in the plan's
+// element type.  Independent of the schedule, built once at plan creation.
+cfd_status build_biased(cfd_plan *p) {
+    const bool f32 = p->dtype != CFD_F64;
+    std::vector<int> bops;
+    for (size_t o = 0; o < p->ops.size(); ++o)
+        if (p->schemes[o].kind == 1) bops.push_back((int)o);
+    p->bgroups.clear();
+    p->nbitems = 0;
+    if (bops.empty()) return CFD_OK;
+    std::vector<double> rec64(bops.size() * kBiasRec, 0.0);
+    for (size_t i = 0; i < bops.size(); ++i) {
+        const Scheme &s = p->schemes[bops[i]];
+        double *r = rec64.data() + i * kBiasRec;
+        r[0] = s.balpha;
+        for (int m = 0; m < 2 * kBiasHalf + 1; ++m) r[1 + m] = s.ba[m];
+        for (int m = 0; m < 2 * kBiasHalf + 2; ++m) r[12 + m] = s.bc[m];
+        r[24] = 1.0 / (1.0 - s.balpha * s.balpha);
+    }
+    std::vector<BiasPass> bp;
+    std::map<int, std::vector<BiasItem>> by_hb;
+    for (size_t b = 0; b < p->blocks.size(); ++b) {
+        const cfd_block &bl = p->blocks[b];
+        const int64_t npts = (int64_t)bl.n[0] * bl.n[1] * bl.n[2];
+        for (size_t i = 0; i < bops.size(); ++i) {
+            const int o = bops[i];
+            const Scheme &s = p->schemes[o];
+            const cfd_op &op = p->ops[o];
+            PassHost ph;
+            ph.dir = op.dir;
+            ph.N = bl.n[op.dir];
+            ph.periodic = bl.boundary[op.dir] == CFD_BOUNDARY_PERIODIC;
+            PassDesc d;
+            const int64_t ob[2] = {p->out_off[b] + p->op_slot[o] * npts, 0};
+            const int tab[2] = {0, 0};
+            const double hi[2] = {0, 0};
+            fill_pass_desc(d, bl, p->in_off[b], ph, ob, tab, hi);
+            BiasPass q;
+            std::memset(&q, 0, sizeof q);
+            q.in_base = d.in_base;
+            q.in_fstride = d.in_fstride;
+            q.vel_base = (s.bias == 0) ? d.in_base + (int64_t)op.vel_field * d.in_fstride : 0;
+            // items carry the input field index; a one-field operator's output
+            // slot holds that field at index 0
+            q.out_fstride = d.out_fstride;
+            q.out_base = d.out_base[0] - (op.field < 0 ? 0 : (int64_t)op.field * d.out_fstride);
+            q.su = d.su;
+            q.sv = d.sv;
+            q.sd = d.sd;
+            q.osu = d.osu;
+            q.osv = d.osv;
+            q.osd = d.osd;
+            q.nu = d.nu;
+            q.nlines = d.nlines;
+            q.N = d.N;
+            q.ng = bl.ng;
+            q.periodic = ph.periodic;
+            q.mode = s.bias;
+            q.tab = (int)i;
+            q.hb = s.bhalf < 2 ? 2 : s.bhalf;
+            q.hinv = 1.0 / bl.h[op.dir];
+            q.wrap = 1.0 / (1.0 - std::pow(-s.balpha, (double)d.N));
+            if (!biased_supported(q.hb)) return fail(CFD_EUNSUPPORTED, "biased stencil half-width not compiled");
+            const int pi = (int)bp.size();
+            bp.push_back(q);
+            const int f0 = op.field < 0 ? 0 : op.field;
+            const int nf = op.field < 0 ? p->nfields : 1;
+            for (int f = 0; f < nf; ++f)
+                for (int l0 = 0; l0 < q.nlines; l0 += kWave)
+                    by_hb[q.hb].push_back(BiasItem{pi, f0 + f, l0, 0});
+        }
+    }
+    std::vector<BiasItem> items;
+    for (auto &kv : by_hb) {
+        cfd_plan::BGroup g;
+        g.hb = kv.first;
+        g.item0 = (int64_t)items.size();
+        g.nitems = (int64_t)kv.second.size();
+        items.insert(items.end(), kv.second.begin(), kv.second.end());
+        p->bgroups.push_back(g);
+    }
+    p->nbitems = (int64_t)items.size();
+    if (p->nbitems > INT32_MAX) return fail(CFD_EUNSUPPORTED, "too many biased work items");
+    HIPCHK(dmalloc((void **)&p->d_bpass.p, bp.size() * sizeof(BiasPass)));
+    HIPCHK(hipMemcpy(p->d_bpass.p, bp.data(), bp.size() * sizeof(BiasPass), hipMemcpyHostToDevice));
+    HIPCHK(dmalloc((void **)&p->d_bitems.p, items.size() * sizeof(BiasItem)));
+    HIPCHK(hipMemcpy(p->d_bitems.p, items.data(), items.size() * sizeof(BiasItem), hipMemcpyHostToDevice));
+    if (f32) {
+        std::vector<float> rec32(rec64.begin(), rec64.end());
+        HIPCHK(dmalloc((void **)&p->d_bcoef.p, rec32.size() * sizeof(float)));
+        HIPCHK(hipMemcpy(p->d_bcoef.p, rec32.data(), rec32.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+        HIPCHK(dmalloc((void **)&p->d_bcoef.p, rec64.size() * sizeof(double)));
+        HIPCHK(hipMemcpy(p->d_bcoef.p, rec64.data(), rec64.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return CFD_OK;
+}
+
+cfd_status launch_biased_groups(cfd_plan *p, const void *in, void *out, hipStream_t st) {
+    for (const cfd_plan::BGroup &g : p->bgroups) {
+        hipError_t e = launch_biased(p->dtype != CFD_F64, g.hb, (const BiasItem *)p->d_bitems.p + g.item0,
+                                     (int)g.nitems, (const BiasPass *)p->d_bpass.p, p->d_bcoef.p, in, out, st);
+        if (e != hipSuccess) return hip_fail(e, "launching the biased-line kernel");
+    }
+    return CFD_OK;
+}
+
 cfd_status launch_group(cfd_plan *p, const Group &g, const void *in, void *out, hipStream_t st) {
     const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
     hipError_t e;
@@ -958,6 +1084,10 @@ cfd_status enqueue_iteration(cfd_plan *p, const void *in, hipStream_t st) {
 cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
     if (p->iter_n > 0 && p->n_iops > 0) {
         cfd_status r = enqueue_iteration(p, in, st);
+        if (r != CFD_OK) return r;
+    }
+    if (p->nbitems > 0) {
+        cfd_status r = launch_biased_groups(p, in, out, st);
         if (r != CFD_OK) return r;
     }
     std::vector<const Group *> act;
@@ -1117,6 +1247,43 @@ cfd_status cfd_scheme_get(const cfd_scheme *sc, int *d, int *order, int *nl, int
     return CFD_OK;
 }
 
+cfd_status cfd_scheme_design_biased(char family, int M, double lambda, int bias, cfd_scheme **out) {
+    if (!out) return fail(CFD_EINVAL, "cfd_scheme_design_biased: null output");
+    std::string err;
+    Scheme s;
+    cfd_status st = design_biased(family, M, lambda, bias, s, err);
+    if (st != CFD_OK) return fail(st, err);
+    *out = new cfd_scheme{s};
+    return CFD_OK;
+}
+
+cfd_status cfd_scheme_get_biased(const cfd_scheme *sc, int *bias, int *order, double *alpha, double *a11,
+                                 double *c12) {
+    if (!sc) return fail(CFD_EINVAL, "cfd_scheme_get_biased: null scheme");
+    const Scheme &s = sc->s;
+    if (s.kind != 1) return fail(CFD_EINVAL, "cfd_scheme_get_biased: '" + s.name + "' is not a biased scheme");
+    if (bias) *bias = s.bias;
+    if (order) *order = s.order;
+    if (alpha) *alpha = s.balpha;
+    if (a11) std::memcpy(a11, s.ba, sizeof s.ba);
+    if (c12) std::memcpy(c12, s.bc, sizeof s.bc);
+    return CFD_OK;
+}
+
+cfd_status cfd_taylor_scheme(int dr, int L, int R, int nclass, const int *dI, const int *Lk, const int *Rk,
+                             double *coef, int cap, int *order) {
+    if (!coef || !order) return fail(CFD_EINVAL, "cfd_taylor_scheme: null output");
+    std::vector<double> c;
+    std::string err;
+    int ord = 0;
+    cfd_status st = taylor_scheme(dr, L, R, nclass, dI, Lk, Rk, c, ord, err);
+    if (st != CFD_OK) return fail(st, err);
+    if ((int)c.size() > cap) return fail(CFD_EINVAL, "cfd_taylor_scheme: coefficient array too small");
+    std::memcpy(coef, c.data(), c.size() * sizeof(double));
+    *order = ord;
+    return CFD_OK;
+}
+
 cfd_status cfd_scheme_required_ghosts(const cfd_scheme *sc, cfd_boundary b, int *ng) {
     if (!sc || !ng) return fail(CFD_EINVAL, "cfd_scheme_required_ghosts: null argument");
     if (b != CFD_BOUNDARY_CLOSURE && b != CFD_BOUNDARY_PERIODIC)
@@ -1145,7 +1312,18 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
         if (op.dir < 0 || op.dir > 2) return fail(CFD_EINVAL, "cfd_plan_create: operator direction not in 0..2");
         if (op.field < -1 || op.field >= desc->nfields)
             return fail(CFD_EINVAL, "cfd_plan_create: operator field out of range");
-        p->schemes.push_back(op.scheme->s);
+        const Scheme &s = op.scheme->s;
+        if (s.kind == 1 && s.bias == 0) {
+            if (op.vel_field < 0 || op.vel_field >= desc->nfields)
+                return fail(CFD_EINVAL, "cfd_plan_create: upwind operator '" + s.name +
+                                            "' needs a velocity field index in 0..nfields-1");
+        } else if (op.vel_field != -1) {
+            return fail(CFD_EINVAL, "cfd_plan_create: vel_field must be -1 for operator '" + s.name +
+                                        "' (only upwind pairs read a velocity field)");
+        }
+        if (s.kind == 1 && desc->dtype == CFD_MIXED_BF16)
+            return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: biased schemes are not supported");
+        p->schemes.push_back(s);
     }
     int64_t slot = 0;
     for (const cfd_op &op : p->ops) {
@@ -1189,6 +1367,10 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
                 return fail(CFD_EGHOST, buf);
             }
             const int N = bl.n[d];
+            if (s.kind == 1) {
+                if (N < 2) return fail(CFD_ESHAPE, "biased operator: lines need at least 2 nodes");
+                continue;
+            }
             if (!per && s.nl > 0 && N < 2 * s.nc + 1) {
                 char buf[160];
                 std::snprintf(buf, sizeof buf, "block %zu: %d nodes along direction %d, closure needs >= %d", b, N,
@@ -1219,7 +1401,7 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
         for (int d = 0; d < 3; ++d) {
             std::vector<int> ops_d;
             for (size_t o = 0; o < p->ops.size(); ++o)
-                if (p->ops[o].dir == d) ops_d.push_back((int)o);
+                if (p->ops[o].dir == d && p->schemes[o].kind == 0) ops_d.push_back((int)o);
             std::vector<bool> used(p->ops.size(), false);
             for (int o : ops_d) {
                 if (used[o]) continue;
@@ -1293,6 +1475,7 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
     }
     p->xcd_interleave_ok = xcd_dispatch_ok(p->device);
     cfd_status st = upload_layout(p.get());
+    if (st == CFD_OK) st = build_biased(p.get());
     if (st == CFD_OK) st = build(p.get());
     if (st != CFD_OK) {
         p->release();
@@ -1735,6 +1918,8 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
     if (iterations < 0) return fail(CFD_EINVAL, "cfd_plan_set_iteration: negative iteration count");
     if (p->dtype == CFD_MIXED_BF16)
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: not available on the dense mixed-precision path");
+    if (iterations > 0 && p->nbitems > 0)
+        return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds biased operators");
     const int c = 2;
     auto restore = [&]() {
         if (!p->base_schemes.empty()) p->schemes = p->base_schemes;

@@ -15,6 +15,7 @@ constexpr int kMaxNL = 2;        // implicit half-width: tri (1) and penta (2)
 constexpr int kMaxHalf = 5;      // RHS / closure stencil half-width
 constexpr int kMaxP = 8;         // partitions per line
 constexpr int kWave = 64;        // CDNA wavefront
+constexpr int kBiasHalf = 5;     // biased schemes: stencil half-width bound
 
 // ---------------------------------------------------------------------------
 // Scheme (host only)
@@ -35,8 +36,30 @@ struct Scheme {
     // from the neighbouring block's previous iterate.
     int ext = 0;
     double cl_d0 = 1.0, cl_up = 0.0, gamma = 0.0;
+    // Biased first-degree schemes (Sec. ssec:domdec_drp): kind 1.  Stored as
+    // the left-biased scheme, alpha x_{k-1} + x_k = sum_m ba_m f_{k+m}
+    // (ba centred at kBiasHalf), and its closure row at k*_-,
+    // x_0 + alpha x_1 = sum_m bc_m f_m (bc on -kBiasHalf .. kBiasHalf+1);
+    // the right-biased scheme is the mirror image.  bias: -1 left-biased,
+    // +1 right-biased, 0 both, combined by the sign of a velocity field.
+    int kind = 0;
+    int bias = -1;
+    int bhalf = 0;                 // largest reach of ba / bc (bc may reach bhalf + 1 to the right)
+    double balpha = 0.0;
+    double ba[2 * kBiasHalf + 1] = {0};
+    double bc[2 * kBiasHalf + 2] = {0};
     std::string name;
 };
+
+// Biased scheme construction (scheme_design.cpp).  family 'V' (M = 1..4) or
+// 'X' (M = 1..3; lambda <= 0 takes the value printed with the scheme).
+cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &out, std::string &err);
+// A fully determined scheme of the multi-derivative ansatz (Eq. mdAnsatz,
+// Eq. Tcons): unknown derivative dr on offsets -L..R (alpha^(dr)_0 = 1),
+// sample classes dI[c] on offsets -Lk[c]..Rk[c].  Coefficients in binary128,
+// returned as doubles: lhs (L+R+1), then each class's (Lk+Rk+1).
+cfd_status taylor_scheme(int dr, int L, int R, int nclass, const int *dI, const int *Lk, const int *Rk,
+                         std::vector<double> &coef, int &order, std::string &err);
 
 // Scheme construction (scheme_design.cpp).  Return CFD_OK or an error code
 // with the message in `err`.
@@ -100,6 +123,29 @@ struct PassDesc {
     double hinv[2];         // h^-d per op
     int64_t ev_base[2];     // iterated closures: element offset of each op's end values
                             // (two per line: left, right; field-major), else unused
+};
+
+// Biased (upwind) operator on the lines of one block along one direction
+// (cfd_biased.hip).  mode: -1 left-biased, +1 right-biased, 0 upwind by the
+// sign of the velocity field at vel_base.  Coefficient record per table
+// (elements of the plan's type): [0] alpha, [1, 12) ba_{-5..5},
+// [12, 24) bc_{-5..6}, [24] 1 / (1 - alpha^2).
+constexpr int kBiasRec = 32;
+struct BiasPass {
+    int64_t in_base;        // input offset of field 0, interior node (0,0,0)
+    int64_t in_fstride;     // input elements per field
+    int64_t vel_base;       // upwind: input offset of the velocity field at interior (0,0,0)
+    int64_t out_base;       // output offset of the operator's first field
+    int64_t out_fstride;    // output elements per field
+    int32_t su, sv, sd;     // input strides (u, v, along the line)
+    int32_t osu, osv, osd;  // output strides
+    int32_t nu, nlines, N, ng;
+    int32_t periodic, mode, tab, hb;
+    double hinv;            // 1 / h
+    double wrap;            // periodic: 1 / (1 - (-alpha)^N)
+};
+struct BiasItem {
+    int32_t pass, field, line0, pad;
 };
 
 // One work item: 64 * (4 / P) lines of one field of one pass.
@@ -183,6 +229,13 @@ hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *sta
                              const void *d, const int64_t *in_off, const int64_t *out_off, const int *shapes,
                              const int *unitpre, int nblocks, int nunits, double a, double b, int bx, int by, int bz,
                              hipStream_t st);   // bx = 0: no ghost refresh
+}  // namespace cfd
+
+namespace cfd {
+// biased (upwind) lines (cfd_biased.hip); hb: stencil half-width class 2..5
+bool biased_supported(int hb);
+hipError_t launch_biased(int f32, int hb, const BiasItem *items, int nitems, const BiasPass *passes,
+                         const void *coefs, const void *in, void *out, hipStream_t st);
 }  // namespace cfd
 
 namespace cfd {

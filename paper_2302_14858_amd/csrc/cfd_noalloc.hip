@@ -105,6 +105,8 @@ extern "C" cfd_status cfd_apply_block_noalloc(const cfd_scheme *sc, const cfd_bl
                                               void *stream) {
     if (!sc || !blk || !in_dev || !out_dev) return nfail(CFD_EINVAL, "cfd_apply_block_noalloc: null argument");
     if (dir < 0 || dir > 2) return nfail(CFD_EINVAL, "cfd_apply_block_noalloc: direction not in 0..2");
+    if (sc->s.kind != 0)
+        return nfail(CFD_EUNSUPPORTED, "cfd_apply_block_noalloc: biased schemes need a plan (cfd_plan_create)");
     if (nfields < 1 || field < -1 || field >= nfields)
         return nfail(CFD_EINVAL, "cfd_apply_block_noalloc: bad field count or field index");
     if (dtype != CFD_F64 && dtype != CFD_F32)

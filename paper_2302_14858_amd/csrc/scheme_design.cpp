@@ -17,6 +17,7 @@
 // The spectral error of such a scheme is a real function of eta, and the
 // constrained quadratic minimisation is solved in the null space of the Taylor
 // conditions with Gauss-Legendre quadrature on [0, eta_c].
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -386,6 +387,260 @@ cfd_status design_centred(int d, int order, int nl, int m, double eta_c, int clo
     return CFD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Fully determined schemes of the multi-derivative ansatz (Eq. mdAnsatz with
+// any sample classes d_I, Eq. Tcons), e.g. the biased schemes of Eq.
+// defChenSchemes or the worked example of Sec. 2.  Unknowns: alpha^(dr) on
+// -L..R with alpha^(dr)_0 = 1, then each class on -Lk..Rk.  Taylor row l:
+//   sum_c sum_n a^(dc)_n n^(l-dc)/(l-dc)!  -  sum_n alpha^(dr)_n n^(l-dr)/(l-dr)!  = 0.
+// As many rows as unknowns (after the normalisation) are imposed; the order is
+// the first violated row minus dr.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Ansatz {
+    int dr, L, R;
+    std::vector<int> dI, Lk, Rk;
+    int nunk() const {
+        int n = L + R + 1;
+        for (size_t c = 0; c < dI.size(); ++c) n += Lk[c] + Rk[c] + 1;
+        return n;
+    }
+};
+
+void ansatz_row(const Ansatz &a, int l, std::vector<q> &row) {
+    row.assign(a.nunk(), 0);
+    int col = 0;
+    for (int n = -a.L; n <= a.R; ++n, ++col)
+        if (l >= a.dr) row[col] = -qpow_int(n, l - a.dr) / qfact(l - a.dr);   // 0^0 = 1
+    for (size_t c = 0; c < a.dI.size(); ++c)
+        for (int n = -a.Lk[c]; n <= a.Rk[c]; ++n, ++col)
+            if (l >= a.dI[c]) row[col] = qpow_int(n, l - a.dI[c]) / qfact(l - a.dI[c]);
+}
+
+bool ansatz_solve(const Ansatz &a, std::vector<q> &x, int &order) {
+    const int n = a.nunk();
+    std::vector<q> A((size_t)n * n, 0), b(n, 0);
+    A[a.L] = 1;   // alpha^(dr)_0 = 1
+    b[0] = 1;
+    for (int l = 0; l < n - 1; ++l) {
+        std::vector<q> row;
+        ansatz_row(a, l, row);
+        for (int k = 0; k < n; ++k) A[(size_t)(l + 1) * n + k] = row[k];
+    }
+    if (!qsolve(n, A, b)) return false;
+    x = b;
+    int l = n - 1;
+    for (;; ++l) {
+        std::vector<q> row;
+        ansatz_row(a, l, row);
+        q r = 0, sc = 0;
+        for (int k = 0; k < n; ++k) {
+            r += row[k] * x[k];
+            sc += qabs(row[k] * x[k]);
+        }
+        if (qabs(r) > (q)1e-28Q * (sc + 1)) break;
+        if (l > 64) break;
+    }
+    order = l - a.dr;
+    return true;
+}
+
+// One biased first-degree scheme in working precision: alpha x_{k-1} + x_k =
+// sum_m a_m f_{k+m} (+ a2 dx^2 f''_k for U).
+struct BiasedQ {
+    q alpha = 0, a2 = 0;
+    q a[2 * 8 + 1] = {0};     // offsets -8..8
+    int order = 0;
+    q at(int m) const { return (m < -8 || m > 8) ? (q)0 : a[m + 8]; }
+};
+
+bool ucd_scheme(char kind, int M, BiasedQ &s) {
+    Ansatz an{1, 1, 0, {0}, {M}, {M}};
+    if (kind == 'U') {
+        an.dI.push_back(2);
+        an.Lk.push_back(0);
+        an.Rk.push_back(0);
+    }
+    std::vector<q> x;
+    if (!ansatz_solve(an, x, s.order)) return false;
+    s.alpha = x[0];
+    for (int m = -M; m <= M; ++m) s.a[m + 8] = x[2 + m + M];
+    s.a2 = (kind == 'U') ? x[2 + 2 * M + 1] : (q)0;
+    return true;
+}
+
+// Taylor residual of row l of a biased scheme (no f'' term):
+//   T_l = sum_m a_m m^l / l!  -  sum_j alpha_j j^(l-1)/(l-1)!.
+q biased_residual(const BiasedQ &s, int l) {
+    q t = 0;
+    for (int m = -8; m <= 8; ++m)
+        if (s.at(m) != 0) t += s.at(m) * qpow_int(m, l) / qfact(l);
+    if (l >= 1) {
+        t -= qpow_int(0, l - 1) / qfact(l - 1);                  // alpha_0 = 1
+        t -= s.alpha * qpow_int(-1, l - 1) / qfact(l - 1);       // alpha_{-1}
+    }
+    return t;
+}
+
+}  // namespace
+
+cfd_status taylor_scheme(int dr, int L, int R, int nclass, const int *dI, const int *Lk, const int *Rk,
+                         std::vector<double> &coef, int &order, std::string &err) {
+    if (dr < 0 || L < 0 || R < 0 || L + R > 16 || nclass < 1 || nclass > 4 || !dI || !Lk || !Rk) {
+        err = "Taylor scheme: bad extents";
+        return CFD_EINVAL;
+    }
+    Ansatz an{dr, L, R, {}, {}, {}};
+    for (int c = 0; c < nclass; ++c) {
+        if (dI[c] < 0 || Lk[c] < 0 || Rk[c] < 0 || Lk[c] + Rk[c] > 16) {
+            err = "Taylor scheme: bad sample class";
+            return CFD_EINVAL;
+        }
+        an.dI.push_back(dI[c]);
+        an.Lk.push_back(Lk[c]);
+        an.Rk.push_back(Rk[c]);
+    }
+    std::vector<q> x;
+    if (!ansatz_solve(an, x, order)) {
+        err = "Taylor scheme: the conditions are singular for these extents";
+        return CFD_ESINGULAR;
+    }
+    coef.assign(x.size(), 0.0);
+    for (size_t i = 0; i < x.size(); ++i) coef[i] = (double)x[i];
+    return CFD_OK;
+}
+
+// Biased schemes of Sec. ssec:domdec_drp.
+//  V_M (family 'V'): Eq. defChenSchemes with alpha^(2)_0 = 0, order 2M+1.
+//  X_M (family 'X'): lambda U_M + (1 - lambda) V_{M+1} (Eq. LCslowfast) with
+//    the f'' sample of U_M replaced by the explicit (2)E_{M+2}; order 2M+2.
+// Closure at k*_-: the mirror image of the scheme plus xi dx^q (alpha^(1) .
+// f^(q)) over its two implicit nodes, f^(q) from the centred (q)E_{q/2}
+// (binomial differences, Tab. diss_scheme), q the first even order above the
+// formal order.  xi matches the lowest imaginary term of the interior
+// wavenumber error (Eqs. ucd_slow_closure_chi, ucd_fast_closure_chi).  With
+// z = i eta, B(z)/A(z) = z + S(z) where S = T/A is the quotient of the
+// Taylor-residual series T(z) = sum_l T_l z^l by A(z) = sum_k z^k sum_j
+// alpha_j j^k/k!; then Im eta~ = -(-1)^(q/2) s_q eta^q + ..., the mirror
+// flips its sign and the correction adds -xi (2 cos eta - 2)^(q/2), so
+// xi = 2 s_q.
+cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &out, std::string &err) {
+    if (bias < -1 || bias > 1) {
+        err = "biased scheme: bias must be -1, +1 or 0";
+        return CFD_EINVAL;
+    }
+    BiasedQ s;
+    if (family == 'V') {
+        if (M < 1 || M > 4) {
+            err = "biased scheme: V_M needs 1 <= M <= 4";
+            return CFD_EUNSUPPORTED;
+        }
+        if (!ucd_scheme('V', M, s)) {
+            err = "biased scheme: singular Taylor system";
+            return CFD_ESINGULAR;
+        }
+    } else if (family == 'X') {
+        if (M < 1 || M > 3) {
+            err = "biased scheme: X_M needs 1 <= M <= 3";
+            return CFD_EUNSUPPORTED;
+        }
+        // sigma printed with the X_M schemes (Tab. ccux_deg_one_col)
+        static const q kLam[4] = {0, (q)37 / 100, (q)86 / 100, (q)146 / 100};
+        const q lam = (lambda > 0) ? (q)lambda : kLam[M];
+        BiasedQ u, v;
+        if (!ucd_scheme('U', M, u) || !ucd_scheme('V', M + 1, v)) {
+            err = "biased scheme: singular Taylor system";
+            return CFD_ESINGULAR;
+        }
+        // (2)E_{M+2}: centred explicit second derivative
+        Ansatz e2{2, 0, 0, {0}, {M + 2}, {M + 2}};
+        std::vector<q> x;
+        int o2 = 0;
+        if (!ansatz_solve(e2, x, o2)) {
+            err = "biased scheme: singular Taylor system";
+            return CFD_ESINGULAR;
+        }
+        s.alpha = lam * u.alpha + (1 - lam) * v.alpha;
+        for (int m = -8; m <= 8; ++m) {
+            q e = (m >= -(M + 2) && m <= M + 2) ? x[1 + m + M + 2] : (q)0;
+            s.a[m + 8] = lam * u.at(m) + (1 - lam) * v.at(m) + lam * u.a2 * e;
+        }
+        s.order = 2 * M + 2;
+        // formal order check: rows 0..order vanish
+        for (int l = 0; l <= s.order; ++l)
+            if (qabs(biased_residual(s, l)) > (q)1e-28Q) {
+                err = "biased scheme: combination lost its formal order";
+                return CFD_ESINGULAR;
+            }
+    } else {
+        err = "biased scheme: unknown family (V or X)";
+        return CFD_EINVAL;
+    }
+    const int p = s.order;
+    const int qo = p + 2 - (p % 2);
+    // S = T / A as power series in z up to z^qo
+    std::vector<q> T(qo + 1), Am(qo + 1), S(qo + 1);
+    for (int l = 0; l <= qo; ++l) T[l] = biased_residual(s, l);
+    for (int k = 0; k <= qo; ++k) Am[k] = (k == 0 ? (q)1 : (q)0) + s.alpha * qpow_int(-1, k) / qfact(k);
+    for (int n = 0; n <= qo; ++n) {
+        q acc = T[n];
+        for (int k = 1; k <= n; ++k) acc -= Am[k] * S[n - k];
+        S[n] = acc / Am[0];
+    }
+    const q xi = 2 * S[qo];
+    // closure at k*_-: mirror (alpha on the next node, stencil -a_{-m}) plus
+    // xi sum_{j=0,1} w_j E_q(m - j), w = (1, alpha)
+    const int h = qo / 2;
+    q c[2 * 8 + 2] = {0};   // offsets -8..9
+    for (int m = -8; m <= 8; ++m) c[m + 8] += -s.at(-m);
+    for (int j = 0; j <= 1; ++j) {
+        const q w = j ? s.alpha : (q)1;
+        for (int t = -h; t <= h; ++t) {
+            q e = qfact(qo) / (qfact(t + h) * qfact(qo - t - h));
+            if ((h - t) % 2) e = -e;
+            c[j + t + 8] += xi * w * e;
+        }
+    }
+    // extents
+    int reach = 0;
+    for (int m = -8; m <= 8; ++m)
+        if (s.at(m) != 0) reach = std::max(reach, std::abs(m));
+    int cl_lo = 0, cl_hi = 0;
+    for (int m = -8; m <= 9; ++m)
+        if (c[m + 8] != 0) {
+            cl_lo = std::min(cl_lo, m);
+            cl_hi = std::max(cl_hi, m);
+        }
+    const int bh = std::max(reach, std::max(-cl_lo, cl_hi - 1));
+    if (bh > kBiasHalf) {
+        err = "biased scheme: stencil wider than the supported half-width";
+        return CFD_EUNSUPPORTED;
+    }
+    Scheme r;
+    r.kind = 1;
+    r.bias = bias;
+    r.d = 1;
+    r.order = p;
+    r.nl = 1;
+    r.nc = 1;
+    r.m = reach;
+    r.mc = std::max(-cl_lo, cl_hi);
+    r.bhalf = bh;
+    r.balpha = (double)s.alpha;
+    for (int m = -kBiasHalf; m <= kBiasHalf; ++m) r.ba[m + kBiasHalf] = (double)s.at(m);
+    for (int m = -kBiasHalf; m <= kBiasHalf + 1; ++m) r.bc[m + kBiasHalf] = (double)c[m + 8];
+    // the left-biased rows as a banded operator, for the generic fields
+    r.lhs[kMaxNL - 1] = r.balpha;
+    r.lhs[kMaxNL] = 1.0;
+    for (int m = -kMaxHalf; m <= kMaxHalf; ++m) r.rhs[kMaxHalf + m] = r.ba[m + kBiasHalf];
+    char nm[48];
+    std::snprintf(nm, sizeof nm, "(1)%c%d%s", family, M, bias < 0 ? "-" : (bias > 0 ? "+" : ""));
+    r.name = nm;
+    out = r;
+    return CFD_OK;
+}
+
 cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &err) {
     std::string base = name, variant;
     size_t colon = name.find(':');
@@ -398,6 +653,22 @@ cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &e
         return CFD_EINVAL;
     }
     const bool order_only = (variant == "E");
+    // biased: "(1)V3-", "(1)X2+", "(1)X2" (both biases, upwind by a velocity field)
+    if (variant.empty() && base.size() >= 5 && base.compare(0, 3, "(1)") == 0 && (base[3] == 'V' || base[3] == 'X') &&
+        base[4] >= '1' && base[4] <= '9') {
+        const std::string tail = base.substr(5);
+        int bias;
+        if (tail.empty()) bias = 0;
+        else if (tail == "-") bias = -1;
+        else if (tail == "+") bias = 1;
+        else {
+            err = "unknown scheme name '" + name + "'";
+            return CFD_EINVAL;
+        }
+        cfd_status bst = design_biased(base[3], base[4] - '0', 0.0, bias, out, err);
+        if (bst == CFD_OK) out.name = name;
+        return bst;
+    }
     if (base.size() < 5 || base[0] != '(' || base[2] != ')' || (base[1] != '1' && base[1] != '2')) {
         err = "unknown scheme name '" + name + "'";
         return CFD_EINVAL;
@@ -567,6 +838,20 @@ cfd_status check_symbol(const Scheme &s, std::string &err) {
 
 int required_ghosts(const Scheme &s, int periodic) {
     if (periodic) return 0;
+    if (s.kind == 1) {
+        // both biases: left closure row reaches its left half-width, row k*_- + 1
+        // the interior left reach - 1, row k*_+ the interior right reach; the
+        // right bias mirrors these
+        int la = 0, ra = 0, lc = 0;
+        for (int m = -kBiasHalf; m <= kBiasHalf; ++m)
+            if (s.ba[m + kBiasHalf] != 0) {
+                la = std::max(la, -m);
+                ra = std::max(ra, m);
+            }
+        for (int m = -kBiasHalf; m <= kBiasHalf + 1; ++m)
+            if (s.bc[m + kBiasHalf] != 0) lc = std::max(lc, -m);
+        return std::max(lc, std::max(la - 1, ra));
+    }
     if (s.nl == 0) return s.m;
     int need = s.m - s.nc;
     for (int j = 0; j < s.nc; ++j) need = std::max(need, s.mc - j);

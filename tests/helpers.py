@@ -4,6 +4,7 @@ from __future__ import annotations
 import numpy as np
 
 import synth
+from oracle import biased as OB
 from oracle import lines as OL
 from oracle import schemes as OS
 
@@ -19,6 +20,15 @@ def op_fields(wl, ops):
     return [wl.nfields if (len(op) < 3 or op[2] < 0) else 1 for op in ops]
 
 
+def biased_name(name):
+    """(base name, bias) for a biased scheme name ("(1)X2-" -> ("(1)X2", -1); "(1)X2" -> upwind, 0),
+    else None."""
+    if len(name) >= 5 and name.startswith("(1)") and name[3] in "VX" and name[4].isdigit():
+        base, tail = name[:5], name[5:]
+        return base, {"-": -1, "+": 1, "": 0}[tail]
+    return None
+
+
 def make_plan(wl, ops, dtype=0):
     import paper_2302_14858_amd as P
     schemes = {}
@@ -27,8 +37,29 @@ def make_plan(wl, ops, dtype=0):
         name = op[0]
         if name not in schemes:
             schemes[name] = P.Scheme.named(name)
-        pops.append((schemes[name], op[1], op[2] if len(op) > 2 else -1))
+        pops.append((schemes[name], op[1], op[2] if len(op) > 2 else -1, op[3] if len(op) > 3 else -1))
     return P.Plan(block_dicts(wl), wl.nfields, pops, dtype=dtype)
+
+
+def oracle_block_op(wl, b, op, f, out=None):
+    """The oracle's result of one operator on field f of block b ([z][y][x] interior)."""
+    blk = wl.blocks[b]
+    d = op[1]
+    per = blk.boundary[d] == synth.PERIODIC
+    bn = biased_name(op[0])
+    if bn is None:
+        return OL.apply_block(OS.named(op[0]), wl.field_view(b, f), blk.ng, blk.h[d], d, periodic=per, out=out)
+    base, bias = bn
+    if bias == 0:
+        ng = blk.ng
+        c = wl.field_view(b, op[3])[ng:ng + blk.n[2], ng:ng + blk.n[1], ng:ng + blk.n[0]]
+        r = OB.upwind_block(base, wl.field_view(b, f), c, ng, blk.h[d], d, periodic=per)
+    else:
+        r = OB.apply_block(base, bias, wl.field_view(b, f), blk.ng, blk.h[d], d, periodic=per)
+    if out is not None:
+        out[...] = r
+        return out
+    return r
 
 
 def gpu_run(plan, wl, ops, dtype=0, graph=False, stream=None):
@@ -76,14 +107,8 @@ def oracle_run(wl, ops, blocks=None):
         blk = wl.blocks[b]
         per = []
         for op in ops:
-            s = OS.named(op[0])
-            d = op[1]
             fsel = list(range(wl.nfields)) if (len(op) < 3 or op[2] < 0) else [op[2]]
-            fl = []
-            for f in fsel:
-                fl.append(OL.apply_block(s, wl.field_view(b, f), blk.ng, blk.h[d], d,
-                                         periodic=blk.boundary[d] == synth.PERIODIC))
-            per.append(fl)
+            per.append([oracle_block_op(wl, b, op, f) for f in fsel])
         res[b] = per
     return res
 
@@ -106,7 +131,6 @@ def oracle_flat(wl, ops, ooffs, nout, blocks=None):
     """The oracle's result in the plan's packed output layout (float64, NaN where nothing is written)."""
     ref = np.full(nout, np.nan)
     nf = op_fields(wl, ops)
-    schemes = {op[0]: OS.named(op[0]) for op in ops}
     blocks = range(len(wl.blocks)) if blocks is None else blocks
     for b in blocks:
         blk = wl.blocks[b]
@@ -119,8 +143,7 @@ def oracle_flat(wl, ops, ooffs, nout, blocks=None):
             for j, f in enumerate(fsel):
                 off = ooffs[b] + (slot + j) * npts
                 view = ref[off:off + npts].reshape(nz, ny, nx)
-                OL.apply_block(schemes[op[0]], wl.field_view(b, f), blk.ng, blk.h[d], d,
-                               periodic=blk.boundary[d] == synth.PERIODIC, out=view)
+                oracle_block_op(wl, b, op, f, out=view)
             slot += nf[o]
     return ref
 

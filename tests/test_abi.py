@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert P.cfd_abi_version() == 1
+    assert P.cfd_abi_version() == 2
 
 
 NAMES = ["(1)P1_1", "(2)P1_1", "(1)P1_2", "(2)P1_2", "(1)P1_3", "(2)P1_3", "(1)Q1_3[1]", "(2)Q1_3[1]",
@@ -181,3 +181,77 @@ def test_create_rejects_nonpositive_symbol():
 def test_debug_alloc_hook_is_harmless_without_device():
     P.cfd_debug_fail_alloc(0)
     P.cfd_debug_fail_alloc(-1)
+
+
+BIASED = ["(1)V1", "(1)V2", "(1)V3", "(1)V4", "(1)X1", "(1)X2", "(1)X3"]
+
+
+@pytest.mark.parametrize("name", BIASED)
+@pytest.mark.parametrize("suffix,bias", [("-", -1), ("+", 1), ("", 0)])
+def test_biased_registry_matches_oracle(name, suffix, bias):
+    """Biased schemes: the library's binary128 construction (xi from the Taylor-residual
+    series) and the oracle's exact one (xi from the complex error series) agree to round-off."""
+    from oracle import biased as OB
+    g = P.Scheme.named(name + suffix).get_biased()
+    s, c = OB.named(name)
+    assert g["bias"] == bias
+    assert g["order"] == s.order
+    assert abs(g["alpha"] - float(s.lhs.get(-1))) <= 2e-16
+    a = np.array([float(s.rhs[0].get(m)) for m in range(-5, 6)])
+    cc = np.array([float(c.rhs[0].get(m)) for m in range(-5, 7)])
+    assert float(c.lhs.get(1)) == float(s.lhs.get(-1))
+    assert np.max(np.abs(a - g["a"])) <= 4e-16 * np.max(np.abs(a))
+    assert np.max(np.abs(cc - g["c"])) <= 8e-16 * np.max(np.abs(cc))
+    sch = P.Scheme.named(name + suffix)
+    assert sch.required_ghosts() == OB.required_ghosts(name)
+    assert sch.required_ghosts(P.CFD_BOUNDARY_PERIODIC) == 0
+
+
+def test_biased_design_ranges_and_lambda():
+    from oracle import biased as OB
+    from fractions import Fraction
+    for fam, M in (("V", 0), ("V", 5), ("X", 0), ("X", 4)):
+        with pytest.raises(P.CfdError) as e:
+            P.Scheme.design_biased(fam, M)
+        assert e.value.status == _lib.CFD_EUNSUPPORTED
+    with pytest.raises(P.CfdError) as e:
+        P.Scheme.design_biased("Q", 2)
+    assert e.value.status == _lib.CFD_EINVAL
+    with pytest.raises(P.CfdError):
+        P.Scheme.design_biased("X", 2, 0.5, 3)
+    # a lambda other than the printed one: both constructions follow it
+    g = P.Scheme.design_biased("X", 2, 0.5, -1).get_biased()
+    s = OB.xscheme(2, Fraction(1, 2))
+    xi, c = OB.xi_closure(s)
+    assert abs(g["alpha"] - float(s.lhs.get(-1))) <= 2e-16
+    a = np.array([float(s.rhs[0].get(m)) for m in range(-5, 6)])
+    cc = np.array([float(c.rhs[0].get(m)) for m in range(-5, 7)])
+    assert np.max(np.abs(a - g["a"])) <= 4e-16 * np.max(np.abs(a))
+    assert np.max(np.abs(cc - g["c"])) <= 8e-16 * np.max(np.abs(cc))
+    with pytest.raises(P.CfdError):
+        P.Scheme.named("(1)X2*")
+    with pytest.raises(P.CfdError):
+        P.Scheme.named("(2)X2")
+
+
+@pytest.mark.parametrize("dr,L,R,classes", [
+    (1, 0, 1, [(0, 1, 2), (2, 0, 0)]),        # the worked example of Sec. 2 (d_I = (0, 2))
+    (1, 1, 0, [(0, 2, 2), (2, 0, 0)]),        # U_2 of Eq. defChenSchemes
+    (1, 1, 1, [(0, 2, 2)]),                   # Pade (1)P1_2
+    (2, 1, 1, [(0, 3, 3)]),                   # fully determined second-degree tridiagonal, M = 3
+    (1, 2, 2, [(0, 2, 2)]),                   # classical pentadiagonal O(8) (Sec. 2)
+])
+def test_taylor_scheme_matches_oracle(dr, L, R, classes):
+    g = P.cfd_taylor_scheme(dr, L, R, classes)
+    lhs, rhs, q = OS.determined_scheme(dr, (L, R), classes)
+    assert g["order"] == q
+    assert np.max(np.abs(np.array([float(v) for v in lhs.coef]) - g["lhs"])) <= 4e-16
+    for st, got in zip(rhs, g["rhs"]):
+        ref = np.array([float(v) for v in st.coef])
+        assert np.max(np.abs(ref - got)) <= 8e-16 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_taylor_scheme_rejects_bad_extents():
+    with pytest.raises(P.CfdError) as e:
+        P.cfd_taylor_scheme(1, 9, 9, [(0, 9, 9)])
+    assert e.value.status == _lib.CFD_EINVAL
