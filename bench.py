@@ -38,6 +38,9 @@ OPS_PENTA = [("(1)QP_O8[1]", 0), ("(1)QP_O8[1]", 1), ("(1)QP_O8[1]", 2),
 OPS_TRI = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2),
            ("(2)Q1_3[1]", 0), ("(2)Q1_3[1]", 1), ("(2)Q1_3[1]", 2)]
 OPS_D1_TRI = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2)]
+# shift advection beta^i d_i f of every field: the X_2 upwind pair along x, y, z with the velocity
+# read from fields 0, 1, 2 (the three shift components)
+OPS_UPWIND = [("(1)X2", 0, -1, 0), ("(1)X2", 1, -1, 1), ("(1)X2", 2, -1, 2)]
 
 
 def algorithmic_bytes(wl, ops, esize):
@@ -178,6 +181,32 @@ def extra_block128(steps, warmup, autotune, ng=4):
     return out
 
 
+def extra_upwind64(steps, warmup, autotune):
+    """batch64 blocks (ng = 5), 22 fields: beta^i d_i f for every field with the X_2 upwind pair
+    (left-biased where beta^i > 0, right-biased where beta^i < 0, Eq. biasderapproxadv), FP64 and FP32."""
+    import torch
+    import synth
+    import paper_2302_14858_amd as P
+    wl = synth.batch64()
+    ops = OPS_UPWIND
+    evals = wl.interior_points * wl.nfields * len(ops)
+    out = {"workload": "upwind64: batch64 blocks (extents from {16,24,32,48}^3, ng=5), 22 fields, beta^i d_i f "
+                       "with the (1)X2 upwind pair along x,y,z, beta^i = fields 0,1,2"}
+    ref = None
+    for label, dt, es in (("f64", P.CFD_F64, 8), ("f32", P.CFD_F32, 4)):
+        plan, x, y, ms, _, launches, items = run_gpu(wl, ops, dt, steps, warmup, autotune=autotune)
+        alg, _, _ = algorithmic_bytes(wl, ops, es)
+        if ref is None:
+            ref = oracle_reference(plan, wl, ops)
+        out[label] = {"ms_per_step": ms, "value": evals / (ms * 1e-3), "unit": "evals/s",
+                      "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "err_vs_oracle": err_vs_oracle(plan, y, wl, ops, ref),
+                      "err_scope": "every output node"}
+        del plan, x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def extra_periodic256(steps, warmup, autotune):
     """Periodic 256^3 x 8 fields, tridiagonal D1 along x, y, z: banded FP64, banded FP32, dense mixed."""
     import torch
@@ -272,7 +301,7 @@ def main():
                     help="set the batch64 launch shape by hand (a set of CFD_SCHED_* bits) instead of autotuning")
     ap.add_argument("--parts", default="",
                     help="with --flags: partitions per class as N:xlines:P,... (as printed in config.schedule)")
-    ap.add_argument("--only", choices=["block128", "periodic256", "wave192"], default=None,
+    ap.add_argument("--only", choices=["block128", "periodic256", "wave192", "upwind64"], default=None,
                     help="run just one of the other workloads and print its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -285,6 +314,8 @@ def main():
             r = extra_block128(args.steps, args.warmup, not args.no_autotune)
         elif args.only == "periodic256":
             r = extra_periodic256(min(args.steps, 20), args.warmup, not args.no_autotune)
+        elif args.only == "upwind64":
+            r = extra_upwind64(args.steps, args.warmup, not args.no_autotune)
         else:
             r = extra_wave192()
         print(json.dumps({args.only: r}), flush=True)
@@ -354,6 +385,8 @@ def main():
         result["extra"]["block128"] = extra_block128(args.steps, args.warmup, not args.no_autotune)
         print("bench: block128 at ng=3", file=sys.stderr, flush=True)
         result["extra"]["block128_ng3"] = extra_block128(args.steps, args.warmup, not args.no_autotune, ng=3)
+        print("bench: upwind64 shift advection", file=sys.stderr, flush=True)
+        result["extra"]["upwind64"] = extra_upwind64(args.steps, args.warmup, not args.no_autotune)
         print("bench: periodic256 precision study", file=sys.stderr, flush=True)
         result["extra"]["periodic256"] = extra_periodic256(min(args.steps, 20), args.warmup, not args.no_autotune)
         print("bench: wave192 RK4", file=sys.stderr, flush=True)

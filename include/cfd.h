@@ -304,7 +304,8 @@ cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream);
  * file, keyed by device arch, dtype, line length, direction class, band,
  * fused operators and launch shape.  Overwrites out_dev.  Allocates a
  * temporary output-sized buffer for the check.  Synchronises the stream.
- * Invalidates a captured graph. */
+ * Invalidates a captured graph.  Biased operators have one launch shape and
+ * are not tuned (a plan holding only biased operators returns at once). */
 cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, void *stream,
                              const char *cache_path);
 

@@ -17,14 +17,28 @@
 // Upwind operator (Eq. biasderapproxadv, with c the velocity field sampled on
 // the grid): c d f = min(c, 0) D[right] f + max(c, 0) D[left] f.
 //
-// One lane per line, 64 lines per wave, four independent waves per
-// workgroup.  Lanes run along the contiguous direction of the block for y
-// and z lines, so every load and store of a wave is one coalesced access.
-// A lane keeps a register window of 2 HB + 3 samples (offsets -(HB+1) ..
-// HB+1 around the current row) and slides it one node per row.  The right-
-// biased sweep runs first (from k*_+ down) and leaves min(c,0) D[right] f in
-// the output; the left-biased sweep (from k*_- up) adds max(c,0) D[left] f.
+// Partitioned kernel (lines of up to 64 nodes): one lane per line, 64 lines
+// per wave; a line is cut into P = 1, 2 or 4 partitions of at most L = 8, 12
+// or 16 rows (the fewest partitions with at most 12 rows where possible),
+// one wave each, so a workgroup of four waves holds 4 / P groups of 64
+// lines.  A wave issues every load of its partition (its rows and the
+// stencil halo) before any arithmetic and keeps them in registers.  Each
+// bias is solved locally with a zero value entering the partition (the
+// closure rows where the partition holds them); the exact solution is the
+// local one plus (-alpha)^distance times the true value entering it.  The
+// waves exchange their local end values through LDS and each walks the
+// chain of partitions before it (around the line on periodic lines, closed
+// by 1 / (1 - (-alpha)^N)) to get its entering values.  Lanes run along the
+// contiguous direction of the block for y and z lines, so each load and
+// store of a wave is one coalesced access; x lines are staged through an LDS
+// tile filled and drained with contiguous accesses along the rows.
+//
+// Sweep kernel (longer lines): one lane per line, a register window of
+// 2 HB + 3 samples slid one node per row; the right-biased sweep leaves
+// min(c,0) D[right] f in the output, the left-biased sweep adds the rest.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "cfd_internal.h"
 
@@ -81,6 +95,210 @@ __device__ __forceinline__ T right_closure(const BCoef<T, HB> &q, const T *w) {
 #pragma unroll
     for (int m = -HB; m <= HB + 1; ++m) r -= q.c[m + HB] * w[HB + 1 - m];
     return r;
+}
+
+template <typename T, int HB>
+__device__ __forceinline__ void load_coef(BCoef<T, HB> &q, const T *rec) {
+    q.alpha = rec[0];
+    q.inv_det = rec[24];
+#pragma unroll
+    for (int m = -HB; m <= HB; ++m) q.a[m + HB] = rec[1 + kBiasHalf + m];
+#pragma unroll
+    for (int m = -HB; m <= HB + 1; ++m) q.c[m + HB] = rec[12 + kBiasHalf + m];
+}
+
+// LDS: exchange area [4 waves][2][64], then (x lines) the tile of the
+// workgroup's lines, [4/P groups x 64 lines][pitch].
+template <typename T, int HB, int L, bool XDIR>
+__global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict__ items,
+                                                     const BiasPass *__restrict__ passes,
+                                                     const T *__restrict__ coefs, const T *__restrict__ in,
+                                                     T *__restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int W = L + 2 * HB + 2;   // f[i] = node k0 - HB - 1 + i
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const BiasItem item = items[blockIdx.x];
+    if (item.pass < 0) return;   // padding of the XCD-interleaved order (whole workgroup)
+    const BiasPass ps = passes[item.pass];
+    const int P = item.P, G = 4 / P;
+    const int g = wv / P, p = wv - g * P;
+    const int N = ps.N, Lr = (N + P - 1) / P;
+    const int k0 = p * Lr;
+    const int nrows = min(Lr, N - k0);   // >= 2: the host picks P so that every partition has 2 rows
+    const int line = item.line0 + 64 * g + lane;
+    const bool active = line < ps.nlines;
+    const int u = active ? line % ps.nu : 0, v = active ? line / ps.nu : 0;
+    const int64_t fbase = ps.in_base + (int64_t)item.field * ps.in_fstride;
+    const int64_t obase = ps.out_base + (int64_t)item.field * ps.out_fstride;
+    T *exch = (T *)smem;
+    T *tile = exch + 4 * 2 * 64;
+    const bool periodic = ps.periodic;
+    const bool closureL = !periodic && p == 0;
+    const bool closureR = !periodic && p == P - 1;
+    const int mode = ps.mode;
+    const T *rec = coefs + (int64_t)ps.tab * kBiasRec;
+    BCoef<T, HB> q;
+    load_coef<T, HB>(q, rec);
+    const T alpha = q.alpha;
+
+    // ---- partition rows and halo into registers
+    T f[W];
+    int vp = N | 1;   // x lines: pitch of the velocity / output tile
+    if (XDIR) {
+        int t0, Tn;
+        if (periodic) {
+            t0 = 0;
+            Tn = N;
+        } else {
+            const int e = min(ps.ng, HB + 1);
+            t0 = -e;
+            Tn = N + 2 * e;
+        }
+        const int tp = Tn | 1;
+        const int nl = 64 * G;
+        // consecutive threads take consecutive nodes of the workgroup's rows
+        for (int e = threadIdx.x; e < nl * Tn; e += 256) {
+            const int l = e / Tn, j = e - l * Tn;
+            const int ln = item.line0 + l;
+            T val = 0;
+            if (ln < ps.nlines) {
+                const int uu = ln % ps.nu, vv = ln / ps.nu;
+                val = in[fbase + (int64_t)uu * ps.su + (int64_t)vv * ps.sv + (t0 + j)];
+            }
+            tile[l * tp + j] = val;
+        }
+        __syncthreads();
+        const T *row = tile + (64 * g + lane) * tp;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            int j = k0 - HB - 1 + i;
+            if (periodic) {
+                j %= N;
+                if (j < 0) j += N;
+                f[i] = row[j];
+            } else {
+                f[i] = (j >= t0 && j < t0 + Tn) ? row[j - t0] : T(0);
+            }
+        }
+        __syncthreads();   // the tile is reused for the velocity and the output
+        if (mode == 0) {
+            for (int e = threadIdx.x; e < nl * N; e += 256) {
+                const int l = e / N, j = e - l * N;
+                const int ln = item.line0 + l;
+                T val = 0;
+                if (ln < ps.nlines) {
+                    const int uu = ln % ps.nu, vv = ln / ps.nu;
+                    val = in[ps.vel_base + (int64_t)uu * ps.su + (int64_t)vv * ps.sv + j];
+                }
+                tile[l * vp + j] = val;
+            }
+        }
+    } else {
+        BLine<T> Lf{in + fbase + (int64_t)u * ps.su + (int64_t)v * ps.sv, ps.sd, N, ps.ng, periodic};
+#pragma unroll
+        for (int i = 0; i < W; ++i) f[i] = active ? Lf.ld(k0 - HB - 1 + i) : T(0);
+    }
+
+    // ---- right-hand sides (closure rows where this partition holds them)
+    T rl[L], rr[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        rl[i] = (closureL && i == 0) ? left_closure<T, HB>(q, f + i) : left_interior<T, HB>(q, f + i);
+        rr[i] = (closureR && i == nrows - 1) ? right_closure<T, HB>(q, f + i) : right_interior<T, HB>(q, f + i);
+    }
+
+    // ---- local solves with zero entering values
+    T xl_last = 0, xr_first = 0;
+    if (mode <= 0) {
+        T xp = 0;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const T x = (closureL && i == 0) ? (rl[0] - alpha * rl[1]) * q.inv_det : rl[i] - alpha * xp;
+            rl[i] = x;
+            xp = x;
+            if (i == nrows - 1) xl_last = x;
+        }
+    }
+    if (mode >= 0) {
+        T xn = 0;
+#pragma unroll
+        for (int i = L - 1; i >= 0; --i) {
+            T x;
+            if (i >= nrows) x = 0;
+            else if (closureR && i == nrows - 1) x = (rr[i] - alpha * (i > 0 ? rr[i > 0 ? i - 1 : 0] : T(0))) * q.inv_det;
+            else x = rr[i] - alpha * xn;
+            rr[i] = x;
+            xn = x;
+        }
+        xr_first = rr[0];
+    }
+    // velocity of y/z lines: loaded here so that the loads overlap the exchange
+    T c[L];
+    if (!XDIR && mode == 0) {
+        const T *vl = in + ps.vel_base + (int64_t)u * ps.su + (int64_t)v * ps.sv;
+#pragma unroll
+        for (int i = 0; i < L; ++i) c[i] = (active && i < nrows) ? vl[(int64_t)(k0 + i) * ps.sd] : T(0);
+    }
+    exch[(wv * 2 + 0) * 64 + lane] = xl_last;
+    exch[(wv * 2 + 1) * 64 + lane] = xr_first;
+    __syncthreads();
+
+    // ---- true values entering the partition
+    const T *pw = rec + kBiasPow;   // (-alpha)^n
+    T X = 0, Y = 0;
+    if (mode <= 0) {
+        if (periodic) {
+            T s = 0;
+            for (int qq = 0; qq < P; ++qq) {
+                const int k1 = min(qq * Lr + Lr, N) - 1;
+                s += pw[N - 1 - k1] * exch[((g * P + qq) * 2 + 0) * 64 + lane];
+            }
+            X = s * (T)ps.wrap;
+        }
+        for (int qq = 0; qq < p; ++qq) X = exch[((g * P + qq) * 2 + 0) * 64 + lane] + pw[min(Lr, N - qq * Lr)] * X;
+    }
+    if (mode >= 0) {
+        if (periodic) {
+            T s = 0;
+            for (int qq = 0; qq < P; ++qq) s += pw[qq * Lr] * exch[((g * P + qq) * 2 + 1) * 64 + lane];
+            Y = s * (T)ps.wrap;
+        }
+        for (int qq = P - 1; qq > p; --qq) Y = exch[((g * P + qq) * 2 + 1) * 64 + lane] + pw[min(Lr, N - qq * Lr)] * Y;
+    }
+
+    // ---- corrected values, combined and stored
+    const T hinv = (T)ps.hinv;
+    T *tl = tile + (64 * g + lane) * vp;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        if (i < nrows) {
+            T val;
+            if (mode < 0) {
+                val = hinv * (rl[i] + pw[i + 1] * X);
+            } else if (mode > 0) {
+                val = hinv * (rr[i] + pw[nrows - i] * Y);
+            } else {
+                const T cv = XDIR ? tl[k0 + i] : c[i];
+                const T xL = rl[i] + pw[i + 1] * X;
+                const T xR = rr[i] + pw[nrows - i] * Y;
+                val = fmin(cv, (T)0) * (hinv * xR) + fmax(cv, (T)0) * (hinv * xL);
+            }
+            if (XDIR) tl[k0 + i] = val;
+            else if (active) out[obase + (int64_t)u * ps.osu + (int64_t)v * ps.osv + (int64_t)(k0 + i) * ps.osd] = val;
+        }
+    }
+    if (XDIR) {
+        __syncthreads();
+        const int nl = 64 * G;
+        for (int e = threadIdx.x; e < nl * N; e += 256) {
+            const int l = e / N, j = e - l * N;
+            const int ln = item.line0 + l;
+            if (ln < ps.nlines) {
+                const int uu = ln % ps.nu, vv = ln / ps.nu;
+                out[obase + (int64_t)uu * ps.osu + (int64_t)vv * ps.osv + j] = tile[l * vp + j];
+            }
+        }
+    }
 }
 
 template <typename T, int HB>
@@ -210,7 +428,7 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
 }
 
 template <typename T>
-const void *biased_fn(int hb) {
+const void *sweep_fn(int hb) {
     switch (hb) {
         case 2: return (const void *)k_biased<T, 2>;
         case 3: return (const void *)k_biased<T, 3>;
@@ -220,29 +438,71 @@ const void *biased_fn(int hb) {
     }
 }
 
+template <typename T, int HB>
+const void *part_fn_hb(int L, int xdir) {
+    if (L == 8) return xdir ? (const void *)k_biased_part<T, HB, 8, true> : (const void *)k_biased_part<T, HB, 8, false>;
+    if (L == 12) return xdir ? (const void *)k_biased_part<T, HB, 12, true> : (const void *)k_biased_part<T, HB, 12, false>;
+    if (L == 16) return xdir ? (const void *)k_biased_part<T, HB, 16, true> : (const void *)k_biased_part<T, HB, 16, false>;
+    return nullptr;
+}
+
+template <typename T>
+const void *part_fn(int hb, int L, int xdir) {
+    switch (hb) {
+        case 2: return part_fn_hb<T, 2>(L, xdir);
+        case 3: return part_fn_hb<T, 3>(L, xdir);
+        case 4: return part_fn_hb<T, 4>(L, xdir);
+        case 5: return part_fn_hb<T, 5>(L, xdir);
+        default: return nullptr;
+    }
+}
+
 }  // namespace
 
 bool biased_supported(int hb) { return hb >= 2 && hb <= 5; }
 
-hipError_t launch_biased(int f32, int hb, const BiasItem *items, int nitems, const BiasPass *passes,
-                         const void *coefs, const void *in, void *out, hipStream_t st) {
-    if (nitems <= 0) return hipSuccess;
-    const int grid = (nitems + 3) / 4;
-    if (f32) {
-        const void *fn = biased_fn<float>(hb);
-        if (!fn) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(((void (*)(const BiasItem *, int, const BiasPass *, const float *, const float *,
-                                      float *))fn),
-                           dim3(grid), dim3(256), 0, st, items, nitems, passes, (const float *)coefs,
-                           (const float *)in, (float *)out);
-    } else {
-        const void *fn = biased_fn<double>(hb);
-        if (!fn) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(((void (*)(const BiasItem *, int, const BiasPass *, const double *, const double *,
-                                      double *))fn),
-                           dim3(grid), dim3(256), 0, st, items, nitems, passes, (const double *)coefs,
-                           (const double *)in, (double *)out);
+size_t biased_lds(int f32, int hb, int L, int xdir, int P, int N) {
+    if (L == 0) return 0;
+    const size_t es = f32 ? 4 : 8;
+    size_t b = 4 * 2 * 64 * es;
+    if (xdir) {
+        const int e = hb + 1;   // at most this many ghost nodes per side are staged
+        const int tp = (N + 2 * e) | 1;
+        b += (size_t)(4 / P) * 64 * (size_t)std::max(tp, N | 1) * es;
     }
+    return b;
+}
+
+hipError_t launch_biased(int f32, int hb, int L, int xdir, size_t lds, const BiasItem *items, int nitems,
+                         const BiasPass *passes, const void *coefs, const void *in, void *out, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (L == 0) {
+        const int grid = (nitems + 3) / 4;
+        const void *fn = f32 ? sweep_fn<float>(hb) : sweep_fn<double>(hb);
+        if (!fn) return hipErrorInvalidValue;
+        if (f32)
+            hipLaunchKernelGGL(((void (*)(const BiasItem *, int, const BiasPass *, const float *, const float *,
+                                          float *))fn),
+                               dim3(grid), dim3(256), 0, st, items, nitems, passes, (const float *)coefs,
+                               (const float *)in, (float *)out);
+        else
+            hipLaunchKernelGGL(((void (*)(const BiasItem *, int, const BiasPass *, const double *, const double *,
+                                          double *))fn),
+                               dim3(grid), dim3(256), 0, st, items, nitems, passes, (const double *)coefs,
+                               (const double *)in, (double *)out);
+        return hipGetLastError();
+    }
+    const void *fn = f32 ? part_fn<float>(hb, L, xdir) : part_fn<double>(hb, L, xdir);
+    if (!fn) return hipErrorInvalidValue;
+    if (f32)
+        hipLaunchKernelGGL(((void (*)(const BiasItem *, const BiasPass *, const float *, const float *, float *))fn),
+                           dim3(nitems), dim3(256), lds, st, items, passes, (const float *)coefs, (const float *)in,
+                           (float *)out);
+    else
+        hipLaunchKernelGGL(((void (*)(const BiasItem *, const BiasPass *, const double *, const double *,
+                                      double *))fn),
+                           dim3(nitems), dim3(256), lds, st, items, passes, (const double *)coefs,
+                           (const double *)in, (double *)out);
     return hipGetLastError();
 }
 

@@ -137,7 +137,8 @@ struct cfd_plan {
     // biased (upwind) operators: one pass per (block, op), work items grouped
     // by stencil half-width class, coefficient records per op
     struct BGroup {
-        int hb = 0;
+        int hb = 0, L = 0, xdir = 0;   // L = 0: sweep kernel
+        size_t lds = 0;
         int64_t item0 = 0, nitems = 0;
     };
     std::vector<BGroup> bgroups;
@@ -902,9 +903,14 @@ cfd_status build_biased(cfd_plan *p) {
         for (int m = 0; m < 2 * kBiasHalf + 1; ++m) r[1 + m] = s.ba[m];
         for (int m = 0; m < 2 * kBiasHalf + 2; ++m) r[12 + m] = s.bc[m];
         r[24] = 1.0 / (1.0 - s.balpha * s.balpha);
+        double pw = 1.0;
+        for (int n = 0; n <= kBiasMaxPN; ++n, pw *= -s.balpha) r[kBiasPow + n] = pw;
     }
     std::vector<BiasPass> bp;
-    std::map<int, std::vector<BiasItem>> by_hb;
+    // kernel class (hb, L, x lines) -> items; L = 0 is the sweep kernel
+    std::map<std::array<int, 3>, std::vector<BiasItem>> by_cls;
+    std::map<std::array<int, 3>, size_t> cls_lds;
+    std::map<std::array<int, 3>, std::vector<int>> by_unit;   // first item of each unit
     for (size_t b = 0; b < p->blocks.size(); ++b) {
         const cfd_block &bl = p->blocks[b];
         const int64_t npts = (int64_t)bl.n[0] * bl.n[1] * bl.n[2];
@@ -951,15 +957,54 @@ cfd_status build_biased(cfd_plan *p) {
             bp.push_back(q);
             const int f0 = op.field < 0 ? 0 : op.field;
             const int nf = op.field < 0 ? p->nfields : 1;
-            for (int f = 0; f < nf; ++f)
-                for (int l0 = 0; l0 < q.nlines; l0 += kWave)
-                    by_hb[q.hb].push_back(BiasItem{pi, f0 + f, l0, 0});
+            // partitions: every partition keeps at least two rows ((P-1) ceil(N/P) <= N - 2)
+            const int N = q.N;
+            // (at most 12 rows per partition where 4 partitions allow it: fewer registers)
+            const int P = (N <= 12) ? 1 : (N <= 24) ? 2 : (N <= kBiasMaxPN) ? 4 : 0;
+            const int Lr = P ? (N + P - 1) / P : 0;
+            const int L = P == 0 ? 0 : (Lr <= 8 ? 8 : Lr <= 12 ? 12 : 16);
+            const int xdir = (P > 0 && op.dir == 0) ? 1 : 0;
+            const std::array<int, 3> key{q.hb, L, xdir};
+            const int step = P ? kWave * (4 / P) : kWave;
+            size_t lds = biased_lds(p->dtype != CFD_F64, q.hb, L, xdir, P ? P : 1, N);
+            size_t &cl = cls_lds[key];
+            cl = std::max(cl, lds);
+            // unit = the items of one line group over all selected fields (they share the velocity)
+            for (int l0 = 0; l0 < q.nlines; l0 += step) {
+                by_unit[key].push_back((int)by_cls[key].size());
+                for (int f = 0; f < nf; ++f) by_cls[key].push_back(BiasItem{pi, f0 + f, l0, P});
+            }
+        }
+    }
+    // Where the device deals workgroups round-robin over its 8 XCDs, a line
+    // group's items (all its fields) go to one XCD: units are dealt to XCDs in
+    // turn and position 8 r + x holds XCD x's r-th item, queues padded with
+    // empty items, so the velocity lines stay in that XCD's L2.
+    if (p->xcd_interleave_ok) {
+        for (auto &kv : by_cls) {
+            if (kv.first[1] == 0) continue;   // sweep kernel: four items per workgroup, plain order
+            const std::vector<int> &u0 = by_unit[kv.first];
+            std::vector<std::vector<BiasItem>> q(kXCDq);
+            for (size_t ui = 0; ui < u0.size(); ++ui) {
+                const int b0 = u0[ui], b1 = (ui + 1 < u0.size()) ? u0[ui + 1] : (int)kv.second.size();
+                for (int i = b0; i < b1; ++i) q[ui % kXCDq].push_back(kv.second[i]);
+            }
+            size_t len = 0;
+            for (auto &v : q) len = std::max(len, v.size());
+            std::vector<BiasItem> inter(len * kXCDq, BiasItem{-1, 0, 0, 0});
+            for (int x = 0; x < kXCDq; ++x)
+                for (size_t r = 0; r < q[x].size(); ++r) inter[r * kXCDq + x] = q[x][r];
+            kv.second.swap(inter);
         }
     }
     std::vector<BiasItem> items;
-    for (auto &kv : by_hb) {
+    for (auto &kv : by_cls) {
         cfd_plan::BGroup g;
-        g.hb = kv.first;
+        g.hb = kv.first[0];
+        g.L = kv.first[1];
+        g.xdir = kv.first[2];
+        g.lds = cls_lds[kv.first];
+        if (g.lds > p->max_lds) return fail(CFD_EUNSUPPORTED, "biased-line tile exceeds the device's LDS");
         g.item0 = (int64_t)items.size();
         g.nitems = (int64_t)kv.second.size();
         items.insert(items.end(), kv.second.begin(), kv.second.end());
@@ -984,8 +1029,9 @@ cfd_status build_biased(cfd_plan *p) {
 
 cfd_status launch_biased_groups(cfd_plan *p, const void *in, void *out, hipStream_t st) {
     for (const cfd_plan::BGroup &g : p->bgroups) {
-        hipError_t e = launch_biased(p->dtype != CFD_F64, g.hb, (const BiasItem *)p->d_bitems.p + g.item0,
-                                     (int)g.nitems, (const BiasPass *)p->d_bpass.p, p->d_bcoef.p, in, out, st);
+        hipError_t e = launch_biased(p->dtype != CFD_F64, g.hb, g.L, g.xdir, g.lds,
+                                     (const BiasItem *)p->d_bitems.p + g.item0, (int)g.nitems,
+                                     (const BiasPass *)p->d_bpass.p, p->d_bcoef.p, in, out, st);
         if (e != hipSuccess) return hip_fail(e, "launching the biased-line kernel");
     }
     return CFD_OK;
@@ -1595,6 +1641,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     }
     const bool f32 = p->dtype != CFD_F64;
     const char *dt = f32 ? "f32" : "f64";
+    if (p->passes.empty()) return CFD_OK;   // only biased operators: one fixed launch shape
     if (p->dtype == CFD_MIXED_BF16) {
         // only the grid kind: persistent or one workgroup per item
         hipEvent_t a0, a1;

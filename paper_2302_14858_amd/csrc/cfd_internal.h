@@ -129,8 +129,11 @@ struct PassDesc {
 // (cfd_biased.hip).  mode: -1 left-biased, +1 right-biased, 0 upwind by the
 // sign of the velocity field at vel_base.  Coefficient record per table
 // (elements of the plan's type): [0] alpha, [1, 12) ba_{-5..5},
-// [12, 24) bc_{-5..6}, [24] 1 / (1 - alpha^2).
-constexpr int kBiasRec = 32;
+// [12, 24) bc_{-5..6}, [24] 1 / (1 - alpha^2), [32, 32 + 65) (-alpha)^n for
+// n = 0..64.
+constexpr int kBiasRec = 128;
+constexpr int kBiasPow = 32;
+constexpr int kBiasMaxPN = 64;   // longest line of the partitioned kernel (4 partitions of 16)
 struct BiasPass {
     int64_t in_base;        // input offset of field 0, interior node (0,0,0)
     int64_t in_fstride;     // input elements per field
@@ -144,8 +147,11 @@ struct BiasPass {
     double hinv;            // 1 / h
     double wrap;            // periodic: 1 / (1 - (-alpha)^N)
 };
+// One work item of the partitioned kernel: 64 * (4 / P) lines of one field of
+// one pass, P partitions per line (one wave each); of the sweep kernel (lines
+// longer than kBiasMaxPN): 64 lines per wave, P = 0.
 struct BiasItem {
-    int32_t pass, field, line0, pad;
+    int32_t pass, field, line0, P;
 };
 
 // One work item: 64 * (4 / P) lines of one field of one pass.
@@ -232,10 +238,14 @@ hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *sta
 }  // namespace cfd
 
 namespace cfd {
-// biased (upwind) lines (cfd_biased.hip); hb: stencil half-width class 2..5
+// biased (upwind) lines (cfd_biased.hip); hb: stencil half-width class 2..5;
+// L: partition length class of the partitioned kernel (8, 12 or 16), 0 for the
+// sweep kernel; xdir: lines along x (LDS-staged).
+// lds: bytes of dynamic LDS.
 bool biased_supported(int hb);
-hipError_t launch_biased(int f32, int hb, const BiasItem *items, int nitems, const BiasPass *passes,
-                         const void *coefs, const void *in, void *out, hipStream_t st);
+size_t biased_lds(int f32, int hb, int L, int xdir, int P, int N);
+hipError_t launch_biased(int f32, int hb, int L, int xdir, size_t lds, const BiasItem *items, int nitems,
+                         const BiasPass *passes, const void *coefs, const void *in, void *out, hipStream_t st);
 }  // namespace cfd
 
 namespace cfd {
