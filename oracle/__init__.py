@@ -12,6 +12,7 @@ product library never does, and the two share no code.
 * ``oracle.wave``     - the first-order wave system under classical RK4: the
   closed-form evolution of one Fourier mode and a plain stepped integrator.
 * ``oracle.iterate``  - hybrid iteration of the block closures.
+* ``oracle.dissipation`` - Kreiss-Oliger dissipation by repeated differences.
 * ``oracle.biased``   - biased (upwind) schemes U, V, X with their xi-closures,
   their line operator (dense solve) and the upwind selection by a velocity
   field.
