@@ -123,6 +123,17 @@ cfd_status cfd_scheme_named(const char *name, cfd_scheme **out);
  * above 5), CFD_EINVAL on a bad family or bias. */
 cfd_status cfd_scheme_design_biased(char family, int M, double lambda, int bias, cfd_scheme **out);
 
+/* Kreiss-Oliger dissipation of Eq. dissdef as an operator:
+ *   Q^(2r) f = -(-1)^r / 2^(2r) sigma dx^(2r-1) (D_+)^r (D_-)^r f,
+ * the explicit centred stencil of (D_+ D_-)^r (the binomial rows of Tab.
+ * diss_scheme) times -(-1)^r sigma / 4^r, output scaled by h^-1 (not h^-2r).
+ * Used in a plan like any explicit scheme (one direction per operator; the
+ * paper adds it in every direction).  Needs r ghost layers on closure lines.
+ * r = 1..5 (degree 2..10; Q^(8), r = 4, with sigma = 0.04 is the paper's
+ * choice), sigma >= 0.  CFD_EUNSUPPORTED outside that range, CFD_EINVAL for a
+ * negative or non-finite sigma. */
+cfd_status cfd_scheme_dissipation(int r, double sigma, cfd_scheme **out);
+
 /* Read back a biased scheme: bias (-1, +1, 0), its formal order, alpha =
  * alpha^(1)_{-1} of the left-biased interior row alpha x_{k-1} + x_k =
  * sum_m a_m f_{k+m}, a[11] = a_{-5..5}, and the left closure row

@@ -13,6 +13,7 @@ product library never does, and the two share no code.
   closed-form evolution of one Fourier mode and a plain stepped integrator.
 * ``oracle.iterate``  - hybrid iteration of the block closures.
 * ``oracle.dissipation`` - Kreiss-Oliger dissipation by repeated differences.
+* ``oracle.mixed``    - symmetrised mixed second derivatives 1/2 (D_i D_j + D_j D_i).
 * ``oracle.biased``   - biased (upwind) schemes U, V, X with their xi-closures,
   their line operator (dense solve) and the upwind selection by a velocity
   field.

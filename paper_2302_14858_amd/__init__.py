@@ -119,6 +119,14 @@ class Scheme:
 
     design_biased = cfd_scheme_design_biased
 
+    @classmethod
+    def cfd_scheme_dissipation(cls, r: int, sigma: float) -> "Scheme":
+        out = ctypes.c_void_p()
+        check(lib().cfd_scheme_dissipation(int(r), float(sigma), ctypes.byref(out)))
+        return cls(out.value)
+
+    dissipation = cfd_scheme_dissipation
+
     def cfd_scheme_get_biased(self) -> Dict:
         bias, order, alpha = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         a = (ctypes.c_double * 11)()

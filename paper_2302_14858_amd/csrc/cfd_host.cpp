@@ -388,7 +388,7 @@ std::vector<PassDesc> pass_descs(const cfd_plan *p, const std::vector<std::array
         for (int o = 0; o < ps.nops; ++o) {
             ob[o] = p->out_off[ps.block] + p->op_slot[ps.op[o]] * npts;
             tab[o] = pass_tab[i][o];
-            hinv[o] = 1.0 / std::pow(b.h[ps.dir], p->schemes[ps.sch[o]].d);
+            hinv[o] = 1.0 / std::pow(b.h[ps.dir], scale_power(p->schemes[ps.sch[o]]));
         }
         fill_pass_desc(pd[i], b, p->in_off[ps.block], ps, ob, tab, hinv);
     }
@@ -1298,6 +1298,16 @@ cfd_status cfd_scheme_design_biased(char family, int M, double lambda, int bias,
     std::string err;
     Scheme s;
     cfd_status st = design_biased(family, M, lambda, bias, s, err);
+    if (st != CFD_OK) return fail(st, err);
+    *out = new cfd_scheme{s};
+    return CFD_OK;
+}
+
+cfd_status cfd_scheme_dissipation(int r, double sigma, cfd_scheme **out) {
+    if (!out) return fail(CFD_EINVAL, "cfd_scheme_dissipation: null output");
+    std::string err;
+    Scheme s;
+    cfd_status st = design_dissipation(r, sigma, s, err);
     if (st != CFD_OK) return fail(st, err);
     *out = new cfd_scheme{s};
     return CFD_OK;

@@ -42,6 +42,9 @@ struct Scheme {
     // x_0 + alpha x_1 = sum_m bc_m f_m (bc on -kBiasHalf .. kBiasHalf+1);
     // the right-biased scheme is the mirror image.  bias: -1 left-biased,
     // +1 right-biased, 0 both, combined by the sign of a velocity field.
+    // Power of h the output is scaled by (h^-hpow); -1 means d.  Kreiss-Oliger
+    // dissipation: stencil of a 2r-th difference (even parity), scaled by h^-1.
+    int hpow = -1;
     int kind = 0;
     int bias = -1;
     int bhalf = 0;                 // largest reach of ba / bc (bc may reach bhalf + 1 to the right)
@@ -54,6 +57,9 @@ struct Scheme {
 // Biased scheme construction (scheme_design.cpp).  family 'V' (M = 1..4) or
 // 'X' (M = 1..3; lambda <= 0 takes the value printed with the scheme).
 cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &out, std::string &err);
+// Kreiss-Oliger dissipation Q^(2r) (Eq. dissdef) as an explicit scheme.
+cfd_status design_dissipation(int r, double sigma, Scheme &out, std::string &err);
+inline int scale_power(const Scheme &s) { return s.hpow >= 0 ? s.hpow : s.d; }
 // A fully determined scheme of the multi-derivative ansatz (Eq. mdAnsatz,
 // Eq. Tcons): unknown derivative dr on offsets -L..R (alpha^(dr)_0 = 1),
 // sample classes dI[c] on offsets -Lk[c]..Rk[c].  Coefficients in binary128,

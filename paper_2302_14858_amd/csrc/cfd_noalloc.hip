@@ -219,7 +219,7 @@ extern "C" cfd_status cfd_apply_block_noalloc(const cfd_scheme *sc, const cfd_bl
     {
         const int64_t ob[2] = {0, 0};
         const int tab[2] = {0, 0};
-        const double hinv[2] = {1.0 / std::pow(b.h[dir], s.d), 0.0};
+        const double hinv[2] = {1.0 / std::pow(b.h[dir], scale_power(s)), 0.0};
         fill_pass_desc(a.pd, b, 0, ps, ob, tab, hinv);
     }
     a.meta = ps.P | (ps.lcode << 4) | ((ps.C - 1) << 8);

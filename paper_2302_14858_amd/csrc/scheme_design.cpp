@@ -641,6 +641,42 @@ cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &ou
     return CFD_OK;
 }
 
+// Kreiss-Oliger dissipation (Eq. dissdef): Q^(2r) = -(-1)^r / 2^(2r) sigma
+// dx^(2r-1) (D_+)^r (D_-)^r.  (D_+ D_-)^r has the centred binomial stencil
+// sum_n (-1)^(r-n) C(2r, r+n) f_{k+n} / dx^(2r) (Tab. diss_scheme), so Q^(2r)
+// is the explicit symmetric stencil q_n = -(-1)^r sigma 4^-r (-1)^(r-n)
+// C(2r, r+n), scaled by dx^-1.  Stored as an explicit scheme of even degree
+// 2r (symmetric stencil) with the output scaled by h^-1.
+cfd_status design_dissipation(int r, double sigma, Scheme &out, std::string &err) {
+    if (r < 1 || r > kMaxHalf) {
+        err = "Kreiss-Oliger dissipation: r must be 1..5 (degree 2..10)";
+        return CFD_EUNSUPPORTED;
+    }
+    if (!(sigma >= 0) || !std::isfinite(sigma)) {
+        err = "Kreiss-Oliger dissipation: sigma must be finite and >= 0";
+        return CFD_EINVAL;
+    }
+    Scheme s;
+    s.d = 2 * r;
+    s.hpow = 1;
+    s.order = 2;
+    s.nl = 0;
+    s.m = r;
+    s.lhs[kMaxNL] = 1.0;
+    const double pre = -((r % 2) ? -1.0 : 1.0) * sigma / std::ldexp(1.0, 2 * r);
+    for (int n = -r; n <= r; ++n) {
+        double c = 1.0;   // C(2r, r+n)
+        for (int i = 1; i <= r + n; ++i) c = c * (2 * r - i + 1) / i;
+        const double sg = ((r - n) % 2) ? -1.0 : 1.0;
+        s.rhs[kMaxHalf + n] = pre * sg * c;
+    }
+    char nm[48];
+    std::snprintf(nm, sizeof nm, "KO%d[%g]", 2 * r, sigma);
+    s.name = nm;
+    out = s;
+    return CFD_OK;
+}
+
 cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &err) {
     std::string base = name, variant;
     size_t colon = name.find(':');

@@ -5,6 +5,7 @@ import numpy as np
 
 import synth
 from oracle import biased as OB
+from oracle import dissipation as ODS
 from oracle import lines as OL
 from oracle import schemes as OS
 
@@ -29,6 +30,20 @@ def biased_name(name):
     return None
 
 
+def ko_name(name):
+    """(r, sigma) for a Kreiss-Oliger operator named "KO<2r>[<sigma>]", else None."""
+    if name.startswith("KO") and "[" in name and name.endswith("]"):
+        deg, sig = name[2:-1].split("[")
+        return int(deg) // 2, float(sig)
+    return None
+
+
+def scheme_for(name):
+    import paper_2302_14858_amd as P
+    ko = ko_name(name)
+    return P.Scheme.dissipation(*ko) if ko else P.Scheme.named(name)
+
+
 def make_plan(wl, ops, dtype=0):
     import paper_2302_14858_amd as P
     schemes = {}
@@ -36,7 +51,7 @@ def make_plan(wl, ops, dtype=0):
     for op in ops:
         name = op[0]
         if name not in schemes:
-            schemes[name] = P.Scheme.named(name)
+            schemes[name] = scheme_for(name)
         pops.append((schemes[name], op[1], op[2] if len(op) > 2 else -1, op[3] if len(op) > 3 else -1))
     return P.Plan(block_dicts(wl), wl.nfields, pops, dtype=dtype)
 
@@ -46,6 +61,13 @@ def oracle_block_op(wl, b, op, f, out=None):
     blk = wl.blocks[b]
     d = op[1]
     per = blk.boundary[d] == synth.PERIODIC
+    ko = ko_name(op[0])
+    if ko is not None:
+        r = ODS.ko_block(wl.field_view(b, f), blk.ng, blk.h[d], d, ko[0], ko[1], periodic=per)
+        if out is not None:
+            out[...] = r
+            return out
+        return r
     bn = biased_name(op[0])
     if bn is None:
         return OL.apply_block(OS.named(op[0]), wl.field_view(b, f), blk.ng, blk.h[d], d, periodic=per, out=out)

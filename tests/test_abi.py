@@ -255,3 +255,33 @@ def test_taylor_scheme_rejects_bad_extents():
     with pytest.raises(P.CfdError) as e:
         P.cfd_taylor_scheme(1, 9, 9, [(0, 9, 9)])
     assert e.value.status == _lib.CFD_EINVAL
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5])
+def test_dissipation_stencil_matches_oracle(r):
+    """The library's Kreiss-Oliger stencil (binomial form) equals the oracle's repeated
+    differences (Eq. dissdef) on a unit impulse, scaled by h^-1."""
+    from oracle import dissipation as ODS
+    sigma = 0.04 * r
+    g = P.Scheme.dissipation(r, sigma).get()
+    assert g["nl"] == 0 and g["m"] == r and g["d"] == 2 * r
+    N = 2 * r + 1
+    imp = np.zeros(N + 2 * r)
+    imp[r + N // 2] = 1.0
+    q = ODS.ko_line(imp, r, 1.0, r, sigma)
+    ref = np.zeros(11)
+    for m in range(-r, r + 1):
+        ref[5 - m] = q[N // 2 + m]
+    assert np.max(np.abs(ref - g["rhs"])) <= 1e-15 * max(1.0, np.max(np.abs(ref)))
+    assert P.Scheme.dissipation(r, sigma).required_ghosts() == r
+
+
+def test_dissipation_rejects_bad_arguments():
+    for r, s in ((0, 0.1), (6, 0.1)):
+        with pytest.raises(P.CfdError) as e:
+            P.Scheme.dissipation(r, s)
+        assert e.value.status == _lib.CFD_EUNSUPPORTED
+    for s in (-0.1, float("nan"), float("inf")):
+        with pytest.raises(P.CfdError) as e:
+            P.Scheme.dissipation(4, s)
+        assert e.value.status == _lib.CFD_EINVAL
