@@ -224,12 +224,21 @@ typedef struct {
  * to every field (field = -1) or to one field index.  vel_field: for an
  * upwind pair of biased schemes (e.g. "(1)X2"), the field holding the
  * velocity c; the operator returns c d f with the bias chosen per node by the
- * sign of c (Eq. biasderapproxadv); -1 for every other scheme. */
+ * sign of c (Eq. biasderapproxadv); -1 for every other scheme.
+ * dir2: -1, or a second direction != dir: the operator is then the
+ * symmetrised mixed derivative 1/2 (D_dir[D_dir2[f]] + D_dir2[D_dir[f]]) of
+ * Sec. ssec:z4c with D the first-degree centred scheme `scheme` (block closure
+ * or periodic per direction).  On a closed direction i the inner derivative
+ * is taken on the lines through the block extended by its ng ghost layers
+ * along i (edge ghosts are read), so the outer one has its ghost values.  The
+ * plan computes both compositions into a scratch buffer it owns (about four
+ * times the operator's output) and averages them. */
 typedef struct {
     const cfd_scheme *scheme;
     int dir;
     int field;
     int vel_field;
+    int dir2;
 } cfd_op;
 
 typedef struct {

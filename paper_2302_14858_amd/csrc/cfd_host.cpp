@@ -94,6 +94,7 @@ struct Group {
     int64_t item0, nitems;
     int grid_persist;
     int qoff_index = -1;   // offset of this group's 9 queue bounds in d_qoff (XCD-aware mode)
+    int iomode = 0;        // buffers: 0 input -> output, 1 input -> scratch, 2 scratch -> scratch
 };
 
 struct TabKey {
@@ -144,6 +145,11 @@ struct cfd_plan {
     std::vector<BGroup> bgroups;
     int64_t nbitems = 0;
     DevBuf d_bpass, d_bitems, d_bcoef;
+    // symmetrised mixed derivatives: scratch (elements), combine segments
+    // (output offset, first-order result, second-order result, count)
+    int64_t mscr_elems = 0, mseg_max = 0;
+    std::vector<int64_t> msegs;
+    DevBuf d_mscr, d_msegs;
     std::vector<Group> groups;
     int64_t nitems = 0;
     hipStream_t cap_stream = nullptr;
@@ -185,6 +191,8 @@ struct cfd_plan {
         d_bpass.release();
         d_bitems.release();
         d_bcoef.release();
+        d_mscr.release();
+        d_msegs.release();
         release_iteration();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
@@ -390,7 +398,13 @@ std::vector<PassDesc> pass_descs(const cfd_plan *p, const std::vector<std::array
             tab[o] = pass_tab[i][o];
             hinv[o] = 1.0 / std::pow(b.h[ps.dir], scale_power(p->schemes[ps.sch[o]]));
         }
-        fill_pass_desc(pd[i], b, p->in_off[ps.block], ps, ob, tab, hinv);
+        if (ps.custom) {
+            pd[i] = ps.geom;
+            pd[i].tab[0] = tab[0];
+            pd[i].hinv[0] = hinv[0];
+        } else {
+            fill_pass_desc(pd[i], b, p->in_off[ps.block], ps, ob, tab, hinv);
+        }
     }
     return pd;
 }
@@ -642,7 +656,7 @@ cfd_status build_groups(cfd_plan *p) {
     //    passes together) so its input is re-read from cache rather than HBM.
     //    A group's LDS is the most any of its items needs.
     const size_t es = f32 ? 4 : 8;
-    std::map<std::pair<const void *, int>, int> gidx;
+    std::map<std::pair<const void *, int>, int> gidx;   // (kernel, sub-launch + 4 iomode)
     std::vector<std::vector<WorkItem>> gitems;
     std::vector<std::vector<int>> gbf;        // block-field of each item
     std::vector<std::vector<int64_t>> gcost;  // rows x lines of each item
@@ -665,7 +679,7 @@ cfd_status build_groups(cfd_plan *p) {
                 int sub = 0;
                 if (p->split_x && ps.dir == 0) sub = 1;
                 else if (p->split_x && p->concurrent && yz_lds_free) sub = 2;
-                auto key = std::make_pair(ps.cls->fn, sub);
+                auto key = std::make_pair(ps.cls->fn, sub + 4 * ps.iomode);
                 auto it = gidx.find(key);
                 int gi;
                 if (it == gidx.end()) {
@@ -674,6 +688,7 @@ cfd_status build_groups(cfd_plan *p) {
                     Group g;
                     g.fn = ps.cls->fn;
                     g.lds = 0;
+                    g.iomode = ps.iomode;
                     groups.push_back(g);
                     gitems.emplace_back();
                     gbf.emplace_back();
@@ -1039,6 +1054,11 @@ cfd_status launch_biased_groups(cfd_plan *p, const void *in, void *out, hipStrea
 
 cfd_status launch_group(cfd_plan *p, const Group &g, const void *in, void *out, hipStream_t st) {
     const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
+    if (g.iomode == 1) out = p->d_mscr.p;
+    if (g.iomode == 2) {
+        in = p->d_mscr.p;
+        out = p->d_mscr.p;
+    }
     hipError_t e;
     if (p->dtype == CFD_MIXED_BF16) {
         e = launch_dense_apply(g.fn, grid, st, (const unsigned char *)p->d_items.p + g.item0 * dense_item_size(),
@@ -1136,27 +1156,36 @@ cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
         cfd_status r = launch_biased_groups(p, in, out, st);
         if (r != CFD_OK) return r;
     }
-    std::vector<const Group *> act;
-    for (const Group &g : p->groups)
-        if (g.nitems > 0) act.push_back(&g);
-    if (p->concurrent && act.size() > 1 && p->aux.size() + 1 >= act.size() && p->ev.size() >= act.size()) {
-        // fork: every group after the first on its own stream, all ordered after
-        // the caller's earlier work; join: the caller's stream waits for all
-        HIPCHK(hipEventRecord(p->ev[0], st));
-        for (size_t i = 1; i < act.size(); ++i) {
-            HIPCHK(hipStreamWaitEvent(p->aux[i - 1], p->ev[0], 0));
-            cfd_status r = launch_group(p, *act[i], in, out, p->aux[i - 1]);
+    // stage 0: every group reading the input; stage 1: the second stage of the
+    // mixed derivatives (reads what stage 0 left in the scratch)
+    for (int stage = 0; stage < 2; ++stage) {
+        std::vector<const Group *> act;
+        for (const Group &g : p->groups)
+            if (g.nitems > 0 && (g.iomode == 2) == (stage == 1)) act.push_back(&g);
+        if (p->concurrent && act.size() > 1 && p->aux.size() + 1 >= act.size() && p->ev.size() >= act.size()) {
+            // fork: every group after the first on its own stream, all ordered after
+            // the caller's earlier work; join: the caller's stream waits for all
+            HIPCHK(hipEventRecord(p->ev[0], st));
+            for (size_t i = 1; i < act.size(); ++i) {
+                HIPCHK(hipStreamWaitEvent(p->aux[i - 1], p->ev[0], 0));
+                cfd_status r = launch_group(p, *act[i], in, out, p->aux[i - 1]);
+                if (r != CFD_OK) return r;
+                HIPCHK(hipEventRecord(p->ev[i], p->aux[i - 1]));
+            }
+            cfd_status r = launch_group(p, *act[0], in, out, st);
             if (r != CFD_OK) return r;
-            HIPCHK(hipEventRecord(p->ev[i], p->aux[i - 1]));
+            for (size_t i = 1; i < act.size(); ++i) HIPCHK(hipStreamWaitEvent(st, p->ev[i], 0));
+        } else {
+            for (const Group *g : act) {
+                cfd_status r = launch_group(p, *g, in, out, st);
+                if (r != CFD_OK) return r;
+            }
         }
-        cfd_status r = launch_group(p, *act[0], in, out, st);
-        if (r != CFD_OK) return r;
-        for (size_t i = 1; i < act.size(); ++i) HIPCHK(hipStreamWaitEvent(st, p->ev[i], 0));
-        return CFD_OK;
     }
-    for (const Group *g : act) {
-        cfd_status r = launch_group(p, *g, in, out, st);
-        if (r != CFD_OK) return r;
+    if (!p->msegs.empty()) {
+        hipError_t e = launch_mixed_combine(p->dtype != CFD_F64, (int)(p->msegs.size() / 4),
+                                            (const int64_t *)p->d_msegs.p, p->mseg_max, p->d_mscr.p, out, st);
+        if (e != hipSuccess) return hip_fail(e, "launching the mixed-derivative combine");
     }
     return CFD_OK;
 }
@@ -1379,6 +1408,15 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
         }
         if (s.kind == 1 && desc->dtype == CFD_MIXED_BF16)
             return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: biased schemes are not supported");
+        if (op.dir2 != -1) {
+            if (op.dir2 < 0 || op.dir2 > 2 || op.dir2 == op.dir)
+                return fail(CFD_EINVAL, "cfd_plan_create: dir2 must be -1 or a direction other than dir");
+            if (s.kind != 0 || s.d != 1 || scale_power(s) != 1)
+                return fail(CFD_EINVAL, "cfd_plan_create: a mixed derivative needs a centred first-degree scheme, not '" +
+                                            s.name + "'");
+            if (desc->dtype == CFD_MIXED_BF16)
+                return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: mixed derivatives are not supported");
+        }
         p->schemes.push_back(s);
     }
     int64_t slot = 0;
@@ -1410,9 +1448,11 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
         p->out_off.push_back(oo);
         in_cur = std::max(in_cur, io + in_n);
         out_cur = std::max(out_cur, oo + out_n);
-        for (size_t o = 0; o < p->ops.size(); ++o) {
+        for (size_t oo = 0; oo < 2 * p->ops.size(); ++oo) {
+            const size_t o = oo / 2;
+            if ((oo & 1) && p->ops[o].dir2 < 0) continue;   // second direction of a mixed derivative
             const Scheme &s = p->schemes[o];
-            const int d = p->ops[o].dir;
+            const int d = (oo & 1) ? p->ops[o].dir2 : p->ops[o].dir;
             const int per = bl.boundary[d] == CFD_BOUNDARY_PERIODIC;
             const int need = required_ghosts(s, per);
             if (bl.ng < need) {
@@ -1457,7 +1497,7 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
         for (int d = 0; d < 3; ++d) {
             std::vector<int> ops_d;
             for (size_t o = 0; o < p->ops.size(); ++o)
-                if (p->ops[o].dir == d && p->schemes[o].kind == 0) ops_d.push_back((int)o);
+                if (p->ops[o].dir == d && p->schemes[o].kind == 0 && p->ops[o].dir2 < 0) ops_d.push_back((int)o);
             std::vector<bool> used(p->ops.size(), false);
             for (int o : ops_d) {
                 if (used[o]) continue;
@@ -1513,6 +1553,106 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
             }
         }
     }
+    // symmetrised mixed derivatives: for each order (inner dj, outer di) a
+    // first-stage pass D_dj f -> scratch S over the block extended by its ghost
+    // layers along di (none if di is periodic), and a second-stage pass
+    // D_di S -> scratch T over the interior; the combine averages the two T.
+    {
+        int64_t scr = 0;
+        for (size_t b = 0; b < p->blocks.size(); ++b) {
+            const cfd_block &bl = p->blocks[b];
+            const int64_t ng = bl.ng;
+            const int64_t n[3] = {bl.n[0], bl.n[1], bl.n[2]};
+            const int64_t PX = n[0] + 2 * ng, PY = n[1] + 2 * ng, PZ = n[2] + 2 * ng;
+            const int64_t s_in[3] = {1, PX, PX * PY};
+            const int64_t s_int[3] = {1, n[0], n[0] * n[1]};
+            const int64_t npts = n[0] * n[1] * n[2];
+            for (size_t o = 0; o < p->ops.size(); ++o) {
+                const cfd_op &op = p->ops[o];
+                if (op.dir2 < 0) continue;
+                const Scheme &s = p->schemes[o];
+                const int nf = op.field < 0 ? p->nfields : 1, f0 = op.field < 0 ? 0 : op.field;
+                int64_t t_off[2];
+                for (int ord = 0; ord < 2; ++ord) {
+                    const int dj = ord == 0 ? op.dir2 : op.dir;   // inner derivative
+                    const int di = ord == 0 ? op.dir : op.dir2;   // outer derivative
+                    const int gi = bl.boundary[di] == CFD_BOUNDARY_PERIODIC ? 0 : bl.ng;
+                    int64_t e[3] = {n[0], n[1], n[2]};
+                    e[di] += 2 * gi;
+                    const int64_t ss[3] = {1, e[0], e[0] * e[1]};
+                    const int64_t ssize = e[0] * e[1] * e[2];
+                    const int64_t S0 = scr;
+                    scr += nf * ssize;
+                    const int64_t T0 = scr;
+                    scr += nf * npts;
+                    t_off[ord] = T0;
+                    for (int st = 1; st <= 2; ++st) {
+                        const int ld = (st == 1) ? dj : di;                 // line direction
+                        const int u = (ld == 0) ? 1 : 0, v = (ld == 2) ? 1 : 2;
+                        const bool per = bl.boundary[ld] == CFD_BOUNDARY_PERIODIC;
+                        PassHost ps;
+                        ps.block = (int)b;
+                        ps.dir = ld;
+                        ps.field0 = f0;
+                        ps.nfield = nf;
+                        ps.N = (int)n[ld];
+                        ps.ng = (st == 1) ? bl.ng : gi;
+                        ps.periodic = per;
+                        ps.nl = s.nl;
+                        ps.nops = 1;
+                        ps.op[0] = ps.sch[0] = (int)o;
+                        ps.par = 1;
+                        ps.mi = s.m;
+                        ps.hw = std::max(s.m, per ? 0 : s.mc);
+                        ps.iomode = st;
+                        ps.custom = true;
+                        PassDesc &q = ps.geom;
+                        std::memset(&q, 0, sizeof q);
+                        if (st == 1) {   // input block, lines along dj; u, v over di extended and the third
+                            q.in_base = p->in_off[b] + ng * (s_in[0] + s_in[1] + s_in[2]) - gi * s_in[di];
+                            q.in_fstride = PX * PY * PZ;
+                            q.su = (int32_t)s_in[u];
+                            q.sv = (int32_t)s_in[v];
+                            q.sd = (int32_t)s_in[ld];
+                            q.out_base[0] = S0;
+                            q.out_fstride = ssize;
+                            q.osu = (int32_t)ss[u];
+                            q.osv = (int32_t)ss[v];
+                            q.osd = (int32_t)ss[ld];
+                            q.nu = (int32_t)e[u];
+                            q.nlines = (int32_t)(e[u] * e[v]);
+                            q.field0 = f0;
+                        } else {         // S, lines along di over the interior; gi ghost layers along di
+                            q.in_base = S0 + gi * ss[di];
+                            q.in_fstride = ssize;
+                            q.su = (int32_t)ss[u];
+                            q.sv = (int32_t)ss[v];
+                            q.sd = (int32_t)ss[ld];
+                            q.out_base[0] = T0;
+                            q.out_fstride = npts;
+                            q.osu = (int32_t)s_int[u];
+                            q.osv = (int32_t)s_int[v];
+                            q.osd = (int32_t)s_int[ld];
+                            q.nu = (int32_t)n[u];
+                            q.nlines = (int32_t)(n[u] * n[v]);
+                            q.field0 = 0;
+                        }
+                        q.N = ps.N;
+                        q.ng = ps.ng;
+                        q.periodic = per;
+                        q.nfield_pass = nf;
+                        p->passes.push_back(ps);
+                    }
+                }
+                const int64_t oo = p->out_off[b] + p->op_slot[o] * npts;
+                p->msegs.insert(p->msegs.end(), {oo, t_off[0], t_off[1], nf * npts});
+                p->mseg_max = std::max(p->mseg_max, nf * npts);
+            }
+        }
+        p->mscr_elems = scr;
+        if (p->msegs.size() / 4 > 65535)
+            return fail(CFD_EUNSUPPORTED, "cfd_plan_create: more than 65535 block x mixed-derivative pairs");
+    }
     // the descriptor is valid; from here on the device is needed
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -1531,6 +1671,17 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
     }
     p->xcd_interleave_ok = xcd_dispatch_ok(p->device);
     cfd_status st = upload_layout(p.get());
+    if (st == CFD_OK && p->mscr_elems > 0) {
+        const size_t es = elem_size(p->dtype);
+        if (dmalloc(&p->d_mscr.p, (size_t)p->mscr_elems * es) != hipSuccess ||
+            dmalloc(&p->d_msegs.p, p->msegs.size() * sizeof(int64_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            st = fail(CFD_ENOMEM, "cfd_plan_create: allocating the mixed-derivative scratch");
+        } else if (hipMemcpy(p->d_msegs.p, p->msegs.data(), p->msegs.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice) != hipSuccess) {
+            st = fail(CFD_EDEVICE, "cfd_plan_create: uploading the mixed-derivative segments");
+        }
+    }
     if (st == CFD_OK) st = build_biased(p.get());
     if (st == CFD_OK) st = build(p.get());
     if (st != CFD_OK) {
@@ -1977,6 +2128,8 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: not available on the dense mixed-precision path");
     if (iterations > 0 && p->nbitems > 0)
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds biased operators");
+    if (iterations > 0 && !p->msegs.empty())
+        return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds mixed derivatives");
     const int c = 2;
     auto restore = [&]() {
         if (!p->base_schemes.empty()) p->schemes = p->base_schemes;

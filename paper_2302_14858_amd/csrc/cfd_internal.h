@@ -196,6 +196,13 @@ struct PassHost {
     int P = 0, L = 0, lcode = 0;
     int C = 1;            // x lines: column chunks the LDS tile is staged in (divides P)
     const LineClass *cls = nullptr;
+    // Passes of the symmetrised mixed derivatives read or write the plan's
+    // scratch buffer: iomode 0 input -> output, 1 input -> scratch (first
+    // stage), 2 scratch -> scratch (second stage, after the first).  Their
+    // strides and offsets are set explicitly (geom) instead of from the block.
+    int iomode = 0;
+    bool custom = false;
+    PassDesc geom{};
 };
 
 // Schedule helpers shared by plans and the allocation-free apply (cfd_host.cpp).
@@ -236,6 +243,9 @@ namespace cfd {
 hipError_t launch_halo(int f32, void *data, const int64_t *off_dev, int nx, int ny, int nz, int ng, int nfields,
                        int bx, int by, int bz, hipStream_t st);
 hipError_t launch_axpby(int f32, int64_t n, double a, const void *x, double b, void *y, hipStream_t st);
+// out[o + e] = (a[ta + e] + b[tb + e]) / 2 for each segment (o, ta, tb, n); a and b in scr
+hipError_t launch_mixed_combine(int f32, int nseg, const int64_t *segs, int64_t max_n, const void *scr, void *out,
+                                hipStream_t st);
 hipError_t launch_xpcy(int f32, int64_t n, const void *x, double c, const void *y, void *z, hipStream_t st);
 hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *stage, const void *acc_in, void *acc,
                              const void *d, const int64_t *in_off, const int64_t *out_off, const int *shapes,

@@ -6,6 +6,7 @@ import numpy as np
 import synth
 from oracle import biased as OB
 from oracle import dissipation as ODS
+from oracle import mixed as OM
 from oracle import lines as OL
 from oracle import schemes as OS
 
@@ -52,7 +53,8 @@ def make_plan(wl, ops, dtype=0):
         name = op[0]
         if name not in schemes:
             schemes[name] = scheme_for(name)
-        pops.append((schemes[name], op[1], op[2] if len(op) > 2 else -1, op[3] if len(op) > 3 else -1))
+        pops.append((schemes[name], op[1], op[2] if len(op) > 2 else -1, op[3] if len(op) > 3 else -1,
+                     op[4] if len(op) > 4 else -1))
     return P.Plan(block_dicts(wl), wl.nfields, pops, dtype=dtype)
 
 
@@ -64,6 +66,13 @@ def oracle_block_op(wl, b, op, f, out=None):
     ko = ko_name(op[0])
     if ko is not None:
         r = ODS.ko_block(wl.field_view(b, f), blk.ng, blk.h[d], d, ko[0], ko[1], periodic=per)
+        if out is not None:
+            out[...] = r
+            return out
+        return r
+    if len(op) > 4 and op[4] >= 0:     # symmetrised mixed derivative along op[1], op[4]
+        r = OM.mixed_block(OS.named(op[0]), wl.field_view(b, f), blk.ng, blk.h,
+                           tuple(bd == synth.PERIODIC for bd in blk.boundary), d, op[4])
         if out is not None:
             out[...] = r
             return out
