@@ -10,7 +10,9 @@ Prints one JSON line: derivative evaluations per second (interior points x
 fields x (direction, order) pairs), the roofline of the line kernels against
 HBM bandwidth, and the oracle's CPU throughput on a bounded sample.  Under
 "extra": the same step in FP32, one 128^3 block with closures (tridiagonal
-D1+D2), the periodic 256^3 precision study (banded FP64 / banded FP32 / dense
+D1+D2), the shift-advection term with the biased X_2 upwind pair and the
+Kreiss-Oliger / mixed-derivative part of the Z4c derivative set on the same
+blocks, the periodic 256^3 precision study (banded FP64 / banded FP32 / dense
 mixed BF16 with FP64 residual refinement, each with its error against the
 oracle) and the RK4 wave evolution on a periodic 192^3 grid.
 """
@@ -207,6 +209,50 @@ def extra_upwind64(steps, warmup, autotune):
     return out
 
 
+OPS_KO = [("KO8[0.04]", 0), ("KO8[0.04]", 1), ("KO8[0.04]", 2)]
+OPS_MIXED = [("(1)QP_O8[1]", 0, -1, -1, 1), ("(1)QP_O8[1]", 0, -1, -1, 2), ("(1)QP_O8[1]", 1, -1, -1, 2)]
+
+
+def mixed_algorithmic_bytes(wl, esize):
+    """The three mixed pairs: every field read once with its face ghosts in all three directions
+    and the edge ghosts of each pair (4 ng^2 per unit length of the third direction), one output
+    per pair written."""
+    rd = wr = 0
+    for b in wl.blocks:
+        nx, ny, nz = b.n
+        n3 = nx * ny * nz
+        g = b.ng
+        faces = 2 * g * (ny * nz + nx * nz + nx * ny)
+        edges = 4 * g * g * (nz + ny + nx)
+        rd += wl.nfields * (n3 + faces + edges)
+        wr += 3 * wl.nfields * n3
+    return (rd + wr) * esize
+
+
+def extra_z4c64(steps, warmup, autotune):
+    """batch64 blocks (ng = 5), 22 fields: Kreiss-Oliger Q^(8) (sigma = 0.04) along x, y, z, and
+    the symmetrised mixed derivatives d_x d_y, d_x d_z, d_y d_z with (1)QP_O8[1], FP64."""
+    import torch
+    import synth
+    import paper_2302_14858_amd as P
+    wl = synth.batch64()
+    out = {"workload": "z4c64: batch64 blocks (extents from {16,24,32,48}^3, ng=5), 22 fields; 'ko8': "
+                       "Kreiss-Oliger Q^(8), sigma=0.04, along x,y,z; 'mixed': 1/2 (D_i D_j + D_j D_i), "
+                       "(1)QP_O8[1], pairs xy, xz, yz; FP64"}
+    for label, ops in (("ko8", OPS_KO), ("mixed", OPS_MIXED)):
+        plan, x, y, ms, _, launches, items = run_gpu(wl, ops, P.CFD_F64, steps, warmup, autotune=autotune)
+        evals = wl.interior_points * wl.nfields * len(ops)
+        alg = algorithmic_bytes(wl, ops, 8)[0] if label == "ko8" else mixed_algorithmic_bytes(wl, 8)
+        ref = oracle_reference(plan, wl, ops)
+        out[label] = {"ms_per_step": ms, "value": evals / (ms * 1e-3), "unit": "evals/s",
+                      "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "kernel_launches_per_step": launches,
+                      "err_vs_oracle": err_vs_oracle(plan, y, wl, ops, ref), "err_scope": "every output node"}
+        del plan, x, y, ref
+        torch.cuda.empty_cache()
+    return out
+
+
 def extra_periodic256(steps, warmup, autotune):
     """Periodic 256^3 x 8 fields, tridiagonal D1 along x, y, z: banded FP64, banded FP32, dense mixed."""
     import torch
@@ -301,7 +347,7 @@ def main():
                     help="set the batch64 launch shape by hand (a set of CFD_SCHED_* bits) instead of autotuning")
     ap.add_argument("--parts", default="",
                     help="with --flags: partitions per class as N:xlines:P,... (as printed in config.schedule)")
-    ap.add_argument("--only", choices=["block128", "periodic256", "wave192", "upwind64"], default=None,
+    ap.add_argument("--only", choices=["block128", "periodic256", "wave192", "upwind64", "z4c64"], default=None,
                     help="run just one of the other workloads and print its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -316,6 +362,8 @@ def main():
             r = extra_periodic256(min(args.steps, 20), args.warmup, not args.no_autotune)
         elif args.only == "upwind64":
             r = extra_upwind64(args.steps, args.warmup, not args.no_autotune)
+        elif args.only == "z4c64":
+            r = extra_z4c64(args.steps, args.warmup, not args.no_autotune)
         else:
             r = extra_wave192()
         print(json.dumps({args.only: r}), flush=True)
@@ -387,6 +435,8 @@ def main():
         result["extra"]["block128_ng3"] = extra_block128(args.steps, args.warmup, not args.no_autotune, ng=3)
         print("bench: upwind64 shift advection", file=sys.stderr, flush=True)
         result["extra"]["upwind64"] = extra_upwind64(args.steps, args.warmup, not args.no_autotune)
+        print("bench: z4c64 dissipation and mixed derivatives", file=sys.stderr, flush=True)
+        result["extra"]["z4c64"] = extra_z4c64(args.steps, args.warmup, not args.no_autotune)
         print("bench: periodic256 precision study", file=sys.stderr, flush=True)
         result["extra"]["periodic256"] = extra_periodic256(min(args.steps, 20), args.warmup, not args.no_autotune)
         print("bench: wave192 RK4", file=sys.stderr, flush=True)

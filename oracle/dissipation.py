@@ -19,13 +19,24 @@ import numpy as np
 
 
 def _dminus(v: np.ndarray, lo: int, h: float):
-    """D_- on samples v of nodes lo, lo+1, ...: defined from node lo+1 on."""
-    return (v[1:] - v[:-1]) / h, lo + 1
+    """D_- along the last axis on samples of nodes lo, lo+1, ...: defined from node lo+1 on."""
+    return (v[..., 1:] - v[..., :-1]) / h, lo + 1
 
 
 def _dplus(v: np.ndarray, lo: int, h: float):
-    """D_+ on samples v of nodes lo, lo+1, ...: defined up to the last node but one."""
-    return (v[1:] - v[:-1]) / h, lo
+    """D_+ along the last axis on samples of nodes lo, lo+1, ...: defined up to the last node but one."""
+    return (v[..., 1:] - v[..., :-1]) / h, lo
+
+
+def _ko_lines(v: np.ndarray, N: int, h: float, r: int, sigma: float) -> np.ndarray:
+    """Q^(2r) on lines stored along the last axis as nodes -r .. N+r-1."""
+    lo = -r
+    for _ in range(r):
+        v, lo = _dminus(v, lo, h)
+    for _ in range(r):
+        v, lo = _dplus(v, lo, h)
+    assert lo == 0 and v.shape[-1] == N, (lo, v.shape, N)
+    return -((-1) ** r) / 2 ** (2 * r) * sigma * h ** (2 * r - 1) * v
 
 
 def ko_line(g: np.ndarray, ng: int, h: float, r: int, sigma: float, periodic: bool = False) -> np.ndarray:
@@ -34,26 +45,18 @@ def ko_line(g: np.ndarray, ng: int, h: float, r: int, sigma: float, periodic: bo
     g = np.asarray(g, dtype=np.float64)
     if periodic:
         N = g.size
-        v = g[np.arange(-r, N + r) % N]
-        lo = -r
-    else:
-        if ng < r:
-            raise ValueError(f"Kreiss-Oliger of degree {2 * r} needs {r} ghost layers, line has {ng}")
-        N = g.size - 2 * ng
-        v = g[ng - r: ng + N + r]
-        lo = -r
-    for _ in range(r):
-        v, lo = _dminus(v, lo, h)
-    for _ in range(r):
-        v, lo = _dplus(v, lo, h)
-    assert lo == 0 and v.size == N, (lo, v.size, N)
-    return -((-1) ** r) / 2 ** (2 * r) * sigma * h ** (2 * r - 1) * v
+        return _ko_lines(g[np.arange(-r, N + r) % N], N, h, r, sigma)
+    if ng < r:
+        raise ValueError(f"Kreiss-Oliger of degree {2 * r} needs {r} ghost layers, line has {ng}")
+    N = g.size - 2 * ng
+    return _ko_lines(g[ng - r: ng + N + r], N, h, r, sigma)
 
 
 def ko_block(f: np.ndarray, ng: int, h: float, direction: int, r: int, sigma: float,
              periodic: bool = False) -> np.ndarray:
     """Q^(2r) along ``direction`` (0=x, 1=y, 2=z) of one block-field [z][y][x] with ng
-    ghosts on every side; returns the interior [z][y][x]."""
+    ghosts on every side; returns the interior [z][y][x].  Every line of the block is
+    differenced at once along the last axis."""
     f = np.asarray(f, dtype=np.float64)
     nz, ny, nx = (e - 2 * ng for e in f.shape)
     ax = 2 - direction
@@ -62,8 +65,10 @@ def ko_block(f: np.ndarray, ng: int, h: float, direction: int, r: int, sigma: fl
     del sl[ax]
     g = g[tuple(sl)]
     N = (nx, ny, nz)[direction]
-    out = np.empty(g.shape[:-1] + (N,))
-    for idx in np.ndindex(*g.shape[:-1]):
-        line = g[idx]
-        out[idx] = ko_line(line[ng:ng + N] if periodic else line, ng, h, r, sigma, periodic)
-    return np.moveaxis(out, -1, ax)
+    if periodic:
+        v = g[..., ng + (np.arange(-r, N + r) % N)]
+    else:
+        if ng < r:
+            raise ValueError(f"Kreiss-Oliger of degree {2 * r} needs {r} ghost layers, block has {ng}")
+        v = g[..., ng - r: ng + N + r]
+    return np.moveaxis(_ko_lines(v, N, h, r, sigma), -1, ax)
