@@ -330,7 +330,8 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
                              const char *cache_path);
 
 /* Choose the schedule by hand: lines of length N along x (xlines = 1) or along
- * y/z (xlines = 0) are cut into `partitions` partitions (1, 2 or 4; 0 restores
+ * y/z (xlines = 0) are cut into `partitions` partitions (1, 2, 4, or 8 where a
+ * class with 8-wave workgroups is compiled for the band; 0 restores
  * the default); flags is a set of CFD_SCHED_*.  N = 0 only sets the flags.
  * CFD_EINVAL if no compiled kernel fits.  Invalidates a captured graph. */
 cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions, int flags);

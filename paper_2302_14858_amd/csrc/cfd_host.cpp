@@ -95,6 +95,7 @@ struct Group {
     int grid_persist;
     int qoff_index = -1;   // offset of this group's 9 queue bounds in d_qoff (XCD-aware mode)
     int iomode = 0;        // buffers: 0 input -> output, 1 input -> scratch, 2 scratch -> scratch
+    int wg = 4;            // wavefronts per workgroup of the kernel class
 };
 
 struct TabKey {
@@ -207,16 +208,18 @@ namespace cfd {
 
 // Exchange-area bytes an item needs: partition coupling (P > 1) or the
 // periodic wrap; none for a single-partition closure line.  Same layout as
-// the kernel's (4/P line groups x operators x 64 lanes x (2 nl P | 1)).
+// the kernel's (waves_for(P) / P line groups x operators x 64 lanes x
+// (2 nl P | 1)).
 size_t exch_bytes(int nl, int nops, int P, bool periodic, size_t es) {
     if (nl <= 0 || (P <= 1 && !periodic)) return 0;
-    return (size_t)(4 / P) * nops * kWave * (size_t)((2 * nl * P) | 1) * es;
+    return (size_t)(waves_for(P) / P) * nops * kWave * (size_t)((2 * nl * P) | 1) * es;
 }
 
-// Tile bytes an x item with P partitions of L rows needs in LDS: 64 (4/P)
-// lines by the columns of one chunk (P/C partitions plus the halo).
+// Tile bytes an x item with P partitions of L rows needs in LDS: 64
+// (waves_for(P) / P) lines by the columns of one chunk (P/C partitions plus
+// the halo).
 size_t x_tile_bytes(int P, int L, int hw, size_t es, int C) {
-    return (size_t)(kWave * 4 / P) * (size_t)((P / C * L + 2 * hw) | 1) * es;
+    return (size_t)(kWave * waves_for(P) / P) * (size_t)((P / C * L + 2 * hw) | 1) * es;
 }
 
 // Column chunks for x lines: the fewest (dividing P) that keep tile and
@@ -245,7 +248,7 @@ int x_chunks(int P, int L, int hw, size_t es, size_t exch) {
 // nodes): the kernel loads it without bounds checks.
 int partition_length(const PassHost &ps, bool f32, int P) {
     int Ls[16];
-    const int n = line_class_Ls(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, Ls, 16, ps.ext);
+    const int n = line_class_Ls(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, Ls, 16, ps.ext, waves_for(P));
     int best = 0;
     for (int i = 0; i < n; ++i) {
         const int L = Ls[i];
@@ -255,7 +258,7 @@ int partition_length(const PassHost &ps, bool f32, int P) {
         if ((P - 1) * L > ps.N - ps.nl) continue;   // every right-closure row in the last partition
         if (P > 1 && (P - 1) * L >= ps.N) continue;                            // no empty partition
         if (!ps.periodic && P > 1 && ps.dir != 0) {
-            const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L, ps.ext);
+            const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L, ps.ext, waves_for(P));
             if (!k || (P - 1) * L + k->hw > ps.N + ps.ng) continue;
         }
         if (!best || L < best) best = L;
@@ -267,13 +270,13 @@ int partition_length(const PassHost &ps, bool f32, int P) {
 // how many.  A candidate needs a compiled class with a fitting L, and (x
 // lines) an LDS tile that fits next to the exchange area.  No heap use (the
 // allocation-free apply calls this too).
-int candidate_Ps(const PassHost &ps, bool f32, size_t max_lds, int out[3]) {
-    int ok[3], Lok[3], n = 0;
+int candidate_Ps(const PassHost &ps, bool f32, size_t max_lds, int out[4]) {
+    int ok[4], Lok[4], n = 0;
     const size_t es = f32 ? 4 : 8;
-    for (int P = 1; P <= 4; P *= 2) {
+    for (int P = 1; P <= 8; P *= 2) {
         const int L = partition_length(ps, f32, P);
         if (!L) continue;
-        const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L, ps.ext);
+        const LineClass *k = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, L, ps.ext, waves_for(P));
         if (!k) continue;
         if (ps.periodic && k->hw > ps.N) continue;
         size_t lds = exch_bytes(ps.nl, ps.nops, P, ps.periodic, es);
@@ -296,7 +299,7 @@ int candidate_Ps(const PassHost &ps, bool f32, size_t max_lds, int out[3]) {
 }
 
 std::vector<int> candidate_Ps(const PassHost &ps, bool f32, size_t max_lds) {
-    int c[3];
+    int c[4];
     const int n = candidate_Ps(ps, f32, max_lds, c);
     return std::vector<int>(c, c + n);
 }
@@ -358,7 +361,7 @@ void fill_coef_block(double *cb, const Scheme &s) {
 void place_pass(PassHost &ps, bool f32, int P) {
     ps.P = P;
     ps.L = partition_length(ps, f32, P);
-    ps.cls = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, ps.L, ps.ext);
+    ps.cls = find_line_class(f32, ps.nl, ps.nops, ps.par, ps.mi, ps.hw, ps.L, ps.ext, waves_for(P));
     ps.lcode = 0;
     for (int j = 0; j < ps.cls->nL; ++j)
         if (ps.cls->Ls[j] == ps.L) ps.lcode = j;
@@ -687,6 +690,7 @@ cfd_status build_groups(cfd_plan *p) {
                     gidx[key] = gi;
                     Group g;
                     g.fn = ps.cls->fn;
+                    g.wg = ps.cls->wg;
                     g.lds = 0;
                     g.iomode = ps.iomode;
                     groups.push_back(g);
@@ -697,7 +701,7 @@ cfd_status build_groups(cfd_plan *p) {
                     gi = it->second;
                 }
                 groups[gi].lds = std::max(groups[gi].lds, lds);
-                const int per_item = kWave * (4 / ps.P);
+                const int per_item = kWave * (waves_for(ps.P) / ps.P);
                 const int meta = ps.P | (ps.lcode << 4) | ((ps.C - 1) << 8);
                 for (int l0 = 0; l0 < pd[i].nlines; l0 += per_item) {
                     gitems[gi].push_back(WorkItem{(int32_t)i, f - ps.field0, l0, meta});
@@ -732,7 +736,7 @@ cfd_status build_groups(cfd_plan *p) {
         g.item0 = (int64_t)items.size();
         g.nitems = (int64_t)gitems[gi].size();
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, g.fn, kWave * 4, g.lds) != hipSuccess || nb < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, g.fn, kWave * g.wg, g.lds) != hipSuccess || nb < 1)
             nb = 1;
         (void)hipGetLastError();
         g.grid_persist = (int)std::min<int64_t>(g.nitems, (int64_t)nb * p->cus);
@@ -1067,7 +1071,7 @@ cfd_status launch_group(cfd_plan *p, const Group &g, const void *in, void *out, 
     } else {
         const void *tabs = (p->dtype == CFD_F64) ? p->d_tab64.p : p->d_tab32.p;
         const int *qoff = (g.qoff_index >= 0) ? (const int *)p->d_qoff.p + g.qoff_index : nullptr;
-        e = launch_lines(g.fn, grid, g.lds, st, (const WorkItem *)p->d_items.p + g.item0, (int)g.nitems, qoff,
+        e = launch_lines(g.fn, g.wg, grid, g.lds, st, (const WorkItem *)p->d_items.p + g.item0, (int)g.nitems, qoff,
                          (const PassDesc *)p->d_pass.p, tabs, (const int64_t *)p->d_taboff.p, in, out,
                          p->iter_n > 0 ? p->d_ev.p : nullptr);
     }
@@ -1841,7 +1845,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     }
     auto keyof = [&](const std::tuple<int, int, int, int> &k) {
         std::ostringstream s;
-        s << "v4:" << arch << ":" << dt << ":N" << std::get<0>(k) << ":x" << std::get<1>(k) << ":nl" << std::get<2>(k)
+        s << "v5:" << arch << ":" << dt << ":N" << std::get<0>(k) << ":x" << std::get<1>(k) << ":nl" << std::get<2>(k)
           << ":ops" << std::get<3>(k);
         return s.str();
     };
@@ -1913,7 +1917,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         p->sched_P.clear();
         if (which == 0) return;
         for (const PassHost &ps : p->passes) {
-            int c[3];
+            int c[4];
             const int n = candidate_Ps(ps, f32, p->max_lds, c);
             const int cap = ps.dir == 0 ? 12 : 16;
             int pick = 0;

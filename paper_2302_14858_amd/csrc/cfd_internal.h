@@ -160,7 +160,7 @@ struct BiasItem {
     int32_t pass, field, line0, P;
 };
 
-// One work item: 64 * (4 / P) lines of one field of one pass.
+// One work item: 64 * (waves_for(P) / P) lines of one field of one pass.
 // meta: P (partitions per line) in bits 0..3, index of L in the kernel's
 // compiled set in bits 4..7, x lines: column chunks C - 1 in bits 8..9.
 struct WorkItem {
@@ -211,7 +211,7 @@ size_t x_tile_bytes(int P, int L, int hw, size_t es, int C = 1);
 bool chunked(const LineClass *k);
 int x_chunks(int P, int L, int hw, size_t es, size_t exch);
 int partition_length(const PassHost &ps, bool f32, int P);
-int candidate_Ps(const PassHost &ps, bool f32, size_t max_lds, int out[3]);
+int candidate_Ps(const PassHost &ps, bool f32, size_t max_lds, int out[4]);
 void fill_pass_desc(PassDesc &q, const cfd_block &b, int64_t in_off, const PassHost &ps, const int64_t out_base[2],
                     const int tab[2], const double hinv[2]);
 void place_pass(PassHost &ps, bool f32, int P);
@@ -219,9 +219,13 @@ void fill_coef_block(double *cb, const Scheme &s);
 cfd_status set_error(cfd_status st, const std::string &msg);   // message for cfd_last_error
 size_t pass_lds(const PassHost &ps, bool f32);
 
-const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext = 0);
-int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap, int ext = 0);
-hipError_t launch_lines(const void *fn, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
+// Wavefronts per workgroup of the kernel class that runs items of P
+// partitions: 4 for P = 1, 2, 4 (4 / P groups of 64 lines), 8 for P = 8.
+inline int waves_for(int P) { return P > 4 ? 8 : 4; }
+const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext, int wg);
+// partition lengths compiled for the class parameters; wg = 0: any workgroup size
+int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap, int ext = 0, int wg = 0);
+hipError_t launch_lines(const void *fn, int wg, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
                         const int *qoff, const PassDesc *passes, const void *tabs, const int64_t *taboff,
                         const void *in, void *out, const void *ev = nullptr);
 hipError_t launch_build_tables(int ntab, const void *specs, double *data, double *scratch, int64_t scratch_per,

@@ -245,13 +245,14 @@ const LineClass kLineClassesF64[] = { CFD_LINE_CLASSES(double, 0) };
 extern const LineClass kLineClassesF32[];
 extern const int kNumLineClassesF32;
 
-const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext) {
+const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext, int wg) {
     const LineClass *tab = f32 ? kLineClassesF32 : kLineClassesF64;
     const int n = f32 ? kNumLineClassesF32 : (int)(sizeof(kLineClassesF64) / sizeof(kLineClassesF64[0]));
     const LineClass *best = nullptr;
     for (int i = 0; i < n; ++i) {
         const LineClass &k = tab[i];
         if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw || k.ext != ext) continue;
+        if (k.wg != wg) continue;
         bool hasL = false;
         for (int j = 0; j < k.nL; ++j) hasL |= (k.Ls[j] == L);
         if (!hasL) continue;
@@ -262,13 +263,14 @@ const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int
     return best;
 }
 
-int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap, int ext) {
+int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap, int ext, int wg) {
     const LineClass *tab = f32 ? kLineClassesF32 : kLineClassesF64;
     const int n = f32 ? kNumLineClassesF32 : (int)(sizeof(kLineClassesF64) / sizeof(kLineClassesF64[0]));
     int cnt = 0;
     for (int i = 0; i < n; ++i) {
         const LineClass &k = tab[i];
         if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw || k.ext != ext) continue;
+        if (wg && k.wg != wg) continue;
         for (int j = 0; j < k.nL; ++j) {
             bool seen = false;
             for (int q = 0; q < cnt; ++q) seen |= (Ls[q] == k.Ls[j]);
@@ -278,12 +280,12 @@ int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, i
     return cnt;
 }
 
-hipError_t launch_lines(const void *fn, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
+hipError_t launch_lines(const void *fn, int wg, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
                         const int *qoff, const PassDesc *passes, const void *tabs, const int64_t *taboff,
                         const void *in, void *out, const void *ev) {
     void *args[] = {(void *)&items, (void *)&nitems, (void *)&qoff, (void *)&passes, (void *)&tabs,
                     (void *)&taboff, (void *)&in, (void *)&out, (void *)&ev};
-    return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWGW), args, lds, st);
+    return hipLaunchKernel(fn, dim3(grid), dim3(64 * wg), args, lds, st);
 }
 
 hipError_t launch_build_tables(int ntab, const void *specs, double *data, double *scratch, int64_t scratch_per,

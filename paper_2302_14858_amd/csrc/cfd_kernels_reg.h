@@ -15,14 +15,18 @@ struct LineClass {
     int Ls[8];
     const void *fn;
     int ext;      // adds the end-value terms of an iterated closure
+    int wg;       // wavefronts per workgroup: 4 (P = 1, 2, 4) or 8 (P = 8)
 };
 
 #define CFD_LC(T, NL, NOPS, PAR, MI, HW, ...)                                                        \
     LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
-              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, false, __VA_ARGS__>), 0}
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, false, 4, __VA_ARGS__>), 0, 4}
+#define CFD_LC8(T, NL, NOPS, PAR, MI, HW, ...)                                                       \
+    LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, false, 8, __VA_ARGS__>), 0, 8}
 #define CFD_LC_EXT(T, NL, NOPS, PAR, MI, HW, ...)                                                    \
     LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
-              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, true, __VA_ARGS__>), 1}
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, true, 4, __VA_ARGS__>), 1, 4}
 
 // The classes compiled for each precision.
 #define CFD_LINE_CLASSES(T, F32)                                                  \
@@ -47,11 +51,17 @@ struct LineClass {
     /* explicit schemes */                                                        \
     CFD_LC(T, 0, 1, 1, 5, 5, 8, 12, 16, 24, 32),                                  \
     CFD_LC(T, 0, 1, 0, 5, 5, 8, 12, 16, 24, 32),                                  \
+    /* long lines in 8 partitions (8-wave workgroups): tridiagonal first +     */ \
+    /* second derivative (16-row partitions alone keep 4 waves per SIMD) and   */ \
+    /* first derivative, partitions of 16..32 rows                             */ \
+    CFD_LC8(T, 1, 2, 1, 3, 4, 16),                                                \
+    CFD_LC8(T, 1, 2, 1, 3, 4, 16, 24, 32),                                        \
+    CFD_LC8(T, 1, 1, 1, 3, 4, 16, 24, 32),                                        \
     /* iterated closures of tridiagonal schemes (hybrid closure iteration) */    \
     CFD_LC_EXT(T, 1, 2, 1, 3, 4, 8, 12, 16),                                      \
     CFD_LC_EXT(T, 1, 1, 1, 3, 4, 8, 12, 16, 24, 32),                              \
     CFD_LC_EXT(T, 1, 1, 0, 5, 5, 8, 12, 16, 24, 32)
 
-const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext);
+const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext, int wg);
 
 }  // namespace cfd

@@ -37,19 +37,13 @@
 
 namespace cfd {
 
-constexpr int kWGW = 4;   // wavefronts per workgroup
 constexpr int kXCD = 8;   // accelerator complex dies (each with its own L2)
 
-
-// Exchange elements (of T) an item with P partitions uses for partition
-// coupling or the periodic wrap: (4/P) line groups x NOPS x 64 lanes x
-// ((2 NL P) | 1); a single-partition closure line uses none.  x items share
-// the area with their tile: the exchange runs after every lane has read its
-// inputs from the tile and before the results are staged back into it.
-template <int NL, int NOPS>
-__device__ __forceinline__ int exch_elems_for(int P, bool periodic) {
-    return (NL > 0 && (P > 1 || periodic)) ? (kWGW / P) * NOPS * 64 * ((2 * NL * P) | 1) : 0;
-}
+// Wavefronts per workgroup: a class is compiled for WG = 4 (items of P = 1, 2
+// or 4 partitions, 4 / P groups of 64 lines) or WG = 8 (items of P = 8
+// partitions, one group of 64 lines).  x items share the exchange area with
+// their tile: the exchange runs after every lane has read its inputs from the
+// tile and before the results are staged back into it.
 
 // Derivatives are written once and not read again by this launch: streaming
 // (non-temporal) stores keep them from evicting the input lines that the other
@@ -276,10 +270,10 @@ __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS
 // RPP = 256 / CW rows per pass: its line advances by RPP per pass without a
 // division, and the loads of BATCH passes are in flight together before their
 // LDS writes.  W is even (partition lengths and 2 HW are).
-template <typename T, int HW>
+template <typename T, int HW, int WG>
 __device__ __forceinline__ void stage_x(const PassDesc &pd, const T *base, int line0, int nrows, int n0, int W,
                                         T *tile, int tpitch, bool periodic) {
-    constexpr int NT = 64 * kWGW;
+    constexpr int NT = 64 * WG;
     constexpr int BATCH = 8;
     const int N = pd.N, ng = pd.ng;
     const int CW = W >> 1;
@@ -333,9 +327,9 @@ __device__ __forceinline__ void stage_x(const PassDesc &pd, const T *base, int l
 // opitch, ncols columns) to the interior output rows of length N:
 // consecutive x-lines of one field are consecutive rows of the output.
 // Thread tid owns node pair tid % CO of rows tid / CO + k * RPP.
-template <typename T>
+template <typename T, int WG>
 __device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N, int ncols, int opitch) {
-    constexpr int NT = 64 * kWGW;
+    constexpr int NT = 64 * WG;
     const int CO = (ncols + 1) >> 1;
     const int RPP = NT / CO;
     const int tid = threadIdx.x;
@@ -353,7 +347,7 @@ __device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N,
 }
 
 // Item body for one compiled partition length L.
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool PAD, bool CHK, bool EXT>
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool PAD, bool CHK, bool EXT, int WG>
 __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *out, bool xdir, bool active,
                                          int lu, int lv) {
     const PassDesc &pd = *c.pd;
@@ -361,7 +355,7 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
     if (xdir) {
         // the tile holds one column chunk (P/C partitions and the halo) at a
         // time: stage it, the waves of that chunk read their inputs, next chunk
-        const int nsub = kWGW / c.P;
+        const int nsub = WG / c.P;
         const int nrows_all = nsub * 64;
         const int N = pd.N;
         const int C = CHK ? c.C : 1;
@@ -370,8 +364,8 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
         if constexpr (CHK) {   // classes with long partitions: any number of chunks
             for (int ch = 0; ch < C; ++ch) {
                 if (ch > 0) __syncthreads();   // the previous chunk's readers are done
-                stage_x<T, HW>(pd, c.fbase, c.line0, nrows_all, ch * PC * L - HW, PC * L + 2 * HW, c.tile,
-                               c.tpitch, c.periodic);
+                stage_x<T, HW, WG>(pd, c.fbase, c.line0, nrows_all, ch * PC * L - HW, PC * L + 2 * HW, c.tile,
+                                   c.tpitch, c.periodic);
                 __syncthreads();
                 if (c.chunk == ch) {
                     const int k0 = (c.p - ch * PC) * L;
@@ -405,7 +399,7 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
                     __syncthreads();
                     const int col0 = ch * PC * L;
                     const int ncols = min(N - col0, PC * L);
-                    if (ncols > 0) store_x(dst + col0, c.tile, nrows, N, ncols, opitch);
+                    if (ncols > 0) store_x<T, WG>(dst + col0, c.tile, nrows, N, ncols, opitch);
                 }
             }
         } else {
@@ -420,7 +414,7 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
                 T *dst = out + pd.out_base[o] + (int64_t)wi.field * pd.out_fstride + (int64_t)wi.line0 * N;
                 int nrows = pd.nlines - wi.line0;
                 if (nrows > nrows_all) nrows = nrows_all;
-                store_x(dst, c.tile, nrows, N, N, opitch);
+                store_x<T, WG>(dst, c.tile, nrows, N, N, opitch);
             }
         }
     } else {
@@ -449,18 +443,18 @@ struct LSet {
     static constexpr int n = sizeof...(Ls);
 };
 
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool CHK, bool EXT, int L0, int... Ls>
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool CHK, bool EXT, int WG, int L0, int... Ls>
 __device__ __forceinline__ void dispatch_L(int lcode, bool pad, LineCtx<T> &c, const WorkItem &wi, T *out,
                                            bool xdir, bool active, int lu, int lv) {
     if (lcode == 0) {
         if (pad)
-            run_item<T, NL, NOPS, PAR, MI, HW, L0, true, CHK, EXT>(c, wi, out, xdir, active, lu, lv);
+            run_item<T, NL, NOPS, PAR, MI, HW, L0, true, CHK, EXT, WG>(c, wi, out, xdir, active, lu, lv);
         else
-            run_item<T, NL, NOPS, PAR, MI, HW, L0, false, CHK, EXT>(c, wi, out, xdir, active, lu, lv);
+            run_item<T, NL, NOPS, PAR, MI, HW, L0, false, CHK, EXT, WG>(c, wi, out, xdir, active, lu, lv);
         return;
     }
     if constexpr (sizeof...(Ls) > 0)
-        dispatch_L<T, NL, NOPS, PAR, MI, HW, CHK, EXT, Ls...>(lcode - 1, pad, c, wi, out, xdir, active, lu, lv);
+        dispatch_L<T, NL, NOPS, PAR, MI, HW, CHK, EXT, WG, Ls...>(lcode - 1, pad, c, wi, out, xdir, active, lu, lv);
 }
 
 // Classes whose partitions reach this many rows stage long x lines in column
@@ -479,8 +473,8 @@ constexpr int max_L() {
 // bits 4..7, x lines: column chunks - 1 in bits 8..9.  Dynamic LDS: exchange
 // area and x tile (one column chunk), overlaid.  EXT: iterated closures, with
 // each line's two end values per op read from ev.
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool EXT, int... Ls>
-__global__ void __launch_bounds__(64 * kWGW)
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool EXT, int WG, int... Ls>
+__global__ void __launch_bounds__(64 * WG)
 k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ qoff,
         const PassDesc *__restrict__ passes, const T *__restrict__ tabs, const int64_t *__restrict__ taboff,
         const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ ev) {
@@ -547,7 +541,7 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
         const int lv = line / pd.nu;
         const T *fbase = in + pd.in_base + (int64_t)(pd.field0 + wi.field) * pd.in_fstride;
         if (xdir) {
-            T *tile = exch;   // shared with the exchange area (see exch_elems_for)
+            T *tile = exch;   // shared with the exchange area
             c.tile = tile;
             c.trow = c.sub * 64 + g;
             if constexpr (kChunked) {   // staged chunk by chunk in the item body
@@ -562,15 +556,15 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
                 c.C = 1;
                 c.chunk = 0;
                 c.tpitch = (Npad + 2 * HW) | 1;
-                stage_x<T, HW>(pd, fbase, wi.line0, (kWGW / c.P) * 64, -HW, Npad + 2 * HW, tile, c.tpitch,
-                               c.periodic);
+                stage_x<T, HW, WG>(pd, fbase, wi.line0, (WG / c.P) * 64, -HW, Npad + 2 * HW, tile, c.tpitch,
+                                   c.periodic);
                 __syncthreads();
             }
         } else {
             c.src = fbase + (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
         }
         const bool pad = c.P * kLs[lcode] != pd.N;
-        dispatch_L<T, NL, NOPS, PAR, MI, HW, kChunked, EXT, Ls...>(lcode, pad, c, wi, out, xdir, active, lu, lv);
+        dispatch_L<T, NL, NOPS, PAR, MI, HW, kChunked, EXT, WG, Ls...>(lcode, pad, c, wi, out, xdir, active, lu, lv);
     }
 }
 

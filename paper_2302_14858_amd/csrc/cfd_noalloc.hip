@@ -163,7 +163,7 @@ extern "C" cfd_status cfd_apply_block_noalloc(const cfd_scheme *sc, const cfd_bl
     ps.par = (s.d % 2) ? 1 : 0;
     ps.mi = s.m;
     ps.hw = std::max(s.m, per ? 0 : s.mc);
-    int cands[3];
+    int cands[4];
     if (candidate_Ps(ps, f32, (size_t)max_lds, cands) == 0)
         return nfail(CFD_EUNSUPPORTED, "cfd_apply_block_noalloc: no compiled line kernel for this line length");
     place_pass(ps, f32, cands[0]);
@@ -173,7 +173,7 @@ extern "C" cfd_status cfd_apply_block_noalloc(const cfd_scheme *sc, const cfd_bl
     const int Npad = ps.P * ps.L;
     const int64_t tel = (table_elems(Npad, ps.P, s.nl) + 7) & ~int64_t(7);
     const int64_t bscr = tab_scratch(ps.P, ps.L, s.nl);
-    const int per_item = kWave * (4 / ps.P);
+    const int per_item = kWave * (waves_for(ps.P) / ps.P);
     const int64_t nlines = (int64_t)b.n[dir == 0 ? 1 : 0] * b.n[dir == 2 ? 1 : 2];
     const int64_t items_per_field = (nlines + per_item - 1) / per_item;
     const int64_t nitems = items_per_field * ps.nfield;
@@ -245,7 +245,7 @@ extern "C" cfd_status cfd_apply_block_noalloc(const cfd_scheme *sc, const cfd_bl
         tabs = base + o_tab32;
     }
     if (e == hipSuccess && nitems > 0)
-        e = launch_lines(ps.cls->fn, (int)nitems, lds, st, a.items, (int)nitems, nullptr, a.pd_dst, tabs, a.taboff,
+        e = launch_lines(ps.cls->fn, ps.cls->wg, (int)nitems, lds, st, a.items, (int)nitems, nullptr, a.pd_dst, tabs, a.taboff,
                          in_dev, out_dev);
     if (e != hipSuccess) {
         (void)hipGetLastError();

@@ -29,7 +29,7 @@ def _each_partition(plan, wl, ops, dtype, Ns):
     tried = 0
     for N in Ns:
         for xl in (0, 1):
-            for parts in (1, 2, 4):
+            for parts in (1, 2, 4, 8):
                 try:
                     plan.set_schedule(N, xl, parts)
                 except P.CfdError:
@@ -159,3 +159,28 @@ def test_allocation_failures_return_enomem_without_leaks(cuda):
     finally:
         P.cfd_debug_fail_alloc(-1)
     assert failures >= 5
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_eight_partition_long_lines(cuda, dtype):
+    """Lines cut into 8 partitions (8-wave workgroups): closure lines of 128 nodes (tridiagonal D1+D2,
+    16-row partitions) and periodic lines of 256 nodes (D1, 32-row partitions), x and y/z, every node
+    against the oracle; then the default and every other partition count give the same bar."""
+    import paper_2302_14858_amd as P
+    # one 128^3 closure block of smooth modes (the batch64 recipe): well conditioned for FP32 D2
+    wl = synth.batch64(nblocks=1, nfields=1, sizes=(128,), ng=4, seed=40)
+    ops = _ops("(1)Q1_3[1]", "(2)Q1_3[1]")
+    plan = H.make_plan(wl, ops, dtype=dtype)
+    _, ooffs = plan.offsets()
+    _, nout = plan.sizes()
+    ref = H.oracle_flat(wl, ops, ooffs, nout)
+    for xl in (0, 1):
+        plan.set_schedule(128, xl, 8)
+    assert H.full_parity(plan, wl, ops, dtype, ref) <= H.tol_for(dtype)
+    assert _each_partition(plan, wl, ops, dtype, (128,)) >= 4
+    wlp = synth.periodic_box(n=(256, 256, 8), nfields=1, nmodes=8, kmax=100, seed=41)
+    opsp = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1)]
+    plan = H.make_plan(wlp, opsp, dtype=dtype)
+    for xl in (0, 1):
+        plan.set_schedule(256, xl, 8)
+    assert H.full_parity(plan, wlp, opsp, dtype) <= H.tol_for(dtype)

@@ -171,4 +171,4 @@ def test_autotune_cache_round_trip(cuda, tmp_path):
         plan.autotune(x, y, cache_path=cache)
         assert H.max_rel_err(H.gpu_run(plan, wl, D12_PENTA), o) <= H.ERR_F64
     lines = open(cache).read().split()
-    assert lines and lines[0].startswith("v4:")
+    assert lines and lines[0].startswith("v5:")
