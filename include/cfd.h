@@ -288,8 +288,22 @@ cfd_status cfd_apply(cfd_plan *p, const void *in_dev, void *out_dev, void *strea
 cfd_status cfd_plan_capture_graph(cfd_plan *p, const void *in_dev, void *out_dev, void *stream);
 
 /* Launch the captured graph (one cfd_apply, Eq. sch_cent_om per line) on
- * `stream`.  CFD_EINVAL if none was captured. */
+ * `stream`.  CFD_EINVAL if none was captured.  If the runtime could not
+ * capture or instantiate the apply, cfd_plan_capture_graph kept its buffers
+ * instead and this call enqueues the same apply eagerly (same result; see
+ * cfd_plan_graph_status). */
 cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream);
+
+/* How cfd_plan_launch_graph replays: 0 nothing captured, 1 an instantiated
+ * HIP graph, 2 the eager fallback (the apply enqueued on each call). */
+cfd_status cfd_plan_graph_status(const cfd_plan *p, int *status);
+
+/* Count the non-finite values (NaN, +-inf) in the plan's output extent
+ * (cfd_plan_sizes' out_elems elements of out_dev, the plan's element type):
+ * a check for results a caller cannot trust (bad input data, an unwritten
+ * output).  Enqueued on `stream`, which it synchronises; uses a counter the
+ * plan allocated at creation. */
+cfd_status cfd_plan_count_nonfinite(cfd_plan *p, const void *out_dev, void *stream, long long *count);
 
 /* Schedule flags. */
 #define CFD_SCHED_PERSISTENT 1   /* grid of (occupancy x CUs) workgroups walking the work list */
@@ -472,6 +486,10 @@ cfd_status cfd_apply_block_noalloc(const cfd_scheme *s, const cfd_block *blk, in
  * and frees what it had allocated.  Process-wide, not thread-safe against
  * concurrent plan creation. */
 void cfd_debug_fail_alloc(long long n);
+
+/* Make the next cfd_plan_capture_graph take its eager fallback as if the
+ * runtime could not capture (on != 0), for tests of that path. */
+void cfd_debug_fail_capture(int on);
 
 #ifdef __cplusplus
 }

@@ -225,6 +225,20 @@ class Plan:
 
     launch_graph = cfd_plan_launch_graph
 
+    def cfd_plan_graph_status(self) -> int:
+        st = ctypes.c_int()
+        check(lib().cfd_plan_graph_status(self._h, ctypes.byref(st)))
+        return st.value
+
+    graph_status = cfd_plan_graph_status
+
+    def cfd_plan_count_nonfinite(self, out, stream=None) -> int:
+        c = ctypes.c_longlong()
+        check(lib().cfd_plan_count_nonfinite(self._h, _dev_ptr(out), _stream_ptr(stream), ctypes.byref(c)))
+        return c.value
+
+    count_nonfinite = cfd_plan_count_nonfinite
+
     def cfd_plan_autotune(self, inp, out, cache_path: Optional[str] = None, stream=None) -> None:
         check(lib().cfd_plan_autotune(self._h, _dev_ptr(inp), _dev_ptr(out), _stream_ptr(stream),
                                       cache_path.encode() if cache_path else None))
@@ -322,6 +336,11 @@ def cfd_apply_block_noalloc(scheme: "Scheme", block: Dict, direction: int, nfiel
     b.out_offset = -1
     check(lib().cfd_apply_block_noalloc(scheme._h, ctypes.byref(b), int(direction), int(nfields), int(field),
                                         int(dtype), _dev_ptr(inp), _dev_ptr(out), _stream_ptr(stream)))
+
+
+def cfd_debug_fail_capture(on: bool = True) -> None:
+    """Test hook: the next graph capture takes the eager fallback."""
+    lib().cfd_debug_fail_capture(int(bool(on)))
 
 
 def cfd_debug_fail_alloc(n: int) -> None:

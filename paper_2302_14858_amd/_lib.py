@@ -69,6 +69,9 @@ SIGNATURES = {
     "cfd_wave_rk_stage": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp]),
     "cfd_wave_rk_stage_halo": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _i, _i, _i, _vp]),
     "cfd_debug_fail_alloc": (None, [_ll]),
+    "cfd_debug_fail_capture": (None, [_i]),
+    "cfd_plan_graph_status": (_i, [_vp, _ip]),
+    "cfd_plan_count_nonfinite": (_i, [_vp, _vp, _vp, _llp]),
     "cfd_plan_set_iteration": (_i, [_vp, _i, _i, _i, _i]),
     "cfd_apply_block_noalloc": (_i, [_vp, ctypes.POINTER(cfd_block), _i, _i, _i, _i, _vp, _vp, _vp]),
 }

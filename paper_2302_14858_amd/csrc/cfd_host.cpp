@@ -53,6 +53,7 @@ cfd_status hip_fail(hipError_t e, const char *what) {
 // device were out of memory, to check that every failure path returns
 // CFD_ENOMEM and frees what it had allocated.
 std::atomic<long long> g_alloc_fail_after{-1};
+std::atomic<bool> g_fail_capture{false};   // test hook: the next capture falls back to eager replay
 
 hipError_t dmalloc(void **ptr, size_t bytes) {
     long long n = g_alloc_fail_after.load();
@@ -158,12 +159,17 @@ struct cfd_plan {
     std::vector<hipEvent_t> ev;           // fork event, then one join event per aux stream
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    const void *eager_in = nullptr;       // capture fallback: the buffers replayed eagerly
+    void *eager_out = nullptr;
+    DevBuf d_count;                       // counter of cfd_plan_count_nonfinite
 
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr;
         graph = nullptr;
+        eager_in = nullptr;
+        eager_out = nullptr;
     }
     void release_iteration() {
         d_iops.release();
@@ -194,6 +200,7 @@ struct cfd_plan {
         d_bcoef.release();
         d_mscr.release();
         d_msegs.release();
+        d_count.release();
         release_iteration();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
@@ -1686,6 +1693,10 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
             st = fail(CFD_EDEVICE, "cfd_plan_create: uploading the mixed-derivative segments");
         }
     }
+    if (st == CFD_OK && dmalloc(&p->d_count.p, sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        st = fail(CFD_ENOMEM, "cfd_plan_create: allocating the result counter");
+    }
     if (st == CFD_OK) st = build_biased(p.get());
     if (st == CFD_OK) st = build(p.get());
     if (st != CFD_OK) {
@@ -1735,7 +1746,17 @@ cfd_status cfd_plan_capture_graph(cfd_plan *p, const void *in_dev, void *out_dev
     HIPCHK(hipSetDevice(p->device));
     p->drop_graph();
     if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
-    HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    // Fallback: where the runtime cannot capture or instantiate the apply (or
+    // the test hook says so), remember the buffers and replay it eagerly.
+    auto fall_back = [&]() {
+        (void)hipGetLastError();
+        p->drop_graph();
+        p->eager_in = in_dev;
+        p->eager_out = out_dev;
+        return CFD_OK;
+    };
+    if (g_fail_capture.exchange(false)) return fall_back();
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return fall_back();
     cfd_status st = enqueue(p, in_dev, out_dev, p->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
@@ -1743,21 +1764,40 @@ cfd_status cfd_plan_capture_graph(cfd_plan *p, const void *in_dev, void *out_dev
         if (g) (void)hipGraphDestroy(g);
         return st;
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    if (e != hipSuccess) return fall_back();
     p->graph = g;
     e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        p->drop_graph();
-        return hip_fail(e, "hipGraphInstantiate");
-    }
+    if (e != hipSuccess) return fall_back();
     return CFD_OK;
 }
 
 cfd_status cfd_plan_launch_graph(cfd_plan *p, void *stream) {
     if (!p) return fail(CFD_EINVAL, "cfd_plan_launch_graph: null plan");
-    if (!p->gexec) return fail(CFD_EINVAL, "cfd_plan_launch_graph: no graph captured");
     HIPCHK(hipSetDevice(p->device));
+    if (!p->gexec) {
+        if (p->eager_in) return enqueue(p, p->eager_in, p->eager_out, (hipStream_t)stream);
+        return fail(CFD_EINVAL, "cfd_plan_launch_graph: no graph captured");
+    }
     HIPCHK(hipGraphLaunch(p->gexec, (hipStream_t)stream));
+    return CFD_OK;
+}
+
+cfd_status cfd_plan_graph_status(const cfd_plan *p, int *status) {
+    if (!p || !status) return fail(CFD_EINVAL, "cfd_plan_graph_status: null argument");
+    *status = p->gexec ? 1 : (p->eager_in ? 2 : 0);
+    return CFD_OK;
+}
+
+cfd_status cfd_plan_count_nonfinite(cfd_plan *p, const void *out_dev, void *stream, long long *count) {
+    if (!p || !out_dev || !count) return fail(CFD_EINVAL, "cfd_plan_count_nonfinite: null argument");
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemsetAsync(p->d_count.p, 0, sizeof(unsigned long long), st));
+    HIPCHK(launch_count_nonfinite(p->dtype != CFD_F64, p->out_elems, out_dev, (unsigned long long *)p->d_count.p, st));
+    unsigned long long c = 0;
+    HIPCHK(hipMemcpyAsync(&c, p->d_count.p, sizeof c, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *count = (long long)c;
     return CFD_OK;
 }
 
@@ -2204,6 +2244,8 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
 }
 
 void cfd_debug_fail_alloc(long long n) { g_alloc_fail_after.store(n < 0 ? -1 : n); }
+
+void cfd_debug_fail_capture(int on) { g_fail_capture.store(on != 0); }
 
 void cfd_plan_destroy(cfd_plan *p) {
     if (!p) return;

@@ -233,6 +233,7 @@ hipError_t launch_build_tables(int ntab, const void *specs, double *data, double
 hipError_t launch_to_f32(int64_t n, const double *a, float *b, hipStream_t st);
 hipError_t launch_xcc_probe(int grid, int *out, hipStream_t st);
 hipError_t launch_count_diff(int64_t nwords, const void *a, const void *b, unsigned long long *cnt, hipStream_t st);
+hipError_t launch_count_nonfinite(int f32, int64_t n, const void *x, unsigned long long *cnt, hipStream_t st);
 size_t tabspec_size();
 void fill_tabspec(void *dst, int N, int P, int L, int nl, int nc, int periodic, const double *alpha5,
                   int64_t off, int ext = 0, double cl_d0 = 1.0, double cl_up = 0.0, double gamma = 0.0);

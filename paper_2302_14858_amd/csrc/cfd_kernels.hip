@@ -233,6 +233,15 @@ __global__ void k_count_diff(int64_t n, const uint32_t *__restrict__ a, const ui
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
 }
 
+template <typename T>
+__global__ void k_count_nonfinite(int64_t n, const T *__restrict__ x, unsigned long long *cnt) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += !isfinite(x[i]);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
+}
+
 __global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = (float)a[i];
@@ -313,6 +322,15 @@ hipError_t launch_count_diff(int64_t nwords, const void *a, const void *b, unsig
     int grid = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (nwords + 255) / 256));
     hipLaunchKernelGGL(k_count_diff, dim3(grid), dim3(256), 0, st, nwords, (const uint32_t *)a, (const uint32_t *)b,
                        cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(int f32, int64_t n, const void *x, unsigned long long *cnt, hipStream_t st) {
+    int grid = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + 255) / 256));
+    if (f32)
+        hipLaunchKernelGGL(k_count_nonfinite<float>, dim3(grid), dim3(256), 0, st, n, (const float *)x, cnt);
+    else
+        hipLaunchKernelGGL(k_count_nonfinite<double>, dim3(grid), dim3(256), 0, st, n, (const double *)x, cnt);
     return hipGetLastError();
 }
 

@@ -172,3 +172,34 @@ def test_autotune_cache_round_trip(cuda, tmp_path):
         assert H.max_rel_err(H.gpu_run(plan, wl, D12_PENTA), o) <= H.ERR_F64
     lines = open(cache).read().split()
     assert lines and lines[0].startswith("v5:")
+
+
+def test_graph_capture_fallback_and_nonfinite_count(cuda):
+    """When the capture fails the plan replays the apply eagerly (graph status 2) with the same
+    result; the non-finite count sees an unwritten (NaN) output and a complete one."""
+    import torch
+    import paper_2302_14858_amd as P
+    wl = synth.batch64(nblocks=3, nfields=2, seed=51)
+    ops = [("(1)QP_O8[1]", 0), ("(2)QP_O8[1]", 1), ("(1)QP_O8[1]", 2)]
+    plan = H.make_plan(wl, ops)
+    _, nout = plan.sizes()
+    x = torch.from_numpy(wl.data).cuda()
+    y0 = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    assert plan.count_nonfinite(y0) == nout
+    plan.apply(x, y0)
+    assert plan.count_nonfinite(y0) == 0
+    assert plan.graph_status() == 0
+    P.cfd_debug_fail_capture(True)
+    y1 = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.capture_graph(x, y1)
+    assert plan.graph_status() == 2
+    for _ in range(2):
+        plan.launch_graph()
+        torch.cuda.synchronize()
+        assert torch.equal(y0, y1)
+        y1.fill_(float("nan"))
+    plan.capture_graph(x, y1)            # hook consumed: a real graph this time
+    assert plan.graph_status() == 1
+    plan.launch_graph()
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
