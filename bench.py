@@ -293,7 +293,9 @@ def extra_wave192(nsteps=200):
     k = np.array(synth.WAVE_K, dtype=np.float64)
     w = float(np.sqrt(np.sum(k * k)))
     out = {"workload": f"wave192: periodic 192^3, plane wave k=(3,5,7), dt=h/4, {nsteps} RK4 steps, (1)Q1_3[1]; "
-                       "'f64'/'f32': one periodic block; 'blocks_*': 64 blocks of 48^3, ng=4, closures + halo exchange"}
+                       "'f64'/'f32': one periodic block; 'blocks_*': 64 blocks of 48^3, ng=4, closures + halo exchange; "
+                       "each stage a derivative apply + the stage kernel ('*_fused': the stage folded into the "
+                       "line kernels' epilogues); schedules autotuned"}
     for variant, bpd in (("", 1), ("blocks_", 4)):
         wl = synth.wave192(n=n, blocks_per_dim=bpd, ng=4)
         h = wl.blocks[0].h[0]
@@ -302,10 +304,13 @@ def extra_wave192(nsteps=200):
         xs = np.arange(n) * h
         ex = [np.exp(-1j * k[a] * xs) for a in range(3)]
         exact = synth.wave_state(xs, xs, xs, T)[0]
-        for label, dt_code in (("f64", P.CFD_F64), ("f32", P.CFD_F32)):
+        for label, dt_code, fused in (("f64", P.CFD_F64, False), ("f32", P.CFD_F32, False),
+                                      ("f64_fused", P.CFD_F64, True), ("f32_fused", P.CFD_F32, True)):
             blocks = [dict(n=b.n, ng=b.ng, h=b.h, boundary=b.boundary) for b in wl.blocks]
             rk = WaveRK4(blocks, P.Scheme.named("(1)Q1_3[1]"), dt, dtype=dt_code,
-                         lattice=(bpd,) * 3 if bpd > 1 else None)
+                         lattice=(bpd,) * 3 if bpd > 1 else None, fused=fused)
+            rk.load(wl.data)
+            rk.plan.autotune(rk.u, rk.d)     # the plain apply's schedule (the fused stage follows it)
             rk.load(wl.data)
             rk.capture()
             rk.load(wl.data)

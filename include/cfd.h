@@ -441,6 +441,29 @@ cfd_status cfd_wave_rk_stage_halo(cfd_plan *p, const void *u0_dev, const void *s
                                   const void *acc_in_dev, void *acc_dev, const void *derivs_dev, double a, double b,
                                   int bx, int by, int bz, void *stream);
 
+/* The same Runge-Kutta stage with the derivatives folded in: the plan's line
+ * kernels, instead of storing D_i Pi, update psi_i (and phi, from the Pi they
+ * read) in their epilogue, and D_z psi_z updates Pi with D_x psi_x and D_y
+ * psi_y, which a first launch stored in work_dev (the plan's output layout and
+ * size; only those two operators' slots are written; contents on return are
+ * scratch).  Two launches on the stream, in order; nothing is allocated.  The
+ * stage arithmetic is that of cfd_wave_rk_stage (k_Pi summed x, y, z in that
+ * order), so both give identical results.  bx = by = bz = 0: no ghost refresh;
+ * a lattice (bx, by, bz >= 1, as for cfd_wave_rk_stage_halo) also refreshes
+ * the face ghosts of the state the next stage reads (stage, or acc when
+ * stage_dev is NULL).
+ * Buffers: u0, src, stage, acc_in, acc as for cfd_wave_rk_stage, except that
+ * stage and acc must not overlap src (the kernels read src while others write
+ * the stage state) or each other, and stage must not be u0: run RK4 with two
+ * stage buffers in turn (u -> s1 -> s2 -> s1 -> u).  All 16-byte aligned.
+ * Errors: CFD_EINVAL (null or aliased buffers, not a wave plan, bad lattice),
+ * CFD_EUNSUPPORTED (dense mixed-precision plan, hybrid closure iteration on,
+ * or no fused kernel compiled for the scheme's band and line length: the
+ * tridiagonal first derivatives with interior half-width up to 3 have one). */
+cfd_status cfd_wave_rk_stage_fused(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev,
+                                   const void *acc_in_dev, void *acc_dev, void *work_dev, double a, double b, int bx,
+                                   int by, int bz, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Allocation-free apply                                                     */
 /* ------------------------------------------------------------------------ */

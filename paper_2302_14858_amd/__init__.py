@@ -289,6 +289,20 @@ class Plan:
 
     wave_rk_stage_halo = cfd_wave_rk_stage_halo
 
+    def cfd_wave_rk_stage_fused(self, u0, src, stage, acc, work, a: float, b: float, lattice=None, stream=None,
+                                acc_in=None) -> None:
+        """The stage with the derivatives folded into the line kernels (two launches; work: a buffer of the
+        plan's output size).  stage and acc must not be src or each other.  lattice (bx, by, bz): also
+        refresh the face ghosts of the state the next stage reads."""
+        bx, by, bz = lattice if lattice is not None else (0, 0, 0)
+        check(lib().cfd_wave_rk_stage_fused(self._h, _dev_ptr(u0), _dev_ptr(src),
+                                            _dev_ptr(stage) if stage is not None else None,
+                                            _dev_ptr(acc_in) if acc_in is not None else None, _dev_ptr(acc),
+                                            _dev_ptr(work), float(a), float(b), int(bx), int(by), int(bz),
+                                            _stream_ptr(stream)))
+
+    wave_rk_stage_fused = cfd_wave_rk_stage_fused
+
     def cfd_plan_set_iteration(self, iterations: int, bx: int = 1, by: int = 1, bz: int = 1) -> None:
         """Hybrid closure iteration on a periodic bx x by x bz block lattice (0: plain block closure)."""
         check(lib().cfd_plan_set_iteration(self._h, int(iterations), int(bx), int(by), int(bz)))

@@ -68,6 +68,7 @@ SIGNATURES = {
     "cfd_xpcy": (_i, [_i, _ll, _vp, _d, _vp, _vp, _vp]),
     "cfd_wave_rk_stage": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp]),
     "cfd_wave_rk_stage_halo": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _i, _i, _i, _vp]),
+    "cfd_wave_rk_stage_fused": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _i, _i, _i, _vp]),
     "cfd_debug_fail_alloc": (None, [_ll]),
     "cfd_debug_fail_capture": (None, [_i]),
     "cfd_plan_graph_status": (_i, [_vp, _ip]),

@@ -95,7 +95,8 @@ struct Group {
     int64_t item0, nitems;
     int grid_persist;
     int qoff_index = -1;   // offset of this group's 9 queue bounds in d_qoff (XCD-aware mode)
-    int iomode = 0;        // buffers: 0 input -> output, 1 input -> scratch, 2 scratch -> scratch
+    int iomode = 0;        // buffers: 0 input -> output, 1 input -> scratch, 2 scratch -> scratch,
+                           // 3 and 4: the two launches of the fused wave stage
     int wg = 4;            // wavefronts per workgroup of the kernel class
 };
 
@@ -162,6 +163,10 @@ struct cfd_plan {
     const void *eager_in = nullptr;       // capture fallback: the buffers replayed eagerly
     void *eager_out = nullptr;
     DevBuf d_count;                       // counter of cfd_plan_count_nonfinite
+    // fused wave stage: the wave operators once more as passes of iomode 3 / 4
+    // with stage epilogues (EpiDesc per pass); ok once their kernels exist
+    bool wave_fused = false, wave_fused_ok = false;
+    DevBuf d_epi;
 
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -201,6 +206,7 @@ struct cfd_plan {
         d_mscr.release();
         d_msegs.release();
         d_count.release();
+        d_epi.release();
         release_iteration();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
@@ -393,6 +399,21 @@ size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }   // F32 and MIXE
 
 constexpr int kXCDq = 8;   // queues of the XCD-aware schedule (one per XCD)
 
+// Passes that only the fused wave stage runs (iomode 3 and 4).
+inline bool fused_pass(const PassHost &ps) { return ps.iomode >= 3; }
+
+// The wave system's operators in the order the stage kernels expect:
+// D_x Pi, D_y Pi, D_z Pi, D_x psi_x, D_y psi_y, D_z psi_z (first degree).
+bool is_wave_plan(const cfd_plan *p) {
+    static const int want[6][2] = {{0, 1}, {1, 1}, {2, 1}, {0, 2}, {1, 3}, {2, 4}};
+    if (p->nfields != 5 || p->ops.size() != 6) return false;
+    for (int o = 0; o < 6; ++o)
+        if (p->ops[o].dir != want[o][0] || p->ops[o].field != want[o][1] || p->schemes[o].d != 1 ||
+            p->schemes[o].kind != 0 || p->ops[o].dir2 >= 0)
+            return false;
+    return true;
+}
+
 // Pass descriptors (strides, offsets, h^-d) of every pass; table indices from pass_tab.
 std::vector<PassDesc> pass_descs(const cfd_plan *p, const std::vector<std::array<int, 2>> &pass_tab) {
     std::vector<PassDesc> pd(p->passes.size());
@@ -475,13 +496,14 @@ cfd_status build_iteration(cfd_plan *p, std::vector<PassDesc> &pd, const std::ve
     std::vector<std::pair<int, int>> pops;
     for (size_t i = 0; i < p->passes.size(); ++i)
         for (int o = 0; o < p->passes[i].nops; ++o) {
+            if (fused_pass(p->passes[i])) continue;
             opidx[std::make_pair((int)i, o)] = (int)pops.size();
             pops.push_back(std::make_pair((int)i, o));
         }
     auto find_pass = [&](int block, int dir, int op) -> int {
         for (size_t i = 0; i < p->passes.size(); ++i) {
             const PassHost &q = p->passes[i];
-            if (q.block != block || q.dir != dir) continue;
+            if (q.block != block || q.dir != dir || fused_pass(q)) continue;
             for (int o = 0; o < q.nops; ++o)
                 if (q.op[o] == op) return opidx[std::make_pair((int)i, o)];
         }
@@ -559,8 +581,25 @@ cfd_status build_groups(cfd_plan *p) {
     }
     if (p->dtype == CFD_MIXED_BF16) return build_dense(p);
     const bool f32 = p->dtype != CFD_F64;
-    // 1. schedule and kernel class of every pass
+    // 1. schedule and kernel class of every pass (the fused wave stage's passes
+    //    only where their kernel classes exist, and not with iterated closures)
+    p->wave_fused_ok = p->wave_fused && p->iter_n == 0;
     for (PassHost &ps : p->passes) {
+        if (fused_pass(ps)) {
+            ps.cls = nullptr;
+            if (!p->wave_fused_ok) continue;
+            std::vector<int> cands = candidate_Ps(ps, f32, p->max_lds);
+            if (cands.empty()) {
+                p->wave_fused_ok = false;
+                continue;
+            }
+            int P = cands[0];
+            auto it = p->sched_P.find(std::make_pair(ps.N, ps.dir == 0 ? 1 : 0));
+            if (it != p->sched_P.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
+                P = it->second;
+            place_pass(ps, f32, P);
+            continue;
+        }
         std::vector<int> cands = candidate_Ps(ps, f32, p->max_lds);
         if (cands.empty()) {
             char buf[200];
@@ -583,6 +622,10 @@ cfd_status build_groups(cfd_plan *p) {
     std::vector<std::array<int, 2>> pass_tab(p->passes.size());
     for (size_t i = 0; i < p->passes.size(); ++i) {
         const PassHost &ps = p->passes[i];
+        if (fused_pass(ps) && !p->wave_fused_ok) {
+            pass_tab[i] = {0, 0};
+            continue;
+        }
         for (int o = 0; o < ps.nops; ++o) {
             TabKey k{ps.sch[o], ps.N, ps.P, ps.L, ps.periodic};
             auto it = tabidx.find(k);
@@ -658,6 +701,47 @@ cfd_status build_groups(cfd_plan *p) {
     HIPCHK(dmalloc((void **)&p->d_pass.p, std::max<size_t>(1, pd.size()) * sizeof(PassDesc)));
     HIPCHK(hipMemcpy(p->d_pass.p, pd.data(), pd.size() * sizeof(PassDesc), hipMemcpyHostToDevice));
 
+    // 3. stage epilogues of the fused wave stage (d_t phi = Pi, d_t Pi = sum_i
+    //    D_i psi_i, d_t psi_i = D_i Pi): D_i Pi updates psi_i, D_y Pi also phi
+    //    (k = Pi, its own line value); D_x psi_x and D_y psi_y are stored in
+    //    the first launch, and D_z psi_z updates Pi with them as addends in
+    //    the second.
+    p->d_epi.release();
+    if (p->wave_fused_ok) {
+        std::vector<EpiDesc> epi(p->passes.size());
+        std::memset(epi.data(), 0, epi.size() * sizeof(EpiDesc));
+        for (size_t i = 0; i < p->passes.size(); ++i) {
+            const PassHost &ps = p->passes[i];
+            if (!fused_pass(ps)) continue;
+            const cfd_block &b = p->blocks[ps.block];
+            const int64_t ng = b.ng, PX = b.n[0] + 2 * ng, PY = b.n[1] + 2 * ng;
+            const int64_t npts = (int64_t)b.n[0] * b.n[1] * b.n[2];
+            EpiDesc &e = epi[i];
+            e.self_tgt = -1;
+            e.block = ps.block;
+            e.dir = ps.dir;
+            for (int d = 0; d < 3; ++d) e.n[d] = b.n[d];
+            e.ng = b.ng;
+            e.sy = (int32_t)PX;
+            e.sz = (int32_t)(PX * PY);
+            e.org = ng * (1 + PX + PX * PY);
+            const int op = ps.op[0];
+            if (op <= 2) {
+                e.mode = 1;
+                e.tgt = 2 + op;
+                if (op == 1) e.self_tgt = 0;
+            } else if (op == 5) {
+                e.mode = 1;
+                e.tgt = 1;
+                e.nadd = 2;
+                e.add[0] = p->out_off[ps.block] + p->op_slot[3] * npts;
+                e.add[1] = p->out_off[ps.block] + p->op_slot[4] * npts;
+            }
+        }
+        HIPCHK(dmalloc((void **)&p->d_epi.p, epi.size() * sizeof(EpiDesc)));
+        HIPCHK(hipMemcpy(p->d_epi.p, epi.data(), epi.size() * sizeof(EpiDesc), hipMemcpyHostToDevice));
+    }
+
     // 4. work items.  One launch group per kernel class (x lines optionally in
     //    a group of their own; with concurrent launches, the y/z items of
     //    blocks none of whose y/z lines need LDS also in a group of their own,
@@ -679,12 +763,14 @@ cfd_status build_groups(cfd_plan *p) {
         bool yz_lds_free = true;
         for (int i : by_block[b]) {
             const PassHost &ps = p->passes[i];
+            if (fused_pass(ps)) continue;
             if (ps.dir != 0 && exch_bytes(ps.nl, ps.nops, ps.P, ps.periodic, es) > 0) yz_lds_free = false;
         }
         for (int f = 0; f < p->nfields; ++f) {
             for (int i : by_block[b]) {
                 const PassHost &ps = p->passes[i];
                 if (f < ps.field0 || f >= ps.field0 + ps.nfield) continue;
+                if (fused_pass(ps) && !p->wave_fused_ok) continue;
                 const size_t lds = pass_lds(ps, f32);
                 int sub = 0;
                 if (p->split_x && ps.dir == 0) sub = 1;
@@ -726,8 +812,10 @@ cfd_status build_groups(cfd_plan *p) {
     std::vector<int> bf_queue(nbf, 0);
     if (p->xcd) {
         std::vector<int64_t> bf_cost(nbf, 0);
-        for (size_t gi = 0; gi < groups.size(); ++gi)
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            if (groups[gi].iomode >= 3) continue;   // the fused stage's copies follow the same queues
             for (size_t e = 0; e < gitems[gi].size(); ++e) bf_cost[gbf[gi][e]] += gcost[gi][e];
+        }
         std::vector<int64_t> load(kXCDq, 0);
         for (int bf = 0; bf < nbf; ++bf) {
             if (!bf_cost[bf]) continue;
@@ -1063,7 +1151,8 @@ cfd_status launch_biased_groups(cfd_plan *p, const void *in, void *out, hipStrea
     return CFD_OK;
 }
 
-cfd_status launch_group(cfd_plan *p, const Group &g, const void *in, void *out, hipStream_t st) {
+cfd_status launch_group(cfd_plan *p, const Group &g, const void *in, void *out, hipStream_t st,
+                        const RkArgs *rk = nullptr) {
     const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
     if (g.iomode == 1) out = p->d_mscr.p;
     if (g.iomode == 2) {
@@ -1080,7 +1169,7 @@ cfd_status launch_group(cfd_plan *p, const Group &g, const void *in, void *out, 
         const int *qoff = (g.qoff_index >= 0) ? (const int *)p->d_qoff.p + g.qoff_index : nullptr;
         e = launch_lines(g.fn, g.wg, grid, g.lds, st, (const WorkItem *)p->d_items.p + g.item0, (int)g.nitems, qoff,
                          (const PassDesc *)p->d_pass.p, tabs, (const int64_t *)p->d_taboff.p, in, out,
-                         p->iter_n > 0 ? p->d_ev.p : nullptr);
+                         p->iter_n > 0 ? p->d_ev.p : nullptr, rk);
     }
     if (e != hipSuccess) return hip_fail(e, "launching a kernel group");
     return CFD_OK;
@@ -1172,7 +1261,7 @@ cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
     for (int stage = 0; stage < 2; ++stage) {
         std::vector<const Group *> act;
         for (const Group &g : p->groups)
-            if (g.nitems > 0 && (g.iomode == 2) == (stage == 1)) act.push_back(&g);
+            if (g.nitems > 0 && g.iomode < 3 && (g.iomode == 2) == (stage == 1)) act.push_back(&g);
         if (p->concurrent && act.size() > 1 && p->aux.size() + 1 >= act.size() && p->ev.size() >= act.size()) {
             // fork: every group after the first on its own stream, all ordered after
             // the caller's earlier work; join: the caller's stream waits for all
@@ -1198,6 +1287,19 @@ cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
                                             (const int64_t *)p->d_msegs.p, p->mseg_max, p->d_mscr.p, out, st);
         if (e != hipSuccess) return hip_fail(e, "launching the mixed-derivative combine");
     }
+    return CFD_OK;
+}
+
+// The fused wave stage: the first launch (iomode 3) updates phi and psi and
+// stores D_x psi_x, D_y psi_y into work; the second (iomode 4), after it on
+// the same stream, updates Pi.
+cfd_status enqueue_wave_fused(cfd_plan *p, const void *src, void *work, const RkArgs &rk, hipStream_t st) {
+    for (int mode = 3; mode <= 4; ++mode)
+        for (const Group &g : p->groups) {
+            if (g.iomode != mode || g.nitems == 0) continue;
+            cfd_status r = launch_group(p, g, src, work, st, &rk);
+            if (r != CFD_OK) return r;
+        }
     return CFD_OK;
 }
 
@@ -1564,6 +1666,18 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
             }
         }
     }
+    // the fused wave stage runs the wave operators' passes once more, in two
+    // launches, with stage epilogues instead of stores
+    if ((desc->dtype == CFD_F64 || desc->dtype == CFD_F32) && is_wave_plan(p.get())) {
+        const size_t n = p->passes.size();
+        for (size_t i = 0; i < n; ++i) {
+            PassHost ps = p->passes[i];
+            ps.ext = 2;
+            ps.iomode = (ps.op[0] == 2 || ps.op[0] == 5) ? 4 : 3;
+            p->passes.push_back(ps);
+        }
+        p->wave_fused = true;
+    }
     // symmetrised mixed derivatives: for each order (inner dj, outer di) a
     // first-stage pass D_dj f -> scratch S over the block extended by its ghost
     // layers along di (none if di is periodic), and a second-stage pass
@@ -1725,8 +1839,17 @@ cfd_status cfd_plan_offsets(const cfd_plan *p, long long *in_offsets, long long 
 
 cfd_status cfd_plan_stats(const cfd_plan *p, int *launches, long long *items) {
     if (!p) return fail(CFD_EINVAL, "cfd_plan_stats: null plan");
-    if (launches) *launches = (int)p->groups.size();
-    if (items) *items = p->nitems;
+    if (launches) {
+        int n = 0;
+        for (const Group &g : p->groups) n += g.iomode < 3;
+        *launches = n;
+    }
+    if (items) {
+        long long n = 0;
+        for (const Group &g : p->groups)
+            if (g.iomode < 3) n += g.nitems;
+        *items = n;
+    }
     return CFD_OK;
 }
 
@@ -1812,7 +1935,7 @@ cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions,
         if (partitions > 0) {
             bool any = false;
             for (const PassHost &ps : p->passes) {
-                if (ps.N != N || (ps.dir == 0) != (xlines != 0)) continue;
+                if (ps.N != N || (ps.dir == 0) != (xlines != 0) || fused_pass(ps)) continue;
                 std::vector<int> c = candidate_Ps(ps, p->dtype != CFD_F64, p->max_lds);
                 if (std::find(c.begin(), c.end(), partitions) == c.end())
                     return fail(CFD_EINVAL, "cfd_plan_set_schedule: no compiled kernel for that partition count");
@@ -1875,7 +1998,8 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     // one class per (line length, x or y/z, band, fused operators)
     std::map<std::tuple<int, int, int, int>, std::vector<int>> classes;
     for (const PassHost &ps : p->passes)
-        classes[std::make_tuple(ps.N, ps.dir == 0 ? 1 : 0, ps.nl, ps.nops)] = candidate_Ps(ps, f32, p->max_lds);
+        if (!fused_pass(ps))
+            classes[std::make_tuple(ps.N, ps.dir == 0 ? 1 : 0, ps.nl, ps.nops)] = candidate_Ps(ps, f32, p->max_lds);
     std::map<std::string, int> cache;
     if (cache_path) {
         std::ifstream f(cache_path);
@@ -1935,7 +2059,9 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
                     p->split_x = split;
                     p->concurrent = conc;
                     r = build(p);
-                    if (r == CFD_OK && conc && p->groups.size() < 2) continue;   // same as sequential
+                    int nplain = 0;
+                    for (const Group &g : p->groups) nplain += g.iomode < 3;
+                    if (r == CFD_OK && conc && nplain < 2) continue;   // same as sequential
                     float ms = 0;
                     if (r == CFD_OK) r = time_apply(ms);
                     if (r == CFD_OK && ms < best) { best = ms; bmode = mode; bs = split; bc = conc; }
@@ -1957,6 +2083,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         p->sched_P.clear();
         if (which == 0) return;
         for (const PassHost &ps : p->passes) {
+            if (fused_pass(ps)) continue;
             int c[4];
             const int n = candidate_Ps(ps, f32, p->max_lds, c);
             const int cap = ps.dir == 0 ? 12 : 16;
@@ -2054,7 +2181,8 @@ cfd_status cfd_plan_get_schedule(const cfd_plan *p, int *persistent, int *split_
     if (persistent) *persistent = p->persistent ? (p->xcd ? 2 : 1) : 0;
     if (split_x) *split_x = p->split_x;
     std::map<std::pair<int, int>, int> used;
-    for (const PassHost &ps : p->passes) used[std::make_pair(ps.N, ps.dir == 0 ? 1 : 0)] = ps.P;
+    for (const PassHost &ps : p->passes)
+        if (!fused_pass(ps)) used[std::make_pair(ps.N, ps.dir == 0 ? 1 : 0)] = ps.P;
     if (n_classes) *n_classes = (int)used.size();
     int i = 0;
     for (auto &kv : used) {
@@ -2165,6 +2293,60 @@ cfd_status cfd_wave_rk_stage_halo(cfd_plan *p, const void *u0_dev, const void *s
     return wave_stage(p, u0_dev, src_dev, stage_dev, acc_in_dev, acc_dev, derivs_dev, a, b, bx, by, bz, stream);
 }
 
+cfd_status cfd_wave_rk_stage_fused(cfd_plan *p, const void *u0_dev, const void *src_dev, void *stage_dev,
+                                   const void *acc_in_dev, void *acc_dev, void *work_dev, double a, double b, int bx,
+                                   int by, int bz, void *stream) {
+    if (!p || !u0_dev || !src_dev || !acc_dev || !work_dev)
+        return fail(CFD_EINVAL, "cfd_wave_rk_stage_fused: null argument");
+    if (!is_wave_plan(p))
+        return fail(CFD_EINVAL, "cfd_wave_rk_stage_fused: operators must be D_x Pi, D_y Pi, D_z Pi, D_x psi_x, "
+                                "D_y psi_y, D_z psi_z (first derivatives) on 5 fields");
+    if (!p->wave_fused)
+        return fail(CFD_EUNSUPPORTED, "cfd_wave_rk_stage_fused: available for FP64 and FP32 plans only");
+    if (p->iter_n > 0)
+        return fail(CFD_EUNSUPPORTED, "cfd_wave_rk_stage_fused: not with the hybrid closure iteration");
+    if (!p->wave_fused_ok)
+        return fail(CFD_EUNSUPPORTED, "cfd_wave_rk_stage_fused: no fused kernel compiled for this scheme and line "
+                                      "length");
+    if (!acc_in_dev) acc_in_dev = acc_dev;
+    if (stage_dev == src_dev || acc_dev == src_dev || (stage_dev && stage_dev == acc_dev) ||
+        (stage_dev && stage_dev == u0_dev))
+        return fail(CFD_EINVAL, "cfd_wave_rk_stage_fused: stage and acc must be buffers of their own (not src, "
+                                "not each other; stage not u0)");
+    if (work_dev == u0_dev || work_dev == src_dev || work_dev == stage_dev || work_dev == acc_in_dev ||
+        work_dev == acc_dev)
+        return fail(CFD_EINVAL, "cfd_wave_rk_stage_fused: work must be a buffer of its own");
+    const bool lattice = bx != 0 || by != 0 || bz != 0;
+    if (lattice) {
+        if (bx < 1 || by < 1 || bz < 1 || (int64_t)bx * by * bz != (int64_t)p->blocks.size())
+            return fail(CFD_EINVAL, "cfd_wave_rk_stage_fused: lattice does not match the plan's block count");
+        const cfd_block &b0 = p->blocks[0];
+        for (const cfd_block &bl : p->blocks)
+            if (bl.n[0] != b0.n[0] || bl.n[1] != b0.n[1] || bl.n[2] != b0.n[2] || bl.ng != b0.ng)
+                return fail(CFD_EINVAL, "cfd_wave_rk_stage_fused: blocks differ in shape");
+        for (int d = 0; d < 3; ++d)
+            if (b0.ng > b0.n[d]) return fail(CFD_ESHAPE, "cfd_wave_rk_stage_fused: ghost width exceeds block extent");
+    }
+    for (const void *q : {u0_dev, src_dev, (const void *)stage_dev, acc_in_dev, (const void *)acc_dev,
+                          (const void *)work_dev})
+        if ((uintptr_t)q % 16) return fail(CFD_EINVAL, "cfd_wave_rk_stage_fused: buffers must be 16-byte aligned");
+    HIPCHK(hipSetDevice(p->device));
+    RkArgs rk{};
+    rk.u0 = u0_dev;
+    rk.stage = stage_dev;
+    rk.acc_in = acc_in_dev;
+    rk.acc = acc_dev;
+    rk.epi = (const EpiDesc *)p->d_epi.p;
+    rk.in_off = (const int64_t *)p->d_inoff.p;
+    rk.a = a;
+    rk.b = b;
+    rk.lat[0] = lattice ? bx : 0;
+    rk.lat[1] = lattice ? by : 0;
+    rk.lat[2] = lattice ? bz : 0;
+    rk.acc_is_u0 = acc_in_dev == u0_dev;
+    return enqueue_wave_fused(p, src_dev, work_dev, rk, (hipStream_t)stream);
+}
+
 cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, int bz) {
     if (!p) return fail(CFD_EINVAL, "cfd_plan_set_iteration: null plan");
     if (iterations < 0) return fail(CFD_EINVAL, "cfd_plan_set_iteration: negative iteration count");
@@ -2178,12 +2360,13 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
     auto restore = [&]() {
         if (!p->base_schemes.empty()) p->schemes = p->base_schemes;
         p->base_schemes.clear();
-        for (PassHost &ps : p->passes) ps.ext = 0;
+        for (PassHost &ps : p->passes) ps.ext = fused_pass(ps) ? 2 : 0;
         p->iter_n = 0;
     };
     if (iterations == 0) {
         restore();
         for (PassHost &ps : p->passes) {
+            if (fused_pass(ps)) continue;   // never changed by the iteration
             ps.mi = ps.hw = 0;
             for (int k = 0; k < ps.nops; ++k) {
                 const Scheme &s = p->schemes[ps.sch[k]];
@@ -2224,6 +2407,7 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
     p->base_schemes = base;
     p->schemes = it;
     for (PassHost &ps : p->passes) {
+        if (fused_pass(ps)) continue;   // the fused wave stage is off while iterating
         ps.ext = 1;
         ps.mi = ps.hw = 0;
         for (int k = 0; k < ps.nops; ++k) {

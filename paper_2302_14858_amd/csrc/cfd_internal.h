@@ -170,6 +170,45 @@ struct WorkItem {
     int32_t meta;
 };
 
+// Method-of-lines stage epilogue of the line kernel (extension mode 2).
+// Instead of storing its derivative D, an item folds it into one explicit
+// Runge-Kutta stage of a state field t:
+//   k = (addends) + D,  stage[t] = u0[t] + a k,  acc[t] = acc_in[t] + b k,
+// where the addends are derivatives of the same node that other passes of an
+// earlier launch stored in the output layout (summed in order).  A pass may
+// also update a second field with k = the input value of its own line at the
+// node (y and z lines only: the lane holds it in registers).  The state
+// arrays have the plan's input layout.  Indexed like the pass descriptors.
+struct EpiDesc {
+    int64_t add[2];       // output offsets (this block) of the addend derivatives
+    int64_t org;          // offset of interior node (0,0,0) within a field
+    int32_t mode;         // 0: store the derivative, 1: stage update
+    int32_t tgt;          // state field of the stage update
+    int32_t self_tgt;     // field updated with k = the line's own value, -1: none
+    int32_t nadd;         // addends (0..2)
+    int32_t block;        // block index (position in the lattice)
+    int32_t dir;          // direction of the pass's lines
+    int32_t n[3], ng;     // block extents and ghost layers
+    int32_t sy, sz;       // state strides along y and z
+};
+// Per-launch arguments of the stage epilogue (passed by value to every line
+// kernel; read only by the classes compiled with mode 2).  With a lattice
+// (lat[0] > 0: the blocks tile a periodic box, block b at (b % bx, b / bx %
+// by, b / (bx by))), the state the next stage reads (stage, else acc) also gets
+// its face ghosts: a node within ng of a face writes its new value into the
+// facing ghost layer of the neighbour across that face.
+struct RkArgs {
+    const void *u0;
+    void *stage;          // nullptr: no stage state
+    const void *acc_in;   // may equal u0 (then read once)
+    void *acc;
+    const EpiDesc *epi;
+    const int64_t *in_off;   // input offset of every block (ghost refresh)
+    double a, b;
+    int32_t lat[3];
+    int32_t acc_is_u0;
+};
+
 }  // namespace cfd
 
 // ---------------------------------------------------------------------------
@@ -192,7 +231,7 @@ struct PassHost {
     int op[2] = {0, 0};   // plan op indices (output order)
     int sch[2] = {0, 0};  // scheme indices
     int N = 0, ng = 0, periodic = 0, nl = 0, par = 0, mi = 0, hw = 0;
-    int ext = 0;          // iterated closures: the kernel adds the end-value terms
+    int ext = 0;          // kernel extension: 1 iterated closures (end-value terms), 2 stage epilogue
     int P = 0, L = 0, lcode = 0;
     int C = 1;            // x lines: column chunks the LDS tile is staged in (divides P)
     const LineClass *cls = nullptr;
@@ -200,6 +239,8 @@ struct PassHost {
     // scratch buffer: iomode 0 input -> output, 1 input -> scratch (first
     // stage), 2 scratch -> scratch (second stage, after the first).  Their
     // strides and offsets are set explicitly (geom) instead of from the block.
+    // Passes of the fused wave stage: iomode 3 (first launch) and 4 (second
+    // launch, after the first), run only by that stage.
     int iomode = 0;
     bool custom = false;
     PassDesc geom{};
@@ -227,7 +268,7 @@ const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int
 int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap, int ext = 0, int wg = 0);
 hipError_t launch_lines(const void *fn, int wg, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
                         const int *qoff, const PassDesc *passes, const void *tabs, const int64_t *taboff,
-                        const void *in, void *out, const void *ev = nullptr);
+                        const void *in, void *out, const void *ev = nullptr, const RkArgs *rk = nullptr);
 hipError_t launch_build_tables(int ntab, const void *specs, double *data, double *scratch, int64_t scratch_per,
                                int *status, hipStream_t st);
 hipError_t launch_to_f32(int64_t n, const double *a, float *b, hipStream_t st);

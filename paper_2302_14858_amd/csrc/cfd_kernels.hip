@@ -291,9 +291,11 @@ int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, i
 
 hipError_t launch_lines(const void *fn, int wg, int grid, size_t lds, hipStream_t st, const WorkItem *items, int nitems,
                         const int *qoff, const PassDesc *passes, const void *tabs, const int64_t *taboff,
-                        const void *in, void *out, const void *ev) {
+                        const void *in, void *out, const void *ev, const RkArgs *rk) {
+    RkArgs r{};
+    if (rk) r = *rk;
     void *args[] = {(void *)&items, (void *)&nitems, (void *)&qoff, (void *)&passes, (void *)&tabs,
-                    (void *)&taboff, (void *)&in, (void *)&out, (void *)&ev};
+                    (void *)&taboff, (void *)&in, (void *)&out, (void *)&ev, (void *)&r};
     return hipLaunchKernel(fn, dim3(grid), dim3(64 * wg), args, lds, st);
 }
 

@@ -14,19 +14,25 @@ struct LineClass {
     int nL;
     int Ls[8];
     const void *fn;
-    int ext;      // adds the end-value terms of an iterated closure
+    int ext;      // extension mode: 1 end-value terms of an iterated closure, 2 stage epilogue
     int wg;       // wavefronts per workgroup: 4 (P = 1, 2, 4) or 8 (P = 8)
 };
 
 #define CFD_LC(T, NL, NOPS, PAR, MI, HW, ...)                                                        \
     LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
-              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, false, 4, __VA_ARGS__>), 0, 4}
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, 0, 4, __VA_ARGS__>), 0, 4}
 #define CFD_LC8(T, NL, NOPS, PAR, MI, HW, ...)                                                       \
     LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
-              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, false, 8, __VA_ARGS__>), 0, 8}
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, 0, 8, __VA_ARGS__>), 0, 8}
 #define CFD_LC_EXT(T, NL, NOPS, PAR, MI, HW, ...)                                                    \
     LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
-              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, true, 4, __VA_ARGS__>), 1, 4}
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, 1, 4, __VA_ARGS__>), 1, 4}
+#define CFD_LC_RK(T, NL, NOPS, PAR, MI, HW, ...)                                                     \
+    LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, 2, 4, __VA_ARGS__>), 2, 4}
+#define CFD_LC8_RK(T, NL, NOPS, PAR, MI, HW, ...)                                                    \
+    LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, 2, 8, __VA_ARGS__>), 2, 8}
 
 // The classes compiled for each precision.
 #define CFD_LINE_CLASSES(T, F32)                                                  \
@@ -60,7 +66,14 @@ struct LineClass {
     /* iterated closures of tridiagonal schemes (hybrid closure iteration) */    \
     CFD_LC_EXT(T, 1, 2, 1, 3, 4, 8, 12, 16),                                      \
     CFD_LC_EXT(T, 1, 1, 1, 3, 4, 8, 12, 16, 24, 32),                              \
-    CFD_LC_EXT(T, 1, 1, 0, 5, 5, 8, 12, 16, 24, 32)
+    CFD_LC_EXT(T, 1, 1, 0, 5, 5, 8, 12, 16, 24, 32),                              \
+    /* the fused Runge-Kutta stage of the wave system (tridiagonal first      */ \
+    /* derivatives with RHS half-width up to 3), the partition sets of the     */ \
+    /* plain classes above; the class without long partitions needs fewer      */ \
+    /* registers and is preferred for the lengths it has                       */ \
+    CFD_LC_RK(T, 1, 1, 1, 3, 4, 8, 12, 16),                                       \
+    CFD_LC_RK(T, 1, 1, 1, 3, 4, 8, 12, 16, 24, 32),                               \
+    CFD_LC8_RK(T, 1, 1, 1, 3, 4, 16, 24, 32)
 
 const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext, int wg);
 

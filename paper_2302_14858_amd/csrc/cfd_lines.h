@@ -80,7 +80,7 @@ struct LineCtx {
 
 // One lane: the p-th partition (L rows) of its line, all NOPS operators.
 // Leaves the solution (times h^-d) in y.
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool X, bool PAD, bool EXT>
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool X, bool PAD, int XM>
 __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS][L], T (&fin)[L + 2 * HW]) {
     const PassDesc &pd = *c.pd;
     const int N = pd.N;
@@ -249,7 +249,7 @@ __device__ __forceinline__ void solve_partition(const LineCtx<T> &c, T (&y)[NOPS
 #pragma unroll
         for (int i = 0; i < L; ++i) y[o][i] *= hinv;
     }
-    if constexpr (EXT) {
+    if constexpr (XM == 1) {
         // iterated closure (Eq. iter_center_P): the block system carries the
         // two end values on its closure rows; add their responses (the
         // influence vectors of the table, zero on padding rows)
@@ -346,11 +346,144 @@ __device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N,
     }
 }
 
+// Stage epilogue, split in two so that a lane issues the loads of a batch of
+// nodes before any of their stores (the state pointers may alias as far as
+// the compiler knows, so a store would otherwise hold back every later load).
+// rk_load: u0 and acc_in of state field t at node offset node (relative to the
+// pass's interior origin).  rk_store: stage = u0 + a k, acc = acc_in + b k,
+// and with a lattice the face ghosts of the next state; (x, y, z) are the
+// node's coordinates in the block.  Same arithmetic as the separate stage
+// kernel.
+template <typename T>
+__device__ __forceinline__ void rk_load(const RkArgs &rk, const PassDesc &pd, int t, int64_t node, T &v, T &ai) {
+    const int64_t idx = pd.in_base + (int64_t)t * pd.in_fstride + node;
+    v = T(0);
+    if (rk.stage || rk.acc_is_u0) v = static_cast<const T *>(rk.u0)[idx];
+    ai = rk.acc_is_u0 ? v : static_cast<const T *>(rk.acc_in)[idx];
+}
+
+// Ghost targets of one block for the stage epilogue: per face (x-, x+, y-,
+// y+, z-, z+) the offset that takes a node's offset within this block's
+// storage to the facing ghost node in the neighbour's storage.  Read once per
+// item (the block is the item's).
+struct RkGhost {
+    int64_t base[6];
+    bool on;
+};
+
+__device__ __forceinline__ RkGhost rk_ghost(const RkArgs &rk, const EpiDesc &ed) {
+    RkGhost g;
+    g.on = rk.lat[0] > 0;
+    if (!g.on) return g;
+    const int bx = rk.lat[0], by = rk.lat[1], bz = rk.lat[2];
+    const int kx = ed.block % bx, ky = (ed.block / bx) % by, kz = ed.block / (bx * by);
+    const int64_t sy = (int64_t)ed.n[1] * ed.sy, sz = (int64_t)ed.n[2] * ed.sz;
+    g.base[0] = rk.in_off[(kz * by + ky) * bx + (kx + bx - 1) % bx] + ed.n[0];
+    g.base[1] = rk.in_off[(kz * by + ky) * bx + (kx + 1) % bx] - ed.n[0];
+    g.base[2] = rk.in_off[(kz * by + (ky + by - 1) % by) * bx + kx] + sy;
+    g.base[3] = rk.in_off[(kz * by + (ky + 1) % by) * bx + kx] - sy;
+    g.base[4] = rk.in_off[(((kz + bz - 1) % bz) * by + ky) * bx + kx] + sz;
+    g.base[5] = rk.in_off[(((kz + 1) % bz) * by + ky) * bx + kx] - sz;
+    return g;
+}
+
+template <typename T>
+__device__ __forceinline__ void rk_store(const RkArgs &rk, const EpiDesc &ed, const RkGhost &gh, const PassDesc &pd,
+                                         int t, int64_t node, int x, int y, int z, T v, T ai, T k) {
+    const int64_t idx = pd.in_base + (int64_t)t * pd.in_fstride + node;
+    const T sv = v + (T)rk.a * k, av = ai + (T)rk.b * k;
+    if (rk.stage) static_cast<T *>(rk.stage)[idx] = sv;
+    static_cast<T *>(rk.acc)[idx] = av;
+    if (gh.on) {
+        const T nv = rk.stage ? sv : av;
+        T *next = static_cast<T *>(rk.stage ? rk.stage : rk.acc);
+        const int64_t here = ed.org + (int64_t)t * pd.in_fstride + node;   // within the block's storage
+        const int ng = ed.ng;
+        if (x < ng) next[gh.base[0] + here] = nv;
+        if (x >= ed.n[0] - ng) next[gh.base[1] + here] = nv;
+        if (y < ng) next[gh.base[2] + here] = nv;
+        if (y >= ed.n[1] - ng) next[gh.base[3] + here] = nv;
+        if (z < ng) next[gh.base[4] + here] = nv;
+        if (z >= ed.n[2] - ng) next[gh.base[5] + here] = nv;
+    }
+}
+
+// k of a stage epilogue: the addends stored at output offset oo (within the
+// block), in order, then the derivative.
+template <typename T>
+__device__ __forceinline__ T rk_k(const EpiDesc &ed, const T *out, int64_t oo, T d) {
+    if (ed.nadd == 0) return d;
+    T s = out[ed.add[0] + oo];
+    if (ed.nadd > 1) s = s + out[ed.add[1] + oo];
+    return s + d;
+}
+
+// Nodes per load batch of the stage epilogue (more batches in flight cost
+// registers, and with them waves per SIMD).
+constexpr int kRkBatch = 4;
+
+// x lines of a stage epilogue: the results staged in the tile (row r = line
+// line0 + r, columns col0 .. col0 + ncols - 1 of the line, pitch opitch) go
+// into the stage update instead of the output.  Thread tid owns node pair
+// tid % CO of rows tid / CO + k * RPP, as in store_x, kRkBatch / 2 rows per
+// load batch.
+template <typename T, int WG>
+__device__ __forceinline__ void store_x_rk(const RkArgs &rk, const EpiDesc &ed, const PassDesc &pd, const T *out,
+                                           const T *tile, int line0, int nrows, int col0, int ncols, int opitch) {
+    constexpr int NT = 64 * WG;
+    constexpr int RB = kRkBatch / 2;
+    const int CO = (ncols + 1) >> 1;
+    const int RPP = NT / CO;
+    const int tid = threadIdx.x;
+    const int r0 = tid / CO;
+    const int c = 2 * (tid - r0 * CO);
+    if (r0 >= RPP) return;
+    const bool second = c + 1 < ncols;
+    const RkGhost gh = rk_ghost(rk, ed);
+    for (int rb = r0; rb < nrows; rb += RB * RPP) {
+        T v[RB][2], ai[RB][2], k[RB][2];
+        int64_t node[RB];
+        int lu[RB], lv[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = rb + q * RPP;
+            if (r >= nrows) continue;
+            const int line = line0 + r;
+            lu[q] = line % pd.nu;
+            lv[q] = line / pd.nu;
+            node[q] = (int64_t)lv[q] * pd.sv + (int64_t)lu[q] * pd.su + col0 + c;
+            const int64_t oo = (int64_t)line * pd.N + col0 + c;
+            rk_load<T>(rk, pd, ed.tgt, node[q], v[q][0], ai[q][0]);
+            k[q][0] = rk_k<T>(ed, out, oo, tile[r * opitch + c]);
+            if (second) {
+                rk_load<T>(rk, pd, ed.tgt, node[q] + 1, v[q][1], ai[q][1]);
+                k[q][1] = rk_k<T>(ed, out, oo + 1, tile[r * opitch + c + 1]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            if (rb + q * RPP >= nrows) continue;
+            rk_store<T>(rk, ed, gh, pd, ed.tgt, node[q], col0 + c, lu[q], lv[q], v[q][0], ai[q][0], k[q][0]);
+            if (second)
+                rk_store<T>(rk, ed, gh, pd, ed.tgt, node[q] + 1, col0 + c + 1, lu[q], lv[q], v[q][1], ai[q][1],
+                            k[q][1]);
+        }
+    }
+}
+
 // Item body for one compiled partition length L.
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool PAD, bool CHK, bool EXT, int WG>
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int L, bool PAD, bool CHK, int XM, int WG>
 __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *out, bool xdir, bool active,
-                                         int lu, int lv) {
+                                         int lu, int lv, const RkArgs &rk) {
     const PassDesc &pd = *c.pd;
+    // stage epilogue (mode 2 classes, single operator): the pass folds its
+    // derivative into a state update instead of storing it
+    bool epi = false;
+    const EpiDesc *ed = nullptr;
+    if constexpr (XM == 2) {
+        ed = rk.epi + wi.pass;
+        epi = ed->mode == 1;
+    }
     T y[NOPS][L];
     if (xdir) {
         // the tile holds one column chunk (P/C partitions and the halo) at a
@@ -377,7 +510,7 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
 #pragma unroll
             for (int t = 0; t < L + 2 * HW; ++t) fin[t] = c.tile[c.trow * c.tpitch + c.p * L + t];
         }
-        solve_partition<T, NL, NOPS, PAR, MI, HW, L, true, PAD, EXT>(c, y, fin);
+        solve_partition<T, NL, NOPS, PAR, MI, HW, L, true, PAD, XM>(c, y, fin);
         // results back through the tile, chunk by chunk, then contiguous
         // coalesced stores: x-lines line0.. of one field are consecutive rows
         // of the interior output
@@ -399,7 +532,12 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
                     __syncthreads();
                     const int col0 = ch * PC * L;
                     const int ncols = min(N - col0, PC * L);
-                    if (ncols > 0) store_x<T, WG>(dst + col0, c.tile, nrows, N, ncols, opitch);
+                    if (ncols > 0) {
+                        if (epi)
+                            store_x_rk<T, WG>(rk, *ed, pd, out, c.tile, wi.line0, nrows, col0, ncols, opitch);
+                        else
+                            store_x<T, WG>(dst + col0, c.tile, nrows, N, ncols, opitch);
+                    }
                 }
             }
         } else {
@@ -414,13 +552,56 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
                 T *dst = out + pd.out_base[o] + (int64_t)wi.field * pd.out_fstride + (int64_t)wi.line0 * N;
                 int nrows = pd.nlines - wi.line0;
                 if (nrows > nrows_all) nrows = nrows_all;
-                store_x<T, WG>(dst, c.tile, nrows, N, N, opitch);
+                if (epi)
+                    store_x_rk<T, WG>(rk, *ed, pd, out, c.tile, wi.line0, nrows, 0, N, opitch);
+                else
+                    store_x<T, WG>(dst, c.tile, nrows, N, N, opitch);
             }
         }
     } else {
         T fin[L + 2 * HW];
-        solve_partition<T, NL, NOPS, PAR, MI, HW, L, false, PAD, EXT>(c, y, fin);
-        if (active) {
+        solve_partition<T, NL, NOPS, PAR, MI, HW, L, false, PAD, XM>(c, y, fin);
+        if constexpr (XM == 2) {
+            if (epi && active) {
+                // node (lu, lv, j) of the line in the block: coordinates by direction
+                const int nreal = pd.N - c.p * L;
+                const int64_t node0 = (int64_t)lv * pd.sv + (int64_t)lu * pd.su + (int64_t)c.p * L * pd.sd;
+                const int64_t oo0 = (int64_t)lv * pd.osv + (int64_t)lu * pd.osu + (int64_t)c.p * L * pd.osd;
+                const bool self = ed->self_tgt >= 0;
+                const RkGhost gh = rk_ghost(rk, *ed);
+                // x and (y or z) of the lane's nodes: lu is x for y and z lines;
+                // the other coordinate is lv, the line's own is j
+                const int dir = ed->dir;
+                // the operator's field (k = derivative and addends), then the
+                // line's own field (k = its value) if the pass updates one
+#pragma unroll
+                for (int pass2 = 0; pass2 < 2; ++pass2) {
+                    if (pass2 == 1 && !self) break;
+                    const int t = pass2 ? ed->self_tgt : ed->tgt;
+#pragma unroll
+                    for (int i0 = 0; i0 < L; i0 += kRkBatch) {
+                        constexpr int RB = kRkBatch;
+                        T v[RB], ai[RB], k[RB];
+#pragma unroll
+                        for (int q = 0; q < RB; ++q) {
+                            const int i = i0 + q;
+                            if (i >= L || (PAD && i >= nreal)) continue;
+                            rk_load<T>(rk, pd, t, node0 + (int64_t)i * pd.sd, v[q], ai[q]);
+                            k[q] = pass2 ? fin[HW + i] : rk_k<T>(*ed, out, oo0 + (int64_t)i * pd.osd, y[0][i]);
+                        }
+#pragma unroll
+                        for (int q = 0; q < RB; ++q) {
+                            const int i = i0 + q;
+                            if (i >= L || (PAD && i >= nreal)) continue;
+                            const int j = c.p * L + i;
+                            rk_store<T>(rk, *ed, gh, pd, t, node0 + (int64_t)i * pd.sd, lu, dir == 1 ? j : lv,
+                                        dir == 2 ? j : lv, v[q], ai[q], k[q]);
+                        }
+                    }
+                }
+            }
+        }
+        if (active && !epi) {
 #pragma unroll
             for (int o = 0; o < NOPS; ++o) {
                 T *dst = out + pd.out_base[o] + (int64_t)wi.field * pd.out_fstride + (int64_t)lv * pd.osv +
@@ -443,18 +624,19 @@ struct LSet {
     static constexpr int n = sizeof...(Ls);
 };
 
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool CHK, bool EXT, int WG, int L0, int... Ls>
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool CHK, int XM, int WG, int L0, int... Ls>
 __device__ __forceinline__ void dispatch_L(int lcode, bool pad, LineCtx<T> &c, const WorkItem &wi, T *out,
-                                           bool xdir, bool active, int lu, int lv) {
+                                           bool xdir, bool active, int lu, int lv, const RkArgs &rk) {
     if (lcode == 0) {
         if (pad)
-            run_item<T, NL, NOPS, PAR, MI, HW, L0, true, CHK, EXT, WG>(c, wi, out, xdir, active, lu, lv);
+            run_item<T, NL, NOPS, PAR, MI, HW, L0, true, CHK, XM, WG>(c, wi, out, xdir, active, lu, lv, rk);
         else
-            run_item<T, NL, NOPS, PAR, MI, HW, L0, false, CHK, EXT, WG>(c, wi, out, xdir, active, lu, lv);
+            run_item<T, NL, NOPS, PAR, MI, HW, L0, false, CHK, XM, WG>(c, wi, out, xdir, active, lu, lv, rk);
         return;
     }
     if constexpr (sizeof...(Ls) > 0)
-        dispatch_L<T, NL, NOPS, PAR, MI, HW, CHK, EXT, WG, Ls...>(lcode - 1, pad, c, wi, out, xdir, active, lu, lv);
+        dispatch_L<T, NL, NOPS, PAR, MI, HW, CHK, XM, WG, Ls...>(lcode - 1, pad, c, wi, out, xdir, active, lu, lv,
+                                                                 rk);
 }
 
 // Classes whose partitions reach this many rows stage long x lines in column
@@ -471,13 +653,14 @@ constexpr int max_L() {
 // Persistent line kernel: every workgroup walks the work list with a grid
 // stride.  Work item meta: P in bits 0..3, index of L in the compiled set in
 // bits 4..7, x lines: column chunks - 1 in bits 8..9.  Dynamic LDS: exchange
-// area and x tile (one column chunk), overlaid.  EXT: iterated closures, with
-// each line's two end values per op read from ev.
-template <typename T, int NL, int NOPS, int PAR, int MI, int HW, bool EXT, int WG, int... Ls>
+// area and x tile (one column chunk), overlaid.  XM (extension mode): 1
+// iterated closures, with each line's two end values per op read from ev; 2
+// stage epilogue of the passes whose EpiDesc asks for it (rk).
+template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int XM, int WG, int... Ls>
 __global__ void __launch_bounds__(64 * WG)
 k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ qoff,
         const PassDesc *__restrict__ passes, const T *__restrict__ tabs, const int64_t *__restrict__ taboff,
-        const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ ev) {
+        const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ ev, const RkArgs rk) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *exch = reinterpret_cast<T *>(smem_raw);
     constexpr int kLs[] = {Ls...};
@@ -529,7 +712,7 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
         int line = wi.line0 + c.sub * 64 + g;
         const bool active = line < pd.nlines;
         if (!active) line = pd.nlines - 1;
-        if constexpr (EXT) {
+        if constexpr (XM == 1) {
 #pragma unroll
             for (int o = 0; o < NOPS; ++o) {
                 const T *e = ev + pd.ev_base[o] + ((int64_t)wi.field * pd.nlines + line) * 2;
@@ -564,7 +747,7 @@ k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ 
             c.src = fbase + (int64_t)lv * pd.sv + (int64_t)lu * pd.su;
         }
         const bool pad = c.P * kLs[lcode] != pd.N;
-        dispatch_L<T, NL, NOPS, PAR, MI, HW, kChunked, EXT, WG, Ls...>(lcode, pad, c, wi, out, xdir, active, lu, lv);
+        dispatch_L<T, NL, NOPS, PAR, MI, HW, kChunked, XM, WG, Ls...>(lcode, pad, c, wi, out, xdir, active, lu, lv, rk);
     }
 }
 
