@@ -323,7 +323,9 @@ cfd_status cfd_plan_count_nonfinite(cfd_plan *p, const void *out_dev, void *stre
                                     launch) run on forked streams at the same time,
                                     joined on the caller's stream before later work;
                                     with CFD_SCHED_SPLIT_X the y/z lines of blocks that
-                                    need no LDS for them get a launch of their own */
+                                    need no LDS for them get a launch of their own; the
+                                    biased operators' kernel classes (one launch each)
+                                    also run on forked streams */
 
 /* Time the candidate schedules of the operator of cfd_apply (Eq.
  * sch_cent_om per line) on the given buffers and keep the fastest:
@@ -338,8 +340,10 @@ cfd_status cfd_plan_count_nonfinite(cfd_plan *p, const void *out_dev, void *stre
  * file, keyed by device arch, dtype, line length, direction class, band,
  * fused operators and launch shape.  Overwrites out_dev.  Allocates a
  * temporary output-sized buffer for the check.  Synchronises the stream.
- * Invalidates a captured graph.  Biased operators have one launch shape and
- * are not tuned (a plan holding only biased operators returns at once). */
+ * Invalidates a captured graph.  Biased operators have one launch per kernel
+ * class; a plan holding only biased operators tunes just whether those run
+ * one after another or concurrently (CFD_SCHED_CONCURRENT), otherwise they
+ * follow the flag the line kernels' tuning chose. */
 cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, void *stream,
                              const char *cache_path);
 

@@ -1141,13 +1141,25 @@ cfd_status build_biased(cfd_plan *p) {
     return CFD_OK;
 }
 
+// One launch per biased kernel class; in the concurrent mode every class after
+// the first on a forked stream (the classes write disjoint outputs), joined
+// before the caller's stream goes on.
 cfd_status launch_biased_groups(cfd_plan *p, const void *in, void *out, hipStream_t st) {
-    for (const cfd_plan::BGroup &g : p->bgroups) {
+    const size_t n = p->bgroups.size();
+    const bool fork = p->concurrent && n > 1 && p->aux.size() + 1 >= n && p->ev.size() >= n;
+    if (fork) HIPCHK(hipEventRecord(p->ev[0], st));
+    for (size_t i = 0; i < n; ++i) {
+        const cfd_plan::BGroup &g = p->bgroups[i];
+        hipStream_t s = (fork && i > 0) ? p->aux[i - 1] : st;
+        if (s != st) HIPCHK(hipStreamWaitEvent(s, p->ev[0], 0));
         hipError_t e = launch_biased(p->dtype != CFD_F64, g.hb, g.L, g.xdir, g.lds,
                                      (const BiasItem *)p->d_bitems.p + g.item0, (int)g.nitems,
-                                     (const BiasPass *)p->d_bpass.p, p->d_bcoef.p, in, out, st);
+                                     (const BiasPass *)p->d_bpass.p, p->d_bcoef.p, in, out, s);
         if (e != hipSuccess) return hip_fail(e, "launching the biased-line kernel");
+        if (s != st) HIPCHK(hipEventRecord(p->ev[i], s));
     }
+    if (fork)
+        for (size_t i = 1; i < n; ++i) HIPCHK(hipStreamWaitEvent(st, p->ev[i], 0));
     return CFD_OK;
 }
 
@@ -1177,7 +1189,8 @@ cfd_status launch_group(cfd_plan *p, const Group &g, const void *in, void *out, 
 
 // Streams and events of the concurrent mode, made outside any capture.
 cfd_status ensure_aux(cfd_plan *p) {
-    const size_t need = p->groups.size() > 1 ? p->groups.size() - 1 : 0;
+    const size_t ng = std::max(p->groups.size(), p->bgroups.size());
+    const size_t need = ng > 1 ? ng - 1 : 0;
     while (p->aux.size() < need) {
         hipStream_t s;
         HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -1969,7 +1982,37 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     }
     const bool f32 = p->dtype != CFD_F64;
     const char *dt = f32 ? "f32" : "f64";
-    if (p->passes.empty()) return CFD_OK;   // only biased operators: one fixed launch shape
+    if (p->passes.empty()) {
+        // only biased operators: their classes' launches one after the other
+        // or on forked streams, whichever is faster
+        if (p->bgroups.size() < 2) return CFD_OK;
+        hipEvent_t a0, a1;
+        HIPCHK(hipEventCreate(&a0));
+        HIPCHK(hipEventCreate(&a1));
+        float best = 1e30f;
+        bool bc = false;
+        cfd_status r = CFD_OK;
+        for (int conc = 0; conc <= 1 && r == CFD_OK; ++conc) {
+            p->concurrent = conc;
+            for (int w = 0; w < 3 && r == CFD_OK; ++w) r = enqueue(p, in_dev, out_dev, st);
+            for (int trial = 0; trial < 3 && r == CFD_OK; ++trial) {
+                (void)hipEventRecord(a0, st);
+                for (int w = 0; w < 10 && r == CFD_OK; ++w) r = enqueue(p, in_dev, out_dev, st);
+                (void)hipEventRecord(a1, st);
+                (void)hipEventSynchronize(a1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, a0, a1);
+                if (ms < best) {
+                    best = ms;
+                    bc = conc;
+                }
+            }
+        }
+        (void)hipEventDestroy(a0);
+        (void)hipEventDestroy(a1);
+        p->concurrent = bc;
+        return r;
+    }
     if (p->dtype == CFD_MIXED_BF16) {
         // only the grid kind: persistent or one workgroup per item
         hipEvent_t a0, a1;

@@ -68,6 +68,44 @@ def test_biased_with_centred_operators_and_graph(cuda):
         torch.cuda.synchronize()
 
 
+def test_biased_concurrent_classes_match_sequential(cuda):
+    """The biased kernel classes (x and y/z lines, several partition lengths) launched on forked
+    streams give the sequential launches' output bit for bit, eagerly and as a replayed graph; a
+    plan of only biased operators autotunes just that flag and keeps the result."""
+    import torch
+    import paper_2302_14858_amd as P
+    wl = synth.batch64(nblocks=6, nfields=3, sizes=(16, 24, 48), ng=5, seed=25)
+    ops = [("(1)X2", d, -1, d) for d in range(3)]
+    plan = H.make_plan(wl, ops)
+    _, nout = plan.sizes()
+    x = torch.from_numpy(wl.data).cuda()
+    ys = []
+    for conc in (False, True):
+        plan.set_schedule(concurrent=conc)
+        y = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+        plan.apply(x, y)
+        torch.cuda.synchronize()
+        ys.append(y)
+    assert torch.equal(ys[0], ys[1])
+    y1 = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.capture_graph(x, y1)
+    for _ in range(3):
+        plan.launch_graph()
+        torch.cuda.synchronize()
+        assert torch.equal(ys[0], y1)
+        y1.fill_(float("nan"))
+        torch.cuda.synchronize()
+    y2 = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.autotune(x, y2)
+    y2.fill_(float("nan"))
+    plan.apply(x, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(ys[0], y2)
+    assert plan.get_schedule()["concurrent"] in (False, True)
+    err = H.full_parity(plan, wl, ops)
+    assert err <= H.ERR_F64, err
+
+
 def test_upwind_sign_selection_on_constant_velocity(cuda):
     """With c = +1 everywhere the upwind pair equals the left-biased operator bit for bit, with
     c = -1 minus the right-biased one (the kernel's min/max weights are exact)."""
