@@ -35,7 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # (x2.0 and x1.0): 0.701 GB read + 1.937 GB written.  Valid for the line kernels as they are now; set
 # to None when they change until the counters are taken again.
 MEASURED_TRAFFIC_BYTES = 2.638e9
-MEASURED_TRAFFIC_FLAGS = 4      # the launch shape the counters were taken on (reported only for that shape)
+MEASURED_TRAFFIC_FLAGS = 4      # the launch shape the counters were taken on (reported only for that shape
+MEASURED_TRAFFIC_PARTS = "16:0:1,16:1:2,24:0:2,24:1:2,32:0:2,32:1:4,48:0:4,48:1:4"   # these partitions
+MEASURED_TRAFFIC_LAUNCHES = 1   # and this many kernel launches per step)
 OPS_PENTA = [("(1)QP_O8[1]", 0), ("(1)QP_O8[1]", 1), ("(1)QP_O8[1]", 2),
              ("(2)QP_O8[1]", 0), ("(2)QP_O8[1]", 1), ("(2)QP_O8[1]", 2)]
 OPS_TRI = [("(1)Q1_3[1]", 0), ("(1)Q1_3[1]", 1), ("(1)Q1_3[1]", 2),
@@ -60,6 +62,11 @@ def algorithmic_bytes(wl, ops, esize):
         rd += wl.nfields * (n3 + ghost)
         wr += len(ops) * wl.nfields * n3
     return (rd + wr) * esize, rd * esize, wr * esize
+
+
+def result_parts(sched):
+    """Partitions per line class of a schedule, as N:xlines:P,..."""
+    return ",".join(f"{n}:{xl}:{pp}" for n, xl, pp in sched["classes"])
 
 
 def run_gpu(wl, ops, dtype, steps, warmup, autotune=True, schedule=None):
@@ -416,12 +423,14 @@ def main():
                    "interior_points": wl.interior_points, "fields": wl.nfields, "ops": len(ops),
                    "evals_per_step": evals, "kernel_launches_per_step": launches, "work_items": items,
                    "schedule": {"flags": sched["flags"],
-                                "parts": ",".join(f"{n}:{xl}:{pp}" for n, xl, pp in sched["classes"])}},
+                                "parts": result_parts(sched)}},
         "err_vs_oracle": err64,
         "err_scope": "every output node of every block, field and operator",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": MEASURED_TRAFFIC_BYTES if sched["flags"] == MEASURED_TRAFFIC_FLAGS else None,
+                     "traffic": (MEASURED_TRAFFIC_BYTES if sched["flags"] == MEASURED_TRAFFIC_FLAGS and
+                                 result_parts(sched) == MEASURED_TRAFFIC_PARTS and
+                                 launches == MEASURED_TRAFFIC_LAUNCHES else None),
                      "algorithmic_bytes": alg, "read_bytes": rd, "write_bytes": wr},
     }
     del x, y, plan

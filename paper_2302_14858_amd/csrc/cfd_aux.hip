@@ -90,10 +90,11 @@ __global__ void k_xpcy(int64_t n, const T *__restrict__ x, T c, const T *__restr
 // stage = u0 + a k (if stage is given; stage may alias src, each node is read
 // before it is written by the same thread) and acc = acc_in + b k.  State
 // arrays hold the five fields with ghosts, [f][z][y][x].
-// One wave per 64-node piece of an interior x-row (all blocks' pieces
-// numbered consecutively, unitpre[b] = first piece of block b): the piece's
-// block, row and x offset are found once, wave-uniform, and each lane takes
-// one node.
+// One wave per 64 consecutive interior nodes of a block in x-fastest order
+// (all blocks' pieces numbered consecutively, unitpre[b] = first piece of
+// block b; a piece may span rows, so rows shorter than 64 nodes still fill
+// the wave): the piece's block is found once, wave-uniform, and each lane
+// takes one node.
 // With a lattice (bx > 0: the blocks tile a periodic box as in
 // cfd_halo_exchange) the state the next derivative reads (stage if given,
 // else acc) also has its face ghosts refreshed: a node within ng of a face
@@ -118,17 +119,16 @@ k_wave_stage(const T *u0, const T *src, T *stage, const T *acc_in, T *acc, const
         }
         const int bi = lo;
         const int nx = shapes[4 * bi], ny = shapes[4 * bi + 1], nz = shapes[4 * bi + 2], ng = shapes[4 * bi + 3];
-        const int cpr = (nx + 63) >> 6;   // pieces per row
-        const int uu = u - unitpre[bi];
-        const int rr = uu / cpr;
-        const int x = ((uu - rr * cpr) << 6) + lane;
-        if (x >= nx) continue;
-        const int z = rr / ny, y = rr - z * ny;
+        const int64_t n3 = (int64_t)nx * ny * nz;
+        const int64_t e = ((int64_t)(u - unitpre[bi]) << 6) + lane;   // interior node, x fastest
+        if (e >= n3) continue;
+        const int64_t rr = e / nx;   // row z ny + y
+        const int x = (int)(e - rr * nx);
+        const int z = (int)(rr / ny), y = (int)(rr - (int64_t)z * ny);
         const int64_t PX = nx + 2 * ng, PY = ny + 2 * ng, PZ = nz + 2 * ng;
         const int64_t fs = PX * PY * PZ;
-        const int64_t n3 = (int64_t)nx * ny * nz;
         const int64_t ip = in_off[bi] + ((int64_t)(z + ng) * PY + (y + ng)) * PX + ng + x;
-        const T *db = d + out_off[bi] + (int64_t)rr * nx + x;
+        const T *db = d + out_off[bi] + e;
         const T k[5] = {src[ip + fs], db[3 * n3] + db[4 * n3] + db[5 * n3], db[0], db[n3], db[2 * n3]};
         T nv[5];
 #pragma unroll

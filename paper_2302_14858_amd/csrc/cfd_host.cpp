@@ -134,7 +134,7 @@ struct cfd_plan {
     std::vector<Scheme> base_schemes;     // the block-closure schemes while schemes holds the iterated ones
     DevBuf d_iops, d_weights, d_ends0, d_endsf, d_ebufA, d_ebufB, d_ev;
     int n_iops = 0, iter_max_units = 0;
-    int64_t nunits = 0;                   // 64-node row pieces of all blocks (stage kernels)
+    int64_t nunits = 0;                   // 64-node interior pieces of all blocks (stage kernels)
     // device state rebuilt by build()
     DevBuf d_tab64, d_tab32, d_taboff, d_pass, d_items, d_inoff, d_qoff, d_outoff, d_shapes;
     DevBuf d_dense, d_dense_specs;        // dense mixed-precision tables
@@ -1206,7 +1206,8 @@ cfd_status ensure_aux(cfd_plan *p) {
 
 // Block layout on the device, read by the ghost exchange and the stage
 // kernels: input and output offsets per block, and per block (nx, ny, nz, ng)
-// followed by the first 64-node row piece of each block and their total.
+// followed by the first 64-node piece (of the interior, x fastest) of each
+// block and their total.
 // Uploaded once at plan creation, so those calls allocate nothing.
 cfd_status upload_layout(cfd_plan *p) {
     const int nb = (int)p->blocks.size();
@@ -1219,7 +1220,7 @@ cfd_status upload_layout(cfd_plan *p) {
         sh[4 * b + 2] = bl.n[2];
         sh[4 * b + 3] = bl.ng;
         sh[4 * nb + b] = (int)std::min<int64_t>(units, INT32_MAX);
-        units += (int64_t)bl.n[1] * bl.n[2] * ((bl.n[0] + 63) / 64);
+        units += ((int64_t)bl.n[0] * bl.n[1] * bl.n[2] + 63) / 64;
     }
     sh[4 * nb + nb] = (int)std::min<int64_t>(units, INT32_MAX);
     p->nunits = units;
