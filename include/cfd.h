@@ -401,6 +401,28 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
  * nfields*bx*by*bz exceeds 65535. */
 cfd_status cfd_halo_exchange(cfd_plan *p, void *data_dev, int bx, int by, int bz, void *stream);
 
+/* Any conforming tiling (Sec. 2.4: each block's ghost layers are the
+ * neighbouring blocks' data): nbr[6 b + f] is the block across face f of
+ * block b (f = 0..5 for x-, x+, y-, y+, z-, z+; a block may be its own
+ * neighbour, e.g. along a periodic direction), or -1 to leave that face's
+ * ghosts as they are (a physical boundary the caller fills).  A face conforms
+ * if both blocks have the same extents along the face's two directions and
+ * the same ng, and the neighbour has at least ng nodes along the face's
+ * normal.  The table is copied to memory the plan allocated at creation (a
+ * synchronous copy: call outside graph capture).  Errors: CFD_EINVAL (index
+ * out of range), CFD_ESHAPE (a face that does not conform), CFD_EUNSUPPORTED
+ * (more than 65535 face x field pairs, or a face of 2^31 or more ghosts). */
+cfd_status cfd_plan_set_neighbors(cfd_plan *p, const int *nbr);
+
+/* Face-ghost exchange by the plan's neighbour table: for every field, the ng
+ * ghost layers of face f of block b receive the neighbour's ng interior layers
+ * facing it (on the + face ghost layer l = the neighbour's interior layer l;
+ * on the - face ghost layer l = layer n - ng + l of the neighbour's n nodes),
+ * at the same coordinates along the face.  Edges and corners are not filled.
+ * data_dev is the plan's input buffer.  One launch, nothing allocated
+ * (graph-safe).  CFD_EINVAL if no table has been set. */
+cfd_status cfd_halo_exchange_table(cfd_plan *p, void *data_dev, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Element-wise stage kernels for method-of-lines time stepping (classical   */
 /* ERK4, Sec. 3.1): y = a*x + b*y and z = x + c*y over n elements.           */

@@ -70,6 +70,37 @@ def fill_ghosts(state, nb, ng, lattice):
             a[ng + nb:, sl, sl] = zp[ng:2 * ng, sl, sl]
 
 
+def fill_ghosts_table(state, ng, nbr):
+    """Face ghosts by a neighbour table (Sec. 2.4: a block's ghost layers hold its neighbours' data).
+
+    state[b][f]: arrays [z][y][x] with ng ghosts on every side (blocks may differ in extent);
+    nbr[b][face] = block across face (x-, x+, y-, y+, z-, z+) or -1 (ghosts left as they are).
+    Ghost layer l of the + face is the neighbour's interior layer l, of the - face its layer n - ng + l,
+    at the same coordinates along the face; edges and corners are not touched.  Reads are taken from a
+    copy made before any write, so a block may be its own neighbour."""
+    src = [[a.copy() for a in blk] for blk in state]
+    for b in range(len(state)):
+        for face in range(6):
+            q = nbr[b][face]
+            if q < 0:
+                continue
+            d, side = face // 2, face % 2
+            ax = 2 - d                          # array axis of direction d
+            for f in range(len(state[b])):
+                a, s_ = state[b][f], src[q][f]
+                n_a = a.shape[ax] - 2 * ng
+                n_q = s_.shape[ax] - 2 * ng
+                idx_a = [slice(ng, a.shape[k] - ng) for k in range(3)]
+                idx_s = [slice(ng, s_.shape[k] - ng) for k in range(3)]
+                if side:
+                    idx_a[ax] = slice(ng + n_a, 2 * ng + n_a)
+                    idx_s[ax] = slice(ng, 2 * ng)
+                else:
+                    idx_a[ax] = slice(0, ng)
+                    idx_s[ax] = slice(n_q, n_q + ng)
+                a[tuple(idx_a)] = s_[tuple(idx_s)]
+
+
 def rhs_blocks(s: Scheme, state, nb, ng, h, periodic):
     out = []
     for b in range(len(state)):

@@ -314,6 +314,21 @@ class Plan:
 
     halo_exchange = cfd_halo_exchange
 
+    def cfd_plan_set_neighbors(self, nbr) -> None:
+        """Face neighbours per block: nbr[b][f] (f = x-, x+, y-, y+, z-, z+), -1 for none."""
+        flat = [int(v) for row in nbr for v in row]
+        if len(flat) != 6 * self.nblocks:
+            raise ValueError("need 6 neighbours per block")
+        arr = (ctypes.c_int * len(flat))(*flat)
+        check(lib().cfd_plan_set_neighbors(self._h, arr))
+
+    set_neighbors = cfd_plan_set_neighbors
+
+    def cfd_halo_exchange_table(self, data, stream=None) -> None:
+        check(lib().cfd_halo_exchange_table(self._h, _dev_ptr(data), _stream_ptr(stream)))
+
+    halo_exchange_table = cfd_halo_exchange_table
+
     def __del__(self):
         try:
             if self._h:

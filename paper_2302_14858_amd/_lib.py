@@ -64,6 +64,8 @@ SIGNATURES = {
     "cfd_plan_get_flags": (_i, [_vp, _ip]),
     "cfd_plan_destroy": (None, [_vp]),
     "cfd_halo_exchange": (_i, [_vp, _vp, _i, _i, _i, _vp]),
+    "cfd_plan_set_neighbors": (_i, [_vp, _vp]),
+    "cfd_halo_exchange_table": (_i, [_vp, _vp, _vp]),
     "cfd_axpby": (_i, [_i, _ll, _d, _vp, _d, _vp, _vp]),
     "cfd_xpcy": (_i, [_i, _ll, _vp, _d, _vp, _vp, _vp]),
     "cfd_wave_rk_stage": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp]),

@@ -1,7 +1,7 @@
-// Auxiliary device kernels: face-ghost exchange for conforming periodic block
-// tilings (the communication step that fills ghost nodes before each block's
-// closure solve, Sec. 2.4) and element-wise stage combinations for explicit
-// Runge-Kutta time stepping (Sec. 3).
+// Auxiliary device kernels: face-ghost exchange for conforming block tilings
+// (periodic lattices or a neighbour table; the communication step that fills
+// ghost nodes before each block's closure solve, Sec. 2.4) and element-wise
+// stage combinations for explicit Runge-Kutta time stepping (Sec. 3).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,6 +68,51 @@ __global__ void k_halo(T *__restrict__ data, const int64_t *__restrict__ off, in
         src = ((sz + ng) * PY + (y + ng)) * PX + x + ng;
     }
     data[off[b] + fbase + dst] = data[off[nb] + fbase + src];
+}
+
+// Face ghosts by a neighbour table: pair = (block b, face, neighbour nb) with
+// face = 2 d + side (d: 0 x, 1 y, 2 z; side 1: the + face).  blockIdx.y is
+// (pair, field), wave-uniform; thread r takes ghost r of the face's ng layers
+// (x fastest where x runs along the face, so a wave's stores are contiguous).
+// b's ghost layer l on the + face is nb's interior layer l, on the - face
+// nb's interior layer n_nb - ng + l; the coordinates along the face are the
+// same in both blocks (conforming faces).  shapes: (nx, ny, nz, ng) per block.
+template <typename T>
+__global__ void k_halo_table(T *__restrict__ data, const int64_t *__restrict__ off, const int *__restrict__ shapes,
+                             const int *__restrict__ pairs, int nfields) {
+    const int pf = blockIdx.y;
+    const int pr = pf / nfields, f = pf - pr * nfields;
+    const int b = pairs[3 * pr], face = pairs[3 * pr + 1], nb = pairs[3 * pr + 2];
+    const int d = face >> 1, side = face & 1;
+    const int n[3] = {shapes[4 * b], shapes[4 * b + 1], shapes[4 * b + 2]};
+    const int ng = shapes[4 * b + 3];
+    const int m[3] = {shapes[4 * nb], shapes[4 * nb + 1], shapes[4 * nb + 2]};
+    const int ta = d == 0 ? n[1] : n[0];   // extents along the face, first one fastest
+    const int tb = d == 2 ? n[1] : n[2];
+    const int count = ng * ta * tb;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    int c[3], layer;
+    if (d == 0) {   // x faces: layer fastest (rows of ng contiguous nodes), then y, z
+        layer = r % ng;
+        const int q = r / ng;
+        c[1] = q % ta;
+        c[2] = q / ta;
+    } else {        // y and z faces: x fastest, then the other face direction, then the layer
+        c[0] = r % ta;
+        const int q = r / ta;
+        const int o = q % tb;
+        layer = q / tb;
+        if (d == 1) c[2] = o; else c[1] = o;
+    }
+    int g[3] = {c[0], c[1], c[2]}, s[3] = {c[0], c[1], c[2]};
+    g[d] = side ? n[d] + layer : layer - ng;
+    s[d] = side ? layer : m[d] - ng + layer;
+    const int64_t PXb = n[0] + 2 * ng, PYb = n[1] + 2 * ng, PZb = n[2] + 2 * ng;
+    const int64_t PXn = m[0] + 2 * ng, PYn = m[1] + 2 * ng, PZn = m[2] + 2 * ng;
+    const int64_t dst = off[b] + (int64_t)f * PXb * PYb * PZb + ((g[2] + ng) * PYb + (g[1] + ng)) * PXb + g[0] + ng;
+    const int64_t src = off[nb] + (int64_t)f * PXn * PYn * PZn + ((s[2] + ng) * PYn + (s[1] + ng)) * PXn + s[0] + ng;
+    data[dst] = data[src];
 }
 
 template <typename T>
@@ -178,6 +223,19 @@ hipError_t launch_halo(int f32, void *data, const int64_t *off_dev, int nx, int 
     else
         hipLaunchKernelGGL(k_halo<double>, grid, dim3(256), 0, st, (double *)data, off_dev, nx, ny, nz, ng, nfields, bx,
                            by, bz, (int)per_field);
+    return hipGetLastError();
+}
+
+hipError_t launch_halo_table(int f32, void *data, const int64_t *off_dev, const int *shapes_dev, const int *pairs_dev,
+                             int npairs, int nfields, int max_face, hipStream_t st) {
+    if (npairs == 0 || max_face == 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_face + 255) / 256), (unsigned)(npairs * nfields));
+    if (f32)
+        hipLaunchKernelGGL(k_halo_table<float>, grid, dim3(256), 0, st, (float *)data, off_dev, shapes_dev, pairs_dev,
+                           nfields);
+    else
+        hipLaunchKernelGGL(k_halo_table<double>, grid, dim3(256), 0, st, (double *)data, off_dev, shapes_dev,
+                           pairs_dev, nfields);
     return hipGetLastError();
 }
 

@@ -167,6 +167,10 @@ struct cfd_plan {
     // with stage epilogues (EpiDesc per pass); ok once their kernels exist
     bool wave_fused = false, wave_fused_ok = false;
     DevBuf d_epi;
+    // ghost exchange by neighbour table: (block, face, neighbour) triples,
+    // room for every face allocated at creation; n_hpairs < 0 until set
+    DevBuf d_hpairs;
+    int n_hpairs = -1, hface_max = 0;
 
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -207,6 +211,7 @@ struct cfd_plan {
         d_msegs.release();
         d_count.release();
         d_epi.release();
+        d_hpairs.release();
         release_iteration();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
@@ -1230,6 +1235,7 @@ cfd_status upload_layout(cfd_plan *p) {
     HIPCHK(hipMemcpy(p->d_outoff.p, p->out_off.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
     HIPCHK(dmalloc((void **)&p->d_inoff.p, nb * sizeof(int64_t)));
     HIPCHK(hipMemcpy(p->d_inoff.p, p->in_off.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(dmalloc((void **)&p->d_hpairs.p, (size_t)18 * nb * sizeof(int)));
     return CFD_OK;
 }
 
@@ -2267,6 +2273,59 @@ cfd_status cfd_halo_exchange(cfd_plan *p, void *data_dev, int bx, int by, int bz
     hipError_t e = launch_halo(p->dtype != CFD_F64, data_dev, (const int64_t *)p->d_inoff.p, b0.n[0], b0.n[1],
                                b0.n[2], b0.ng, p->nfields, bx, by, bz, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launching halo exchange");
+    return CFD_OK;
+}
+
+cfd_status cfd_plan_set_neighbors(cfd_plan *p, const int *nbr) {
+    if (!p || !nbr) return fail(CFD_EINVAL, "cfd_plan_set_neighbors: null argument");
+    const int nb = (int)p->blocks.size();
+    std::vector<int> pairs;
+    int64_t fmax = 0;
+    for (int b = 0; b < nb; ++b)
+        for (int face = 0; face < 6; ++face) {
+            const int q = nbr[6 * b + face];
+            if (q == -1) continue;
+            if (q < 0 || q >= nb) return fail(CFD_EINVAL, "cfd_plan_set_neighbors: neighbour index out of range");
+            const cfd_block &A = p->blocks[b], &B = p->blocks[q];
+            const int d = face >> 1;
+            const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;   // the directions along the face
+            char buf[200];
+            if (A.ng != B.ng || A.n[t0] != B.n[t0] || A.n[t1] != B.n[t1]) {
+                std::snprintf(buf, sizeof buf, "cfd_plan_set_neighbors: face %d of block %d does not conform to "
+                              "block %d (extents along the face and ghost widths must agree)", face, b, q);
+                return fail(CFD_ESHAPE, buf);
+            }
+            if (B.n[d] < A.ng) {
+                std::snprintf(buf, sizeof buf, "cfd_plan_set_neighbors: block %d has fewer than ng = %d nodes "
+                              "along direction %d", q, A.ng, d);
+                return fail(CFD_ESHAPE, buf);
+            }
+            const int64_t PX = A.n[0] + 2 * A.ng, PY = A.n[1] + 2 * A.ng, PZ = A.n[2] + 2 * A.ng;
+            if (PX * PY * PZ * p->nfields >= (int64_t(1) << 40))
+                return fail(CFD_EUNSUPPORTED, "cfd_plan_set_neighbors: block too large");
+            fmax = std::max<int64_t>(fmax, (int64_t)A.ng * A.n[t0] * A.n[t1]);
+            pairs.insert(pairs.end(), {b, face, q});
+        }
+    const int np = (int)(pairs.size() / 3);
+    if (fmax >= (int64_t(1) << 31) || (int64_t)np * p->nfields > 65535)
+        return fail(CFD_EUNSUPPORTED, "cfd_plan_set_neighbors: faces or face-fields too many for one launch");
+    HIPCHK(hipSetDevice(p->device));
+    if (np > 0) HIPCHK(hipMemcpy(p->d_hpairs.p, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice));
+    p->n_hpairs = np;
+    p->hface_max = (int)fmax;
+    return CFD_OK;
+}
+
+cfd_status cfd_halo_exchange_table(cfd_plan *p, void *data_dev, void *stream) {
+    if (!p || !data_dev) return fail(CFD_EINVAL, "cfd_halo_exchange_table: null argument");
+    if (p->n_hpairs < 0) return fail(CFD_EINVAL, "cfd_halo_exchange_table: no neighbour table set");
+    if (((uintptr_t)data_dev % elem_size(p->dtype)))
+        return fail(CFD_EINVAL, "cfd_halo_exchange_table: misaligned buffer");
+    HIPCHK(hipSetDevice(p->device));
+    hipError_t e = launch_halo_table(p->dtype != CFD_F64, data_dev, (const int64_t *)p->d_inoff.p,
+                                     (const int *)p->d_shapes.p, (const int *)p->d_hpairs.p, p->n_hpairs, p->nfields,
+                                     p->hface_max, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launching the table ghost exchange");
     return CFD_OK;
 }
 

@@ -154,3 +154,126 @@ def test_fused_stage_halo_rejects_bad_lattices(cuda):
     assert e.value.status == _lib.CFD_EINVAL
     call(good, (2, 1, 1))                  # the valid lattice runs
     torch.cuda.synchronize()
+
+
+def _lattice_table(bx, by, bz):
+    t = []
+    for b in range(bx * by * bz):
+        kx, ky, kz = b % bx, (b // bx) % by, b // (bx * by)
+        idx = lambda x, y, z: ((z % bz) * by + (y % by)) * bx + (x % bx)
+        t.append([idx(kx - 1, ky, kz), idx(kx + 1, ky, kz), idx(kx, ky - 1, kz), idx(kx, ky + 1, kz),
+                  idx(kx, ky, kz - 1), idx(kx, ky, kz + 1)])
+    return t
+
+
+def _split_state(data, blocks, nfields):
+    """Per-block, per-field [z][y][x] views of the flat plan input (default layout)."""
+    out, off = [], 0
+    for b in blocks:
+        ng = b["ng"]
+        shp = tuple(e + 2 * ng for e in reversed(b["n"]))
+        size = int(np.prod(shp))
+        out.append([data[off + f * size: off + (f + 1) * size].reshape(shp) for f in range(nfields)])
+        off += nfields * size
+    return out
+
+
+def test_halo_table_equals_lattice_exchange_and_oracle(cuda):
+    """cfd_halo_exchange_table with a periodic lattice's table = cfd_halo_exchange = the oracle."""
+    import torch
+    import paper_2302_14858_amd as P
+    wl = synth.wave192(n=24, blocks_per_dim=2, ng=4)
+    blocks = _blocks(wl)
+    plan = P.Plan(blocks, 5, [(P.Scheme.named("(1)Q1_3[1]"), 0)])
+    plan.set_neighbors(_lattice_table(2, 2, 2))
+    rng = np.random.default_rng(8)
+    data = rng.standard_normal(wl.data.size)
+    x = torch.from_numpy(data).cuda()
+    y = x.clone()
+    plan.halo_exchange(x, 2, 2, 2)
+    plan.halo_exchange_table(y)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    st = _split_state(data.copy(), blocks, 5)
+    W.fill_ghosts_table(st, 4, _lattice_table(2, 2, 2))
+    ref = np.concatenate([a.ravel() for blk in st for a in blk])
+    assert np.array_equal(y.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_halo_table_uneven_tiling(cuda, dtype):
+    """Blocks of different extents along x (conforming faces), blocks that are their own neighbour and
+    faces left alone (-1), against the oracle; replayed from a captured graph too."""
+    import torch
+    import paper_2302_14858_amd as P
+    ng = 4
+    C = synth.CLOSURE
+    blocks = [dict(n=(nx, 10, 6), ng=ng, h=(0.1, 0.1, 0.1), boundary=(C, C, C)) for nx in (12, 20, 8)]
+    blocks.append(dict(n=(12, 9, 6), ng=ng, h=(0.1, 0.1, 0.1), boundary=(C, C, C)))   # only its own neighbour
+    table = [[2, 1, 0, 0, 0, 0], [0, 2, 1, 1, -1, -1], [1, 0, 2, 2, 2, 2], [3, 3, -1, 3, 3, -1]]
+    plan = P.Plan(blocks, 3, [(P.Scheme.named("(1)Q1_3[1]"), 0)], dtype=dtype)
+    plan.set_neighbors(table)
+    nin, _ = plan.sizes()
+    tdt = torch.float64 if dtype == 0 else torch.float32
+    rng = np.random.default_rng(9)
+    host = rng.standard_normal(nin).astype(np.float64 if dtype == 0 else np.float32)
+    x = torch.from_numpy(host.copy()).cuda()
+    plan.halo_exchange_table(x)
+    torch.cuda.synchronize()
+    st = _split_state(host.astype(np.float64), blocks, 3)
+    W.fill_ghosts_table(st, ng, table)
+    ref = np.concatenate([a.ravel() for blk in st for a in blk])
+    assert np.array_equal(x.double().cpu().numpy(), ref)
+    # captured: the same exchange replayed on fresh data
+    g = torch.cuda.CUDAGraph()
+    z = torch.from_numpy(host.copy()).cuda()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.halo_exchange_table(z, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    z.copy_(torch.from_numpy(host.copy()).to(device="cuda", dtype=tdt))
+    with torch.cuda.graph(g):
+        plan.halo_exchange_table(z, stream=torch.cuda.current_stream())
+    for _ in range(2):
+        z.copy_(torch.from_numpy(host.copy()).to(device="cuda", dtype=tdt))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(z, x)
+
+
+def test_halo_table_rejections(cuda):
+    """Host checks of cfd_plan_set_neighbors and cfd_halo_exchange_table."""
+    import torch
+    import paper_2302_14858_amd as P
+    from paper_2302_14858_amd import _lib
+    C = synth.CLOSURE
+    blocks = [dict(n=(12, 10, 6), ng=4, h=(0.1,) * 3, boundary=(C,) * 3),
+              dict(n=(12, 8, 6), ng=4, h=(0.1,) * 3, boundary=(C,) * 3),
+              dict(n=(3, 10, 6), ng=4, h=(0.1,) * 3, boundary=(C,) * 3)]
+    plan = P.Plan(blocks, 1, [(P.Scheme.named("(1)E3"), 1)])
+    nin, _ = plan.sizes()
+    x = torch.zeros(nin, dtype=torch.float64, device="cuda")
+
+    def status(fn):
+        with pytest.raises(P.CfdError) as e:
+            fn()
+        return e.value.status
+
+    assert status(lambda: plan.halo_exchange_table(x)) == _lib.CFD_EINVAL                  # no table yet
+    none = [[-1] * 6 for _ in range(3)]
+    bad = [r[:] for r in none]
+    bad[0][1] = 3
+    assert status(lambda: plan.set_neighbors(bad)) == _lib.CFD_EINVAL                       # out of range
+    bad = [r[:] for r in none]
+    bad[0][1] = 1                                                                           # ny 10 vs 8
+    assert status(lambda: plan.set_neighbors(bad)) == _lib.CFD_ESHAPE
+    bad = [r[:] for r in none]
+    bad[0][1] = 2                                                                           # 3 < ng nodes
+    assert status(lambda: plan.set_neighbors(bad)) == _lib.CFD_ESHAPE
+    ok = [r[:] for r in none]
+    ok[0][0] = ok[0][1] = 0
+    plan.set_neighbors(ok)
+    plan.halo_exchange_table(x)
+    torch.cuda.synchronize()

@@ -58,3 +58,67 @@ def test_ghost_fill_equals_periodic_sampling():
         for face in ((slice(0, 4), sl, sl), (slice(16, 20), sl, sl), (sl, slice(0, 4), sl),
                      (sl, slice(16, 20), sl), (sl, sl, slice(0, 4)), (sl, sl, slice(16, 20))):
             assert np.allclose(st[b][0][face], ref[face], atol=1e-13)
+
+
+def _lattice_table(bx, by, bz):
+    """Neighbour table of a periodic bx*by*bz lattice (block (kz by + ky) bx + kx)."""
+    t = []
+    for b in range(bx * by * bz):
+        kx, ky, kz = b % bx, (b // bx) % by, b // (bx * by)
+        idx = lambda x, y, z: ((z % bz) * by + (y % by)) * bx + (x % bx)
+        t.append([idx(kx - 1, ky, kz), idx(kx + 1, ky, kz), idx(kx, ky - 1, kz), idx(kx, ky + 1, kz),
+                  idx(kx, ky, kz - 1), idx(kx, ky, kz + 1)])
+    return t
+
+
+def test_ghost_fill_table_equals_lattice_fill():
+    """The table form with a lattice's table is the lattice form, exactly."""
+    wl = synth.wave192(n=24, blocks_per_dim=2, ng=4)
+    a, b = _state_from(wl), _state_from(wl)
+    rng = np.random.default_rng(3)
+    for blk in a:
+        for x in blk:
+            x[...] = rng.standard_normal(x.shape)
+    b = [[x.copy() for x in blk] for blk in a]
+    W.fill_ghosts(a, 12, 4, (2, 2, 2))
+    W.fill_ghosts_table(b, 4, _lattice_table(2, 2, 2))
+    for ba, bb in zip(a, b):
+        for xa, xb in zip(ba, bb):
+            assert np.array_equal(xa, xb)
+
+
+def test_ghost_fill_table_samples_a_periodic_function_on_an_uneven_tiling():
+    """Three blocks of 12, 20 and 8 nodes along x tile a periodic interval (y and z: each block its own
+    neighbour, periodic); after the fill every face ghost holds the function at its position, and the
+    faces marked -1 keep their old values."""
+    ng, ny, nz, h = 4, 10, 6, 0.1
+    nxs = [12, 20, 8]
+    X = sum(nxs) * h
+    x0 = np.cumsum([0] + nxs[:-1]) * h
+
+    def f(x, y, z):
+        return np.sin(2 * np.pi * x / X) + np.cos(2 * np.pi * y / (ny * h)) + np.sin(4 * np.pi * z / (nz * h))
+
+    st, ref = [], []
+    for b, nx in enumerate(nxs):
+        xs = x0[b] + (np.arange(nx + 2 * ng) - ng) * h
+        ys = (np.arange(ny + 2 * ng) - ng) * h
+        zs = (np.arange(nz + 2 * ng) - ng) * h
+        full = f(xs[None, None, :], ys[None, :, None], zs[:, None, None])
+        ref.append(full)
+        a = np.full_like(full, -7.0)
+        a[ng:-ng, ng:-ng, ng:-ng] = full[ng:-ng, ng:-ng, ng:-ng]
+        st.append([a])
+    table = [[2, 1, 0, 0, 0, 0], [0, 2, 1, 1, -1, -1], [1, 0, 2, 2, 2, 2]]
+    W.fill_ghosts_table(st, ng, table)
+    sl = slice(ng, -ng)
+    for b in range(3):
+        a, r = st[b][0], ref[b]
+        faces = [(sl, sl, slice(0, ng)), (sl, sl, slice(-ng, None)), (sl, slice(0, ng), sl),
+                 (sl, slice(-ng, None), sl), (slice(0, ng), sl, sl), (slice(-ng, None), sl, sl)]
+        for face, region in enumerate(faces):
+            if table[b][face] < 0:
+                assert np.all(a[region] == -7.0)
+            else:
+                assert np.allclose(a[region], r[region], atol=1e-12), (b, face)
+        assert a[0, 0, 0] == -7.0            # corners untouched
