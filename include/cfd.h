@@ -423,6 +423,29 @@ cfd_status cfd_plan_set_neighbors(cfd_plan *p, const int *nbr);
  * (graph-safe).  CFD_EINVAL if no table has been set. */
 cfd_status cfd_halo_exchange_table(cfd_plan *p, void *data_dev, void *stream);
 
+/* Vertex-centred tilings (Eq. gridDisc, G_VC: a block of N_B cells holds
+ * N_B + 1 nodes, and neighbours share their extremal node).  As
+ * cfd_plan_set_neighbors, but the exchange then continues the ghost layers
+ * past the shared node (on the + face ghost layer l = the neighbour's node
+ * 1 + l, on the - face node n - 1 - ng + l), the neighbour needs ng + 1
+ * nodes along the normal, and every face must be mutual (if block b names q
+ * across face f, q names b across the opposite face).  The table also
+ * drives cfd_shared_node_average.  Errors as cfd_plan_set_neighbors, and
+ * CFD_EINVAL for a face that is not mutual. */
+cfd_status cfd_plan_set_neighbors_vc(cfd_plan *p, const int *nbr);
+
+/* Shared-node averaging of vertex-centred blocks (the averaging of shared
+ * extremal nodes that the sampling figure and the footnote on the
+ * communication matrix of Sec. 2.4 call for): along x, then y, then z, a
+ * block's last node and its + neighbour's first node, the same point, both
+ * receive the mean of the two values, so a node shared by 2, 4 or 8 blocks
+ * ends with the mean of all its copies.  output = 0: data_dev is the plan's
+ * input buffer (every field; ghosts untouched); output = 1: the plan's output
+ * buffer (every operator and field), e.g. to make the derivatives each block
+ * computed at its shared nodes single-valued.  Three launches, nothing
+ * allocated.  CFD_EINVAL if no vertex-centred table has been set. */
+cfd_status cfd_shared_node_average(cfd_plan *p, void *data_dev, int output, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Element-wise stage kernels for method-of-lines time stepping (classical   */
 /* ERK4, Sec. 3.1): y = a*x + b*y and z = x + c*y over n elements.           */

@@ -70,14 +70,18 @@ def fill_ghosts(state, nb, ng, lattice):
             a[ng + nb:, sl, sl] = zp[ng:2 * ng, sl, sl]
 
 
-def fill_ghosts_table(state, ng, nbr):
+def fill_ghosts_table(state, ng, nbr, shared=0):
     """Face ghosts by a neighbour table (Sec. 2.4: a block's ghost layers hold its neighbours' data).
 
     state[b][f]: arrays [z][y][x] with ng ghosts on every side (blocks may differ in extent);
     nbr[b][face] = block across face (x-, x+, y-, y+, z-, z+) or -1 (ghosts left as they are).
     Ghost layer l of the + face is the neighbour's interior layer l, of the - face its layer n - ng + l,
     at the same coordinates along the face; edges and corners are not touched.  Reads are taken from a
-    copy made before any write, so a block may be its own neighbour."""
+    copy made before any write, so a block may be its own neighbour.
+
+    shared = 1: vertex-centred sampling (Eq. gridDisc, G_VC): neighbouring blocks share their extremal
+    node, so the ghost layers continue past it: layer l of the + face is the neighbour's node 1 + l, of
+    the - face its node n - 1 - ng + l."""
     src = [[a.copy() for a in blk] for blk in state]
     for b in range(len(state)):
         for face in range(6):
@@ -94,11 +98,36 @@ def fill_ghosts_table(state, ng, nbr):
                 idx_s = [slice(ng, s_.shape[k] - ng) for k in range(3)]
                 if side:
                     idx_a[ax] = slice(ng + n_a, 2 * ng + n_a)
-                    idx_s[ax] = slice(ng, 2 * ng)
+                    idx_s[ax] = slice(ng + shared, 2 * ng + shared)
                 else:
                     idx_a[ax] = slice(0, ng)
-                    idx_s[ax] = slice(n_q, n_q + ng)
+                    idx_s[ax] = slice(n_q - shared, n_q + ng - shared)
                 a[tuple(idx_a)] = s_[tuple(idx_s)]
+
+
+def shared_node_average(blocks, ng, nbr):
+    """Vertex-centred tilings (Eq. gridDisc, G_VC; the averaging of shared nodes the sampling figure and
+    the communication matrix's footnote call for): block b's last node along d and its + neighbour's
+    first node are one point; both get the mean of the two values.  Directions x, y, z in turn, so a
+    node shared by 4 (edge) or 8 (corner) blocks ends with the mean of all its copies.
+
+    blocks[b]: list of arrays [z][y][x] with ng ghost layers on every side (ng = 0 for interior-only
+    outputs); averaged in place over the face's interior nodes."""
+    for d in range(3):
+        ax = 2 - d
+        for b in range(len(blocks)):
+            q = nbr[b][2 * d + 1]
+            if q < 0:
+                continue
+            for a, c in zip(blocks[b], blocks[q]):
+                n_a = a.shape[ax] - 2 * ng
+                ia = [slice(ng, a.shape[k] - ng) for k in range(3)]
+                ic = [slice(ng, c.shape[k] - ng) for k in range(3)]
+                ia[ax] = ng + n_a - 1
+                ic[ax] = ng
+                m = 0.5 * (a[tuple(ia)] + c[tuple(ic)])
+                a[tuple(ia)] = m
+                c[tuple(ic)] = m
 
 
 def rhs_blocks(s: Scheme, state, nb, ng, h, periodic):

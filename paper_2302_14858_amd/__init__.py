@@ -329,6 +329,21 @@ class Plan:
 
     halo_exchange_table = cfd_halo_exchange_table
 
+    def cfd_plan_set_neighbors_vc(self, nbr) -> None:
+        """Vertex-centred tiling: neighbours share their extremal nodes (table as set_neighbors)."""
+        flat = [int(v) for row in nbr for v in row]
+        if len(flat) != 6 * self.nblocks:
+            raise ValueError("need 6 neighbours per block")
+        arr = (ctypes.c_int * len(flat))(*flat)
+        check(lib().cfd_plan_set_neighbors_vc(self._h, arr))
+
+    set_neighbors_vc = cfd_plan_set_neighbors_vc
+
+    def cfd_shared_node_average(self, data, output: bool = False, stream=None) -> None:
+        check(lib().cfd_shared_node_average(self._h, _dev_ptr(data), int(bool(output)), _stream_ptr(stream)))
+
+    shared_node_average = cfd_shared_node_average
+
     def __del__(self):
         try:
             if self._h:

@@ -66,6 +66,8 @@ SIGNATURES = {
     "cfd_halo_exchange": (_i, [_vp, _vp, _i, _i, _i, _vp]),
     "cfd_plan_set_neighbors": (_i, [_vp, _vp]),
     "cfd_halo_exchange_table": (_i, [_vp, _vp, _vp]),
+    "cfd_plan_set_neighbors_vc": (_i, [_vp, _vp]),
+    "cfd_shared_node_average": (_i, [_vp, _vp, _i, _vp]),
     "cfd_axpby": (_i, [_i, _ll, _d, _vp, _d, _vp, _vp]),
     "cfd_xpcy": (_i, [_i, _ll, _vp, _d, _vp, _vp, _vp]),
     "cfd_wave_rk_stage": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp]),

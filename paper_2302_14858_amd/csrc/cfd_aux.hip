@@ -74,12 +74,14 @@ __global__ void k_halo(T *__restrict__ data, const int64_t *__restrict__ off, in
 // face = 2 d + side (d: 0 x, 1 y, 2 z; side 1: the + face).  blockIdx.y is
 // (pair, field), wave-uniform; thread r takes ghost r of the face's ng layers
 // (x fastest where x runs along the face, so a wave's stores are contiguous).
-// b's ghost layer l on the + face is nb's interior layer l, on the - face
-// nb's interior layer n_nb - ng + l; the coordinates along the face are the
-// same in both blocks (conforming faces).  shapes: (nx, ny, nz, ng) per block.
+// b's ghost layer l on the + face is nb's interior layer l + shift, on the -
+// face nb's interior layer n_nb - ng + l - shift (shift 1: vertex-centred
+// blocks, whose extremal nodes are shared, so the ghosts continue past the
+// shared node); the coordinates along the face are the same in both blocks
+// (conforming faces).  shapes: (nx, ny, nz, ng) per block.
 template <typename T>
 __global__ void k_halo_table(T *__restrict__ data, const int64_t *__restrict__ off, const int *__restrict__ shapes,
-                             const int *__restrict__ pairs, int nfields) {
+                             const int *__restrict__ pairs, int nfields, int shift) {
     const int pf = blockIdx.y;
     const int pr = pf / nfields, f = pf - pr * nfields;
     const int b = pairs[3 * pr], face = pairs[3 * pr + 1], nb = pairs[3 * pr + 2];
@@ -107,12 +109,47 @@ __global__ void k_halo_table(T *__restrict__ data, const int64_t *__restrict__ o
     }
     int g[3] = {c[0], c[1], c[2]}, s[3] = {c[0], c[1], c[2]};
     g[d] = side ? n[d] + layer : layer - ng;
-    s[d] = side ? layer : m[d] - ng + layer;
+    s[d] = side ? layer + shift : m[d] - ng + layer - shift;
     const int64_t PXb = n[0] + 2 * ng, PYb = n[1] + 2 * ng, PZb = n[2] + 2 * ng;
     const int64_t PXn = m[0] + 2 * ng, PYn = m[1] + 2 * ng, PZn = m[2] + 2 * ng;
     const int64_t dst = off[b] + (int64_t)f * PXb * PYb * PZb + ((g[2] + ng) * PYb + (g[1] + ng)) * PXb + g[0] + ng;
     const int64_t src = off[nb] + (int64_t)f * PXn * PYn * PZn + ((s[2] + ng) * PYn + (s[1] + ng)) * PXn + s[0] + ng;
     data[dst] = data[src];
+}
+
+// Shared nodes of vertex-centred blocks along direction d: pair = (b, nb),
+// nb across b's + face; b's last node and nb's first node along d are one
+// point and both get the mean of the two values.  blockIdx.y is (pair, slot):
+// slot = field of the input layout (ghosted = 1: ng ghost layers) or
+// operator-field of the output layout (ghosted = 0, slots of npts elements).
+// Within one direction every shared node belongs to one pair, so the pairs
+// do not race; the host runs x, y, z in turn.
+template <typename T>
+__global__ void k_shared_avg(T *__restrict__ data, const int64_t *__restrict__ off, const int *__restrict__ shapes,
+                             const int *__restrict__ pairs, int nslots, int ghosted, int d) {
+    const int pf = blockIdx.y;
+    const int pr = pf / nslots, sl = pf - pr * nslots;
+    const int b = pairs[2 * pr], nb = pairs[2 * pr + 1];
+    const int n[3] = {shapes[4 * b], shapes[4 * b + 1], shapes[4 * b + 2]};
+    const int m[3] = {shapes[4 * nb], shapes[4 * nb + 1], shapes[4 * nb + 2]};
+    const int g = ghosted ? shapes[4 * b + 3] : 0;
+    const int ta = d == 0 ? n[1] : n[0];
+    const int tb = d == 2 ? n[1] : n[2];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= ta * tb) return;
+    int c[3];
+    c[d == 0 ? 1 : 0] = r % ta;
+    c[d == 2 ? 1 : 2] = r / ta;
+    int ca[3] = {c[0], c[1], c[2]}, cb[3] = {c[0], c[1], c[2]};
+    ca[d] = n[d] - 1;
+    cb[d] = 0;
+    const int64_t PXa = n[0] + 2 * g, PYa = n[1] + 2 * g, PZa = n[2] + 2 * g;
+    const int64_t PXb = m[0] + 2 * g, PYb = m[1] + 2 * g, PZb = m[2] + 2 * g;
+    const int64_t ia = off[b] + (int64_t)sl * PXa * PYa * PZa + ((ca[2] + g) * PYa + (ca[1] + g)) * PXa + ca[0] + g;
+    const int64_t ib = off[nb] + (int64_t)sl * PXb * PYb * PZb + ((cb[2] + g) * PYb + (cb[1] + g)) * PXb + cb[0] + g;
+    const T v = (data[ia] + data[ib]) * T(0.5);
+    data[ia] = v;
+    data[ib] = v;
 }
 
 template <typename T>
@@ -227,15 +264,28 @@ hipError_t launch_halo(int f32, void *data, const int64_t *off_dev, int nx, int 
 }
 
 hipError_t launch_halo_table(int f32, void *data, const int64_t *off_dev, const int *shapes_dev, const int *pairs_dev,
-                             int npairs, int nfields, int max_face, hipStream_t st) {
+                             int npairs, int nfields, int max_face, int shift, hipStream_t st) {
     if (npairs == 0 || max_face == 0) return hipSuccess;
     const dim3 grid((unsigned)((max_face + 255) / 256), (unsigned)(npairs * nfields));
     if (f32)
         hipLaunchKernelGGL(k_halo_table<float>, grid, dim3(256), 0, st, (float *)data, off_dev, shapes_dev, pairs_dev,
-                           nfields);
+                           nfields, shift);
     else
         hipLaunchKernelGGL(k_halo_table<double>, grid, dim3(256), 0, st, (double *)data, off_dev, shapes_dev,
-                           pairs_dev, nfields);
+                           pairs_dev, nfields, shift);
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_avg(int f32, void *data, const int64_t *off_dev, const int *shapes_dev, const int *pairs_dev,
+                             int npairs, int nslots, int ghosted, int d, int max_face, hipStream_t st) {
+    if (npairs == 0 || max_face == 0 || nslots == 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_face + 255) / 256), (unsigned)(npairs * nslots));
+    if (f32)
+        hipLaunchKernelGGL(k_shared_avg<float>, grid, dim3(256), 0, st, (float *)data, off_dev, shapes_dev, pairs_dev,
+                           nslots, ghosted, d);
+    else
+        hipLaunchKernelGGL(k_shared_avg<double>, grid, dim3(256), 0, st, (double *)data, off_dev, shapes_dev,
+                           pairs_dev, nslots, ghosted, d);
     return hipGetLastError();
 }
 

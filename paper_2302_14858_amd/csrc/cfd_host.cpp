@@ -171,6 +171,11 @@ struct cfd_plan {
     // room for every face allocated at creation; n_hpairs < 0 until set
     DevBuf d_hpairs;
     int n_hpairs = -1, hface_max = 0;
+    // vertex-centred tables: ghosts continue past the shared node (hshift 1);
+    // (block, + neighbour) pairs per direction for the shared-node average
+    int hshift = 0;
+    DevBuf d_vpairs;
+    int nvp[3] = {0, 0, 0}, voff[3] = {0, 0, 0}, vface_max[3] = {0, 0, 0};
 
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -212,6 +217,7 @@ struct cfd_plan {
         d_count.release();
         d_epi.release();
         d_hpairs.release();
+        d_vpairs.release();
         release_iteration();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
@@ -1236,6 +1242,7 @@ cfd_status upload_layout(cfd_plan *p) {
     HIPCHK(dmalloc((void **)&p->d_inoff.p, nb * sizeof(int64_t)));
     HIPCHK(hipMemcpy(p->d_inoff.p, p->in_off.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
     HIPCHK(dmalloc((void **)&p->d_hpairs.p, (size_t)18 * nb * sizeof(int)));
+    HIPCHK(dmalloc((void **)&p->d_vpairs.p, (size_t)6 * nb * sizeof(int)));
     return CFD_OK;
 }
 
@@ -2276,43 +2283,97 @@ cfd_status cfd_halo_exchange(cfd_plan *p, void *data_dev, int bx, int by, int bz
     return CFD_OK;
 }
 
-cfd_status cfd_plan_set_neighbors(cfd_plan *p, const int *nbr) {
-    if (!p || !nbr) return fail(CFD_EINVAL, "cfd_plan_set_neighbors: null argument");
+// Neighbour table of either sampling (shared = 1: vertex-centred blocks whose
+// extremal nodes coincide with their neighbours').
+static cfd_status set_neighbors_impl(cfd_plan *p, const int *nbr, int shared, const char *who) {
+    if (!p || !nbr) return fail(CFD_EINVAL, std::string(who) + ": null argument");
     const int nb = (int)p->blocks.size();
-    std::vector<int> pairs;
-    int64_t fmax = 0;
+    std::vector<int> pairs, vp[3];
+    int64_t fmax = 0, vmax[3] = {0, 0, 0};
+    char buf[240];
     for (int b = 0; b < nb; ++b)
         for (int face = 0; face < 6; ++face) {
             const int q = nbr[6 * b + face];
             if (q == -1) continue;
-            if (q < 0 || q >= nb) return fail(CFD_EINVAL, "cfd_plan_set_neighbors: neighbour index out of range");
+            if (q < 0 || q >= nb) return fail(CFD_EINVAL, std::string(who) + ": neighbour index out of range");
             const cfd_block &A = p->blocks[b], &B = p->blocks[q];
             const int d = face >> 1;
             const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;   // the directions along the face
-            char buf[200];
             if (A.ng != B.ng || A.n[t0] != B.n[t0] || A.n[t1] != B.n[t1]) {
-                std::snprintf(buf, sizeof buf, "cfd_plan_set_neighbors: face %d of block %d does not conform to "
-                              "block %d (extents along the face and ghost widths must agree)", face, b, q);
+                std::snprintf(buf, sizeof buf, "%s: face %d of block %d does not conform to block %d (extents "
+                              "along the face and ghost widths must agree)", who, face, b, q);
                 return fail(CFD_ESHAPE, buf);
             }
-            if (B.n[d] < A.ng) {
-                std::snprintf(buf, sizeof buf, "cfd_plan_set_neighbors: block %d has fewer than ng = %d nodes "
-                              "along direction %d", q, A.ng, d);
+            if (B.n[d] < A.ng + shared || (shared && A.n[d] < 2)) {
+                std::snprintf(buf, sizeof buf, "%s: block %d has fewer than %d nodes along direction %d", who, q,
+                              A.ng + shared, d);
                 return fail(CFD_ESHAPE, buf);
+            }
+            if (shared && nbr[6 * q + (face ^ 1)] != b) {
+                std::snprintf(buf, sizeof buf, "%s: vertex-centred faces must be mutual (block %d face %d names "
+                              "block %d, whose opposite face does not name block %d)", who, b, face, q, b);
+                return fail(CFD_EINVAL, buf);
             }
             const int64_t PX = A.n[0] + 2 * A.ng, PY = A.n[1] + 2 * A.ng, PZ = A.n[2] + 2 * A.ng;
             if (PX * PY * PZ * p->nfields >= (int64_t(1) << 40))
-                return fail(CFD_EUNSUPPORTED, "cfd_plan_set_neighbors: block too large");
+                return fail(CFD_EUNSUPPORTED, std::string(who) + ": block too large");
             fmax = std::max<int64_t>(fmax, (int64_t)A.ng * A.n[t0] * A.n[t1]);
             pairs.insert(pairs.end(), {b, face, q});
+            if (shared && (face & 1)) {
+                vp[d].insert(vp[d].end(), {b, q});
+                vmax[d] = std::max<int64_t>(vmax[d], (int64_t)A.n[t0] * A.n[t1]);
+            }
         }
     const int np = (int)(pairs.size() / 3);
-    if (fmax >= (int64_t(1) << 31) || (int64_t)np * p->nfields > 65535)
-        return fail(CFD_EUNSUPPORTED, "cfd_plan_set_neighbors: faces or face-fields too many for one launch");
+    int64_t nslots = 0;
+    for (int nf : p->op_nf) nslots += nf;
+    nslots = std::max<int64_t>(nslots, p->nfields);
+    bool big = fmax >= (int64_t(1) << 31) || (int64_t)np * p->nfields > 65535;
+    for (int d = 0; d < 3; ++d) big = big || (int64_t)(vp[d].size() / 2) * nslots > 65535;
+    if (big) return fail(CFD_EUNSUPPORTED, std::string(who) + ": faces or face-fields too many for one launch");
     HIPCHK(hipSetDevice(p->device));
     if (np > 0) HIPCHK(hipMemcpy(p->d_hpairs.p, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice));
+    std::vector<int> allv;
+    for (int d = 0; d < 3; ++d) {
+        p->voff[d] = (int)(allv.size() / 2);
+        p->nvp[d] = (int)(vp[d].size() / 2);
+        p->vface_max[d] = (int)vmax[d];
+        allv.insert(allv.end(), vp[d].begin(), vp[d].end());
+    }
+    if (!allv.empty()) HIPCHK(hipMemcpy(p->d_vpairs.p, allv.data(), allv.size() * sizeof(int), hipMemcpyHostToDevice));
     p->n_hpairs = np;
     p->hface_max = (int)fmax;
+    p->hshift = shared;
+    return CFD_OK;
+}
+
+cfd_status cfd_plan_set_neighbors(cfd_plan *p, const int *nbr) {
+    return set_neighbors_impl(p, nbr, 0, "cfd_plan_set_neighbors");
+}
+
+cfd_status cfd_plan_set_neighbors_vc(cfd_plan *p, const int *nbr) {
+    return set_neighbors_impl(p, nbr, 1, "cfd_plan_set_neighbors_vc");
+}
+
+cfd_status cfd_shared_node_average(cfd_plan *p, void *data_dev, int output, void *stream) {
+    if (!p || !data_dev) return fail(CFD_EINVAL, "cfd_shared_node_average: null argument");
+    if (p->n_hpairs < 0 || p->hshift != 1)
+        return fail(CFD_EINVAL, "cfd_shared_node_average: no vertex-centred neighbour table set");
+    if (((uintptr_t)data_dev % elem_size(p->dtype)))
+        return fail(CFD_EINVAL, "cfd_shared_node_average: misaligned buffer");
+    int nslots = p->nfields;
+    if (output) {
+        nslots = 0;
+        for (int nf : p->op_nf) nslots += nf;
+    }
+    HIPCHK(hipSetDevice(p->device));
+    const int64_t *off = (const int64_t *)(output ? p->d_outoff.p : p->d_inoff.p);
+    for (int d = 0; d < 3; ++d) {
+        hipError_t e = launch_shared_avg(p->dtype != CFD_F64, data_dev, off, (const int *)p->d_shapes.p,
+                                         (const int *)p->d_vpairs.p + 2 * p->voff[d], p->nvp[d], nslots,
+                                         output ? 0 : 1, d, p->vface_max[d], (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "launching the shared-node average");
+    }
     return CFD_OK;
 }
 
@@ -2324,7 +2385,7 @@ cfd_status cfd_halo_exchange_table(cfd_plan *p, void *data_dev, void *stream) {
     HIPCHK(hipSetDevice(p->device));
     hipError_t e = launch_halo_table(p->dtype != CFD_F64, data_dev, (const int64_t *)p->d_inoff.p,
                                      (const int *)p->d_shapes.p, (const int *)p->d_hpairs.p, p->n_hpairs, p->nfields,
-                                     p->hface_max, (hipStream_t)stream);
+                                     p->hface_max, p->hshift, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launching the table ghost exchange");
     return CFD_OK;
 }

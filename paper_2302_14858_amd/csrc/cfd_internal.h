@@ -288,9 +288,14 @@ inline int64_t tab_scratch(int P, int L, int nl) {
 namespace cfd {
 hipError_t launch_halo(int f32, void *data, const int64_t *off_dev, int nx, int ny, int nz, int ng, int nfields,
                        int bx, int by, int bz, hipStream_t st);
-// pairs_dev: npairs triples (block, face 2 d + side, neighbour); max_face: the most ghost nodes of one face
+// pairs_dev: npairs triples (block, face 2 d + side, neighbour); max_face: the most ghost nodes of one face;
+// shift 1: vertex-centred blocks (shared extremal nodes)
 hipError_t launch_halo_table(int f32, void *data, const int64_t *off_dev, const int *shapes_dev, const int *pairs_dev,
-                             int npairs, int nfields, int max_face, hipStream_t st);
+                             int npairs, int nfields, int max_face, int shift, hipStream_t st);
+// shared-node averaging along direction d: pairs_dev: npairs (block, + neighbour); max_face: the most nodes of
+// one face; ghosted 1: input layout (nslots fields), 0: output layout (nslots operator-fields)
+hipError_t launch_shared_avg(int f32, void *data, const int64_t *off_dev, const int *shapes_dev, const int *pairs_dev,
+                             int npairs, int nslots, int ghosted, int d, int max_face, hipStream_t st);
 hipError_t launch_axpby(int f32, int64_t n, double a, const void *x, double b, void *y, hipStream_t st);
 // out[o + e] = (a[ta + e] + b[tb + e]) / 2 for each segment (o, ta, tb, n); a and b in scr
 hipError_t launch_mixed_combine(int f32, int nseg, const int64_t *segs, int64_t max_n, const void *scr, void *out,

@@ -277,3 +277,105 @@ def test_halo_table_rejections(cuda):
     plan.set_neighbors(ok)
     plan.halo_exchange_table(x)
     torch.cuda.synchronize()
+
+
+def _vc_tiling():
+    """Three vertex-centred blocks along x (11, 7 and 9 nodes: N_B + 1 each), y and z periodic onto
+    themselves; ng = 4."""
+    C = synth.CLOSURE
+    blocks = [dict(n=(nx, 7, 6), ng=4, h=(0.1,) * 3, boundary=(C,) * 3) for nx in (11, 7, 9)]
+    table = [[2, 1, 0, 0, 0, 0], [0, 2, 1, 1, 1, 1], [1, 0, 2, 2, 2, 2]]
+    return blocks, table
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_vertex_centred_exchange_and_average(cuda, dtype):
+    """Vertex-centred tiling: the exchange continues past the shared node and the shared-node average
+    (input layout, then the derivatives of the output layout) equals the oracle bit for bit."""
+    import torch
+    import paper_2302_14858_amd as P
+    blocks, table = _vc_tiling()
+    sch = P.Scheme.named("(1)Q1_3[1]")
+    plan = P.Plan(blocks, 2, [(sch, 0), (sch, 1)], dtype=dtype)
+    plan.set_neighbors_vc(table)
+    nin, nout = plan.sizes()
+    npdt = np.float64 if dtype == 0 else np.float32
+    rng = np.random.default_rng(10)
+    host = rng.standard_normal(nin).astype(npdt)
+    x = torch.from_numpy(host.copy()).cuda()
+    plan.halo_exchange_table(x)
+    plan.shared_node_average(x)
+    torch.cuda.synchronize()
+    st = _split_state(host.copy(), blocks, 2)
+    W.fill_ghosts_table(st, 4, table, shared=1)
+    W.shared_node_average(st, 4, table)
+    ref = np.concatenate([a.ravel() for blk in st for a in blk])
+    assert np.array_equal(x.cpu().numpy(), ref)
+    # derivatives of the exchanged, averaged data; then their shared nodes averaged
+    y = torch.full((nout,), float("nan"), dtype=x.dtype, device="cuda")
+    plan.apply(x, y)
+    torch.cuda.synchronize()
+    raw = y.cpu().numpy().copy()
+    plan.shared_node_average(y, output=True)
+    torch.cuda.synchronize()
+    outs, off = [], 0
+    for b in blocks:
+        shp = tuple(reversed(b["n"]))
+        size = int(np.prod(shp))
+        outs.append([raw[off + k * size: off + (k + 1) * size].reshape(shp) for k in range(2 * 2)])
+        off += 4 * size
+    W.shared_node_average(outs, 0, table)
+    ref_out = np.concatenate([a.ravel() for blk in outs for a in blk])
+    assert np.array_equal(y.cpu().numpy(), ref_out)
+
+
+def test_vertex_centred_corner_nodes_on_a_lattice(cuda):
+    """A 2x2x2 periodic lattice of vertex-centred blocks: nodes shared by 2, 4 and 8 blocks end with
+    the mean of their copies, as in the oracle."""
+    import torch
+    import paper_2302_14858_amd as P
+    C = synth.CLOSURE
+    blocks = [dict(n=(6, 6, 6), ng=4, h=(0.1,) * 3, boundary=(C,) * 3) for _ in range(8)]
+    plan = P.Plan(blocks, 1, [(P.Scheme.named("(1)Q1_3[1]"), 0)])
+    table = _lattice_table(2, 2, 2)
+    plan.set_neighbors_vc(table)
+    nin, _ = plan.sizes()
+    host = np.random.default_rng(11).standard_normal(nin)
+    x = torch.from_numpy(host.copy()).cuda()
+    plan.shared_node_average(x)
+    torch.cuda.synchronize()
+    st = _split_state(host.copy(), blocks, 1)
+    W.shared_node_average(st, 4, table)
+    assert np.array_equal(x.cpu().numpy(), np.concatenate([a.ravel() for blk in st for a in blk]))
+
+
+def test_vertex_centred_rejections(cuda):
+    import torch
+    import paper_2302_14858_amd as P
+    from paper_2302_14858_amd import _lib
+    blocks, table = _vc_tiling()
+    plan = P.Plan(blocks, 1, [(P.Scheme.named("(1)Q1_3[1]"), 1)])
+    nin, _ = plan.sizes()
+    x = torch.zeros(nin, dtype=torch.float64, device="cuda")
+
+    def status(fn):
+        with pytest.raises(P.CfdError) as e:
+            fn()
+        return e.value.status
+
+    assert status(lambda: plan.shared_node_average(x)) == _lib.CFD_EINVAL       # no table
+    plan.set_neighbors(table)                                                  # cell-centred table
+    assert status(lambda: plan.shared_node_average(x)) == _lib.CFD_EINVAL
+    bad = [r[:] for r in table]
+    bad[0][1] = 2                                                               # 0 -> 2, but 2's x- is 1
+    assert status(lambda: plan.set_neighbors_vc(bad)) == _lib.CFD_EINVAL
+    thin = [dict(n=(11, 7, 6), ng=4, h=(0.1,) * 3, boundary=(synth.CLOSURE,) * 3),
+            dict(n=(4, 7, 6), ng=4, h=(0.1,) * 3, boundary=(synth.CLOSURE,) * 3)]
+    p2 = P.Plan(thin, 1, [(P.Scheme.named("(1)Q1_3[1]"), 1)])
+    with pytest.raises(P.CfdError) as e:                                        # 4 nodes < ng + 1
+        p2.set_neighbors_vc([[1, 1, -1, -1, -1, -1], [0, 0, -1, -1, -1, -1]])
+    assert e.value.status == _lib.CFD_ESHAPE
+    plan.set_neighbors_vc(table)
+    plan.halo_exchange_table(x)
+    plan.shared_node_average(x)
+    torch.cuda.synchronize()

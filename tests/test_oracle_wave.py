@@ -122,3 +122,75 @@ def test_ghost_fill_table_samples_a_periodic_function_on_an_uneven_tiling():
             else:
                 assert np.allclose(a[region], r[region], atol=1e-12), (b, face)
         assert a[0, 0, 0] == -7.0            # corners untouched
+
+
+def test_vertex_centred_ghost_fill_samples_the_function():
+    """Vertex-centred blocks (N_B + 1 nodes, the extremal node shared with the neighbour, Eq. gridDisc):
+    after the shared fill every face ghost holds the function at its position (the shared node is not
+    repeated)."""
+    ng, h = 3, 0.1
+    nbs = [10, 6, 8]                    # cells per block along x: nodes = N_B + 1
+    ny, nz = 7, 5                       # y, z: one VC block periodic onto itself (N_B = n - 1 cells)
+    X = sum(nbs) * h
+    x0 = np.cumsum([0] + nbs[:-1]) * h
+    Y, Z = (ny - 1) * h, (nz - 1) * h
+
+    def f(x, y, z):
+        return np.sin(2 * np.pi * x / X) * np.cos(2 * np.pi * y / Y) + np.sin(2 * np.pi * z / Z)
+
+    st, ref = [], []
+    for b, nb in enumerate(nbs):
+        xs = x0[b] + (np.arange(nb + 1 + 2 * ng) - ng) * h
+        ys = (np.arange(ny + 2 * ng) - ng) * h
+        zs = (np.arange(nz + 2 * ng) - ng) * h
+        full = f(xs[None, None, :], ys[None, :, None], zs[:, None, None])
+        ref.append(full)
+        a = np.full_like(full, 5.0)
+        a[ng:-ng, ng:-ng, ng:-ng] = full[ng:-ng, ng:-ng, ng:-ng]
+        st.append([a])
+    table = [[2, 1, 0, 0, 0, 0], [0, 2, 1, 1, 1, 1], [1, 0, 2, 2, 2, 2]]
+    W.fill_ghosts_table(st, ng, table, shared=1)
+    sl = slice(ng, -ng)
+    for b in range(3):
+        a, r = st[b][0], ref[b]
+        for region in [(sl, sl, slice(0, ng)), (sl, sl, slice(-ng, None)), (sl, slice(0, ng), sl),
+                       (sl, slice(-ng, None), sl), (slice(0, ng), sl, sl), (slice(-ng, None), sl, sl)]:
+            assert np.allclose(a[region], r[region], atol=1e-12), b
+
+
+def test_shared_node_average_means_every_copy():
+    """A node shared by 2, 4 or 8 vertex-centred blocks ends with the mean of all its copies (the x, y,
+    z sweeps compose to it), interior nodes are untouched, and a second pass changes nothing."""
+    rng = np.random.default_rng(4)
+    n = 5
+    # 2 x 2 x 2 periodic lattice of VC blocks, interior-only arrays (ng = 0)
+    blocks = [[rng.standard_normal((n, n, n))] for _ in range(8)]
+    orig = [[a.copy() for a in blk] for blk in blocks]
+    idx = lambda x, y, z: ((z % 2) * 2 + (y % 2)) * 2 + (x % 2)
+    table = []
+    for b in range(8):
+        kx, ky, kz = b % 2, (b // 2) % 2, b // 4
+        table.append([idx(kx - 1, ky, kz), idx(kx + 1, ky, kz), idx(kx, ky - 1, kz), idx(kx, ky + 1, kz),
+                      idx(kx, ky, kz - 1), idx(kx, ky, kz + 1)])
+    W.shared_node_average(blocks, 0, table)
+    # global node coordinates: block (kx, ky, kz) node (i, j, k) sits at (kx (n-1) + i, ...) mod 2 (n-1)
+    M = 2 * (n - 1)
+    copies = {}
+    for b in range(8):
+        kx, ky, kz = b % 2, (b // 2) % 2, b // 4
+        for k in range(n):
+            for j in range(n):
+                for i in range(n):
+                    key = ((kx * (n - 1) + i) % M, (ky * (n - 1) + j) % M, (kz * (n - 1) + k) % M)
+                    copies.setdefault(key, []).append((orig[b][0][k, j, i], blocks[b][0][k, j, i]))
+    mult = set()
+    for key, cs in copies.items():
+        mean = np.mean([c[0] for c in cs])
+        mult.add(len(cs))
+        for _, new in cs:
+            assert abs(new - mean) <= 1e-14 * max(1.0, abs(mean)), (key, len(cs))
+    assert mult == {1, 2, 4, 8}
+    again = [[a.copy() for a in blk] for blk in blocks]
+    W.shared_node_average(again, 0, table)
+    for x, y in zip(blocks, again):
+        assert np.array_equal(x[0], y[0])
