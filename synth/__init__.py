@@ -20,6 +20,10 @@ small-amplitude noise; uneven mesh blocks with ghost layers, Sec. 2.4):
 * ``wave192``     : periodic 192^3 plane wave k = (3,5,7) for the first-order wave
                     system (phi, Pi, psi_x, psi_y, psi_z), as one periodic block
                     or as a 4x4x4 lattice of 48^3 blocks.
+* ``decomp_line`` : the paper's decomposition test functions g and h (Eqs.
+                    test_grid_conv_g, test_grid_conv_h, with the parameters of the
+                    decomposition study) on a periodic [0, 2 pi) line of N_M
+                    cell-centred samples, split into blocks of N_B with ghosts.
 """
 from __future__ import annotations
 
@@ -253,3 +257,31 @@ def wave192(n: int = 192, blocks_per_dim: int = 1, ng: int = 4) -> Workload:
 
     data, offs = _fill(blocks, 5, fill)
     return Workload(f"wave{n}", blocks, 5, data, offs)
+
+
+def paper_g(x, A=0.05, S=1.0, N1=2, x0=0.2):
+    """g of Eq. test_grid_conv_g, with the parameters of the first-degree decomposition study."""
+    return A * np.exp(-S * np.sin(N1 * (np.asarray(x) - x0)))
+
+
+def paper_h(x, S=3.0, x0=np.pi, N1=5, N2=11, phiS=3.0, c1=1.2, c2=-1.0):
+    """h of Eq. test_grid_conv_h, with the parameters of the second-degree decomposition study (on
+    [0, 2 pi) its Gaussian factor is below 2e-13 at the ends, so its samples are periodic to that)."""
+    x = np.asarray(x)
+    return np.exp(-S * (x - x0) ** 2) * (c1 * np.sin(N2 * x) + c2 * np.cos(N2 * x)) + np.sin(N1 * x - phiS)
+
+
+def decomp_line(fn, NM: int = 128, NB: int = 16, ng: int = 4, ny: int = 1, nz: int = 1) -> Workload:
+    """fn sampled cell-centred on a periodic [0, 2 pi) line of NM nodes (node j at (j + 1/2) 2 pi/NM, Eq.
+    gridDisc), as NM/NB blocks of NB x ny x nz interior nodes along x (closures on every face, the value
+    constant along y and z), ghosts sampled from the same periodic function (the exact exchange)."""
+    NS = NM // NB
+    h = 2 * np.pi / NM
+    blocks = [Block((NB, ny, nz), ng, (h, h, h), (CLOSURE,) * 3, ((I * NB + 0.5) * h, 0.0, 0.0)) for I in range(NS)]
+
+    def fill(b, f, x, y, z):
+        row = fn(np.mod(x, 2 * np.pi))
+        return np.broadcast_to(row[None, None, :], (z.size, y.size, x.size)).copy()
+
+    data, offs = _fill(blocks, 1, fill)
+    return Workload("decomp_line", blocks, 1, data, offs)

@@ -141,3 +141,49 @@ def test_iteration_rejects_what_it_cannot_do(cuda):
     with pytest.raises(P.CfdError) as e:
         plan.set_iteration(2, *lat)
     assert e.value.status == P._lib.CFD_EGHOST
+
+
+@pytest.mark.parametrize("name,fn", [("(1)P1_2", synth.paper_g), ("(1)Q1_3[1]", synth.paper_g),
+                                     ("(2)P1_2", synth.paper_h)])
+def test_decomposition_study_on_the_gpu(cuda, name, fn):
+    """The decomposition study of Sec. 2.5 (the paper's g or h on N_M = 128 cell-centred samples, blocks
+    of N_B = 16 with N_g = 4): the library's iterates 0..3 on the block lattice and its global periodic
+    derivative match the oracle node by node, and give the oracle's modal RMS errors (Eq.
+    err_met_rms_sp)."""
+    import torch
+    import paper_2302_14858_amd as P
+    NM, NB, ng = 128, 16, 4
+    s = OS.named(name)
+    wl = synth.decomp_line(fn, NM=NM, NB=NB, ng=ng, ny=2, nz=2)
+    h = wl.blocks[0].h[0]
+    xg = (np.arange(NM) + 0.5) * h
+    glob_ref = OL.apply_line(s, fn(xg), 0, h, periodic=True)
+    scale = np.max(np.abs(glob_ref))
+    # global periodic line on the GPU
+    gb = [dict(n=(NM, 2, 2), ng=0, h=(h,) * 3, boundary=(synth.PERIODIC,) * 3)]
+    gplan = P.Plan(gb, 1, [(P.Scheme.named(name), 0)])
+    gx = torch.from_numpy(np.broadcast_to(fn(xg)[None, None, :], (2, 2, NM)).copy().ravel()).cuda()
+    gy = torch.full((NM * 4,), float("nan"), dtype=torch.float64, device="cuda")
+    gplan.apply(gx, gy)
+    torch.cuda.synchronize()
+    glob = gy.cpu().numpy().reshape(2, 2, NM)[0, 0]
+    assert np.max(np.abs(glob - glob_ref)) <= 1e-12 * scale
+    # decomposed, iterated
+    blocks = [dict(n=b.n, ng=b.ng, h=b.h, boundary=b.boundary) for b in wl.blocks]
+    plan = P.Plan(blocks, 1, [(P.Scheme.named(name), 0)])
+    lines = np.stack([wl.field_view(b, 0)[ng, ng, :] for b in range(len(wl.blocks))])
+    ref_its = IT.iterate_1d(s, lines, ng, h, 3)
+    x = torch.from_numpy(wl.data).cuda()
+    _, nout = plan.sizes()
+    for i in range(4):
+        plan.set_iteration(i, NM // NB, 1, 1)
+        y = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+        plan.apply(x, y)
+        torch.cuda.synchronize()
+        got = y.cpu().numpy().reshape(NM // NB, 2, 2, NB)[:, 0, 0, :].reshape(-1)
+        ref = ref_its[i].reshape(-1)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * scale, i
+        ea, et = IT.modal_rms_error(glob, got)
+        ra, rt = IT.modal_rms_error(glob_ref, ref)
+        if i <= 2:
+            assert abs(ea - ra) <= 1e-3 * ra and abs(et - rt) <= 1e-3 * rt, (i, ea, ra, et, rt)

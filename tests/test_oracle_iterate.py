@@ -11,6 +11,7 @@
 import numpy as np
 import pytest
 
+import synth
 from oracle import iterate as IT
 from oracle import lines as L
 from oracle import schemes as S
@@ -168,3 +169,51 @@ def test_lattice_driver_matches_1d():
     ref = IT.iterate_1d(s, row, ng, h, 2)[-1]
     for kx in range(3):
         assert np.array_equal(res[(kx, 1, 0)][5, 3, :], ref[kx])
+
+
+# --- the decomposition error metric (Eq. err_met_rms_sp) and the decomposition study (Sec. 2.5) ---
+
+def test_modal_rms_error_closed_forms():
+    """Equal inputs give zero; an added delta cos(3x) moves the two coefficients n = +-3 by delta/2
+    each, so over the 4 selected modes eps_A = delta / (2 sqrt 2); a phase shift phi of the 3x wave
+    gives eps_theta = phi / sqrt 2."""
+    N = 64
+    x = 2 * np.pi * np.arange(N) / N
+    base = np.cos(3 * x) + 0.5 * np.sin(5 * x)
+    assert IT.modal_rms_error(base, base) == (0.0, 0.0)
+    d = 1e-3
+    ea, et = IT.modal_rms_error(base, base + d * np.cos(3 * x))
+    assert abs(ea - d / (2 * np.sqrt(2))) < 1e-15 and et < 1e-13
+    phi = 0.05
+    ea, et = IT.modal_rms_error(base, np.cos(3 * x + phi) + 0.5 * np.sin(5 * x))
+    assert abs(et - phi / np.sqrt(2)) < 1e-12
+
+
+def _decomp_errors(name, fn, NB, iters=3):
+    s = S.named(name)
+    NM, ng = 128, 4
+    wl = synth.decomp_line(fn, NM=NM, NB=NB, ng=ng)
+    h = wl.blocks[0].h[0]
+    xg = (np.arange(NM) + 0.5) * h
+    glob = L.apply_line(s, fn(xg), 0, h, periodic=True)
+    blocks = np.stack([wl.field_view(b, 0)[ng, ng, :] for b in range(len(wl.blocks))])
+    its = IT.iterate_1d(s, blocks, ng, h, iters)
+    return [IT.modal_rms_error(glob, it.reshape(-1)) for it in its]
+
+
+@pytest.mark.parametrize("name,fn", [("(1)P1_2", synth.paper_g), ("(1)Q1_3[1]", synth.paper_g),
+                                     ("(2)P1_2", synth.paper_h), ("(2)Q1_3[1]", synth.paper_h)])
+def test_decomposition_study_trends(name, fn):
+    """The trends the decomposition figures report, on the paper's g and h at N_M = 128, N_g = 4: the
+    iterated closures approach the global scheme (both errors fall with every iteration, by two orders
+    of magnitude or more after three), and for the first degree the larger sub-domains (N_B = 32) give
+    the smaller error at every iteration."""
+    e16 = _decomp_errors(name, fn, 16)
+    e32 = _decomp_errors(name, fn, 32)
+    for e in (e16, e32):
+        for i in range(3):
+            assert e[i + 1][0] < e[i][0] and e[i + 1][1] < e[i][1], (name, i, e)
+        assert e[3][0] < 1e-2 * e[0][0]
+    if name.startswith("(1)"):
+        for i in range(4):
+            assert e32[i][0] < e16[i][0], (name, i)
