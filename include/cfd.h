@@ -101,6 +101,9 @@ const char *cfd_last_error(void);
  *                      scheme reads a velocity field c (cfd_op.vel_field) and
  *                      returns c d f, left-biased where c > 0 and right-biased
  *                      where c < 0 (Eq. biasderapproxadv).
+ *   "(1)VMs", "(1)XMs" the symmetrised scheme: the average of the left- and
+ *                      right-biased derivatives (the symmetrisation of biased
+ *                      schemes in the decomposition study of Sec. 2.5).
  * out: receives a library-owned handle.  CFD_EINVAL on an unknown name. */
 cfd_status cfd_scheme_named(const char *name, cfd_scheme **out);
 
@@ -117,7 +120,8 @@ cfd_status cfd_scheme_named(const char *name, cfd_scheme **out);
  * formal order, xi matching the lowest imaginary term of the interior
  * scheme's wavenumber error (Eqs. ucd_slow_closure_chi, ucd_fast_closure_chi).
  * bias: -1 left-biased (closure row at k*_-, Eq. closure_left_X), +1 right-
- * biased (its mirror image), 0 upwind pair (see cfd_scheme_named).
+ * biased (its mirror image), 0 upwind pair, 2 symmetrised (the mean of both
+ * biases; see cfd_scheme_named).
  * Ghost layers needed: the reach of both biases' rows (M + 2 for X_M, M + 1
  * for V_M).  CFD_EUNSUPPORTED outside the ranges above (stencil half-widths
  * above 5), CFD_EINVAL on a bad family or bias. */

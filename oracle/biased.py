@@ -30,6 +30,8 @@ Written from Daszuta, arXiv 2302.14858, Sec. ssec:domdec_drp:
   (left bias, closure row at k*_-) and its mirror image (right bias, closure
   row at k*_+), or the circulant system on periodic lines, assembled densely
   and solved with numpy (LU with partial pivoting): f~ = h^-1 A^-1 B f.
+* ``symmetrised_block``: the mean of both biases' derivatives (the
+  symmetrisation of biased schemes in the decomposition study, Sec. 2.5).
 * ``upwind_block``: the shift-advection term c d f of Eq. biasderapproxadv,
   with c a field sampled on the grid (the shift component, Sec. ssec:z4c):
   c > 0 takes the left-biased scheme (Im eta~ <= 0), c < 0 the right-biased
@@ -239,3 +241,11 @@ def upwind_block(name: str, f: np.ndarray, c: np.ndarray, ng: int, h: float, dir
     dr = apply_block(name, +1, f, ng, h, direction, periodic)
     c = np.asarray(c, dtype=np.float64)
     return 0.5 * (c - np.abs(c)) * dr + 0.5 * (c + np.abs(c)) * dl
+
+
+def symmetrised_block(name: str, f: np.ndarray, ng: int, h: float, direction: int,
+                      periodic: bool = False) -> np.ndarray:
+    """The symmetrised biased derivative: the mean of the left- and right-biased results
+    (the symmetrisation of biased schemes in the decomposition study of Sec. 2.5)."""
+    return 0.5 * (apply_block(name, -1, f, ng, h, direction, periodic) +
+                  apply_block(name, +1, f, ng, h, direction, periodic))

@@ -209,7 +209,8 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
 
     // ---- local solves with zero entering values
     T xl_last = 0, xr_first = 0;
-    if (mode <= 0) {
+    const bool left = mode <= 0 || mode == 2;   // -1 left, 0 upwind, 2 symmetrised: the left-biased solve
+    if (left) {
         T xp = 0;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
     // ---- true values entering the partition
     const T *pw = rec + kBiasPow;   // (-alpha)^n
     T X = 0, Y = 0;
-    if (mode <= 0) {
+    if (left) {
         if (periodic) {
             T s = 0;
             for (int qq = 0; qq < P; ++qq) {
@@ -275,8 +276,10 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
             T val;
             if (mode < 0) {
                 val = hinv * (rl[i] + pw[i + 1] * X);
-            } else if (mode > 0) {
+            } else if (mode == 1) {
                 val = hinv * (rr[i] + pw[nrows - i] * Y);
+            } else if (mode == 2) {
+                val = T(0.5) * (hinv * (rl[i] + pw[i + 1] * X) + hinv * (rr[i] + pw[nrows - i] * Y));
             } else {
                 const T cv = XDIR ? tl[k0 + i] : c[i];
                 const T xL = rl[i] + pw[i + 1] * X;
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
         for (int i = 0; i < W; ++i) w[i] = L.ld(i - (HB + 1));
         T sl = 0, sr = 0, pw = 1;
         for (int k = 0; k < N; ++k) {
-            if (ps.mode <= 0) sl = sl * (-alpha) + left_interior<T, HB>(q, w);
+            if (ps.mode <= 0 || ps.mode == 2) sl = sl * (-alpha) + left_interior<T, HB>(q, w);
             if (ps.mode >= 0) {
                 sr += pw * right_interior<T, HB>(q, w);
                 pw *= -alpha;
@@ -359,6 +362,7 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
         auto emit = [&](int k, T x) {
             T val = hinv * x;
             if (ps.mode == 0) val = fmin(vel[(int64_t)k * ps.sd], (T)0) * val;
+            if (ps.mode == 2) val = T(0.5) * val;
             o[(int64_t)k * osd] = val;
         };
 #pragma unroll
@@ -391,10 +395,11 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
     }
 
     // left-biased sweep, k = 0 .. N-1
-    if (ps.mode <= 0) {
+    if (ps.mode <= 0 || ps.mode == 2) {
         auto emit = [&](int k, T x) {
             T val = hinv * x;
             if (ps.mode == 0) val = o[(int64_t)k * osd] + fmax(vel[(int64_t)k * ps.sd], (T)0) * val;
+            if (ps.mode == 2) val = o[(int64_t)k * osd] + T(0.5) * val;
             o[(int64_t)k * osd] = val;
         };
 #pragma unroll

@@ -133,7 +133,7 @@ struct PassDesc {
 
 // Biased (upwind) operator on the lines of one block along one direction
 // (cfd_biased.hip).  mode: -1 left-biased, +1 right-biased, 0 upwind by the
-// sign of the velocity field at vel_base.  Coefficient record per table
+// sign of the velocity field at vel_base, 2 the mean of both biases.  Coefficient record per table
 // (elements of the plan's type): [0] alpha, [1, 12) ba_{-5..5},
 // [12, 24) bc_{-5..6}, [24] 1 / (1 - alpha^2), [32, 32 + 65) (-alpha)^n for
 // n = 0..64.

@@ -526,8 +526,8 @@ cfd_status taylor_scheme(int dr, int L, int R, int nclass, const int *dI, const 
 // flips its sign and the correction adds -xi (2 cos eta - 2)^(q/2), so
 // xi = 2 s_q.
 cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &out, std::string &err) {
-    if (bias < -1 || bias > 1) {
-        err = "biased scheme: bias must be -1, +1 or 0";
+    if (bias < -1 || bias > 2) {
+        err = "biased scheme: bias must be -1, +1, 0 (upwind pair) or 2 (symmetrised)";
         return CFD_EINVAL;
     }
     BiasedQ s;
@@ -635,7 +635,7 @@ cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &ou
     r.lhs[kMaxNL] = 1.0;
     for (int m = -kMaxHalf; m <= kMaxHalf; ++m) r.rhs[kMaxHalf + m] = r.ba[m + kBiasHalf];
     char nm[48];
-    std::snprintf(nm, sizeof nm, "(1)%c%d%s", family, M, bias < 0 ? "-" : (bias > 0 ? "+" : ""));
+    std::snprintf(nm, sizeof nm, "(1)%c%d%s", family, M, bias < 0 ? "-" : (bias == 1 ? "+" : (bias == 2 ? "s" : "")));
     r.name = nm;
     out = r;
     return CFD_OK;
@@ -689,7 +689,8 @@ cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &e
         return CFD_EINVAL;
     }
     const bool order_only = (variant == "E");
-    // biased: "(1)V3-", "(1)X2+", "(1)X2" (both biases, upwind by a velocity field)
+    // biased: "(1)V3-", "(1)X2+", "(1)X2" (both biases, upwind by a velocity field), "(1)X2s" (the
+    // average of both biases)
     if (variant.empty() && base.size() >= 5 && base.compare(0, 3, "(1)") == 0 && (base[3] == 'V' || base[3] == 'X') &&
         base[4] >= '1' && base[4] <= '9') {
         const std::string tail = base.substr(5);
@@ -697,6 +698,7 @@ cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &e
         if (tail.empty()) bias = 0;
         else if (tail == "-") bias = -1;
         else if (tail == "+") bias = 1;
+        else if (tail == "s") bias = 2;
         else {
             err = "unknown scheme name '" + name + "'";
             return CFD_EINVAL;

@@ -23,11 +23,11 @@ def op_fields(wl, ops):
 
 
 def biased_name(name):
-    """(base name, bias) for a biased scheme name ("(1)X2-" -> ("(1)X2", -1); "(1)X2" -> upwind, 0),
-    else None."""
+    """(base name, bias) for a biased scheme name ("(1)X2-" -> ("(1)X2", -1); "(1)X2" -> upwind, 0;
+    "(1)X2s" -> symmetrised, 2), else None."""
     if len(name) >= 5 and name.startswith("(1)") and name[3] in "VX" and name[4].isdigit():
         base, tail = name[:5], name[5:]
-        return base, {"-": -1, "+": 1, "": 0}[tail]
+        return base, {"-": -1, "+": 1, "": 0, "s": 2}[tail]
     return None
 
 
@@ -85,6 +85,8 @@ def oracle_block_op(wl, b, op, f, out=None):
         ng = blk.ng
         c = wl.field_view(b, op[3])[ng:ng + blk.n[2], ng:ng + blk.n[1], ng:ng + blk.n[0]]
         r = OB.upwind_block(base, wl.field_view(b, f), c, ng, blk.h[d], d, periodic=per)
+    elif bias == 2:
+        r = OB.symmetrised_block(base, wl.field_view(b, f), blk.ng, blk.h[d], d, periodic=per)
     else:
         r = OB.apply_block(base, bias, wl.field_view(b, f), blk.ng, blk.h[d], d, periodic=per)
     if out is not None:

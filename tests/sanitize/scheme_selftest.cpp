@@ -73,11 +73,11 @@ int main() {
     // biased generator
     for (char fam : {'V', 'X'})
         for (int M = 0; M <= 6; ++M)
-            for (int bias = -2; bias <= 2; ++bias) {
+            for (int bias = -2; bias <= 3; ++bias) {
                 Scheme s;
                 cfd_status st = design_biased(fam, M, 0.0, bias, s, err);
                 const bool ok_range = (fam == 'V') ? (M >= 1 && M <= 4) : (M >= 1 && M <= 3);
-                if (bias < -1 || bias > 1) EXPECT(st == CFD_EINVAL);
+                if (bias < -1 || bias > 2) EXPECT(st == CFD_EINVAL);
                 else if (ok_range) EXPECT(st == CFD_OK);
                 else EXPECT(st == CFD_EUNSUPPORTED);
             }

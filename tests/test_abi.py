@@ -187,7 +187,7 @@ BIASED = ["(1)V1", "(1)V2", "(1)V3", "(1)V4", "(1)X1", "(1)X2", "(1)X3"]
 
 
 @pytest.mark.parametrize("name", BIASED)
-@pytest.mark.parametrize("suffix,bias", [("-", -1), ("+", 1), ("", 0)])
+@pytest.mark.parametrize("suffix,bias", [("-", -1), ("+", 1), ("", 0), ("s", 2)])
 def test_biased_registry_matches_oracle(name, suffix, bias):
     """Biased schemes: the library's binary128 construction (xi from the Taylor-residual
     series) and the oracle's exact one (xi from the complex error series) agree to round-off."""
@@ -219,6 +219,7 @@ def test_biased_design_ranges_and_lambda():
     assert e.value.status == _lib.CFD_EINVAL
     with pytest.raises(P.CfdError):
         P.Scheme.design_biased("X", 2, 0.5, 3)
+    assert P.Scheme.design_biased("X", 2, 0.0, 2).get_biased()["bias"] == 2
     # a lambda other than the printed one: both constructions follow it
     g = P.Scheme.design_biased("X", 2, 0.5, -1).get_biased()
     s = OB.xscheme(2, Fraction(1, 2))

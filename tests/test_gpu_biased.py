@@ -156,3 +156,17 @@ def test_biased_plan_validation(cuda):
         p2.set_iteration(1, 2, 1, 1)
     assert e.value.status == _lib.CFD_EUNSUPPORTED
     del plan
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("name", ["(1)V3s", "(1)X2s"])
+def test_symmetrised_biased(cuda, name, dtype):
+    """The mean of both biases, along x, y, z: closure blocks (lengths 7..48, the partitioned kernel),
+    a periodic box, and lines of 80 nodes (the sweep kernel), against the oracle."""
+    for wl in (synth.batch64(nblocks=5, nfields=2, sizes=(7, 16, 48), ng=5, seed=26),
+               synth.periodic_box(n=(64, 5, 9), nfields=2, seed=27),
+               synth.batch64(nblocks=2, nfields=1, sizes=(80,), ng=5, seed=28)):
+        ops = [(name, d) for d in range(3)]
+        plan = H.make_plan(wl, ops, dtype=dtype)
+        err = H.full_parity(plan, wl, ops, dtype)
+        assert err <= H.tol_for(dtype), (wl.name, err)

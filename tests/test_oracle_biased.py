@@ -229,3 +229,23 @@ def test_ghost_requirement_rule():
         assert B.required_ghosts(f"(1)V{M}") == M + 1
     with pytest.raises(ValueError):
         B.line_matrix("(1)X2", -1, 12, 3, False)
+
+
+@pytest.mark.parametrize("name", ["(1)V2", "(1)X2", "(1)X3"])
+def test_symmetrised_is_non_dissipative_on_periodic_lines(name):
+    """The mean of both biases (the symmetrisation of the decomposition study) keeps only the real
+    part of the modified wavenumber: D sin(theta) = Re eta~ cos(theta) / h, with no sin component (the
+    right bias's Im eta~ is the left one's, negated)."""
+    s, _ = B.named(name)
+    N, ng = 40, 0
+    h = 2 * np.pi / N
+    x = np.arange(N) * h
+    for k, ph in ((1, 0.2), (7, 1.3), (15, 0.4)):
+        th = k * x + ph
+        f = np.broadcast_to(np.sin(th)[None, None, :], (2, 3, N)).copy()
+        got = B.symmetrised_block(name, f, ng, h, 0, periodic=True)
+        with mp.workdps(30):
+            et = complex(S.modified_wavenumber_power(s, k * h) / 1j)
+        ref = et.real * np.cos(th) / h
+        assert np.max(np.abs(got - ref[None, None, :])) < 1e-12 * np.max(np.abs(ref)), k
+        assert abs(et.imag) > 1e-6 or k == 1   # the biases themselves dissipate
