@@ -378,15 +378,25 @@ void cfd_plan_destroy(cfd_plan *p);
  * apply returns iterate [n]: iterate 0 is the block closure; iterate i solves
  * the interior tridiagonal rows of each block line on k*_- - 1 .. k*_+ + 1 with
  * the derivative at k*_- - 2 and k*_+ + 2 fixed to the neighbouring blocks'
- * iterate i - 1 at those nodes.  Only tridiagonal schemes (CFD_EUNSUPPORTED
- * otherwise); ng must cover the closure and the interior stencil on the row
+ * iterate i - 1 at those nodes.  Only tridiagonal centred schemes
+ * (CFD_EUNSUPPORTED otherwise); ng must cover the closure and the interior stencil on the row
  * past the block end, max(closure requirement, M + 1) (CFD_EGHOST).
  * iterations = 0 returns to the plain block closure.  Allocates the end-value
  * arrays (two values per line, operator and field, five arrays) and builds the
  * end-node weights in FP64 on the device; invalidates a captured graph.  An
  * apply then enqueues n + 1 small kernels over the end values before the line
- * kernels, and reads the input twice.  CFD_EINVAL if the lattice does not
- * match the plan. */
+ * kernels, and reads the input twice.
+ * Biased operators (Eq. iter_left_X and its mirror image) iterate too: for
+ * i >= 1 every row of a line takes the interior scheme and the derivative at
+ * k*_- - 1 (left bias; k*_+ + 1 right bias), in the ghost layer, is fixed to
+ * the neighbouring block's iterate i - 1 there (its last / first node); the
+ * upwind pair and the symmetrised mean use the iterated biases.  Each
+ * iteration re-runs the biased kernel (one value per line and bias is passed
+ * on by a small gather kernel), so an apply costs n + 1 biased passes.  Lines
+ * of at most 64 nodes (CFD_EUNSUPPORTED otherwise); ng must cover the closure
+ * and the interior stencil on the first and last rows (CFD_EGHOST).
+ * Mixed derivatives are not iterated (CFD_EUNSUPPORTED).  CFD_EINVAL if the
+ * lattice does not match the plan. */
 cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, int bz);
 
 /* ------------------------------------------------------------------------ */

@@ -249,3 +249,52 @@ def symmetrised_block(name: str, f: np.ndarray, ng: int, h: float, direction: in
     (the symmetrisation of biased schemes in the decomposition study of Sec. 2.5)."""
     return 0.5 * (apply_block(name, -1, f, ng, h, direction, periodic) +
                   apply_block(name, +1, f, ng, h, direction, periodic))
+
+
+def iterated_ghosts(name: str) -> int:
+    """Ghost layers the iteration needs: the closure's, and the interior rows that now also run on the
+    first (left bias) or last (right bias) node, reaching the interior stencil's full half-width."""
+    s, _ = named(name)
+    return max(required_ghosts(name), s.rhs[0].L, s.rhs[0].R)
+
+
+def iterate_1d(name: str, bias: int, blocks, ng: int, h: float, iters: int):
+    """Iterates [0] .. [iters] of a biased scheme on a periodic tiling of sub-domains (Eq.
+    iter_left_X for the left bias, its mirror image for the right one).
+
+    [0] is the block-closure derivative (Eq. closure_left_X).  For i > 0 every row of the
+    sub-domain takes the interior scheme, and the value at k^c = k*_- - 1 (left bias; k*_+ + 1 for the
+    right bias), a ghost node, is fixed to the previous iterate there: the last node of the left
+    neighbour (the first node of the right neighbour).  blocks: (NS, N_B + 2 ng) samples, ghosts
+    filled from the neighbours, optionally with trailing axes of independent lines.  Returns the list
+    of iterates, each (NS, N_B, ...)."""
+    blocks = np.asarray(blocks, dtype=np.float64)
+    NS, NB = blocks.shape[0], blocks.shape[1] - 2 * ng
+    s, _ = named(name)
+    if bias > 0:
+        s = mirror(s)
+    D0 = line_matrix(name, bias, NB, ng, False)
+    out = [np.stack([np.tensordot(D0, blocks[I], axes=(1, 0)) / h for I in range(NS)])]
+    # interior right-hand sides of every row, and the one implicit neighbour's weight
+    r = np.zeros((NS, NB) + blocks.shape[2:])
+    for m in s.rhs[0].offsets():
+        r += _f(s.rhs[0].get(m)) * blocks[:, ng + m: ng + m + NB]
+    r /= h
+    side = -1 if bias < 0 else 1
+    a = _f(s.lhs.get(side))
+    for _ in range(iters):
+        prev = out[-1]
+        cur = np.empty_like(prev)
+        for I in range(NS):
+            if bias < 0:
+                x = prev[(I - 1) % NS, NB - 1]
+                for k in range(NB):
+                    x = r[I, k] - a * x
+                    cur[I, k] = x
+            else:
+                x = prev[(I + 1) % NS, 0]
+                for k in range(NB - 1, -1, -1):
+                    x = r[I, k] - a * x
+                    cur[I, k] = x
+        out.append(cur)
+    return out

@@ -109,11 +109,19 @@ __device__ __forceinline__ void load_coef(BCoef<T, HB> &q, const T *rec) {
 
 // LDS: exchange area [4 waves][2][64], then (x lines) the tile of the
 // workgroup's lines, [4/P groups x 64 lines][pitch].
+// Iterated closures (Eq. iter_left_X and its mirror; ev given): every row of
+// a closure line takes the interior scheme, and the solution entering at node
+// -1 (left bias) / N (right bias) is ev[2 e] / ev[2 e + 1] of the line's
+// entry e = ev_base + field * nlines + line, instead of the closure rows.
+// ends (if given) receives, unscaled (before h^-1), the left-biased solution
+// at node N - 1 and the right-biased one at node 0 of every line, the values
+// the neighbours' next iterate enters with.
 template <typename T, int HB, int L, bool XDIR>
 __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict__ items,
                                                      const BiasPass *__restrict__ passes,
                                                      const T *__restrict__ coefs, const T *__restrict__ in,
-                                                     T *__restrict__ out) {
+                                                     T *__restrict__ out, const T *__restrict__ ev,
+                                                     T *__restrict__ ends) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int W = L + 2 * HB + 2;   // f[i] = node k0 - HB - 1 + i
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -133,8 +141,10 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
     T *exch = (T *)smem;
     T *tile = exch + 4 * 2 * 64;
     const bool periodic = ps.periodic;
-    const bool closureL = !periodic && p == 0;
-    const bool closureR = !periodic && p == P - 1;
+    const bool iter = ev != nullptr && !periodic;
+    const bool closureL = !periodic && p == 0 && !iter;
+    const bool closureR = !periodic && p == P - 1 && !iter;
+    const int64_t eix = 2 * (ps.ev_base + (int64_t)item.field * ps.nlines + line);   // this line's end entries
     const int mode = ps.mode;
     const T *rec = coefs + (int64_t)ps.tab * kBiasRec;
     BCoef<T, HB> q;
@@ -247,6 +257,10 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
     // ---- true values entering the partition
     const T *pw = rec + kBiasPow;   // (-alpha)^n
     T X = 0, Y = 0;
+    if (iter && active) {   // the values entering the line, from the neighbours' previous iterate
+        X = ev[eix];
+        Y = ev[eix + 1];
+    }
     if (left) {
         if (periodic) {
             T s = 0;
@@ -265,6 +279,12 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
             Y = s * (T)ps.wrap;
         }
         for (int qq = P - 1; qq > p; --qq) Y = exch[((g * P + qq) * 2 + 1) * 64 + lane] + pw[min(Lr, N - qq * Lr)] * Y;
+    }
+
+    // ---- the line's end values for the neighbours' next iterate (unscaled)
+    if (ends && active && !periodic) {
+        if (left && p == P - 1) ends[eix] = rl[nrows - 1] + pw[nrows] * X;
+        if (mode >= 0 && p == 0) ends[eix + 1] = rr[0] + pw[nrows] * Y;
     }
 
     // ---- corrected values, combined and stored
@@ -478,8 +498,33 @@ size_t biased_lds(int f32, int hb, int L, int xdir, int P, int N) {
     return b;
 }
 
+// End values of the next iterate: for every biased pass (rec = ev base of
+// the pass, of its left neighbour along the lines, of its right neighbour,
+// entries), entry e takes the left neighbour's left-biased last value and the
+// right neighbour's right-biased first value of the same field and line.
+template <typename T>
+__global__ void k_bias_gather(const int64_t *__restrict__ recs, const T *__restrict__ ends, T *__restrict__ ev) {
+    const int64_t *r = recs + 4 * blockIdx.y;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= r[3]) return;
+    ev[2 * (r[0] + e)] = ends[2 * (r[1] + e)];
+    ev[2 * (r[0] + e) + 1] = ends[2 * (r[2] + e) + 1];
+}
+
+hipError_t launch_bias_gather(int f32, int npass, int64_t max_entries, const int64_t *recs, const void *ends, void *ev,
+                              hipStream_t st) {
+    if (npass == 0 || max_entries == 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_entries + 255) / 256), (unsigned)npass);
+    if (f32)
+        hipLaunchKernelGGL(k_bias_gather<float>, grid, dim3(256), 0, st, recs, (const float *)ends, (float *)ev);
+    else
+        hipLaunchKernelGGL(k_bias_gather<double>, grid, dim3(256), 0, st, recs, (const double *)ends, (double *)ev);
+    return hipGetLastError();
+}
+
 hipError_t launch_biased(int f32, int hb, int L, int xdir, size_t lds, const BiasItem *items, int nitems,
-                         const BiasPass *passes, const void *coefs, const void *in, void *out, hipStream_t st) {
+                         const BiasPass *passes, const void *coefs, const void *in, void *out, const void *ev,
+                         void *ends, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     if (L == 0) {
         const int grid = (nitems + 3) / 4;
@@ -500,14 +545,15 @@ hipError_t launch_biased(int f32, int hb, int L, int xdir, size_t lds, const Bia
     const void *fn = f32 ? part_fn<float>(hb, L, xdir) : part_fn<double>(hb, L, xdir);
     if (!fn) return hipErrorInvalidValue;
     if (f32)
-        hipLaunchKernelGGL(((void (*)(const BiasItem *, const BiasPass *, const float *, const float *, float *))fn),
+        hipLaunchKernelGGL(((void (*)(const BiasItem *, const BiasPass *, const float *, const float *, float *,
+                                      const float *, float *))fn),
                            dim3(nitems), dim3(256), lds, st, items, passes, (const float *)coefs, (const float *)in,
-                           (float *)out);
+                           (float *)out, (const float *)ev, (float *)ends);
     else
-        hipLaunchKernelGGL(((void (*)(const BiasItem *, const BiasPass *, const double *, const double *,
-                                      double *))fn),
+        hipLaunchKernelGGL(((void (*)(const BiasItem *, const BiasPass *, const double *, const double *, double *,
+                                      const double *, double *))fn),
                            dim3(nitems), dim3(256), lds, st, items, passes, (const double *)coefs,
-                           (const double *)in, (double *)out);
+                           (const double *)in, (double *)out, (const double *)ev, (double *)ends);
     return hipGetLastError();
 }
 

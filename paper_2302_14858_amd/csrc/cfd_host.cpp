@@ -148,6 +148,12 @@ struct cfd_plan {
     std::vector<BGroup> bgroups;
     int64_t nbitems = 0;
     DevBuf d_bpass, d_bitems, d_bcoef;
+    // iterated biased closures: per biased pass its block, operator and end
+    // entries (fields x lines); end values (entering, and written by each
+    // iterate) and the gather records, built by cfd_plan_set_iteration
+    std::vector<std::array<int64_t, 4>> bpinfo;   // block, op, ev_base, entries
+    int64_t bev_entries = 0, bev_max = 0;
+    DevBuf d_bev, d_bends, d_bgrecs;
     // symmetrised mixed derivatives: scratch (elements), combine segments
     // (output offset, first-order result, second-order result, count)
     int64_t mscr_elems = 0, mseg_max = 0;
@@ -185,6 +191,13 @@ struct cfd_plan {
         eager_in = nullptr;
         eager_out = nullptr;
     }
+    // kept across rebuilds of the launch groups (autotuning, schedules)
+    void release_biased_iteration() {
+        d_bev.release();
+        d_bends.release();
+        d_bgrecs.release();
+        bev_max = 0;
+    }
     void release_iteration() {
         d_iops.release();
         d_weights.release();
@@ -217,6 +230,7 @@ struct cfd_plan {
         d_count.release();
         d_epi.release();
         d_hpairs.release();
+        release_biased_iteration();
         d_vpairs.release();
         release_iteration();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -1032,6 +1046,8 @@ cfd_status build_biased(cfd_plan *p) {
         for (int n = 0; n <= kBiasMaxPN; ++n, pw *= -s.balpha) r[kBiasPow + n] = pw;
     }
     std::vector<BiasPass> bp;
+    int64_t ev_total = 0;
+    p->bpinfo.clear();
     // kernel class (hb, L, x lines) -> items; L = 0 is the sweep kernel
     std::map<std::array<int, 3>, std::vector<BiasItem>> by_cls;
     std::map<std::array<int, 3>, size_t> cls_lds;
@@ -1077,9 +1093,13 @@ cfd_status build_biased(cfd_plan *p) {
             q.hb = s.bhalf < 2 ? 2 : s.bhalf;
             q.hinv = 1.0 / bl.h[op.dir];
             q.wrap = 1.0 / (1.0 - std::pow(-s.balpha, (double)d.N));
+            q.ev_base = ev_total;
             if (!biased_supported(q.hb)) return fail(CFD_EUNSUPPORTED, "biased stencil half-width not compiled");
             const int pi = (int)bp.size();
             bp.push_back(q);
+            const int64_t entries = (int64_t)p->nfields * q.nlines;
+            p->bpinfo.push_back({(int64_t)b, (int64_t)o, ev_total, entries});
+            ev_total += entries;
             const int f0 = op.field < 0 ? 0 : op.field;
             const int nf = op.field < 0 ? p->nfields : 1;
             // partitions: every partition keeps at least two rows ((P-1) ceil(N/P) <= N - 2)
@@ -1136,6 +1156,7 @@ cfd_status build_biased(cfd_plan *p) {
         p->bgroups.push_back(g);
     }
     p->nbitems = (int64_t)items.size();
+    p->bev_entries = ev_total;
     if (p->nbitems > INT32_MAX) return fail(CFD_EUNSUPPORTED, "too many biased work items");
     HIPCHK(dmalloc((void **)&p->d_bpass.p, bp.size() * sizeof(BiasPass)));
     HIPCHK(hipMemcpy(p->d_bpass.p, bp.data(), bp.size() * sizeof(BiasPass), hipMemcpyHostToDevice));
@@ -1155,7 +1176,8 @@ cfd_status build_biased(cfd_plan *p) {
 // One launch per biased kernel class; in the concurrent mode every class after
 // the first on a forked stream (the classes write disjoint outputs), joined
 // before the caller's stream goes on.
-cfd_status launch_biased_groups(cfd_plan *p, const void *in, void *out, hipStream_t st) {
+cfd_status launch_biased_groups(cfd_plan *p, const void *in, void *out, hipStream_t st, const void *ev = nullptr,
+                                void *ends = nullptr) {
     const size_t n = p->bgroups.size();
     const bool fork = p->concurrent && n > 1 && p->aux.size() + 1 >= n && p->ev.size() >= n;
     if (fork) HIPCHK(hipEventRecord(p->ev[0], st));
@@ -1165,7 +1187,7 @@ cfd_status launch_biased_groups(cfd_plan *p, const void *in, void *out, hipStrea
         if (s != st) HIPCHK(hipStreamWaitEvent(s, p->ev[0], 0));
         hipError_t e = launch_biased(p->dtype != CFD_F64, g.hb, g.L, g.xdir, g.lds,
                                      (const BiasItem *)p->d_bitems.p + g.item0, (int)g.nitems,
-                                     (const BiasPass *)p->d_bpass.p, p->d_bcoef.p, in, out, s);
+                                     (const BiasPass *)p->d_bpass.p, p->d_bcoef.p, in, out, ev, ends, s);
         if (e != hipSuccess) return hip_fail(e, "launching the biased-line kernel");
         if (s != st) HIPCHK(hipEventRecord(p->ev[i], s));
     }
@@ -1279,7 +1301,18 @@ cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
         cfd_status r = enqueue_iteration(p, in, st);
         if (r != CFD_OK) return r;
     }
-    if (p->nbitems > 0) {
+    if (p->nbitems > 0 && p->iter_n > 0 && p->d_bev.p) {
+        // iterated biased closures: iterate [0] writes every line's end values,
+        // each later iterate enters with its neighbours' (Eq. iter_left_X)
+        cfd_status r = launch_biased_groups(p, in, out, st, nullptr, p->d_bends.p);
+        for (int i = 1; i <= p->iter_n && r == CFD_OK; ++i) {
+            hipError_t e = launch_bias_gather(p->dtype != CFD_F64, (int)p->bpinfo.size(), p->bev_max,
+                                              (const int64_t *)p->d_bgrecs.p, p->d_bends.p, p->d_bev.p, st);
+            if (e != hipSuccess) return hip_fail(e, "launching the biased end-value gather");
+            r = launch_biased_groups(p, in, out, st, p->d_bev.p, p->d_bends.p);
+        }
+        if (r != CFD_OK) return r;
+    } else if (p->nbitems > 0) {
         cfd_status r = launch_biased_groups(p, in, out, st);
         if (r != CFD_OK) return r;
     }
@@ -2516,12 +2549,11 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
     if (iterations < 0) return fail(CFD_EINVAL, "cfd_plan_set_iteration: negative iteration count");
     if (p->dtype == CFD_MIXED_BF16)
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: not available on the dense mixed-precision path");
-    if (iterations > 0 && p->nbitems > 0)
-        return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds biased operators");
     if (iterations > 0 && !p->msegs.empty())
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds mixed derivatives");
     const int c = 2;
     auto restore = [&]() {
+        p->release_biased_iteration();
         if (!p->base_schemes.empty()) p->schemes = p->base_schemes;
         p->base_schemes.clear();
         for (PassHost &ps : p->passes) ps.ext = fused_pass(ps) ? 2 : 0;
@@ -2555,6 +2587,31 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
     std::vector<Scheme> base = p->base_schemes.empty() ? p->schemes : p->base_schemes;
     std::vector<Scheme> it(base.size());
     for (size_t o = 0; o < base.size(); ++o) {
+        if (base[o].kind == 1) {
+            // biased (Eq. iter_left_X): the same scheme, every row interior and the
+            // entering value k^c = k*_- - 1 (k*_+ + 1) from the neighbour; lines of at
+            // most the partitioned kernel's length, and ghosts for the interior
+            // stencil on the first and last rows
+            it[o] = base[o];
+            const int N = b0.n[p->ops[o].dir];
+            if (N > kBiasMaxPN)
+                return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: iterated biased closures need lines of at most "
+                                              "64 nodes");
+            int la = 0, ra = 0;
+            for (int m = -kBiasHalf; m <= kBiasHalf; ++m)
+                if (base[o].ba[m + kBiasHalf] != 0) {
+                    la = std::max(la, -m);
+                    ra = std::max(ra, m);
+                }
+            const int need = std::max(required_ghosts(base[o], 0), std::max(la, ra));
+            if (b0.ng < need) {
+                char buf[200];
+                std::snprintf(buf, sizeof buf, "cfd_plan_set_iteration: scheme '%s' iterated needs %d ghost layers, "
+                              "blocks have %d", base[o].name.c_str(), need, b0.ng);
+                return fail(CFD_EGHOST, buf);
+            }
+            continue;
+        }
         std::string err;
         cfd_status st = make_iterated(base[o], c, it[o], err);
         if (st != CFD_OK) return fail(st, "cfd_plan_set_iteration: scheme '" + base[o].name + "': " + err);
@@ -2587,7 +2644,43 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
     p->lat[2] = bz;
     HIPCHK(hipSetDevice(p->device));
     cfd_status st = build(p);
-    if (st != CFD_OK) restore();
+    if (st == CFD_OK && p->nbitems > 0) {
+        // biased passes: end-value buffers and, per pass, the passes of its
+        // neighbours along its lines on the periodic lattice
+        p->release_biased_iteration();
+        const size_t es = elem_size(p->dtype);
+        const int nbops = (int)(p->bpinfo.size() / p->blocks.size());
+        std::vector<int64_t> recs;
+        int64_t emax = 0;
+        for (size_t i = 0; i < p->bpinfo.size(); ++i) {
+            const auto &bi = p->bpinfo[i];
+            const int b = (int)bi[0], o = (int)bi[1], d = p->ops[o].dir;
+            int k[3] = {b % bx, (b / bx) % by, b / (bx * by)};
+            int km[3] = {k[0], k[1], k[2]}, kp[3] = {k[0], k[1], k[2]};
+            km[d] = (k[d] + p->lat[d] - 1) % p->lat[d];
+            kp[d] = (k[d] + 1) % p->lat[d];
+            const int bm = (km[2] * by + km[1]) * bx + km[0], bp = (kp[2] * by + kp[1]) * bx + kp[0];
+            const int slot = (int)(i % nbops);   // the same operator's pass in the neighbour
+            recs.insert(recs.end(), {bi[2], p->bpinfo[(size_t)bm * nbops + slot][2],
+                                     p->bpinfo[(size_t)bp * nbops + slot][2], bi[3]});
+            emax = std::max(emax, bi[3]);
+        }
+        hipError_t e = dmalloc(&p->d_bev.p, (size_t)std::max<int64_t>(1, 2 * p->bev_entries) * es);
+        if (e == hipSuccess) e = dmalloc(&p->d_bends.p, (size_t)std::max<int64_t>(1, 2 * p->bev_entries) * es);
+        if (e == hipSuccess) e = dmalloc(&p->d_bgrecs.p, std::max<size_t>(1, recs.size()) * sizeof(int64_t));
+        if (e == hipSuccess && !recs.empty())
+            e = hipMemcpy(p->d_bgrecs.p, recs.data(), recs.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess || p->bpinfo.size() > 65535) {
+            (void)hipGetLastError();
+            st = e != hipSuccess ? hip_fail(e, "cfd_plan_set_iteration: biased end-value buffers")
+                                 : fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: more than 65535 biased passes");
+        }
+        p->bev_max = emax;
+    }
+    if (st != CFD_OK) {
+        restore();
+        (void)build(p);
+    }
     return st;
 }
 

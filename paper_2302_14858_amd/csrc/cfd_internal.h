@@ -152,6 +152,7 @@ struct BiasPass {
     int32_t periodic, mode, tab, hb;
     double hinv;            // 1 / h
     double wrap;            // periodic: 1 / (1 - (-alpha)^N)
+    int64_t ev_base;        // iterated closures: first (field 0, line 0) entry of the pass's end values
 };
 // One work item of the partitioned kernel: 64 * (4 / P) lines of one field of
 // one pass, P partitions per line (one wave each); of the sweep kernel (lines
@@ -314,8 +315,14 @@ namespace cfd {
 // lds: bytes of dynamic LDS.
 bool biased_supported(int hb);
 size_t biased_lds(int f32, int hb, int L, int xdir, int P, int N);
+// ev: entering end values of an iterated closure (nullptr: the block closure); ends: receives every
+// line's end values (nullptr: not written); partitioned kernel only (L > 0)
 hipError_t launch_biased(int f32, int hb, int L, int xdir, size_t lds, const BiasItem *items, int nitems,
-                         const BiasPass *passes, const void *coefs, const void *in, void *out, hipStream_t st);
+                         const BiasPass *passes, const void *coefs, const void *in, void *out, const void *ev,
+                         void *ends, hipStream_t st);
+// recs: npass records (ev base of the pass, of its left neighbour, of its right neighbour, entries)
+hipError_t launch_bias_gather(int f32, int npass, int64_t max_entries, const int64_t *recs, const void *ends, void *ev,
+                              hipStream_t st);
 }  // namespace cfd
 
 namespace cfd {

@@ -151,9 +151,12 @@ def test_biased_plan_validation(cuda):
     assert e.value.status == _lib.CFD_EUNSUPPORTED
     plan = P.Plan(bd, 2, [(P.Scheme.named("(1)X1-"), 0)])
     wlat = synth.lattice(n=(8, 8, 8), lat=(2, 1, 1), ng=4, nfields=1)
-    with pytest.raises(P.CfdError) as e:
-        p2 = P.Plan(H.block_dicts(wlat), 1, [(P.Scheme.named("(1)X2-"), 0)])
-        p2.set_iteration(1, 2, 1, 1)
+    p2 = P.Plan(H.block_dicts(wlat), 1, [(P.Scheme.named("(1)X2-"), 0)])
+    p2.set_iteration(1, 2, 1, 1)                          # iterated biased closures are supported
+    wlong = synth.lattice(n=(80, 4, 4), lat=(2, 1, 1), ng=4, nfields=1)
+    with pytest.raises(P.CfdError) as e:                 # ... on lines of at most 64 nodes
+        p3 = P.Plan(H.block_dicts(wlong), 1, [(P.Scheme.named("(1)X2-"), 0)])
+        p3.set_iteration(1, 2, 1, 1)
     assert e.value.status == _lib.CFD_EUNSUPPORTED
     del plan
 

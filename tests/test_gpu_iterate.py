@@ -187,3 +187,74 @@ def test_decomposition_study_on_the_gpu(cuda, name, fn):
         ra, rt = IT.modal_rms_error(glob_ref, ref)
         if i <= 2:
             assert abs(ea - ra) <= 1e-3 * ra and abs(et - rt) <= 1e-3 * rt, (i, ea, ra, et, rt)
+
+
+def _biased_lattice_iter(wl, lat, base, bias, d, f, iters):
+    """The oracle's biased iterate [iters] (Eq. iter_left_X and its mirror) along direction d of a
+    periodic lattice: block index -> interior [z][y][x]."""
+    from oracle import biased as OB
+    nb = len(wl.blocks)
+    ng = wl.blocks[0].ng
+    h = wl.blocks[0].h[d]
+    ax = 2 - d
+    keys = [(b % lat[0], (b // lat[0]) % lat[1], b // (lat[0] * lat[1])) for b in range(nb)]
+    rows = {}
+    for b, k in enumerate(keys):
+        rows.setdefault(tuple(v for i, v in enumerate(k) if i != d), {})[k[d]] = b
+    out = {}
+    for members in rows.values():
+        order = [members[i] for i in range(lat[d])]
+        stack = np.stack([np.moveaxis(wl.field_view(b, f), ax, 0) for b in order])   # (NS, N+2ng, a, b)
+        stack = stack[:, :, ng:-ng, ng:-ng]
+        shp = stack.shape
+        res = OB.iterate_1d(base, bias, stack.reshape(shp[0], shp[1], -1), ng, h, iters)[-1]
+        res = res.reshape((shp[0], shp[1] - 2 * ng) + shp[2:])
+        for i, b in enumerate(order):
+            out[b] = np.moveaxis(res[i], 0, ax)
+    return out
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("base", ["(1)X2", "(1)V3"])
+def test_biased_iterates_match_oracle(cuda, base, dtype):
+    """Iterated biased closures (Eq. iter_left_X and its mirror image) on a periodic lattice: the left
+    and right biases, the upwind pair and the symmetrised mean along x, y and z, iterates 0..3,
+    against the oracle at every output node."""
+    import torch
+    lat = (3, 2, 2)
+    wl = synth.lattice(n=(16, 12, 20), lat=lat, ng=5, nfields=3, seed=12)
+    ops = []
+    for d in range(3):
+        ops += [(base + "-", d, 1), (base + "+", d, 2), (base, d, 0, 1), (base + "s", d, 2)]
+    plan = H.make_plan(wl, ops, dtype=dtype)
+    _, nout = plan.sizes()
+    _, ooffs = plan.offsets()
+    tdt = torch.float64 if dtype == 0 else torch.float32
+    x = torch.from_numpy(wl.data).to(device="cuda", dtype=tdt)
+    nb = len(wl.blocks)
+    ng = wl.blocks[0].ng
+    for iters in range(4):
+        plan.set_iteration(iters, *lat)
+        y = torch.full((nout,), float("nan"), dtype=tdt, device="cuda")
+        plan.apply(x, y)
+        torch.cuda.synchronize()
+        got = H.unpack(wl, ops, y.double().cpu().numpy(), ooffs)
+        for o, op in enumerate(ops):
+            d = op[1]
+            L = _biased_lattice_iter(wl, lat, base, -1, d, op[2], iters)
+            R = _biased_lattice_iter(wl, lat, base, +1, d, op[2], iters)
+            for b in range(nb):
+                if op[0].endswith("-"):
+                    ref = L[b]
+                elif op[0].endswith("+"):
+                    ref = R[b]
+                elif op[0].endswith("s"):
+                    ref = 0.5 * (L[b] + R[b])
+                else:
+                    n = wl.blocks[b].n
+                    c = wl.field_view(b, op[3])[ng:ng + n[2], ng:ng + n[1], ng:ng + n[0]]
+                    ref = 0.5 * (c - np.abs(c)) * R[b] + 0.5 * (c + np.abs(c)) * L[b]
+                g = got[b][o][0]
+                err = np.max(np.abs(g - ref)) / max(np.max(np.abs(ref)), 1e-300)
+                assert err <= H.tol_for(dtype), (iters, op, b, err)
+    plan.set_iteration(0)

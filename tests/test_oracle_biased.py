@@ -249,3 +249,47 @@ def test_symmetrised_is_non_dissipative_on_periodic_lines(name):
         ref = et.real * np.cos(th) / h
         assert np.max(np.abs(got - ref[None, None, :])) < 1e-12 * np.max(np.abs(ref)), k
         assert abs(et.imag) > 1e-6 or k == 1   # the biases themselves dissipate
+
+
+@pytest.mark.parametrize("name", ["(1)V2", "(1)X1", "(1)X2"])
+@pytest.mark.parametrize("bias", [-1, 1])
+def test_iterated_biased_closure_converges_to_the_global_scheme(name, bias):
+    """Eq. iter_left_X (and its mirror): passing one end value per iteration across a periodic tiling
+    converges to the global periodic biased operator, the error shrinking by about |alpha|^N_B per
+    iteration (the end value's influence decays as (-alpha)^k along the sub-domain)."""
+    ng, NB, NS = B.iterated_ghosts(name), 12, 6
+    NM = NB * NS
+    h = 2 * np.pi / NM
+    x = (np.arange(NM) + 0.5) * h
+    f = np.sin(3 * x + 0.4) + 0.3 * np.cos(7 * x)
+    blocks = np.stack([f[(np.arange(-ng, NB + ng) + I * NB) % NM] for I in range(NS)])
+    its = B.iterate_1d(name, bias, blocks, ng, h, 8)
+    glob = B.line_matrix(name, bias, NM, 0, True) @ f / h
+    err = [np.max(np.abs(it.reshape(-1) - glob)) for it in its]
+    s, _ = B.named(name)
+    rate = abs(float(s.lhs.get(-1))) ** NB
+    for i in range(1, 8):
+        assert err[i + 1] <= 2.0 * rate * err[i] + 1e-13 * np.max(np.abs(glob)), (i, err)
+    assert err[8] < 1e-12 * np.max(np.abs(glob))
+    assert err[1] < 1e-2 * err[0]
+
+
+def test_biased_iteration_converges_faster_than_centred():
+    """The decomposition study's remark: under iteration the biased schemes converge more rapidly
+    than the centred ones (here X_2^- against P_2^1 on the paper's g, N_M = 128, N_B = 16)."""
+    import synth
+    from oracle import iterate as IT
+    from oracle import lines as OL
+    from oracle import schemes as OS
+    NM, NB = 128, 16
+    h = 2 * np.pi / NM
+    xg = (np.arange(NM) + 0.5) * h
+    g = synth.paper_g(xg)
+    ng = 4
+    blocks = np.stack([synth.paper_g((I * NB + np.arange(-ng, NB + ng) + 0.5) * h) for I in range(NM // NB)])
+    gb = B.line_matrix("(1)X2", -1, NM, 0, True) @ g / h
+    eb = [IT.modal_rms_error(gb, it.reshape(-1))[0] for it in B.iterate_1d("(1)X2", -1, blocks, ng, h, 2)]
+    sc = OS.named("(1)P1_2")
+    gc = OL.apply_line(sc, g, 0, h, periodic=True)
+    ec = [IT.modal_rms_error(gc, it.reshape(-1))[0] for it in IT.iterate_1d(sc, blocks, ng, h, 2)]
+    assert eb[1] / eb[0] < 0.1 * (ec[1] / ec[0]), (eb, ec)
