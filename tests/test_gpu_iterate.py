@@ -258,3 +258,56 @@ def test_biased_iterates_match_oracle(cuda, base, dtype):
                 err = np.max(np.abs(g - ref)) / max(np.max(np.abs(ref)), 1e-300)
                 assert err <= H.tol_for(dtype), (iters, op, b, err)
     plan.set_iteration(0)
+
+
+def test_biased_and_centred_iterate_together_and_replay(cuda):
+    """A plan holding centred and biased operators iterates both (each against its oracle), and a
+    captured graph of the iterated apply replays the eager result bit for bit."""
+    import torch
+    lat = (2, 2, 1)
+    wl = synth.lattice(n=(16, 16, 12), lat=lat, ng=5, nfields=2, seed=13)
+    ops = [("(1)Q1_3[1]", 0), ("(1)X2-", 1), ("(1)X2", 0, 0, 1), ("(2)Q1_3[1]", 1)]
+    plan = H.make_plan(wl, ops)
+    _, nout = plan.sizes()
+    _, ooffs = plan.offsets()
+    plan.set_iteration(2, *lat)
+    x = torch.from_numpy(wl.data).cuda()
+    y = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.apply(x, y)
+    torch.cuda.synchronize()
+    got = H.unpack(wl, ops, y.cpu().numpy(), ooffs)
+    nb = len(wl.blocks)
+    ng = wl.blocks[0].ng
+    keys = [(b % lat[0], (b // lat[0]) % lat[1], b // (lat[0] * lat[1])) for b in range(nb)]
+    for o, op in enumerate(ops):
+        d = op[1]
+        nfo = wl.nfields if len(op) < 3 or op[2] < 0 else 1
+        for fi in range(nfo):
+            f = fi if nfo > 1 else op[2]
+            if op[0].startswith("(1)X2"):
+                L = _biased_lattice_iter(wl, lat, "(1)X2", -1, d, f, 2)
+                R = _biased_lattice_iter(wl, lat, "(1)X2", +1, d, f, 2)
+            else:
+                s = OS.named(op[0])
+                ref_c = IT.iterate_lattice(s, {keys[b]: wl.field_view(b, f) for b in range(nb)}, lat, ng,
+                                           wl.blocks[0].h[d], d, 2)
+            for b in range(nb):
+                if op[0] == "(1)X2-":
+                    ref = L[b]
+                elif op[0] == "(1)X2":
+                    n = wl.blocks[b].n
+                    c = wl.field_view(b, op[3])[ng:ng + n[2], ng:ng + n[1], ng:ng + n[0]]
+                    ref = 0.5 * (c - np.abs(c)) * R[b] + 0.5 * (c + np.abs(c)) * L[b]
+                else:
+                    ref = ref_c[keys[b]]
+                err = np.max(np.abs(got[b][o][fi] - ref)) / np.max(np.abs(ref))
+                assert err <= H.ERR_F64, (op, b, fi, err)
+    y1 = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.capture_graph(x, y1)
+    for _ in range(3):
+        plan.launch_graph()
+        torch.cuda.synchronize()
+        assert torch.equal(y, y1)
+        y1.fill_(float("nan"))
+        torch.cuda.synchronize()
+    plan.set_iteration(0)
