@@ -311,3 +311,36 @@ def test_biased_and_centred_iterate_together_and_replay(cuda):
         y1.fill_(float("nan"))
         torch.cuda.synchronize()
     plan.set_iteration(0)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_biased_iteration_seeded_sweep(cuda, seed):
+    """Seeded random lattices, block extents, biased schemes, biases and iteration counts, against the
+    oracle."""
+    import torch
+    rng = np.random.default_rng(200 + seed)
+    base = ["(1)V1", "(1)V2", "(1)X1", "(1)X2", "(1)X3"][int(rng.integers(0, 5))]
+    lat = tuple(int(v) for v in rng.integers(1, 4, size=3))
+    if np.prod(lat) == 1:
+        lat = (2, 1, 1)
+    n = tuple(int(v) for v in rng.integers(9, 33, size=3))
+    d = int(rng.integers(0, 3))
+    iters = int(rng.integers(1, 4))
+    suffix = ["-", "+", "s"][int(rng.integers(0, 3))]
+    wl = synth.lattice(n=n, lat=lat, ng=5, nfields=1, seed=300 + seed)
+    ops = [(base + suffix, d)]
+    plan = H.make_plan(wl, ops)
+    plan.set_iteration(iters, *lat)
+    _, nout = plan.sizes()
+    _, ooffs = plan.offsets()
+    x = torch.from_numpy(wl.data).cuda()
+    y = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.apply(x, y)
+    torch.cuda.synchronize()
+    got = H.unpack(wl, ops, y.cpu().numpy(), ooffs)
+    L = _biased_lattice_iter(wl, lat, base, -1, d, 0, iters)
+    R = _biased_lattice_iter(wl, lat, base, +1, d, 0, iters)
+    for b in range(len(wl.blocks)):
+        ref = {"-": L[b], "+": R[b], "s": 0.5 * (L[b] + R[b])}[suffix]
+        err = np.max(np.abs(got[b][0][0] - ref)) / np.max(np.abs(ref))
+        assert err <= H.ERR_F64, (seed, base + suffix, lat, n, d, iters, b, err)

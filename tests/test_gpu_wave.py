@@ -379,3 +379,50 @@ def test_vertex_centred_rejections(cuda):
     plan.halo_exchange_table(x)
     plan.shared_node_average(x)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_halo_table_seeded_sweep(cuda, seed):
+    """Seeded random conforming tilings: a row of blocks along one direction with random extents along
+    it (equal across it), random open faces, either sampling, random ghost width and dtype; the
+    exchange (and for vertex-centred tilings the shared-node average) against the oracle."""
+    import torch
+    import paper_2302_14858_amd as P
+    rng = np.random.default_rng(100 + seed)
+    d = int(rng.integers(0, 3))
+    nb = int(rng.integers(1, 5))
+    ng = int(rng.integers(1, 5))
+    vc = bool(rng.integers(0, 2))
+    dtype = int(rng.integers(0, 2))
+    base = [int(rng.integers(ng + 2, 14)) for _ in range(3)]
+    blocks = []
+    for i in range(nb):
+        n = list(base)
+        n[d] = int(rng.integers(ng + 2, 20))
+        blocks.append(dict(n=tuple(n), ng=ng, h=(0.1,) * 3, boundary=(synth.CLOSURE,) * 3))
+    table = []
+    for i in range(nb):
+        row = [i, i, i, i, i, i]                       # transverse faces: periodic onto the block itself
+        row[2 * d] = (i - 1) % nb
+        row[2 * d + 1] = (i + 1) % nb
+        table.append(row)
+    if not vc:                                         # open a few faces (vertex-centred faces must stay mutual)
+        for i in range(nb):
+            for f in range(6):
+                if rng.random() < 0.2:
+                    table[i][f] = -1
+    plan = P.Plan(blocks, 2, [(P.Scheme.named("(1)E1"), (d + 1) % 3)], dtype=dtype)
+    (plan.set_neighbors_vc if vc else plan.set_neighbors)(table)
+    nin, _ = plan.sizes()
+    npdt = np.float64 if dtype == 0 else np.float32
+    host = rng.standard_normal(nin).astype(npdt)
+    x = torch.from_numpy(host.copy()).cuda()
+    plan.halo_exchange_table(x)
+    if vc:
+        plan.shared_node_average(x)
+    torch.cuda.synchronize()
+    st = _split_state(host.copy(), blocks, 2)
+    W.fill_ghosts_table(st, ng, table, shared=1 if vc else 0)
+    if vc:
+        W.shared_node_average(st, ng, table)
+    assert np.array_equal(x.cpu().numpy(), np.concatenate([a.ravel() for blk in st for a in blk])), (seed, d, nb, vc)
