@@ -26,6 +26,15 @@ Written from Daszuta, arXiv 2302.14858, Sec. ssec:domdec_drp:
   of Eq. LCslowfast with the f'' sample replaced by the explicit (2)E_{M+2}
   (Tab. misc_explicit), and its xi-closure; lambda is the sigma printed in
   Tab. ccux_deg_one_col.
+* ``wscheme`` / ``w_rows``: W^-_M, the same combination with lambda the sigma
+  of Tab. ccuw_deg_one_col, keeping the f'' term, which is now the centred
+  tridiagonal Pade second derivative (2)P1_M solved on the line with its
+  matched explicit closure (Tabs. pade_deg_two, the compact approximant the
+  text names for W; its caption's "(1)P" can only be the second-degree
+  scheme).  At k*_+ that f'' is the closure's explicit value, which turns the
+  interior row into the printed Wtilde^-_M; at k*_- the closure Wbar^-_M is
+  the xi-closure of that explicit row (mirror at k*_-, where f'' is again the
+  closure's).  ``w_eps_series``: the interior error with the compact f''.
 * ``line_matrix`` / ``apply_block``: the banded system of Eq. closure_left_X
   (left bias, closure row at k*_-) and its mirror image (right bias, closure
   row at k*_+), or the circulant system on periodic lines, assembled densely
@@ -51,6 +60,8 @@ from typing import Dict, List, Tuple
 
 import numpy as np
 
+from . import lines as L
+from . import schemes as S
 from .schemes import Scheme, Stencil, determined_scheme, eps_series
 
 
@@ -141,10 +152,83 @@ def xscheme(M: int, lam: Fraction = None) -> Scheme:
     return Scheme(f"(1)X{M}-", 1, u.order, lhs, [_stencil_from_map(0, r0)], [])
 
 
+# sigma of Tab. ccuw_deg_one_col
+W_LAMBDA = {1: Fraction(38, 100), 2: Fraction(71, 100), 3: Fraction(95, 100)}
+
+
+def wscheme(M: int, lam: Fraction = None) -> Scheme:
+    """W^-_M: lambda U^-_M + (1 - lambda) V^-_{M+1} (Eq. LCslowfast), the f'' term kept
+    (rhs[1], derivative class 2) for the embedded second derivative."""
+    if lam is None:
+        lam = W_LAMBDA[M]
+    u, v = ucd("U", M), ucd("V", M + 1)
+    lhs = Stencil(1, 1, 0, [lam * u.lhs.get(n) + (1 - lam) * v.lhs.get(n) for n in (-1, 0)])
+    r0: Dict[int, Fraction] = {}
+    for st, w in ((u.rhs[0], lam), (v.rhs[0], 1 - lam)):
+        for n in st.offsets():
+            r0[n] = r0.get(n, Fraction(0)) + w * st.get(n)
+    a2 = lam * u.rhs[1].get(0)
+    return Scheme(f"(1)W{M}-", 1, u.order, lhs, [_stencil_from_map(0, r0), Stencil(2, 0, 0, [a2])], [])
+
+
+def embedded_second(M: int) -> Scheme:
+    """The second derivative W_M embeds: (2)P1_M with its matched explicit closure."""
+    return S.named(f"(2)P1_{M}")
+
+
+def with_explicit_second(s: Scheme, e2: Stencil) -> Scheme:
+    """The row of s with its f'' sample replaced by the explicit dx^2 f'' ~ e2 . f."""
+    a2 = s.rhs[1].get(0)
+    r0: Dict[int, Fraction] = {}
+    for st, w in ((s.rhs[0], Fraction(1)), (e2, a2)):
+        for n in st.offsets():
+            r0[n] = r0.get(n, Fraction(0)) + w * st.get(n)
+    return Scheme(s.name + ":explicit", 1, s.order, s.lhs, [_stencil_from_map(0, r0)], [])
+
+
+def w_rows(M: int) -> Tuple[Scheme, Scheme, Scheme]:
+    """(W^-_M interior, Wbar^-_M at k*_-, Wtilde^-_M at k*_+)."""
+    s = wscheme(M)
+    wt = with_explicit_second(s, embedded_second(M).closure[0])
+    _, wb = xi_closure(wt)
+    return s, wb, wt
+
+
+def _conv(a: Stencil, b: Stencil, dK: int) -> Dict[int, Fraction]:
+    out: Dict[int, Fraction] = {}
+    for i in a.offsets():
+        for j in b.offsets():
+            out[i + j] = out.get(i + j, Fraction(0)) + Fraction(a.get(i)) * Fraction(b.get(j))
+    return out
+
+
+def w_compact_scheme(M: int) -> Scheme:
+    """The interior W^-_M with its compact f'' as one scheme on f alone (periodic lines).
+
+    With A2 f''~ = h^-2 B2 f the row is A1 . f~' = h^-1 (B0 . f + a2 (B2 / A2) . f), i.e. the
+    scheme (A1 * A2) . f~' = h^-1 (B0 * A2 + a2 B2) . f with * the convolution of stencils."""
+    s, P = wscheme(M), embedded_second(M)
+    a2 = s.rhs[1].get(0)
+    lhs = _conv(s.lhs, P.lhs, 1)
+    r = _conv(s.rhs[0], P.lhs, 0)
+    for n in P.rhs[0].offsets():
+        r[n] = r.get(n, Fraction(0)) + a2 * P.rhs[0].get(n)
+    lo, hi = min(lhs), max(lhs)
+    return Scheme(f"(1)W{M}-:compact", 1, s.order,
+                  Stencil(1, -lo, hi, [lhs.get(n, Fraction(0)) for n in range(lo, hi + 1)]),
+                  [_stencil_from_map(0, r)], [])
+
+
+def w_eps_series(M: int, nterms: int):
+    """Relative wavenumber error series of the interior W^-_M with its compact f''."""
+    return S.eps_series(w_compact_scheme(M), nterms, exact=True)
+
+
 @lru_cache(maxsize=None)
 def named(name: str) -> Tuple[Scheme, Scheme]:
-    """(left-biased interior scheme, its closure row at k*_-) for "(1)V{M}" (M = 1..4)
-    or "(1)X{M}" (M = 1..3).  U needs the sampled f'' and is not a line operator on f alone."""
+    """(left-biased interior scheme, its closure row at k*_-) for "(1)V{M}" (M = 1..4),
+    "(1)X{M}" or "(1)W{M}" (M = 1..3).  U needs the sampled f'' and is not a line operator on f
+    alone; W carries its f'' term in rhs[1], filled by the embedded second derivative."""
     if not name.startswith("(1)"):
         raise KeyError(name)
     kind, M = name[3], int(name[4:])
@@ -152,6 +236,9 @@ def named(name: str) -> Tuple[Scheme, Scheme]:
         s = ucd("V", M)
     elif kind == "X" and M in X_LAMBDA:
         s = xscheme(M)
+    elif kind == "W" and M in W_LAMBDA:
+        s, wb, _ = w_rows(M)
+        return s, wb
     else:
         raise KeyError(name)
     return s, xi_closure(s)[1]
@@ -161,9 +248,13 @@ def required_ghosts(name: str) -> int:
     """Reach past a block end of the rows of both biases (N_g >= M + 2 for X_M,
     after Eq. closure_left_X).  Left bias: the closure row k*_- reaches its
     left half-width, interior row k*_- + 1 its left half-width - 1, interior
-    row k*_+ its right half-width; the right bias is the mirror image."""
+    row k*_+ its right half-width; the right bias is the mirror image.  W also
+    needs what its embedded second derivative's closure reaches."""
     s, c = named(name)
-    return max(c.rhs[0].L, s.rhs[0].L - 1, s.rhs[0].R)
+    need = max(c.rhs[0].L, s.rhs[0].L - 1, s.rhs[0].R)
+    if name[3] == "W":
+        need = max(need, S.required_ghosts(embedded_second(int(name[4:])), False))
+    return need
 
 
 # ---------------------------------------------------------------------------
@@ -184,6 +275,22 @@ def line_matrix(name: str, bias: int, N: int, ng: int, periodic: bool) -> np.nda
         s, c = mirror(s), mirror(c)
     A = np.zeros((N, N))
     B = np.zeros((N, N + 2 * ng))
+    E2 = None
+    if len(s.rhs) > 1:
+        # W: the f'' term of every interior row from the embedded second derivative
+        # (unit spacing), dense over the same samples
+        P = embedded_second(int(name[4:]))
+        E2 = np.zeros((N, N + 2 * ng))
+        for j in range(N + 2 * ng):
+            if periodic and not (ng <= j < ng + N):
+                continue
+            e = np.zeros(N + 2 * ng)
+            e[j] = 1.0
+            if periodic:
+                e[:ng] = e[N:N + ng]
+                e[ng + N:] = e[ng:2 * ng]
+            E2[:, j] = L.apply_line(P, e, ng, 1.0, periodic)
+        a2 = _f(s.rhs[1].get(0))
 
     def put(row, lhs, rhs, wrap):
         for n in lhs.offsets():
@@ -205,6 +312,8 @@ def line_matrix(name: str, bias: int, N: int, ng: int, periodic: bool) -> np.nda
             put(k, c.lhs, c.rhs[0], False)
         else:
             put(k, s.lhs, s.rhs[0], periodic)
+            if E2 is not None:
+                B[k] += a2 * E2[k]
     return np.linalg.solve(A, B)
 
 

@@ -1,7 +1,7 @@
 """Pins of the biased-scheme oracle (oracle/biased.py) against the paper.
 
 Every printed tuple of Tabs. ucd_slow, ucd_fast, ucd_slow_closure,
-ucd_fast_closure and ccux_deg_one_col is reproduced exactly (fixtures in
+ucd_fast_closure, ccux_deg_one_col and ccuw_deg_one_col is reproduced exactly (fixtures in
 tests/golden/biased_tables.json, typed from the paper); the line operator is
 pinned by polynomial exactness on every row, the closed form of Eq.
 fdpwerrdef on periodic lines, the mirror symmetry between the two biases, the
@@ -76,6 +76,64 @@ def test_ccux_table_exact(M):
     assert [c.rhs[0].get(n) for n in range(-W, W + 2)] == [_fr(v) for v in g["closure_a0"]]
 
 
+@pytest.mark.parametrize("M", [1, 2, 3])
+def test_ccuw_table_exact(M):
+    """Tab. ccuw_deg_one_col: W^-_M as the lambda = sigma combination with its f'' term; Wtilde^-_M
+    as that row with f'' from the explicit closure of (2)P1_M; Wbar^-_M as the xi-closure of Wtilde;
+    eps of the interior with the compact (2)P1_M second derivative."""
+    g = GOLD["ccuw"][str(M)]
+    assert B.W_LAMBDA[M] == _fr(g["sigma"])
+    s, wb, wt = B.w_rows(M)
+    assert s.order == 2 * M + 2
+    assert [s.lhs.get(n) for n in (-1, 0)] == [_fr(v) for v in g["a1"]]
+    W = M + 1
+    assert (s.rhs[0].L, s.rhs[0].R) == (W, W)
+    assert [s.rhs[0].get(n) for n in range(-W, W + 1)] == [_fr(v) for v in g["a0"]]
+    assert s.rhs[1].dK == 2 and s.rhs[1].get(0) == _fr(g["a2"])
+    assert [wt.lhs.get(n) for n in (-1, 0)] == [_fr(v) for v in g["tilde_a1"]]
+    assert (wt.rhs[0].L, wt.rhs[0].R) == (M + 2, M + 2)
+    assert [wt.rhs[0].get(n) for n in range(-(M + 2), M + 3)] == [_fr(v) for v in g["tilde_a0"]]
+    assert [wb.lhs.get(n) for n in (0, 1)] == [_fr(v) for v in g["closure_a1"]]
+    assert (wb.rhs[0].L, wb.rhs[0].R) == (M + 2, M + 3)
+    assert [wb.rhs[0].get(n) for n in range(-(M + 2), M + 4)] == [_fr(v) for v in g["closure_a0"]]
+    ser = B.w_eps_series(M, s.order + 2)
+    for j in range(s.order):
+        assert ser[j] == (0, 0)
+    for j, re, im in g["eps"]:
+        assert ser[j] == (_fr(re), _fr(im))
+
+
+@pytest.mark.parametrize("M", [1, 2, 3])
+@pytest.mark.parametrize("bias", [-1, 1])
+def test_w_line_end_rows_are_the_printed_closures(M, bias):
+    """The W line operator (interior rows with f'' from the (2)P1_M line solve) has, as the
+    right side of its end rows, exactly the printed Wbar (closed end) and Wtilde (other end):
+    A D = B row by row, A the bidiagonal left side."""
+    g = GOLD["ccuw"][str(M)]
+    name, N = f"(1)W{M}", 17
+    ng = B.required_ghosts(name)
+    D = B.line_matrix(name, bias, N, ng, False)
+    al = float(_fr(g["a1"][0]))
+    wbar = np.array([float(_fr(v)) for v in g["closure_a0"]])
+    wtil = np.array([float(_fr(v)) for v in g["tilde_a0"]])
+    if bias < 0:
+        closed = D[0] + al * D[1]                 # x_0 + alpha x_1 = Wbar . f
+        other = D[N - 1] + al * D[N - 2]          # alpha x_{N-2} + x_{N-1} = Wtilde . f
+        ref_c = np.zeros(N + 2 * ng)
+        ref_c[ng - (M + 2): ng + M + 4] = wbar
+        ref_o = np.zeros(N + 2 * ng)
+        ref_o[ng + N - 1 - (M + 2): ng + N + M + 2] = wtil
+    else:                                         # mirror image: offsets reversed, signs flipped
+        closed = D[N - 1] + al * D[N - 2]
+        other = D[0] + al * D[1]
+        ref_c = np.zeros(N + 2 * ng)
+        ref_c[ng + N - 1 - (M + 3): ng + N + M + 2] = -wbar[::-1]
+        ref_o = np.zeros(N + 2 * ng)
+        ref_o[ng - (M + 2): ng + M + 3] = -wtil[::-1]
+    assert np.max(np.abs(closed - ref_c)) < 1e-13
+    assert np.max(np.abs(other - ref_o)) < 1e-13
+
+
 def test_explicit_derivative_stencils_match_tab_diss_scheme():
     for q, row in GOLD["diss_scheme"].items():
         if q.startswith("_"):
@@ -112,7 +170,7 @@ def _poly_line(deg, N, ng, h, x0=0.37):
     return f, df[ng:ng + N]
 
 
-@pytest.mark.parametrize("name", ["(1)V2", "(1)V4", "(1)X1", "(1)X2", "(1)X3"])
+@pytest.mark.parametrize("name", ["(1)V2", "(1)V4", "(1)X1", "(1)X2", "(1)X3", "(1)W1", "(1)W2", "(1)W3"])
 @pytest.mark.parametrize("bias", [-1, 1])
 def test_polynomial_exactness_every_row(name, bias):
     s, _ = B.named(name)
@@ -129,12 +187,15 @@ def test_polynomial_exactness_every_row(name, bias):
     assert rel > 100 * max(worst, 1e-15)                      # order is not higher than stated
 
 
-@pytest.mark.parametrize("name", ["(1)V3", "(1)X1", "(1)X2", "(1)X3"])
+@pytest.mark.parametrize("name", ["(1)V3", "(1)X1", "(1)X2", "(1)X3", "(1)W1", "(1)W3"])
 @pytest.mark.parametrize("bias", [-1, 1])
 def test_periodic_closed_form(name, bias):
     """On a periodic line a Fourier mode is an eigenvector with eigenvalue
-    i eta~(eta)/h (Eq. fdpwerrdef): D sin(theta) = (Re eta~ cos theta - Im eta~ sin theta)/h."""
+    i eta~(eta)/h (Eq. fdpwerrdef): D sin(theta) = (Re eta~ cos theta - Im eta~ sin theta)/h.
+    For W, eta~ is that of the interior row with the compact (2)P1_M second derivative."""
     s, _ = B.named(name)
+    if name[3] == "W":
+        s = B.w_compact_scheme(int(name[4:]))
     if bias > 0:
         s = B.mirror(s)
     N = 48
@@ -151,7 +212,7 @@ def test_periodic_closed_form(name, bias):
         assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref)), k
 
 
-@pytest.mark.parametrize("name", ["(1)V2", "(1)X2"])
+@pytest.mark.parametrize("name", ["(1)V2", "(1)X2", "(1)W2"])
 @pytest.mark.parametrize("periodic", [False, True])
 def test_biases_are_mirror_images(name, periodic):
     """D+[f](x_k) = -D-[f reversed](x_{N-1-k}): the right-biased operator is the
@@ -164,7 +225,7 @@ def test_biases_are_mirror_images(name, periodic):
     assert np.max(np.abs(Dr @ g + (Dl @ g[::-1])[::-1])) < 1e-12
 
 
-@pytest.mark.parametrize("name,order", [("(1)V2", 5), ("(1)X1", 4), ("(1)X2", 6)])
+@pytest.mark.parametrize("name,order", [("(1)V2", 5), ("(1)X1", 4), ("(1)X2", 6), ("(1)W1", 4), ("(1)W2", 6)])
 def test_convergence_order_closure_lines(name, order):
     errs = []
     Ns = [32, 64, 128]
@@ -227,6 +288,8 @@ def test_ghost_requirement_rule():
         assert B.required_ghosts(f"(1)X{M}") == M + 2
     for M in (1, 2, 3, 4):
         assert B.required_ghosts(f"(1)V{M}") == M + 1
+    for M in (1, 2, 3):                 # W_M: its closure and the embedded (2)P1_M closure
+        assert B.required_ghosts(f"(1)W{M}") == M + 2
     with pytest.raises(ValueError):
         B.line_matrix("(1)X2", -1, 12, 3, False)
 
