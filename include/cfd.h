@@ -97,6 +97,9 @@ const char *cfd_last_error(void);
  *   "(1)VM-", "(1)VM+" M = 1..4: V_M of Tab. ucd_fast, left / right biased,
  *                      with the xi-closure of Tab. ucd_fast_closure.
  *   "(1)XM-", "(1)XM+" M = 1..3: X_M of Tab. ccux_deg_one_col with its closure.
+ *   "(1)WM-", "(1)WM+" M = 1..3: W_M of Tab. ccuw_deg_one_col (embedded compact
+ *                      second derivative) with its closure; "(1)WM" and "(1)WMs"
+ *                      as below.
  *   "(1)VM", "(1)XM"   both biases as an upwind pair: an operator with this
  *                      scheme reads a velocity field c (cfd_op.vel_field) and
  *                      returns c d f, left-biased where c > 0 and right-biased
@@ -126,6 +129,19 @@ cfd_status cfd_scheme_named(const char *name, cfd_scheme **out);
  * for V_M).  CFD_EUNSUPPORTED outside the ranges above (stencil half-widths
  * above 5), CFD_EINVAL on a bad family or bias. */
 cfd_status cfd_scheme_design_biased(char family, int M, double lambda, int bias, cfd_scheme **out);
+/* family 'W': W_M (M = 1..3, Tab. ccuw_deg_one_col), the same combination
+ * keeping alpha^(2)_0 dx^2 f''_k on every interior row, with f'' the compact
+ * centred (2)P1_M solved on the same line with its matched explicit closure
+ * (lambda <= 0 takes the printed sigma), formal order 2M+2.  At the far end
+ * k*_+ (left bias) that f'' is the closure's explicit value, which makes the
+ * row there the printed Wtilde; the closure at k*_- (the printed Wbar) is
+ * built as above from that explicit row.  In a plan a W operator runs the
+ * (2)P1_M pass over the block interior into plan scratch before the biased
+ * launches (M + 2 ghost layers; the embedded pass takes the line lengths of the
+ * centred second-degree path: closure lines of 3..128 nodes, periodic lines of
+ * P partitions of a compiled length, e.g. 8, 12, 16, 24, 32, 48, 64, 96, 128;
+ * other lengths give CFD_EUNSUPPORTED at plan creation); cfd_plan_set_iteration
+ * refuses plans with W operators. */
 
 /* Kreiss-Oliger dissipation of Eq. dissdef as an operator:
  *   Q^(2r) f = -(-1)^r / 2^(2r) sigma dx^(2r-1) (D_+)^r (D_-)^r f,
@@ -145,6 +161,13 @@ cfd_status cfd_scheme_dissipation(int r, double sigma, cfd_scheme **out);
  * NULL.  CFD_EINVAL for a centred scheme. */
 cfd_status cfd_scheme_get_biased(const cfd_scheme *s, int *bias, int *order, double *alpha, double *a11,
                                  double *c12);
+
+/* Read back the embedded second derivative of a biased scheme (W_M of Tab.
+ * ccuw_deg_one_col): alpha2 receives alpha^(2)_0 of the left-biased interior
+ * row (its right side is sum_m a_m f_{k+m} + alpha2 dx^2 f''_k; the right bias
+ * takes -alpha2), m2 the M of the embedded (2)P1_M.  Schemes without one give
+ * 0 and 0.  Either pointer may be NULL.  CFD_EINVAL for a centred scheme. */
+cfd_status cfd_scheme_get_embedded(const cfd_scheme *s, double *alpha2, int *m2);
 
 /* Fully determined scheme of the multi-derivative ansatz (Eq. mdAnsatz):
  * derivative of degree dr on offsets -L..R (alpha^(dr)_0 = 1) against

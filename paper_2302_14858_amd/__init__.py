@@ -137,6 +137,13 @@ class Scheme:
 
     get_biased = cfd_scheme_get_biased
 
+    def cfd_scheme_get_embedded(self) -> Dict:
+        a2, m2 = ctypes.c_double(), ctypes.c_int()
+        check(lib().cfd_scheme_get_embedded(self._h, ctypes.byref(a2), ctypes.byref(m2)))
+        return {"alpha2": a2.value, "M": m2.value}
+
+    get_embedded = cfd_scheme_get_embedded
+
     def cfd_scheme_required_ghosts(self, boundary: int = CFD_BOUNDARY_CLOSURE) -> int:
         ng = ctypes.c_int()
         check(lib().cfd_scheme_required_ghosts(self._h, boundary, ctypes.byref(ng)))

@@ -47,6 +47,7 @@ SIGNATURES = {
     "cfd_scheme_get": (_i, [_vp, _ip, _ip, _ip, _ip, _ip, _ip, _dp, _dp, _dp]),
     "cfd_scheme_design_biased": (_i, [ctypes.c_char, _i, _d, _i, _pp]),
     "cfd_scheme_get_biased": (_i, [_vp, _ip, _ip, _dp, _dp, _dp]),
+    "cfd_scheme_get_embedded": (_i, [_vp, _dp, _ip]),
     "cfd_scheme_dissipation": (_i, [_i, _d, _pp]),
     "cfd_taylor_scheme": (_i, [_i, _i, _i, _i, _ip, _ip, _ip, _dp, _i, _ip]),
     "cfd_scheme_required_ghosts": (_i, [_vp, _i, _ip]),

@@ -17,6 +17,10 @@
 // Upwind operator (Eq. biasderapproxadv, with c the velocity field sampled on
 // the grid): c d f = min(c, 0) D[right] f + max(c, 0) D[left] f.
 //
+// W schemes (Tab. ccuw_deg_one_col) add w2 s_k to every interior row's right
+// side (-w2 s_k for the right bias), s the embedded second derivative another
+// launch left in the plan scratch and w2 = a2 h^2; the closure rows take none.
+//
 // Partitioned kernel (lines of up to 64 nodes): one lane per line, 64 lines
 // per wave; a line is cut into P = 1, 2 or 4 partitions of at most L = 8, 12
 // or 16 rows (the fewest partitions with at most 12 rows where possible),
@@ -216,6 +220,19 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
         rl[i] = (closureL && i == 0) ? left_closure<T, HB>(q, f + i) : left_interior<T, HB>(q, f + i);
         rr[i] = (closureR && i == nrows - 1) ? right_closure<T, HB>(q, f + i) : right_interior<T, HB>(q, f + i);
     }
+    if (ps.s2 && active) {   // W: the embedded second derivative on the interior rows
+        const T *s2 = (const T *)ps.s2 + ps.s2_base + (int64_t)item.field * ps.out_fstride +
+                      (int64_t)u * ps.osu + (int64_t)v * ps.osv;
+        const T w2 = (T)ps.w2;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            if (i < nrows) {
+                const T e = w2 * s2[(int64_t)(k0 + i) * ps.osd];
+                if (!(closureL && i == 0)) rl[i] += e;
+                if (!(closureR && i == nrows - 1)) rr[i] -= e;
+            }
+        }
+    }
 
     // ---- local solves with zero entering values
     T xl_last = 0, xr_first = 0;
@@ -357,6 +374,12 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
     const T hinv = (T)ps.hinv;
     const T alpha = q.alpha;
     T w[W];
+    // W: w2 times the embedded second derivative at node k (interior rows only)
+    const T *s2 = ps.s2 ? (const T *)ps.s2 + ps.s2_base + (int64_t)item.field * ps.out_fstride +
+                              (int64_t)u * ps.osu + (int64_t)v * ps.osv
+                        : nullptr;
+    const T w2 = (T)ps.w2;
+    auto e2 = [&](int k) -> T { return s2 ? w2 * s2[(int64_t)k * osd] : T(0); };
 
     T xl_wrap = 0, xr_wrap = 0;
     if (ps.periodic) {
@@ -364,9 +387,9 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
         for (int i = 0; i < W; ++i) w[i] = L.ld(i - (HB + 1));
         T sl = 0, sr = 0, pw = 1;
         for (int k = 0; k < N; ++k) {
-            if (ps.mode <= 0 || ps.mode == 2) sl = sl * (-alpha) + left_interior<T, HB>(q, w);
+            if (ps.mode <= 0 || ps.mode == 2) sl = sl * (-alpha) + (left_interior<T, HB>(q, w) + e2(k));
             if (ps.mode >= 0) {
-                sr += pw * right_interior<T, HB>(q, w);
+                sr += pw * (right_interior<T, HB>(q, w) - e2(k));
                 pw *= -alpha;
             }
 #pragma unroll
@@ -394,7 +417,7 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
 #pragma unroll
             for (int i = W - 1; i > 0; --i) w[i] = w[i - 1];
             w[0] = L.ld(N - 2 - (HB + 1));
-            const T r = right_interior<T, HB>(q, w);
+            const T r = right_interior<T, HB>(q, w) - e2(N - 2);
             const T xe = (rb - alpha * r) * q.inv_det;
             xn = r - alpha * xe;
             emit(N - 1, xe);
@@ -405,7 +428,7 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
             k = N - 3;
         }
         for (; k >= 0; --k) {
-            const T x = right_interior<T, HB>(q, w) - alpha * xn;
+            const T x = (right_interior<T, HB>(q, w) - e2(k)) - alpha * xn;
             emit(k, x);
             xn = x;
 #pragma unroll
@@ -431,7 +454,7 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
 #pragma unroll
             for (int i = 0; i < W - 1; ++i) w[i] = w[i + 1];
             w[W - 1] = L.ld(1 + HB + 1);
-            const T r = left_interior<T, HB>(q, w);
+            const T r = left_interior<T, HB>(q, w) + e2(1);
             const T x0 = (rb - alpha * r) * q.inv_det;
             xp = r - alpha * x0;
             emit(0, x0);
@@ -442,7 +465,7 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
             k = 2;
         }
         for (; k < N; ++k) {
-            const T x = left_interior<T, HB>(q, w) - alpha * xp;
+            const T x = (left_interior<T, HB>(q, w) + e2(k)) - alpha * xp;
             emit(k, x);
             xp = x;
 #pragma unroll

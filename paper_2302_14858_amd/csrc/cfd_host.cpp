@@ -114,7 +114,7 @@ struct cfd_plan {
     cfd_dtype dtype = CFD_F64;
     int nfields = 1;
     std::vector<cfd_block> blocks;
-    std::vector<Scheme> schemes;          // one per op
+    std::vector<Scheme> schemes;          // one per op, then the second derivatives W operators embed
     std::vector<cfd_op> ops;              // scheme pointers not used after creation
     std::vector<int> op_nf;               // fields each op writes
     std::vector<int64_t> op_slot;         // S_op
@@ -159,6 +159,11 @@ struct cfd_plan {
     int64_t mscr_elems = 0, mseg_max = 0;
     std::vector<int64_t> msegs;
     DevBuf d_mscr, d_msegs;
+    // W operators: scheme index of the embedded (2)P1_M per op (-1: none), and
+    // per (block, op) the scratch offset of its first field's h^-2 (2)P1_M f,
+    // written by line passes that run before the biased launches
+    std::vector<int> emb_sch;
+    std::map<std::pair<int, int>, int64_t> emb_off;
     std::vector<Group> groups;
     int64_t nitems = 0;
     hipStream_t cap_stream = nullptr;
@@ -1094,6 +1099,15 @@ cfd_status build_biased(cfd_plan *p) {
             q.hinv = 1.0 / bl.h[op.dir];
             q.wrap = 1.0 / (1.0 - std::pow(-s.balpha, (double)d.N));
             q.ev_base = ev_total;
+            q.s2 = nullptr;
+            q.s2_base = 0;
+            q.w2 = 0.0;
+            if (p->emb_sch[o] >= 0) {
+                const int f0e = op.field < 0 ? 0 : op.field;
+                q.s2 = p->d_mscr.p;
+                q.s2_base = p->emb_off.at(std::make_pair((int)b, o)) - (int64_t)f0e * npts;
+                q.w2 = s.ba2 * bl.h[op.dir] * bl.h[op.dir];
+            }
             if (!biased_supported(q.hb)) return fail(CFD_EUNSUPPORTED, "biased stencil half-width not compiled");
             const int pi = (int)bp.size();
             bp.push_back(q);
@@ -1301,24 +1315,35 @@ cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
         cfd_status r = enqueue_iteration(p, in, st);
         if (r != CFD_OK) return r;
     }
-    if (p->nbitems > 0 && p->iter_n > 0 && p->d_bev.p) {
-        // iterated biased closures: iterate [0] writes every line's end values,
-        // each later iterate enters with its neighbours' (Eq. iter_left_X)
-        cfd_status r = launch_biased_groups(p, in, out, st, nullptr, p->d_bends.p);
-        for (int i = 1; i <= p->iter_n && r == CFD_OK; ++i) {
-            hipError_t e = launch_bias_gather(p->dtype != CFD_F64, (int)p->bpinfo.size(), p->bev_max,
-                                              (const int64_t *)p->d_bgrecs.p, p->d_bends.p, p->d_bev.p, st);
-            if (e != hipSuccess) return hip_fail(e, "launching the biased end-value gather");
-            r = launch_biased_groups(p, in, out, st, p->d_bev.p, p->d_bends.p);
+    auto biased = [&]() -> cfd_status {
+        if (p->nbitems > 0 && p->iter_n > 0 && p->d_bev.p) {
+            // iterated biased closures: iterate [0] writes every line's end values,
+            // each later iterate enters with its neighbours' (Eq. iter_left_X)
+            cfd_status r = launch_biased_groups(p, in, out, st, nullptr, p->d_bends.p);
+            for (int i = 1; i <= p->iter_n && r == CFD_OK; ++i) {
+                hipError_t e = launch_bias_gather(p->dtype != CFD_F64, (int)p->bpinfo.size(), p->bev_max,
+                                                  (const int64_t *)p->d_bgrecs.p, p->d_bends.p, p->d_bev.p, st);
+                if (e != hipSuccess) return hip_fail(e, "launching the biased end-value gather");
+                r = launch_biased_groups(p, in, out, st, p->d_bev.p, p->d_bends.p);
+            }
+            return r;
         }
-        if (r != CFD_OK) return r;
-    } else if (p->nbitems > 0) {
-        cfd_status r = launch_biased_groups(p, in, out, st);
+        if (p->nbitems > 0) return launch_biased_groups(p, in, out, st);
+        return CFD_OK;
+    };
+    // W operators read the second derivative stage 0 leaves in the scratch
+    const bool biased_late = !p->emb_off.empty();
+    if (!biased_late) {
+        cfd_status r = biased();
         if (r != CFD_OK) return r;
     }
     // stage 0: every group reading the input; stage 1: the second stage of the
     // mixed derivatives (reads what stage 0 left in the scratch)
     for (int stage = 0; stage < 2; ++stage) {
+        if (stage == 1 && biased_late) {
+            cfd_status r = biased();
+            if (r != CFD_OK) return r;
+        }
         std::vector<const Group *> act;
         for (const Group &g : p->groups)
             if (g.nitems > 0 && g.iomode < 3 && (g.iomode == 2) == (stage == 1)) act.push_back(&g);
@@ -1528,6 +1553,15 @@ cfd_status cfd_scheme_get_biased(const cfd_scheme *sc, int *bias, int *order, do
     return CFD_OK;
 }
 
+cfd_status cfd_scheme_get_embedded(const cfd_scheme *sc, double *alpha2, int *m2) {
+    if (!sc) return fail(CFD_EINVAL, "cfd_scheme_get_embedded: null scheme");
+    const Scheme &s = sc->s;
+    if (s.kind != 1) return fail(CFD_EINVAL, "cfd_scheme_get_embedded: '" + s.name + "' is not a biased scheme");
+    if (alpha2) *alpha2 = s.ba2;
+    if (m2) *m2 = s.emb;
+    return CFD_OK;
+}
+
 cfd_status cfd_taylor_scheme(int dr, int L, int R, int nclass, const int *dI, const int *Lk, const int *Rk,
                              double *coef, int cap, int *order) {
     if (!coef || !order) return fail(CFD_EINVAL, "cfd_taylor_scheme: null output");
@@ -1591,6 +1625,19 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
                 return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: mixed derivatives are not supported");
         }
         p->schemes.push_back(s);
+    }
+    p->emb_sch.assign(p->ops.size(), -1);
+    for (size_t o = 0; o < p->ops.size(); ++o) {
+        const Scheme &s = p->schemes[o];
+        if (s.kind != 1 || s.emb == 0) continue;
+        Scheme e2;
+        std::string err;
+        char nm[16];
+        std::snprintf(nm, sizeof nm, "(2)P1_%d", s.emb);
+        cfd_status est = scheme_from_name(nm, e2, err);
+        if (est != CFD_OK) return fail(est, "cfd_plan_create: embedded second derivative: " + err);
+        p->emb_sch[o] = (int)p->schemes.size();
+        p->schemes.push_back(e2);
     }
     int64_t slot = 0;
     for (const cfd_op &op : p->ops) {
@@ -1832,6 +1879,71 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
                 const int64_t oo = p->out_off[b] + p->op_slot[o] * npts;
                 p->msegs.insert(p->msegs.end(), {oo, t_off[0], t_off[1], nf * npts});
                 p->mseg_max = std::max(p->mseg_max, nf * npts);
+            }
+        }
+        // W operators: their embedded (2)P1_M along the operator's direction over
+        // the block interior, into scratch (lines through the interior only)
+        for (size_t b = 0; b < p->blocks.size(); ++b) {
+            const cfd_block &bl = p->blocks[b];
+            const int64_t ng = bl.ng;
+            const int64_t n[3] = {bl.n[0], bl.n[1], bl.n[2]};
+            const int64_t PX = n[0] + 2 * ng, PY = n[1] + 2 * ng, PZ = n[2] + 2 * ng;
+            const int64_t s_in[3] = {1, PX, PX * PY};
+            const int64_t s_int[3] = {1, n[0], n[0] * n[1]};
+            const int64_t npts = n[0] * n[1] * n[2];
+            for (size_t o = 0; o < p->ops.size(); ++o) {
+                if (p->emb_sch[o] < 0) continue;
+                const cfd_op &op = p->ops[o];
+                const Scheme &e2 = p->schemes[p->emb_sch[o]];
+                const int nf = op.field < 0 ? p->nfields : 1, f0 = op.field < 0 ? 0 : op.field;
+                const int ld = op.dir;
+                const int u = (ld == 0) ? 1 : 0, v = (ld == 2) ? 1 : 2;
+                const bool per = bl.boundary[ld] == CFD_BOUNDARY_PERIODIC;
+                if (!per && n[ld] < 3)
+                    return fail(CFD_ESHAPE, "W operator: closure lines need at least 3 nodes for the embedded "
+                                            "second derivative");
+                if (per && n[ld] < std::max(2 * e2.nl + 1, std::max(e2.m, e2.mc)))
+                    return fail(CFD_ESHAPE, "W operator: periodic line shorter than the embedded stencil");
+                const int64_t S0 = scr;
+                scr += nf * npts;
+                p->emb_off[std::make_pair((int)b, (int)o)] = S0;
+                PassHost ps;
+                ps.block = (int)b;
+                ps.dir = ld;
+                ps.field0 = f0;
+                ps.nfield = nf;
+                ps.N = (int)n[ld];
+                ps.ng = bl.ng;
+                ps.periodic = per;
+                ps.nl = e2.nl;
+                ps.nops = 1;
+                ps.op[0] = (int)o;
+                ps.sch[0] = p->emb_sch[o];
+                ps.par = 0;
+                ps.mi = e2.m;
+                ps.hw = std::max(e2.m, per ? 0 : e2.mc);
+                ps.iomode = 1;
+                ps.custom = true;
+                PassDesc &q = ps.geom;
+                std::memset(&q, 0, sizeof q);
+                q.in_base = p->in_off[b] + ng * (s_in[0] + s_in[1] + s_in[2]);
+                q.in_fstride = PX * PY * PZ;
+                q.su = (int32_t)s_in[u];
+                q.sv = (int32_t)s_in[v];
+                q.sd = (int32_t)s_in[ld];
+                q.out_base[0] = S0;
+                q.out_fstride = npts;
+                q.osu = (int32_t)s_int[u];
+                q.osv = (int32_t)s_int[v];
+                q.osd = (int32_t)s_int[ld];
+                q.nu = (int32_t)n[u];
+                q.nlines = (int32_t)(n[u] * n[v]);
+                q.field0 = f0;
+                q.N = ps.N;
+                q.ng = ps.ng;
+                q.periodic = per;
+                q.nfield_pass = nf;
+                p->passes.push_back(ps);
             }
         }
         p->mscr_elems = scr;
@@ -2551,6 +2663,9 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: not available on the dense mixed-precision path");
     if (iterations > 0 && !p->msegs.empty())
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds mixed derivatives");
+    if (iterations > 0 && !p->emb_off.empty())
+        return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds W operators (their embedded second "
+                                      "derivative has no iterated closure)");
     const int c = 2;
     auto restore = [&]() {
         p->release_biased_iteration();

@@ -51,11 +51,16 @@ struct Scheme {
     double balpha = 0.0;
     double ba[2 * kBiasHalf + 1] = {0};
     double bc[2 * kBiasHalf + 2] = {0};
+    // W_M: interior rows also carry ba2 dx^2 f''_k, with f'' the centred
+    // (2)P1_M (M = emb) solved on the same line with its matched closure;
+    // emb = 0 for schemes without an embedded second derivative.
+    int emb = 0;
+    double ba2 = 0.0;
     std::string name;
 };
 
-// Biased scheme construction (scheme_design.cpp).  family 'V' (M = 1..4) or
-// 'X' (M = 1..3; lambda <= 0 takes the value printed with the scheme).
+// Biased scheme construction (scheme_design.cpp).  family 'V' (M = 1..4), 'X'
+// or 'W' (M = 1..3; lambda <= 0 takes the value printed with the scheme).
 cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &out, std::string &err);
 // Kreiss-Oliger dissipation Q^(2r) (Eq. dissdef) as an explicit scheme.
 cfd_status design_dissipation(int r, double sigma, Scheme &out, std::string &err);
@@ -153,6 +158,13 @@ struct BiasPass {
     double hinv;            // 1 / h
     double wrap;            // periodic: 1 / (1 - (-alpha)^N)
     int64_t ev_base;        // iterated closures: first (field 0, line 0) entry of the pass's end values
+    // W schemes: the embedded second derivative, h^-2 (2)P1_M f, of field f at
+    // interior node (u, v, k) is s2[s2_base + f out_fstride + u osu + v osv + k osd]
+    // (plan scratch, output strides); its weight in a left-biased interior row
+    // is w2 = ba2 h^2 (the right-biased rows take -w2).  s2 = null otherwise.
+    const void *s2;
+    int64_t s2_base;
+    double w2;
 };
 // One work item of the partitioned kernel: 64 * (4 / P) lines of one field of
 // one pass, P partitions per line (one wave each); of the sweep kernel (lines

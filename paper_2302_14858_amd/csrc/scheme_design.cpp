@@ -515,6 +515,12 @@ cfd_status taylor_scheme(int dr, int L, int R, int nclass, const int *dI, const 
 //  V_M (family 'V'): Eq. defChenSchemes with alpha^(2)_0 = 0, order 2M+1.
 //  X_M (family 'X'): lambda U_M + (1 - lambda) V_{M+1} (Eq. LCslowfast) with
 //    the f'' sample of U_M replaced by the explicit (2)E_{M+2}; order 2M+2.
+//  W_M (family 'W'): the same combination keeping a2 dx^2 f''_k, with f'' the
+//    compact centred (2)P1_M solved on the line with its matched explicit
+//    closure (Tab. ccuw_deg_one_col); order 2M+2.  At k*_+ that f'' is the
+//    closure's explicit value, so the row there is the interior row with the
+//    closure stencil in place of f'' (the printed Wtilde); the closure at
+//    k*_- is built, as below, from that explicit row.
 // Closure at k*_-: the mirror image of the scheme plus xi dx^q (alpha^(1) .
 // f^(q)) over its two implicit nodes, f^(q) from the centred (q)E_{q/2}
 // (binomial differences, Tab. diss_scheme), q the first even order above the
@@ -573,15 +579,47 @@ cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &ou
                 err = "biased scheme: combination lost its formal order";
                 return CFD_ESINGULAR;
             }
+    } else if (family == 'W') {
+        if (M < 1 || M > 3) {
+            err = "biased scheme: W_M needs 1 <= M <= 3";
+            return CFD_EUNSUPPORTED;
+        }
+        // sigma printed with the W_M schemes (Tab. ccuw_deg_one_col)
+        static const q kLamW[4] = {0, (q)38 / 100, (q)71 / 100, (q)95 / 100};
+        const q lam = (lambda > 0) ? (q)lambda : kLamW[M];
+        BiasedQ u, v;
+        if (!ucd_scheme('U', M, u) || !ucd_scheme('V', M + 1, v)) {
+            err = "biased scheme: singular Taylor system";
+            return CFD_ESINGULAR;
+        }
+        s.alpha = lam * u.alpha + (1 - lam) * v.alpha;
+        for (int m = -8; m <= 8; ++m) s.a[m + 8] = lam * u.at(m) + (1 - lam) * v.at(m);
+        s.a2 = lam * u.a2;
+        s.order = 2 * M + 2;
+        for (int l = 0; l <= s.order; ++l)
+            if (qabs(biased_residual(s, l) + (l == 2 ? s.a2 : (q)0)) > (q)1e-28Q) {
+                err = "biased scheme: combination lost its formal order";
+                return CFD_ESINGULAR;
+            }
     } else {
-        err = "biased scheme: unknown family (V or X)";
+        err = "biased scheme: unknown family (V, X or W)";
         return CFD_EINVAL;
+    }
+    // the row the closure is built from: the scheme itself, or for W the row
+    // with f'' taken from the explicit closure of (2)P1_M
+    BiasedQ sx = s;
+    if (family == 'W') {
+        Scheme p2;
+        cfd_status pst = design_centred(2, 2 * M + 2, 1, M, 0.0, M + 2, true, p2, err);
+        if (pst != CFD_OK) return pst;
+        for (int m = -(M + 2); m <= M + 2; ++m) sx.a[m + 8] += s.a2 * (q)p2.cl[0][kMaxHalf + m];
+        sx.a2 = 0;
     }
     const int p = s.order;
     const int qo = p + 2 - (p % 2);
     // S = T / A as power series in z up to z^qo
     std::vector<q> T(qo + 1), Am(qo + 1), S(qo + 1);
-    for (int l = 0; l <= qo; ++l) T[l] = biased_residual(s, l);
+    for (int l = 0; l <= qo; ++l) T[l] = biased_residual(sx, l);
     for (int k = 0; k <= qo; ++k) Am[k] = (k == 0 ? (q)1 : (q)0) + s.alpha * qpow_int(-1, k) / qfact(k);
     for (int n = 0; n <= qo; ++n) {
         q acc = T[n];
@@ -593,7 +631,7 @@ cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &ou
     // xi sum_{j=0,1} w_j E_q(m - j), w = (1, alpha)
     const int h = qo / 2;
     q c[2 * 8 + 2] = {0};   // offsets -8..9
-    for (int m = -8; m <= 8; ++m) c[m + 8] += -s.at(-m);
+    for (int m = -8; m <= 8; ++m) c[m + 8] += -sx.at(-m);
     for (int j = 0; j <= 1; ++j) {
         const q w = j ? s.alpha : (q)1;
         for (int t = -h; t <= h; ++t) {
@@ -630,6 +668,10 @@ cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &ou
     r.balpha = (double)s.alpha;
     for (int m = -kBiasHalf; m <= kBiasHalf; ++m) r.ba[m + kBiasHalf] = (double)s.at(m);
     for (int m = -kBiasHalf; m <= kBiasHalf + 1; ++m) r.bc[m + kBiasHalf] = (double)c[m + 8];
+    if (family == 'W') {
+        r.emb = M;
+        r.ba2 = (double)s.a2;
+    }
     // the left-biased rows as a banded operator, for the generic fields
     r.lhs[kMaxNL - 1] = r.balpha;
     r.lhs[kMaxNL] = 1.0;
@@ -691,7 +733,7 @@ cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &e
     const bool order_only = (variant == "E");
     // biased: "(1)V3-", "(1)X2+", "(1)X2" (both biases, upwind by a velocity field), "(1)X2s" (the
     // average of both biases)
-    if (variant.empty() && base.size() >= 5 && base.compare(0, 3, "(1)") == 0 && (base[3] == 'V' || base[3] == 'X') &&
+    if (variant.empty() && base.size() >= 5 && base.compare(0, 3, "(1)") == 0 && (base[3] == 'V' || base[3] == 'X' || base[3] == 'W') &&
         base[4] >= '1' && base[4] <= '9') {
         const std::string tail = base.substr(5);
         int bias;
@@ -888,7 +930,9 @@ int required_ghosts(const Scheme &s, int periodic) {
             }
         for (int m = -kBiasHalf; m <= kBiasHalf + 1; ++m)
             if (s.bc[m + kBiasHalf] != 0) lc = std::max(lc, -m);
-        return std::max(lc, std::max(la - 1, ra));
+        int need = std::max(lc, std::max(la - 1, ra));
+        if (s.emb) need = std::max(need, s.emb + 2);   // the embedded (2)P1_M closure
+        return need;
     }
     if (s.nl == 0) return s.m;
     int need = s.m - s.nc;

@@ -25,7 +25,7 @@ def op_fields(wl, ops):
 def biased_name(name):
     """(base name, bias) for a biased scheme name ("(1)X2-" -> ("(1)X2", -1); "(1)X2" -> upwind, 0;
     "(1)X2s" -> symmetrised, 2), else None."""
-    if len(name) >= 5 and name.startswith("(1)") and name[3] in "VX" and name[4].isdigit():
+    if len(name) >= 5 and name.startswith("(1)") and name[3] in "VXW" and name[4].isdigit():
         base, tail = name[:5], name[5:]
         return base, {"-": -1, "+": 1, "": 0, "s": 2}[tail]
     return None

@@ -183,7 +183,7 @@ def test_debug_alloc_hook_is_harmless_without_device():
     P.cfd_debug_fail_alloc(-1)
 
 
-BIASED = ["(1)V1", "(1)V2", "(1)V3", "(1)V4", "(1)X1", "(1)X2", "(1)X3"]
+BIASED = ["(1)V1", "(1)V2", "(1)V3", "(1)V4", "(1)X1", "(1)X2", "(1)X3", "(1)W1", "(1)W2", "(1)W3"]
 
 
 @pytest.mark.parametrize("name", BIASED)
@@ -205,12 +205,17 @@ def test_biased_registry_matches_oracle(name, suffix, bias):
     sch = P.Scheme.named(name + suffix)
     assert sch.required_ghosts() == OB.required_ghosts(name)
     assert sch.required_ghosts(P.CFD_BOUNDARY_PERIODIC) == 0
+    e = sch.get_embedded()
+    if name[3] == "W":
+        assert e["M"] == int(name[4:]) and e["alpha2"] == float(s.rhs[1].get(0))
+    else:
+        assert e == {"alpha2": 0.0, "M": 0}
 
 
 def test_biased_design_ranges_and_lambda():
     from oracle import biased as OB
     from fractions import Fraction
-    for fam, M in (("V", 0), ("V", 5), ("X", 0), ("X", 4)):
+    for fam, M in (("V", 0), ("V", 5), ("X", 0), ("X", 4), ("W", 0), ("W", 4)):
         with pytest.raises(P.CfdError) as e:
             P.Scheme.design_biased(fam, M)
         assert e.value.status == _lib.CFD_EUNSUPPORTED
@@ -229,6 +234,19 @@ def test_biased_design_ranges_and_lambda():
     cc = np.array([float(c.rhs[0].get(m)) for m in range(-5, 7)])
     assert np.max(np.abs(a - g["a"])) <= 4e-16 * np.max(np.abs(a))
     assert np.max(np.abs(cc - g["c"])) <= 8e-16 * np.max(np.abs(cc))
+    # W with another lambda: the library and the oracle's construction follow it
+    g = P.Scheme.design_biased("W", 2, 0.5, 1).get_biased()
+    s = OB.wscheme(2, Fraction(1, 2))
+    _, c = OB.xi_closure(OB.with_explicit_second(s, OB.embedded_second(2).closure[0]))
+    a = np.array([float(s.rhs[0].get(m)) for m in range(-5, 6)])
+    cc = np.array([float(c.rhs[0].get(m)) for m in range(-5, 7)])
+    assert g["bias"] == 1 and abs(g["alpha"] - float(s.lhs.get(-1))) <= 2e-16
+    assert np.max(np.abs(a - g["a"])) <= 4e-16 * np.max(np.abs(a))
+    assert np.max(np.abs(cc - g["c"])) <= 8e-16 * np.max(np.abs(cc))
+    assert P.Scheme.design_biased("W", 2, 0.5, 1).get_embedded()["alpha2"] == float(s.rhs[1].get(0))
+    with pytest.raises(P.CfdError) as e:
+        P.Scheme.named("(1)Q1_3[1]").get_embedded()
+    assert e.value.status == _lib.CFD_EINVAL
     with pytest.raises(P.CfdError):
         P.Scheme.named("(1)X2*")
     with pytest.raises(P.CfdError):

@@ -173,3 +173,61 @@ def test_symmetrised_biased(cuda, name, dtype):
         plan = H.make_plan(wl, ops, dtype=dtype)
         err = H.full_parity(plan, wl, ops, dtype)
         assert err <= H.tol_for(dtype), (wl.name, err)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("M", [1, 2, 3])
+def test_w_schemes_embedded_second_derivative(cuda, M, dtype):
+    """W_M (Tab. ccuw_deg_one_col): both biases, the upwind pair and the symmetrised mean along x, y, z,
+    each interior row taking the compact (2)P1_M second derivative that a line pass leaves in the plan
+    scratch before the biased launches: closure blocks (lengths 7..48, the partitioned kernel; N_g =
+    M + 2 and one more), a periodic box (line lengths the periodic line kernel takes for the embedded
+    pass: partitions of 8..32 rows), and lines of 80 nodes (the sweep kernel), against the oracle."""
+    from oracle import biased as OB
+    name = f"(1)W{M}"
+    ng = OB.required_ghosts(name)
+    for wl in (synth.batch64(nblocks=5, nfields=3, sizes=(7, 16, 23, 48), ng=ng, seed=31 + M),
+               synth.batch64(nblocks=3, nfields=2, sizes=(9, 16), ng=ng + 1, seed=34 + M),
+               synth.periodic_box(n=(64, 8, 12), nfields=2, seed=37 + M),
+               synth.batch64(nblocks=2, nfields=2, sizes=(80, 12), ng=ng, seed=40 + M)):
+        ops = []
+        for d in range(3):
+            ops += [(name + "-", d), (name + "+", d, 1), (name, d, -1, 1), (name + "s", d)]
+        plan = H.make_plan(wl, ops, dtype=dtype)
+        err = H.full_parity(plan, wl, ops, dtype)
+        assert err <= H.tol_for(dtype), (wl.name, err)
+
+
+def test_w_scheme_in_a_mixed_plan_and_graph(cuda):
+    """W operators beside centred and X operators in one plan (the embedded pass shares the launch
+    groups of the centred passes; the biased launches follow them), autotuned; the captured graph
+    replays the eager result bit for bit, and cfd_plan_set_iteration refuses the plan."""
+    import torch
+    import paper_2302_14858_amd as P
+    from paper_2302_14858_amd import _lib
+    wl = synth.batch64(nblocks=5, nfields=4, ng=5, seed=44)
+    ops = [("(1)QP_O8[1]", 0), ("(2)QP_O8[1]", 1), ("(1)W2-", 0, 2), ("(1)W3", 1, -1, 0), ("(1)X2+", 2),
+           ("(1)W1s", 2, 3)]
+    plan = H.make_plan(wl, ops)
+    err = H.full_parity(plan, wl, ops)
+    assert err <= H.ERR_F64, err
+    _, nout = plan.sizes()
+    x = torch.from_numpy(wl.data).cuda()
+    y0 = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.autotune(x, y0)
+    y0.fill_(float("nan"))
+    plan.apply(x, y0)
+    torch.cuda.synchronize()
+    assert not torch.isnan(y0).any()
+    y1 = torch.full((nout,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.capture_graph(x, y1)
+    for _ in range(3):
+        plan.launch_graph()
+        torch.cuda.synchronize()
+        assert torch.equal(y0, y1)
+        y1.fill_(float("nan"))
+        torch.cuda.synchronize()
+    with pytest.raises(P.CfdError) as e:
+        plan.set_iteration(1, 5, 1, 1)
+    assert e.value.status == _lib.CFD_EUNSUPPORTED
+
