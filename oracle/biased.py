@@ -6,7 +6,9 @@ module; only ``tests/`` and the benchmark's CPU-baseline leg use it.
 Written from Daszuta, arXiv 2302.14858, Sec. ssec:domdec_drp:
 
 * ``ucd``: the left-biased first-degree schemes U^-_M (order 2M+2, with the
-  embedded f'' sample) and V^-_M (order 2M+1, alpha^(2)_0 = 0) of
+  f'' sample; as a line operator, ``line_matrices`` / ``apply_block_hermite``,
+  it takes the sampled f'' as data on every row, closure row included) and
+  V^-_M (order 2M+1, alpha^(2)_0 = 0) of
   Eq. defChenSchemes, fixed by Taylor matching (Eq. Tcons) on the ansatz of
   Eq. mdAnsatz with alpha^(1) on nodes k-1, k and alpha^(0) on k-M .. k+M.
 * ``mirror``: the right-biased scheme of a left-biased one,
@@ -226,14 +228,17 @@ def w_eps_series(M: int, nterms: int):
 
 @lru_cache(maxsize=None)
 def named(name: str) -> Tuple[Scheme, Scheme]:
-    """(left-biased interior scheme, its closure row at k*_-) for "(1)V{M}" (M = 1..4),
-    "(1)X{M}" or "(1)W{M}" (M = 1..3).  U needs the sampled f'' and is not a line operator on f
-    alone; W carries its f'' term in rhs[1], filled by the embedded second derivative."""
+    """(left-biased interior scheme, its closure row at k*_-) for "(1)V{M}", "(1)U{M}" (M = 1..4),
+    "(1)X{M}" or "(1)W{M}" (M = 1..3).  U carries the sampled f'' term in rhs[1] of both rows
+    (a Hermite-type input, see ``line_matrices``); W carries its f'' term in rhs[1] of the interior
+    row, filled by the embedded second derivative."""
     if not name.startswith("(1)"):
         raise KeyError(name)
     kind, M = name[3], int(name[4:])
     if kind == "V" and 1 <= M <= 4:
         s = ucd("V", M)
+    elif kind == "U" and 1 <= M <= 4:
+        s = ucd("U", M)
     elif kind == "X" and M in X_LAMBDA:
         s = xscheme(M)
     elif kind == "W" and M in W_LAMBDA:
@@ -270,13 +275,24 @@ def line_matrix(name: str, bias: int, N: int, ng: int, periodic: bool) -> np.nda
     """Dense D with f~ = h^-1 D g for one line, g holding the N + 2 ng samples
     (g[ng + k] is interior node k).  bias = -1: left-biased rows with the closure
     at k*_-; bias = +1: the mirror image (closure at k*_+)."""
+    if name[3] == "U":
+        raise ValueError(f"{name} needs the sampled f'' (line_matrices)")
+    return line_matrices(name, bias, N, ng, periodic)[0]
+
+
+@lru_cache(maxsize=None)
+def line_matrices(name: str, bias: int, N: int, ng: int, periodic: bool):
+    """(D, D2): f~ = h^-1 D g + h D2 s for one line, s the sampled f'' on the N interior nodes
+    (D2 is None unless the scheme samples f'', i.e. U_M: every row of Eq. defChenSchemes, closure
+    row included, carries its alpha^(2)_0 dx^2 f''_k)."""
     s, c = named(name)
     if bias > 0:
         s, c = mirror(s), mirror(c)
     A = np.zeros((N, N))
     B = np.zeros((N, N + 2 * ng))
     E2 = None
-    if len(s.rhs) > 1:
+    C2 = np.zeros((N, N)) if name[3] == "U" else None
+    if len(s.rhs) > 1 and C2 is None:
         # W: the f'' term of every interior row from the embedded second derivative
         # (unit spacing), dense over the same samples
         P = embedded_second(int(name[4:]))
@@ -310,11 +326,17 @@ def line_matrix(name: str, bias: int, N: int, ng: int, periodic: bool) -> np.nda
         closure_row = (not periodic) and ((bias < 0 and k == 0) or (bias > 0 and k == N - 1))
         if closure_row:
             put(k, c.lhs, c.rhs[0], False)
+            if C2 is not None:
+                C2[k, k] = _f(c.rhs[1].get(0))
         else:
             put(k, s.lhs, s.rhs[0], periodic)
             if E2 is not None:
                 B[k] += a2 * E2[k]
-    return np.linalg.solve(A, B)
+            if C2 is not None:
+                C2[k, k] = _f(s.rhs[1].get(0))
+    if C2 is None:
+        return np.linalg.solve(A, B), None
+    return np.linalg.solve(A, B), np.linalg.solve(A, C2)
 
 
 def apply_block(name: str, bias: int, f: np.ndarray, ng: int, h: float, direction: int,
@@ -341,23 +363,52 @@ def apply_block(name: str, bias: int, f: np.ndarray, ng: int, h: float, directio
     return np.moveaxis(out, -1, ax)
 
 
+def apply_block_hermite(name: str, bias: int, f: np.ndarray, f2: np.ndarray, ng: int, h: float, direction: int,
+                        periodic: bool = False) -> np.ndarray:
+    """U_M: the biased first derivative along ``direction`` of one block-field [z][y][x] (ng ghosts)
+    given the sampled second derivative f2 of the same field along that direction on the interior
+    [z][y][x]."""
+    f = np.asarray(f, dtype=np.float64)
+    nz, ny, nx = (e - 2 * ng for e in f.shape)
+    N = (nx, ny, nz)[direction]
+    D, D2 = line_matrices(name, bias, N, ng, periodic)
+    ax = 2 - direction
+    g = np.moveaxis(f, ax, -1)
+    sl = [slice(ng, ng + e) for e in (nz, ny, nx)]
+    del sl[ax]
+    g = g[tuple(sl)]
+    if periodic:
+        gi = g[..., ng:ng + N]
+        g = np.concatenate([gi[..., N - ng:] if ng else gi[..., :0], gi, gi[..., :ng]], axis=-1)
+    s2 = np.moveaxis(np.asarray(f2, dtype=np.float64), ax, -1)
+    out = g @ D.T / h + (s2 @ D2.T) * h
+    return np.moveaxis(out, -1, ax)
+
+
+def _one_bias(name, bias, f, ng, h, direction, periodic, f2):
+    if f2 is not None:
+        return apply_block_hermite(name, bias, f, f2, ng, h, direction, periodic)
+    return apply_block(name, bias, f, ng, h, direction, periodic)
+
+
 def upwind_block(name: str, f: np.ndarray, c: np.ndarray, ng: int, h: float, direction: int,
-                 periodic: bool = False) -> np.ndarray:
+                 periodic: bool = False, f2: np.ndarray = None) -> np.ndarray:
     """c d_dir f with upwind selection (Eq. biasderapproxadv, read as stated in
     the module header): c > 0 takes the left-biased scheme, c < 0 the
-    right-biased one; c is the interior [z][y][x] of the velocity field."""
-    dl = apply_block(name, -1, f, ng, h, direction, periodic)
-    dr = apply_block(name, +1, f, ng, h, direction, periodic)
+    right-biased one; c is the interior [z][y][x] of the velocity field
+    (f2: the sampled f'' of U_M)."""
+    dl = _one_bias(name, -1, f, ng, h, direction, periodic, f2)
+    dr = _one_bias(name, +1, f, ng, h, direction, periodic, f2)
     c = np.asarray(c, dtype=np.float64)
     return 0.5 * (c - np.abs(c)) * dr + 0.5 * (c + np.abs(c)) * dl
 
 
 def symmetrised_block(name: str, f: np.ndarray, ng: int, h: float, direction: int,
-                      periodic: bool = False) -> np.ndarray:
+                      periodic: bool = False, f2: np.ndarray = None) -> np.ndarray:
     """The symmetrised biased derivative: the mean of the left- and right-biased results
     (the symmetrisation of biased schemes in the decomposition study of Sec. 2.5)."""
-    return 0.5 * (apply_block(name, -1, f, ng, h, direction, periodic) +
-                  apply_block(name, +1, f, ng, h, direction, periodic))
+    return 0.5 * (_one_bias(name, -1, f, ng, h, direction, periodic, f2) +
+                  _one_bias(name, +1, f, ng, h, direction, periodic, f2))
 
 
 def iterated_ghosts(name: str) -> int:

@@ -356,3 +356,55 @@ def test_biased_iteration_converges_faster_than_centred():
     gc = OL.apply_line(sc, g, 0, h, periodic=True)
     ec = [IT.modal_rms_error(gc, it.reshape(-1))[0] for it in IT.iterate_1d(sc, blocks, ng, h, 2)]
     assert eb[1] / eb[0] < 0.1 * (ec[1] / ec[0]), (eb, ec)
+
+
+@pytest.mark.parametrize("M", [1, 2, 3])
+@pytest.mark.parametrize("bias", [-1, 1])
+def test_u_line_operator_with_sampled_second_derivative(M, bias):
+    """U_M as a line operator on (f, f''): exact on polynomials up to its formal order 2M+2 on every
+    row, closure row included (its f'' term is the mirror's, -alpha^(2)_0), and not beyond; the
+    closure row's f'' weight is the interior's negated."""
+    name = f"(1)U{M}"
+    s, c = B.named(name)
+    assert c.rhs[1].dK == 2 and c.rhs[1].get(0) == -s.rhs[1].get(0)
+    ng, N, h = B.required_ghosts(name), 19, 0.1
+    D, D2 = B.line_matrices(name, bias, N, ng, False)
+    x = (np.arange(N + 2 * ng) - ng) * h + 0.37
+    worst = 0.0
+    for deg in range(s.order + 2):
+        t = x / (N * h)
+        coef = np.arange(1, deg + 2) * 0.1 + 1
+        f = sum(cf * t ** j for j, cf in enumerate(coef))
+        df = sum((j * cf * t ** (j - 1) for j, cf in enumerate(coef) if j), np.zeros_like(t)) / (N * h)
+        d2f = sum((j * (j - 1) * cf * t ** (j - 2) for j, cf in enumerate(coef) if j > 1), np.zeros_like(t)) / (N * h) ** 2
+        got = D @ f / h + h * (D2 @ d2f[ng:ng + N])
+        rel = np.max(np.abs(got - df[ng:ng + N])) / max(1.0, np.max(np.abs(df)))
+        if deg <= s.order:
+            assert rel < 1e-11, deg
+            worst = max(worst, rel)
+        else:                                                 # order is not higher than stated
+            assert rel > 10 * max(worst, 1e-15)
+    with pytest.raises(ValueError):
+        B.line_matrix(name, bias, N, ng, False)
+
+
+@pytest.mark.parametrize("M", [1, 3])
+@pytest.mark.parametrize("bias", [-1, 1])
+def test_u_periodic_closed_form(M, bias):
+    """On a periodic line, with f'' sampled exactly, a Fourier mode is an eigenvector with the
+    eigenvalue of U_M's symbol (Eq. fdpwerrdef with the f'' class)."""
+    name = f"(1)U{M}"
+    s, _ = B.named(name)
+    if bias > 0:
+        s = B.mirror(s)
+    N = 48
+    h = 2 * np.pi / N
+    x = np.arange(N) * h
+    D, D2 = B.line_matrices(name, bias, N, 0, True)
+    for k, ph in ((1, 0.3), (7, 1.1), (19, 2.0)):
+        th = k * x + ph
+        got = D @ np.sin(th) / h + h * (D2 @ (-k * k * np.sin(th)))
+        with mp.workdps(30):
+            et = complex(S.modified_wavenumber_power(s, k * h) / 1j)
+        ref = (et.real * np.cos(th) - et.imag * np.sin(th)) / h
+        assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref)), k
