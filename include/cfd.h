@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define CFD_ABI_VERSION 2
+#define CFD_ABI_VERSION 3
 
 typedef enum {
     CFD_OK = 0,
@@ -97,6 +97,9 @@ const char *cfd_last_error(void);
  *   "(1)VM-", "(1)VM+" M = 1..4: V_M of Tab. ucd_fast, left / right biased,
  *                      with the xi-closure of Tab. ucd_fast_closure.
  *   "(1)XM-", "(1)XM+" M = 1..3: X_M of Tab. ccux_deg_one_col with its closure.
+ *   "(1)UM-", "(1)UM+" M = 1..3: U_M of Tab. ucd_slow with the xi-closure of Tab.
+ *                      ucd_slow_closure; it samples f'' (cfd_op.aux_field) on
+ *                      every row, the closure row included.
  *   "(1)WM-", "(1)WM+" M = 1..3: W_M of Tab. ccuw_deg_one_col (embedded compact
  *                      second derivative) with its closure; "(1)WM" and "(1)WMs"
  *                      as below.
@@ -129,7 +132,11 @@ cfd_status cfd_scheme_named(const char *name, cfd_scheme **out);
  * for V_M).  CFD_EUNSUPPORTED outside the ranges above (stencil half-widths
  * above 5), CFD_EINVAL on a bad family or bias. */
 cfd_status cfd_scheme_design_biased(char family, int M, double lambda, int bias, cfd_scheme **out);
-/* family 'W': W_M (M = 1..3, Tab. ccuw_deg_one_col), the same combination
+/* family 'U': U_M (M = 1..3; M = 4 needs a wider closure than the kernels
+ * take), Eq. defChenSchemes with the f'' sample, formal order 2M+2; its rows
+ * read f'' from an input field (cfd_op.aux_field): interior rows with weight
+ * alpha^(2)_0, the closure row with the mirror's, -alpha^(2)_0.
+ * family 'W': W_M (M = 1..3, Tab. ccuw_deg_one_col), the same combination
  * keeping alpha^(2)_0 dx^2 f''_k on every interior row, with f'' the compact
  * centred (2)P1_M solved on the same line with its matched explicit closure
  * (lambda <= 0 takes the printed sigma), formal order 2M+2.  At the far end
@@ -162,11 +169,12 @@ cfd_status cfd_scheme_dissipation(int r, double sigma, cfd_scheme **out);
 cfd_status cfd_scheme_get_biased(const cfd_scheme *s, int *bias, int *order, double *alpha, double *a11,
                                  double *c12);
 
-/* Read back the embedded second derivative of a biased scheme (W_M of Tab.
- * ccuw_deg_one_col): alpha2 receives alpha^(2)_0 of the left-biased interior
- * row (its right side is sum_m a_m f_{k+m} + alpha2 dx^2 f''_k; the right bias
- * takes -alpha2), m2 the M of the embedded (2)P1_M.  Schemes without one give
- * 0 and 0.  Either pointer may be NULL.  CFD_EINVAL for a centred scheme. */
+/* Read back the second-derivative term of a biased scheme: alpha2 receives
+ * alpha^(2)_0 of the left-biased interior row (its right side is
+ * sum_m a_m f_{k+m} + alpha2 dx^2 f''_k; the right bias takes -alpha2), m2 the
+ * M of the embedded (2)P1_M for W_M (Tab. ccuw_deg_one_col), 0 for U_M (f''
+ * sampled from cfd_op.aux_field).  Schemes without the term give 0 and 0.
+ * Either pointer may be NULL.  CFD_EINVAL for a centred scheme. */
 cfd_status cfd_scheme_get_embedded(const cfd_scheme *s, double *alpha2, int *m2);
 
 /* Fully determined scheme of the multi-derivative ansatz (Eq. mdAnsatz):
@@ -259,13 +267,18 @@ typedef struct {
  * is taken on the lines through the block extended by its ng ghost layers
  * along i (edge ghosts are read), so the outer one has its ghost values.  The
  * plan computes both compositions into a scratch buffer it owns (about four
- * times the operator's output) and averages them. */
+ * times the operator's output) and averages them.
+ * aux_field: for a U_M scheme ("(1)UM-" etc., Tab. ucd_slow), which samples
+ * f'' as data, the field holding the second derivative of `field` along dir
+ * (read on the interior nodes; field must be a single index); -1 for every
+ * other scheme. */
 typedef struct {
     const cfd_scheme *scheme;
     int dir;
     int field;
     int vel_field;
     int dir2;
+    int aux_field;
 } cfd_op;
 
 typedef struct {

@@ -165,9 +165,10 @@ class Plan:
 
     blocks: list of dicts with keys n (3 ints), ng, h (3 floats), boundary (3 ints),
             optional in_offset / out_offset (elements; default packed).
-    ops:    list of (Scheme, dir), (Scheme, dir, field), (Scheme, dir, field, vel_field) or
-            (Scheme, dir, field, vel_field, dir2); vel_field (the velocity of an upwind pair) and
-            dir2 (second direction of a mixed derivative) default to -1.
+    ops:    list of (Scheme, dir), (Scheme, dir, field), (Scheme, dir, field, vel_field),
+            (Scheme, dir, field, vel_field, dir2) or (..., dir2, aux_field); vel_field (the velocity
+            of an upwind pair), dir2 (second direction of a mixed derivative) and aux_field (the
+            sampled f'' a U scheme reads) default to -1.
     """
 
     def __init__(self, blocks: List[Dict], nfields: int, ops: Sequence, dtype: int = CFD_F64, device: int = 0):
@@ -188,6 +189,7 @@ class Plan:
             oarr[i].field = int(op[2]) if len(op) > 2 else -1
             oarr[i].vel_field = int(op[3]) if len(op) > 3 else -1
             oarr[i].dir2 = int(op[4]) if len(op) > 4 else -1
+            oarr[i].aux_field = int(op[5]) if len(op) > 5 else -1
         desc = _lib.cfd_plan_desc(nb, arr, int(nfields), len(ops), oarr, int(dtype), int(device), 0)
         out = ctypes.c_void_p()
         check(lib().cfd_plan_create(ctypes.byref(desc), ctypes.byref(out)))

@@ -22,7 +22,7 @@ class cfd_block(ctypes.Structure):
 
 class cfd_op(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_void_p), ("dir", ctypes.c_int), ("field", ctypes.c_int),
-                ("vel_field", ctypes.c_int), ("dir2", ctypes.c_int)]
+                ("vel_field", ctypes.c_int), ("dir2", ctypes.c_int), ("aux_field", ctypes.c_int)]
 
 
 class cfd_plan_desc(ctypes.Structure):

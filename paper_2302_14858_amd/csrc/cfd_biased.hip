@@ -20,6 +20,8 @@
 // W schemes (Tab. ccuw_deg_one_col) add w2 s_k to every interior row's right
 // side (-w2 s_k for the right bias), s the embedded second derivative another
 // launch left in the plan scratch and w2 = a2 h^2; the closure rows take none.
+// U schemes (Tab. ucd_slow) read s, the sampled f'', from an input field and
+// add it on every row, the closure row with its own weight w2c.
 //
 // Partitioned kernel (lines of up to 64 nodes): one lane per line, 64 lines
 // per wave; a line is cut into P = 1, 2 or 4 partitions of at most L = 8, 12
@@ -220,16 +222,16 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
         rl[i] = (closureL && i == 0) ? left_closure<T, HB>(q, f + i) : left_interior<T, HB>(q, f + i);
         rr[i] = (closureR && i == nrows - 1) ? right_closure<T, HB>(q, f + i) : right_interior<T, HB>(q, f + i);
     }
-    if (ps.s2 && active) {   // W: the embedded second derivative on the interior rows
-        const T *s2 = (const T *)ps.s2 + ps.s2_base + (int64_t)item.field * ps.out_fstride +
-                      (int64_t)u * ps.osu + (int64_t)v * ps.osv;
-        const T w2 = (T)ps.w2;
+    if ((ps.s2 || ps.s2_in) && active) {   // W, U: the second-derivative term of each row
+        const T *s2 = (ps.s2_in ? in : (const T *)ps.s2) + ps.s2_base + (int64_t)item.field * ps.s2f +
+                      (int64_t)u * ps.s2u + (int64_t)v * ps.s2v;
+        const T w2 = (T)ps.w2, w2c = (T)ps.w2c;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             if (i < nrows) {
-                const T e = w2 * s2[(int64_t)(k0 + i) * ps.osd];
-                if (!(closureL && i == 0)) rl[i] += e;
-                if (!(closureR && i == nrows - 1)) rr[i] -= e;
+                const T e = s2[(int64_t)(k0 + i) * ps.s2d];
+                rl[i] += ((closureL && i == 0) ? w2c : w2) * e;
+                rr[i] -= ((closureR && i == nrows - 1) ? w2c : w2) * e;
             }
         }
     }
@@ -374,12 +376,14 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
     const T hinv = (T)ps.hinv;
     const T alpha = q.alpha;
     T w[W];
-    // W: w2 times the embedded second derivative at node k (interior rows only)
-    const T *s2 = ps.s2 ? (const T *)ps.s2 + ps.s2_base + (int64_t)item.field * ps.out_fstride +
-                              (int64_t)u * ps.osu + (int64_t)v * ps.osv
-                        : nullptr;
-    const T w2 = (T)ps.w2;
-    auto e2 = [&](int k) -> T { return s2 ? w2 * s2[(int64_t)k * osd] : T(0); };
+    // W, U: the second-derivative term at node k, interior rows (e2) and closure row (e2c)
+    const T *s2 = (ps.s2 || ps.s2_in) ? (ps.s2_in ? in : (const T *)ps.s2) + ps.s2_base +
+                                            (int64_t)item.field * ps.s2f + (int64_t)u * ps.s2u +
+                                            (int64_t)v * ps.s2v
+                                      : nullptr;
+    const T w2 = (T)ps.w2, w2c = (T)ps.w2c;
+    auto e2 = [&](int k) -> T { return s2 ? w2 * s2[(int64_t)k * ps.s2d] : T(0); };
+    auto e2c = [&](int k) -> T { return s2 ? w2c * s2[(int64_t)k * ps.s2d] : T(0); };
 
     T xl_wrap = 0, xr_wrap = 0;
     if (ps.periodic) {
@@ -413,7 +417,7 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
         int k = N - 1;
         T xn = xr_wrap;
         if (!ps.periodic) {
-            const T rb = right_closure<T, HB>(q, w);
+            const T rb = right_closure<T, HB>(q, w) - e2c(N - 1);
 #pragma unroll
             for (int i = W - 1; i > 0; --i) w[i] = w[i - 1];
             w[0] = L.ld(N - 2 - (HB + 1));
@@ -450,7 +454,7 @@ __global__ __launch_bounds__(256) void k_biased(const BiasItem *__restrict__ ite
         int k = 0;
         T xp = xl_wrap;
         if (!ps.periodic) {
-            const T rb = left_closure<T, HB>(q, w);
+            const T rb = left_closure<T, HB>(q, w) + e2c(0);
 #pragma unroll
             for (int i = 0; i < W - 1; ++i) w[i] = w[i + 1];
             w[W - 1] = L.ld(1 + HB + 1);

@@ -1100,13 +1100,27 @@ cfd_status build_biased(cfd_plan *p) {
             q.wrap = 1.0 / (1.0 - std::pow(-s.balpha, (double)d.N));
             q.ev_base = ev_total;
             q.s2 = nullptr;
-            q.s2_base = 0;
-            q.w2 = 0.0;
-            if (p->emb_sch[o] >= 0) {
+            q.s2_base = q.s2f = 0;
+            q.s2u = q.s2v = q.s2d = q.s2_in = 0;
+            q.w2 = q.w2c = 0.0;
+            const double h2 = bl.h[op.dir] * bl.h[op.dir];
+            if (p->emb_sch[o] >= 0) {   // W: the embedded pass's result in scratch
                 const int f0e = op.field < 0 ? 0 : op.field;
                 q.s2 = p->d_mscr.p;
                 q.s2_base = p->emb_off.at(std::make_pair((int)b, o)) - (int64_t)f0e * npts;
-                q.w2 = s.ba2 * bl.h[op.dir] * bl.h[op.dir];
+                q.s2f = d.out_fstride;
+                q.s2u = d.osu;
+                q.s2v = d.osv;
+                q.s2d = d.osd;
+                q.w2 = s.ba2 * h2;
+            } else if (s.hermite) {     // U: the sampled f'' field of the input
+                q.s2_in = 1;
+                q.s2_base = d.in_base + (int64_t)op.aux_field * d.in_fstride;
+                q.s2u = d.su;
+                q.s2v = d.sv;
+                q.s2d = d.sd;
+                q.w2 = s.ba2 * h2;
+                q.w2c = s.bc2 * h2;
             }
             if (!biased_supported(q.hb)) return fail(CFD_EUNSUPPORTED, "biased stencil half-width not compiled");
             const int pi = (int)bp.size();
@@ -1612,6 +1626,15 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
         } else if (op.vel_field != -1) {
             return fail(CFD_EINVAL, "cfd_plan_create: vel_field must be -1 for operator '" + s.name +
                                         "' (only upwind pairs read a velocity field)");
+        }
+        if (s.kind == 1 && s.hermite) {
+            if (op.aux_field < 0 || op.aux_field >= desc->nfields || op.field < 0)
+                return fail(CFD_EINVAL, "cfd_plan_create: operator '" + s.name +
+                                            "' samples f'': it needs one field and aux_field, the field holding "
+                                            "its second derivative, in 0..nfields-1");
+        } else if (op.aux_field != -1) {
+            return fail(CFD_EINVAL, "cfd_plan_create: aux_field must be -1 for operator '" + s.name +
+                                        "' (only U schemes read a sampled second derivative)");
         }
         if (s.kind == 1 && desc->dtype == CFD_MIXED_BF16)
             return fail(CFD_EUNSUPPORTED, "mixed-precision dense path: biased schemes are not supported");
@@ -2666,6 +2689,9 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
     if (iterations > 0 && !p->emb_off.empty())
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds W operators (their embedded second "
                                       "derivative has no iterated closure)");
+    for (size_t o = 0; o < p->ops.size() && iterations > 0; ++o)
+        if (p->schemes[o].kind == 1 && p->schemes[o].hermite)
+            return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds U operators (sampled f'')");
     const int c = 2;
     auto restore = [&]() {
         p->release_biased_iteration();

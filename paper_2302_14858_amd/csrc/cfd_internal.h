@@ -56,11 +56,15 @@ struct Scheme {
     // emb = 0 for schemes without an embedded second derivative.
     int emb = 0;
     double ba2 = 0.0;
+    // U_M: every row carries a sampled f''_k from an input field (cfd_op
+    // aux_field), weight ba2 on interior rows and bc2 on the closure row.
+    int hermite = 0;
+    double bc2 = 0.0;
     std::string name;
 };
 
-// Biased scheme construction (scheme_design.cpp).  family 'V' (M = 1..4), 'X'
-// or 'W' (M = 1..3; lambda <= 0 takes the value printed with the scheme).
+// Biased scheme construction (scheme_design.cpp).  family 'U' or 'V' (M = 1..4),
+// 'X' or 'W' (M = 1..3; lambda <= 0 takes the value printed with the scheme).
 cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &out, std::string &err);
 // Kreiss-Oliger dissipation Q^(2r) (Eq. dissdef) as an explicit scheme.
 cfd_status design_dissipation(int r, double sigma, Scheme &out, std::string &err);
@@ -158,13 +162,17 @@ struct BiasPass {
     double hinv;            // 1 / h
     double wrap;            // periodic: 1 / (1 - (-alpha)^N)
     int64_t ev_base;        // iterated closures: first (field 0, line 0) entry of the pass's end values
-    // W schemes: the embedded second derivative, h^-2 (2)P1_M f, of field f at
-    // interior node (u, v, k) is s2[s2_base + f out_fstride + u osu + v osv + k osd]
-    // (plan scratch, output strides); its weight in a left-biased interior row
-    // is w2 = ba2 h^2 (the right-biased rows take -w2).  s2 = null otherwise.
+    // Second-derivative term of W and U schemes: the value for field f at
+    // interior node (u, v, k) is src[s2_base + f s2f + u s2u + v s2v + k s2d],
+    // src the plan scratch s2 (W: the embedded h^-2 (2)P1_M f, output strides)
+    // or, with s2_in, the input (U: the sampled f'' field, input strides, s2f =
+    // 0).  Weights in a left-biased row: w2 = ba2 h^2 on interior rows, w2c =
+    // bc2 h^2 on the closure row; the right-biased rows take -w2, -w2c.
+    // Neither: s2 = null and s2_in = 0.
     const void *s2;
-    int64_t s2_base;
-    double w2;
+    int64_t s2_base, s2f;
+    int32_t s2u, s2v, s2d, s2_in;
+    double w2, w2c;
 };
 // One work item of the partitioned kernel: 64 * (4 / P) lines of one field of
 // one pass, P partitions per line (one wave each); of the sweep kernel (lines

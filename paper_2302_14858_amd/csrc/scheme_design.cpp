@@ -537,7 +537,16 @@ cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &ou
         return CFD_EINVAL;
     }
     BiasedQ s;
-    if (family == 'V') {
+    if (family == 'U') {
+        if (M < 1 || M > 4) {
+            err = "biased scheme: U_M needs 1 <= M <= 4";
+            return CFD_EUNSUPPORTED;
+        }
+        if (!ucd_scheme('U', M, s)) {
+            err = "biased scheme: singular Taylor system";
+            return CFD_ESINGULAR;
+        }
+    } else if (family == 'V') {
         if (M < 1 || M > 4) {
             err = "biased scheme: V_M needs 1 <= M <= 4";
             return CFD_EUNSUPPORTED;
@@ -602,7 +611,7 @@ cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &ou
                 return CFD_ESINGULAR;
             }
     } else {
-        err = "biased scheme: unknown family (V, X or W)";
+        err = "biased scheme: unknown family (U, V, X or W)";
         return CFD_EINVAL;
     }
     // the row the closure is built from: the scheme itself, or for W the row
@@ -619,7 +628,7 @@ cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &ou
     const int qo = p + 2 - (p % 2);
     // S = T / A as power series in z up to z^qo
     std::vector<q> T(qo + 1), Am(qo + 1), S(qo + 1);
-    for (int l = 0; l <= qo; ++l) T[l] = biased_residual(sx, l);
+    for (int l = 0; l <= qo; ++l) T[l] = biased_residual(sx, l) + (l == 2 ? sx.a2 : (q)0);
     for (int k = 0; k <= qo; ++k) Am[k] = (k == 0 ? (q)1 : (q)0) + s.alpha * qpow_int(-1, k) / qfact(k);
     for (int n = 0; n <= qo; ++n) {
         q acc = T[n];
@@ -671,6 +680,11 @@ cfd_status design_biased(char family, int M, double lambda, int bias, Scheme &ou
     if (family == 'W') {
         r.emb = M;
         r.ba2 = (double)s.a2;
+    }
+    if (family == 'U') {   // sampled f'' on every row; the closure row is the mirror's
+        r.hermite = 1;
+        r.ba2 = (double)s.a2;
+        r.bc2 = -(double)s.a2;
     }
     // the left-biased rows as a banded operator, for the generic fields
     r.lhs[kMaxNL - 1] = r.balpha;
@@ -733,7 +747,7 @@ cfd_status scheme_from_name(const std::string &name, Scheme &out, std::string &e
     const bool order_only = (variant == "E");
     // biased: "(1)V3-", "(1)X2+", "(1)X2" (both biases, upwind by a velocity field), "(1)X2s" (the
     // average of both biases)
-    if (variant.empty() && base.size() >= 5 && base.compare(0, 3, "(1)") == 0 && (base[3] == 'V' || base[3] == 'X' || base[3] == 'W') &&
+    if (variant.empty() && base.size() >= 5 && base.compare(0, 3, "(1)") == 0 && (base[3] == 'U' || base[3] == 'V' || base[3] == 'X' || base[3] == 'W') &&
         base[4] >= '1' && base[4] <= '9') {
         const std::string tail = base.substr(5);
         int bias;

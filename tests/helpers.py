@@ -25,7 +25,7 @@ def op_fields(wl, ops):
 def biased_name(name):
     """(base name, bias) for a biased scheme name ("(1)X2-" -> ("(1)X2", -1); "(1)X2" -> upwind, 0;
     "(1)X2s" -> symmetrised, 2), else None."""
-    if len(name) >= 5 and name.startswith("(1)") and name[3] in "VXW" and name[4].isdigit():
+    if len(name) >= 5 and name.startswith("(1)") and name[3] in "UVXW" and name[4].isdigit():
         base, tail = name[:5], name[5:]
         return base, {"-": -1, "+": 1, "": 0, "s": 2}[tail]
     return None
@@ -54,7 +54,7 @@ def make_plan(wl, ops, dtype=0):
         if name not in schemes:
             schemes[name] = scheme_for(name)
         pops.append((schemes[name], op[1], op[2] if len(op) > 2 else -1, op[3] if len(op) > 3 else -1,
-                     op[4] if len(op) > 4 else -1))
+                     op[4] if len(op) > 4 else -1, op[5] if len(op) > 5 else -1))
     return P.Plan(block_dicts(wl), wl.nfields, pops, dtype=dtype)
 
 
@@ -81,12 +81,17 @@ def oracle_block_op(wl, b, op, f, out=None):
     if bn is None:
         return OL.apply_block(OS.named(op[0]), wl.field_view(b, f), blk.ng, blk.h[d], d, periodic=per, out=out)
     base, bias = bn
+    ng = blk.ng
+    interior = (slice(ng, ng + blk.n[2]), slice(ng, ng + blk.n[1]), slice(ng, ng + blk.n[0]))
+    # U schemes: the sampled f'' is the field op[5] (interior)
+    f2 = wl.field_view(b, op[5])[interior] if len(op) > 5 and op[5] >= 0 else None
     if bias == 0:
-        ng = blk.ng
-        c = wl.field_view(b, op[3])[ng:ng + blk.n[2], ng:ng + blk.n[1], ng:ng + blk.n[0]]
-        r = OB.upwind_block(base, wl.field_view(b, f), c, ng, blk.h[d], d, periodic=per)
+        c = wl.field_view(b, op[3])[interior]
+        r = OB.upwind_block(base, wl.field_view(b, f), c, ng, blk.h[d], d, periodic=per, f2=f2)
     elif bias == 2:
-        r = OB.symmetrised_block(base, wl.field_view(b, f), blk.ng, blk.h[d], d, periodic=per)
+        r = OB.symmetrised_block(base, wl.field_view(b, f), blk.ng, blk.h[d], d, periodic=per, f2=f2)
+    elif f2 is not None:
+        r = OB.apply_block_hermite(base, bias, wl.field_view(b, f), f2, blk.ng, blk.h[d], d, periodic=per)
     else:
         r = OB.apply_block(base, bias, wl.field_view(b, f), blk.ng, blk.h[d], d, periodic=per)
     if out is not None:

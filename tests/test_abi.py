@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert P.cfd_abi_version() == 2
+    assert P.cfd_abi_version() == 3
 
 
 NAMES = ["(1)P1_1", "(2)P1_1", "(1)P1_2", "(2)P1_2", "(1)P1_3", "(2)P1_3", "(1)Q1_3[1]", "(2)Q1_3[1]",
@@ -183,7 +183,8 @@ def test_debug_alloc_hook_is_harmless_without_device():
     P.cfd_debug_fail_alloc(-1)
 
 
-BIASED = ["(1)V1", "(1)V2", "(1)V3", "(1)V4", "(1)X1", "(1)X2", "(1)X3", "(1)W1", "(1)W2", "(1)W3"]
+BIASED = ["(1)V1", "(1)V2", "(1)V3", "(1)V4", "(1)X1", "(1)X2", "(1)X3", "(1)W1", "(1)W2", "(1)W3",
+          "(1)U1", "(1)U2", "(1)U3"]
 
 
 @pytest.mark.parametrize("name", BIASED)
@@ -208,6 +209,8 @@ def test_biased_registry_matches_oracle(name, suffix, bias):
     e = sch.get_embedded()
     if name[3] == "W":
         assert e["M"] == int(name[4:]) and e["alpha2"] == float(s.rhs[1].get(0))
+    elif name[3] == "U":
+        assert e["M"] == 0 and e["alpha2"] == float(s.rhs[1].get(0)) == -float(c.rhs[1].get(0))
     else:
         assert e == {"alpha2": 0.0, "M": 0}
 
@@ -215,7 +218,7 @@ def test_biased_registry_matches_oracle(name, suffix, bias):
 def test_biased_design_ranges_and_lambda():
     from oracle import biased as OB
     from fractions import Fraction
-    for fam, M in (("V", 0), ("V", 5), ("X", 0), ("X", 4), ("W", 0), ("W", 4)):
+    for fam, M in (("V", 0), ("V", 5), ("X", 0), ("X", 4), ("W", 0), ("W", 4), ("U", 0), ("U", 4), ("U", 5)):
         with pytest.raises(P.CfdError) as e:
             P.Scheme.design_biased(fam, M)
         assert e.value.status == _lib.CFD_EUNSUPPORTED

@@ -231,3 +231,44 @@ def test_w_scheme_in_a_mixed_plan_and_graph(cuda):
         plan.set_iteration(1, 5, 1, 1)
     assert e.value.status == _lib.CFD_EUNSUPPORTED
 
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("M", [1, 2, 3])
+def test_u_schemes_with_sampled_second_derivative(cuda, M, dtype):
+    """U_M (Tab. ucd_slow, closure of Tab. ucd_slow_closure) reading f'' from another field of the
+    block on every row, the closure row included: both biases, the upwind pair and the symmetrised
+    mean along x, y, z on closure blocks (lengths 7..48 and 80, both kernels) and a periodic box.  The
+    f'' field is independent data, so every term of the rows is exercised."""
+    from oracle import biased as OB
+    name = f"(1)U{M}"
+    ng = OB.required_ghosts(name)
+    for wl in (synth.batch64(nblocks=5, nfields=3, sizes=(7, 16, 23, 48), ng=ng, seed=51 + M),
+               synth.periodic_box(n=(64, 5, 9), nfields=3, seed=54 + M),
+               synth.batch64(nblocks=2, nfields=3, sizes=(80, 12), ng=ng, seed=57 + M)):
+        ops = []
+        for d in range(3):
+            ops += [(name + "-", d, 0, -1, -1, 2), (name + "+", d, 1, -1, -1, 2), (name, d, 0, 1, -1, 2),
+                    (name + "s", d, 2, -1, -1, 0)]
+        plan = H.make_plan(wl, ops, dtype=dtype)
+        err = H.full_parity(plan, wl, ops, dtype)
+        assert err <= H.tol_for(dtype), (wl.name, err)
+
+
+def test_u_scheme_validation(cuda):
+    """A U operator needs a single field and the field of its sampled f''; other schemes refuse an
+    aux_field; the hybrid iteration is refused for plans holding U operators."""
+    import paper_2302_14858_amd as P
+    from paper_2302_14858_amd import _lib
+    wl = synth.lattice(n=(16, 16, 16), lat=(2, 1, 1), ng=4, nfields=2)
+    blocks = H.block_dicts(wl)
+    u = P.Scheme.named("(1)U2-")
+    for ops in ([(u, 0)], [(u, 0, 0)], [(u, 0, 0, -1, -1, 2)], [(u, 0, -1, -1, -1, 1)],
+                [(P.Scheme.named("(1)X2-"), 0, 0, -1, -1, 1)]):
+        with pytest.raises(P.CfdError) as e:
+            P.Plan(blocks, 2, ops)
+        assert e.value.status == _lib.CFD_EINVAL
+    plan = P.Plan(blocks, 2, [(u, 0, 0, -1, -1, 1)])
+    with pytest.raises(P.CfdError) as e:
+        plan.set_iteration(1, 2, 1, 1)
+    assert e.value.status == _lib.CFD_EUNSUPPORTED
