@@ -71,11 +71,12 @@ int main() {
         EXPECT(design_centred(1, 6, 1, 3, -1.0, 4, 1, s, err) == CFD_EINVAL);
     }
     // biased generator
-    for (char fam : {'V', 'X'})
+    for (char fam : {'U', 'V', 'X', 'W'})
         for (int M = 0; M <= 6; ++M)
             for (int bias = -2; bias <= 3; ++bias) {
                 Scheme s;
                 cfd_status st = design_biased(fam, M, 0.0, bias, s, err);
+                // U_4 designs but its closure is wider than the compiled half-width
                 const bool ok_range = (fam == 'V') ? (M >= 1 && M <= 4) : (M >= 1 && M <= 3);
                 if (bias < -1 || bias > 2) EXPECT(st == CFD_EINVAL);
                 else if (ok_range) EXPECT(st == CFD_OK);
@@ -85,6 +86,9 @@ int main() {
         Scheme s;
         EXPECT(design_biased('Q', 2, 0.0, 0, s, err) == CFD_EINVAL);
         EXPECT(design_biased('X', 2, 0.5, -1, s, err) == CFD_OK);
+        EXPECT(design_biased('W', 2, 0.5, 1, s, err) == CFD_OK && s.emb == 2 && s.ba2 != 0.0);
+        EXPECT(design_biased('U', 3, 0.0, 0, s, err) == CFD_OK && s.hermite == 1 && s.bc2 == -s.ba2);
+        EXPECT(required_ghosts(s, 0) == 5 && required_ghosts(s, 1) == 0);
     }
     // dissipation
     for (int r = 0; r <= 6; ++r) {
