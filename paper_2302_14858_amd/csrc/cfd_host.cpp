@@ -1808,12 +1808,21 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
         }
         p->wave_fused = true;
     }
-    // symmetrised mixed derivatives: for each order (inner dj, outer di) a
-    // first-stage pass D_dj f -> scratch S over the block extended by its ghost
-    // layers along di (none if di is periodic), and a second-stage pass
-    // D_di S -> scratch T over the interior; the combine averages the two T.
+    // symmetrised mixed derivatives: the order with inner direction dj and
+    // outer di needs D_dj f on the block extended by its ghost layers along di
+    // (none if di is periodic).  One first-stage pass D_dj f -> scratch S_dj per
+    // (block, fields, dj, scheme) covers every operator of the plan that needs
+    // it: S_dj is extended along each outer direction those operators pair with
+    // dj (the lines along dj through both extensions also run, unused).  For
+    // each order a second-stage pass D_di S_dj -> scratch T over the interior;
+    // the combine averages the two T.
     {
         int64_t scr = 0;
+        struct Inner {
+            int ext = 0;         // bit k: extended along k
+            int64_t S0 = 0;      // scratch offset
+            int64_t e[3] = {0, 0, 0};
+        };
         for (size_t b = 0; b < p->blocks.size(); ++b) {
             const cfd_block &bl = p->blocks[b];
             const int64_t ng = bl.ng;
@@ -1822,82 +1831,133 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
             const int64_t s_in[3] = {1, PX, PX * PY};
             const int64_t s_int[3] = {1, n[0], n[0] * n[1]};
             const int64_t npts = n[0] * n[1] * n[2];
+            int64_t g[3];
+            for (int k = 0; k < 3; ++k) g[k] = bl.boundary[k] == CFD_BOUNDARY_PERIODIC ? 0 : ng;
+            // (scheme, first field, fields, inner direction) -> its scratch
+            std::map<std::tuple<const void *, int, int, int>, Inner> inner;
+            auto key_of = [&](const cfd_op &op, int dj) {
+                const int nf = op.field < 0 ? p->nfields : 1, f0 = op.field < 0 ? 0 : op.field;
+                return std::make_tuple((const void *)op.scheme, f0, nf, dj);
+            };
+            for (size_t o = 0; o < p->ops.size(); ++o) {
+                const cfd_op &op = p->ops[o];
+                if (op.dir2 < 0) continue;
+                inner[key_of(op, op.dir2)].ext |= 1 << op.dir;
+                inner[key_of(op, op.dir)].ext |= 1 << op.dir2;
+            }
+            for (auto &kv : inner) {
+                const int f0 = std::get<1>(kv.first), nf = std::get<2>(kv.first), dj = std::get<3>(kv.first);
+                Inner &in = kv.second;
+                int64_t off = 0;
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t gk = (in.ext >> k & 1) ? g[k] : 0;
+                    in.e[k] = n[k] + 2 * gk;
+                    off += gk * s_in[k];
+                }
+                const int64_t ss[3] = {1, in.e[0], in.e[0] * in.e[1]};
+                in.S0 = scr;
+                scr += nf * in.e[0] * in.e[1] * in.e[2];
+                int o = -1;   // an operator of this group: scheme and output bookkeeping
+                for (size_t q = 0; q < p->ops.size() && o < 0; ++q)
+                    if (p->ops[q].dir2 >= 0 && (key_of(p->ops[q], p->ops[q].dir2) == kv.first ||
+                                                key_of(p->ops[q], p->ops[q].dir) == kv.first))
+                        o = (int)q;
+                const Scheme &s = p->schemes[o];
+                const int u = (dj == 0) ? 1 : 0, v = (dj == 2) ? 1 : 2;
+                const bool per = bl.boundary[dj] == CFD_BOUNDARY_PERIODIC;
+                PassHost ps;
+                ps.block = (int)b;
+                ps.dir = dj;
+                ps.field0 = f0;
+                ps.nfield = nf;
+                ps.N = (int)n[dj];
+                ps.ng = bl.ng;
+                ps.periodic = per;
+                ps.nl = s.nl;
+                ps.nops = 1;
+                ps.op[0] = ps.sch[0] = o;
+                ps.par = 1;
+                ps.mi = s.m;
+                ps.hw = std::max(s.m, per ? 0 : s.mc);
+                ps.iomode = 1;
+                ps.custom = true;
+                PassDesc &q = ps.geom;
+                std::memset(&q, 0, sizeof q);
+                q.in_base = p->in_off[b] + ng * (s_in[0] + s_in[1] + s_in[2]) - off;
+                q.in_fstride = PX * PY * PZ;
+                q.su = (int32_t)s_in[u];
+                q.sv = (int32_t)s_in[v];
+                q.sd = (int32_t)s_in[dj];
+                q.out_base[0] = in.S0;
+                q.out_fstride = in.e[0] * in.e[1] * in.e[2];
+                q.osu = (int32_t)ss[u];
+                q.osv = (int32_t)ss[v];
+                q.osd = (int32_t)ss[dj];
+                q.nu = (int32_t)in.e[u];
+                q.nlines = (int32_t)(in.e[u] * in.e[v]);
+                q.field0 = f0;
+                q.N = ps.N;
+                q.ng = ps.ng;
+                q.periodic = per;
+                q.nfield_pass = nf;
+                p->passes.push_back(ps);
+            }
             for (size_t o = 0; o < p->ops.size(); ++o) {
                 const cfd_op &op = p->ops[o];
                 if (op.dir2 < 0) continue;
                 const Scheme &s = p->schemes[o];
-                const int nf = op.field < 0 ? p->nfields : 1, f0 = op.field < 0 ? 0 : op.field;
+                const int nf = op.field < 0 ? p->nfields : 1;
                 int64_t t_off[2];
                 for (int ord = 0; ord < 2; ++ord) {
                     const int dj = ord == 0 ? op.dir2 : op.dir;   // inner derivative
                     const int di = ord == 0 ? op.dir : op.dir2;   // outer derivative
-                    const int gi = bl.boundary[di] == CFD_BOUNDARY_PERIODIC ? 0 : bl.ng;
-                    int64_t e[3] = {n[0], n[1], n[2]};
-                    e[di] += 2 * gi;
-                    const int64_t ss[3] = {1, e[0], e[0] * e[1]};
-                    const int64_t ssize = e[0] * e[1] * e[2];
-                    const int64_t S0 = scr;
-                    scr += nf * ssize;
+                    const Inner &in = inner.at(key_of(op, dj));
+                    const int64_t ss[3] = {1, in.e[0], in.e[0] * in.e[1]};
                     const int64_t T0 = scr;
                     scr += nf * npts;
                     t_off[ord] = T0;
-                    for (int st = 1; st <= 2; ++st) {
-                        const int ld = (st == 1) ? dj : di;                 // line direction
-                        const int u = (ld == 0) ? 1 : 0, v = (ld == 2) ? 1 : 2;
-                        const bool per = bl.boundary[ld] == CFD_BOUNDARY_PERIODIC;
-                        PassHost ps;
-                        ps.block = (int)b;
-                        ps.dir = ld;
-                        ps.field0 = f0;
-                        ps.nfield = nf;
-                        ps.N = (int)n[ld];
-                        ps.ng = (st == 1) ? bl.ng : gi;
-                        ps.periodic = per;
-                        ps.nl = s.nl;
-                        ps.nops = 1;
-                        ps.op[0] = ps.sch[0] = (int)o;
-                        ps.par = 1;
-                        ps.mi = s.m;
-                        ps.hw = std::max(s.m, per ? 0 : s.mc);
-                        ps.iomode = st;
-                        ps.custom = true;
-                        PassDesc &q = ps.geom;
-                        std::memset(&q, 0, sizeof q);
-                        if (st == 1) {   // input block, lines along dj; u, v over di extended and the third
-                            q.in_base = p->in_off[b] + ng * (s_in[0] + s_in[1] + s_in[2]) - gi * s_in[di];
-                            q.in_fstride = PX * PY * PZ;
-                            q.su = (int32_t)s_in[u];
-                            q.sv = (int32_t)s_in[v];
-                            q.sd = (int32_t)s_in[ld];
-                            q.out_base[0] = S0;
-                            q.out_fstride = ssize;
-                            q.osu = (int32_t)ss[u];
-                            q.osv = (int32_t)ss[v];
-                            q.osd = (int32_t)ss[ld];
-                            q.nu = (int32_t)e[u];
-                            q.nlines = (int32_t)(e[u] * e[v]);
-                            q.field0 = f0;
-                        } else {         // S, lines along di over the interior; gi ghost layers along di
-                            q.in_base = S0 + gi * ss[di];
-                            q.in_fstride = ssize;
-                            q.su = (int32_t)ss[u];
-                            q.sv = (int32_t)ss[v];
-                            q.sd = (int32_t)ss[ld];
-                            q.out_base[0] = T0;
-                            q.out_fstride = npts;
-                            q.osu = (int32_t)s_int[u];
-                            q.osv = (int32_t)s_int[v];
-                            q.osd = (int32_t)s_int[ld];
-                            q.nu = (int32_t)n[u];
-                            q.nlines = (int32_t)(n[u] * n[v]);
-                            q.field0 = 0;
-                        }
-                        q.N = ps.N;
-                        q.ng = ps.ng;
-                        q.periodic = per;
-                        q.nfield_pass = nf;
-                        p->passes.push_back(ps);
-                    }
+                    // lines along di over the interior of S_dj; its g[di] ghost layers along di
+                    int64_t base = in.S0;
+                    for (int k = 0; k < 3; ++k)
+                        if (in.ext >> k & 1) base += g[k] * ss[k];
+                    const int u = (di == 0) ? 1 : 0, v = (di == 2) ? 1 : 2;
+                    const bool per = bl.boundary[di] == CFD_BOUNDARY_PERIODIC;
+                    PassHost ps;
+                    ps.block = (int)b;
+                    ps.dir = di;
+                    ps.field0 = op.field < 0 ? 0 : op.field;
+                    ps.nfield = nf;
+                    ps.N = (int)n[di];
+                    ps.ng = (int)g[di];
+                    ps.periodic = per;
+                    ps.nl = s.nl;
+                    ps.nops = 1;
+                    ps.op[0] = ps.sch[0] = (int)o;
+                    ps.par = 1;
+                    ps.mi = s.m;
+                    ps.hw = std::max(s.m, per ? 0 : s.mc);
+                    ps.iomode = 2;
+                    ps.custom = true;
+                    PassDesc &q = ps.geom;
+                    std::memset(&q, 0, sizeof q);
+                    q.in_base = base;
+                    q.in_fstride = in.e[0] * in.e[1] * in.e[2];
+                    q.su = (int32_t)ss[u];
+                    q.sv = (int32_t)ss[v];
+                    q.sd = (int32_t)ss[di];
+                    q.out_base[0] = T0;
+                    q.out_fstride = npts;
+                    q.osu = (int32_t)s_int[u];
+                    q.osv = (int32_t)s_int[v];
+                    q.osd = (int32_t)s_int[di];
+                    q.nu = (int32_t)n[u];
+                    q.nlines = (int32_t)(n[u] * n[v]);
+                    q.field0 = 0;
+                    q.N = ps.N;
+                    q.ng = ps.ng;
+                    q.periodic = per;
+                    q.nfield_pass = nf;
+                    p->passes.push_back(ps);
                 }
                 const int64_t oo = p->out_off[b] + p->op_slot[o] * npts;
                 p->msegs.insert(p->msegs.end(), {oo, t_off[0], t_off[1], nf * npts});
