@@ -113,6 +113,38 @@ __device__ __forceinline__ void load_coef(BCoef<T, HB> &q, const T *rec) {
     for (int m = -HB; m <= HB + 1; ++m) q.c[m + HB] = rec[12 + kBiasHalf + m];
 }
 
+// Walk of a thread over the elements e = threadIdx.x, + 256, ... of a
+// [lines][cols] tile (cols <= 256) in row-major order, with the (u, v) position of its line
+// kept up to date, so the fill and drain loops divide only once.
+struct TileWalk {
+    int l, j, dq, dr, cols;   // row (line of the workgroup), column, row / column step
+    int ln, uu, vv;           // line index in the pass, its u and v
+    __device__ __forceinline__ TileWalk(int t, int cols_, int line0, int nu) : cols(cols_) {
+        l = t / cols;
+        j = t - l * cols;
+        dq = 256 / cols;
+        dr = 256 - dq * cols;
+        ln = line0 + l;
+        uu = ln % nu;
+        vv = ln / nu;
+    }
+    __device__ __forceinline__ void next(int nu) {
+        int dl = dq;
+        j += dr;
+        if (j >= cols) {
+            j -= cols;
+            ++dl;
+        }
+        l += dl;
+        ln += dl;
+        uu += dl;
+        while (uu >= nu) {
+            uu -= nu;
+            ++vv;
+        }
+    }
+};
+
 // LDS: exchange area [4 waves][2][64], then (x lines) the tile of the
 // workgroup's lines, [4/P groups x 64 lines][pitch].
 // Iterated closures (Eq. iter_left_X and its mirror; ev given): every row of
@@ -173,15 +205,10 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
         const int tp = Tn | 1;
         const int nl = 64 * G;
         // consecutive threads take consecutive nodes of the workgroup's rows
-        for (int e = threadIdx.x; e < nl * Tn; e += 256) {
-            const int l = e / Tn, j = e - l * Tn;
-            const int ln = item.line0 + l;
+        for (TileWalk w(threadIdx.x, Tn, item.line0, ps.nu); w.l < nl; w.next(ps.nu)) {
             T val = 0;
-            if (ln < ps.nlines) {
-                const int uu = ln % ps.nu, vv = ln / ps.nu;
-                val = in[fbase + (int64_t)uu * ps.su + (int64_t)vv * ps.sv + (t0 + j)];
-            }
-            tile[l * tp + j] = val;
+            if (w.ln < ps.nlines) val = in[fbase + (int64_t)w.uu * ps.su + (int64_t)w.vv * ps.sv + (t0 + w.j)];
+            tile[w.l * tp + w.j] = val;
         }
         __syncthreads();
         const T *row = tile + (64 * g + lane) * tp;
@@ -198,15 +225,10 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
         }
         __syncthreads();   // the tile is reused for the velocity and the output
         if (mode == 0) {
-            for (int e = threadIdx.x; e < nl * N; e += 256) {
-                const int l = e / N, j = e - l * N;
-                const int ln = item.line0 + l;
+            for (TileWalk w(threadIdx.x, N, item.line0, ps.nu); w.l < nl; w.next(ps.nu)) {
                 T val = 0;
-                if (ln < ps.nlines) {
-                    const int uu = ln % ps.nu, vv = ln / ps.nu;
-                    val = in[ps.vel_base + (int64_t)uu * ps.su + (int64_t)vv * ps.sv + j];
-                }
-                tile[l * vp + j] = val;
+                if (w.ln < ps.nlines) val = in[ps.vel_base + (int64_t)w.uu * ps.su + (int64_t)w.vv * ps.sv + w.j];
+                tile[w.l * vp + w.j] = val;
             }
         }
     } else {
@@ -332,14 +354,8 @@ __global__ __launch_bounds__(256) void k_biased_part(const BiasItem *__restrict_
     if (XDIR) {
         __syncthreads();
         const int nl = 64 * G;
-        for (int e = threadIdx.x; e < nl * N; e += 256) {
-            const int l = e / N, j = e - l * N;
-            const int ln = item.line0 + l;
-            if (ln < ps.nlines) {
-                const int uu = ln % ps.nu, vv = ln / ps.nu;
-                out[obase + (int64_t)uu * ps.osu + (int64_t)vv * ps.osv + j] = tile[l * vp + j];
-            }
-        }
+        for (TileWalk w(threadIdx.x, N, item.line0, ps.nu); w.l < nl; w.next(ps.nu))
+            if (w.ln < ps.nlines) out[obase + (int64_t)w.uu * ps.osu + (int64_t)w.vv * ps.osv + w.j] = tile[w.l * vp + w.j];
     }
 }
 
