@@ -266,8 +266,11 @@ typedef struct {
  * or periodic per direction).  On a closed direction i the inner derivative
  * is taken on the lines through the block extended by its ng ghost layers
  * along i (edge ghosts are read), so the outer one has its ghost values.  The
- * plan computes both compositions into a scratch buffer it owns (about four
- * times the operator's output) and averages them.
+ * plan computes the inner derivatives into a scratch buffer it owns (per
+ * block-field and inner direction, the block extended along the outer
+ * directions the plan pairs it with; the operators of a plan share them);
+ * the first order's outer derivative stores half its value into the output
+ * and the second order's adds half of its own.
  * aux_field: for a U_M scheme ("(1)UM-" etc., Tab. ucd_slow), which samples
  * f'' as data, the field holding the second derivative of `field` along dir
  * (read on the interior nodes; field must be a single index); -1 for every

@@ -331,30 +331,5 @@ hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *sta
                            shapes, unitpre, nblocks, nunits, a, b, bx, by, bz);
     return hipGetLastError();
 }
-// Second half of the symmetrised mixed derivative: the two orders of the
-// composition, computed into the plan's scratch, averaged into the output.
-// Segment g (blockIdx.y): segs[4g .. 4g+3] = output offset, offsets of the
-// two orders in the scratch, element count.
-template <typename T>
-__global__ __launch_bounds__(256) void k_mixed_combine(const int64_t *__restrict__ segs, const T *__restrict__ scr,
-                                                       T *__restrict__ out) {
-    const int64_t *sg = segs + 4 * (int64_t)blockIdx.y;
-    const int64_t o = sg[0], ta = sg[1], tb = sg[2], n = sg[3];
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
-        out[o + e] = (T)0.5 * (scr[ta + e] + scr[tb + e]);
-}
-
-hipError_t launch_mixed_combine(int f32, int nseg, const int64_t *segs, int64_t max_n, const void *scr, void *out,
-                                hipStream_t st) {
-    if (nseg <= 0) return hipSuccess;
-    const int gx = (int)std::min<int64_t>((max_n + 255) / 256, 4096);
-    if (f32)
-        hipLaunchKernelGGL(k_mixed_combine<float>, dim3(gx, nseg), dim3(256), 0, st, segs, (const float *)scr,
-                           (float *)out);
-    else
-        hipLaunchKernelGGL(k_mixed_combine<double>, dim3(gx, nseg), dim3(256), 0, st, segs, (const double *)scr,
-                           (double *)out);
-    return hipGetLastError();
-}
 
 }  // namespace cfd

@@ -96,6 +96,7 @@ struct Group {
     int grid_persist;
     int qoff_index = -1;   // offset of this group's 9 queue bounds in d_qoff (XCD-aware mode)
     int iomode = 0;        // buffers: 0 input -> output, 1 input -> scratch, 2 scratch -> scratch,
+                           // 5 scratch -> output, 6 the same accumulating;
                            // 3 and 4: the two launches of the fused wave stage
     int wg = 4;            // wavefronts per workgroup of the kernel class
 };
@@ -154,11 +155,11 @@ struct cfd_plan {
     std::vector<std::array<int64_t, 4>> bpinfo;   // block, op, ev_base, entries
     int64_t bev_entries = 0, bev_max = 0;
     DevBuf d_bev, d_bends, d_bgrecs;
-    // symmetrised mixed derivatives: scratch (elements), combine segments
-    // (output offset, first-order result, second-order result, count)
-    int64_t mscr_elems = 0, mseg_max = 0;
-    std::vector<int64_t> msegs;
-    DevBuf d_mscr, d_msegs;
+    // scratch of the mixed derivatives' first stage and of the W operators'
+    // embedded second derivative (elements)
+    int64_t mscr_elems = 0;
+    DevBuf d_mscr;
+    int64_t n_mixed = 0;                  // (block, mixed-derivative operator) pairs
     // W operators: scheme index of the embedded (2)P1_M per op (-1: none), and
     // per (block, op) the scratch offset of its first field's h^-2 (2)P1_M f,
     // written by line passes that run before the biased launches
@@ -231,7 +232,6 @@ struct cfd_plan {
         d_bitems.release();
         d_bcoef.release();
         d_mscr.release();
-        d_msegs.release();
         d_count.release();
         d_epi.release();
         d_hpairs.release();
@@ -430,7 +430,11 @@ size_t elem_size(cfd_dtype t) { return t == CFD_F64 ? 8 : 4; }   // F32 and MIXE
 constexpr int kXCDq = 8;   // queues of the XCD-aware schedule (one per XCD)
 
 // Passes that only the fused wave stage runs (iomode 3 and 4).
-inline bool fused_pass(const PassHost &ps) { return ps.iomode >= 3; }
+inline bool fused_iomode(int m) { return m == 3 || m == 4; }
+inline bool fused_pass(const PassHost &ps) { return fused_iomode(ps.iomode); }
+// Launch stage of a group of the plain apply: 0 reads the input, 1 reads what
+// stage 0 left in the scratch, 2 accumulates into what stage 1 stored.
+inline int apply_stage(int m) { return (m == 0 || m == 1) ? 0 : (m == 6 ? 2 : 1); }
 
 // The wave system's operators in the order the stage kernels expect:
 // D_x Pi, D_y Pi, D_z Pi, D_x psi_x, D_y psi_y, D_z psi_z (first degree).
@@ -457,7 +461,7 @@ std::vector<PassDesc> pass_descs(const cfd_plan *p, const std::vector<std::array
         for (int o = 0; o < ps.nops; ++o) {
             ob[o] = p->out_off[ps.block] + p->op_slot[ps.op[o]] * npts;
             tab[o] = pass_tab[i][o];
-            hinv[o] = 1.0 / std::pow(b.h[ps.dir], scale_power(p->schemes[ps.sch[o]]));
+            hinv[o] = ps.hscale / std::pow(b.h[ps.dir], scale_power(p->schemes[ps.sch[o]]));
         }
         if (ps.custom) {
             pd[i] = ps.geom;
@@ -843,7 +847,7 @@ cfd_status build_groups(cfd_plan *p) {
     if (p->xcd) {
         std::vector<int64_t> bf_cost(nbf, 0);
         for (size_t gi = 0; gi < groups.size(); ++gi) {
-            if (groups[gi].iomode >= 3) continue;   // the fused stage's copies follow the same queues
+            if (fused_iomode(groups[gi].iomode)) continue;   // the fused stage's copies follow the same queues
             for (size_t e = 0; e < gitems[gi].size(); ++e) bf_cost[gbf[gi][e]] += gcost[gi][e];
         }
         std::vector<int64_t> load(kXCDq, 0);
@@ -1228,6 +1232,7 @@ cfd_status launch_group(cfd_plan *p, const Group &g, const void *in, void *out, 
                         const RkArgs *rk = nullptr) {
     const int grid = p->persistent ? g.grid_persist : (int)g.nitems;
     if (g.iomode == 1) out = p->d_mscr.p;
+    if (g.iomode == 5 || g.iomode == 6) in = p->d_mscr.p;
     if (g.iomode == 2) {
         in = p->d_mscr.p;
         out = p->d_mscr.p;
@@ -1352,15 +1357,16 @@ cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
         if (r != CFD_OK) return r;
     }
     // stage 0: every group reading the input; stage 1: the second stage of the
-    // mixed derivatives (reads what stage 0 left in the scratch)
-    for (int stage = 0; stage < 2; ++stage) {
+    // mixed derivatives (reads what stage 0 left in the scratch; the first
+    // order stores into the output); stage 2: the second order adds to it
+    for (int stage = 0; stage < 3; ++stage) {
         if (stage == 1 && biased_late) {
             cfd_status r = biased();
             if (r != CFD_OK) return r;
         }
         std::vector<const Group *> act;
         for (const Group &g : p->groups)
-            if (g.nitems > 0 && g.iomode < 3 && (g.iomode == 2) == (stage == 1)) act.push_back(&g);
+            if (g.nitems > 0 && !fused_iomode(g.iomode) && apply_stage(g.iomode) == stage) act.push_back(&g);
         if (p->concurrent && act.size() > 1 && p->aux.size() + 1 >= act.size() && p->ev.size() >= act.size()) {
             // fork: every group after the first on its own stream, all ordered after
             // the caller's earlier work; join: the caller's stream waits for all
@@ -1380,11 +1386,6 @@ cfd_status enqueue(cfd_plan *p, const void *in, void *out, hipStream_t st) {
                 if (r != CFD_OK) return r;
             }
         }
-    }
-    if (!p->msegs.empty()) {
-        hipError_t e = launch_mixed_combine(p->dtype != CFD_F64, (int)(p->msegs.size() / 4),
-                                            (const int64_t *)p->d_msegs.p, p->mseg_max, p->d_mscr.p, out, st);
-        if (e != hipSuccess) return hip_fail(e, "launching the mixed-derivative combine");
     }
     return CFD_OK;
 }
@@ -1907,15 +1908,12 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
                 if (op.dir2 < 0) continue;
                 const Scheme &s = p->schemes[o];
                 const int nf = op.field < 0 ? p->nfields : 1;
-                int64_t t_off[2];
+                const int64_t oo = p->out_off[b] + p->op_slot[o] * npts;
                 for (int ord = 0; ord < 2; ++ord) {
                     const int dj = ord == 0 ? op.dir2 : op.dir;   // inner derivative
                     const int di = ord == 0 ? op.dir : op.dir2;   // outer derivative
                     const Inner &in = inner.at(key_of(op, dj));
                     const int64_t ss[3] = {1, in.e[0], in.e[0] * in.e[1]};
-                    const int64_t T0 = scr;
-                    scr += nf * npts;
-                    t_off[ord] = T0;
                     // lines along di over the interior of S_dj; its g[di] ghost layers along di
                     int64_t base = in.S0;
                     for (int k = 0; k < 3; ++k)
@@ -1936,7 +1934,10 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
                     ps.par = 1;
                     ps.mi = s.m;
                     ps.hw = std::max(s.m, per ? 0 : s.mc);
-                    ps.iomode = 2;
+                    // half of each order: the first stores it, the second adds its own
+                    ps.iomode = ord == 0 ? 5 : 6;
+                    ps.ext = ord == 0 ? 0 : 3;
+                    ps.hscale = 0.5;
                     ps.custom = true;
                     PassDesc &q = ps.geom;
                     std::memset(&q, 0, sizeof q);
@@ -1945,7 +1946,7 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
                     q.su = (int32_t)ss[u];
                     q.sv = (int32_t)ss[v];
                     q.sd = (int32_t)ss[di];
-                    q.out_base[0] = T0;
+                    q.out_base[0] = oo;
                     q.out_fstride = npts;
                     q.osu = (int32_t)s_int[u];
                     q.osv = (int32_t)s_int[v];
@@ -1959,9 +1960,7 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
                     q.nfield_pass = nf;
                     p->passes.push_back(ps);
                 }
-                const int64_t oo = p->out_off[b] + p->op_slot[o] * npts;
-                p->msegs.insert(p->msegs.end(), {oo, t_off[0], t_off[1], nf * npts});
-                p->mseg_max = std::max(p->mseg_max, nf * npts);
+                ++p->n_mixed;
             }
         }
         // W operators: their embedded (2)P1_M along the operator's direction over
@@ -2030,8 +2029,6 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
             }
         }
         p->mscr_elems = scr;
-        if (p->msegs.size() / 4 > 65535)
-            return fail(CFD_EUNSUPPORTED, "cfd_plan_create: more than 65535 block x mixed-derivative pairs");
     }
     // the descriptor is valid; from here on the device is needed
     int ndev = 0;
@@ -2053,13 +2050,9 @@ cfd_status cfd_plan_create(const cfd_plan_desc *desc, cfd_plan **out) {
     cfd_status st = upload_layout(p.get());
     if (st == CFD_OK && p->mscr_elems > 0) {
         const size_t es = elem_size(p->dtype);
-        if (dmalloc(&p->d_mscr.p, (size_t)p->mscr_elems * es) != hipSuccess ||
-            dmalloc(&p->d_msegs.p, p->msegs.size() * sizeof(int64_t)) != hipSuccess) {
+        if (dmalloc(&p->d_mscr.p, (size_t)p->mscr_elems * es) != hipSuccess) {
             (void)hipGetLastError();
-            st = fail(CFD_ENOMEM, "cfd_plan_create: allocating the mixed-derivative scratch");
-        } else if (hipMemcpy(p->d_msegs.p, p->msegs.data(), p->msegs.size() * sizeof(int64_t),
-                             hipMemcpyHostToDevice) != hipSuccess) {
-            st = fail(CFD_EDEVICE, "cfd_plan_create: uploading the mixed-derivative segments");
+            st = fail(CFD_ENOMEM, "cfd_plan_create: allocating the plan scratch");
         }
     }
     if (st == CFD_OK && dmalloc(&p->d_count.p, sizeof(unsigned long long)) != hipSuccess) {
@@ -2096,13 +2089,13 @@ cfd_status cfd_plan_stats(const cfd_plan *p, int *launches, long long *items) {
     if (!p) return fail(CFD_EINVAL, "cfd_plan_stats: null plan");
     if (launches) {
         int n = 0;
-        for (const Group &g : p->groups) n += g.iomode < 3;
+        for (const Group &g : p->groups) n += !fused_iomode(g.iomode);
         *launches = n;
     }
     if (items) {
         long long n = 0;
         for (const Group &g : p->groups)
-            if (g.iomode < 3) n += g.nitems;
+            if (!fused_iomode(g.iomode)) n += g.nitems;
         *items = n;
     }
     return CFD_OK;
@@ -2345,7 +2338,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
                     p->concurrent = conc;
                     r = build(p);
                     int nplain = 0;
-                    for (const Group &g : p->groups) nplain += g.iomode < 3;
+                    for (const Group &g : p->groups) nplain += !fused_iomode(g.iomode);
                     if (r == CFD_OK && conc && nplain < 2) continue;   // same as sequential
                     float ms = 0;
                     if (r == CFD_OK) r = time_apply(ms);
@@ -2744,7 +2737,7 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
     if (iterations < 0) return fail(CFD_EINVAL, "cfd_plan_set_iteration: negative iteration count");
     if (p->dtype == CFD_MIXED_BF16)
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: not available on the dense mixed-precision path");
-    if (iterations > 0 && !p->msegs.empty())
+    if (iterations > 0 && p->n_mixed > 0)
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds mixed derivatives");
     if (iterations > 0 && !p->emb_off.empty())
         return fail(CFD_EUNSUPPORTED, "cfd_plan_set_iteration: the plan holds W operators (their embedded second "
@@ -2757,7 +2750,7 @@ cfd_status cfd_plan_set_iteration(cfd_plan *p, int iterations, int bx, int by, i
         p->release_biased_iteration();
         if (!p->base_schemes.empty()) p->schemes = p->base_schemes;
         p->base_schemes.clear();
-        for (PassHost &ps : p->passes) ps.ext = fused_pass(ps) ? 2 : 0;
+        for (PassHost &ps : p->passes) ps.ext = fused_pass(ps) ? 2 : (ps.iomode == 6 ? 3 : 0);
         p->iter_n = 0;
     };
     if (iterations == 0) {

@@ -252,18 +252,22 @@ struct PassHost {
     int op[2] = {0, 0};   // plan op indices (output order)
     int sch[2] = {0, 0};  // scheme indices
     int N = 0, ng = 0, periodic = 0, nl = 0, par = 0, mi = 0, hw = 0;
-    int ext = 0;          // kernel extension: 1 iterated closures (end-value terms), 2 stage epilogue
+    int ext = 0;          // kernel extension: 1 iterated closures (end-value terms), 2 stage epilogue,
+                          // 3 accumulate into the output
     int P = 0, L = 0, lcode = 0;
     int C = 1;            // x lines: column chunks the LDS tile is staged in (divides P)
     const LineClass *cls = nullptr;
     // Passes of the symmetrised mixed derivatives read or write the plan's
     // scratch buffer: iomode 0 input -> output, 1 input -> scratch (first
-    // stage), 2 scratch -> scratch (second stage, after the first).  Their
-    // strides and offsets are set explicitly (geom) instead of from the block.
+    // stage), 2 scratch -> scratch, 5 scratch -> output (second stage, after
+    // the first), 6 scratch -> output accumulating (third stage, ext 3).  Their
+    // strides and offsets are set explicitly (geom) instead of from the block,
+    // and hscale multiplies their h^-d.
     // Passes of the fused wave stage: iomode 3 (first launch) and 4 (second
     // launch, after the first), run only by that stage.
     int iomode = 0;
     bool custom = false;
+    double hscale = 1.0;
     PassDesc geom{};
 };
 
@@ -318,9 +322,6 @@ hipError_t launch_halo_table(int f32, void *data, const int64_t *off_dev, const 
 hipError_t launch_shared_avg(int f32, void *data, const int64_t *off_dev, const int *shapes_dev, const int *pairs_dev,
                              int npairs, int nslots, int ghosted, int d, int max_face, hipStream_t st);
 hipError_t launch_axpby(int f32, int64_t n, double a, const void *x, double b, void *y, hipStream_t st);
-// out[o + e] = (a[ta + e] + b[tb + e]) / 2 for each segment (o, ta, tb, n); a and b in scr
-hipError_t launch_mixed_combine(int f32, int nseg, const int64_t *segs, int64_t max_n, const void *scr, void *out,
-                                hipStream_t st);
 hipError_t launch_xpcy(int f32, int64_t n, const void *x, double c, const void *y, void *z, hipStream_t st);
 hipError_t launch_wave_stage(int f32, const void *u0, const void *src, void *stage, const void *acc_in, void *acc,
                              const void *d, const int64_t *in_off, const int64_t *out_off, const int *shapes,

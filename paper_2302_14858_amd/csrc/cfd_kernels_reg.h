@@ -14,7 +14,7 @@ struct LineClass {
     int nL;
     int Ls[8];
     const void *fn;
-    int ext;      // extension mode: 1 end-value terms of an iterated closure, 2 stage epilogue
+    int ext;      // extension mode: 1 end-value terms of an iterated closure, 2 stage epilogue, 3 accumulate
     int wg;       // wavefronts per workgroup: 4 (P = 1, 2, 4) or 8 (P = 8)
 };
 
@@ -30,6 +30,12 @@ struct LineClass {
 #define CFD_LC_RK(T, NL, NOPS, PAR, MI, HW, ...)                                                     \
     LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
               reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, 2, 4, __VA_ARGS__>), 2, 4}
+#define CFD_LC_ACC(T, NL, NOPS, PAR, MI, HW, ...)                                                    \
+    LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, 3, 4, __VA_ARGS__>), 3, 4}
+#define CFD_LC8_ACC(T, NL, NOPS, PAR, MI, HW, ...)                                                   \
+    LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
+              reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, 3, 8, __VA_ARGS__>), 3, 8}
 #define CFD_LC8_RK(T, NL, NOPS, PAR, MI, HW, ...)                                                    \
     LineClass{NL, NOPS, PAR, MI, HW, LSet<__VA_ARGS__>::n, {__VA_ARGS__},                              \
               reinterpret_cast<const void *>(&k_lines<T, NL, NOPS, PAR, MI, HW, 2, 8, __VA_ARGS__>), 2, 8}
@@ -73,7 +79,13 @@ struct LineClass {
     /* registers and is preferred for the lengths it has                       */ \
     CFD_LC_RK(T, 1, 1, 1, 3, 4, 8, 12, 16),                                       \
     CFD_LC_RK(T, 1, 1, 1, 3, 4, 8, 12, 16, 24, 32),                               \
-    CFD_LC8_RK(T, 1, 1, 1, 3, 4, 16, 24, 32)
+    CFD_LC8_RK(T, 1, 1, 1, 3, 4, 16, 24, 32),                                     \
+    /* accumulating first derivatives: the second order of the symmetrised     */ \
+    /* mixed derivatives (explicit, tri- and pentadiagonal; long tri lines)     */ \
+    CFD_LC_ACC(T, 0, 1, 1, 5, 5, 8, 12, 16, 24, 32),                              \
+    CFD_LC_ACC(T, 1, 1, 1, 5, 5, 8, 12, 16, 24, 32),                              \
+    CFD_LC_ACC(T, 2, 1, 1, 5, 5, 8, 12, 16, 24, 32),                              \
+    CFD_LC8_ACC(T, 1, 1, 1, 3, 4, 16, 24, 32)
 
 const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext, int wg);
 

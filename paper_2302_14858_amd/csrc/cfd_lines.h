@@ -327,7 +327,7 @@ __device__ __forceinline__ void stage_x(const PassDesc &pd, const T *base, int l
 // opitch, ncols columns) to the interior output rows of length N:
 // consecutive x-lines of one field are consecutive rows of the output.
 // Thread tid owns node pair tid % CO of rows tid / CO + k * RPP.
-template <typename T, int WG>
+template <typename T, int WG, bool ACC = false>
 __device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N, int ncols, int opitch) {
     constexpr int NT = 64 * WG;
     const int CO = (ncols + 1) >> 1;
@@ -339,8 +339,12 @@ __device__ __forceinline__ void store_x(T *dst, const T *tile, int nrows, int N,
     const bool second = c + 1 < ncols;
 #pragma unroll 4
     for (int r = r0; r < nrows; r += RPP) {
-        const T a = tile[r * opitch + c];
-        const T b = tile[r * opitch + c + 1];
+        T a = tile[r * opitch + c];
+        T b = tile[r * opitch + c + 1];
+        if constexpr (ACC) {   // accumulate into what an earlier launch stored
+            a += dst[(int64_t)r * N + c];
+            if (second) b += dst[(int64_t)r * N + c + 1];
+        }
         store_out(dst + (int64_t)r * N + c, a);
         if (second) store_out(dst + (int64_t)r * N + c + 1, b);
     }
@@ -536,7 +540,7 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
                         if (epi)
                             store_x_rk<T, WG>(rk, *ed, pd, out, c.tile, wi.line0, nrows, col0, ncols, opitch);
                         else
-                            store_x<T, WG>(dst + col0, c.tile, nrows, N, ncols, opitch);
+                            store_x<T, WG, XM == 3>(dst + col0, c.tile, nrows, N, ncols, opitch);
                     }
                 }
             }
@@ -555,7 +559,7 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
                 if (epi)
                     store_x_rk<T, WG>(rk, *ed, pd, out, c.tile, wi.line0, nrows, 0, N, opitch);
                 else
-                    store_x<T, WG>(dst, c.tile, nrows, N, N, opitch);
+                    store_x<T, WG, XM == 3>(dst, c.tile, nrows, N, N, opitch);
             }
         }
     } else {
@@ -608,10 +612,28 @@ __device__ __forceinline__ void run_item(LineCtx<T> &c, const WorkItem &wi, T *o
                          (int64_t)lu * pd.osu + (int64_t)c.p * L * pd.osd;
                 const int64_t osd = pd.osd;
                 const int nreal = pd.N - c.p * L;   // rows of this partition inside the line
+                if constexpr (XM == 3) {
+                    // accumulate, in batches: a batch's earlier values are all loaded
+                    // before its stores (which may alias them as far as the compiler
+                    // knows), without holding a whole partition of them at once
+                    constexpr int RB = 4;
 #pragma unroll
-                for (int i = 0; i < L; ++i) {
-                    if (!PAD || i < nreal) store_out(dst, y[o][i]);
-                    dst += osd;
+                    for (int i0 = 0; i0 < L; i0 += RB) {
+                        T prev[RB];
+#pragma unroll
+                        for (int q = 0; q < RB; ++q)
+                            if (i0 + q < L && (!PAD || i0 + q < nreal)) prev[q] = dst[(int64_t)(i0 + q) * osd];
+#pragma unroll
+                        for (int q = 0; q < RB; ++q)
+                            if (i0 + q < L && (!PAD || i0 + q < nreal))
+                                store_out(dst + (int64_t)(i0 + q) * osd, y[o][i0 + q] + prev[q]);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < L; ++i) {
+                        if (!PAD || i < nreal) store_out(dst, y[o][i]);
+                        dst += osd;
+                    }
                 }
             }
         }
@@ -655,7 +677,9 @@ constexpr int max_L() {
 // bits 4..7, x lines: column chunks - 1 in bits 8..9.  Dynamic LDS: exchange
 // area and x tile (one column chunk), overlaid.  XM (extension mode): 1
 // iterated closures, with each line's two end values per op read from ev; 2
-// stage epilogue of the passes whose EpiDesc asks for it (rk).
+// stage epilogue of the passes whose EpiDesc asks for it (rk); 3 accumulate:
+// the derivative is added to what the output already holds (the second
+// order of a symmetrised mixed derivative, after a launch stored the first).
 template <typename T, int NL, int NOPS, int PAR, int MI, int HW, int XM, int WG, int... Ls>
 __global__ void __launch_bounds__(64 * WG)
 k_lines(const WorkItem *__restrict__ items, int nitems, const int *__restrict__ qoff,
