@@ -272,3 +272,31 @@ def test_u_scheme_validation(cuda):
     with pytest.raises(P.CfdError) as e:
         plan.set_iteration(1, 2, 1, 1)
     assert e.value.status == _lib.CFD_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_u_w_seeded_sweep(cuda, seed):
+    """Seeded sweep: random block extents (7..64), ghost widths, schemes among U_1..U_3 and W_1..W_3,
+    biases (-, +, s, upwind), directions, field selections and dtypes, against the oracle."""
+    from oracle import biased as OB
+    rng = np.random.default_rng(900 + seed)
+    kind = ["U", "W"][seed % 2]
+    M = int(rng.integers(1, 4))
+    name = f"(1){kind}{M}"
+    ng = OB.required_ghosts(name) + int(rng.integers(0, 2))
+    sizes = tuple(int(v) for v in rng.choice([7, 9, 13, 16, 20, 31, 40, 64], size=3, replace=False))
+    wl = synth.batch64(nblocks=int(rng.integers(2, 5)), nfields=3, sizes=sizes, ng=ng, seed=950 + seed)
+    dtype = int(rng.integers(0, 2))
+    ops = []
+    for d in range(3):
+        suf = ["-", "+", "s", ""][int(rng.integers(0, 4))]
+        f = int(rng.integers(0, 3))
+        aux = (f + 1) % 3 if kind == "U" else -1
+        vel = (f + 2) % 3 if suf == "" else -1
+        if kind == "W" and rng.random() < 0.5 and suf != "":
+            ops.append((name + suf, d))                      # every field
+        else:
+            ops.append((name + suf, d, f, vel, -1, aux))
+    plan = H.make_plan(wl, ops, dtype=dtype)
+    err = H.full_parity(plan, wl, ops, dtype)
+    assert err <= H.tol_for(dtype), (name, ops, sizes, ng, dtype, err)

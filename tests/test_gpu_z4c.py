@@ -147,3 +147,13 @@ def test_mixed_plan_validation(cuda):
     with pytest.raises(P.CfdError) as e:                 # (1)QP_O8[1] needs 5 ghost layers
         P.Plan(bd, 2, [(P.Scheme.named("(1)QP_O8[1]"), 0, -1, -1, 1)])
     assert e.value.status == _lib.CFD_EGHOST
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_mixed_long_periodic_lines_accumulate(cuda, dtype):
+    """Second orders that accumulate along 192-node periodic lines (eight partitions: the 8-wave
+    accumulating class) and along short lines, against the oracle at every node."""
+    wl = synth.periodic_box(n=(192, 8, 12), nfields=2, seed=37)
+    ops = [("(1)Q1_3[1]", 1, -1, -1, 0), ("(1)Q1_3[1]", 2, 0, -1, 0), ("(1)Q1_3[1]", 1, 1, -1, 2)]
+    plan = H.make_plan(wl, ops, dtype=dtype)
+    assert H.full_parity(plan, wl, ops, dtype) <= H.tol_for(dtype)
