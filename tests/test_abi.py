@@ -121,6 +121,28 @@ def test_plan_bad_arguments():
     assert e.value.status == _lib.CFD_EINVAL
 
 
+def test_plan_second_derivative_operands_checked():
+    """Host validation before any device call: a U scheme needs one field and the field of its
+    sampled f''; an aux_field on any other scheme is refused; a W scheme's embedded (2)P1_M needs
+    closure lines of 3 nodes and periodic lines as long as its stencil."""
+    u = P.Scheme.named("(1)U2-")
+    for ops in ([(u, 0)], [(u, 0, 0)], [(u, 0, 0, -1, -1, 3)], [(u, 0, -1, -1, -1, 1)],
+                [(P.Scheme.named("(1)W2-"), 0, 0, -1, -1, 1)], [(P.Scheme.named("(1)Q1_3[1]"), 0, -1, -1, -1, 0)]):
+        with pytest.raises(P.CfdError) as e:
+            P.Plan([_blk()], 2, ops)
+        assert e.value.status == _lib.CFD_EINVAL, ops
+    w = P.Scheme.named("(1)W3+")
+    with pytest.raises(P.CfdError) as e:
+        P.Plan([_blk(n=(2, 16, 16), ng=5)], 1, [(w, 0)])
+    assert e.value.status == _lib.CFD_ESHAPE
+    with pytest.raises(P.CfdError) as e:
+        P.Plan([_blk(n=(4, 16, 16), ng=0, boundary=(1, 1, 1))], 1, [(w, 0)])
+    assert e.value.status == _lib.CFD_ESHAPE
+    with pytest.raises(P.CfdError) as e:
+        P.Plan([_blk(ng=4)], 1, [(w, 0)])
+    assert e.value.status == _lib.CFD_EGHOST
+
+
 def test_valid_plan_needs_a_device_without_gpu():
     import torch
     if torch.cuda.is_available():
