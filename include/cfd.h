@@ -41,7 +41,7 @@ typedef enum {
     CFD_ESINGULAR = 4,    /* scheme system singular or not solvable without pivoting */
     CFD_ENOMEM = 5,       /* host or device allocation failed */
     CFD_EDEVICE = 6,      /* HIP runtime error (launch, copy, earlier kernel fault) */
-    CFD_EUNSUPPORTED = 7  /* valid request this build does not implement */
+    CFD_EUNSUPPORTED = 7  /* valid request the library does not implement */
 } cfd_status;
 
 typedef enum {
