@@ -18,8 +18,9 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libcfd_mi355x.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["scheme_design.cpp", "cfd_host.cpp", "cfd_kernels.hip", "cfd_kernels_f32.hip", "cfd_aux.hip", "cfd_dense.hip",
-           "cfd_noalloc.hip", "cfd_iterate.hip", "cfd_biased.hip"]
+SOURCES = ["scheme_design.cpp", "cfd_host.cpp", "cfd_kernels.hip", "cfd_kernels_f32.hip", "cfd_kernels_ext.hip",
+           "cfd_kernels_ext_f32.hip", "cfd_aux.hip", "cfd_dense.hip", "cfd_noalloc.hip", "cfd_iterate.hip",
+           "cfd_biased.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

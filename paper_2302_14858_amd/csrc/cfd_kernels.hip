@@ -250,42 +250,47 @@ __global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restr
 // ---------------------------------------------------------------------------
 // Registry of compiled line-kernel classes
 // ---------------------------------------------------------------------------
-const LineClass kLineClassesF64[] = { CFD_LINE_CLASSES(double, 0) };
-extern const LineClass kLineClassesF32[];
-extern const int kNumLineClassesF32;
+extern const LineClass kLineClassesF64[] = { CFD_LINE_CLASSES(double, 0) };
+extern const int kNumLineClassesF64 = (int)(sizeof(kLineClassesF64) / sizeof(kLineClassesF64[0]));
+
+namespace {
+// The classes of one precision: the plain table, then the extension table.
+template <typename F>
+void for_each_class(int f32, F &&fn) {
+    const LineClass *tabs[2] = {f32 ? kLineClassesF32 : kLineClassesF64, f32 ? kLineClassesExtF32 : kLineClassesExtF64};
+    const int ns[2] = {f32 ? kNumLineClassesF32 : kNumLineClassesF64,
+                       f32 ? kNumLineClassesExtF32 : kNumLineClassesExtF64};
+    for (int t = 0; t < 2; ++t)
+        for (int i = 0; i < ns[t]; ++i) fn(tabs[t][i]);
+}
+}  // namespace
 
 const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext, int wg) {
-    const LineClass *tab = f32 ? kLineClassesF32 : kLineClassesF64;
-    const int n = f32 ? kNumLineClassesF32 : (int)(sizeof(kLineClassesF64) / sizeof(kLineClassesF64[0]));
     const LineClass *best = nullptr;
-    for (int i = 0; i < n; ++i) {
-        const LineClass &k = tab[i];
-        if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw || k.ext != ext) continue;
-        if (k.wg != wg) continue;
+    for_each_class(f32, [&](const LineClass &k) {
+        if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw || k.ext != ext) return;
+        if (k.wg != wg) return;
         bool hasL = false;
         for (int j = 0; j < k.nL; ++j) hasL |= (k.Ls[j] == L);
-        if (!hasL) continue;
+        if (!hasL) return;
         if (!best || (k.mi + k.hw) < (best->mi + best->hw) ||
             ((k.mi + k.hw) == (best->mi + best->hw) && k.nL < best->nL))
             best = &k;
-    }
+    });
     return best;
 }
 
 int line_class_Ls(int f32, int nl, int nops, int par, int mi, int hw, int *Ls, int cap, int ext, int wg) {
-    const LineClass *tab = f32 ? kLineClassesF32 : kLineClassesF64;
-    const int n = f32 ? kNumLineClassesF32 : (int)(sizeof(kLineClassesF64) / sizeof(kLineClassesF64[0]));
     int cnt = 0;
-    for (int i = 0; i < n; ++i) {
-        const LineClass &k = tab[i];
-        if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw || k.ext != ext) continue;
-        if (wg && k.wg != wg) continue;
+    for_each_class(f32, [&](const LineClass &k) {
+        if (k.nl != nl || k.nops != nops || k.par != par || k.mi < mi || k.hw < hw || k.ext != ext) return;
+        if (wg && k.wg != wg) return;
         for (int j = 0; j < k.nL; ++j) {
             bool seen = false;
             for (int q = 0; q < cnt; ++q) seen |= (Ls[q] == k.Ls[j]);
             if (!seen && cnt < cap) Ls[cnt++] = k.Ls[j];
         }
-    }
+    });
     return cnt;
 }
 

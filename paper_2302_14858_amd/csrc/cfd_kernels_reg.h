@@ -53,6 +53,8 @@ struct LineClass {
     /* tridiagonal first derivative, RHS half-width 3 (short and long lines) */   \
     CFD_LC(T, 1, 1, 1, 3, 4, 8, 12, 16, 24, 32),                                  \
     CFD_LC(T, 1, 1, 1, 3, 4, 48, 64),                                             \
+    /* tridiagonal second derivative alone on long lines */                       \
+    CFD_LC(T, 1, 1, 0, 3, 4, 48, 64),                                             \
     /* tridiagonal first derivative, RHS half-width 2 */                          \
     CFD_LC(T, 1, 1, 1, 2, 4, 8, 16, 32, 64),                                      \
     /* any single operator with stencils up to half-width 5 */                    \
@@ -64,11 +66,16 @@ struct LineClass {
     CFD_LC(T, 0, 1, 1, 5, 5, 8, 12, 16, 24, 32),                                  \
     CFD_LC(T, 0, 1, 0, 5, 5, 8, 12, 16, 24, 32),                                  \
     /* long lines in 8 partitions (8-wave workgroups): tridiagonal first +     */ \
-    /* second derivative (16-row partitions alone keep 4 waves per SIMD) and   */ \
-    /* first derivative, partitions of 16..32 rows                             */ \
+    /* second derivative (16-row partitions alone keep 4 waves per SIMD), and  */ \
+    /* first or second derivative alone, partitions of 16..32 rows             */ \
     CFD_LC8(T, 1, 2, 1, 3, 4, 16),                                                \
     CFD_LC8(T, 1, 2, 1, 3, 4, 16, 24, 32),                                        \
     CFD_LC8(T, 1, 1, 1, 3, 4, 16, 24, 32),                                        \
+    CFD_LC8(T, 1, 1, 0, 3, 4, 16, 24, 32)
+
+// The classes with a kernel extension, compiled in translation units of their
+// own (cfd_kernels_ext*.hip) so that the build runs more of them in parallel.
+#define CFD_LINE_CLASSES_EXT(T, F32)                                              \
     /* iterated closures of tridiagonal schemes (hybrid closure iteration) */    \
     CFD_LC_EXT(T, 1, 2, 1, 3, 4, 8, 12, 16),                                      \
     CFD_LC_EXT(T, 1, 1, 1, 3, 4, 8, 12, 16, 24, 32),                              \
@@ -88,5 +95,15 @@ struct LineClass {
     CFD_LC8_ACC(T, 1, 1, 1, 3, 4, 16, 24, 32)
 
 const LineClass *find_line_class(int f32, int nl, int nops, int par, int mi, int hw, int L, int ext, int wg);
+
+// The tables, one per precision and translation unit.
+extern const LineClass kLineClassesF64[];
+extern const int kNumLineClassesF64;
+extern const LineClass kLineClassesF32[];
+extern const int kNumLineClassesF32;
+extern const LineClass kLineClassesExtF64[];
+extern const int kNumLineClassesExtF64;
+extern const LineClass kLineClassesExtF32[];
+extern const int kNumLineClassesExtF32;
 
 }  // namespace cfd

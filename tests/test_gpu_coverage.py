@@ -184,3 +184,16 @@ def test_eight_partition_long_lines(cuda, dtype):
     for xl in (0, 1):
         plan.set_schedule(256, xl, 8)
     assert H.full_parity(plan, wlp, opsp, dtype) <= H.tol_for(dtype)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_second_derivative_alone_on_long_lines(cuda, dtype):
+    """A tridiagonal second derivative without a first-derivative partner on lines longer than four
+    partitions of 32 rows: periodic 256-node and 192-node lines and 200-node closure lines, x, y and z
+    (the 8-wave and 48/64-row classes of the even parity), against the oracle at every node."""
+    for wl in (synth.periodic_box(n=(256, 8, 192), nfields=2, seed=61),
+               synth.batch64(nblocks=2, nfields=2, sizes=(200, 9), ng=4, seed=62)):
+        ops = [("(2)Q1_3[1]", d) for d in range(3)]
+        plan = H.make_plan(wl, ops, dtype=dtype)
+        err = H.full_parity(plan, wl, ops, dtype)
+        assert err <= H.tol_for(dtype), (wl.name, err)
