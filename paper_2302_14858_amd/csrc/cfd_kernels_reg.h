@@ -53,7 +53,9 @@ struct LineClass {
     /* tridiagonal first derivative, RHS half-width 3 (short and long lines) */   \
     CFD_LC(T, 1, 1, 1, 3, 4, 8, 12, 16, 24, 32),                                  \
     CFD_LC(T, 1, 1, 1, 3, 4, 48, 64),                                             \
-    /* tridiagonal second derivative alone on long lines */                       \
+    /* tridiagonal second derivative alone, RHS half-width up to 3 (short and   */ \
+    /* long lines)                                                              */ \
+    CFD_LC(T, 1, 1, 0, 3, 4, 8, 12, 16, 24, 32),                                  \
     CFD_LC(T, 1, 1, 0, 3, 4, 48, 64),                                             \
     /* tridiagonal first derivative, RHS half-width 2 */                          \
     CFD_LC(T, 1, 1, 1, 2, 4, 8, 16, 32, 64),                                      \
