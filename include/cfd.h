@@ -384,9 +384,9 @@ cfd_status cfd_plan_count_nonfinite(cfd_plan *p, const void *out_dev, void *stre
  * fused operators and launch shape.  Overwrites out_dev.  Allocates a
  * temporary output-sized buffer for the check.  Synchronises the stream.
  * Invalidates a captured graph.  Biased operators have one launch per kernel
- * class; a plan holding only biased operators tunes just whether those run
- * one after another or concurrently (CFD_SCHED_CONCURRENT), otherwise they
- * follow the flag the line kernels' tuning chose. */
+ * class; whether those run one after another or concurrently is tuned last,
+ * under the line kernels' schedule (a plan holding only biased operators
+ * tunes just that, and reports it as CFD_SCHED_CONCURRENT). */
 cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, void *stream,
                              const char *cache_path);
 

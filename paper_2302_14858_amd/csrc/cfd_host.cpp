@@ -127,6 +127,7 @@ struct cfd_plan {
     bool split_x = false;                 // x-lines in a launch of their own
     bool xcd = false;                     // XCD-aware queues (persistent grid only)
     bool concurrent = false;              // kernel groups on forked streams, joined at the end
+    bool bconcurrent = false;             // the biased kernel classes on forked streams
     int cus = 256;
     size_t max_lds = 65536;
     bool xcd_interleave_ok = false;       // dispatch check passed: the XCD-interleaved per-item order covers every item
@@ -1211,7 +1212,7 @@ cfd_status build_biased(cfd_plan *p) {
 cfd_status launch_biased_groups(cfd_plan *p, const void *in, void *out, hipStream_t st, const void *ev = nullptr,
                                 void *ends = nullptr) {
     const size_t n = p->bgroups.size();
-    const bool fork = p->concurrent && n > 1 && p->aux.size() + 1 >= n && p->ev.size() >= n;
+    const bool fork = p->bconcurrent && n > 1 && p->aux.size() + 1 >= n && p->ev.size() >= n;
     if (fork) HIPCHK(hipEventRecord(p->ev[0], st));
     for (size_t i = 0; i < n; ++i) {
         const cfd_plan::BGroup &g = p->bgroups[i];
@@ -2202,6 +2203,7 @@ cfd_status cfd_plan_set_schedule(cfd_plan *p, int N, int xlines, int partitions,
     p->split_x = (flags & CFD_SCHED_SPLIT_X) != 0;
     p->xcd = (flags & CFD_SCHED_XCD) != 0;
     p->concurrent = (flags & CFD_SCHED_CONCURRENT) != 0;
+    p->bconcurrent = p->concurrent;
     return build(p);
 }
 
@@ -2217,9 +2219,9 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
     }
     const bool f32 = p->dtype != CFD_F64;
     const char *dt = f32 ? "f32" : "f64";
-    if (p->passes.empty()) {
-        // only biased operators: their classes' launches one after the other
-        // or on forked streams, whichever is faster
+    // the biased kernel classes' launches one after the other or on forked
+    // streams, whichever makes the whole apply faster
+    auto tune_biased = [&]() -> cfd_status {
         if (p->bgroups.size() < 2) return CFD_OK;
         hipEvent_t a0, a1;
         HIPCHK(hipEventCreate(&a0));
@@ -2228,7 +2230,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         bool bc = false;
         cfd_status r = CFD_OK;
         for (int conc = 0; conc <= 1 && r == CFD_OK; ++conc) {
-            p->concurrent = conc;
+            p->bconcurrent = conc;
             for (int w = 0; w < 3 && r == CFD_OK; ++w) r = enqueue(p, in_dev, out_dev, st);
             for (int trial = 0; trial < 3 && r == CFD_OK; ++trial) {
                 (void)hipEventRecord(a0, st);
@@ -2245,7 +2247,12 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
         }
         (void)hipEventDestroy(a0);
         (void)hipEventDestroy(a1);
-        p->concurrent = bc;
+        p->bconcurrent = bc;
+        return r;
+    };
+    if (p->passes.empty()) {   // only biased operators: just that choice (reported as the plan's flag)
+        cfd_status r = tune_biased();
+        p->concurrent = p->bconcurrent;
         return r;
     }
     if (p->dtype == CFD_MIXED_BF16) {
@@ -2450,6 +2457,7 @@ cfd_status cfd_plan_autotune(cfd_plan *p, const void *in_dev, void *out_dev, voi
             result = build(p);
         }
     }
+    if (result == CFD_OK) result = tune_biased();   // under the line kernels' schedule
     return result;
 }
 
